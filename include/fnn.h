@@ -1,0 +1,192 @@
+/*
+ * fnn.h -- C ABI of the MI355X epsilon-graph library.
+ *
+ * Exact fixed-radius near-neighbour graphs in a general metric space with a
+ * cover tree (Raulet, Morozov, Buluc, Yelick, "Distributed-Memory Parallel
+ * Algorithms for Fixed-Radius Near Neighbor Graph Construction").
+ *
+ * Problem statement (Definitions): a finite point set P with a metric d and a
+ * threshold eps > 0; the epsilon-graph has an edge (p, q) for every pair with
+ * d(p, q) <= eps.  This library returns it as a symmetric CSR over the input
+ * indices.  Two calls do the work: a batched, level-by-level cover-tree
+ * build (Section IV-A, Algorithms 1 and 2) and an all-points range query
+ * over that tree (Section IV-B, Algorithm 3, with query batches).
+ *
+ * Conventions
+ *  - Plain C, no C++ or framework types cross this boundary.
+ *  - Pointers documented as "device" are HIP device pointers on the current
+ *    device; "host" pointers are ordinary host memory.
+ *  - Every call returns FNN_OK (0) or a negative error code; on error the
+ *    output handle is set to NULL, nothing leaks, and fnn_last_error()
+ *    returns a message (thread-local).
+ *  - Work is enqueued on the calling thread's bound stream (fnn_set_stream;
+ *    default: the null stream).  fnn_tree_build and fnn_eps_graph return
+ *    after their results are complete on that stream (they synchronize on
+ *    it, since sizes are data dependent).
+ *  - Library-owned memory is released with fnn_free.
+ */
+#ifndef FNN_H
+#define FNN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Metrics (Definitions: Euclidean, cosine, Hamming and edit distance are
+ * the metrics the paper names; "cosine" is taken as the angle, which is a
+ * metric, and edit distance as unit-cost Levenshtein). */
+typedef enum {
+    FNN_L2 = 0,          /* float32 rows [n x dim]                            */
+    FNN_ANGULAR = 1,     /* float32 rows [n x dim], no zero row               */
+    FNN_HAMMING = 2,     /* uint64 rows [n x dim/64]; dim = bits, % 64 == 0   */
+    FNN_LEVENSHTEIN = 3  /* uint8 rows [n x dim]; dim = row stride in bytes,  */
+                         /* symbols < 32, padded with 0xFF; length = index of */
+                         /* the first 0xFF (or dim); dim <= 256               */
+} fnn_metric;
+
+/* Error codes. */
+enum {
+    FNN_OK = 0,
+    FNN_EINVAL = -1,        /* bad argument (NaN/Inf coordinate, eps <= 0,  */
+                            /* dim rules, zero angular row, NULL pointer)    */
+    FNN_ENOMEM = -2,        /* device or host allocation failed              */
+    FNN_EHIP = -3,          /* a HIP runtime call failed                     */
+    FNN_EUNSUPPORTED = -4,  /* valid input outside what the kernels support  */
+    FNN_EINTERNAL = -5      /* an internal consistency check failed          */
+};
+
+/* Leaf-tile arithmetic of the query. */
+typedef enum {
+    FNN_PREC_FP32 = 0,   /* direct-difference FP32 tiles (the plain path)      */
+    FNN_PREC_BF16 = 1,   /* MFMA BF16 Gram filter, FP32 recompute of survivors */
+    FNN_PREC_FP8 = 2     /* MFMA FP8 (E4M3) Gram filter, FP32 recompute        */
+} fnn_precision;
+
+/* How CSR rows are sized. */
+typedef enum {
+    FNN_SCHED_TWO_PASS = 0,  /* count pass, scan, fill pass (always exact)     */
+    FNN_SCHED_LEARNED = 1    /* cost-model pre-sized slots, one pass; rows that */
+                             /* overflow fall back to the two-pass path         */
+} fnn_sched;
+
+/* Options for the _ex calls.  Zero-initialise, set struct_size, then set the
+ * fields to change; a zero field keeps its default. */
+typedef struct fnn_options {
+    int32_t struct_size;  /* sizeof(fnn_options)                             */
+    int32_t zeta;         /* leaf size (Algorithm 2); default 64             */
+    int32_t pack;         /* points per query/leaf tile block; default 64    */
+    int32_t precision;    /* fnn_precision; default FNN_PREC_FP32            */
+    int32_t sched;        /* fnn_sched; default FNN_SCHED_TWO_PASS           */
+    int32_t validate;     /* 1: also measure the max FP32 distance error     */
+                          /* against FP64 and count filter false negatives    */
+    int32_t kmax;         /* centres accepted per net-selection pass (1..64) */
+    int32_t reserved[9];
+} fnn_options;
+
+typedef struct fnn_tree fnn_tree;  /* opaque; device-resident cover tree */
+
+/* Symmetric CSR result.  Rows are the input indices 0..n-1; each row lists
+ * its neighbours' input indices in ascending order, no self loops, and
+ * dist[k] is the FP32 distance (within 1e-5 relative of FP64).  Arrays are
+ * device memory owned by the library. */
+typedef struct fnn_csr {
+    uint32_t kind;        /* library tag; do not modify                      */
+    uint32_t pad_;
+    int64_t n;
+    int64_t nnz;
+    int64_t *row_ptr;     /* device, n + 1                                   */
+    int32_t *col;         /* device, nnz                                     */
+    float *dist;          /* device, nnz                                     */
+} fnn_csr;
+
+/* Counters and timings of the last build or query on a handle. */
+typedef struct fnn_stats {
+    int64_t n;
+    int64_t nodes;            /* cover-tree vertices                         */
+    int64_t leaf_blocks;      /* leaf vertices holding <= zeta points        */
+    int64_t packs;            /* query tile blocks                           */
+    int64_t rounds;           /* build levels processed                      */
+    int64_t netsel_passes;    /* net-selection passes over all hubs          */
+    int64_t build_dist_evals; /* metric evaluations in the build             */
+    int64_t traverse_tests;   /* node-pair tests in the traversal            */
+    int64_t interactions;     /* block pairs sent to leaf tiles              */
+    int64_t tile_pairs;       /* point pairs evaluated in leaf tiles (once   */
+                              /* per unordered pair, per pass)               */
+    int64_t filter_pairs;     /* pairs screened by the MFMA filter           */
+    int64_t filter_survivors; /* pairs the filter passed to FP32             */
+    int64_t fp64_rechecks;    /* borderline pairs decided in FP64            */
+    int64_t edges;            /* nnz (ordered pairs)                          */
+    int64_t overflow_rows;    /* learned schedule: rows re-done in two pass  */
+    int64_t validate_mismatch;/* validate: filter false negatives (must be 0)*/
+    double max_rel_err;       /* validate: max |dist32 - dist64| / dist64    */
+    double build_ms, traverse_ms, tile_ms, count_ms, scan_ms, fill_ms,
+           sort_ms, total_ms;
+    double reserved[8];
+} fnn_stats;
+
+/* Build the cover tree of n points (Algorithms 1-2).  points: device
+ * pointer, layout per metric above, caller-owned, only read during the
+ * call (the tree keeps its own permuted copy).  n >= 1.  On success *out
+ * receives a library-owned tree. */
+int fnn_tree_build(const void *points, int64_t n, int32_t dim,
+                   fnn_metric metric, fnn_tree **out);
+int fnn_tree_build_ex(const void *points, int64_t n, int32_t dim,
+                      fnn_metric metric, const fnn_options *opt,
+                      fnn_tree **out);
+
+/* All-points range query: every ordered pair (i, j), i != j, with
+ * d(p_i, p_j) <= eps, as a symmetric CSR (Definitions; Algorithm 3 run for
+ * query batches).  eps must be finite and > 0; Hamming and Levenshtein use
+ * floor(eps).  The edge set equals the FP64 reference predicate exactly. */
+int fnn_eps_graph(const fnn_tree *tree, double eps, fnn_csr **out);
+int fnn_eps_graph_ex(const fnn_tree *tree, double eps,
+                     const fnn_options *opt, fnn_csr **out);
+
+/* Release a fnn_tree* or fnn_csr* (NULL is ignored). */
+void fnn_free(void *handle);
+
+/* Stream for this thread's later calls (a hipStream_t; NULL = null stream). */
+int fnn_set_stream(void *stream);
+
+/* Optional allocator for the memory handed back to the caller (tree arrays
+ * and CSR arrays).  alloc returns a device pointer or NULL; free releases it.
+ * Scratch memory always comes from the library's stream-ordered pool.
+ * Passing NULL functions restores hipMalloc / hipFree. */
+typedef void *(*fnn_alloc_fn)(size_t bytes, void *ctx);
+typedef void (*fnn_free_fn)(void *ptr, void *ctx);
+int fnn_set_allocator(fnn_alloc_fn alloc, fnn_free_fn free_, void *ctx);
+
+/* Copy the counters of the last operation on a tree or CSR handle. */
+int fnn_get_stats(const void *handle, fnn_stats *out);
+
+/* Debug export of the cover tree to caller-provided host arrays.
+ * fnn_tree_info gives the sizes; fnn_tree_export fills:
+ *   order[n]        input index of each point in tree order
+ *   center[nodes]   input index of each vertex's point
+ *   radius[nodes]   stored radius (an upper bound on d(center, x) over the
+ *                   vertex's points)
+ *   level[nodes]    split level (children lie within 2^level of the centre,
+ *                   sibling centres are more than 2^(level-1) apart)
+ *   child_begin/child_count[nodes]  children are consecutive vertex ids
+ *   pt_begin/pt_end[nodes]          the vertex's points are
+ *                                   order[pt_begin .. pt_end)
+ * A vertex with child_count == 0 is a leaf block: its points are leaves. */
+int fnn_tree_info(const fnn_tree *tree, int64_t *n, int64_t *nodes);
+int fnn_tree_export(const fnn_tree *tree, int32_t *order, int32_t *center,
+                    float *radius, int32_t *level, int32_t *child_begin,
+                    int32_t *child_count, int32_t *pt_begin, int32_t *pt_end);
+
+/* Message of the last error on this thread ("" if none). */
+const char *fnn_last_error(void);
+
+/* ABI version (major * 10000 + minor * 100 + patch). */
+int fnn_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FNN_H */

@@ -1,0 +1,284 @@
+"""MI355X epsilon-graph library: Python binding of the C ABI in
+``include/fnn.h`` (argument marshalling only; every step of the path runs in
+the HIP kernels of ``libfnn.so``).
+
+    import torch, paper_2510_14147_amd as fnn
+    tree = fnn.fnn_tree_build(points_cuda, "l2")        # cover tree on the GPU
+    g = fnn.fnn_eps_graph(tree, eps)                     # symmetric CSR
+    g.row_ptr, g.col, g.dist                             # torch tensors (cuda)
+
+PyTorch provides device memory (the caching allocator backs every array the
+library hands back) and the stream (the current torch stream).  If the
+compiled library is missing the import still works but every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfnn.so")
+
+METRICS = {"l2": 0, "angular": 1, "hamming": 2, "levenshtein": 3}
+PRECISIONS = {"fp32": 0, "bf16": 1, "fp8": 2}
+SCHEDS = {"two_pass": 0, "learned": 1}
+
+FNN_OK, FNN_EINVAL, FNN_ENOMEM, FNN_EHIP, FNN_EUNSUPPORTED, FNN_EINTERNAL = \
+    0, -1, -2, -3, -4, -5
+
+
+class FnnError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"fnn error {code}: {msg}")
+        self.code = code
+
+
+class fnn_options(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_int32), ("zeta", ctypes.c_int32),
+                ("pack", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("sched", ctypes.c_int32), ("validate", ctypes.c_int32),
+                ("kmax", ctypes.c_int32), ("reserved", ctypes.c_int32 * 9)]
+
+
+class fnn_csr(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_uint32), ("pad_", ctypes.c_uint32),
+                ("n", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p),
+                ("dist", ctypes.c_void_p)]
+
+
+_STAT_I64 = ["n", "nodes", "leaf_blocks", "packs", "rounds", "netsel_passes",
+             "build_dist_evals", "traverse_tests", "interactions",
+             "tile_pairs", "filter_pairs", "filter_survivors",
+             "fp64_rechecks", "edges", "overflow_rows", "validate_mismatch"]
+_STAT_F64 = ["max_rel_err", "build_ms", "traverse_ms", "tile_ms", "count_ms",
+             "scan_ms", "fill_ms", "sort_ms", "total_ms"]
+
+
+class fnn_stats(ctypes.Structure):
+    _fields_ = ([(k, ctypes.c_int64) for k in _STAT_I64] +
+                [(k, ctypes.c_double) for k in _STAT_F64] +
+                [("reserved", ctypes.c_double * 8)])
+
+
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+_lib = None
+_lock = threading.Lock()
+_live = {}          # device pointer -> torch tensor owning it
+
+
+def _torch():
+    import torch
+    return torch
+
+
+@_ALLOC_FN
+def _alloc_cb(nbytes, ctx):
+    torch = _torch()
+    t = torch.empty(int(nbytes), dtype=torch.uint8, device="cuda")
+    p = t.data_ptr()
+    _live[p] = t
+    return p
+
+
+@_FREE_FN
+def _free_cb(ptr, ctx):
+    _live.pop(ptr, None)
+
+
+def lib():
+    """Load libfnn.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                "libfnn.so is not built; run python -c 'import __graft_entry__ as g; g.build()'")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+        L.fnn_version.restype = ctypes.c_int
+        L.fnn_last_error.restype = ctypes.c_char_p
+        L.fnn_set_stream.argtypes = [vp]
+        L.fnn_set_allocator.argtypes = [_ALLOC_FN, _FREE_FN, vp]
+        L.fnn_tree_build_ex.argtypes = [vp, i64, i32, ctypes.c_int,
+                                        ctypes.POINTER(fnn_options),
+                                        ctypes.POINTER(vp)]
+        L.fnn_tree_build.argtypes = [vp, i64, i32, ctypes.c_int,
+                                     ctypes.POINTER(vp)]
+        L.fnn_eps_graph_ex.argtypes = [vp, ctypes.c_double,
+                                       ctypes.POINTER(fnn_options),
+                                       ctypes.POINTER(ctypes.POINTER(fnn_csr))]
+        L.fnn_eps_graph.argtypes = [vp, ctypes.c_double,
+                                    ctypes.POINTER(ctypes.POINTER(fnn_csr))]
+        L.fnn_free.argtypes = [vp]
+        L.fnn_free.restype = None
+        L.fnn_get_stats.argtypes = [vp, ctypes.POINTER(fnn_stats)]
+        L.fnn_tree_info.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+        L.fnn_tree_export.argtypes = [vp] + [vp] * 8
+        _lib = L
+        L.fnn_set_allocator(_alloc_cb, _free_cb, None)
+    return _lib
+
+
+def _check(rc):
+    if rc != FNN_OK:
+        raise FnnError(rc, lib().fnn_last_error().decode())
+
+
+def _bind_stream():
+    torch = _torch()
+    lib().fnn_set_stream(ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+
+
+def _options(**kw) -> fnn_options:
+    o = fnn_options()
+    o.struct_size = ctypes.sizeof(fnn_options)
+    for k, v in kw.items():
+        if v is None:
+            continue
+        if k == "precision" and isinstance(v, str):
+            v = PRECISIONS[v]
+        if k == "sched" and isinstance(v, str):
+            v = SCHEDS[v]
+        setattr(o, k, int(v))
+    return o
+
+
+def _stats(handle) -> dict:
+    s = fnn_stats()
+    _check(lib().fnn_get_stats(handle, ctypes.byref(s)))
+    return {k: getattr(s, k) for k in _STAT_I64 + _STAT_F64}
+
+
+class Tree:
+    """A device-resident cover tree (fnn_tree handle)."""
+
+    def __init__(self, handle, n, dim, metric):
+        self.handle, self.n, self.dim, self.metric = handle, n, dim, metric
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def free(self):
+        if self.handle:
+            lib().fnn_free(self.handle)
+            self.handle = None
+
+    @property
+    def stats(self):
+        return _stats(self.handle)
+
+
+class Graph:
+    """Symmetric CSR epsilon-graph; row_ptr int64 [n+1], col int32 [nnz],
+    dist float32 [nnz] are torch tensors on the device."""
+
+    def __init__(self, ptr):
+        torch = _torch()
+        self._ptr = ptr
+        c = ptr.contents
+        self.n, self.nnz = int(c.n), int(c.nnz)
+        self.row_ptr = _live[c.row_ptr][: 8 * (self.n + 1)].view(torch.int64)
+        self.col = _live[c.col][: 4 * self.nnz].view(torch.int32)
+        self.dist = _live[c.dist][: 4 * self.nnz].view(torch.float32)
+        self.stats = _stats(ptr)
+
+    def free(self):
+        if self._ptr:
+            lib().fnn_free(ctypes.cast(self._ptr, ctypes.c_void_p))
+            self._ptr = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def to_numpy(self):
+        return (self.row_ptr.cpu().numpy(), self.col.cpu().numpy(),
+                self.dist.cpu().numpy())
+
+
+def _as_device_points(points, metric: str):
+    torch = _torch()
+    if metric in ("l2", "angular"):
+        t = torch.as_tensor(points, dtype=torch.float32)
+        if t.dim() != 2:
+            raise ValueError("points must be [n, dim]")
+        return t.to("cuda").contiguous(), t.shape[1]
+    if metric == "hamming":
+        if isinstance(points, np.ndarray):
+            t = torch.from_numpy(np.ascontiguousarray(points).view(np.int64))
+        else:
+            t = points
+        return t.to("cuda").contiguous(), t.shape[1] * 64
+    if isinstance(points, np.ndarray):
+        t = torch.from_numpy(np.ascontiguousarray(points, dtype=np.uint8))
+    else:
+        t = points
+    return t.to("cuda").contiguous(), t.shape[1]
+
+
+def fnn_tree_build(points, metric: str = "l2", zeta=None, pack=None,
+                   kmax=None) -> Tree:
+    """Cover tree of ``points`` (numpy array or tensor; moved to the GPU)."""
+    m = METRICS[metric]
+    t, dim = _as_device_points(points, metric)
+    _bind_stream()
+    h = ctypes.c_void_p()
+    o = _options(zeta=zeta, pack=pack, kmax=kmax)
+    _check(lib().fnn_tree_build_ex(ctypes.c_void_p(t.data_ptr()), t.shape[0],
+                                   dim, m, ctypes.byref(o), ctypes.byref(h)))
+    tree = Tree(h, t.shape[0], dim, metric)
+    return tree
+
+
+def fnn_eps_graph(tree: Tree, eps: float, precision="fp32",
+                  sched="two_pass", validate=False) -> Graph:
+    _bind_stream()
+    out = ctypes.POINTER(fnn_csr)()
+    o = _options(precision=precision, sched=sched, validate=int(validate))
+    _check(lib().fnn_eps_graph_ex(tree.handle, float(eps), ctypes.byref(o),
+                                  ctypes.byref(out)))
+    return Graph(out)
+
+
+def fnn_free(obj):
+    obj.free()
+
+
+def fnn_get_stats(obj) -> dict:
+    return obj.stats
+
+
+def fnn_tree_export(tree: Tree) -> dict:
+    """Host copy of the cover tree (layout of fnn_tree_export in fnn.h)."""
+    n, nn = ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().fnn_tree_info(tree.handle, ctypes.byref(n), ctypes.byref(nn)))
+    n, nn = n.value, nn.value
+    a = dict(order=np.zeros(n, np.int32), center=np.zeros(nn, np.int32),
+             radius=np.zeros(nn, np.float32), level=np.zeros(nn, np.int32),
+             child_begin=np.zeros(nn, np.int32), child_count=np.zeros(nn, np.int32),
+             pt_begin=np.zeros(nn, np.int32), pt_end=np.zeros(nn, np.int32))
+    _bind_stream()
+    _check(lib().fnn_tree_export(tree.handle, *[ctypes.c_void_p(a[k].ctypes.data) for k in
+                                                ("order", "center", "radius", "level",
+                                                 "child_begin", "child_count",
+                                                 "pt_begin", "pt_end")]))
+    a["nnodes"] = nn
+    return a
+
+
+def version() -> int:
+    return lib().fnn_version()

@@ -1,0 +1,268 @@
+// C ABI entry points (include/fnn.h): argument checks, error codes,
+// ownership.  No exception crosses this boundary.
+#include <math.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+
+#include "tree.h"
+
+namespace fnn {
+extern thread_local hipStream_t g_stream;
+void set_alloc_hook(fnn_alloc_fn a, fnn_free_fn f, void *ctx);
+void build_tree(fnn_tree *T, const void *points, Scratch &S);
+void eps_graph(const fnn_tree *T, double eps, const Options &opt, fnn_csr *C,
+               fnn_stats &st, Scratch &S);
+
+static thread_local std::string g_err;
+
+static int set_err(int code, const std::string &m)
+{
+    g_err = m;
+    return code;
+}
+
+Options read_options(const fnn_options *o)
+{
+    Options r;
+    if (!o)
+        return r;
+    if (o->struct_size < (int32_t)offsetof(fnn_options, reserved))
+        fail(FNN_EINVAL, "fnn_options.struct_size is too small (%d)",
+             (int)o->struct_size);
+    if (o->zeta < 0 || o->pack < 0 || o->kmax < 0)
+        fail(FNN_EINVAL, "negative option");
+    if (o->zeta)
+        r.zeta = o->zeta;
+    if (o->pack)
+        r.pack = o->pack;
+    if (o->precision < 0 || o->precision > FNN_PREC_FP8)
+        fail(FNN_EINVAL, "unknown precision %d", (int)o->precision);
+    r.precision = o->precision;
+    if (o->sched < 0 || o->sched > FNN_SCHED_LEARNED)
+        fail(FNN_EINVAL, "unknown schedule %d", (int)o->sched);
+    r.sched = o->sched;
+    r.validate = o->validate ? 1 : 0;
+    if (o->kmax)
+        r.kmax = o->kmax > 64 ? 64 : o->kmax;
+    return r;
+}
+
+struct CsrBox {
+    fnn_csr pub;
+    fnn_stats stats;
+};
+
+}  // namespace fnn
+
+using namespace fnn;
+
+extern "C" {
+
+int fnn_version(void) { return 100; }
+
+const char *fnn_last_error(void) { return g_err.c_str(); }
+
+int fnn_set_stream(void *stream)
+{
+    g_stream = (hipStream_t)stream;
+    return FNN_OK;
+}
+
+int fnn_set_allocator(fnn_alloc_fn alloc, fnn_free_fn free_, void *ctx)
+{
+    if ((alloc == nullptr) != (free_ == nullptr))
+        return set_err(FNN_EINVAL, "allocator and free must both be set or both NULL");
+    set_alloc_hook(alloc, free_, ctx);
+    return FNN_OK;
+}
+
+int fnn_tree_build_ex(const void *points, int64_t n, int32_t dim,
+                      fnn_metric metric, const fnn_options *opt, fnn_tree **out)
+{
+    if (!out)
+        return set_err(FNN_EINVAL, "out is NULL");
+    *out = nullptr;
+    fnn_tree *T = nullptr;
+    try {
+        if (!points)
+            fail(FNN_EINVAL, "points is NULL");
+        if (n < 1 || n > (int64_t)INT32_MAX / 2 - 1)
+            fail(FNN_EINVAL, "n must be in [1, 2^30 - 1] (got %lld)", (long long)n);
+        if (metric < FNN_L2 || metric > FNN_LEVENSHTEIN)
+            fail(FNN_EINVAL, "unknown metric %d", (int)metric);
+        if (dim < 1)
+            fail(FNN_EINVAL, "dim must be >= 1");
+        Options o = read_options(opt);
+        if (o.zeta < 1)
+            fail(FNN_EINVAL, "zeta must be >= 1");
+        T = new fnn_tree();
+        T->metric = metric;
+        T->n = n;
+        T->dim = dim;
+        T->opt = o;
+        switch (metric) {
+        case FNN_L2:
+        case FNN_ANGULAR:
+            if (dim > 65536)
+                fail(FNN_EUNSUPPORTED, "dim > 65536");
+            T->dp = (dim + 3) / 4 * 4;
+            break;
+        case FNN_HAMMING:
+            if (dim % 64)
+                fail(FNN_EINVAL, "Hamming dim (bits) must be a multiple of 64");
+            if (dim / 64 > 16)
+                fail(FNN_EUNSUPPORTED, "Hamming codes longer than 1024 bits");
+            T->dp = dim / 64;
+            break;
+        default:
+            if (dim > 64 * MAX_LEV_WORDS)
+                fail(FNN_EUNSUPPORTED, "Levenshtein stride > %d", 64 * MAX_LEV_WORDS);
+            T->dp = dim;
+            break;
+        }
+        Scratch S(current_stream());
+        build_tree(T, points, S);
+        *out = T;
+        return FNN_OK;
+    } catch (const Error &e) {
+        delete T;
+        return set_err(e.code, e.msg);
+    } catch (const std::bad_alloc &) {
+        delete T;
+        return set_err(FNN_ENOMEM, "host allocation failed");
+    } catch (...) {
+        delete T;
+        return set_err(FNN_EINTERNAL, "unexpected exception");
+    }
+}
+
+int fnn_tree_build(const void *points, int64_t n, int32_t dim,
+                   fnn_metric metric, fnn_tree **out)
+{
+    return fnn_tree_build_ex(points, n, dim, metric, nullptr, out);
+}
+
+int fnn_eps_graph_ex(const fnn_tree *tree, double eps, const fnn_options *opt,
+                     fnn_csr **out)
+{
+    if (!out)
+        return set_err(FNN_EINVAL, "out is NULL");
+    *out = nullptr;
+    CsrBox *B = nullptr;
+    try {
+        if (!tree || tree->kind != KIND_TREE)
+            fail(FNN_EINVAL, "not a tree handle");
+        if (!(eps > 0.0) || !isfinite(eps))
+            fail(FNN_EINVAL, "eps must be finite and > 0");
+        Options o = read_options(opt);
+        B = new CsrBox();
+        memset(&B->pub, 0, sizeof B->pub);
+        memset(&B->stats, 0, sizeof B->stats);
+        B->pub.kind = KIND_CSR;
+        Scratch S(current_stream());
+        eps_graph(tree, eps, o, &B->pub, B->stats, S);
+        *out = &B->pub;
+        return FNN_OK;
+    } catch (const Error &e) {
+        if (B) {
+            out_free(B->pub.row_ptr);
+            out_free(B->pub.col);
+            out_free(B->pub.dist);
+            delete B;
+        }
+        return set_err(e.code, e.msg);
+    } catch (...) {
+        if (B) {
+            out_free(B->pub.row_ptr);
+            out_free(B->pub.col);
+            out_free(B->pub.dist);
+            delete B;
+        }
+        return set_err(FNN_EINTERNAL, "unexpected exception");
+    }
+}
+
+int fnn_eps_graph(const fnn_tree *tree, double eps, fnn_csr **out)
+{
+    return fnn_eps_graph_ex(tree, eps, nullptr, out);
+}
+
+void fnn_free(void *handle)
+{
+    if (!handle)
+        return;
+    uint32_t kind = *(const uint32_t *)handle;
+    if (kind == KIND_TREE) {
+        fnn_tree *T = (fnn_tree *)handle;
+        T->kind = 0;
+        delete T;
+    } else if (kind == KIND_CSR) {
+        CsrBox *B = (CsrBox *)handle;  // pub is the first member
+        out_free(B->pub.row_ptr);
+        out_free(B->pub.col);
+        out_free(B->pub.dist);
+        B->pub.kind = 0;
+        delete B;
+    }
+}
+
+int fnn_get_stats(const void *handle, fnn_stats *out)
+{
+    if (!handle || !out)
+        return set_err(FNN_EINVAL, "NULL argument");
+    uint32_t kind = *(const uint32_t *)handle;
+    if (kind == KIND_TREE)
+        *out = ((const fnn_tree *)handle)->stats;
+    else if (kind == KIND_CSR)
+        *out = ((const CsrBox *)handle)->stats;
+    else
+        return set_err(FNN_EINVAL, "not a library handle");
+    return FNN_OK;
+}
+
+int fnn_tree_info(const fnn_tree *tree, int64_t *n, int64_t *nodes)
+{
+    if (!tree || tree->kind != KIND_TREE)
+        return set_err(FNN_EINVAL, "not a tree handle");
+    if (n)
+        *n = tree->n;
+    if (nodes)
+        *nodes = tree->nnodes;
+    return FNN_OK;
+}
+
+int fnn_tree_export(const fnn_tree *T, int32_t *order, int32_t *center,
+                    float *radius, int32_t *level, int32_t *child_begin,
+                    int32_t *child_count, int32_t *pt_begin, int32_t *pt_end)
+{
+    if (!T || T->kind != KIND_TREE)
+        return set_err(FNN_EINVAL, "not a tree handle");
+    try {
+        hipStream_t s = current_stream();
+        const size_t nb = sizeof(int32_t) * (size_t)T->nnodes;
+        struct {
+            void *dst;
+            const void *src;
+            size_t bytes;
+        } cp[] = {{order, T->perm, sizeof(int32_t) * (size_t)T->n},
+                  {center, T->center, nb},
+                  {radius, T->radius, sizeof(float) * (size_t)T->nnodes},
+                  {level, T->level, nb},
+                  {child_begin, T->child_begin, nb},
+                  {child_count, T->child_count, nb},
+                  {pt_begin, T->pt_begin, nb},
+                  {pt_end, T->pt_end, nb}};
+        for (auto &c : cp)
+            if (c.dst)
+                FNN_HIP(hipMemcpyAsync(c.dst, c.src, c.bytes,
+                                       hipMemcpyDeviceToHost, s));
+        FNN_HIP(hipStreamSynchronize(s));
+        return FNN_OK;
+    } catch (const Error &e) {
+        return set_err(e.code, e.msg);
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,1090 @@
+// Level-wise batched cover-tree construction (Section IV-A; Algorithm 1
+// SplitVertex driven level by level as in Algorithm 2 BuildLevel), for every
+// hub of a level at once.
+//
+// Data layout.  Points stay in input order during the build; a permutation
+// perm[pos] keeps every hub's points contiguous (its segment).  Per
+// position: D = FP32 key to the currently assigned centre, L = index of that
+// centre within the hub's centre list (cent[hub_begin + j], input indices).
+//
+// One level ("round"):
+//  1. net selection, repeated passes over all active hubs:
+//       k_update  -- apply the centres accepted in the last pass (D <- min,
+//                    L <- argmin, strict '<' so ties stay with the earlier
+//                    centre), then report per 64-point chunk the farthest
+//                    point not yet within 2^{l-1} of its centre;
+//       k_select  -- per hub, accept up to kmax of those farthest points,
+//                    farthest first, each only if it is more than 2^{l-1}
+//                    from every centre accepted in the same pass.
+//     A hub stops when no point is farther than 2^{l-1} from its centre.
+//     Threshold decisions inside the FP32 rounding band are made in FP64.
+//  2. stable segmented partition of every hub by centre (radix sort on the
+//     child id), children become vertices one level down; children with
+//     more than zeta points (and nonzero radius) are next level's hubs.
+#include <float.h>
+#include <limits.h>
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+
+#include "tree.h"
+
+namespace fnn {
+
+constexpr int CH = 64;  // chunk of a hub handled by one wave
+
+// ------------------------------------------------------------ thresholds --
+
+static void round_out(double lo, double hi, float *flo, float *fhi)
+{
+    float a = (float)lo, b = (float)hi;
+    if ((double)a > lo)
+        a = nextafterf(a, -INFINITY);
+    if ((double)b < hi)
+        b = nextafterf(b, INFINITY);
+    *flo = a;
+    *fhi = b;
+}
+
+// Band of the FP32 key around the exact threshold key T (see common.h).
+static Thr band(int metric, int dp, double T, double p64)
+{
+    const double u = 1.0 / 16777216.0;
+    Thr t;
+    t.p64 = p64;
+    if (metric == M_L2) {
+        double b = 2.0 * (dp + 4) * u;
+        double a = (dp + 4) * 1e-37;
+        round_out(T * (1.0 - b) - a, T * (1.0 + b) + a, &t.lo, &t.hi);
+        if (!(t.lo < FLT_MAX))
+            t.lo = FLT_MAX;
+    } else {
+        double dl = T * 2.0 * (3.0 * dp + 24) * u + 16.0 * u * sqrt(T) + 1e-9;
+        round_out(T - dl, T + dl, &t.lo, &t.hi);
+    }
+    return t;
+}
+
+Thr make_thr_eps(int metric, int dp, double eps)
+{
+    if (metric == M_HAM || metric == M_LEV) {
+        Thr t;
+        double k = floor(eps);
+        if (k > 1e9)
+            k = 1e9;
+        t.lo = t.hi = (float)k;
+        t.p64 = k;
+        return t;
+    }
+    if (metric == M_L2) {
+        double E2 = eps * eps;
+        return band(metric, dp, E2, E2);
+    }
+    double C = eps >= M_PI ? -1.0 : cos(eps);
+    return band(metric, dp, 2.0 - 2.0 * C, C);
+}
+
+void make_level_table(int metric, int dp, LevelTab *tab)
+{
+    for (int i = 0; i < NLEV; ++i) {
+        int l = i - LOFF;
+        double tau = ldexp(1.0, l);
+        Thr t;
+        if (metric == M_HAM || metric == M_LEV) {
+            double k = floor(tau);
+            if (k > 1e9)
+                k = 1e9;
+            t.lo = t.hi = (float)k;
+            t.p64 = k;
+        } else if (metric == M_L2) {
+            double T = ldexp(1.0, 2 * l);
+            t = band(metric, dp, T, T);
+        } else {
+            double C = tau >= M_PI ? -1.0 : cos(tau);
+            t = band(metric, dp, 2.0 - 2.0 * C, C);
+        }
+        tab->t[i] = t;
+    }
+}
+
+// ------------------------------------------------------------- ingest ----
+
+__global__ void k_ingest_vec(const float *__restrict__ in, int n, int dim,
+                             int dp, int angular, float *__restrict__ x,
+                             float *__restrict__ xn, int *err)
+{
+    const int i = blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+    const int lane = threadIdx.x & (WAVE - 1);
+    if (i >= n)
+        return;
+    const float *r = in + (size_t)i * dim;
+    float *o = x + (size_t)i * dp;
+    float ss = 0.f;
+    bool bad = false;
+    for (int k = lane; k < dp; k += WAVE) {
+        float v = k < dim ? r[k] : 0.f;
+        bad |= !isfinite(v);
+        ss = fmaf(v, v, ss);
+        o[k] = v;
+    }
+    if (__any(bad)) {
+        if (lane == 0)
+            atomicOr(err, ERR_INPUT);
+        return;
+    }
+    if (angular) {
+        ss = wave_sum(ss);
+        if (!(ss > 0.f) || !isfinite(ss)) {
+            if (lane == 0)
+                atomicOr(err, ERR_INPUT);
+            return;
+        }
+        // unit row in FP32 (the key's error band allows for its rounding)
+        float inv = 1.0f / sqrtf(ss);
+        float *on = xn + (size_t)i * dp;
+        for (int k = lane; k < dp; k += WAVE)
+            on[k] = o[k] * inv;
+    }
+}
+
+__global__ void k_ingest_lev(const uint8_t *__restrict__ in, int n, int stride,
+                             int32_t *__restrict__ len, int *__restrict__ sigma,
+                             int *err)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    const uint8_t *r = in + (size_t)i * stride;
+    int l = 0, mx = -1;
+    while (l < stride && r[l] != 0xFF) {
+        mx = max(mx, (int)r[l]);
+        ++l;
+    }
+    len[i] = l;
+    if (mx >= MAX_SIGMA)
+        atomicOr(err, ERR_INPUT);
+    else if (mx >= 0)
+        atomicMax(sigma, mx + 1);
+}
+
+__global__ void k_peq(const uint8_t *__restrict__ s, const int32_t *__restrict__ len,
+                      int n, int stride, int sigma, int W,
+                      uint64_t *__restrict__ peq)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    uint64_t *o = peq + (size_t)i * sigma * W;
+    for (int k = 0; k < sigma * W; ++k)
+        o[k] = 0ull;
+    const uint8_t *r = s + (size_t)i * stride;
+    const int l = len[i];
+    for (int p = 0; p < l; ++p) {
+        int c = r[p];
+        if (c < sigma)
+            o[c * W + (p >> 6)] |= 1ull << (p & 63);
+    }
+}
+
+// --------------------------------------------------------------- root ----
+
+template <int M>
+__global__ void k_root_keys(Pts P, int32_t *__restrict__ perm,
+                            float *__restrict__ D, unsigned *__restrict__ kmax)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    float k = 0.f;
+    if (i < P.n) {
+        perm[i] = i;
+        k = key32<M>(P, i, 0);
+        D[i] = k;
+    }
+    k = wave_max(k);
+    if ((threadIdx.x & (WAVE - 1)) == 0)
+        atomicMax(kmax, __float_as_uint(k));
+}
+
+// -------------------------------------------------------------- chunks ---
+
+struct Hubs {
+    int32_t *node, *b, *e, *lvl, *m, *ma, *act, *cb, *ce, *kof;
+};
+
+__global__ void k_hub_sizes(const int32_t *__restrict__ b,
+                            const int32_t *__restrict__ e, int H,
+                            int32_t *__restrict__ nch, int32_t *__restrict__ sz)
+{
+    const int h = blockIdx.x * blockDim.x + threadIdx.x;
+    if (h >= H)
+        return;
+    int s = e[h] - b[h];
+    nch[h] = (s + CH - 1) / CH;
+    sz[h] = s;
+}
+
+__global__ void k_make_chunks(Hubs hb, int H, const int32_t *__restrict__ choff,
+                              const int32_t *__restrict__ itemoff,
+                              int32_t *__restrict__ ch_hub,
+                              int32_t *__restrict__ ch_s,
+                              int32_t *__restrict__ ch_e,
+                              int32_t *__restrict__ ch_k)
+{
+    const int h = blockIdx.x;
+    if (h >= H)
+        return;
+    const int c0 = choff[h], c1 = choff[h + 1];
+    const int b = hb.b[h], e = hb.e[h];
+    if (threadIdx.x == 0) {
+        hb.cb[h] = c0;
+        hb.ce[h] = c1;
+        hb.kof[h] = itemoff[h];
+    }
+    for (int c = c0 + threadIdx.x; c < c1; c += blockDim.x) {
+        int s = b + (c - c0) * CH;
+        ch_hub[c] = h;
+        ch_s[c] = s;
+        ch_e[c] = min(s + CH, e);
+        ch_k[c] = itemoff[h] + (c - c0) * CH;
+    }
+}
+
+__global__ void __launch_bounds__(CH)
+k_round_init(const int32_t *__restrict__ ch_s, const int32_t *__restrict__ ch_e,
+             const int32_t *__restrict__ ch_k, int32_t *__restrict__ L,
+             int32_t *__restrict__ hpos)
+{
+    const int c = blockIdx.x;
+    const int p = ch_s[c] + threadIdx.x;
+    if (p < ch_e[c]) {
+        L[p] = 0;
+        hpos[ch_k[c] + threadIdx.x] = p;
+    }
+}
+
+// ------------------------------------------------------ net selection ----
+
+__device__ __forceinline__ bool better(float d, int id, float d2, int id2)
+{
+    return d > d2 || (d == d2 && id < id2);
+}
+
+template <int M>
+__global__ void __launch_bounds__(CH)
+k_update(Pts P, const int32_t *__restrict__ ch_hub, const int32_t *__restrict__ ch_s,
+         const int32_t *__restrict__ ch_e, Hubs hb,
+         const int32_t *__restrict__ cent, const int32_t *__restrict__ perm,
+         float *__restrict__ D, int32_t *__restrict__ L,
+         const LevelTab *__restrict__ tab, float *__restrict__ cb_D,
+         int32_t *__restrict__ cb_id, unsigned long long *__restrict__ cnt)
+{
+    const int c = blockIdx.x;
+    const int h = ch_hub[c];
+    if (!hb.act[h])
+        return;
+    const int s = ch_s[c], e = ch_e[c];
+    const int p = s + threadIdx.x;
+    const bool valid = p < e;
+    const int b = hb.b[h];
+    const int j0 = hb.ma[h], j1 = hb.m[h];
+    float dv = -1.f;
+    int id = INT_MAX;
+    if (valid) {
+        const int o = perm[p];
+        float dcur = D[p];
+        int lcur = L[p];
+        for (int j = j0; j < j1; ++j) {
+            float k = key32<M>(P, o, cent[b + j]);
+            if (k < dcur) {
+                dcur = k;
+                lcur = j;
+            }
+        }
+        if (j1 > j0) {
+            D[p] = dcur;
+            L[p] = lcur;
+        }
+        const Thr T = tab->t[hb.lvl[h] - 1 + LOFF];
+        if (!within<M>(P, o, cent[b + lcur], dcur, T, cnt + 1)) {
+            dv = dcur;
+            id = o;
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        float d2 = __shfl_xor(dv, off, WAVE);
+        int i2 = __shfl_xor(id, off, WAVE);
+        if (better(d2, i2, dv, id)) {
+            dv = d2;
+            id = i2;
+        }
+    }
+    if (threadIdx.x == 0) {
+        cb_D[c] = dv;
+        cb_id[c] = id;
+        if (j1 > j0)
+            atomicAdd(cnt, (unsigned long long)(j1 - j0) * (unsigned)(e - s));
+    }
+}
+
+constexpr int SEL_T = 256;
+constexpr int MAX_K = 64;
+
+template <int M>
+__global__ void __launch_bounds__(SEL_T)
+k_select(Pts P, Hubs hb, int32_t *__restrict__ cent, float *__restrict__ cb_D,
+         const int32_t *__restrict__ cb_id, const LevelTab *__restrict__ tab,
+         int kmax, int32_t *__restrict__ n_active,
+         unsigned long long *__restrict__ cnt)
+{
+    const int h = blockIdx.x;
+    if (!hb.act[h])
+        return;
+    __shared__ int acc[MAX_K];
+    __shared__ int nacc, ok;
+    __shared__ float rd[SEL_T / WAVE];
+    __shared__ int ri[SEL_T / WAVE], rc[SEL_T / WAVE];
+    __shared__ float bd_s;
+    __shared__ int bid_s, bc_s;
+    const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
+    const int c0 = hb.cb[h], c1 = hb.ce[h];
+    const int b = hb.b[h], m0 = hb.m[h];
+    const Thr T = tab->t[hb.lvl[h] - 1 + LOFF];
+    if (threadIdx.x == 0)
+        nacc = 0;
+    __syncthreads();
+    for (int it = 0; it < kmax; ++it) {
+        float bd = -1.f;
+        int bid = INT_MAX, bc = -1;
+        for (int c = c0 + threadIdx.x; c < c1; c += SEL_T) {
+            float d = cb_D[c];
+            int id = cb_id[c];
+            if (d >= 0.f && better(d, id, bd, bid)) {
+                bd = d;
+                bid = id;
+                bc = c;
+            }
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            float d2 = __shfl_xor(bd, off, WAVE);
+            int i2 = __shfl_xor(bid, off, WAVE);
+            int c2 = __shfl_xor(bc, off, WAVE);
+            if (better(d2, i2, bd, bid)) {
+                bd = d2;
+                bid = i2;
+                bc = c2;
+            }
+        }
+        if (lane == 0) {
+            rd[wid] = bd;
+            ri[wid] = bid;
+            rc[wid] = bc;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int w = 1; w < SEL_T / WAVE; ++w)
+                if (better(rd[w], ri[w], bd, bid)) {
+                    bd = rd[w];
+                    bid = ri[w];
+                    bc = rc[w];
+                }
+            bd_s = bd;
+            bid_s = bid;
+            bc_s = bc;
+            ok = 1;
+        }
+        __syncthreads();
+        if (bd_s < 0.f)
+            break;
+        const int cand = bid_s;
+        const int na = nacc;
+        for (int a = threadIdx.x; a < na; a += SEL_T) {
+            float k = key32<M>(P, cand, acc[a]);
+            if (within<M>(P, cand, acc[a], k, T, cnt + 1))
+                ok = 0;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            if (ok && nacc < MAX_K)
+                acc[nacc++] = cand;
+            cb_D[bc_s] = -1.f;
+            if (na > 0)
+                atomicAdd(cnt, (unsigned long long)na);
+        }
+        __syncthreads();
+    }
+    for (int a = threadIdx.x; a < nacc; a += SEL_T)
+        cent[b + m0 + a] = acc[a];
+    if (threadIdx.x == 0) {
+        hb.ma[h] = m0;
+        hb.m[h] = m0 + nacc;
+        if (nacc == 0)
+            hb.act[h] = 0;
+        else
+            atomicAdd(n_active, 1);
+    }
+}
+
+// ----------------------------------------------------------- partition ---
+
+__global__ void __launch_bounds__(CH)
+k_part_keys(const int32_t *__restrict__ ch_hub, const int32_t *__restrict__ ch_s,
+            const int32_t *__restrict__ ch_e, const int32_t *__restrict__ ch_k,
+            const int32_t *__restrict__ child_base,
+            const int32_t *__restrict__ L, uint32_t *__restrict__ key,
+            uint32_t *__restrict__ val)
+{
+    const int c = blockIdx.x;
+    const int p = ch_s[c] + threadIdx.x;
+    if (p < ch_e[c]) {
+        const int k = ch_k[c] + threadIdx.x;
+        key[k] = (uint32_t)(child_base[ch_hub[c]] + L[p]);
+        val[k] = (uint32_t)p;
+    }
+}
+
+__global__ void k_part_gather(const uint32_t *__restrict__ src, int NH,
+                              const int32_t *__restrict__ perm,
+                              const float *__restrict__ D,
+                              int32_t *__restrict__ tperm, float *__restrict__ tD)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= NH)
+        return;
+    const int s = (int)src[k];
+    tperm[k] = perm[s];
+    tD[k] = D[s];
+}
+
+__global__ void k_part_store(const uint32_t *__restrict__ skey, int NH,
+                             const int32_t *__restrict__ hpos,
+                             const int32_t *__restrict__ tperm,
+                             const float *__restrict__ tD,
+                             int32_t *__restrict__ perm, float *__restrict__ D,
+                             int32_t *__restrict__ cfirst,
+                             int32_t *__restrict__ clast,
+                             unsigned *__restrict__ ckmax)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool valid = k < NH;
+    uint32_t key = valid ? skey[k] : 0xFFFFFFFFu;
+    float d = 0.f;
+    if (valid) {
+        const int p = hpos[k];
+        perm[p] = tperm[k];
+        d = tD[k];
+        D[p] = d;
+        if (k == 0 || skey[k - 1] != key)
+            cfirst[key] = p;
+        if (k == NH - 1 || skey[k + 1] != key)
+            clast[key] = p;
+    }
+    // wave-aggregated maximum when the whole wave belongs to one child
+    const uint32_t k0 = __shfl(key, 0, WAVE);
+    const bool same = __all(key == k0);
+    if (same) {
+        float m = wave_max(d);
+        if ((threadIdx.x & (WAVE - 1)) == 0 && k0 != 0xFFFFFFFFu)
+            atomicMax(&ckmax[k0], __float_as_uint(m));
+    } else if (valid) {
+        atomicMax(&ckmax[key], __float_as_uint(d));
+    }
+}
+
+struct NodeArrays {
+    int32_t *center, *level, *cbeg, *ccnt, *pb, *pe;
+    float *radius;
+};
+
+__global__ void k_children(Hubs hb, int H, int metric, int dp, int zeta,
+                           int node_base, const int32_t *__restrict__ child_base,
+                           const int32_t *__restrict__ cent,
+                           const int32_t *__restrict__ cfirst,
+                           const int32_t *__restrict__ clast,
+                           const unsigned *__restrict__ ckmax, NodeArrays nd,
+                           int32_t *__restrict__ hubflag)
+{
+    const int h = blockIdx.x;
+    if (h >= H)
+        return;
+    const int b = hb.b[h], m = hb.m[h], lv = hb.lvl[h];
+    const int cb = child_base[h];
+    if (threadIdx.x == 0) {
+        const int v = hb.node[h];
+        nd.cbeg[v] = node_base + cb;
+        nd.ccnt[v] = m;
+    }
+    for (int j = threadIdx.x; j < m; j += blockDim.x) {
+        const int g = cb + j;
+        const int v = node_base + g;
+        const int pb = cfirst[g], pe = clast[g] + 1;
+        const float km = __uint_as_float(ckmax[g]);
+        const float r = radius_from_key(metric, dp, km);
+        int l = lv - 1;
+        if (r > 0.f)
+            l = min(level_of(r), lv - 1);
+        nd.center[v] = cent[b + j];
+        nd.radius[v] = r;
+        nd.level[v] = l;
+        nd.pb[v] = pb;
+        nd.pe[v] = pe;
+        nd.cbeg[v] = 0;
+        nd.ccnt[v] = 0;
+        hubflag[g] = (pe - pb > zeta && km > 0.f) ? 1 : 0;
+    }
+}
+
+__global__ void k_next_hubs(int C, int node_base,
+                            const int32_t *__restrict__ flag,
+                            const int32_t *__restrict__ fscan, NodeArrays nd,
+                            Hubs nh, int32_t *__restrict__ cent)
+{
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= C || !flag[g])
+        return;
+    const int q = fscan[g];
+    const int v = node_base + g;
+    nh.node[q] = v;
+    nh.b[q] = nd.pb[v];
+    nh.e[q] = nd.pe[v];
+    nh.lvl[q] = nd.level[v];
+    nh.m[q] = 1;
+    nh.ma[q] = 1;
+    nh.act[q] = 1;
+    cent[nd.pb[v]] = nd.center[v];
+}
+
+// ------------------------------------------------------------ finalize ---
+
+__global__ void k_inverse(const int32_t *__restrict__ perm, int n,
+                          int32_t *__restrict__ inv)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < n)
+        inv[perm[p]] = p;
+}
+
+__global__ void k_center_pos(const int32_t *__restrict__ center,
+                             const int32_t *__restrict__ inv, int nn,
+                             int32_t *__restrict__ cpos)
+{
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < nn)
+        cpos[v] = inv[center[v]];
+}
+
+template <class T>
+__global__ void k_gather_rows(const T *__restrict__ in, const int32_t *__restrict__ perm,
+                              int n, int stride, T *__restrict__ out)
+{
+    const int p = blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+    const int lane = threadIdx.x & (WAVE - 1);
+    if (p >= n)
+        return;
+    const T *r = in + (size_t)perm[p] * stride;
+    T *o = out + (size_t)p * stride;
+    for (int k = lane; k < stride; k += WAVE)
+        o[k] = r[k];
+}
+
+// ---- query tree: packs of consecutive sibling leaf blocks ----------------
+
+__global__ void k_qt_count(int nn, const int32_t *__restrict__ ccnt,
+                           const int32_t *__restrict__ cbeg,
+                           const int32_t *__restrict__ pb,
+                           const int32_t *__restrict__ pe, int P,
+                           int32_t *__restrict__ npk, int32_t *__restrict__ nqk)
+{
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= nn)
+        return;
+    const int cc = ccnt[v];
+    int packs = 0, kids = 0, run = -1;
+    for (int a = 0; a < cc; ++a) {
+        const int u = cbeg[v] + a;
+        if (ccnt[u] > 0) {
+            ++kids;
+            run = -1;
+            continue;
+        }
+        const int sz = pe[u] - pb[u];
+        if (run >= 0 && run + sz <= P) {
+            run += sz;
+        } else {
+            ++packs;
+            ++kids;
+            run = sz;
+        }
+    }
+    npk[v] = packs;
+    nqk[v] = kids;
+}
+
+__global__ void k_qt_fill(int nn, const int32_t *__restrict__ ccnt,
+                          const int32_t *__restrict__ cbeg,
+                          const int32_t *__restrict__ pb,
+                          const int32_t *__restrict__ pe,
+                          const int32_t *__restrict__ cpos,
+                          const float *__restrict__ radius, int P,
+                          const int32_t *__restrict__ pkoff,
+                          const int32_t *__restrict__ kidoff,
+                          int32_t *__restrict__ q_cpos, float *__restrict__ q_rad,
+                          int32_t *__restrict__ q_pb, int32_t *__restrict__ q_pe,
+                          int32_t *__restrict__ q_kbeg,
+                          int32_t *__restrict__ q_kcnt,
+                          int32_t *__restrict__ q_kids)
+{
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= nn)
+        return;
+    const int cc = ccnt[v];
+    // internal vertices keep their own attributes; leaf blocks are not
+    // query-tree vertices (they live inside packs)
+    q_cpos[v] = cpos[v];
+    q_rad[v] = radius[v];
+    q_pb[v] = pb[v];
+    q_pe[v] = pe[v];
+    q_kbeg[v] = kidoff[v];
+    q_kcnt[v] = kidoff[v + 1] - kidoff[v];
+    if (cc == 0)
+        return;
+    int pk = nn + pkoff[v] - 1;  // id of the current pack
+    int kd = kidoff[v];
+    int run = -1;
+    for (int a = 0; a < cc; ++a) {
+        const int u = cbeg[v] + a;
+        if (ccnt[u] > 0) {
+            q_kids[kd++] = u;
+            run = -1;
+            continue;
+        }
+        const int sz = pe[u] - pb[u];
+        if (run >= 0 && run + sz <= P) {
+            run += sz;
+            q_pe[pk] = pe[u];
+        } else {
+            ++pk;
+            q_kids[kd++] = pk;
+            run = sz;
+            q_cpos[pk] = cpos[u];
+            q_pb[pk] = pb[u];
+            q_pe[pk] = pe[u];
+            q_kbeg[pk] = 0;
+            q_kcnt[pk] = 0;
+            q_rad[pk] = 0.f;
+        }
+    }
+}
+
+// Radius of each pack: the largest key from its centre to its points.
+template <int M>
+__global__ void k_pack_radius(Pts P, int first, int npk,
+                              const int32_t *__restrict__ q_cpos,
+                              const int32_t *__restrict__ q_pb,
+                              const int32_t *__restrict__ q_pe, int dp,
+                              float *__restrict__ q_rad)
+{
+    const int k = blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+    const int lane = threadIdx.x & (WAVE - 1);
+    if (k >= npk)
+        return;
+    const int q = first + k;
+    const int c = q_cpos[q];
+    float m = 0.f;
+    for (int p = q_pb[q] + lane; p < q_pe[q]; p += WAVE)
+        m = fmaxf(m, key32<M>(P, c, p));
+    m = wave_max(m);
+    if (lane == 0)
+        q_rad[q] = radius_from_key(M, dp, m);
+}
+
+// -------------------------------------------------------------- driver ---
+
+static int bitlen(uint32_t v)
+{
+    int b = 0;
+    while (v) {
+        ++b;
+        v >>= 1;
+    }
+    return b;
+}
+
+template <int M>
+static void build_impl(fnn_tree *T, const void *points, Scratch &S)
+{
+    hipStream_t st = S.stream();
+    const int n = (int)T->n;
+    int *err = S.get<int>(1);
+    fill(err, 0, 1, st);
+    unsigned long long *cnt = S.get<unsigned long long>(4);
+    fill(cnt, 0ull, 4, st);
+
+    hipEvent_t ev0, ev1;
+    FNN_HIP(hipEventCreate(&ev0));
+    FNN_HIP(hipEventCreate(&ev1));
+    FNN_HIP(hipEventRecord(ev0, st));
+
+    // ---- ingest (input order) -------------------------------------------
+    Pts P{};
+    P.metric = M;
+    P.n = n;
+    P.dim = T->dim;
+    P.dp = T->dp;
+    float *x_in = nullptr, *xn_in = nullptr;
+    if (M == M_L2 || M == M_ANG) {
+        x_in = S.get<float>((size_t)n * T->dp);
+        if (M == M_ANG)
+            xn_in = S.get<float>((size_t)n * T->dp);
+        hipLaunchKernelGGL(k_ingest_vec, dim3(cdiv(n, 4)), dim3(256), 0, st,
+                           (const float *)points, n, T->dim, T->dp,
+                           M == M_ANG ? 1 : 0, x_in, xn_in, err);
+        P.x = x_in;
+        P.xn = xn_in;
+    } else if (M == M_HAM) {
+        P.h = (const uint64_t *)points;
+    } else {
+        int32_t *len_in = S.get<int32_t>(n);
+        int *sig = S.get<int>(1);
+        fill(sig, 1, 1, st);
+        hipLaunchKernelGGL(k_ingest_lev, dim3(cdiv(n, 256)), dim3(256), 0, st,
+                           (const uint8_t *)points, n, T->dim, len_in, sig, err);
+        int e = read_scalar(err, st);
+        if (e)
+            fail(FNN_EINVAL, "Levenshtein input has a symbol >= %d", MAX_SIGMA);
+        T->sigma = read_scalar(sig, st);
+        T->W = (T->dim + 63) / 64;
+        uint64_t *peq_in = S.get<uint64_t>((size_t)n * T->sigma * T->W);
+        hipLaunchKernelGGL(k_peq, dim3(cdiv(n, 256)), dim3(256), 0, st,
+                           (const uint8_t *)points, len_in, n, T->dim, T->sigma,
+                           T->W, peq_in);
+        P.s = (const uint8_t *)points;
+        P.len = len_in;
+        P.peq = peq_in;
+        P.sigma = T->sigma;
+        P.W = T->W;
+    }
+    {
+        int e = read_scalar(err, st);
+        if (e & ERR_INPUT)
+            fail(FNN_EINVAL, M == M_ANG ? "input has a NaN/Inf coordinate or a zero row"
+                                        : "input has a NaN/Inf coordinate");
+    }
+
+    LevelTab htab;
+    make_level_table(M, T->dp, &htab);
+    LevelTab *tab = S.get<LevelTab>(1);
+    FNN_HIP(hipMemcpyAsync(tab, &htab, sizeof(LevelTab), hipMemcpyHostToDevice,
+                           st));
+
+    // ---- node arrays (at most 2n - 1 vertices) ------------------------------
+    const size_t cap = 2 * (size_t)n + 1;
+    NodeArrays nd;
+    nd.center = S.get<int32_t>(cap);
+    nd.level = S.get<int32_t>(cap);
+    nd.cbeg = S.get<int32_t>(cap);
+    nd.ccnt = S.get<int32_t>(cap);
+    nd.pb = S.get<int32_t>(cap);
+    nd.pe = S.get<int32_t>(cap);
+    nd.radius = S.get<float>(cap);
+
+    int32_t *perm = S.get<int32_t>(n);
+    float *D = S.get<float>(n);
+    int32_t *L = S.get<int32_t>(n);
+    int32_t *cent = S.get<int32_t>(n);
+    int32_t *hpos = S.get<int32_t>(n);
+    int32_t *tperm = S.get<int32_t>(n);
+    float *tD = S.get<float>(n);
+    uint32_t *key = S.get<uint32_t>(n), *val = S.get<uint32_t>(n);
+    uint32_t *skey = S.get<uint32_t>(n), *sval = S.get<uint32_t>(n);
+    int32_t *cfirst = S.get<int32_t>(n), *clast = S.get<int32_t>(n);
+    unsigned *ckmax = S.get<unsigned>(n + 1);
+    int32_t *hubflag = S.get<int32_t>(n + 1), *fscan = S.get<int32_t>(n + 2);
+    const int maxch = (int)cdiv(n, CH) + n / 2 + 2;  // chunks over all hubs
+    int32_t *ch_hub = S.get<int32_t>(maxch), *ch_s = S.get<int32_t>(maxch),
+            *ch_e = S.get<int32_t>(maxch), *ch_k = S.get<int32_t>(maxch);
+    float *cb_D = S.get<float>(maxch);
+    int32_t *cb_id = S.get<int32_t>(maxch);
+    int32_t *n_active = S.get<int32_t>(1);
+
+    auto alloc_hubs = [&](int cnt_) {
+        Hubs hb;
+        hb.node = S.get<int32_t>(cnt_);
+        hb.b = S.get<int32_t>(cnt_);
+        hb.e = S.get<int32_t>(cnt_);
+        hb.lvl = S.get<int32_t>(cnt_);
+        hb.m = S.get<int32_t>(cnt_);
+        hb.ma = S.get<int32_t>(cnt_);
+        hb.act = S.get<int32_t>(cnt_);
+        hb.cb = S.get<int32_t>(cnt_);
+        hb.ce = S.get<int32_t>(cnt_);
+        hb.kof = S.get<int32_t>(cnt_);
+        return hb;
+    };
+    const int hub_cap = n / 2 + 2;  // every hub holds more than zeta >= 1 points
+    Hubs hubs = alloc_hubs(hub_cap), nhubs = alloc_hubs(hub_cap);
+    int32_t *nch = S.get<int32_t>(hub_cap + 1), *hsz = S.get<int32_t>(hub_cap + 1);
+    int32_t *choff = S.get<int32_t>(hub_cap + 2), *itemoff = S.get<int32_t>(hub_cap + 2);
+    int32_t *child_base = S.get<int32_t>(hub_cap + 2);
+
+    // ---- root: D[p] = d(p, p_0) (Algorithm 1's pre-initialised D) ---------
+    unsigned *rk = S.get<unsigned>(1);
+    fill(rk, 0u, 1, st);
+    hipLaunchKernelGGL((k_root_keys<M>), dim3(cdiv(n, 256)), dim3(256), 0, st,
+                       P, perm, D, rk);
+    const unsigned r0bits = read_scalar(rk, st);
+    float r0key;
+    memcpy(&r0key, &r0bits, sizeof r0key);
+    const float r0 = radius_from_key(M, T->dp, r0key);
+    const int l0 = r0 > 0.f ? level_of(r0) : 0;
+    // host staging values stay alive until the synchronisation below
+    int32_t h0[7] = {0, l0, 0, 0, 0, n, 0};
+    int32_t one[10] = {0, 0, n, l0, 1, 1, 1, 0, 0, 0};
+    int32_t zero = 0;
+    {
+        // root vertex: centre 0, all points
+        FNN_HIP(hipMemcpyAsync(nd.center, &h0[0], 4, hipMemcpyHostToDevice, st));
+        FNN_HIP(hipMemcpyAsync(nd.level, &h0[1], 4, hipMemcpyHostToDevice, st));
+        FNN_HIP(hipMemcpyAsync(nd.cbeg, &h0[2], 4, hipMemcpyHostToDevice, st));
+        FNN_HIP(hipMemcpyAsync(nd.ccnt, &h0[3], 4, hipMemcpyHostToDevice, st));
+        FNN_HIP(hipMemcpyAsync(nd.pb, &h0[4], 4, hipMemcpyHostToDevice, st));
+        FNN_HIP(hipMemcpyAsync(nd.pe, &h0[5], 4, hipMemcpyHostToDevice, st));
+        FNN_HIP(hipMemcpyAsync(nd.radius, &r0, 4, hipMemcpyHostToDevice, st));
+    }
+    int H = 0;
+    int64_t node_count = 1;
+    if (n > T->opt.zeta && r0key > 0.f) {
+        int32_t *dst[10] = {hubs.node, hubs.b, hubs.e, hubs.lvl, hubs.m,
+                            hubs.ma, hubs.act, hubs.cb, hubs.ce, hubs.kof};
+        for (int i = 0; i < 10; ++i)
+            FNN_HIP(hipMemcpyAsync(dst[i], &one[i], 4, hipMemcpyHostToDevice, st));
+        FNN_HIP(hipMemcpyAsync(cent, &zero, 4, hipMemcpyHostToDevice, st));
+        H = 1;
+    }
+    FNN_HIP(hipStreamSynchronize(st));
+
+    int rounds = 0, passes = 0;
+    while (H > 0) {
+        ++rounds;
+        // chunk table of this level's hubs
+        hipLaunchKernelGGL(k_hub_sizes, dim3(cdiv(H, 256)), dim3(256), 0, st,
+                           hubs.b, hubs.e, H, nch, hsz);
+        scan_i32(nch, choff, H, S);
+        scan_i32(hsz, itemoff, H, S);
+        int32_t tot[2];
+        FNN_HIP(hipMemcpyAsync(&tot[0], choff + H, 4, hipMemcpyDeviceToHost, st));
+        FNN_HIP(hipMemcpyAsync(&tot[1], itemoff + H, 4, hipMemcpyDeviceToHost, st));
+        FNN_HIP(hipStreamSynchronize(st));
+        const int NC = tot[0], NH = tot[1];
+        if (NC > maxch || NH > n)
+            fail(FNN_EINTERNAL, "chunk table overflow (%d > %d)", NC, maxch);
+        hipLaunchKernelGGL(k_make_chunks, dim3(H), dim3(64), 0, st, hubs, H,
+                           choff, itemoff, ch_hub, ch_s, ch_e, ch_k);
+        hipLaunchKernelGGL(k_round_init, dim3(NC), dim3(CH), 0, st, ch_s, ch_e,
+                           ch_k, L, hpos);
+
+        // ---- net selection passes ----------------------------------------
+        for (;;) {
+            ++passes;
+            fill(n_active, 0, 1, st);
+            hipLaunchKernelGGL((k_update<M>), dim3(NC), dim3(CH), 0, st, P,
+                               ch_hub, ch_s, ch_e, hubs, cent, perm, D, L, tab,
+                               cb_D, cb_id, cnt);
+            hipLaunchKernelGGL((k_select<M>), dim3(H), dim3(SEL_T), 0, st, P,
+                               hubs, cent, cb_D, cb_id, tab, T->opt.kmax,
+                               n_active, cnt);
+            if (read_scalar(n_active, st) == 0)
+                break;
+        }
+
+        // ---- partition into children ---------------------------------------
+        scan_i32(hubs.m, child_base, H, S);
+        const int C = read_scalar(child_base + H, st);
+        if (node_count + C > (int64_t)cap)
+            fail(FNN_EINTERNAL, "vertex capacity exceeded");
+        hipLaunchKernelGGL(k_part_keys, dim3(NC), dim3(CH), 0, st, ch_hub, ch_s,
+                           ch_e, ch_k, child_base, L, key, val);
+        radix_sort_pairs(key, val, skey, sval, NH, bitlen((uint32_t)C), S);
+        hipLaunchKernelGGL(k_part_gather, dim3(cdiv(NH, 256)), dim3(256), 0, st,
+                           sval, NH, perm, D, tperm, tD);
+        fill(ckmax, 0u, C, st);
+        hipLaunchKernelGGL(k_part_store, dim3(cdiv(NH, 256)), dim3(256), 0, st,
+                           skey, NH, hpos, tperm, tD, perm, D, cfirst, clast,
+                           ckmax);
+        hipLaunchKernelGGL(k_children, dim3(H), dim3(64), 0, st, hubs, H, M,
+                           T->dp, T->opt.zeta, (int)node_count, child_base, cent,
+                           cfirst, clast, ckmax, nd, hubflag);
+        scan_i32(hubflag, fscan, C, S);
+        const int Hn = read_scalar(fscan + C, st);
+        if (Hn > hub_cap)
+            fail(FNN_EINTERNAL, "hub capacity exceeded");
+        hipLaunchKernelGGL(k_next_hubs, dim3(cdiv(C, 256)), dim3(256), 0, st, C,
+                           (int)node_count, hubflag, fscan, nd, nhubs, cent);
+        node_count += C;
+        std::swap(hubs, nhubs);
+        H = Hn;
+    }
+
+    // ---- finalize: tree order, vertex centre positions ------------------
+    const int nn = (int)node_count;
+    T->nnodes = nn;
+    T->perm = (int32_t *)T->own(sizeof(int32_t) * n);
+    FNN_HIP(hipMemcpyAsync(T->perm, perm, sizeof(int32_t) * n,
+                           hipMemcpyDeviceToDevice, st));
+    int32_t *inv = S.get<int32_t>(n);
+    hipLaunchKernelGGL(k_inverse, dim3(cdiv(n, 256)), dim3(256), 0, st, perm, n,
+                       inv);
+    T->center = (int32_t *)T->own(sizeof(int32_t) * nn);
+    T->center_pos = (int32_t *)T->own(sizeof(int32_t) * nn);
+    T->radius = (float *)T->own(sizeof(float) * nn);
+    T->level = (int32_t *)T->own(sizeof(int32_t) * nn);
+    T->child_begin = (int32_t *)T->own(sizeof(int32_t) * nn);
+    T->child_count = (int32_t *)T->own(sizeof(int32_t) * nn);
+    T->pt_begin = (int32_t *)T->own(sizeof(int32_t) * nn);
+    T->pt_end = (int32_t *)T->own(sizeof(int32_t) * nn);
+    auto cp = [&](void *dst, const void *src, size_t b) {
+        FNN_HIP(hipMemcpyAsync(dst, src, b, hipMemcpyDeviceToDevice, st));
+    };
+    cp(T->center, nd.center, 4 * (size_t)nn);
+    cp(T->radius, nd.radius, 4 * (size_t)nn);
+    cp(T->level, nd.level, 4 * (size_t)nn);
+    cp(T->child_begin, nd.cbeg, 4 * (size_t)nn);
+    cp(T->child_count, nd.ccnt, 4 * (size_t)nn);
+    cp(T->pt_begin, nd.pb, 4 * (size_t)nn);
+    cp(T->pt_end, nd.pe, 4 * (size_t)nn);
+    hipLaunchKernelGGL(k_center_pos, dim3(cdiv(nn, 256)), dim3(256), 0, st,
+                       nd.center, inv, nn, T->center_pos);
+
+    // point data in tree order
+    Pts Q = P;
+    if (M == M_L2 || M == M_ANG) {
+        T->x = (float *)T->own(sizeof(float) * (size_t)n * T->dp);
+        hipLaunchKernelGGL((k_gather_rows<float>), dim3(cdiv(n, 4)), dim3(256), 0,
+                           st, x_in, perm, n, T->dp, T->x);
+        Q.x = T->x;
+        if (M == M_ANG) {
+            T->xn = (float *)T->own(sizeof(float) * (size_t)n * T->dp);
+            hipLaunchKernelGGL((k_gather_rows<float>), dim3(cdiv(n, 4)),
+                               dim3(256), 0, st, xn_in, perm, n, T->dp, T->xn);
+            Q.xn = T->xn;
+        }
+    } else if (M == M_HAM) {
+        T->h = (uint64_t *)T->own(sizeof(uint64_t) * (size_t)n * T->dp);
+        hipLaunchKernelGGL((k_gather_rows<uint64_t>), dim3(cdiv(n, 4)),
+                           dim3(256), 0, st, P.h, perm, n, T->dp, T->h);
+        Q.h = T->h;
+    } else {
+        T->s = (uint8_t *)T->own((size_t)n * T->dp);
+        T->len = (int32_t *)T->own(sizeof(int32_t) * n);
+        T->peq = (uint64_t *)T->own(sizeof(uint64_t) * (size_t)n * T->sigma * T->W);
+        hipLaunchKernelGGL((k_gather_rows<uint8_t>), dim3(cdiv(n, 4)), dim3(256),
+                           0, st, P.s, perm, n, T->dp, T->s);
+        hipLaunchKernelGGL((k_gather_rows<int32_t>), dim3(cdiv(n, 4)), dim3(256),
+                           0, st, P.len, perm, n, 1, T->len);
+        hipLaunchKernelGGL((k_gather_rows<uint64_t>), dim3(cdiv(n, 4)),
+                           dim3(256), 0, st, P.peq, perm, n, T->sigma * T->W,
+                           T->peq);
+        Q.s = T->s;
+        Q.len = T->len;
+        Q.peq = T->peq;
+    }
+
+    // ---- query tree with packs ------------------------------------------
+    const int PK = T->opt.pack;
+    int32_t *npk = S.get<int32_t>(nn + 1), *nqk = S.get<int32_t>(nn + 1);
+    int32_t *pkoff = S.get<int32_t>(nn + 2), *kidoff = S.get<int32_t>(nn + 2);
+    hipLaunchKernelGGL(k_qt_count, dim3(cdiv(nn, 256)), dim3(256), 0, st, nn,
+                       nd.ccnt, nd.cbeg, nd.pb, nd.pe, PK, npk, nqk);
+    scan_i32(npk, pkoff, nn, S);
+    scan_i32(nqk, kidoff, nn, S);
+    int32_t tots[2];
+    FNN_HIP(hipMemcpyAsync(&tots[0], pkoff + nn, 4, hipMemcpyDeviceToHost, st));
+    FNN_HIP(hipMemcpyAsync(&tots[1], kidoff + nn, 4, hipMemcpyDeviceToHost, st));
+    FNN_HIP(hipStreamSynchronize(st));
+    int npacks = tots[0], nkids = tots[1];
+    const bool root_leaf = (nn == 1);
+    if (root_leaf)
+        npacks = 1;
+    const int nq = nn + npacks;
+    T->npacks = npacks;
+    T->nq = nq;
+    T->q_center_pos = (int32_t *)T->own(sizeof(int32_t) * nq);
+    T->q_radius = (float *)T->own(sizeof(float) * nq);
+    T->q_pt_begin = (int32_t *)T->own(sizeof(int32_t) * nq);
+    T->q_pt_end = (int32_t *)T->own(sizeof(int32_t) * nq);
+    T->q_kbeg = (int32_t *)T->own(sizeof(int32_t) * nq);
+    T->q_kcnt = (int32_t *)T->own(sizeof(int32_t) * nq);
+    T->q_kids = (int32_t *)T->own(sizeof(int32_t) * (nkids + 1));
+    hipLaunchKernelGGL(k_qt_fill, dim3(cdiv(nn, 256)), dim3(256), 0, st, nn,
+                       nd.ccnt, nd.cbeg, nd.pb, nd.pe, T->center_pos, nd.radius, PK,
+                       pkoff, kidoff, T->q_center_pos, T->q_radius, T->q_pt_begin,
+                       T->q_pt_end, T->q_kbeg, T->q_kcnt, T->q_kids);
+    int32_t vals[5] = {0, n, 0, 0, 0};
+    if (root_leaf) {
+        // the whole set is one leaf block: one pack, the query tree's root
+        FNN_HIP(hipMemcpyAsync(T->q_center_pos + nn, T->center_pos, 4,
+                               hipMemcpyDeviceToDevice, st));
+        FNN_HIP(hipMemcpyAsync(T->q_pt_begin + nn, &vals[0], 4,
+                               hipMemcpyHostToDevice, st));
+        FNN_HIP(hipMemcpyAsync(T->q_pt_end + nn, &vals[1], 4,
+                               hipMemcpyHostToDevice, st));
+        FNN_HIP(hipMemcpyAsync(T->q_kbeg + nn, &vals[2], 4,
+                               hipMemcpyHostToDevice, st));
+        FNN_HIP(hipMemcpyAsync(T->q_kcnt + nn, &vals[3], 4,
+                               hipMemcpyHostToDevice, st));
+        T->qroot = nn;
+    } else {
+        T->qroot = 0;
+    }
+    if (npacks > 0)
+        hipLaunchKernelGGL((k_pack_radius<M>), dim3(cdiv(npacks, 4)), dim3(256),
+                           0, st, Q, nn, npacks, T->q_center_pos, T->q_pt_begin,
+                           T->q_pt_end, T->dp, T->q_radius);
+
+    FNN_HIP(hipEventRecord(ev1, st));
+    unsigned long long hc[4];
+    FNN_HIP(hipMemcpyAsync(hc, cnt, sizeof hc, hipMemcpyDeviceToHost, st));
+    FNN_HIP(hipStreamSynchronize(st));
+    float ms = 0.f;
+    FNN_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+    (void)hipEventDestroy(ev0);
+    (void)hipEventDestroy(ev1);
+    {
+        int e = read_scalar(err, st);
+        if (e & ERR_INDEX)
+            fail(FNN_EINTERNAL, "build index check failed");
+    }
+
+    fnn_stats &s = T->stats;
+    s.n = n;
+    s.nodes = nn;
+    s.packs = npacks;
+    s.rounds = rounds;
+    s.netsel_passes = passes;
+    s.build_dist_evals = (int64_t)(hc[0] + n);
+    s.fp64_rechecks = (int64_t)hc[1];
+    s.build_ms = ms;
+    s.total_ms = ms;
+    T->depth = rounds;
+}
+
+void build_tree(fnn_tree *T, const void *points, Scratch &S)
+{
+    switch (T->metric) {
+    case M_L2:
+        build_impl<M_L2>(T, points, S);
+        break;
+    case M_ANG:
+        build_impl<M_ANG>(T, points, S);
+        break;
+    case M_HAM:
+        build_impl<M_HAM>(T, points, S);
+        break;
+    default:
+        build_impl<M_LEV>(T, points, S);
+        break;
+    }
+}
+
+}  // namespace fnn

@@ -1,0 +1,863 @@
+// All-points range query over the cover tree (Section IV-B, Algorithm 3 run
+// for batches of queries) and CSR emission.
+//
+// Batched query.  A query batch is a query-tree vertex (a cover-tree vertex,
+// or a pack of consecutive sibling leaf blocks) with centre c and radius r
+// bounding its points.  A pair of vertices (A, B) can hold an edge only if
+// d(c_A, c_B) <= r_A + r_B + eps (triangle inequality, the pruning rule of
+// Algorithm 3 applied to two balls).  Starting from (root, root), surviving
+// pairs are expanded level by level on the GPU (the vertex with the larger
+// radius is split; a self pair (A, A) becomes all child pairs (a_i, a_j),
+// i <= j), until both sides are packs.  Each unordered pack pair is produced
+// once; its point pairs are then evaluated once and written to both rows.
+//
+// Leaf tiles.  64 x 64 point pairs per work-group step, register-blocked
+// 4 x 4 per thread, coordinates staged through LDS.  Every FP32 key outside
+// the rounding band of eps decides the edge directly; keys inside it are
+// decided by the FP64 reference predicate.
+//
+// Emission (plain schedule): count pass -> exclusive scan -> fill pass that
+// reserves each row's slots with one atomic per row per tile -> per-row sort
+// of the columns.
+#include <float.h>
+#include <limits.h>
+#include <math.h>
+
+#include <algorithm>
+
+#include "tree.h"
+
+namespace fnn {
+
+constexpr int TT = 256;   // threads per tile work-group
+constexpr int TS = 64;    // tile side
+constexpr int KC = 32;    // coordinates per LDS stage
+constexpr int LDA = 68;   // padded LDS row (floats)
+
+struct QView {
+    const int32_t *cpos, *pb, *pe, *kbeg, *kcnt, *kids;
+    const float *rad;
+    int nn;  // ids >= nn are packs
+};
+
+struct Prune {
+    float rel;   // relative slack on r_A + r_B + eps
+    float abs_;  // absolute slack
+    float eps;   // eps as a distance (floor(eps) for integer metrics)
+};
+
+template <int M>
+__device__ __forceinline__ bool may_touch(const Pts &P, const QView &Q,
+                                          const Prune &pr, int a, int b)
+{
+    const float k = key32<M>(P, Q.cpos[a], Q.cpos[b]);
+    const float d = key_to_dist<M>(k);
+    const float lim = Q.rad[a] + Q.rad[b] + pr.eps;
+    if constexpr (M == M_HAM || M == M_LEV)
+        return d <= lim;
+    else
+        return d <= lim * (1.f + pr.rel) + pr.abs_;
+}
+
+// ------------------------------------------------------------ traversal --
+
+struct Emit {
+    int2 *next;
+    int2 *inter;
+    unsigned long long *cnt;  // [0] next, [1] inter, [2] tests
+    long long next_cap, inter_cap;
+    int *overflow;
+};
+
+__device__ __forceinline__ void emit_pair(const Emit &E, const QView &Q,
+                                          bool valid, int a, int b)
+{
+    const int lane = threadIdx.x & (WAVE - 1);
+    const bool term = valid && a >= Q.nn && b >= Q.nn;
+    const bool nxt = valid && !term;
+    const uint64_t mt = __ballot(term), mn = __ballot(nxt);
+    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    unsigned long long bt = 0, bn = 0;
+    if (lane == 0) {
+        if (mt)
+            bt = atomicAdd(&E.cnt[1], (unsigned long long)__popcll(mt));
+        if (mn)
+            bn = atomicAdd(&E.cnt[0], (unsigned long long)__popcll(mn));
+    }
+    bt = __shfl(bt, 0, WAVE);
+    bn = __shfl(bn, 0, WAVE);
+    if (term) {
+        unsigned long long p = bt + __popcll(mt & lt);
+        if ((long long)p < E.inter_cap)
+            E.inter[p] = make_int2(a, b);
+        else
+            *E.overflow = 1;
+    }
+    if (nxt) {
+        unsigned long long p = bn + __popcll(mn & lt);
+        if ((long long)p < E.next_cap)
+            E.next[p] = make_int2(a, b);
+        else
+            *E.overflow = 1;
+    }
+}
+
+template <int M>
+__global__ void __launch_bounds__(256)
+k_expand(Pts P, QView Q, Prune pr, const int2 *__restrict__ cur, long long ncur,
+         Emit E)
+{
+    const long long w = (long long)blockIdx.x * (blockDim.x / WAVE) +
+                        threadIdx.x / WAVE;
+    const int lane = threadIdx.x & (WAVE - 1);
+    if (w >= ncur)
+        return;
+    const int2 pr2 = cur[w];
+    const int a = pr2.x, b = pr2.y;
+    unsigned long long tests = 0;
+    if (a == b) {
+        if (a >= Q.nn) {  // a single pack against itself
+            emit_pair(E, Q, lane == 0, a, a);
+            return;
+        }
+        const int m = Q.kcnt[a], k0 = Q.kbeg[a];
+        const long long tot = (long long)m * (m + 1) / 2;
+        for (long long base = 0; base < tot; base += WAVE) {
+            const long long t = base + lane;
+            bool valid = t < tot;
+            int i = 0, j = 0;
+            if (valid) {
+                // t -> (i, j), i <= j, row-major over the upper triangle
+                double mm = m + 0.5;
+                i = (int)floor(mm - sqrt(mm * mm - 2.0 * (double)t));
+                if (i < 0)
+                    i = 0;
+                while (i > 0 && (long long)i * m - (long long)i * (i - 1) / 2 > t)
+                    --i;
+                while ((long long)(i + 1) * m - (long long)(i + 1) * i / 2 <= t)
+                    ++i;
+                j = i + (int)(t - ((long long)i * m - (long long)i * (i - 1) / 2));
+            }
+            int ka = 0, kb = 0;
+            if (valid) {
+                ka = Q.kids[k0 + i];
+                kb = Q.kids[k0 + j];
+                if (i != j) {
+                    ++tests;
+                    valid = may_touch<M>(P, Q, pr, ka, kb);
+                }
+            }
+            emit_pair(E, Q, valid, ka, kb);
+        }
+    } else {
+        const bool at = a >= Q.nn, bt_ = b >= Q.nn;
+        int s, o;
+        if (at && bt_) {  // cannot happen (packs pairs are emitted directly)
+            emit_pair(E, Q, lane == 0, a, b);
+            return;
+        }
+        if (at)
+            s = b, o = a;
+        else if (bt_)
+            s = a, o = b;
+        else if (Q.rad[a] >= Q.rad[b])
+            s = a, o = b;
+        else
+            s = b, o = a;
+        const int m = Q.kcnt[s], k0 = Q.kbeg[s];
+        for (int base = 0; base < m; base += WAVE) {
+            const int t = base + lane;
+            bool valid = t < m;
+            int ka = 0;
+            if (valid) {
+                ka = Q.kids[k0 + t];
+                ++tests;
+                valid = may_touch<M>(P, Q, pr, ka, o);
+            }
+            emit_pair(E, Q, valid, ka, o);
+        }
+    }
+    tests = wave_sum(tests);
+    if (lane == 0)
+        atomicAdd(&E.cnt[2], tests);
+}
+
+// --------------------------------------------------------------- tiles ---
+
+struct TileOut {
+    int32_t *deg;                 // count pass
+    unsigned long long *cursor;   // fill pass: next free slot of each row
+    int32_t *col;
+    float *dist;
+    unsigned long long *cnt;      // [0] pairs, [1] FP64 rechecks
+    unsigned long long nnz;       // fill pass: slots available
+    int *err;                     // fill pass: a write would leave the CSR
+};
+
+template <int M>
+struct TileSmem;
+
+template <>
+struct TileSmem<M_L2> {
+    float A[KC][LDA], B[KC][LDA];
+};
+template <>
+struct TileSmem<M_ANG> {
+    float A[KC][LDA], B[KC][LDA];
+};
+constexpr int HAM_MAXW = 16;
+template <>
+struct TileSmem<M_HAM> {
+    uint64_t A[HAM_MAXW][TS], B[HAM_MAXW][TS];
+};
+template <>
+struct TileSmem<M_LEV> {
+    int dummy;
+};
+
+template <int M, bool FILL>
+__global__ void __launch_bounds__(TT)
+k_tile(Pts P, const int2 *__restrict__ inter, const int32_t *__restrict__ q_pb,
+       const int32_t *__restrict__ q_pe, const int32_t *__restrict__ perm,
+       Thr E, int fp64_dist, TileOut out)
+{
+    __shared__ TileSmem<M> sm;
+    __shared__ unsigned long long mask[TS];
+    __shared__ float dt[FILL ? TS * (TS + 1) : 1];
+    const int t = threadIdx.x, ty = t / 16, tx = t % 16;
+    const int2 pr = inter[blockIdx.x];
+    const int A = pr.x, B = pr.y;
+    const bool diag = A == B;
+    const int a0 = q_pb[A], na = q_pe[A] - a0;
+    const int b0 = q_pb[B], nb = q_pe[B] - b0;
+    unsigned long long rechecks = 0, pairs = 0;
+
+    for (int ia = 0; ia < na; ia += TS) {
+        for (int jb = diag ? ia : 0; jb < nb; jb += TS) {
+            const int ra = min(TS, na - ia), rb = min(TS, nb - jb);
+            const bool sdiag = diag && ia == jb;
+            const int pa = a0 + ia, pb = b0 + jb;  // first tree positions
+            if (t < TS)
+                mask[t] = 0ull;
+            float acc[4][4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    acc[i][j] = 0.f;
+
+            if constexpr (M == M_L2 || M == M_ANG) {
+                const float *X = (M == M_ANG) ? P.xn : P.x;
+                const int dp = P.dp;
+                for (int k0 = 0; k0 < dp; k0 += KC) {
+                    __syncthreads();
+#pragma unroll
+                    for (int q = 0; q < 2; ++q) {
+                        const int f = t + q * TT;  // float4 index in 64 x 8
+                        const int row = f / (KC / 4), c4 = f % (KC / 4);
+                        const int kk = k0 + c4 * 4;
+                        float4 va = make_float4(0.f, 0.f, 0.f, 0.f), vb = va;
+                        if (row < ra && kk < dp)
+                            va = *reinterpret_cast<const float4 *>(
+                                X + (size_t)(pa + row) * dp + kk);
+                        if (row < rb && kk < dp)
+                            vb = *reinterpret_cast<const float4 *>(
+                                X + (size_t)(pb + row) * dp + kk);
+                        sm.A[c4 * 4 + 0][row] = va.x;
+                        sm.A[c4 * 4 + 1][row] = va.y;
+                        sm.A[c4 * 4 + 2][row] = va.z;
+                        sm.A[c4 * 4 + 3][row] = va.w;
+                        sm.B[c4 * 4 + 0][row] = vb.x;
+                        sm.B[c4 * 4 + 1][row] = vb.y;
+                        sm.B[c4 * 4 + 2][row] = vb.z;
+                        sm.B[c4 * 4 + 3][row] = vb.w;
+                    }
+                    __syncthreads();
+                    const int kend = min(KC, dp - k0);
+                    for (int k = 0; k < kend; ++k) {
+                        const float4 u = *reinterpret_cast<const float4 *>(&sm.A[k][ty * 4]);
+                        const float4 v = *reinterpret_cast<const float4 *>(&sm.B[k][tx * 4]);
+                        const float ua[4] = {u.x, u.y, u.z, u.w};
+                        const float vb[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                        for (int i = 0; i < 4; ++i)
+#pragma unroll
+                            for (int j = 0; j < 4; ++j) {
+                                const float d = ua[i] - vb[j];
+                                acc[i][j] = fmaf(d, d, acc[i][j]);
+                            }
+                    }
+                }
+            } else if constexpr (M == M_HAM) {
+                const int W = P.dp;
+                __syncthreads();
+                for (int e = t; e < W * TS; e += TT) {
+                    const int row = e / W, w = e % W;
+                    sm.A[w][row] = row < ra ? P.h[(size_t)(pa + row) * W + w] : 0ull;
+                    sm.B[w][row] = row < rb ? P.h[(size_t)(pb + row) * W + w] : 0ull;
+                }
+                __syncthreads();
+                int hc[4][4] = {};
+                for (int w = 0; w < W; ++w) {
+                    uint64_t ua[4], vb[4];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        ua[i] = sm.A[w][ty * 4 + i];
+                        vb[i] = sm.B[w][tx * 4 + i];
+                    }
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+#pragma unroll
+                        for (int j = 0; j < 4; ++j)
+                            hc[i][j] += __popcll(ua[i] ^ vb[j]);
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        acc[i][j] = (float)hc[i][j];
+                __syncthreads();
+            } else {  // Levenshtein: one bit-parallel DP per pair
+                __syncthreads();
+                const int kk = (int)E.lo;
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int ri = ty * 4 + i, cj = tx * 4 + j;
+                        float v = FLT_MAX;
+                        if (ri < ra && cj < rb && (!sdiag || ri < cj)) {
+                            const int p = pa + ri, q = pb + cj;
+                            const int lp = P.len[p], lq = P.len[q];
+                            if (abs(lp - lq) <= kk)
+                                v = (float)key32<M_LEV>(P, p, q);
+                        }
+                        acc[i][j] = v;
+                    }
+            }
+
+            // ---- exactness guard and edge bits ----------------------------
+            unsigned long long rc = 0;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int ri = ty * 4 + i;
+                unsigned nib = 0;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int cj = tx * 4 + j;
+                    if (ri < ra && cj < rb && (!sdiag || ri < cj)) {
+                        const float k = acc[i][j];
+                        bool e;
+                        if constexpr (M == M_HAM || M == M_LEV) {
+                            e = k <= E.lo;
+                        } else {
+                            if (k < E.lo)
+                                e = true;
+                            else if (k > E.hi)
+                                e = false;
+                            else {
+                                ++rc;
+                                if constexpr (M == M_L2)
+                                    e = l2_sq64(P.x + (size_t)(pa + ri) * P.dp,
+                                                P.x + (size_t)(pb + cj) * P.dp,
+                                                P.dim) <= E.p64;
+                                else
+                                    e = ang_within64(P.x + (size_t)(pa + ri) * P.dp,
+                                                     P.x + (size_t)(pb + cj) * P.dp,
+                                                     P.dim, E.p64);
+                            }
+                        }
+                        if (e) {
+                            nib |= 1u << j;
+                            if constexpr (FILL)
+                                dt[ri * (TS + 1) + cj] =
+                                    edge_dist<M>(P, pa + ri, pb + cj, k, fp64_dist);
+                        }
+                    }
+                }
+                if (nib)
+                    atomicOr(&mask[ri], (unsigned long long)nib << (tx * 4));
+            }
+            rechecks += rc;
+            if (t == 0)
+                pairs += sdiag ? (unsigned long long)ra * (ra - 1) / 2
+                               : (unsigned long long)ra * rb;
+            __syncthreads();
+
+            // ---- rows (threads 0..63) and columns (threads 64..127) -------
+            if (t < TS) {
+                const int r = t;
+                const unsigned long long bits = r < ra ? mask[r] : 0ull;
+                int c = __popcll(bits);
+                if (c) {
+                    const int orow = perm[pa + r];
+                    if constexpr (!FILL) {
+                        atomicAdd(&out.deg[orow], c);
+                    } else {
+                        unsigned long long o = atomicAdd(&out.cursor[orow],
+                                                         (unsigned long long)c);
+                        if (o + c > out.nnz) {
+                            atomicOr(out.err, ERR_INDEX);
+                            c = 0;
+                        }
+                        unsigned long long bb = c ? bits : 0ull;
+                        while (bb) {
+                            const int j = __ffsll((long long)bb) - 1;
+                            bb &= bb - 1;
+                            out.col[o] = perm[pb + j];
+                            out.dist[o] = dt[r * (TS + 1) + j];
+                            ++o;
+                        }
+                    }
+                }
+            } else if (t < 2 * TS) {
+                const int cc = t - TS;
+                if (cc < rb) {
+                    int c = 0;
+                    for (int r = 0; r < ra; ++r)
+                        c += (int)((mask[r] >> cc) & 1ull);
+                    if (c) {
+                        const int ocol = perm[pb + cc];
+                        if constexpr (!FILL) {
+                            atomicAdd(&out.deg[ocol], c);
+                        } else {
+                            unsigned long long o = atomicAdd(&out.cursor[ocol],
+                                                             (unsigned long long)c);
+                            if (o + c > out.nnz) {
+                                atomicOr(out.err, ERR_INDEX);
+                                c = 0;
+                            }
+                            for (int r = 0; c && r < ra; ++r)
+                                if ((mask[r] >> cc) & 1ull) {
+                                    out.col[o] = perm[pa + r];
+                                    out.dist[o] = dt[r * (TS + 1) + cc];
+                                    ++o;
+                                }
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    rechecks = wave_sum(rechecks);
+    if ((t & (WAVE - 1)) == 0 && rechecks)
+        atomicAdd(&out.cnt[1], rechecks);
+    if (t == 0)
+        atomicAdd(&out.cnt[0], pairs);
+}
+
+// ------------------------------------------------------------ row sort ---
+
+__device__ __forceinline__ unsigned long long pack_entry(int32_t c, float d)
+{
+    return ((unsigned long long)(uint32_t)c << 32) | __float_as_uint(d);
+}
+
+// Rows of at most 64 entries: one wave per row, bitonic sort across lanes.
+__global__ void __launch_bounds__(256)
+k_sort_small(const int64_t *__restrict__ row_ptr, int n, int32_t *__restrict__ col,
+             float *__restrict__ dist, int32_t *__restrict__ mid_list,
+             int32_t *__restrict__ long_list, int32_t *__restrict__ counts)
+{
+    const int r = blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+    const int lane = threadIdx.x & (WAVE - 1);
+    if (r >= n)
+        return;
+    const int64_t b = row_ptr[r];
+    const int64_t len = row_ptr[r + 1] - b;
+    if (len <= 1)
+        return;
+    if (len > WAVE) {
+        if (lane == 0) {
+            if (len <= 4096)
+                mid_list[atomicAdd(&counts[0], 1)] = r;
+            else
+                long_list[atomicAdd(&counts[1], 1)] = r;
+        }
+        return;
+    }
+    unsigned long long v = lane < len ? pack_entry(col[b + lane], dist[b + lane])
+                                      : ~0ull;
+    for (int k = 2; k <= WAVE; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            unsigned long long o = __shfl_xor(v, j, WAVE);
+            const bool up = (lane & k) == 0;
+            const bool lower = (lane & j) == 0;
+            const bool take_min = (lower == up);
+            v = take_min ? (o < v ? o : v) : (o > v ? o : v);
+        }
+    }
+    if (lane < len) {
+        col[b + lane] = (int32_t)(v >> 32);
+        dist[b + lane] = __uint_as_float((uint32_t)v);
+    }
+}
+
+// Rows of 65..4096 entries: one work-group per row, bitonic sort in LDS.
+__global__ void __launch_bounds__(256)
+k_sort_mid(const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ list,
+           int32_t *__restrict__ col, float *__restrict__ dist)
+{
+    __shared__ unsigned long long s[4096];
+    const int r = list[blockIdx.x];
+    const int64_t b = row_ptr[r];
+    const int len = (int)(row_ptr[r + 1] - b);
+    int P2 = 1;
+    while (P2 < len)
+        P2 <<= 1;
+    for (int i = threadIdx.x; i < P2; i += blockDim.x)
+        s[i] = i < len ? pack_entry(col[b + i], dist[b + i]) : ~0ull;
+    __syncthreads();
+    for (int k = 2; k <= P2; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < P2; i += blockDim.x) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const bool up = (i & k) == 0;
+                    unsigned long long x = s[i], y = s[l];
+                    if ((x > y) == up) {
+                        s[i] = y;
+                        s[l] = x;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = threadIdx.x; i < len; i += blockDim.x) {
+        col[b + i] = (int32_t)(s[i] >> 32);
+        dist[b + i] = __uint_as_float((uint32_t)s[i]);
+    }
+}
+
+// Longer rows: one work-group per row, bitonic sort in a global scratch
+// buffer (rare: only rows with more than 4096 neighbours).
+__global__ void __launch_bounds__(256)
+k_sort_long(const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ list,
+            const int64_t *__restrict__ soff, unsigned long long *__restrict__ scr,
+            int32_t *__restrict__ col, float *__restrict__ dist)
+{
+    const int r = list[blockIdx.x];
+    const int64_t b = row_ptr[r];
+    const int64_t len = row_ptr[r + 1] - b;
+    unsigned long long *s = scr + soff[blockIdx.x];
+    int64_t P2 = 1;
+    while (P2 < len)
+        P2 <<= 1;
+    for (int64_t i = threadIdx.x; i < P2; i += blockDim.x)
+        s[i] = i < len ? pack_entry(col[b + i], dist[b + i]) : ~0ull;
+    __syncthreads();
+    for (int64_t k = 2; k <= P2; k <<= 1) {
+        for (int64_t j = k >> 1; j > 0; j >>= 1) {
+            for (int64_t i = threadIdx.x; i < P2; i += blockDim.x) {
+                const int64_t l = i ^ j;
+                if (l > i) {
+                    const bool up = (i & k) == 0;
+                    unsigned long long x = s[i], y = s[l];
+                    if ((x > y) == up) {
+                        s[i] = y;
+                        s[l] = x;
+                    }
+                }
+            }
+            __threadfence_block();
+            __syncthreads();
+        }
+    }
+    for (int64_t i = threadIdx.x; i < len; i += blockDim.x) {
+        col[b + i] = (int32_t)(s[i] >> 32);
+        dist[b + i] = __uint_as_float((uint32_t)s[i]);
+    }
+}
+
+__global__ void k_long_sizes(const int64_t *__restrict__ row_ptr,
+                             const int32_t *__restrict__ list, int nl,
+                             int64_t *__restrict__ p2)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nl)
+        return;
+    const int r = list[i];
+    const int64_t len = row_ptr[r + 1] - row_ptr[r];
+    int64_t P2 = 1;
+    while (P2 < len)
+        P2 <<= 1;
+    p2[i] = P2;
+}
+
+__global__ void k_cursor_init(const int64_t *__restrict__ row_ptr, int n,
+                              unsigned long long *__restrict__ cur)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n)
+        cur[i] = (unsigned long long)row_ptr[i];
+}
+
+__global__ void k_cursor_check(const int64_t *__restrict__ row_ptr, int n,
+                               const unsigned long long *__restrict__ cur,
+                               int *__restrict__ bad)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && cur[i] != (unsigned long long)row_ptr[i + 1])
+        atomicOr(bad, 1);
+}
+
+// -------------------------------------------------------------- driver ---
+
+struct Timer {
+    hipEvent_t e[8];
+    int k = 0;
+    hipStream_t s;
+    explicit Timer(hipStream_t st) : s(st)
+    {
+        for (auto &x : e)
+            FNN_HIP(hipEventCreate(&x));
+    }
+    ~Timer()
+    {
+        for (auto &x : e)
+            (void)hipEventDestroy(x);
+    }
+    void mark() { FNN_HIP(hipEventRecord(e[k++], s)); }
+    double ms(int a, int b)
+    {
+        float v = 0.f;
+        FNN_HIP(hipEventElapsedTime(&v, e[a], e[b]));
+        return v;
+    }
+};
+
+template <int M>
+static void traverse(const fnn_tree *T, const Pts &P, const QView &Q,
+                     const Prune &pr, Scratch &S, int2 **inter_out,
+                     long long *ninter_out, fnn_stats &st)
+{
+    hipStream_t s = S.stream();
+    long long cap_cur = 1 << 16, cap_next = 1 << 16;
+    long long cap_int = std::max<long long>(1 << 16, T->npacks * 8);
+    int2 *cur = S.get<int2>(cap_cur), *next = S.get<int2>(cap_next);
+    int2 *inter = S.get<int2>(cap_int);
+    unsigned long long *cnt = S.get<unsigned long long>(4);
+    int *ovf = S.get<int>(1);
+    fill(cnt, 0ull, 4, s);
+    int2 root = make_int2(T->qroot, T->qroot);
+    FNN_HIP(hipMemcpyAsync(cur, &root, sizeof(int2), hipMemcpyHostToDevice, s));
+    long long ncur = 1, ninter = 0, tests = 0;
+    while (ncur > 0) {
+        for (;;) {
+            unsigned long long init[3] = {0ull, (unsigned long long)ninter, 0ull};
+            FNN_HIP(hipMemcpyAsync(cnt, init, sizeof init, hipMemcpyHostToDevice, s));
+            fill(ovf, 0, 1, s);
+            Emit E{next, inter, cnt, cap_next, cap_int, ovf};
+            const long long blocks = cdiv(ncur, 4);
+            hipLaunchKernelGGL((k_expand<M>), dim3((unsigned)blocks), dim3(256), 0,
+                               s, P, Q, pr, cur, ncur, E);
+            unsigned long long hc[3];
+            int hov = 0;
+            FNN_HIP(hipMemcpyAsync(hc, cnt, sizeof hc, hipMemcpyDeviceToHost, s));
+            FNN_HIP(hipMemcpyAsync(&hov, ovf, sizeof(int), hipMemcpyDeviceToHost, s));
+            FNN_HIP(hipStreamSynchronize(s));
+            if (!hov) {
+                ncur = (long long)hc[0];
+                ninter = (long long)hc[1];
+                tests += (long long)hc[2];
+                break;
+            }
+            // grow the buffer(s) that overflowed and redo this level
+            if ((long long)hc[0] > cap_next) {
+                cap_next = (long long)(hc[0] * 5 / 4 + 1024);
+                next = S.get<int2>(cap_next);
+            }
+            if ((long long)hc[1] > cap_int) {
+                long long nc = (long long)(hc[1] * 5 / 4 + 1024);
+                int2 *ni = S.get<int2>(nc);
+                if (ninter > 0)
+                    FNN_HIP(hipMemcpyAsync(ni, inter, sizeof(int2) * ninter,
+                                           hipMemcpyDeviceToDevice, s));
+                inter = ni;
+                cap_int = nc;
+            }
+        }
+        std::swap(cur, next);
+        std::swap(cap_cur, cap_next);
+        if (ncur > cap_next) {
+            cap_next = ncur * 2;
+            next = S.get<int2>(cap_next);
+        }
+    }
+    *inter_out = inter;
+    *ninter_out = ninter;
+    st.traverse_tests = tests;
+    st.interactions = ninter;
+}
+
+template <int M>
+static void launch_tiles(bool fill_pass, const Pts &P, const int2 *inter,
+                         long long ninter, const fnn_tree *T, const Thr &E,
+                         int fp64_dist, const TileOut &o, hipStream_t s)
+{
+    const long long MAXG = 1ll << 30;
+    for (long long off = 0; off < ninter; off += MAXG) {
+        const long long g = std::min(MAXG, ninter - off);
+        if (fill_pass)
+            hipLaunchKernelGGL((k_tile<M, true>), dim3((unsigned)g), dim3(TT), 0, s,
+                               P, inter + off, T->q_pt_begin, T->q_pt_end, T->perm,
+                               E, fp64_dist, o);
+        else
+            hipLaunchKernelGGL((k_tile<M, false>), dim3((unsigned)g), dim3(TT), 0,
+                               s, P, inter + off, T->q_pt_begin, T->q_pt_end,
+                               T->perm, E, fp64_dist, o);
+    }
+}
+
+template <int M>
+static void eps_graph_impl(const fnn_tree *T, double eps, const Options &opt,
+                           fnn_csr *C, fnn_stats &st, Scratch &S)
+{
+    hipStream_t s = S.stream();
+    const int n = (int)T->n;
+    Timer tm(s);
+    tm.mark();  // 0
+
+    Pts P{};
+    P.metric = M;
+    P.n = n;
+    P.dim = T->dim;
+    P.dp = T->dp;
+    P.W = T->W;
+    P.sigma = T->sigma;
+    P.x = T->x;
+    P.xn = T->xn;
+    P.h = T->h;
+    P.s = T->s;
+    P.len = T->len;
+    P.peq = T->peq;
+
+    QView Q{T->q_center_pos, T->q_pt_begin, T->q_pt_end, T->q_kbeg,
+            T->q_kcnt,       T->q_kids,     T->q_radius, (int)T->nnodes};
+    const Thr E = make_thr_eps(M, T->dp, eps);
+    Prune pr;
+    const double u = 1.0 / 16777216.0;
+    pr.rel = (float)std::max(1e-4, 8.0 * (T->dp + 4) * u);
+    pr.abs_ = M == M_ANG ? 1e-5f : (M == M_L2 ? 1e-30f : 0.f);
+    pr.eps = (M == M_HAM || M == M_LEV) ? E.lo : (float)eps;
+    if (M == M_ANG && eps >= M_PI)
+        pr.eps = 4.f;  // every pair may touch
+    const int fp64_dist = (M == M_ANG) || (M == M_L2 && (T->dim + 2) * u > 1e-5);
+
+    // ---- traversal ------------------------------------------------------
+    int2 *inter = nullptr;
+    long long ninter = 0;
+    traverse<M>(T, P, Q, pr, S, &inter, &ninter, st);
+    tm.mark();  // 1
+
+    // ---- count pass -----------------------------------------------------
+    unsigned long long *cnt = S.get<unsigned long long>(4);
+    fill(cnt, 0ull, 4, s);
+    TileOut o{};
+    o.cnt = cnt;
+    o.deg = S.get<int32_t>(n);
+    fill(o.deg, 0, n, s);
+    launch_tiles<M>(false, P, inter, ninter, T, E, fp64_dist, o, s);
+    tm.mark();  // 2
+
+    // ---- scan -----------------------------------------------------------
+    C->n = n;
+    C->row_ptr = (int64_t *)out_alloc(sizeof(int64_t) * ((size_t)n + 1));
+    scan_i32_to_i64(o.deg, C->row_ptr, n, S);
+    const int64_t nnz = read_scalar(C->row_ptr + n, s);
+    C->nnz = nnz;
+    C->col = (int32_t *)out_alloc(sizeof(int32_t) * (size_t)std::max<int64_t>(nnz, 1));
+    C->dist = (float *)out_alloc(sizeof(float) * (size_t)std::max<int64_t>(nnz, 1));
+    tm.mark();  // 3
+
+    // ---- fill pass ------------------------------------------------------
+    unsigned long long hc0[2];
+    FNN_HIP(hipMemcpyAsync(hc0, cnt, sizeof hc0, hipMemcpyDeviceToHost, s));
+    o.cursor = S.get<unsigned long long>(n);
+    hipLaunchKernelGGL(k_cursor_init, dim3(cdiv(n, 256)), dim3(256), 0, s,
+                       C->row_ptr, n, o.cursor);
+    o.col = C->col;
+    o.dist = C->dist;
+    o.nnz = (unsigned long long)nnz;
+    int *bad = S.get<int>(1);
+    fill(bad, 0, 1, s);
+    o.err = bad;
+    if (nnz > 0)
+        launch_tiles<M>(true, P, inter, ninter, T, E, fp64_dist, o, s);
+    hipLaunchKernelGGL(k_cursor_check, dim3(cdiv(n, 256)), dim3(256), 0, s,
+                       C->row_ptr, n, o.cursor, bad);
+    tm.mark();  // 4
+
+    // ---- per-row sort ---------------------------------------------------
+    int32_t *mid = S.get<int32_t>(n), *lng = S.get<int32_t>(n);
+    int32_t *cc = S.get<int32_t>(2);
+    fill(cc, 0, 2, s);
+    if (nnz > 0) {
+        hipLaunchKernelGGL(k_sort_small, dim3(cdiv(n, 4)), dim3(256), 0, s,
+                           C->row_ptr, n, C->col, C->dist, mid, lng, cc);
+        int32_t hcc[2];
+        FNN_HIP(hipMemcpyAsync(hcc, cc, sizeof hcc, hipMemcpyDeviceToHost, s));
+        FNN_HIP(hipStreamSynchronize(s));
+        if (hcc[0] > 0)
+            hipLaunchKernelGGL(k_sort_mid, dim3(hcc[0]), dim3(256), 0, s,
+                               C->row_ptr, mid, C->col, C->dist);
+        if (hcc[1] > 0) {
+            int64_t *p2 = S.get<int64_t>(hcc[1] + 1);
+            int64_t *soff = S.get<int64_t>(hcc[1] + 2);
+            hipLaunchKernelGGL(k_long_sizes, dim3(cdiv(hcc[1], 256)), dim3(256), 0,
+                               s, C->row_ptr, lng, hcc[1], p2);
+            scan_i64(p2, soff, hcc[1], S);
+            const int64_t tot = read_scalar(soff + hcc[1], s);
+            unsigned long long *scr = S.get<unsigned long long>(tot);
+            hipLaunchKernelGGL(k_sort_long, dim3(hcc[1]), dim3(256), 0, s,
+                               C->row_ptr, lng, soff, scr, C->col, C->dist);
+        }
+    }
+    tm.mark();  // 5
+    unsigned long long hc[2];
+    int hbad = 0;
+    FNN_HIP(hipMemcpyAsync(hc, cnt, sizeof hc, hipMemcpyDeviceToHost, s));
+    FNN_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s));
+    FNN_HIP(hipStreamSynchronize(s));
+    if (hbad)
+        fail(FNN_EINTERNAL, "count and fill passes disagree");
+
+    st.n = n;
+    st.nodes = T->nnodes;
+    st.packs = T->npacks;
+    st.tile_pairs = (int64_t)hc[0];
+    st.fp64_rechecks = (int64_t)hc[1];
+    st.edges = nnz;
+    st.traverse_ms = tm.ms(0, 1);
+    st.count_ms = tm.ms(1, 2);
+    st.scan_ms = tm.ms(2, 3);
+    st.fill_ms = tm.ms(3, 4);
+    st.sort_ms = tm.ms(4, 5);
+    st.tile_ms = st.count_ms + st.fill_ms;
+    st.total_ms = tm.ms(0, 5);
+    (void)hc0;
+    (void)opt;
+}
+
+void eps_graph(const fnn_tree *T, double eps, const Options &opt, fnn_csr *C,
+               fnn_stats &st, Scratch &S)
+{
+    switch (T->metric) {
+    case M_L2:
+        eps_graph_impl<M_L2>(T, eps, opt, C, st, S);
+        break;
+    case M_ANG:
+        eps_graph_impl<M_ANG>(T, eps, opt, C, st, S);
+        break;
+    case M_HAM:
+        eps_graph_impl<M_HAM>(T, eps, opt, C, st, S);
+        break;
+    default:
+        eps_graph_impl<M_LEV>(T, eps, opt, C, st, S);
+        break;
+    }
+}
+
+}  // namespace fnn

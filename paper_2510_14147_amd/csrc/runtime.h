@@ -1,0 +1,105 @@
+// Host runtime helpers: error propagation, stream binding, stream-ordered
+// scratch memory, and the device primitives (scan, radix sort) used by the
+// build and the query.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+namespace fnn {
+
+// Internal exception; converted to an error code at the C ABI.
+struct Error {
+    int code;
+    std::string msg;
+};
+
+[[noreturn]] void fail(int code, const char *fmt, ...);
+
+#define FNN_HIP(call)                                                        \
+    do {                                                                     \
+        hipError_t e_ = (call);                                              \
+        if (e_ != hipSuccess)                                                \
+            ::fnn::fail(-3, "%s failed: %s (%s:%d)", #call,                  \
+                        hipGetErrorString(e_), __FILE__, __LINE__);          \
+    } while (0)
+
+hipStream_t current_stream();
+
+// Stream-ordered scratch allocations released (stream-ordered) on scope
+// exit.  Backed by the device's default memory pool, whose release
+// threshold is raised once so freed blocks are reused.
+class Scratch {
+  public:
+    explicit Scratch(hipStream_t s) : s_(s) {}
+    ~Scratch();
+    Scratch(const Scratch &) = delete;
+    Scratch &operator=(const Scratch &) = delete;
+    void *raw(size_t bytes);
+    template <class T>
+    T *get(size_t count)
+    {
+        return static_cast<T *>(raw(count * sizeof(T) + 16));
+    }
+    void release(void *p);
+    hipStream_t stream() const { return s_; }
+
+  private:
+    hipStream_t s_;
+    std::vector<void *> ptrs_;
+};
+
+// Memory handed to the caller (tree / CSR arrays): the user allocator if one
+// is set, else hipMalloc.
+void *out_alloc(size_t bytes);
+void out_free(void *p);
+
+// Exclusive scan: out[0..n] with out[n] = total.
+void scan_i32_to_i64(const int32_t *in, int64_t *out, int64_t n, Scratch &S);
+void scan_i64(const int64_t *in, int64_t *out, int64_t n, Scratch &S);
+void scan_i32(const int32_t *in, int32_t *out, int64_t n, Scratch &S);
+
+// Stable LSD radix sort of (key, value) pairs by the low `bits` bits of the
+// key.  Sorted output lands in keys_out / vals_out.
+void radix_sort_pairs(const uint32_t *keys_in, const uint32_t *vals_in,
+                      uint32_t *keys_out, uint32_t *vals_out, int64_t n,
+                      int bits, Scratch &S);
+
+// Device fill with a kernel (never a memset node, so the call is safe to
+// record in a captured graph).
+template <class T>
+__global__ void k_fill(T *__restrict__ p, T v, int64_t n)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t st = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += st)
+        p[i] = v;
+}
+
+template <class T>
+void fill(T *p, T v, int64_t n, hipStream_t s)
+{
+    if (n <= 0)
+        return;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 65536)
+        blocks = 65536;
+    hipLaunchKernelGGL((k_fill<T>), dim3((unsigned)blocks), dim3(256), 0, s, p,
+                       v, n);
+}
+
+template <class T>
+T read_scalar(const T *dptr, hipStream_t s)
+{
+    T v;
+    FNN_HIP(hipMemcpyAsync(&v, dptr, sizeof(T), hipMemcpyDeviceToHost, s));
+    FNN_HIP(hipStreamSynchronize(s));
+    return v;
+}
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+}  // namespace fnn

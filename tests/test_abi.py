@@ -1,0 +1,66 @@
+"""The C-ABI library loads and exports every symbol include/fnn.h declares;
+argument checks that need no GPU (CPU only, no compute calls)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fnn.h")
+LIB = os.path.join(ROOT, "paper_2510_14147_amd", "libfnn.so")
+
+
+def declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fnn_[a-z_0-9]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        from paper_2510_14147_amd import build
+        build.build()
+    return ctypes.CDLL(LIB)
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared()
+    assert "fnn_tree_build" in names and "fnn_eps_graph" in names
+    assert "fnn_free" in names
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_version_and_error_string(lib):
+    lib.fnn_version.restype = ctypes.c_int
+    assert lib.fnn_version() >= 100
+    lib.fnn_last_error.restype = ctypes.c_char_p
+    assert isinstance(lib.fnn_last_error(), bytes)
+
+
+def test_argument_errors_without_gpu(lib):
+    vp = ctypes.c_void_p
+    out = vp(123)
+    lib.fnn_tree_build.argtypes = [vp, ctypes.c_int64, ctypes.c_int32,
+                                   ctypes.c_int, ctypes.POINTER(vp)]
+    assert lib.fnn_tree_build(None, 10, 4, 0, ctypes.byref(out)) == -1
+    assert out.value is None
+    lib.fnn_last_error.restype = ctypes.c_char_p
+    assert b"NULL" in lib.fnn_last_error()
+    assert lib.fnn_tree_build(vp(16), 0, 4, 0, ctypes.byref(out)) == -1
+    assert lib.fnn_tree_build(vp(16), 10, 4, 7, ctypes.byref(out)) == -1
+    lib.fnn_eps_graph.argtypes = [vp, ctypes.c_double, ctypes.POINTER(vp)]
+    assert lib.fnn_eps_graph(None, 1.0, ctypes.byref(out)) == -1
+    lib.fnn_free.argtypes = [vp]
+    lib.fnn_free(None)
+    lib.fnn_set_allocator.argtypes = [vp, vp, vp]
+    assert lib.fnn_set_allocator(vp(1), None, None) == -1
+
+
+def test_options_struct_matches_header():
+    from paper_2510_14147_amd import fnn_options, fnn_stats, fnn_csr
+    assert ctypes.sizeof(fnn_options) == 16 * 4
+    assert ctypes.sizeof(fnn_csr) == 8 + 8 + 8 + 3 * 8
+    assert ctypes.sizeof(fnn_stats) == 16 * 8 + 9 * 8 + 8 * 8

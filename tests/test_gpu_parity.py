@@ -1,0 +1,117 @@
+"""GPU parity: the HIP path's epsilon-graph equals the FP64 oracle's exactly
+(row_ptr and col identical, zero missing and zero extra edges; distances
+within 1e-5 relative of FP64), and the exported GPU cover tree satisfies the
+invariants under the oracle's pinned comparisons."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_2510_14147_amd import datagen as G
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+W = json.load(open(os.path.join(ROOT, "paper_2510_14147_amd", "workloads.json")))
+MID = {"l2": 0, "angular": 1, "hamming": 2, "levenshtein": 3}
+RTOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def fnn():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2510_14147_amd as f
+    f.lib()
+    return f
+
+
+def gpu_graph(fnn, x, metric, eps, **kw):
+    print(f"[case] metric={metric} n={len(x)} eps={eps} kw={kw}", flush=True)
+    tree = fnn.fnn_tree_build(x, metric, **{k: v for k, v in kw.items()
+                                           if k in ("zeta", "pack", "kmax")})
+    g = fnn.fnn_eps_graph(tree, eps, **{k: v for k, v in kw.items()
+                                        if k in ("precision", "sched", "validate")})
+    return tree, g
+
+
+def check(fnn, orc, x, metric, eps, tree_check=True, **kw):
+    tree, g = gpu_graph(fnn, x, metric, eps, **kw)
+    rp, col, dist = g.to_numpy()
+    ref = orc.bruteforce(x, MID[metric], eps)
+    cmp = orc.compare_csr(rp, col, dist, *ref, rtol=RTOL)
+    assert cmp["missing"] == 0 and cmp["extra"] == 0, cmp
+    assert cmp["ok"], cmp
+    assert orc.csr_symmetric(rp, col, dist)
+    if tree_check:
+        t = fnn.fnn_tree_export(tree)
+        t["radius"] = t["radius"].astype(np.float64)
+        v = orc.check_tree(x, MID[metric], t)
+        assert all(c == 0 for c in v.values()), v
+    return tree, g, cmp
+
+
+def test_worked_example(fnn, orc):
+    fx = json.load(open(os.path.join(ROOT, "tests", "golden", "worked_example_1d.json")))
+    x = np.asarray(fx["points"], np.float32)
+    tree, g, _ = check(fnn, orc, x, "l2", fx["eps"], zeta=1)
+    rp, col, dist = g.to_numpy()
+    assert rp.tolist() == fx["csr"]["row_ptr"] and col.tolist() == fx["csr"]["col"]
+
+
+@pytest.mark.parametrize("n,d,zeta", [(1000, 3, 8), (3001, 5, 64), (5000, 16, 16)])
+def test_l2_random(fnn, orc, n, d, zeta):
+    x = G.random_points(n, d, seed=n + d, duplicates=n // 50)
+    eps = 0.25 if d <= 5 else 0.9
+    check(fnn, orc, x, "l2", eps, zeta=zeta)
+
+
+def test_c1_full(fnn, orc):
+    x = G.c1_clusters()
+    check(fnn, orc, x, "l2", W["c1"]["eps"])
+
+
+def test_angular(fnn, orc):
+    x = G.angular_dirs(n=8000, dim=16)
+    check(fnn, orc, x, "angular", W["ang"]["eps"])
+
+
+@pytest.mark.parametrize("bits", [128, 256])
+def test_hamming(fnn, orc, bits):
+    x = G.random_codes(3000, bits, seed=bits, n_centers=10, flip=0.08)
+    check(fnn, orc, x, "hamming", 0.12 * bits)
+
+
+def test_levenshtein(fnn, orc):
+    x = G.random_strings(2000, seed=5, n_seeds=40, min_len=30, max_len=120,
+                         p_edit=0.04)
+    check(fnn, orc, x, "levenshtein", 6.0)
+
+
+def test_single_point(fnn, orc):
+    x = np.zeros((1, 3), np.float32)
+    tree, g = gpu_graph(fnn, x, "l2", 1.0)
+    rp, col, dist = g.to_numpy()
+    assert rp.tolist() == [0, 0] and g.nnz == 0
+
+
+def test_all_duplicates(fnn, orc):
+    x = np.ones((300, 4), np.float32)
+    check(fnn, orc, x, "l2", 1e-3)
+
+
+def test_tiny_and_huge_eps(fnn, orc):
+    x = G.random_points(700, 3, seed=3)
+    check(fnn, orc, x, "l2", 1e-6)
+    check(fnn, orc, x, "l2", 10.0)
+
+
+def test_deterministic(fnn, orc):
+    x = G.random_points(4000, 6, seed=11, duplicates=40)
+    _, g1 = gpu_graph(fnn, x, "l2", 0.3)
+    _, g2 = gpu_graph(fnn, x, "l2", 0.3)
+    a, b = g1.to_numpy(), g2.to_numpy()
+    for u, v in zip(a, b):
+        assert np.array_equal(u, v)
