@@ -114,10 +114,10 @@ __global__ void k_ingest_vec(const float *__restrict__ in, int n, int dim,
                              int dp, int angular, float *__restrict__ x,
                              float *__restrict__ xn, int *err)
 {
-    const int i = blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
     const int lane = threadIdx.x & (WAVE - 1);
-    if (i >= n)
-        return;
+    const int wpb = blockDim.x / WAVE;
+    for (int i = blockIdx.x * wpb + threadIdx.x / WAVE; i < n;
+         i += gridDim.x * wpb) {
     const float *r = in + (size_t)i * dim;
     float *o = x + (size_t)i * dp;
     float ss = 0.f;
@@ -131,20 +131,21 @@ __global__ void k_ingest_vec(const float *__restrict__ in, int n, int dim,
     if (__any(bad)) {
         if (lane == 0)
             atomicOr(err, ERR_INPUT);
-        return;
+        continue;
     }
     if (angular) {
         ss = wave_sum(ss);
         if (!(ss > 0.f) || !isfinite(ss)) {
             if (lane == 0)
                 atomicOr(err, ERR_INPUT);
-            return;
+            continue;
         }
         // unit row in FP32 (the key's error band allows for its rounding)
         float inv = 1.0f / sqrtf(ss);
         float *on = xn + (size_t)i * dp;
         for (int k = lane; k < dp; k += WAVE)
             on[k] = o[k] * inv;
+    }
     }
 }
 
@@ -230,35 +231,35 @@ __global__ void k_make_chunks(Hubs hb, int H, const int32_t *__restrict__ choff,
                               int32_t *__restrict__ ch_e,
                               int32_t *__restrict__ ch_k)
 {
-    const int h = blockIdx.x;
-    if (h >= H)
-        return;
-    const int c0 = choff[h], c1 = choff[h + 1];
-    const int b = hb.b[h], e = hb.e[h];
-    if (threadIdx.x == 0) {
-        hb.cb[h] = c0;
-        hb.ce[h] = c1;
-        hb.kof[h] = itemoff[h];
-    }
-    for (int c = c0 + threadIdx.x; c < c1; c += blockDim.x) {
-        int s = b + (c - c0) * CH;
-        ch_hub[c] = h;
-        ch_s[c] = s;
-        ch_e[c] = min(s + CH, e);
-        ch_k[c] = itemoff[h] + (c - c0) * CH;
+    for (int h = blockIdx.x; h < H; h += gridDim.x) {
+        const int c0 = choff[h], c1 = choff[h + 1];
+        const int b = hb.b[h], e = hb.e[h];
+        if (threadIdx.x == 0) {
+            hb.cb[h] = c0;
+            hb.ce[h] = c1;
+            hb.kof[h] = itemoff[h];
+        }
+        for (int c = c0 + threadIdx.x; c < c1; c += blockDim.x) {
+            int s = b + (c - c0) * CH;
+            ch_hub[c] = h;
+            ch_s[c] = s;
+            ch_e[c] = min(s + CH, e);
+            ch_k[c] = itemoff[h] + (c - c0) * CH;
+        }
     }
 }
 
 __global__ void __launch_bounds__(CH)
 k_round_init(const int32_t *__restrict__ ch_s, const int32_t *__restrict__ ch_e,
-             const int32_t *__restrict__ ch_k, int32_t *__restrict__ L,
+             const int32_t *__restrict__ ch_k, int NC, int32_t *__restrict__ L,
              int32_t *__restrict__ hpos)
 {
-    const int c = blockIdx.x;
-    const int p = ch_s[c] + threadIdx.x;
-    if (p < ch_e[c]) {
-        L[p] = 0;
-        hpos[ch_k[c] + threadIdx.x] = p;
+    for (int c = blockIdx.x; c < NC; c += gridDim.x) {
+        const int p = ch_s[c] + threadIdx.x;
+        if (p < ch_e[c]) {
+            L[p] = 0;
+            hpos[ch_k[c] + threadIdx.x] = p;
+        }
     }
 }
 
@@ -272,16 +273,16 @@ __device__ __forceinline__ bool better(float d, int id, float d2, int id2)
 template <int M>
 __global__ void __launch_bounds__(CH)
 k_update(Pts P, const int32_t *__restrict__ ch_hub, const int32_t *__restrict__ ch_s,
-         const int32_t *__restrict__ ch_e, Hubs hb,
+         const int32_t *__restrict__ ch_e, int NC, Hubs hb,
          const int32_t *__restrict__ cent, const int32_t *__restrict__ perm,
          float *__restrict__ D, int32_t *__restrict__ L,
          const LevelTab *__restrict__ tab, float *__restrict__ cb_D,
          int32_t *__restrict__ cb_id, unsigned long long *__restrict__ cnt)
 {
-    const int c = blockIdx.x;
+    for (int c = blockIdx.x; c < NC; c += gridDim.x) {
     const int h = ch_hub[c];
     if (!hb.act[h])
-        return;
+        continue;
     const int s = ch_s[c], e = ch_e[c];
     const int p = s + threadIdx.x;
     const bool valid = p < e;
@@ -325,6 +326,7 @@ k_update(Pts P, const int32_t *__restrict__ ch_hub, const int32_t *__restrict__ 
         if (j1 > j0)
             atomicAdd(cnt, (unsigned long long)(j1 - j0) * (unsigned)(e - s));
     }
+    }
 }
 
 constexpr int SEL_T = 256;
@@ -332,14 +334,11 @@ constexpr int MAX_K = 64;
 
 template <int M>
 __global__ void __launch_bounds__(SEL_T)
-k_select(Pts P, Hubs hb, int32_t *__restrict__ cent, float *__restrict__ cb_D,
+k_select(Pts P, Hubs hb, int H, int32_t *__restrict__ cent, float *__restrict__ cb_D,
          const int32_t *__restrict__ cb_id, const LevelTab *__restrict__ tab,
          int kmax, int32_t *__restrict__ n_active,
          unsigned long long *__restrict__ cnt)
 {
-    const int h = blockIdx.x;
-    if (!hb.act[h])
-        return;
     __shared__ int acc[MAX_K];
     __shared__ int nacc, ok;
     __shared__ float rd[SEL_T / WAVE];
@@ -347,6 +346,9 @@ k_select(Pts P, Hubs hb, int32_t *__restrict__ cent, float *__restrict__ cb_D,
     __shared__ float bd_s;
     __shared__ int bid_s, bc_s;
     const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
+    for (int h = blockIdx.x; h < H; h += gridDim.x) {
+    if (!hb.act[h])
+        continue;
     const int c0 = hb.cb[h], c1 = hb.ce[h];
     const int b = hb.b[h], m0 = hb.m[h];
     const Thr T = tab->t[hb.lvl[h] - 1 + LOFF];
@@ -416,6 +418,7 @@ k_select(Pts P, Hubs hb, int32_t *__restrict__ cent, float *__restrict__ cb_D,
     }
     for (int a = threadIdx.x; a < nacc; a += SEL_T)
         cent[b + m0 + a] = acc[a];
+    __syncthreads();
     if (threadIdx.x == 0) {
         hb.ma[h] = m0;
         hb.m[h] = m0 + nacc;
@@ -424,6 +427,8 @@ k_select(Pts P, Hubs hb, int32_t *__restrict__ cent, float *__restrict__ cb_D,
         else
             atomicAdd(n_active, 1);
     }
+    __syncthreads();
+    }
 }
 
 // ----------------------------------------------------------- partition ---
@@ -431,16 +436,17 @@ k_select(Pts P, Hubs hb, int32_t *__restrict__ cent, float *__restrict__ cb_D,
 __global__ void __launch_bounds__(CH)
 k_part_keys(const int32_t *__restrict__ ch_hub, const int32_t *__restrict__ ch_s,
             const int32_t *__restrict__ ch_e, const int32_t *__restrict__ ch_k,
-            const int32_t *__restrict__ child_base,
+            int NC, const int32_t *__restrict__ child_base,
             const int32_t *__restrict__ L, uint32_t *__restrict__ key,
             uint32_t *__restrict__ val)
 {
-    const int c = blockIdx.x;
-    const int p = ch_s[c] + threadIdx.x;
-    if (p < ch_e[c]) {
-        const int k = ch_k[c] + threadIdx.x;
-        key[k] = (uint32_t)(child_base[ch_hub[c]] + L[p]);
-        val[k] = (uint32_t)p;
+    for (int c = blockIdx.x; c < NC; c += gridDim.x) {
+        const int p = ch_s[c] + threadIdx.x;
+        if (p < ch_e[c]) {
+            const int k = ch_k[c] + threadIdx.x;
+            key[k] = (uint32_t)(child_base[ch_hub[c]] + L[p]);
+            val[k] = (uint32_t)p;
+        }
     }
 }
 
@@ -505,9 +511,7 @@ __global__ void k_children(Hubs hb, int H, int metric, int dp, int zeta,
                            const unsigned *__restrict__ ckmax, NodeArrays nd,
                            int32_t *__restrict__ hubflag)
 {
-    const int h = blockIdx.x;
-    if (h >= H)
-        return;
+    for (int h = blockIdx.x; h < H; h += gridDim.x) {
     const int b = hb.b[h], m = hb.m[h], lv = hb.lvl[h];
     const int cb = child_base[h];
     if (threadIdx.x == 0) {
@@ -532,6 +536,7 @@ __global__ void k_children(Hubs hb, int H, int metric, int dp, int zeta,
         nd.cbeg[v] = 0;
         nd.ccnt[v] = 0;
         hubflag[g] = (pe - pb > zeta && km > 0.f) ? 1 : 0;
+    }
     }
 }
 
@@ -578,14 +583,15 @@ template <class T>
 __global__ void k_gather_rows(const T *__restrict__ in, const int32_t *__restrict__ perm,
                               int n, int stride, T *__restrict__ out)
 {
-    const int p = blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
     const int lane = threadIdx.x & (WAVE - 1);
-    if (p >= n)
-        return;
-    const T *r = in + (size_t)perm[p] * stride;
-    T *o = out + (size_t)p * stride;
-    for (int k = lane; k < stride; k += WAVE)
-        o[k] = r[k];
+    const int wpb = blockDim.x / WAVE;
+    for (int p = blockIdx.x * wpb + threadIdx.x / WAVE; p < n;
+         p += gridDim.x * wpb) {
+        const T *r = in + (size_t)perm[p] * stride;
+        T *o = out + (size_t)p * stride;
+        for (int k = lane; k < stride; k += WAVE)
+            o[k] = r[k];
+    }
 }
 
 // ---- query tree: packs of consecutive sibling leaf blocks ----------------
@@ -685,18 +691,19 @@ __global__ void k_pack_radius(Pts P, int first, int npk,
                               const int32_t *__restrict__ q_pe, int dp,
                               float *__restrict__ q_rad)
 {
-    const int k = blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
     const int lane = threadIdx.x & (WAVE - 1);
-    if (k >= npk)
-        return;
-    const int q = first + k;
-    const int c = q_cpos[q];
-    float m = 0.f;
-    for (int p = q_pb[q] + lane; p < q_pe[q]; p += WAVE)
-        m = fmaxf(m, key32<M>(P, c, p));
-    m = wave_max(m);
-    if (lane == 0)
-        q_rad[q] = radius_from_key(M, dp, m);
+    const int wpb = blockDim.x / WAVE;
+    for (int k = blockIdx.x * wpb + threadIdx.x / WAVE; k < npk;
+         k += gridDim.x * wpb) {
+        const int q = first + k;
+        const int c = q_cpos[q];
+        float m = 0.f;
+        for (int p = q_pb[q] + lane; p < q_pe[q]; p += WAVE)
+            m = fmaxf(m, key32<M>(P, c, p));
+        m = wave_max(m);
+        if (lane == 0)
+            q_rad[q] = radius_from_key(M, dp, m);
+    }
 }
 
 // -------------------------------------------------------------- driver ---
@@ -737,7 +744,7 @@ static void build_impl(fnn_tree *T, const void *points, Scratch &S)
         x_in = S.get<float>((size_t)n * T->dp);
         if (M == M_ANG)
             xn_in = S.get<float>((size_t)n * T->dp);
-        hipLaunchKernelGGL(k_ingest_vec, dim3(cdiv(n, 4)), dim3(256), 0, st,
+        FNN_LAUNCH(k_ingest_vec, dim3(grid_for(n, 4)), dim3(256), 0, st,
                            (const float *)points, n, T->dim, T->dp,
                            M == M_ANG ? 1 : 0, x_in, xn_in, err);
         P.x = x_in;
@@ -748,7 +755,7 @@ static void build_impl(fnn_tree *T, const void *points, Scratch &S)
         int32_t *len_in = S.get<int32_t>(n);
         int *sig = S.get<int>(1);
         fill(sig, 1, 1, st);
-        hipLaunchKernelGGL(k_ingest_lev, dim3(cdiv(n, 256)), dim3(256), 0, st,
+        FNN_LAUNCH(k_ingest_lev, dim3(cdiv(n, 256)), dim3(256), 0, st,
                            (const uint8_t *)points, n, T->dim, len_in, sig, err);
         int e = read_scalar(err, st);
         if (e)
@@ -756,7 +763,7 @@ static void build_impl(fnn_tree *T, const void *points, Scratch &S)
         T->sigma = read_scalar(sig, st);
         T->W = (T->dim + 63) / 64;
         uint64_t *peq_in = S.get<uint64_t>((size_t)n * T->sigma * T->W);
-        hipLaunchKernelGGL(k_peq, dim3(cdiv(n, 256)), dim3(256), 0, st,
+        FNN_LAUNCH(k_peq, dim3(cdiv(n, 256)), dim3(256), 0, st,
                            (const uint8_t *)points, len_in, n, T->dim, T->sigma,
                            T->W, peq_in);
         P.s = (const uint8_t *)points;
@@ -831,7 +838,7 @@ static void build_impl(fnn_tree *T, const void *points, Scratch &S)
     // ---- root: D[p] = d(p, p_0) (Algorithm 1's pre-initialised D) ---------
     unsigned *rk = S.get<unsigned>(1);
     fill(rk, 0u, 1, st);
-    hipLaunchKernelGGL((k_root_keys<M>), dim3(cdiv(n, 256)), dim3(256), 0, st,
+    FNN_LAUNCH((k_root_keys<M>), dim3(cdiv(n, 256)), dim3(256), 0, st,
                        P, perm, D, rk);
     const unsigned r0bits = read_scalar(rk, st);
     float r0key;
@@ -868,7 +875,7 @@ static void build_impl(fnn_tree *T, const void *points, Scratch &S)
     while (H > 0) {
         ++rounds;
         // chunk table of this level's hubs
-        hipLaunchKernelGGL(k_hub_sizes, dim3(cdiv(H, 256)), dim3(256), 0, st,
+        FNN_LAUNCH(k_hub_sizes, dim3(cdiv(H, 256)), dim3(256), 0, st,
                            hubs.b, hubs.e, H, nch, hsz);
         scan_i32(nch, choff, H, S);
         scan_i32(hsz, itemoff, H, S);
@@ -879,20 +886,20 @@ static void build_impl(fnn_tree *T, const void *points, Scratch &S)
         const int NC = tot[0], NH = tot[1];
         if (NC > maxch || NH > n)
             fail(FNN_EINTERNAL, "chunk table overflow (%d > %d)", NC, maxch);
-        hipLaunchKernelGGL(k_make_chunks, dim3(H), dim3(64), 0, st, hubs, H,
+        FNN_LAUNCH(k_make_chunks, dim3(grid_for(H, 1)), dim3(64), 0, st, hubs, H,
                            choff, itemoff, ch_hub, ch_s, ch_e, ch_k);
-        hipLaunchKernelGGL(k_round_init, dim3(NC), dim3(CH), 0, st, ch_s, ch_e,
-                           ch_k, L, hpos);
+        FNN_LAUNCH(k_round_init, dim3(grid_for(NC, 1)), dim3(CH), 0, st, ch_s,
+                   ch_e, ch_k, NC, L, hpos);
 
         // ---- net selection passes ----------------------------------------
         for (;;) {
             ++passes;
             fill(n_active, 0, 1, st);
-            hipLaunchKernelGGL((k_update<M>), dim3(NC), dim3(CH), 0, st, P,
-                               ch_hub, ch_s, ch_e, hubs, cent, perm, D, L, tab,
+            FNN_LAUNCH((k_update<M>), dim3(grid_for(NC, 1)), dim3(CH), 0, st, P,
+                               ch_hub, ch_s, ch_e, NC, hubs, cent, perm, D, L, tab,
                                cb_D, cb_id, cnt);
-            hipLaunchKernelGGL((k_select<M>), dim3(H), dim3(SEL_T), 0, st, P,
-                               hubs, cent, cb_D, cb_id, tab, T->opt.kmax,
+            FNN_LAUNCH((k_select<M>), dim3(grid_for(H, 1)), dim3(SEL_T), 0, st, P,
+                               hubs, H, cent, cb_D, cb_id, tab, T->opt.kmax,
                                n_active, cnt);
             if (read_scalar(n_active, st) == 0)
                 break;
@@ -903,23 +910,23 @@ static void build_impl(fnn_tree *T, const void *points, Scratch &S)
         const int C = read_scalar(child_base + H, st);
         if (node_count + C > (int64_t)cap)
             fail(FNN_EINTERNAL, "vertex capacity exceeded");
-        hipLaunchKernelGGL(k_part_keys, dim3(NC), dim3(CH), 0, st, ch_hub, ch_s,
-                           ch_e, ch_k, child_base, L, key, val);
+        FNN_LAUNCH(k_part_keys, dim3(grid_for(NC, 1)), dim3(CH), 0, st, ch_hub,
+                   ch_s, ch_e, ch_k, NC, child_base, L, key, val);
         radix_sort_pairs(key, val, skey, sval, NH, bitlen((uint32_t)C), S);
-        hipLaunchKernelGGL(k_part_gather, dim3(cdiv(NH, 256)), dim3(256), 0, st,
+        FNN_LAUNCH(k_part_gather, dim3(cdiv(NH, 256)), dim3(256), 0, st,
                            sval, NH, perm, D, tperm, tD);
         fill(ckmax, 0u, C, st);
-        hipLaunchKernelGGL(k_part_store, dim3(cdiv(NH, 256)), dim3(256), 0, st,
+        FNN_LAUNCH(k_part_store, dim3(cdiv(NH, 256)), dim3(256), 0, st,
                            skey, NH, hpos, tperm, tD, perm, D, cfirst, clast,
                            ckmax);
-        hipLaunchKernelGGL(k_children, dim3(H), dim3(64), 0, st, hubs, H, M,
+        FNN_LAUNCH(k_children, dim3(grid_for(H, 1)), dim3(64), 0, st, hubs, H, M,
                            T->dp, T->opt.zeta, (int)node_count, child_base, cent,
                            cfirst, clast, ckmax, nd, hubflag);
         scan_i32(hubflag, fscan, C, S);
         const int Hn = read_scalar(fscan + C, st);
         if (Hn > hub_cap)
             fail(FNN_EINTERNAL, "hub capacity exceeded");
-        hipLaunchKernelGGL(k_next_hubs, dim3(cdiv(C, 256)), dim3(256), 0, st, C,
+        FNN_LAUNCH(k_next_hubs, dim3(cdiv(C, 256)), dim3(256), 0, st, C,
                            (int)node_count, hubflag, fscan, nd, nhubs, cent);
         node_count += C;
         std::swap(hubs, nhubs);
@@ -933,7 +940,7 @@ static void build_impl(fnn_tree *T, const void *points, Scratch &S)
     FNN_HIP(hipMemcpyAsync(T->perm, perm, sizeof(int32_t) * n,
                            hipMemcpyDeviceToDevice, st));
     int32_t *inv = S.get<int32_t>(n);
-    hipLaunchKernelGGL(k_inverse, dim3(cdiv(n, 256)), dim3(256), 0, st, perm, n,
+    FNN_LAUNCH(k_inverse, dim3(cdiv(n, 256)), dim3(256), 0, st, perm, n,
                        inv);
     T->center = (int32_t *)T->own(sizeof(int32_t) * nn);
     T->center_pos = (int32_t *)T->own(sizeof(int32_t) * nn);
@@ -953,36 +960,36 @@ static void build_impl(fnn_tree *T, const void *points, Scratch &S)
     cp(T->child_count, nd.ccnt, 4 * (size_t)nn);
     cp(T->pt_begin, nd.pb, 4 * (size_t)nn);
     cp(T->pt_end, nd.pe, 4 * (size_t)nn);
-    hipLaunchKernelGGL(k_center_pos, dim3(cdiv(nn, 256)), dim3(256), 0, st,
+    FNN_LAUNCH(k_center_pos, dim3(cdiv(nn, 256)), dim3(256), 0, st,
                        nd.center, inv, nn, T->center_pos);
 
     // point data in tree order
     Pts Q = P;
     if (M == M_L2 || M == M_ANG) {
         T->x = (float *)T->own(sizeof(float) * (size_t)n * T->dp);
-        hipLaunchKernelGGL((k_gather_rows<float>), dim3(cdiv(n, 4)), dim3(256), 0,
+        FNN_LAUNCH((k_gather_rows<float>), dim3(grid_for(n, 4)), dim3(256), 0,
                            st, x_in, perm, n, T->dp, T->x);
         Q.x = T->x;
         if (M == M_ANG) {
             T->xn = (float *)T->own(sizeof(float) * (size_t)n * T->dp);
-            hipLaunchKernelGGL((k_gather_rows<float>), dim3(cdiv(n, 4)),
+            FNN_LAUNCH((k_gather_rows<float>), dim3(grid_for(n, 4)),
                                dim3(256), 0, st, xn_in, perm, n, T->dp, T->xn);
             Q.xn = T->xn;
         }
     } else if (M == M_HAM) {
         T->h = (uint64_t *)T->own(sizeof(uint64_t) * (size_t)n * T->dp);
-        hipLaunchKernelGGL((k_gather_rows<uint64_t>), dim3(cdiv(n, 4)),
+        FNN_LAUNCH((k_gather_rows<uint64_t>), dim3(grid_for(n, 4)),
                            dim3(256), 0, st, P.h, perm, n, T->dp, T->h);
         Q.h = T->h;
     } else {
         T->s = (uint8_t *)T->own((size_t)n * T->dp);
         T->len = (int32_t *)T->own(sizeof(int32_t) * n);
         T->peq = (uint64_t *)T->own(sizeof(uint64_t) * (size_t)n * T->sigma * T->W);
-        hipLaunchKernelGGL((k_gather_rows<uint8_t>), dim3(cdiv(n, 4)), dim3(256),
+        FNN_LAUNCH((k_gather_rows<uint8_t>), dim3(grid_for(n, 4)), dim3(256),
                            0, st, P.s, perm, n, T->dp, T->s);
-        hipLaunchKernelGGL((k_gather_rows<int32_t>), dim3(cdiv(n, 4)), dim3(256),
+        FNN_LAUNCH((k_gather_rows<int32_t>), dim3(grid_for(n, 4)), dim3(256),
                            0, st, P.len, perm, n, 1, T->len);
-        hipLaunchKernelGGL((k_gather_rows<uint64_t>), dim3(cdiv(n, 4)),
+        FNN_LAUNCH((k_gather_rows<uint64_t>), dim3(grid_for(n, 4)),
                            dim3(256), 0, st, P.peq, perm, n, T->sigma * T->W,
                            T->peq);
         Q.s = T->s;
@@ -994,7 +1001,7 @@ static void build_impl(fnn_tree *T, const void *points, Scratch &S)
     const int PK = T->opt.pack;
     int32_t *npk = S.get<int32_t>(nn + 1), *nqk = S.get<int32_t>(nn + 1);
     int32_t *pkoff = S.get<int32_t>(nn + 2), *kidoff = S.get<int32_t>(nn + 2);
-    hipLaunchKernelGGL(k_qt_count, dim3(cdiv(nn, 256)), dim3(256), 0, st, nn,
+    FNN_LAUNCH(k_qt_count, dim3(cdiv(nn, 256)), dim3(256), 0, st, nn,
                        nd.ccnt, nd.cbeg, nd.pb, nd.pe, PK, npk, nqk);
     scan_i32(npk, pkoff, nn, S);
     scan_i32(nqk, kidoff, nn, S);
@@ -1016,7 +1023,7 @@ static void build_impl(fnn_tree *T, const void *points, Scratch &S)
     T->q_kbeg = (int32_t *)T->own(sizeof(int32_t) * nq);
     T->q_kcnt = (int32_t *)T->own(sizeof(int32_t) * nq);
     T->q_kids = (int32_t *)T->own(sizeof(int32_t) * (nkids + 1));
-    hipLaunchKernelGGL(k_qt_fill, dim3(cdiv(nn, 256)), dim3(256), 0, st, nn,
+    FNN_LAUNCH(k_qt_fill, dim3(cdiv(nn, 256)), dim3(256), 0, st, nn,
                        nd.ccnt, nd.cbeg, nd.pb, nd.pe, T->center_pos, nd.radius, PK,
                        pkoff, kidoff, T->q_center_pos, T->q_radius, T->q_pt_begin,
                        T->q_pt_end, T->q_kbeg, T->q_kcnt, T->q_kids);
@@ -1038,7 +1045,7 @@ static void build_impl(fnn_tree *T, const void *points, Scratch &S)
         T->qroot = 0;
     }
     if (npacks > 0)
-        hipLaunchKernelGGL((k_pack_radius<M>), dim3(cdiv(npacks, 4)), dim3(256),
+        FNN_LAUNCH((k_pack_radius<M>), dim3(grid_for(npacks, 4)), dim3(256),
                            0, st, Q, nn, npacks, T->q_center_pos, T->q_pt_begin,
                            T->q_pt_end, T->dp, T->q_radius);
 

@@ -102,23 +102,19 @@ __device__ __forceinline__ void emit_pair(const Emit &E, const QView &Q,
     }
 }
 
+// Expand one vertex pair (whole wave).  Returns the number of tests made by
+// this lane.
 template <int M>
-__global__ void __launch_bounds__(256)
-k_expand(Pts P, QView Q, Prune pr, const int2 *__restrict__ cur, long long ncur,
-         Emit E)
+__device__ unsigned long long expand_one(const Pts &P, const QView &Q,
+                                         const Prune &pr, int a, int b,
+                                         const Emit &E)
 {
-    const long long w = (long long)blockIdx.x * (blockDim.x / WAVE) +
-                        threadIdx.x / WAVE;
     const int lane = threadIdx.x & (WAVE - 1);
-    if (w >= ncur)
-        return;
-    const int2 pr2 = cur[w];
-    const int a = pr2.x, b = pr2.y;
     unsigned long long tests = 0;
     if (a == b) {
         if (a >= Q.nn) {  // a single pack against itself
             emit_pair(E, Q, lane == 0, a, a);
-            return;
+            return 0;
         }
         const int m = Q.kcnt[a], k0 = Q.kbeg[a];
         const long long tot = (long long)m * (m + 1) / 2;
@@ -154,7 +150,7 @@ k_expand(Pts P, QView Q, Prune pr, const int2 *__restrict__ cur, long long ncur,
         int s, o;
         if (at && bt_) {  // cannot happen (packs pairs are emitted directly)
             emit_pair(E, Q, lane == 0, a, b);
-            return;
+            return 0;
         }
         if (at)
             s = b, o = a;
@@ -177,8 +173,24 @@ k_expand(Pts P, QView Q, Prune pr, const int2 *__restrict__ cur, long long ncur,
             emit_pair(E, Q, valid, ka, o);
         }
     }
+    return tests;
+}
+
+template <int M>
+__global__ void __launch_bounds__(256)
+k_expand(Pts P, QView Q, Prune pr, const int2 *__restrict__ cur, long long ncur,
+         Emit E)
+{
+    const int lane = threadIdx.x & (WAVE - 1);
+    const long long wpb = blockDim.x / WAVE;
+    unsigned long long tests = 0;
+    for (long long w = (long long)blockIdx.x * wpb + threadIdx.x / WAVE;
+         w < ncur; w += (long long)gridDim.x * wpb) {
+        const int2 pr2 = cur[w];
+        tests += expand_one<M>(P, Q, pr, pr2.x, pr2.y, E);
+    }
     tests = wave_sum(tests);
-    if (lane == 0)
+    if (lane == 0 && tests)
         atomicAdd(&E.cnt[2], tests);
 }
 
@@ -217,20 +229,21 @@ struct TileSmem<M_LEV> {
 
 template <int M, bool FILL>
 __global__ void __launch_bounds__(TT)
-k_tile(Pts P, const int2 *__restrict__ inter, const int32_t *__restrict__ q_pb,
-       const int32_t *__restrict__ q_pe, const int32_t *__restrict__ perm,
-       Thr E, int fp64_dist, TileOut out)
+k_tile(Pts P, const int2 *__restrict__ inter, long long ninter,
+       const int32_t *__restrict__ q_pb, const int32_t *__restrict__ q_pe,
+       const int32_t *__restrict__ perm, Thr E, int fp64_dist, TileOut out)
 {
     __shared__ TileSmem<M> sm;
     __shared__ unsigned long long mask[TS];
     __shared__ float dt[FILL ? TS * (TS + 1) : 1];
     const int t = threadIdx.x, ty = t / 16, tx = t % 16;
-    const int2 pr = inter[blockIdx.x];
+    unsigned long long rechecks = 0, pairs = 0;
+    for (long long it = blockIdx.x; it < ninter; it += gridDim.x) {
+    const int2 pr = inter[it];
     const int A = pr.x, B = pr.y;
     const bool diag = A == B;
     const int a0 = q_pb[A], na = q_pe[A] - a0;
     const int b0 = q_pb[B], nb = q_pe[B] - b0;
-    unsigned long long rechecks = 0, pairs = 0;
 
     for (int ia = 0; ia < na; ia += TS) {
         for (int jb = diag ? ia : 0; jb < nb; jb += TS) {
@@ -440,6 +453,7 @@ k_tile(Pts P, const int2 *__restrict__ inter, const int32_t *__restrict__ q_pb,
             __syncthreads();
         }
     }
+    }
     rechecks = wave_sum(rechecks);
     if ((t & (WAVE - 1)) == 0 && rechecks)
         atomicAdd(&out.cnt[1], rechecks);
@@ -460,14 +474,14 @@ k_sort_small(const int64_t *__restrict__ row_ptr, int n, int32_t *__restrict__ c
              float *__restrict__ dist, int32_t *__restrict__ mid_list,
              int32_t *__restrict__ long_list, int32_t *__restrict__ counts)
 {
-    const int r = blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
     const int lane = threadIdx.x & (WAVE - 1);
-    if (r >= n)
-        return;
+    const int wpb = blockDim.x / WAVE;
+    for (int r = blockIdx.x * wpb + threadIdx.x / WAVE; r < n;
+         r += gridDim.x * wpb) {
     const int64_t b = row_ptr[r];
     const int64_t len = row_ptr[r + 1] - b;
     if (len <= 1)
-        return;
+        continue;
     if (len > WAVE) {
         if (lane == 0) {
             if (len <= 4096)
@@ -475,7 +489,7 @@ k_sort_small(const int64_t *__restrict__ row_ptr, int n, int32_t *__restrict__ c
             else
                 long_list[atomicAdd(&counts[1], 1)] = r;
         }
-        return;
+        continue;
     }
     unsigned long long v = lane < len ? pack_entry(col[b + lane], dist[b + lane])
                                       : ~0ull;
@@ -492,15 +506,17 @@ k_sort_small(const int64_t *__restrict__ row_ptr, int n, int32_t *__restrict__ c
         col[b + lane] = (int32_t)(v >> 32);
         dist[b + lane] = __uint_as_float((uint32_t)v);
     }
+    }
 }
 
 // Rows of 65..4096 entries: one work-group per row, bitonic sort in LDS.
 __global__ void __launch_bounds__(256)
 k_sort_mid(const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ list,
-           int32_t *__restrict__ col, float *__restrict__ dist)
+           int nl, int32_t *__restrict__ col, float *__restrict__ dist)
 {
     __shared__ unsigned long long s[4096];
-    const int r = list[blockIdx.x];
+    for (int li = blockIdx.x; li < nl; li += gridDim.x) {
+    const int r = list[li];
     const int64_t b = row_ptr[r];
     const int len = (int)(row_ptr[r + 1] - b);
     int P2 = 1;
@@ -528,6 +544,8 @@ k_sort_mid(const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ list
     for (int i = threadIdx.x; i < len; i += blockDim.x) {
         col[b + i] = (int32_t)(s[i] >> 32);
         dist[b + i] = __uint_as_float((uint32_t)s[i]);
+    }
+    __syncthreads();
     }
 }
 
@@ -650,9 +668,8 @@ static void traverse(const fnn_tree *T, const Pts &P, const QView &Q,
             FNN_HIP(hipMemcpyAsync(cnt, init, sizeof init, hipMemcpyHostToDevice, s));
             fill(ovf, 0, 1, s);
             Emit E{next, inter, cnt, cap_next, cap_int, ovf};
-            const long long blocks = cdiv(ncur, 4);
-            hipLaunchKernelGGL((k_expand<M>), dim3((unsigned)blocks), dim3(256), 0,
-                               s, P, Q, pr, cur, ncur, E);
+            FNN_LAUNCH((k_expand<M>), dim3(grid_for(ncur, 4)), dim3(256), 0, s,
+                       P, Q, pr, cur, ncur, E);
             unsigned long long hc[3];
             int hov = 0;
             FNN_HIP(hipMemcpyAsync(hc, cnt, sizeof hc, hipMemcpyDeviceToHost, s));
@@ -697,18 +714,15 @@ static void launch_tiles(bool fill_pass, const Pts &P, const int2 *inter,
                          long long ninter, const fnn_tree *T, const Thr &E,
                          int fp64_dist, const TileOut &o, hipStream_t s)
 {
-    const long long MAXG = 1ll << 30;
-    for (long long off = 0; off < ninter; off += MAXG) {
-        const long long g = std::min(MAXG, ninter - off);
-        if (fill_pass)
-            hipLaunchKernelGGL((k_tile<M, true>), dim3((unsigned)g), dim3(TT), 0, s,
-                               P, inter + off, T->q_pt_begin, T->q_pt_end, T->perm,
-                               E, fp64_dist, o);
-        else
-            hipLaunchKernelGGL((k_tile<M, false>), dim3((unsigned)g), dim3(TT), 0,
-                               s, P, inter + off, T->q_pt_begin, T->q_pt_end,
-                               T->perm, E, fp64_dist, o);
-    }
+    if (ninter <= 0)
+        return;
+    const dim3 g(grid_for(ninter, 1));
+    if (fill_pass)
+        FNN_LAUNCH((k_tile<M, true>), g, dim3(TT), 0, s, P, inter, ninter,
+                   T->q_pt_begin, T->q_pt_end, T->perm, E, fp64_dist, o);
+    else
+        FNN_LAUNCH((k_tile<M, false>), g, dim3(TT), 0, s, P, inter, ninter,
+                   T->q_pt_begin, T->q_pt_end, T->perm, E, fp64_dist, o);
 }
 
 template <int M>
@@ -768,15 +782,15 @@ static void eps_graph_impl(const fnn_tree *T, double eps, const Options &opt,
     scan_i32_to_i64(o.deg, C->row_ptr, n, S);
     const int64_t nnz = read_scalar(C->row_ptr + n, s);
     C->nnz = nnz;
+    unsigned long long hc0[2];  // count-pass counters (stream is idle here)
+    FNN_HIP(hipMemcpy(hc0, cnt, sizeof hc0, hipMemcpyDeviceToHost));
     C->col = (int32_t *)out_alloc(sizeof(int32_t) * (size_t)std::max<int64_t>(nnz, 1));
     C->dist = (float *)out_alloc(sizeof(float) * (size_t)std::max<int64_t>(nnz, 1));
     tm.mark();  // 3
 
     // ---- fill pass ------------------------------------------------------
-    unsigned long long hc0[2];
-    FNN_HIP(hipMemcpyAsync(hc0, cnt, sizeof hc0, hipMemcpyDeviceToHost, s));
     o.cursor = S.get<unsigned long long>(n);
-    hipLaunchKernelGGL(k_cursor_init, dim3(cdiv(n, 256)), dim3(256), 0, s,
+    FNN_LAUNCH(k_cursor_init, dim3(cdiv(n, 256)), dim3(256), 0, s,
                        C->row_ptr, n, o.cursor);
     o.col = C->col;
     o.dist = C->dist;
@@ -786,7 +800,7 @@ static void eps_graph_impl(const fnn_tree *T, double eps, const Options &opt,
     o.err = bad;
     if (nnz > 0)
         launch_tiles<M>(true, P, inter, ninter, T, E, fp64_dist, o, s);
-    hipLaunchKernelGGL(k_cursor_check, dim3(cdiv(n, 256)), dim3(256), 0, s,
+    FNN_LAUNCH(k_cursor_check, dim3(cdiv(n, 256)), dim3(256), 0, s,
                        C->row_ptr, n, o.cursor, bad);
     tm.mark();  // 4
 
@@ -795,23 +809,23 @@ static void eps_graph_impl(const fnn_tree *T, double eps, const Options &opt,
     int32_t *cc = S.get<int32_t>(2);
     fill(cc, 0, 2, s);
     if (nnz > 0) {
-        hipLaunchKernelGGL(k_sort_small, dim3(cdiv(n, 4)), dim3(256), 0, s,
+        FNN_LAUNCH(k_sort_small, dim3(grid_for(n, 4)), dim3(256), 0, s,
                            C->row_ptr, n, C->col, C->dist, mid, lng, cc);
         int32_t hcc[2];
         FNN_HIP(hipMemcpyAsync(hcc, cc, sizeof hcc, hipMemcpyDeviceToHost, s));
         FNN_HIP(hipStreamSynchronize(s));
         if (hcc[0] > 0)
-            hipLaunchKernelGGL(k_sort_mid, dim3(hcc[0]), dim3(256), 0, s,
-                               C->row_ptr, mid, C->col, C->dist);
+            FNN_LAUNCH(k_sort_mid, dim3(grid_for(hcc[0], 1)), dim3(256), 0, s,
+                           C->row_ptr, mid, hcc[0], C->col, C->dist);
         if (hcc[1] > 0) {
             int64_t *p2 = S.get<int64_t>(hcc[1] + 1);
             int64_t *soff = S.get<int64_t>(hcc[1] + 2);
-            hipLaunchKernelGGL(k_long_sizes, dim3(cdiv(hcc[1], 256)), dim3(256), 0,
+            FNN_LAUNCH(k_long_sizes, dim3(cdiv(hcc[1], 256)), dim3(256), 0,
                                s, C->row_ptr, lng, hcc[1], p2);
             scan_i64(p2, soff, hcc[1], S);
             const int64_t tot = read_scalar(soff + hcc[1], s);
             unsigned long long *scr = S.get<unsigned long long>(tot);
-            hipLaunchKernelGGL(k_sort_long, dim3(hcc[1]), dim3(256), 0, s,
+            FNN_LAUNCH(k_sort_long, dim3(hcc[1]), dim3(256), 0, s,
                                C->row_ptr, lng, soff, scr, C->col, C->dist);
         }
     }
@@ -827,8 +841,8 @@ static void eps_graph_impl(const fnn_tree *T, double eps, const Options &opt,
     st.n = n;
     st.nodes = T->nnodes;
     st.packs = T->npacks;
-    st.tile_pairs = (int64_t)hc[0];
-    st.fp64_rechecks = (int64_t)hc[1];
+    st.tile_pairs = (int64_t)hc0[0];
+    st.fp64_rechecks = (int64_t)hc0[1];
     st.edges = nnz;
     st.traverse_ms = tm.ms(0, 1);
     st.count_ms = tm.ms(1, 2);
@@ -837,7 +851,6 @@ static void eps_graph_impl(const fnn_tree *T, double eps, const Options &opt,
     st.sort_ms = tm.ms(4, 5);
     st.tile_ms = st.count_ms + st.fill_ms;
     st.total_ms = tm.ms(0, 5);
-    (void)hc0;
     (void)opt;
 }
 

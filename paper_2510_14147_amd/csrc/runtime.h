@@ -27,6 +27,12 @@ struct Error {
                         hipGetErrorString(e_), __FILE__, __LINE__);          \
     } while (0)
 
+#define FNN_LAUNCH(kernel, grid, block, shmem, stream, ...)                  \
+    do {                                                                     \
+        hipLaunchKernelGGL(kernel, grid, block, shmem, stream, __VA_ARGS__); \
+        FNN_HIP(hipGetLastError());                                          \
+    } while (0)
+
 hipStream_t current_stream();
 
 // Stream-ordered scratch allocations released (stream-ordered) on scope
@@ -87,8 +93,7 @@ void fill(T *p, T v, int64_t n, hipStream_t s)
     int64_t blocks = (n + 255) / 256;
     if (blocks > 65536)
         blocks = 65536;
-    hipLaunchKernelGGL((k_fill<T>), dim3((unsigned)blocks), dim3(256), 0, s, p,
-                       v, n);
+    FNN_LAUNCH((k_fill<T>), dim3((unsigned)blocks), dim3(256), 0, s, p, v, n);
 }
 
 template <class T>
@@ -101,5 +106,19 @@ T read_scalar(const T *dptr, hipStream_t s)
 }
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// A dispatch carries its grid size in work-items as a 32-bit number, so a
+// launch is capped at MAX_BLOCKS work-groups and kernels whose item count
+// grows with the input loop over items with a grid stride.
+constexpr int64_t MAX_BLOCKS = 1 << 20;
+inline unsigned grid_for(int64_t items, int64_t items_per_block)
+{
+    int64_t b = cdiv(items, items_per_block);
+    if (b < 1)
+        b = 1;
+    if (b > MAX_BLOCKS)
+        b = MAX_BLOCKS;
+    return (unsigned)b;
+}
 
 }  // namespace fnn

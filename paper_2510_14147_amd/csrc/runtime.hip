@@ -235,17 +235,17 @@ static void scan_impl(const TI *in, TO *out, int64_t n, Scratch &S)
     int64_t ntiles = cdiv(n, SCAN_TILE);
     TO *sums = S.get<TO>(ntiles + 1);
     TO *offs = S.get<TO>(ntiles + 1);
-    hipLaunchKernelGGL((k_scan_tiles<TI, TO>), dim3((unsigned)ntiles),
+    FNN_LAUNCH((k_scan_tiles<TI, TO>), dim3((unsigned)ntiles),
                        dim3(SCAN_T), 0, s, in, out, sums, n);
     if (ntiles == 1) {
-        hipLaunchKernelGGL((k_scan_single<TO>), dim3(1), dim3(1), 0, s, offs,
+        FNN_LAUNCH((k_scan_single<TO>), dim3(1), dim3(1), 0, s, offs,
                            sums);
     } else {
         scan_impl<TO, TO>(sums, offs, ntiles, S);
     }
-    hipLaunchKernelGGL((k_scan_add<TO>), dim3((unsigned)ntiles), dim3(SCAN_T),
+    FNN_LAUNCH((k_scan_add<TO>), dim3((unsigned)ntiles), dim3(SCAN_T),
                        0, s, out, offs, n);
-    hipLaunchKernelGGL((k_scan_total<TO>), dim3(1), dim3(1), 0, s, out, offs,
+    FNN_LAUNCH((k_scan_total<TO>), dim3(1), dim3(1), 0, s, out, offs,
                        ntiles, n);
 }
 
@@ -365,10 +365,10 @@ void radix_sort_pairs(const uint32_t *keys_in, const uint32_t *vals_in,
         uint32_t *ok = to_out ? keys_out : tk;
         uint32_t *ov = to_out ? vals_out : tv;
         (void)last;
-        hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)ntiles), dim3(RS_T), 0, s,
+        FNN_LAUNCH(k_rs_hist, dim3((unsigned)ntiles), dim3(RS_T), 0, s,
                            ck, n, p * 8, hist, ntiles);
         scan_i32_to_i64(hist, offs, (int64_t)RS_BINS * ntiles, S);
-        hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)ntiles), dim3(RS_T), 0,
+        FNN_LAUNCH(k_rs_scatter, dim3((unsigned)ntiles), dim3(RS_T), 0,
                            s, ck, cv, ok, ov, n, p * 8, offs, ntiles);
         ck = ok;
         cv = ov;
