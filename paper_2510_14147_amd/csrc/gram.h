@@ -1,0 +1,41 @@
+// Shared declarations of the leaf-tile kernels (plain FP32 and MFMA
+// filter): output sinks and the MFMA filter's arguments.
+#pragma once
+
+#include "tree.h"
+
+namespace fnn {
+
+struct TileOut {
+    int32_t *deg;                 // count pass
+    unsigned long long *cursor;   // fill pass: next free slot of each row
+    int32_t *col;
+    float *dist;
+    // [0] pairs evaluated exactly, [1] FP64 rechecks, [2] pairs screened by
+    // the MFMA filter, [3] filter survivors, [4] edges the filter would have
+    // dropped (validate; must stay 0), [5] max relative distance error
+    // (float bits, validate)
+    unsigned long long *cnt;
+    unsigned long long nnz;       // fill pass: slots available
+    int *err;                     // fill pass: a write would leave the CSR
+};
+
+struct GramArgs {
+    int nn, npacks, nunits, nlist, kq;
+    const void *q;        // quantised rows [n][kq] (tree order)
+    const float *hx;      // (1 - c1) |x - mu|^2 per point
+    float e2f;            // eps^2 in key space, slightly enlarged
+    float gscale;         // 1 / scale^2 (FP8 global scale)
+    Thr E;
+    int fp64_dist, validate;
+    const int32_t *lg, *lb, *ubeg;  // work lists: group, B pack, unit starts
+    const int32_t *q_pb, *q_pe, *perm;
+};
+
+void gram_prepare(const fnn_tree *T, int prec, double eps, const Thr &E,
+                  const int2 *inter, long long ninter, Scratch &S, GramArgs &G,
+                  int2 **rest, long long *nrest);
+void gram_launch(int metric, int prec, bool fill_pass, const Pts &P,
+                 const GramArgs &G, const TileOut &o, hipStream_t s);
+
+}  // namespace fnn

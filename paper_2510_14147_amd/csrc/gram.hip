@@ -1,0 +1,627 @@
+// MFMA Gram filter for the Euclidean and angular leaf tiles.
+//
+// d(x,y)^2 = |x|^2 + |y|^2 - 2 x.y.  The inner products of a tile are taken
+// on the matrix cores from BF16 (or FP8 E4M3) copies of the globally centred
+// points, accumulated in FP32.  With u the unit roundoff of the input
+// format, |q(x).q(y) - x.y| <= (2u + u^2)|x||y| (Cauchy-Schwarz), plus the
+// FP32 accumulation and the rounding of the norms; all of it is below
+// c1 * (|x|^2 + |y|^2).  A pair is rejected only if
+//     (1 - c1)(|x|^2 + |y|^2) - 2 g~ > eps^2,
+// which implies d^2 > eps^2: the filter never drops an edge.  A surviving
+// pair is recomputed by direct FP32 difference and decided exactly like the
+// plain tiles (rounding band -> FP64 reference predicate).
+//
+// Work decomposition: query packs are grouped four at a time (consecutive
+// pack ids).  A work-group (4 waves) takes one group and a run of the union
+// of its members' interaction lists; wave w holds pack 4g+w (<= 64 rows) in
+// registers, the B pack of each step is staged once in LDS and read by all
+// four waves.  Every unordered point pair is evaluated once: a wave skips B
+// packs with a smaller id, and inside its own pack keeps only pairs whose
+// first point precedes the second in tree order.
+#include <float.h>
+#include <limits.h>
+#include <math.h>
+
+#include <algorithm>
+
+#include <string.h>
+
+#include "gram.h"
+
+namespace fnn {
+
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(16))) float f32x16;
+typedef __attribute__((ext_vector_type(8))) int i32x8;
+
+constexpr int GP = 64;           // rows per pack (max) on the MFMA path
+
+// ---------------------------------------------------------------- prep ---
+
+__global__ void k_colsum(const float *__restrict__ x, int n, int dp,
+                         float *__restrict__ sums)
+{
+    // block b takes rows [b*R, (b+1)*R); thread t sums columns t, t+256..
+    const int R = 1024;
+    const int r0 = blockIdx.x * R, r1 = min(n, r0 + R);
+    for (int c = threadIdx.x; c < dp; c += blockDim.x) {
+        float s = 0.f;
+        for (int r = r0; r < r1; ++r)
+            s += x[(size_t)r * dp + c];
+        atomicAdd(&sums[c], s);
+    }
+}
+
+// Quantised rows of x - mu (tree order) and the per-point norm term.
+template <int PREC>
+__global__ void k_quant(const float *__restrict__ x, int n, int dp, int kq,
+                        const float *__restrict__ sums, float inv_n,
+                        float scale, float one_minus_c1, void *__restrict__ q,
+                        float *__restrict__ hx)
+{
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wpb = blockDim.x / WAVE;
+    for (int i = blockIdx.x * wpb + threadIdx.x / WAVE; i < n;
+         i += gridDim.x * wpb) {
+        float ss = 0.f;
+        for (int k = lane; k < kq; k += WAVE) {
+            float v = 0.f;
+            if (k < dp) {
+                v = x[(size_t)i * dp + k] - sums[k] * inv_n;
+                ss = fmaf(v, v, ss);
+            }
+            if constexpr (PREC == FNN_PREC_BF16) {
+                ((__bf16 *)q)[(size_t)i * kq + k] = (__bf16)v;
+            } else {
+                float s = fminf(fmaxf(v * scale, -448.f), 448.f);
+                unsigned w = (unsigned)__builtin_amdgcn_cvt_pk_fp8_f32(s, 0.f, 0, false);
+                ((uint8_t *)q)[(size_t)i * kq + k] = (uint8_t)(w & 0xFF);
+            }
+        }
+        ss = wave_sum(ss);
+        if (lane == 0)
+            hx[i] = one_minus_c1 * ss;
+    }
+}
+
+__global__ void k_absmax(const float *__restrict__ x, int n, int dp,
+                         const float *__restrict__ sums, float inv_n,
+                         unsigned *__restrict__ mx)
+{
+    float m = 0.f;
+    const int64_t tot = (int64_t)n * dp;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
+         e += (int64_t)gridDim.x * blockDim.x)
+        m = fmaxf(m, fabsf(x[e] - sums[e % dp] * inv_n));
+    m = wave_max(m);
+    if ((threadIdx.x & (WAVE - 1)) == 0)
+        atomicMax(mx, __float_as_uint(m));
+}
+
+// ---------------------------------------------------- interaction lists ---
+
+// Canonical orientation (smaller pack id first) and routing: pairs of
+// ordinary packs go to the MFMA path (key = B pack, value = group), pairs
+// touching an oversized pack go to the plain FP32 tiles.
+__global__ void k_route(const int2 *__restrict__ inter, long long ninter,
+                        const int32_t *__restrict__ q_pb,
+                        const int32_t *__restrict__ q_pe, int nn, int pack,
+                        uint32_t *__restrict__ key, uint32_t *__restrict__ val,
+                        unsigned long long *__restrict__ cnt,
+                        int2 *__restrict__ rest)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+         i < ninter; i += (long long)gridDim.x * blockDim.x) {
+        int2 p = inter[i];
+        int a = min(p.x, p.y), b = max(p.x, p.y);
+        const bool big = (q_pe[a] - q_pb[a] > pack) || (q_pe[b] - q_pb[b] > pack);
+        if (big) {
+            unsigned long long o = atomicAdd(&cnt[1], 1ull);
+            rest[o] = make_int2(a, b);
+        } else {
+            unsigned long long o = atomicAdd(&cnt[0], 1ull);
+            key[o] = (uint32_t)(b - nn);
+            val[o] = (uint32_t)((a - nn) >> 2);
+        }
+    }
+}
+
+// After sorting by (group, B): mark the first of each distinct pair.
+__global__ void k_uniq_flags(const uint32_t *__restrict__ g,
+                             const uint32_t *__restrict__ b, long long m,
+                             int32_t *__restrict__ flag)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < m;
+         i += (long long)gridDim.x * blockDim.x)
+        flag[i] = (i == 0 || g[i] != g[i - 1] || b[i] != b[i - 1]) ? 1 : 0;
+}
+
+__global__ void k_uniq_write(const uint32_t *__restrict__ g,
+                             const uint32_t *__restrict__ b, long long m,
+                             const int32_t *__restrict__ flag,
+                             const int32_t *__restrict__ pos,
+                             int32_t *__restrict__ lg, int32_t *__restrict__ lb)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < m;
+         i += (long long)gridDim.x * blockDim.x)
+        if (flag[i]) {
+            lg[pos[i]] = (int32_t)g[i];
+            lb[pos[i]] = (int32_t)b[i];
+        }
+}
+
+// Work units: runs of at most RUN consecutive list entries of one group.
+__global__ void k_group_first(const int32_t *__restrict__ lg, int m,
+                              int32_t *__restrict__ gfirst)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m;
+         i += gridDim.x * blockDim.x)
+        if (i == 0 || lg[i] != lg[i - 1])
+            gfirst[lg[i]] = i;
+}
+
+__global__ void k_units(const int32_t *__restrict__ lg, int m, int run,
+                        const int32_t *__restrict__ gfirst,
+                        int32_t *__restrict__ flag)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m;
+         i += gridDim.x * blockDim.x)
+        flag[i] = ((i - gfirst[lg[i]]) % run) == 0 ? 1 : 0;
+}
+
+__global__ void k_units_write(const int32_t *__restrict__ flag,
+                              const int32_t *__restrict__ pos, int m,
+                              int32_t *__restrict__ ubeg)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m;
+         i += gridDim.x * blockDim.x)
+        if (flag[i])
+            ubeg[pos[i]] = i;
+}
+
+// ------------------------------------------------------------ the tile ---
+
+constexpr int GT = 256;          // 4 waves
+
+template <int PREC>
+struct GramCfg;
+template <>
+struct GramCfg<FNN_PREC_BF16> {
+    static constexpr int KSTEP = 16;  // k per MFMA
+    static constexpr int EB = 2;      // bytes per element
+};
+template <>
+struct GramCfg<FNN_PREC_FP8> {
+    static constexpr int KSTEP = 64;
+    static constexpr int EB = 1;
+};
+
+struct SurvStats {
+    unsigned long long nsurv, nrc, nmis;
+    unsigned maxerr;
+};
+
+// Exact decision for one pair that passed the filter (or, when validating,
+// any pair): direct-difference FP32 key, FP64 inside the rounding band, and
+// emission of both directed edges.
+template <int M, bool FILL>
+__device__ __noinline__ void survivor(const Pts &P, const GramArgs &G,
+                                      const TileOut &out, int pi, int pj,
+                                      unsigned passed, SurvStats &st)
+{
+    const float k = key32<M>(P, pi, pj);
+    bool edge;
+    if (k < G.E.lo) {
+        edge = true;
+    } else if (k > G.E.hi) {
+        edge = false;
+    } else {
+        ++st.nrc;
+        if constexpr (M == M_L2)
+            edge = l2_sq64(P.x + (size_t)pi * P.dp, P.x + (size_t)pj * P.dp,
+                           P.dim) <= G.E.p64;
+        else
+            edge = ang_within64(P.x + (size_t)pi * P.dp,
+                                P.x + (size_t)pj * P.dp, P.dim, G.E.p64);
+    }
+    st.nsurv += passed;
+    if (!edge)
+        return;
+    if (!passed)
+        ++st.nmis;  // validate: the filter would have lost this edge
+    const float dd = edge_dist<M>(P, pi, pj, k, G.fp64_dist);
+    if (G.validate) {
+        float ref;
+        if constexpr (M == M_L2)
+            ref = (float)sqrt(l2_sq64(P.x + (size_t)pi * P.dp,
+                                      P.x + (size_t)pj * P.dp, P.dim));
+        else
+            ref = (float)ang_dist64(P.x + (size_t)pi * P.dp,
+                                    P.x + (size_t)pj * P.dp, P.dim);
+        const float re = ref > 0.f ? fabsf(dd - ref) / ref : fabsf(dd);
+        st.maxerr = max(st.maxerr, __float_as_uint(re));
+    }
+    const int oi = G.perm[pi], oj = G.perm[pj];
+    if constexpr (!FILL) {
+        atomicAdd(&out.deg[oi], 1);
+        atomicAdd(&out.deg[oj], 1);
+    } else {
+        unsigned long long s1 = atomicAdd(&out.cursor[oi], 1ull);
+        unsigned long long s2 = atomicAdd(&out.cursor[oj], 1ull);
+        if (s1 < out.nnz && s2 < out.nnz) {
+            out.col[s1] = oj;
+            out.dist[s1] = dd;
+            out.col[s2] = oi;
+            out.dist[s2] = dd;
+        } else {
+            atomicOr(out.err, ERR_INDEX);
+        }
+    }
+}
+
+template <int M, int PREC, int NKS, bool FILL>
+__global__ void __launch_bounds__(GT)
+k_gram(Pts P, GramArgs G, TileOut out)
+{
+    using C = GramCfg<PREC>;
+    constexpr int KS = C::KSTEP;
+    constexpr int BPE = C::EB;
+    constexpr int kq = NKS * KS;               // padded k (elements)
+    constexpr int nks = NKS;                   // MFMA k-steps
+    constexpr int rowb = kq * BPE;             // bytes per quantised row
+    constexpr int ldb = rowb + 16;             // LDS row stride (bytes)
+    extern __shared__ __align__(16) unsigned char smem[];
+    unsigned char *Bs = smem;                  // [GP][ldb]
+    float *ayS = (float *)(smem + GP * ldb);   // [GP]
+    float *axS = ayS + GP;                     // [4][GP]
+
+    const int t = threadIdx.x, lane = t & (WAVE - 1), w = t / WAVE;
+    const int l32 = lane & 31, hi = lane >> 5;
+    unsigned long long npairs = 0;
+    SurvStats stats{0, 0, 0, 0};
+
+    for (int u = blockIdx.x; u < G.nunits; u += gridDim.x) {
+        const int e0 = G.ubeg[u], e1 = G.ubeg[u + 1];
+        const int g = G.lg[e0];
+        const int a = G.nn + 4 * g + w;        // this wave's pack
+        // packs larger than GP (duplicate groups) are tiled by the plain path
+        const bool has_a = (4 * g + w) < G.npacks && G.q_pe[a] - G.q_pb[a] <= GP;
+        const int pa = has_a ? G.q_pb[a] : 0;
+        const int na = has_a ? G.q_pe[a] - pa : 0;
+
+        // ---- this wave's A rows into registers (two 32-row blocks) ------
+        i32x8 Areg[2][4];                      // up to 4 k-steps of 8 dwords
+        // BF16: one k-step is 16 bytes per lane (4 dwords); FP8: 32 bytes.
+        // Registers hold the whole padded k range (kq <= 128 supported).
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks)
+                Areg[rb][ks] = (i32x8){0, 0, 0, 0, 0, 0, 0, 0};
+        if (has_a) {
+#pragma unroll
+            for (int rb = 0; rb < 2; ++rb) {
+                const int r = rb * 32 + l32;
+                if (r < na) {
+                    const unsigned char *src =
+                        (const unsigned char *)G.q + (size_t)(pa + r) * rowb;
+                    if constexpr (PREC == FNN_PREC_BF16) {
+                        // k-step ks: elements ks*16 + hi*8 .. +8 (16 bytes)
+                        #pragma unroll
+                        for (int ks = 0; ks < nks; ++ks) {
+                            const int4 v = *(const int4 *)(src + (ks * 16 + hi * 8) * 2);
+                            const int slot = ks >> 1, half = ks & 1;
+                            Areg[rb][slot][half * 4 + 0] = v.x;
+                            Areg[rb][slot][half * 4 + 1] = v.y;
+                            Areg[rb][slot][half * 4 + 2] = v.z;
+                            Areg[rb][slot][half * 4 + 3] = v.w;
+                        }
+                    } else {
+                        #pragma unroll
+                        for (int ks = 0; ks < nks; ++ks) {
+                            const int4 v0 = *(const int4 *)(src + ks * 64 + hi * 32);
+                            const int4 v1 = *(const int4 *)(src + ks * 64 + hi * 32 + 16);
+                            Areg[rb][ks] = (i32x8){v0.x, v0.y, v0.z, v0.w,
+                                                   v1.x, v1.y, v1.z, v1.w};
+                        }
+                    }
+                }
+            }
+        }
+        // row terms of the filter: ax = (hx - eps2') / 2
+        for (int r = lane; r < GP; r += WAVE)
+            axS[w * GP + r] = (r < na) ? 0.5f * (G.hx[pa + r] - G.e2f) : FLT_MAX;
+
+        for (int e = e0; e < e1; ++e) {
+            const int b = G.nn + G.lb[e];
+            const int pb = G.q_pb[b];
+            const int nb = G.q_pe[b] - pb;
+            __syncthreads();
+            // ---- stage B rows (all four waves use them) -------------------
+            for (int c = t; c < GP * (rowb / 16); c += GT) {
+                const int r = c / (rowb / 16), o = (c % (rowb / 16)) * 16;
+                int4 v = make_int4(0, 0, 0, 0);
+                if (r < nb)
+                    v = *(const int4 *)((const unsigned char *)G.q +
+                                        (size_t)(pb + r) * rowb + o);
+                *(int4 *)(Bs + r * ldb + o) = v;
+            }
+            if (t < GP)
+                ayS[t] = (t < nb) ? 0.5f * G.hx[pb + t] : FLT_MAX;
+            __syncthreads();
+            if (!has_a || b < a)
+                continue;                      // pair handled elsewhere
+            const bool self = (b == a);
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb) {
+                if (cb * 32 >= nb)
+                    break;
+                f32x16 acc[2];
+                acc[0] = (f32x16){};
+                acc[1] = (f32x16){};
+                const unsigned char *brow = Bs + (cb * 32 + l32) * ldb;
+                #pragma unroll
+                        for (int ks = 0; ks < nks; ++ks) {
+                    if constexpr (PREC == FNN_PREC_BF16) {
+                        const int4 bv = *(const int4 *)(brow + (ks * 16 + hi * 8) * 2);
+                        bf16x8 bb;
+                        __builtin_memcpy(&bb, &bv, 16);
+                        const int slot = ks >> 1, half = ks & 1;
+#pragma unroll
+                        for (int rb = 0; rb < 2; ++rb) {
+                            const int4 av = make_int4(Areg[rb][slot][half * 4 + 0],
+                                                      Areg[rb][slot][half * 4 + 1],
+                                                      Areg[rb][slot][half * 4 + 2],
+                                                      Areg[rb][slot][half * 4 + 3]);
+                            bf16x8 aa;
+                            __builtin_memcpy(&aa, &av, 16);
+                            acc[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                                aa, bb, acc[rb], 0, 0, 0);
+                        }
+                    } else {
+                        const int4 b0 = *(const int4 *)(brow + ks * 64 + hi * 32);
+                        const int4 b1 = *(const int4 *)(brow + ks * 64 + hi * 32 + 16);
+                        const i32x8 bb = (i32x8){b0.x, b0.y, b0.z, b0.w,
+                                                 b1.x, b1.y, b1.z, b1.w};
+#pragma unroll
+                        for (int rb = 0; rb < 2; ++rb)
+                            acc[rb] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+                                Areg[rb][ks], bb, acc[rb], 0, 0, 0, 127, 0, 127);
+                    }
+                }
+                // ---- filter: one pass bit per accumulator ------------------
+                const int col = cb * 32 + l32;
+                const float ay = ayS[col];
+                unsigned pm = 0, om = 0;
+#pragma unroll
+                for (int rb = 0; rb < 2; ++rb) {
+#pragma unroll
+                    for (int q = 0; q < 16; ++q) {
+                        const int row = rb * 32 + 8 * (q >> 2) + 4 * hi + (q & 3);
+                        const float ax = axS[w * GP + row];
+                        const bool ok = row < na && col < nb && (!self || row < col);
+                        const bool pass = ok && (acc[rb][q] * G.gscale - ay >= ax);
+                        pm |= (unsigned)pass << (rb * 16 + q);
+                        om |= (unsigned)ok << (rb * 16 + q);
+                    }
+                }
+                // ---- survivors: exact FP32 recompute, rounding-band guard ---
+                unsigned todo = G.validate ? om : pm;
+                while (todo) {
+                    const int bit = __ffs(todo) - 1;
+                    todo &= todo - 1;
+                    const int rb = bit >> 4, q = bit & 15;
+                    const int row = rb * 32 + 8 * (q >> 2) + 4 * hi + (q & 3);
+                    survivor<M, FILL>(P, G, out, pa + row, pb + col,
+                                      (pm >> bit) & 1u, stats);
+                }
+                // pairs screened by this wave in this column block
+                if (lane == 0) {
+                    const int nc = min(32, nb - cb * 32);
+                    for (int cc = 0; cc < nc; ++cc)
+                        npairs += self ? min(na, cb * 32 + cc) : na;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    const unsigned long long nsurv = wave_sum(stats.nsurv);
+    const unsigned long long nrc = wave_sum(stats.nrc);
+    const unsigned long long nmis = wave_sum(stats.nmis);
+    const unsigned maxerr = wave_max(stats.maxerr);
+    if (lane == 0) {
+        if (npairs)
+            atomicAdd(&out.cnt[2], npairs);
+        if (nsurv)
+            atomicAdd(&out.cnt[3], nsurv);
+        if (nrc)
+            atomicAdd(&out.cnt[1], nrc);
+        if (nmis)
+            atomicAdd(&out.cnt[4], nmis);
+        if (maxerr)
+            atomicMax((unsigned *)&out.cnt[5], maxerr);
+    }
+}
+
+template <int M, int PREC, int NKS>
+static void launch_gram_k(bool fill_pass, const Pts &P, const GramArgs &G,
+                          const TileOut &o, hipStream_t s)
+{
+    const int rowb = NKS * GramCfg<PREC>::KSTEP * GramCfg<PREC>::EB;
+    const size_t sh = (size_t)GP * (rowb + 16) + sizeof(float) * GP * 5;
+    const dim3 grid(grid_for(G.nunits, 1));
+    if (fill_pass)
+        FNN_LAUNCH((k_gram<M, PREC, NKS, true>), grid, dim3(GT), sh, s, P, G, o);
+    else
+        FNN_LAUNCH((k_gram<M, PREC, NKS, false>), grid, dim3(GT), sh, s, P, G, o);
+}
+
+template <int M, int PREC>
+static void launch_gram(bool fill_pass, const Pts &P, const GramArgs &G,
+                        const TileOut &o, hipStream_t s)
+{
+    if (G.nunits <= 0)
+        return;
+    const int nks = G.kq / GramCfg<PREC>::KSTEP;
+    if constexpr (PREC == FNN_PREC_BF16) {
+        switch (nks) {
+        case 1: launch_gram_k<M, PREC, 1>(fill_pass, P, G, o, s); break;
+        case 2: launch_gram_k<M, PREC, 2>(fill_pass, P, G, o, s); break;
+        case 3: launch_gram_k<M, PREC, 3>(fill_pass, P, G, o, s); break;
+        case 4: launch_gram_k<M, PREC, 4>(fill_pass, P, G, o, s); break;
+        case 5: launch_gram_k<M, PREC, 5>(fill_pass, P, G, o, s); break;
+        case 6: launch_gram_k<M, PREC, 6>(fill_pass, P, G, o, s); break;
+        case 7: launch_gram_k<M, PREC, 7>(fill_pass, P, G, o, s); break;
+        default: launch_gram_k<M, PREC, 8>(fill_pass, P, G, o, s); break;
+        }
+    } else {
+        if (nks == 1)
+            launch_gram_k<M, PREC, 1>(fill_pass, P, G, o, s);
+        else
+            launch_gram_k<M, PREC, 2>(fill_pass, P, G, o, s);
+    }
+}
+
+void gram_launch(int metric, int prec, bool fill_pass, const Pts &P,
+                 const GramArgs &G, const TileOut &o, hipStream_t s)
+{
+    if (metric == M_L2) {
+        if (prec == FNN_PREC_BF16)
+            launch_gram<M_L2, FNN_PREC_BF16>(fill_pass, P, G, o, s);
+        else
+            launch_gram<M_L2, FNN_PREC_FP8>(fill_pass, P, G, o, s);
+    } else {
+        if (prec == FNN_PREC_BF16)
+            launch_gram<M_ANG, FNN_PREC_BF16>(fill_pass, P, G, o, s);
+        else
+            launch_gram<M_ANG, FNN_PREC_FP8>(fill_pass, P, G, o, s);
+    }
+}
+
+// ------------------------------------------------------------- host side --
+
+// Quantised copy + per-point terms, and the MFMA work lists, for one query.
+void gram_prepare(const fnn_tree *T, int prec, double eps, const Thr &E,
+                  const int2 *inter, long long ninter, Scratch &S, GramArgs &G,
+                  int2 **rest, long long *nrest)
+{
+    hipStream_t s = S.stream();
+    const int n = (int)T->n, dp = T->dp;
+    const int d = T->dim;
+    const float *X = T->metric == M_ANG ? T->xn : T->x;
+    const int KS = prec == FNN_PREC_BF16 ? 16 : 64;
+    const int kq = (int)cdiv(dp, KS) * KS;
+    if (kq > 128)
+        fail(FNN_EUNSUPPORTED, "MFMA filter supports dim <= 128 (got %d)", d);
+    const double u32 = 1.0 / 16777216.0;
+    const double u = prec == FNN_PREC_BF16 ? 1.0 / 256.0 : 1.0 / 16.0;
+    // margin coefficient (see the header comment); the FP8 subnormal terms
+    // are absorbed by the global scale that maps the largest |coordinate| to
+    // at least 224.
+    const double c1 = 2.25 * u + (3.0 * kq + 2.0 * d + 64.0) * u32 +
+                      (prec == FNN_PREC_FP8 ? 4.0 * d / 224.0 / 512.0 : 0.0);
+    // mean, scale
+    float *sums = S.get<float>(dp);
+    fill(sums, 0.f, dp, s);
+    FNN_LAUNCH(k_colsum, dim3((unsigned)cdiv(n, 1024)), dim3(256), 0, s, X, n,
+               dp, sums);
+    float scale = 1.f;
+    if (prec == FNN_PREC_FP8) {
+        unsigned *mx = S.get<unsigned>(1);
+        fill(mx, 0u, 1, s);
+        FNN_LAUNCH(k_absmax, dim3(grid_for((int64_t)n * dp, 256)), dim3(256), 0,
+                   s, X, n, dp, sums, 1.0f / n, mx);
+        unsigned mb = read_scalar(mx, s);
+        float m;
+        memcpy(&m, &mb, 4);
+        if (m > 0.f) {
+            int e;
+            frexpf(224.0f / m, &e);  // 2^(e-1) <= 224/m < 2^e
+            scale = ldexpf(1.f, e - 1);
+        }
+    }
+    G.gscale = 1.0f / (scale * scale);
+    G.kq = kq;
+    void *qbuf = S.raw((size_t)n * kq * (prec == FNN_PREC_BF16 ? 2 : 1) + 64);
+    float *hxbuf = S.get<float>(n);
+    G.q = qbuf;
+    G.hx = hxbuf;
+    if (prec == FNN_PREC_BF16)
+        FNN_LAUNCH((k_quant<FNN_PREC_BF16>), dim3(grid_for(n, 4)), dim3(256), 0,
+                   s, X, n, dp, kq, sums, 1.0f / n, scale, (float)(1.0 - c1), qbuf,
+                   hxbuf);
+    else
+        FNN_LAUNCH((k_quant<FNN_PREC_FP8>), dim3(grid_for(n, 4)), dim3(256), 0,
+                   s, X, n, dp, kq, sums, 1.0f / n, scale, (float)(1.0 - c1), qbuf,
+                   hxbuf);
+    // the filter compares against eps^2 in key space, slightly enlarged so
+    // the FP32 evaluation of the test itself cannot flip a true edge
+    const double T2 = T->metric == M_L2 ? eps * eps : 2.0 - 2.0 * E.p64;
+    G.e2f = (float)(T2 * (1.0 + 64.0 * u32) + 1e-30);
+    G.E = E;
+
+    // ---- lists: canonical pairs, routed, unique per (group, B) ----------
+    const int nn = (int)T->nnodes;
+    const int npk = (int)T->npacks;
+    uint32_t *k1 = S.get<uint32_t>(ninter + 1), *v1 = S.get<uint32_t>(ninter + 1);
+    int2 *rs = S.get<int2>(ninter + 1);
+    unsigned long long *cnt = S.get<unsigned long long>(2);
+    fill(cnt, 0ull, 2, s);
+    FNN_LAUNCH(k_route, dim3(grid_for(ninter, 256)), dim3(256), 0, s, inter,
+               ninter, T->q_pt_begin, T->q_pt_end, nn, GP, k1, v1, cnt, rs);
+    unsigned long long hc[2];
+    FNN_HIP(hipMemcpyAsync(hc, cnt, sizeof hc, hipMemcpyDeviceToHost, s));
+    FNN_HIP(hipStreamSynchronize(s));
+    const long long m = (long long)hc[0];
+    *rest = rs;
+    *nrest = (long long)hc[1];
+    G.nn = nn;
+    G.npacks = npk;
+    if (m == 0) {
+        G.nunits = 0;
+        return;
+    }
+    auto bits = [](uint32_t v) {
+        int b = 0;
+        while (v) {
+            ++b;
+            v >>= 1;
+        }
+        return b;
+    };
+    uint32_t *k2 = S.get<uint32_t>(m), *v2 = S.get<uint32_t>(m);
+    // sort by B, then stably by group: (group, B) order
+    radix_sort_pairs(k1, v1, k2, v2, m, bits((uint32_t)npk), S);
+    uint32_t *gk = S.get<uint32_t>(m), *bv = S.get<uint32_t>(m);
+    radix_sort_pairs(v2, k2, gk, bv, m, bits((uint32_t)(npk / 4 + 1)), S);
+    int32_t *flag = S.get<int32_t>(m + 1), *pos = S.get<int32_t>(m + 2);
+    FNN_LAUNCH(k_uniq_flags, dim3(grid_for(m, 256)), dim3(256), 0, s, gk, bv, m,
+               flag);
+    scan_i32(flag, pos, m, S);
+    const int mu = read_scalar(pos + m, s);
+    int32_t *lg = S.get<int32_t>(mu + 1), *lb = S.get<int32_t>(mu + 1);
+    G.lg = lg;
+    G.lb = lb;
+    FNN_LAUNCH(k_uniq_write, dim3(grid_for(m, 256)), dim3(256), 0, s, gk, bv, m,
+               flag, pos, lg, lb);
+    // units of at most RUN entries of one group
+    const int RUN = 64;
+    int32_t *uf = S.get<int32_t>(mu + 1), *up = S.get<int32_t>(mu + 2);
+    int32_t *gfirst = S.get<int32_t>(npk / 4 + 2);
+    FNN_LAUNCH(k_group_first, dim3(grid_for(mu, 256)), dim3(256), 0, s, lg, mu,
+               gfirst);
+    FNN_LAUNCH(k_units, dim3(grid_for(mu, 256)), dim3(256), 0, s, lg, mu, RUN,
+               gfirst, uf);
+    scan_i32(uf, up, mu, S);
+    const int nu = read_scalar(up + mu, s);
+    int32_t *ubeg = S.get<int32_t>(nu + 1);
+    G.ubeg = ubeg;
+    FNN_LAUNCH(k_units_write, dim3(grid_for(mu, 256)), dim3(256), 0, s, uf, up,
+               mu, ubeg);
+    FNN_HIP(hipMemcpyAsync(ubeg + nu, &mu, sizeof(int), hipMemcpyHostToDevice, s));
+    FNN_HIP(hipStreamSynchronize(s));
+    G.nunits = nu;
+    G.nlist = mu;
+}
+
+}  // namespace fnn

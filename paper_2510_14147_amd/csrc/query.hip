@@ -23,9 +23,11 @@
 #include <limits.h>
 #include <math.h>
 
+#include <string.h>
+
 #include <algorithm>
 
-#include "tree.h"
+#include "gram.h"
 
 namespace fnn {
 
@@ -195,16 +197,6 @@ k_expand(Pts P, QView Q, Prune pr, const int2 *__restrict__ cur, long long ncur,
 }
 
 // --------------------------------------------------------------- tiles ---
-
-struct TileOut {
-    int32_t *deg;                 // count pass
-    unsigned long long *cursor;   // fill pass: next free slot of each row
-    int32_t *col;
-    float *dist;
-    unsigned long long *cnt;      // [0] pairs, [1] FP64 rechecks
-    unsigned long long nnz;       // fill pass: slots available
-    int *err;                     // fill pass: a write would leave the CSR
-};
 
 template <int M>
 struct TileSmem;
@@ -766,15 +758,35 @@ static void eps_graph_impl(const fnn_tree *T, double eps, const Options &opt,
     traverse<M>(T, P, Q, pr, S, &inter, &ninter, st);
     tm.mark();  // 1
 
+    // ---- MFMA filter set-up (vector metrics, dim <= 128) ----------------
+    const bool use_gram = (M == M_L2 || M == M_ANG) && opt.precision != FNN_PREC_FP32;
+    GramArgs G{};
+    int2 *plain = inter;
+    long long nplain = ninter;
+    if constexpr (M == M_L2 || M == M_ANG) {
+        if (use_gram) {
+            gram_prepare(T, opt.precision, eps, E, inter, ninter, S, G, &plain,
+                         &nplain);
+            G.fp64_dist = fp64_dist;
+            G.validate = opt.validate;
+            G.q_pb = T->q_pt_begin;
+            G.q_pe = T->q_pt_end;
+            G.perm = T->perm;
+        }
+    }
+    tm.mark();  // 2
+
     // ---- count pass -----------------------------------------------------
-    unsigned long long *cnt = S.get<unsigned long long>(4);
-    fill(cnt, 0ull, 4, s);
+    unsigned long long *cnt = S.get<unsigned long long>(8);
+    fill(cnt, 0ull, 8, s);
     TileOut o{};
     o.cnt = cnt;
     o.deg = S.get<int32_t>(n);
     fill(o.deg, 0, n, s);
-    launch_tiles<M>(false, P, inter, ninter, T, E, fp64_dist, o, s);
-    tm.mark();  // 2
+    if (use_gram)
+        gram_launch(M, opt.precision, false, P, G, o, s);
+    launch_tiles<M>(false, P, plain, nplain, T, E, fp64_dist, o, s);
+    tm.mark();  // 3
 
     // ---- scan -----------------------------------------------------------
     C->n = n;
@@ -782,11 +794,11 @@ static void eps_graph_impl(const fnn_tree *T, double eps, const Options &opt,
     scan_i32_to_i64(o.deg, C->row_ptr, n, S);
     const int64_t nnz = read_scalar(C->row_ptr + n, s);
     C->nnz = nnz;
-    unsigned long long hc0[2];  // count-pass counters (stream is idle here)
+    unsigned long long hc0[8];  // count-pass counters (stream is idle here)
     FNN_HIP(hipMemcpy(hc0, cnt, sizeof hc0, hipMemcpyDeviceToHost));
     C->col = (int32_t *)out_alloc(sizeof(int32_t) * (size_t)std::max<int64_t>(nnz, 1));
     C->dist = (float *)out_alloc(sizeof(float) * (size_t)std::max<int64_t>(nnz, 1));
-    tm.mark();  // 3
+    tm.mark();  // 4
 
     // ---- fill pass ------------------------------------------------------
     o.cursor = S.get<unsigned long long>(n);
@@ -798,11 +810,14 @@ static void eps_graph_impl(const fnn_tree *T, double eps, const Options &opt,
     int *bad = S.get<int>(1);
     fill(bad, 0, 1, s);
     o.err = bad;
-    if (nnz > 0)
-        launch_tiles<M>(true, P, inter, ninter, T, E, fp64_dist, o, s);
+    if (nnz > 0) {
+        if (use_gram)
+            gram_launch(M, opt.precision, true, P, G, o, s);
+        launch_tiles<M>(true, P, plain, nplain, T, E, fp64_dist, o, s);
+    }
     FNN_LAUNCH(k_cursor_check, dim3(cdiv(n, 256)), dim3(256), 0, s,
                        C->row_ptr, n, o.cursor, bad);
-    tm.mark();  // 4
+    tm.mark();  // 5
 
     // ---- per-row sort ---------------------------------------------------
     int32_t *mid = S.get<int32_t>(n), *lng = S.get<int32_t>(n);
@@ -829,7 +844,7 @@ static void eps_graph_impl(const fnn_tree *T, double eps, const Options &opt,
                                C->row_ptr, lng, soff, scr, C->col, C->dist);
         }
     }
-    tm.mark();  // 5
+    tm.mark();  // 6
     unsigned long long hc[2];
     int hbad = 0;
     FNN_HIP(hipMemcpyAsync(hc, cnt, sizeof hc, hipMemcpyDeviceToHost, s));
@@ -841,16 +856,25 @@ static void eps_graph_impl(const fnn_tree *T, double eps, const Options &opt,
     st.n = n;
     st.nodes = T->nnodes;
     st.packs = T->npacks;
-    st.tile_pairs = (int64_t)hc0[0];
+    st.tile_pairs = (int64_t)(hc0[0] + hc0[3]);
     st.fp64_rechecks = (int64_t)hc0[1];
+    st.filter_pairs = (int64_t)hc0[2];
+    st.filter_survivors = (int64_t)hc0[3];
+    st.validate_mismatch = (int64_t)hc0[4];
+    {
+        unsigned eb = (unsigned)hc0[5];
+        float ef;
+        memcpy(&ef, &eb, 4);
+        st.max_rel_err = ef;
+    }
     st.edges = nnz;
-    st.traverse_ms = tm.ms(0, 1);
-    st.count_ms = tm.ms(1, 2);
-    st.scan_ms = tm.ms(2, 3);
-    st.fill_ms = tm.ms(3, 4);
-    st.sort_ms = tm.ms(4, 5);
+    st.traverse_ms = tm.ms(0, 1) + tm.ms(1, 2);
+    st.count_ms = tm.ms(2, 3);
+    st.scan_ms = tm.ms(3, 4);
+    st.fill_ms = tm.ms(4, 5);
+    st.sort_ms = tm.ms(5, 6);
     st.tile_ms = st.count_ms + st.fill_ms;
-    st.total_ms = tm.ms(0, 5);
+    st.total_ms = tm.ms(0, 6);
     (void)opt;
 }
 

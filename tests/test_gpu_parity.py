@@ -115,3 +115,34 @@ def test_deterministic(fnn, orc):
     a, b = g1.to_numpy(), g2.to_numpy()
     for u, v in zip(a, b):
         assert np.array_equal(u, v)
+
+
+# ---- MFMA Gram filter (BF16 / FP8) -----------------------------------------
+
+@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+@pytest.mark.parametrize("case", ["c1", "rand16", "c2_8k", "ang"])
+def test_mfma_filter_parity(fnn, orc, prec, case):
+    if case == "c1":
+        x, eps, metric = G.c1_clusters(), W["c1"]["eps"], "l2"
+    elif case == "rand16":
+        x, eps, metric = G.random_points(4000, 16, seed=77, duplicates=30), 0.9, "l2"
+    elif case == "c2_8k":
+        x, eps, metric = G.c2_manifold(n=8000), W["c2_50k"]["eps"][1], "l2"
+    else:
+        x, eps, metric = G.angular_dirs(n=6000, dim=16), W["ang"]["eps"], "angular"
+    tree, g, cmp = check(fnn, orc, x, metric, eps, tree_check=False,
+                         precision=prec, validate=True)
+    st = g.stats
+    assert st["filter_pairs"] > 0
+    assert st["validate_mismatch"] == 0
+    assert st["max_rel_err"] <= 1e-5
+
+
+def test_mfma_filter_screens(fnn, orc):
+    # without validation the filter must reject most pairs of a 128-d set
+    x = G.c2_manifold(n=20000)
+    eps = W["c2_50k"]["eps"][0]
+    tree, g, cmp = check(fnn, orc, x, "l2", eps, tree_check=False, precision="bf16")
+    st = g.stats
+    assert st["filter_survivors"] < 0.05 * st["filter_pairs"]
+    assert st["filter_survivors"] >= g.nnz // 2
