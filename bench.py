@@ -143,7 +143,17 @@ def main():
     # on the stream it runs on).  Algorithmic work: 3*d flops per pair
     # (difference, square, accumulate) for the vector metrics.
     roof = None
-    if metric in ("l2", "angular") and tq["count_ms"] > 0:
+    if metric in ("l2", "angular") and args.precision != "fp32" and tq["count_ms"] > 0:
+        # MFMA Gram filter: 2*k flops per screened pair (k = padded dim)
+        kq = -(-dim // 16) * 16 if args.precision == "bf16" else -(-dim // 64) * 64
+        flops = 2.0 * kq * tq["filter_pairs"]
+        ach = flops / (tq["count_ms"] / 1e3) / 1e12
+        peak = PEAK_BF16_TFLOPS if args.precision == "bf16" else PEAK_FP8_TFLOPS
+        roof = {"bound": "mfma", "achieved": round(ach, 3), "peak": peak,
+                "unit": "TFLOP/s", "frac": round(ach / peak, 4), "traffic": None,
+                "kernel": f"k_gram<L2,{args.precision},count>",
+                "kernel_ms": round(tq["count_ms"], 3), "flops_per_launch": flops}
+    elif metric in ("l2", "angular") and tq["count_ms"] > 0:
         flops = 3.0 * dim * tq["tile_pairs"]
         ach = flops / (tq["count_ms"] / 1e3) / 1e12
         roof = {"bound": "alu", "achieved": round(ach, 3),
@@ -167,6 +177,7 @@ def main():
                       "fill": tq["fill_ms"], "sort": tq["sort_ms"]},
         "counters": {k: tq[k] for k in ("interactions", "tile_pairs",
                                         "traverse_tests", "fp64_rechecks",
+                                        "filter_pairs", "filter_survivors",
                                         "packs", "nodes")} |
                     {"build_dist_evals": tb["build_dist_evals"],
                      "rounds": tb["rounds"], "netsel_passes": tb["netsel_passes"]},

@@ -30,7 +30,20 @@ struct GramArgs {
     int fp64_dist, validate;
     const int32_t *lg, *lb, *ubeg;  // work lists: group, B pack, unit starts
     const int32_t *q_pb, *q_pe, *perm;
+    // survivor list: (i, j | passed << 31) tree positions
+    int2 *surv;
+    unsigned long long *nsurv;     // running count (may exceed cap)
+    long long surv_cap;
 };
+
+// Exact decision of the survivor list: edge list (input ids, FP32 distance)
+// and per-row degrees; returns nothing, counts land in out.cnt.
+void survivors_launch(int metric, const Pts &P, const GramArgs &G,
+                      long long nsurv, int2 *edges, float *edist,
+                      unsigned long long *nedges, const TileOut &o,
+                      hipStream_t s);
+void edges_scatter(const int2 *edges, const float *edist, long long ne,
+                   const TileOut &o, hipStream_t s);
 
 void gram_prepare(const fnn_tree *T, int prec, double eps, const Thr &E,
                   const int2 *inter, long long ninter, Scratch &S, GramArgs &G,

@@ -196,70 +196,7 @@ struct GramCfg<FNN_PREC_FP8> {
     static constexpr int EB = 1;
 };
 
-struct SurvStats {
-    unsigned long long nsurv, nrc, nmis;
-    unsigned maxerr;
-};
-
-// Exact decision for one pair that passed the filter (or, when validating,
-// any pair): direct-difference FP32 key, FP64 inside the rounding band, and
-// emission of both directed edges.
-template <int M, bool FILL>
-__device__ __noinline__ void survivor(const Pts &P, const GramArgs &G,
-                                      const TileOut &out, int pi, int pj,
-                                      unsigned passed, SurvStats &st)
-{
-    const float k = key32<M>(P, pi, pj);
-    bool edge;
-    if (k < G.E.lo) {
-        edge = true;
-    } else if (k > G.E.hi) {
-        edge = false;
-    } else {
-        ++st.nrc;
-        if constexpr (M == M_L2)
-            edge = l2_sq64(P.x + (size_t)pi * P.dp, P.x + (size_t)pj * P.dp,
-                           P.dim) <= G.E.p64;
-        else
-            edge = ang_within64(P.x + (size_t)pi * P.dp,
-                                P.x + (size_t)pj * P.dp, P.dim, G.E.p64);
-    }
-    st.nsurv += passed;
-    if (!edge)
-        return;
-    if (!passed)
-        ++st.nmis;  // validate: the filter would have lost this edge
-    const float dd = edge_dist<M>(P, pi, pj, k, G.fp64_dist);
-    if (G.validate) {
-        float ref;
-        if constexpr (M == M_L2)
-            ref = (float)sqrt(l2_sq64(P.x + (size_t)pi * P.dp,
-                                      P.x + (size_t)pj * P.dp, P.dim));
-        else
-            ref = (float)ang_dist64(P.x + (size_t)pi * P.dp,
-                                    P.x + (size_t)pj * P.dp, P.dim);
-        const float re = ref > 0.f ? fabsf(dd - ref) / ref : fabsf(dd);
-        st.maxerr = max(st.maxerr, __float_as_uint(re));
-    }
-    const int oi = G.perm[pi], oj = G.perm[pj];
-    if constexpr (!FILL) {
-        atomicAdd(&out.deg[oi], 1);
-        atomicAdd(&out.deg[oj], 1);
-    } else {
-        unsigned long long s1 = atomicAdd(&out.cursor[oi], 1ull);
-        unsigned long long s2 = atomicAdd(&out.cursor[oj], 1ull);
-        if (s1 < out.nnz && s2 < out.nnz) {
-            out.col[s1] = oj;
-            out.dist[s1] = dd;
-            out.col[s2] = oi;
-            out.dist[s2] = dd;
-        } else {
-            atomicOr(out.err, ERR_INDEX);
-        }
-    }
-}
-
-template <int M, int PREC, int NKS, bool FILL>
+template <int M, int PREC, int NKS>
 __global__ void __launch_bounds__(GT)
 k_gram(Pts P, GramArgs G, TileOut out)
 {
@@ -278,7 +215,7 @@ k_gram(Pts P, GramArgs G, TileOut out)
     const int t = threadIdx.x, lane = t & (WAVE - 1), w = t / WAVE;
     const int l32 = lane & 31, hi = lane >> 5;
     unsigned long long npairs = 0;
-    SurvStats stats{0, 0, 0, 0};
+    const uint64_t ltmask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
 
     for (int u = blockIdx.x; u < G.nunits; u += gridDim.x) {
         const int e0 = G.ubeg[u], e1 = G.ubeg[u + 1];
@@ -332,23 +269,45 @@ k_gram(Pts P, GramArgs G, TileOut out)
         for (int r = lane; r < GP; r += WAVE)
             axS[w * GP + r] = (r < na) ? 0.5f * (G.hx[pa + r] - G.e2f) : FLT_MAX;
 
+        // B tiles are software-pipelined: the rows of entry e+1 are loaded
+        // into registers while entry e is on the matrix cores.
+        constexpr int CPR = rowb / 16;                      // 16-byte chunks per row
+        constexpr int NCH = (GP * CPR + GT - 1) / GT;       // chunks per thread
+        int4 pre[NCH];
+        float pre_ay = FLT_MAX;
+        auto load_b = [&](int e) {
+            const int bb = G.nn + G.lb[e];
+            const int pbb = G.q_pb[bb];
+            const int nbb = G.q_pe[bb] - pbb;
+#pragma unroll
+            for (int i = 0; i < NCH; ++i) {
+                const int c = t + i * GT;
+                const int r = c / CPR, o = (c % CPR) * 16;
+                pre[i] = make_int4(0, 0, 0, 0);
+                if (c < GP * CPR && r < nbb)
+                    pre[i] = *(const int4 *)((const unsigned char *)G.q +
+                                             (size_t)(pbb + r) * rowb + o);
+            }
+            if (t < GP)
+                pre_ay = (t < nbb) ? 0.5f * G.hx[pbb + t] : FLT_MAX;
+        };
+        load_b(e0);
         for (int e = e0; e < e1; ++e) {
             const int b = G.nn + G.lb[e];
             const int pb = G.q_pb[b];
             const int nb = G.q_pe[b] - pb;
             __syncthreads();
-            // ---- stage B rows (all four waves use them) -------------------
-            for (int c = t; c < GP * (rowb / 16); c += GT) {
-                const int r = c / (rowb / 16), o = (c % (rowb / 16)) * 16;
-                int4 v = make_int4(0, 0, 0, 0);
-                if (r < nb)
-                    v = *(const int4 *)((const unsigned char *)G.q +
-                                        (size_t)(pb + r) * rowb + o);
-                *(int4 *)(Bs + r * ldb + o) = v;
+#pragma unroll
+            for (int i = 0; i < NCH; ++i) {
+                const int c = t + i * GT;
+                if (c < GP * CPR)
+                    *(int4 *)(Bs + (c / CPR) * ldb + (c % CPR) * 16) = pre[i];
             }
             if (t < GP)
-                ayS[t] = (t < nb) ? 0.5f * G.hx[pb + t] : FLT_MAX;
+                ayS[t] = pre_ay;
             __syncthreads();
+            if (e + 1 < e1)
+                load_b(e + 1);
             if (!has_a || b < a)
                 continue;                      // pair handled elsewhere
             const bool self = (b == a);
@@ -400,47 +359,197 @@ k_gram(Pts P, GramArgs G, TileOut out)
                         const int row = rb * 32 + 8 * (q >> 2) + 4 * hi + (q & 3);
                         const float ax = axS[w * GP + row];
                         const bool ok = row < na && col < nb && (!self || row < col);
-                        const bool pass = ok && (acc[rb][q] * G.gscale - ay >= ax);
+                        const float gq = PREC == FNN_PREC_BF16 ? acc[rb][q] : acc[rb][q] * G.gscale;
+                        const bool pass = ok && (gq - ay >= ax);
                         pm |= (unsigned)pass << (rb * 16 + q);
                         om |= (unsigned)ok << (rb * 16 + q);
                     }
                 }
-                // ---- survivors: exact FP32 recompute, rounding-band guard ---
-                unsigned todo = G.validate ? om : pm;
-                while (todo) {
-                    const int bit = __ffs(todo) - 1;
-                    todo &= todo - 1;
-                    const int rb = bit >> 4, q = bit & 15;
-                    const int row = rb * 32 + 8 * (q >> 2) + 4 * hi + (q & 3);
-                    survivor<M, FILL>(P, G, out, pa + row, pb + col,
-                                      (pm >> bit) & 1u, stats);
+                // ---- survivors: appended for the exact decision kernel -----
+                const unsigned todo = G.validate ? om : pm;
+                const int mine = __popc(todo);
+                int incl = mine;
+#pragma unroll
+                for (int o = 1; o < WAVE; o <<= 1) {
+                    const int v = __shfl_up(incl, o, WAVE);
+                    if (lane >= o)
+                        incl += v;
+                }
+                const int total = __shfl(incl, WAVE - 1, WAVE);
+                if (total) {
+                    unsigned long long base = 0;
+                    if (lane == 0)
+                        base = atomicAdd(G.nsurv, (unsigned long long)total);
+                    base = __shfl(base, 0, WAVE);
+                    unsigned long long o = base + (unsigned long long)(incl - mine);
+                    unsigned tb = todo;
+                    while (tb) {
+                        const int bit = __ffs(tb) - 1;
+                        tb &= tb - 1;
+                        const int rb = bit >> 4, q = bit & 15;
+                        const int row = rb * 32 + 8 * (q >> 2) + 4 * hi + (q & 3);
+                        if ((long long)o < G.surv_cap)
+                            G.surv[o] = make_int2(pa + row,
+                                                  (pb + col) | (int)(((pm >> bit) & 1u) << 31));
+                        ++o;
+                    }
                 }
                 // pairs screened by this wave in this column block
                 if (lane == 0) {
-                    const int nc = min(32, nb - cb * 32);
-                    for (int cc = 0; cc < nc; ++cc)
-                        npairs += self ? min(na, cb * 32 + cc) : na;
+                    // rows r < na against columns c0 .. c0+nc-1 (r < c if self)
+                    const long long nc = min(32, nb - cb * 32), c0 = cb * 32;
+                    if (!self) {
+                        npairs += (unsigned long long)(na * nc);
+                    } else {
+                        // sum_{c=c0}^{c0+nc-1} min(na, c)
+                        const long long lo = c0, hi2 = c0 + nc;  // [lo, hi2)
+                        const long long mid = max(lo, min(hi2, (long long)na));
+                        npairs += (unsigned long long)((mid - lo) * (lo + mid - 1) / 2 +
+                                                       (hi2 - mid) * na);
+                    }
                 }
             }
         }
         __syncthreads();
     }
-    const unsigned long long nsurv = wave_sum(stats.nsurv);
-    const unsigned long long nrc = wave_sum(stats.nrc);
-    const unsigned long long nmis = wave_sum(stats.nmis);
-    const unsigned maxerr = wave_max(stats.maxerr);
+    if (lane == 0 && npairs)
+        atomicAdd(&out.cnt[2], npairs);
+}
+
+// Exact decision of every survivor: direct-difference FP32 key, FP64 inside
+// the rounding band; edges go to an unordered list (input ids, distance) and
+// to the row degrees.
+template <int M>
+__global__ void __launch_bounds__(256)
+k_survive(Pts P, GramArgs G, long long ns, int2 *__restrict__ edges,
+          float *__restrict__ edist, unsigned long long *__restrict__ nedges,
+          TileOut out)
+{
+    const int lane = threadIdx.x & (WAVE - 1);
+    const uint64_t ltm = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    unsigned long long nrc = 0, npass = 0, nmis = 0;
+    unsigned maxerr = 0;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    // the loop runs a whole number of waves so that ballots see every lane
+    const long long lim = (ns + WAVE - 1) / WAVE * WAVE;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < lim;
+         i += stride) {
+        bool edge = false;
+        float dd = 0.f;
+        int oi = 0, oj = 0;
+        if (i < ns) {
+            const int2 e = G.surv[i];
+            const int pi = e.x, pj = e.y & 0x7FFFFFFF;
+            const bool passed = (e.y >> 31) & 1;
+            npass += passed;
+            const float k = key32<M>(P, pi, pj);
+            if (k < G.E.lo) {
+                edge = true;
+            } else if (k > G.E.hi) {
+                edge = false;
+            } else {
+                ++nrc;
+                if constexpr (M == M_L2)
+                    edge = l2_sq64(P.x + (size_t)pi * P.dp, P.x + (size_t)pj * P.dp,
+                                   P.dim) <= G.E.p64;
+                else
+                    edge = ang_within64(P.x + (size_t)pi * P.dp,
+                                        P.x + (size_t)pj * P.dp, P.dim, G.E.p64);
+            }
+            if (edge) {
+                if (!passed)
+                    ++nmis;  // validate: the filter would have lost this edge
+                dd = edge_dist<M>(P, pi, pj, k, G.fp64_dist);
+                if (G.validate) {
+                    float ref;
+                    if constexpr (M == M_L2)
+                        ref = (float)sqrt(l2_sq64(P.x + (size_t)pi * P.dp,
+                                                  P.x + (size_t)pj * P.dp, P.dim));
+                    else
+                        ref = (float)ang_dist64(P.x + (size_t)pi * P.dp,
+                                                P.x + (size_t)pj * P.dp, P.dim);
+                    const float re = ref > 0.f ? fabsf(dd - ref) / ref : fabsf(dd);
+                    maxerr = max(maxerr, __float_as_uint(re));
+                }
+                oi = G.perm[pi];
+                oj = G.perm[pj];
+                atomicAdd(&out.deg[oi], 1);
+                atomicAdd(&out.deg[oj], 1);
+            }
+        }
+        const uint64_t m = __ballot(edge);
+        if (m) {
+            unsigned long long base = 0;
+            if (lane == 0)
+                base = atomicAdd(nedges, (unsigned long long)__popcll(m));
+            base = __shfl(base, 0, WAVE);
+            if (edge) {
+                const unsigned long long o = base + __popcll(m & ltm);
+                edges[o] = make_int2(oi, oj);
+                edist[o] = dd;
+            }
+        }
+    }
+    nrc = wave_sum(nrc);
+    npass = wave_sum(npass);
+    nmis = wave_sum(nmis);
+    maxerr = wave_max(maxerr);
     if (lane == 0) {
-        if (npairs)
-            atomicAdd(&out.cnt[2], npairs);
-        if (nsurv)
-            atomicAdd(&out.cnt[3], nsurv);
         if (nrc)
             atomicAdd(&out.cnt[1], nrc);
+        if (npass)
+            atomicAdd(&out.cnt[3], npass);
         if (nmis)
             atomicAdd(&out.cnt[4], nmis);
         if (maxerr)
             atomicMax((unsigned *)&out.cnt[5], maxerr);
     }
+}
+
+__global__ void k_edges_scatter(const int2 *__restrict__ edges,
+                                const float *__restrict__ edist, long long ne,
+                                TileOut out)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < ne;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int2 e = edges[i];
+        const float d = edist[i];
+        const unsigned long long s1 = atomicAdd(&out.cursor[e.x], 1ull);
+        const unsigned long long s2 = atomicAdd(&out.cursor[e.y], 1ull);
+        if (s1 < out.nnz && s2 < out.nnz) {
+            out.col[s1] = e.y;
+            out.dist[s1] = d;
+            out.col[s2] = e.x;
+            out.dist[s2] = d;
+        } else {
+            atomicOr(out.err, ERR_INDEX);
+        }
+    }
+}
+
+void survivors_launch(int metric, const Pts &P, const GramArgs &G,
+                      long long nsurv, int2 *edges, float *edist,
+                      unsigned long long *nedges, const TileOut &o,
+                      hipStream_t s)
+{
+    if (nsurv <= 0)
+        return;
+    const dim3 g(grid_for(nsurv, 256));
+    if (metric == M_L2)
+        FNN_LAUNCH((k_survive<M_L2>), g, dim3(256), 0, s, P, G, nsurv, edges,
+                   edist, nedges, o);
+    else
+        FNN_LAUNCH((k_survive<M_ANG>), g, dim3(256), 0, s, P, G, nsurv, edges,
+                   edist, nedges, o);
+}
+
+void edges_scatter(const int2 *edges, const float *edist, long long ne,
+                   const TileOut &o, hipStream_t s)
+{
+    if (ne <= 0)
+        return;
+    FNN_LAUNCH(k_edges_scatter, dim3(grid_for(ne, 256)), dim3(256), 0, s, edges,
+               edist, ne, o);
 }
 
 template <int M, int PREC, int NKS>
@@ -450,10 +559,8 @@ static void launch_gram_k(bool fill_pass, const Pts &P, const GramArgs &G,
     const int rowb = NKS * GramCfg<PREC>::KSTEP * GramCfg<PREC>::EB;
     const size_t sh = (size_t)GP * (rowb + 16) + sizeof(float) * GP * 5;
     const dim3 grid(grid_for(G.nunits, 1));
-    if (fill_pass)
-        FNN_LAUNCH((k_gram<M, PREC, NKS, true>), grid, dim3(GT), sh, s, P, G, o);
-    else
-        FNN_LAUNCH((k_gram<M, PREC, NKS, false>), grid, dim3(GT), sh, s, P, G, o);
+    (void)fill_pass;
+    FNN_LAUNCH((k_gram<M, PREC, NKS>), grid, dim3(GT), sh, s, P, G, o);
 }
 
 template <int M, int PREC>

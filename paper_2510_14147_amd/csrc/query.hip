@@ -783,8 +783,35 @@ static void eps_graph_impl(const fnn_tree *T, double eps, const Options &opt,
     o.cnt = cnt;
     o.deg = S.get<int32_t>(n);
     fill(o.deg, 0, n, s);
-    if (use_gram)
-        gram_launch(M, opt.precision, false, P, G, o, s);
+    int2 *gedges = nullptr;
+    float *gedist = nullptr;
+    long long ngedges = 0;
+    if (use_gram) {
+        // one filter pass; the survivor buffer sizes itself (a second
+        // attempt only if the first guess was too small)
+        unsigned long long *ns = S.get<unsigned long long>(2);
+        long long cap = opt.validate ? (long long)n * (n - 1) / 2 + 1
+                                     : std::max<long long>(1ll << 24, 64ll * n);
+        for (int attempt = 0;; ++attempt) {
+            G.surv = S.get<int2>(cap);
+            G.surv_cap = cap;
+            G.nsurv = ns;
+            fill(ns, 0ull, 2, s);
+            fill(cnt + 2, 0ull, 1, s);
+            gram_launch(M, opt.precision, false, P, G, o, s);
+            const long long got = (long long)read_scalar(ns, s);
+            if (got <= cap || attempt > 0) {
+                if (got > cap)
+                    fail(FNN_EINTERNAL, "survivor list overflow");
+                gedges = S.get<int2>(got + 1);
+                gedist = S.get<float>(got + 1);
+                survivors_launch(M, P, G, got, gedges, gedist, ns + 1, o, s);
+                ngedges = (long long)read_scalar(ns + 1, s);
+                break;
+            }
+            cap = got + got / 8 + 1024;
+        }
+    }
     launch_tiles<M>(false, P, plain, nplain, T, E, fp64_dist, o, s);
     tm.mark();  // 3
 
@@ -812,7 +839,7 @@ static void eps_graph_impl(const fnn_tree *T, double eps, const Options &opt,
     o.err = bad;
     if (nnz > 0) {
         if (use_gram)
-            gram_launch(M, opt.precision, true, P, G, o, s);
+            edges_scatter(gedges, gedist, ngedges, o, s);
         launch_tiles<M>(true, P, plain, nplain, T, E, fp64_dist, o, s);
     }
     FNN_LAUNCH(k_cursor_check, dim3(cdiv(n, 256)), dim3(256), 0, s,
