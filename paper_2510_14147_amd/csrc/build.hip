@@ -270,6 +270,9 @@ __device__ __forceinline__ bool better(float d, int id, float d2, int id2)
     return d > d2 || (d == d2 && id < id2);
 }
 
+constexpr int UPD_K = 32;   // centres staged per pass
+constexpr int UPD_D = 128;  // largest row stride staged in LDS
+
 template <int M>
 __global__ void __launch_bounds__(CH)
 k_update(Pts P, const int32_t *__restrict__ ch_hub, const int32_t *__restrict__ ch_s,
@@ -279,6 +282,7 @@ k_update(Pts P, const int32_t *__restrict__ ch_hub, const int32_t *__restrict__ 
          const LevelTab *__restrict__ tab, float *__restrict__ cb_D,
          int32_t *__restrict__ cb_id, unsigned long long *__restrict__ cnt)
 {
+    __shared__ __align__(16) float cen[UPD_K * UPD_D];
     for (int c = blockIdx.x; c < NC; c += gridDim.x) {
     const int h = ch_hub[c];
     if (!hb.act[h])
@@ -290,17 +294,64 @@ k_update(Pts P, const int32_t *__restrict__ ch_hub, const int32_t *__restrict__ 
     const int j0 = hb.ma[h], j1 = hb.m[h];
     float dv = -1.f;
     int id = INT_MAX;
+    bool staged = false;
+    if constexpr (M == M_L2 || M == M_ANG) {
+        // vector metrics: the pass's new centres go to LDS once per chunk and
+        // every point row is read once for all of them
+        staged = (j1 > j0) && (j1 - j0) <= UPD_K && P.dp <= UPD_D;
+        if (staged) {
+            const float *X = (M == M_ANG) ? P.xn : P.x;
+            const int nj = j1 - j0, dp = P.dp;
+            for (int e = threadIdx.x; e < nj * dp; e += CH)
+                cen[e] = X[(size_t)cent[b + j0 + e / dp] * dp + (e % dp)];
+        }
+        __syncthreads();
+    }
     if (valid) {
         const int o = perm[p];
         float dcur = D[p];
         int lcur = L[p];
-        for (int j = j0; j < j1; ++j) {
-            float k = key32<M>(P, o, cent[b + j]);
-            if (k < dcur) {
-                dcur = k;
-                lcur = j;
+        if constexpr (M == M_L2 || M == M_ANG) {
+            if (staged) {
+                const float *X = (M == M_ANG) ? P.xn : P.x;
+                const float *row = X + (size_t)o * P.dp;
+                const int nj = j1 - j0;
+                float acc[UPD_K];
+#pragma unroll
+                for (int j = 0; j < UPD_K; ++j)
+                    acc[j] = 0.f;
+                for (int k = 0; k < P.dp; k += 4) {
+                    const float4 v = *reinterpret_cast<const float4 *>(row + k);
+#pragma unroll
+                    for (int j = 0; j < UPD_K; ++j) {
+                        if (j < nj) {
+                            const float4 c = *reinterpret_cast<const float4 *>(
+                                cen + j * P.dp + k);
+                            const float d0 = v.x - c.x, d1 = v.y - c.y,
+                                        d2 = v.z - c.z, d3 = v.w - c.w;
+                            acc[j] = fmaf(d0, d0, acc[j]);
+                            acc[j] = fmaf(d1, d1, acc[j]);
+                            acc[j] = fmaf(d2, d2, acc[j]);
+                            acc[j] = fmaf(d3, d3, acc[j]);
+                        }
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < UPD_K; ++j)
+                    if (j < nj && acc[j] < dcur) {
+                        dcur = acc[j];
+                        lcur = j0 + j;
+                    }
             }
         }
+        if (!staged)
+            for (int j = j0; j < j1; ++j) {
+                float k = key32<M>(P, o, cent[b + j]);
+                if (k < dcur) {
+                    dcur = k;
+                    lcur = j;
+                }
+            }
         if (j1 > j0) {
             D[p] = dcur;
             L[p] = lcur;

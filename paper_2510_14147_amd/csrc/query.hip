@@ -71,36 +71,56 @@ struct Emit {
     int *overflow;
 };
 
-__device__ __forceinline__ void emit_pair(const Emit &E, const QView &Q,
-                                          bool valid, int a, int b)
+// Per-wave staging of emitted pairs in LDS: one global reservation per
+// STG entries instead of one contended atomic per wave step.
+constexpr int STG = 512;
+struct Stage {
+    int2 *buf[2];   // [0] next frontier, [1] interactions
+    int n[2];       // entries held (wave-uniform)
+};
+
+__device__ __forceinline__ void stage_flush(const Emit &E, Stage &sg, int k)
+{
+    __builtin_amdgcn_wave_barrier();
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int c = sg.n[k];
+    if (c == 0)
+        return;
+    unsigned long long base = 0;
+    if (lane == 0)
+        base = atomicAdd(&E.cnt[k], (unsigned long long)c);
+    base = __shfl(base, 0, WAVE);
+    int2 *dst = k ? E.inter : E.next;
+    const long long cap = k ? E.inter_cap : E.next_cap;
+    for (int i = lane; i < c; i += WAVE) {
+        const long long p = (long long)(base + i);
+        if (p < cap)
+            dst[p] = sg.buf[k][i];
+        else
+            *E.overflow = 1;
+    }
+    sg.n[k] = 0;
+}
+
+__device__ __forceinline__ void emit_pair(const Emit &E, Stage &sg,
+                                          const QView &Q, bool valid, int a,
+                                          int b)
 {
     const int lane = threadIdx.x & (WAVE - 1);
     const bool term = valid && a >= Q.nn && b >= Q.nn;
     const bool nxt = valid && !term;
-    const uint64_t mt = __ballot(term), mn = __ballot(nxt);
+    const uint64_t m[2] = {__ballot(nxt), __ballot(term)};
     const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-    unsigned long long bt = 0, bn = 0;
-    if (lane == 0) {
-        if (mt)
-            bt = atomicAdd(&E.cnt[1], (unsigned long long)__popcll(mt));
-        if (mn)
-            bn = atomicAdd(&E.cnt[0], (unsigned long long)__popcll(mn));
-    }
-    bt = __shfl(bt, 0, WAVE);
-    bn = __shfl(bn, 0, WAVE);
-    if (term) {
-        unsigned long long p = bt + __popcll(mt & lt);
-        if ((long long)p < E.inter_cap)
-            E.inter[p] = make_int2(a, b);
-        else
-            *E.overflow = 1;
-    }
-    if (nxt) {
-        unsigned long long p = bn + __popcll(mn & lt);
-        if ((long long)p < E.next_cap)
-            E.next[p] = make_int2(a, b);
-        else
-            *E.overflow = 1;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const int c = __popcll(m[k]);
+        if (c == 0)
+            continue;
+        if (sg.n[k] + c > STG)
+            stage_flush(E, sg, k);
+        if ((m[k] >> lane) & 1ull)
+            sg.buf[k][sg.n[k] + __popcll(m[k] & lt)] = make_int2(a, b);
+        sg.n[k] += c;
     }
 }
 
@@ -109,13 +129,13 @@ __device__ __forceinline__ void emit_pair(const Emit &E, const QView &Q,
 template <int M>
 __device__ unsigned long long expand_one(const Pts &P, const QView &Q,
                                          const Prune &pr, int a, int b,
-                                         const Emit &E)
+                                         const Emit &E, Stage &sg)
 {
     const int lane = threadIdx.x & (WAVE - 1);
     unsigned long long tests = 0;
     if (a == b) {
         if (a >= Q.nn) {  // a single pack against itself
-            emit_pair(E, Q, lane == 0, a, a);
+            emit_pair(E, sg, Q, lane == 0, a, a);
             return 0;
         }
         const int m = Q.kcnt[a], k0 = Q.kbeg[a];
@@ -145,13 +165,13 @@ __device__ unsigned long long expand_one(const Pts &P, const QView &Q,
                     valid = may_touch<M>(P, Q, pr, ka, kb);
                 }
             }
-            emit_pair(E, Q, valid, ka, kb);
+            emit_pair(E, sg, Q, valid, ka, kb);
         }
     } else {
         const bool at = a >= Q.nn, bt_ = b >= Q.nn;
         int s, o;
         if (at && bt_) {  // cannot happen (packs pairs are emitted directly)
-            emit_pair(E, Q, lane == 0, a, b);
+            emit_pair(E, sg, Q, lane == 0, a, b);
             return 0;
         }
         if (at)
@@ -172,10 +192,43 @@ __device__ unsigned long long expand_one(const Pts &P, const QView &Q,
                 ++tests;
                 valid = may_touch<M>(P, Q, pr, ka, o);
             }
-            emit_pair(E, Q, valid, ka, o);
+            emit_pair(E, sg, Q, valid, ka, o);
         }
     }
     return tests;
+}
+
+// Upper bound of the pairs a level can emit (no distances): m children of
+// the split vertex, or m(m+1)/2 child pairs of a self pair.
+__global__ void k_expand_bound(QView Q, const int2 *__restrict__ cur,
+                               long long ncur,
+                               unsigned long long *__restrict__ bound)
+{
+    unsigned long long b = 0;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < ncur;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int2 p = cur[i];
+        const int a = p.x, c = p.y;
+        if (a == c) {
+            const long long m = a >= Q.nn ? 1 : Q.kcnt[a];
+            b += (unsigned long long)(m * (m + 1) / 2);
+        } else {
+            const bool at = a >= Q.nn, ct = c >= Q.nn;
+            int s;
+            if (at && ct)
+                s = -1;
+            else if (at)
+                s = c;
+            else if (ct)
+                s = a;
+            else
+                s = Q.rad[a] >= Q.rad[c] ? a : c;
+            b += s < 0 ? 1ull : (unsigned long long)Q.kcnt[s];
+        }
+    }
+    b = wave_sum(b);
+    if ((threadIdx.x & (WAVE - 1)) == 0 && b)
+        atomicAdd(bound, b);
 }
 
 template <int M>
@@ -183,14 +236,21 @@ __global__ void __launch_bounds__(256)
 k_expand(Pts P, QView Q, Prune pr, const int2 *__restrict__ cur, long long ncur,
          Emit E)
 {
-    const int lane = threadIdx.x & (WAVE - 1);
+    __shared__ int2 stg[256 / WAVE][2][STG];
+    const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
     const long long wpb = blockDim.x / WAVE;
+    Stage sg;
+    sg.buf[0] = stg[wid][0];
+    sg.buf[1] = stg[wid][1];
+    sg.n[0] = sg.n[1] = 0;
     unsigned long long tests = 0;
-    for (long long w = (long long)blockIdx.x * wpb + threadIdx.x / WAVE;
-         w < ncur; w += (long long)gridDim.x * wpb) {
+    for (long long w = (long long)blockIdx.x * wpb + wid; w < ncur;
+         w += (long long)gridDim.x * wpb) {
         const int2 pr2 = cur[w];
-        tests += expand_one<M>(P, Q, pr, pr2.x, pr2.y, E);
+        tests += expand_one<M>(P, Q, pr, pr2.x, pr2.y, E, sg);
     }
+    stage_flush(E, sg, 0);
+    stage_flush(E, sg, 1);
     tests = wave_sum(tests);
     if (lane == 0 && tests)
         atomicAdd(&E.cnt[2], tests);
@@ -645,55 +705,53 @@ static void traverse(const fnn_tree *T, const Pts &P, const QView &Q,
 {
     hipStream_t s = S.stream();
     long long cap_cur = 1 << 16, cap_next = 1 << 16;
-    long long cap_int = std::max<long long>(1 << 16, T->npacks * 8);
+    long long cap_int = std::max<long long>(1 << 20, T->npacks * 16);
     int2 *cur = S.get<int2>(cap_cur), *next = S.get<int2>(cap_next);
     int2 *inter = S.get<int2>(cap_int);
     unsigned long long *cnt = S.get<unsigned long long>(4);
     int *ovf = S.get<int>(1);
-    fill(cnt, 0ull, 4, s);
     int2 root = make_int2(T->qroot, T->qroot);
     FNN_HIP(hipMemcpyAsync(cur, &root, sizeof(int2), hipMemcpyHostToDevice, s));
     long long ncur = 1, ninter = 0, tests = 0;
     while (ncur > 0) {
-        for (;;) {
-            unsigned long long init[3] = {0ull, (unsigned long long)ninter, 0ull};
-            FNN_HIP(hipMemcpyAsync(cnt, init, sizeof init, hipMemcpyHostToDevice, s));
-            fill(ovf, 0, 1, s);
-            Emit E{next, inter, cnt, cap_next, cap_int, ovf};
-            FNN_LAUNCH((k_expand<M>), dim3(grid_for(ncur, 4)), dim3(256), 0, s,
-                       P, Q, pr, cur, ncur, E);
-            unsigned long long hc[3];
-            int hov = 0;
-            FNN_HIP(hipMemcpyAsync(hc, cnt, sizeof hc, hipMemcpyDeviceToHost, s));
-            FNN_HIP(hipMemcpyAsync(&hov, ovf, sizeof(int), hipMemcpyDeviceToHost, s));
-            FNN_HIP(hipStreamSynchronize(s));
-            if (!hov) {
-                ncur = (long long)hc[0];
-                ninter = (long long)hc[1];
-                tests += (long long)hc[2];
-                break;
-            }
-            // grow the buffer(s) that overflowed and redo this level
-            if ((long long)hc[0] > cap_next) {
-                cap_next = (long long)(hc[0] * 5 / 4 + 1024);
-                next = S.get<int2>(cap_next);
-            }
-            if ((long long)hc[1] > cap_int) {
-                long long nc = (long long)(hc[1] * 5 / 4 + 1024);
-                int2 *ni = S.get<int2>(nc);
-                if (ninter > 0)
-                    FNN_HIP(hipMemcpyAsync(ni, inter, sizeof(int2) * ninter,
-                                           hipMemcpyDeviceToDevice, s));
-                inter = ni;
-                cap_int = nc;
-            }
-        }
-        std::swap(cur, next);
-        std::swap(cap_cur, cap_next);
-        if (ncur > cap_next) {
-            cap_next = ncur * 2;
+        // bound the level's output and size both buffers before running it
+        fill(cnt + 3, 0ull, 1, s);
+        FNN_LAUNCH(k_expand_bound, dim3(grid_for(ncur, 256)), dim3(256), 0, s, Q,
+                   cur, ncur, cnt + 3);
+        const long long bnd = (long long)read_scalar(cnt + 3, s);
+        if (bnd > cap_next) {
+            S.release(next);
+            cap_next = bnd + bnd / 8 + 1024;
             next = S.get<int2>(cap_next);
         }
+        if (ninter + bnd > cap_int) {
+            long long nc = std::max(cap_int * 2, ninter + bnd + (ninter + bnd) / 8);
+            int2 *ni = S.get<int2>(nc);
+            if (ninter > 0)
+                FNN_HIP(hipMemcpyAsync(ni, inter, sizeof(int2) * ninter,
+                                       hipMemcpyDeviceToDevice, s));
+            S.release(inter);
+            inter = ni;
+            cap_int = nc;
+        }
+        unsigned long long init[3] = {0ull, (unsigned long long)ninter, 0ull};
+        FNN_HIP(hipMemcpyAsync(cnt, init, sizeof init, hipMemcpyHostToDevice, s));
+        fill(ovf, 0, 1, s);
+        Emit E{next, inter, cnt, cap_next, cap_int, ovf};
+        FNN_LAUNCH((k_expand<M>), dim3(grid_for(ncur, 4)), dim3(256), 0, s, P, Q,
+                   pr, cur, ncur, E);
+        unsigned long long hc[3];
+        int hov = 0;
+        FNN_HIP(hipMemcpyAsync(hc, cnt, sizeof hc, hipMemcpyDeviceToHost, s));
+        FNN_HIP(hipMemcpyAsync(&hov, ovf, sizeof(int), hipMemcpyDeviceToHost, s));
+        FNN_HIP(hipStreamSynchronize(s));
+        if (hov)
+            fail(FNN_EINTERNAL, "traversal emitted more pairs than its bound");
+        ncur = (long long)hc[0];
+        ninter = (long long)hc[1];
+        tests += (long long)hc[2];
+        std::swap(cur, next);
+        std::swap(cap_cur, cap_next);
     }
     *inter_out = inter;
     *ninter_out = ninter;
