@@ -91,8 +91,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the epsilon-graph path has no "
-              "multi-GPU mode in this build (see the sharding note in the "
-              "design document); run with --gpus 1", file=sys.stderr)
+              "multi-GPU mode; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
