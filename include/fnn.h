@@ -83,7 +83,11 @@ typedef struct fnn_options {
     int32_t validate;     /* 1: also measure the max FP32 distance error     */
                           /* against FP64 and count filter false negatives    */
     int32_t kmax;         /* centres accepted per net-selection pass (1..64) */
-    int32_t reserved[9];
+    int32_t trace;        /* 1: keep per-point features and targets of this  */
+                          /* query for training the cost model               */
+    int32_t slack_pct;    /* learned schedule: slot slack in percent of the  */
+                          /* predicted row length (default 30; may be < 0)   */
+    int32_t reserved[7];
 } fnn_options;
 
 typedef struct fnn_tree fnn_tree;  /* opaque; device-resident cover tree */
@@ -124,7 +128,9 @@ typedef struct fnn_stats {
     double max_rel_err;       /* validate: max |dist32 - dist64| / dist64    */
     double build_ms, traverse_ms, tile_ms, count_ms, scan_ms, fill_ms,
            sort_ms, total_ms;
-    double reserved[8];
+    double pred_mae;          /* learned: mean |predicted - true| log1p(deg) */
+    double pred_sum_ratio;    /* learned: sum predicted / sum true degrees    */
+    double reserved[6];
 } fnn_stats;
 
 /* Build the cover tree of n points (Algorithms 1-2).  points: device
@@ -178,6 +184,38 @@ int fnn_tree_info(const fnn_tree *tree, int64_t *n, int64_t *nodes);
 int fnn_tree_export(const fnn_tree *tree, int32_t *order, int32_t *center,
                     float *radius, int32_t *level, int32_t *child_begin,
                     int32_t *child_count, int32_t *pt_begin, int32_t *pt_end);
+
+/* ---- learned cost model (schedules only; never decides an edge) ----------
+ * A 16 -> 64 -> 64 -> 2 perceptron with SiLU activations predicts, per point,
+ * log1p(block pairs of its query pack) and log1p(its neighbour count) from
+ * scale-free tree features.  Parameters: 5378 floats, row-major
+ * W1[64][16], b1[64], W2[64][64], b2[64], W3[2][64], b3[2].  Loss of a batch
+ * of B samples: (1/(2B)) * sum of squared errors over both outputs. */
+#define FNN_MLP_NPARAMS 5378
+#define FNN_MLP_NFEAT 16
+
+/* Install the model used by FNN_SCHED_LEARNED (host array of
+ * FNN_MLP_NPARAMS floats, copied). */
+int fnn_set_cost_model(const float *params, int64_t nparams);
+
+/* Trace of a query run with options.trace = 1: device arrays, owned by the
+ * CSR handle, in tree order: features [n][16], targets [n][2]. */
+int fnn_get_trace(const fnn_csr *csr, const float **features,
+                  const float **targets, int64_t *n);
+
+/* Inference: Y[n][2] = f(X[n][16]); all device pointers. */
+int fnn_mlp_forward(const float *params, const float *X, int64_t n, float *Y);
+
+/* Full-batch loss and its gradient (device params/X/T/grad; *loss on host). */
+int fnn_mlp_loss_grad(const float *params, const float *X, const float *T,
+                      int64_t n, float *grad, double *loss);
+
+/* Train in place with Adam (device params, X, T): `epochs` passes over a
+ * seeded shuffle in batches of `batch`; epoch_loss (host, may be NULL)
+ * receives the mean loss of each epoch. */
+int fnn_mlp_train(float *params, const float *X, const float *T, int64_t n,
+                  int32_t epochs, int32_t batch, float lr, uint64_t seed,
+                  double *epoch_loss);
 
 /* Message of the last error on this thread ("" if none). */
 const char *fnn_last_error(void);

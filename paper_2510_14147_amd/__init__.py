@@ -40,7 +40,8 @@ class fnn_options(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_int32), ("zeta", ctypes.c_int32),
                 ("pack", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("sched", ctypes.c_int32), ("validate", ctypes.c_int32),
-                ("kmax", ctypes.c_int32), ("reserved", ctypes.c_int32 * 9)]
+                ("kmax", ctypes.c_int32), ("trace", ctypes.c_int32),
+                ("slack_pct", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
 
 
 class fnn_csr(ctypes.Structure):
@@ -55,13 +56,14 @@ _STAT_I64 = ["n", "nodes", "leaf_blocks", "packs", "rounds", "netsel_passes",
              "tile_pairs", "filter_pairs", "filter_survivors",
              "fp64_rechecks", "edges", "overflow_rows", "validate_mismatch"]
 _STAT_F64 = ["max_rel_err", "build_ms", "traverse_ms", "tile_ms", "count_ms",
-             "scan_ms", "fill_ms", "sort_ms", "total_ms"]
+             "scan_ms", "fill_ms", "sort_ms", "total_ms", "pred_mae",
+             "pred_sum_ratio"]
 
 
 class fnn_stats(ctypes.Structure):
     _fields_ = ([(k, ctypes.c_int64) for k in _STAT_I64] +
                 [(k, ctypes.c_double) for k in _STAT_F64] +
-                [("reserved", ctypes.c_double * 8)])
+                [("reserved", ctypes.c_double * 6)])
 
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -123,6 +125,14 @@ def lib():
         L.fnn_get_stats.argtypes = [vp, ctypes.POINTER(fnn_stats)]
         L.fnn_tree_info.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
         L.fnn_tree_export.argtypes = [vp] + [vp] * 8
+        L.fnn_set_cost_model.argtypes = [vp, i64]
+        L.fnn_get_trace.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                    ctypes.POINTER(i64)]
+        L.fnn_mlp_forward.argtypes = [vp, vp, i64, vp]
+        L.fnn_mlp_loss_grad.argtypes = [vp, vp, vp, i64, vp,
+                                        ctypes.POINTER(ctypes.c_double)]
+        L.fnn_mlp_train.argtypes = [vp, vp, vp, i64, i32, i32, ctypes.c_float,
+                                    ctypes.c_uint64, vp]
         _lib = L
         L.fnn_set_allocator(_alloc_cb, _free_cb, None)
     return _lib
@@ -193,6 +203,14 @@ class Graph:
         self.col = _live[c.col][: 4 * self.nnz].view(torch.int32)
         self.dist = _live[c.dist][: 4 * self.nnz].view(torch.float32)
         self.stats = _stats(ptr)
+        self.features = self.targets = None
+        f, t, nn = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_int64()
+        if lib().fnn_get_trace(ctypes.cast(ptr, ctypes.c_void_p), ctypes.byref(f),
+                               ctypes.byref(t), ctypes.byref(nn)) == FNN_OK:
+            self.features = _live[f.value][: 4 * MLP_NFEAT * self.n].view(
+                torch.float32).view(self.n, MLP_NFEAT)
+            self.targets = _live[t.value][: 8 * self.n].view(torch.float32).view(
+                self.n, 2)
 
     def free(self):
         if self._ptr:
@@ -244,11 +262,34 @@ def fnn_tree_build(points, metric: str = "l2", zeta=None, pack=None,
     return tree
 
 
+MLP_NPARAMS, MLP_NFEAT = 5378, 16
+COST_MODEL_PATH = os.path.join(_HERE, "cost_model.json")
+_model_set = False
+
+
+def fnn_set_cost_model(params) -> None:
+    """Install the cost model (5378 floats) used by sched="learned"."""
+    global _model_set
+    a = np.ascontiguousarray(np.asarray(params, dtype=np.float32).ravel())
+    _check(lib().fnn_set_cost_model(ctypes.c_void_p(a.ctypes.data), a.size))
+    _model_set = True
+
+
+def load_cost_model(path: str = COST_MODEL_PATH) -> np.ndarray:
+    import json
+    with open(path) as f:
+        return np.asarray(json.load(f)["params"], dtype=np.float32)
+
+
 def fnn_eps_graph(tree: Tree, eps: float, precision="fp32",
-                  sched="two_pass", validate=False) -> Graph:
+                  sched="two_pass", validate=False, trace=False,
+                  slack_pct=None) -> Graph:
+    if sched == "learned" and not _model_set and os.path.exists(COST_MODEL_PATH):
+        fnn_set_cost_model(load_cost_model())
     _bind_stream()
     out = ctypes.POINTER(fnn_csr)()
-    o = _options(precision=precision, sched=sched, validate=int(validate))
+    o = _options(precision=precision, sched=sched, validate=int(validate),
+                 trace=int(trace), slack_pct=slack_pct)
     _check(lib().fnn_eps_graph_ex(tree.handle, float(eps), ctypes.byref(o),
                                   ctypes.byref(out)))
     return Graph(out)
@@ -282,3 +323,40 @@ def fnn_tree_export(tree: Tree) -> dict:
 
 def version() -> int:
     return lib().fnn_version()
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def fnn_mlp_forward(params, X):
+    """Y[n,2] = f(X[n,16]) with the library's inference kernel (cuda
+    float32 tensors)."""
+    torch = _torch()
+    Y = torch.empty((X.shape[0], 2), dtype=torch.float32, device=X.device)
+    _bind_stream()
+    _check(lib().fnn_mlp_forward(_ptr(params), _ptr(X), X.shape[0], _ptr(Y)))
+    return Y
+
+
+def fnn_mlp_loss_grad(params, X, T):
+    """(loss, grad) of the full batch, from the library's backward kernel."""
+    torch = _torch()
+    g = torch.empty(MLP_NPARAMS, dtype=torch.float32, device=X.device)
+    loss = ctypes.c_double()
+    _bind_stream()
+    _check(lib().fnn_mlp_loss_grad(_ptr(params), _ptr(X), _ptr(T), X.shape[0],
+                                   _ptr(g), ctypes.byref(loss)))
+    return loss.value, g
+
+
+def fnn_mlp_train(params, X, T, epochs=4, batch=4096, lr=1e-3, seed=0):
+    """Train params in place (Adam); returns the mean loss of each epoch."""
+    losses = np.zeros(max(epochs, 1), dtype=np.float64)
+    _bind_stream()
+    _check(lib().fnn_mlp_train(_ptr(params), _ptr(X), _ptr(T), X.shape[0],
+                               int(epochs), int(batch), ctypes.c_float(lr),
+                               ctypes.c_uint64(seed),
+                               ctypes.c_void_p(losses.ctypes.data)))
+    return losses[:epochs]
+

@@ -6,14 +6,41 @@
 #include <new>
 #include <string>
 
-#include "tree.h"
+#include <mutex>
+
+#include "learn.h"
 
 namespace fnn {
 extern thread_local hipStream_t g_stream;
 void set_alloc_hook(fnn_alloc_fn a, fnn_free_fn f, void *ctx);
 void build_tree(fnn_tree *T, const void *points, Scratch &S);
 void eps_graph(const fnn_tree *T, double eps, const Options &opt, fnn_csr *C,
-               fnn_stats &st, Scratch &S);
+               fnn_stats &st, Scratch &S, float **tf, float **tt);
+
+// The installed cost model: one device copy per device.
+static std::mutex g_model_mu;
+static std::vector<float> g_model_host;
+static float *g_model_dev[64] = {nullptr};
+static uint64_t g_model_gen = 0, g_model_dev_gen[64] = {0};
+
+const float *cost_model_device()
+{
+    std::lock_guard<std::mutex> lk(g_model_mu);
+    if (g_model_host.empty())
+        return nullptr;
+    int dev = 0;
+    FNN_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64)
+        fail(FNN_EUNSUPPORTED, "device id %d", dev);
+    if (!g_model_dev[dev])
+        FNN_HIP(hipMalloc(&g_model_dev[dev], sizeof(float) * MLP_NPAR));
+    if (g_model_dev_gen[dev] != g_model_gen) {
+        FNN_HIP(hipMemcpy(g_model_dev[dev], g_model_host.data(),
+                          sizeof(float) * MLP_NPAR, hipMemcpyHostToDevice));
+        g_model_dev_gen[dev] = g_model_gen;
+    }
+    return g_model_dev[dev];
+}
 
 static thread_local std::string g_err;
 
@@ -46,13 +73,29 @@ Options read_options(const fnn_options *o)
     r.validate = o->validate ? 1 : 0;
     if (o->kmax)
         r.kmax = o->kmax > 64 ? 64 : o->kmax;
+    r.trace = o->trace ? 1 : 0;
+    if (o->slack_pct)
+        r.slack_pct = o->slack_pct < -90 ? -90 : o->slack_pct;
     return r;
 }
 
 struct CsrBox {
     fnn_csr pub;
     fnn_stats stats;
+    float *trace_feat;
+    float *trace_targ;
 };
+
+static void free_box(CsrBox *B)
+{
+    out_free(B->pub.row_ptr);
+    out_free(B->pub.col);
+    out_free(B->pub.dist);
+    out_free(B->trace_feat);
+    out_free(B->trace_targ);
+    B->pub.kind = 0;
+    delete B;
+}
 
 }  // namespace fnn
 
@@ -160,26 +203,22 @@ int fnn_eps_graph_ex(const fnn_tree *tree, double eps, const fnn_options *opt,
         B = new CsrBox();
         memset(&B->pub, 0, sizeof B->pub);
         memset(&B->stats, 0, sizeof B->stats);
+        B->trace_feat = B->trace_targ = nullptr;
         B->pub.kind = KIND_CSR;
-        Scratch S(current_stream());
-        eps_graph(tree, eps, o, &B->pub, B->stats, S);
+        {
+            Scratch S(current_stream());
+            eps_graph(tree, eps, o, &B->pub, B->stats, S, &B->trace_feat,
+                      &B->trace_targ);
+        }
         *out = &B->pub;
         return FNN_OK;
     } catch (const Error &e) {
-        if (B) {
-            out_free(B->pub.row_ptr);
-            out_free(B->pub.col);
-            out_free(B->pub.dist);
-            delete B;
-        }
+        if (B)
+            free_box(B);
         return set_err(e.code, e.msg);
     } catch (...) {
-        if (B) {
-            out_free(B->pub.row_ptr);
-            out_free(B->pub.col);
-            out_free(B->pub.dist);
-            delete B;
-        }
+        if (B)
+            free_box(B);
         return set_err(FNN_EINTERNAL, "unexpected exception");
     }
 }
@@ -199,12 +238,7 @@ void fnn_free(void *handle)
         T->kind = 0;
         delete T;
     } else if (kind == KIND_CSR) {
-        CsrBox *B = (CsrBox *)handle;  // pub is the first member
-        out_free(B->pub.row_ptr);
-        out_free(B->pub.col);
-        out_free(B->pub.dist);
-        B->pub.kind = 0;
-        delete B;
+        free_box((CsrBox *)handle);  // pub is the first member
     }
 }
 
@@ -259,6 +293,84 @@ int fnn_tree_export(const fnn_tree *T, int32_t *order, int32_t *center,
                 FNN_HIP(hipMemcpyAsync(c.dst, c.src, c.bytes,
                                        hipMemcpyDeviceToHost, s));
         FNN_HIP(hipStreamSynchronize(s));
+        return FNN_OK;
+    } catch (const Error &e) {
+        return set_err(e.code, e.msg);
+    }
+}
+
+int fnn_set_cost_model(const float *params, int64_t nparams)
+{
+    if (!params || nparams != MLP_NPAR)
+        return set_err(FNN_EINVAL, "cost model needs 5378 parameters");
+    for (int64_t i = 0; i < nparams; ++i)
+        if (!isfinite(params[i]))
+            return set_err(FNN_EINVAL, "cost model parameter is not finite");
+    std::lock_guard<std::mutex> lk(g_model_mu);
+    g_model_host.assign(params, params + nparams);
+    ++g_model_gen;
+    return FNN_OK;
+}
+
+int fnn_get_trace(const fnn_csr *csr, const float **features,
+                  const float **targets, int64_t *n)
+{
+    if (!csr || csr->kind != KIND_CSR)
+        return set_err(FNN_EINVAL, "not a CSR handle");
+    const CsrBox *B = (const CsrBox *)csr;
+    if (!B->trace_feat || !B->trace_targ)
+        return set_err(FNN_EINVAL, "query was not run with options.trace = 1");
+    if (features)
+        *features = B->trace_feat;
+    if (targets)
+        *targets = B->trace_targ;
+    if (n)
+        *n = csr->n;
+    return FNN_OK;
+}
+
+int fnn_mlp_forward(const float *params, const float *X, int64_t n, float *Y)
+{
+    if (!params || (n > 0 && (!X || !Y)) || n < 0)
+        return set_err(FNN_EINVAL, "bad argument");
+    try {
+        hipStream_t s = current_stream();
+        mlp_forward(params, X, n, Y, s);
+        FNN_HIP(hipStreamSynchronize(s));
+        return FNN_OK;
+    } catch (const Error &e) {
+        return set_err(e.code, e.msg);
+    }
+}
+
+int fnn_mlp_loss_grad(const float *params, const float *X, const float *T,
+                      int64_t n, float *grad, double *loss)
+{
+    if (!params || !grad || n < 0 || (n > 0 && (!X || !T)))
+        return set_err(FNN_EINVAL, "bad argument");
+    try {
+        Scratch S(current_stream());
+        const double l = mlp_loss_grad(params, X, T, n, grad, S);
+        if (loss)
+            *loss = l;
+        return FNN_OK;
+    } catch (const Error &e) {
+        return set_err(e.code, e.msg);
+    }
+}
+
+int fnn_mlp_train(float *params, const float *X, const float *T, int64_t n,
+                  int32_t epochs, int32_t batch, float lr, uint64_t seed,
+                  double *epoch_loss)
+{
+    if (!params || n < 0 || (n > 0 && (!X || !T)) || epochs < 0 || batch < 0 ||
+        !(lr > 0.f))
+        return set_err(FNN_EINVAL, "bad argument");
+    if (n > (int64_t)UINT32_MAX)
+        return set_err(FNN_EUNSUPPORTED, "too many samples");
+    try {
+        Scratch S(current_stream());
+        mlp_train(params, X, T, n, epochs, batch, lr, seed, epoch_loss, S);
         return FNN_OK;
     } catch (const Error &e) {
         return set_err(e.code, e.msg);

@@ -18,6 +18,12 @@ struct TileOut {
     unsigned long long *cnt;
     unsigned long long nnz;       // fill pass: slots available
     int *err;                     // fill pass: a write would leave the CSR
+    // learned schedule: per-row slot end (slots of row r end at row_end[r]);
+    // a row that would pass it is flagged in ovf and not written
+    const int64_t *row_end;
+    int32_t *ovf;
+    // restricted fill: only rows with row_filter[r] != 0 are written
+    const int32_t *row_filter;
 };
 
 struct GramArgs {

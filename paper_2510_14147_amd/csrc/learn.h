@@ -1,0 +1,30 @@
+// Learned cost model: shared declarations.
+#pragma once
+
+#include "tree.h"
+
+namespace fnn {
+
+constexpr int MLP_F = 16, MLP_H = 64, MLP_O = 2;
+constexpr int MLP_NPAR = MLP_H * MLP_F + MLP_H + MLP_H * MLP_H + MLP_H +
+                         MLP_O * MLP_H + MLP_O;  // 5378
+
+struct FeatArgs {
+    const int32_t *pack_of, *leaf_of, *parent, *depth, *center_pos, *pb, *pe,
+        *ccnt, *q_cpos, *q_pb, *q_pe;
+    const float *radius, *q_rad;
+    float eps;
+};
+
+void tree_aux(fnn_tree *T, Scratch &S);
+void compute_features(const fnn_tree *T, const Pts &P, float eps, float *feat,
+                      hipStream_t s);
+void mlp_forward(const float *theta, const float *X, long long n, float *Y,
+                 hipStream_t s);
+double mlp_loss_grad(const float *theta, const float *X, const float *T,
+                     long long n, float *grad, Scratch &S);
+void mlp_train(float *theta, const float *X, const float *T, long long n,
+               int epochs, int batch, float lr, unsigned long long seed,
+               double *epoch_loss, Scratch &S);
+
+}  // namespace fnn

@@ -28,6 +28,7 @@
 #include <algorithm>
 
 #include "gram.h"
+#include "learn.h"
 
 namespace fnn {
 
@@ -454,15 +455,22 @@ k_tile(Pts P, const int2 *__restrict__ inter, long long ninter,
                 const int r = t;
                 const unsigned long long bits = r < ra ? mask[r] : 0ull;
                 int c = __popcll(bits);
+                const int orow = c ? perm[pa + r] : 0;
+                if (c && FILL && out.row_filter && !out.row_filter[orow])
+                    c = 0;
                 if (c) {
-                    const int orow = perm[pa + r];
                     if constexpr (!FILL) {
                         atomicAdd(&out.deg[orow], c);
                     } else {
                         unsigned long long o = atomicAdd(&out.cursor[orow],
                                                          (unsigned long long)c);
-                        if (o + c > out.nnz) {
-                            atomicOr(out.err, ERR_INDEX);
+                        const unsigned long long lim =
+                            out.row_end ? (unsigned long long)out.row_end[orow] : out.nnz;
+                        if (o + c > lim) {
+                            if (out.row_end)
+                                out.ovf[orow] = 1;
+                            else
+                                atomicOr(out.err, ERR_INDEX);
                             c = 0;
                         }
                         unsigned long long bb = c ? bits : 0ull;
@@ -481,15 +489,23 @@ k_tile(Pts P, const int2 *__restrict__ inter, long long ninter,
                     int c = 0;
                     for (int r = 0; r < ra; ++r)
                         c += (int)((mask[r] >> cc) & 1ull);
+                    const int ocol = c ? perm[pb + cc] : 0;
+                    if (c && FILL && out.row_filter && !out.row_filter[ocol])
+                        c = 0;
                     if (c) {
-                        const int ocol = perm[pb + cc];
                         if constexpr (!FILL) {
                             atomicAdd(&out.deg[ocol], c);
                         } else {
                             unsigned long long o = atomicAdd(&out.cursor[ocol],
                                                              (unsigned long long)c);
-                            if (o + c > out.nnz) {
-                                atomicOr(out.err, ERR_INDEX);
+                            const unsigned long long lim =
+                                out.row_end ? (unsigned long long)out.row_end[ocol]
+                                            : out.nnz;
+                            if (o + c > lim) {
+                                if (out.row_end)
+                                    out.ovf[ocol] = 1;
+                                else
+                                    atomicOr(out.err, ERR_INDEX);
                                 c = 0;
                             }
                             for (int r = 0; c && r < ra; ++r)
@@ -673,6 +689,146 @@ __global__ void k_cursor_check(const int64_t *__restrict__ row_ptr, int n,
         atomicOr(bad, 1);
 }
 
+// ------------------------------------------------- learned schedule ----
+
+// Slots per row from the predicted log1p(degree) (tree order p -> row).
+__global__ void k_caps(const float *__restrict__ pred, const int32_t *__restrict__ perm,
+                       int n, float slack, int32_t *__restrict__ cap)
+{
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < n;
+         p += gridDim.x * blockDim.x) {
+        const float e = fmaxf(expm1f(fminf(pred[2 * p + 1], 30.f)), 0.f);
+        float c = ceilf(e * (1.f + slack) + 4.f);
+        c = fminf(c, (float)(n - 1));
+        cap[perm[p]] = (int32_t)fmaxf(c, 0.f);
+    }
+}
+
+__global__ void k_deg_from_cursor(const unsigned long long *__restrict__ cur,
+                                  const int64_t *__restrict__ sb, int n,
+                                  int32_t *__restrict__ deg)
+{
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n;
+         r += gridDim.x * blockDim.x)
+        deg[r] = (int32_t)(cur[r] - (unsigned long long)sb[r]);
+}
+
+// Rows that fitted their slots move to the CSR (one wave per row).
+__global__ void k_compact(const int64_t *__restrict__ sb, const int32_t *__restrict__ scol,
+                          const float *__restrict__ sdist,
+                          const int32_t *__restrict__ ovf,
+                          const int64_t *__restrict__ row_ptr, int n,
+                          int32_t *__restrict__ col, float *__restrict__ dist,
+                          int32_t *__restrict__ novf)
+{
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wpb = blockDim.x / WAVE;
+    int cnt = 0;
+    for (int r = blockIdx.x * wpb + threadIdx.x / WAVE; r < n;
+         r += gridDim.x * wpb) {
+        if (ovf[r]) {
+            cnt += lane == 0;
+            continue;
+        }
+        const int64_t b = row_ptr[r], len = row_ptr[r + 1] - b, s0 = sb[r];
+        for (int64_t i = lane; i < len; i += WAVE) {
+            col[b + i] = scol[s0 + i];
+            dist[b + i] = sdist[s0 + i];
+        }
+    }
+    if (lane == 0 && cnt)
+        atomicAdd(novf, cnt);
+}
+
+// Packs holding an overflowed row, then the block pairs touching them.
+__global__ void k_mark_packs(const int32_t *__restrict__ ovf,
+                             const int32_t *__restrict__ perm,
+                             const int32_t *__restrict__ pack_of, int n,
+                             int32_t *__restrict__ flag)
+{
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < n;
+         p += gridDim.x * blockDim.x)
+        if (ovf[perm[p]])
+            flag[pack_of[p]] = 1;
+}
+
+__global__ void k_sublist(const int2 *__restrict__ inter, long long ni,
+                          const int32_t *__restrict__ flag, int2 *__restrict__ out,
+                          unsigned long long *__restrict__ cnt)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < ni;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int2 e = inter[i];
+        if (flag[e.x] || flag[e.y])
+            out[atomicAdd(cnt, 1ull)] = e;
+    }
+}
+
+__global__ void k_cursor_check_rows(const int64_t *__restrict__ row_ptr, int n,
+                                    const unsigned long long *__restrict__ cur,
+                                    const int32_t *__restrict__ only,
+                                    int *__restrict__ bad)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += gridDim.x * blockDim.x)
+        if ((!only || only[i]) && cur[i] != (unsigned long long)row_ptr[i + 1])
+            atomicOr(bad, 1);
+}
+
+// Per-pack visits (block pairs a pack takes part in).
+__global__ void k_visits(const int2 *__restrict__ inter, long long ni, int nn,
+                         int32_t *__restrict__ vis)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < ni;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int2 e = inter[i];
+        atomicAdd(&vis[e.x - nn], 1);
+        if (e.y != e.x)
+            atomicAdd(&vis[e.y - nn], 1);
+    }
+}
+
+__global__ void k_targets(const int32_t *__restrict__ vis,
+                          const int32_t *__restrict__ pack_of,
+                          const int32_t *__restrict__ perm,
+                          const int64_t *__restrict__ row_ptr, int n, int nn,
+                          float *__restrict__ tg)
+{
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < n;
+         p += gridDim.x * blockDim.x) {
+        const int r = perm[p];
+        tg[2 * p] = log1pf((float)vis[pack_of[p] - nn]);
+        tg[2 * p + 1] = log1pf((float)(row_ptr[r + 1] - row_ptr[r]));
+    }
+}
+
+// Prediction error against the true degrees: sum |pred - log1p(deg)|,
+// sum expm1(pred), sum deg.
+__global__ void k_pred_err(const float *__restrict__ pred,
+                           const int32_t *__restrict__ perm,
+                           const int64_t *__restrict__ row_ptr, int n,
+                           double *__restrict__ acc)
+{
+    double a = 0.0, b = 0.0, c = 0.0;
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < n;
+         p += gridDim.x * blockDim.x) {
+        const int r = perm[p];
+        const double d = (double)(row_ptr[r + 1] - row_ptr[r]);
+        const double y = pred[2 * p + 1];
+        a += fabs(y - log1p(d));
+        b += expm1(fmin(y, 30.0));
+        c += d;
+    }
+    a = wave_sum(a);
+    b = wave_sum(b);
+    c = wave_sum(c);
+    if ((threadIdx.x & (WAVE - 1)) == 0) {
+        atomicAdd(&acc[0], a);
+        atomicAdd(&acc[1], b);
+        atomicAdd(&acc[2], c);
+    }
+}
+
 // -------------------------------------------------------------- driver ---
 
 struct Timer {
@@ -775,10 +931,22 @@ static void launch_tiles(bool fill_pass, const Pts &P, const int2 *inter,
                    T->q_pt_begin, T->q_pt_end, T->perm, E, fp64_dist, o);
 }
 
+// Learned-schedule state of one query.
+struct Learned {
+    const float *model = nullptr;  // device parameters (null: no model)
+    float *feat = nullptr;         // [n][16] tree order
+    float *pred = nullptr;         // [n][2]
+    float *targ = nullptr;         // [n][2] (trace)
+};
+
+const float *cost_model_device();
+
 template <int M>
-static void eps_graph_impl(const fnn_tree *T, double eps, const Options &opt,
-                           fnn_csr *C, fnn_stats &st, Scratch &S)
+static void eps_graph_impl(const fnn_tree *Tc, double eps, const Options &opt,
+                           fnn_csr *C, fnn_stats &st, Scratch &S,
+                           float **trace_feat, float **trace_targ)
 {
+    fnn_tree *T = const_cast<fnn_tree *>(Tc);  // lazily built caches only
     hipStream_t s = S.stream();
     const int n = (int)T->n;
     Timer tm(s);
@@ -809,6 +977,26 @@ static void eps_graph_impl(const fnn_tree *T, double eps, const Options &opt,
     if (M == M_ANG && eps >= M_PI)
         pr.eps = 4.f;  // every pair may touch
     const int fp64_dist = (M == M_ANG) || (M == M_L2 && (T->dim + 2) * u > 1e-5);
+    const bool learned = opt.sched == FNN_SCHED_LEARNED;
+
+    // ---- learned cost model: features and predictions ------------------
+    Learned Lm;
+    if (learned || opt.trace) {
+        tree_aux(T, S);
+        const float feps = std::max(pr.eps, 0.5f);
+        Lm.feat = opt.trace ? (float *)out_alloc(sizeof(float) * MLP_F * (size_t)n)
+                            : S.get<float>((size_t)n * MLP_F);
+        if (opt.trace)
+            *trace_feat = Lm.feat;
+        compute_features(T, P, feps, Lm.feat, s);
+    }
+    if (learned) {
+        Lm.model = cost_model_device();
+        if (!Lm.model)
+            fail(FNN_EINVAL, "learned schedule requested but no cost model is set");
+        Lm.pred = S.get<float>(2 * (size_t)n);
+        mlp_forward(Lm.model, Lm.feat, n, Lm.pred, s);
+    }
 
     // ---- traversal ------------------------------------------------------
     int2 *inter = nullptr;
@@ -834,75 +1022,163 @@ static void eps_graph_impl(const fnn_tree *T, double eps, const Options &opt,
     }
     tm.mark();  // 2
 
-    // ---- count pass -----------------------------------------------------
     unsigned long long *cnt = S.get<unsigned long long>(8);
     fill(cnt, 0ull, 8, s);
     TileOut o{};
     o.cnt = cnt;
-    o.deg = S.get<int32_t>(n);
-    fill(o.deg, 0, n, s);
-    int2 *gedges = nullptr;
-    float *gedist = nullptr;
-    long long ngedges = 0;
-    if (use_gram) {
-        // one filter pass; the survivor buffer sizes itself (a second
-        // attempt only if the first guess was too small)
-        unsigned long long *ns = S.get<unsigned long long>(2);
-        long long cap = opt.validate ? (long long)n * (n - 1) / 2 + 1
-                                     : std::max<long long>(1ll << 24, 64ll * n);
-        for (int attempt = 0;; ++attempt) {
-            G.surv = S.get<int2>(cap);
-            G.surv_cap = cap;
-            G.nsurv = ns;
-            fill(ns, 0ull, 2, s);
-            fill(cnt + 2, 0ull, 1, s);
-            gram_launch(M, opt.precision, false, P, G, o, s);
-            const long long got = (long long)read_scalar(ns, s);
-            if (got <= cap || attempt > 0) {
-                if (got > cap)
-                    fail(FNN_EINTERNAL, "survivor list overflow");
-                gedges = S.get<int2>(got + 1);
-                gedist = S.get<float>(got + 1);
-                survivors_launch(M, P, G, got, gedges, gedist, ns + 1, o, s);
-                ngedges = (long long)read_scalar(ns + 1, s);
-                break;
-            }
-            cap = got + got / 8 + 1024;
-        }
-    }
-    launch_tiles<M>(false, P, plain, nplain, T, E, fp64_dist, o, s);
-    tm.mark();  // 3
-
-    // ---- scan -----------------------------------------------------------
-    C->n = n;
-    C->row_ptr = (int64_t *)out_alloc(sizeof(int64_t) * ((size_t)n + 1));
-    scan_i32_to_i64(o.deg, C->row_ptr, n, S);
-    const int64_t nnz = read_scalar(C->row_ptr + n, s);
-    C->nnz = nnz;
-    unsigned long long hc0[8];  // count-pass counters (stream is idle here)
-    FNN_HIP(hipMemcpy(hc0, cnt, sizeof hc0, hipMemcpyDeviceToHost));
-    C->col = (int32_t *)out_alloc(sizeof(int32_t) * (size_t)std::max<int64_t>(nnz, 1));
-    C->dist = (float *)out_alloc(sizeof(float) * (size_t)std::max<int64_t>(nnz, 1));
-    tm.mark();  // 4
-
-    // ---- fill pass ------------------------------------------------------
-    o.cursor = S.get<unsigned long long>(n);
-    FNN_LAUNCH(k_cursor_init, dim3(cdiv(n, 256)), dim3(256), 0, s,
-                       C->row_ptr, n, o.cursor);
-    o.col = C->col;
-    o.dist = C->dist;
-    o.nnz = (unsigned long long)nnz;
     int *bad = S.get<int>(1);
     fill(bad, 0, 1, s);
     o.err = bad;
-    if (nnz > 0) {
-        if (use_gram)
-            edges_scatter(gedges, gedist, ngedges, o, s);
+    C->n = n;
+    C->row_ptr = (int64_t *)out_alloc(sizeof(int64_t) * ((size_t)n + 1));
+    int64_t nnz = 0;
+    int64_t novf = 0;
+    unsigned long long hc0[8] = {0};
+
+    if (use_gram || !learned) {
+        // ---- count pass (plain tiles) / filter + exact survivors (MFMA) ---
+        o.deg = S.get<int32_t>(n);
+        fill(o.deg, 0, n, s);
+        int2 *gedges = nullptr;
+        float *gedist = nullptr;
+        long long ngedges = 0;
+        if (use_gram) {
+            unsigned long long *ns = S.get<unsigned long long>(2);
+            long long cap = std::max<long long>(1ll << 24, 64ll * n);
+            if (learned) {
+                // predicted ordered edges / 2, times the filter's survivor
+                // factor (BF16 ~1.5, FP8 tens on high-dimensional data)
+                double *acc = S.get<double>(3);
+                fill(acc, 0.0, 3, s);
+                int64_t *zero_rp = S.get<int64_t>(n + 1);
+                fill(zero_rp, (int64_t)0, n + 1, s);
+                FNN_LAUNCH(k_pred_err, dim3(grid_for(n, 256)), dim3(256), 0, s,
+                           Lm.pred, T->perm, zero_rp, n, acc);
+                double hacc[3];
+                FNN_HIP(hipMemcpyAsync(hacc, acc, sizeof hacc, hipMemcpyDeviceToHost, s));
+                FNN_HIP(hipStreamSynchronize(s));
+                const double fac = opt.precision == FNN_PREC_BF16 ? 2.0 : 40.0;
+                cap = std::max<long long>(1ll << 20, (long long)(0.5 * hacc[1] * fac));
+            }
+            if (opt.validate)
+                cap = std::max<long long>(cap, (long long)n * (n - 1) / 2 + 1);
+            for (int attempt = 0;; ++attempt) {
+                G.surv = S.get<int2>(cap);
+                G.surv_cap = cap;
+                G.nsurv = ns;
+                fill(ns, 0ull, 2, s);
+                fill(cnt + 2, 0ull, 1, s);
+                gram_launch(M, opt.precision, false, P, G, o, s);
+                const long long got = (long long)read_scalar(ns, s);
+                if (got <= cap || attempt > 0) {
+                    if (got > cap)
+                        fail(FNN_EINTERNAL, "survivor list overflow");
+                    gedges = S.get<int2>(got + 1);
+                    gedist = S.get<float>(got + 1);
+                    survivors_launch(M, P, G, got, gedges, gedist, ns + 1, o, s);
+                    ngedges = (long long)read_scalar(ns + 1, s);
+                    break;
+                }
+                S.release(G.surv);
+                cap = got + got / 8 + 1024;
+                ++novf;  // a second filter pass was needed
+            }
+        }
+        launch_tiles<M>(false, P, plain, nplain, T, E, fp64_dist, o, s);
+        tm.mark();  // 3
+
+        scan_i32_to_i64(o.deg, C->row_ptr, n, S);
+        nnz = read_scalar(C->row_ptr + n, s);
+        C->nnz = nnz;
+        FNN_HIP(hipMemcpy(hc0, cnt, sizeof hc0, hipMemcpyDeviceToHost));
+        C->col = (int32_t *)out_alloc(sizeof(int32_t) * (size_t)std::max<int64_t>(nnz, 1));
+        C->dist = (float *)out_alloc(sizeof(float) * (size_t)std::max<int64_t>(nnz, 1));
+        tm.mark();  // 4
+
+        // ---- fill pass --------------------------------------------------
+        o.cursor = S.get<unsigned long long>(n);
+        FNN_LAUNCH(k_cursor_init, dim3(grid_for(n, 256)), dim3(256), 0, s,
+                   C->row_ptr, n, o.cursor);
+        o.col = C->col;
+        o.dist = C->dist;
+        o.nnz = (unsigned long long)nnz;
+        if (nnz > 0) {
+            if (use_gram)
+                edges_scatter(gedges, gedist, ngedges, o, s);
+            launch_tiles<M>(true, P, plain, nplain, T, E, fp64_dist, o, s);
+        }
+        FNN_LAUNCH(k_cursor_check_rows, dim3(grid_for(n, 256)), dim3(256), 0, s,
+                   C->row_ptr, n, o.cursor, (const int32_t *)nullptr, bad);
+        tm.mark();  // 5
+    } else {
+        // ---- learned schedule: one tile pass into predicted slots ----------
+        int32_t *cap = S.get<int32_t>(n);
+        const float slack = opt.slack_pct / 100.f;
+        FNN_LAUNCH(k_caps, dim3(grid_for(n, 256)), dim3(256), 0, s, Lm.pred, T->perm,
+                   n, slack, cap);
+        int64_t *sb = S.get<int64_t>(n + 1);
+        scan_i32_to_i64(cap, sb, n, S);
+        const int64_t nslot = read_scalar(sb + n, s);
+        int32_t *scol = S.get<int32_t>(std::max<int64_t>(nslot, 1));
+        float *sdist = S.get<float>(std::max<int64_t>(nslot, 1));
+        int32_t *ovf = S.get<int32_t>(n);
+        fill(ovf, 0, n, s);
+        o.cursor = S.get<unsigned long long>(n);
+        FNN_LAUNCH(k_cursor_init, dim3(grid_for(n, 256)), dim3(256), 0, s, sb, n,
+                   o.cursor);
+        o.col = scol;
+        o.dist = sdist;
+        o.nnz = (unsigned long long)nslot;
+        o.row_end = sb + 1;
+        o.ovf = ovf;
         launch_tiles<M>(true, P, plain, nplain, T, E, fp64_dist, o, s);
+        tm.mark();  // 3
+        // cursors advanced by every edge, written or not: exact degrees
+        o.deg = S.get<int32_t>(n);
+        FNN_LAUNCH(k_deg_from_cursor, dim3(grid_for(n, 256)), dim3(256), 0, s,
+                   o.cursor, sb, n, o.deg);
+        scan_i32_to_i64(o.deg, C->row_ptr, n, S);
+        nnz = read_scalar(C->row_ptr + n, s);
+        C->nnz = nnz;
+        FNN_HIP(hipMemcpy(hc0, cnt, sizeof hc0, hipMemcpyDeviceToHost));
+        C->col = (int32_t *)out_alloc(sizeof(int32_t) * (size_t)std::max<int64_t>(nnz, 1));
+        C->dist = (float *)out_alloc(sizeof(float) * (size_t)std::max<int64_t>(nnz, 1));
+        tm.mark();  // 4
+        int32_t *nov = S.get<int32_t>(1);
+        fill(nov, 0, 1, s);
+        FNN_LAUNCH(k_compact, dim3(grid_for(n, 4)), dim3(256), 0, s, sb, scol, sdist,
+                   ovf, C->row_ptr, n, C->col, C->dist, nov);
+        novf = read_scalar(nov, s);
+        if (novf > 0) {
+            // overflowed rows: re-run the tiles of the packs holding them,
+            // writing only those rows, straight into the CSR
+            int32_t *pflag = S.get<int32_t>(T->nq);
+            fill(pflag, 0, T->nq, s);
+            FNN_LAUNCH(k_mark_packs, dim3(grid_for(n, 256)), dim3(256), 0, s, ovf,
+                       T->perm, T->pack_of, n, pflag);
+            int2 *sub = S.get<int2>(nplain + 1);
+            unsigned long long *sc = S.get<unsigned long long>(1);
+            fill(sc, 0ull, 1, s);
+            FNN_LAUNCH(k_sublist, dim3(grid_for(nplain, 256)), dim3(256), 0, s,
+                       plain, nplain, pflag, sub, sc);
+            const long long nsub = (long long)read_scalar(sc, s);
+            TileOut o2 = o;
+            o2.cnt = cnt + 6;  // keep the pass counters of the main pass
+            o2.row_end = nullptr;
+            o2.ovf = nullptr;
+            o2.row_filter = ovf;
+            o2.col = C->col;
+            o2.dist = C->dist;
+            o2.nnz = (unsigned long long)nnz;
+            o2.cursor = S.get<unsigned long long>(n);
+            FNN_LAUNCH(k_cursor_init, dim3(grid_for(n, 256)), dim3(256), 0, s,
+                       C->row_ptr, n, o2.cursor);
+            launch_tiles<M>(true, P, sub, nsub, T, E, fp64_dist, o2, s);
+            FNN_LAUNCH(k_cursor_check_rows, dim3(grid_for(n, 256)), dim3(256), 0,
+                       s, C->row_ptr, n, o2.cursor, ovf, bad);
+        }
+        tm.mark();  // 5
     }
-    FNN_LAUNCH(k_cursor_check, dim3(cdiv(n, 256)), dim3(256), 0, s,
-                       C->row_ptr, n, o.cursor, bad);
-    tm.mark();  // 5
 
     // ---- per-row sort ---------------------------------------------------
     int32_t *mid = S.get<int32_t>(n), *lng = S.get<int32_t>(n);
@@ -910,29 +1186,50 @@ static void eps_graph_impl(const fnn_tree *T, double eps, const Options &opt,
     fill(cc, 0, 2, s);
     if (nnz > 0) {
         FNN_LAUNCH(k_sort_small, dim3(grid_for(n, 4)), dim3(256), 0, s,
-                           C->row_ptr, n, C->col, C->dist, mid, lng, cc);
+                   C->row_ptr, n, C->col, C->dist, mid, lng, cc);
         int32_t hcc[2];
         FNN_HIP(hipMemcpyAsync(hcc, cc, sizeof hcc, hipMemcpyDeviceToHost, s));
         FNN_HIP(hipStreamSynchronize(s));
         if (hcc[0] > 0)
             FNN_LAUNCH(k_sort_mid, dim3(grid_for(hcc[0], 1)), dim3(256), 0, s,
-                           C->row_ptr, mid, hcc[0], C->col, C->dist);
+                       C->row_ptr, mid, hcc[0], C->col, C->dist);
         if (hcc[1] > 0) {
             int64_t *p2 = S.get<int64_t>(hcc[1] + 1);
             int64_t *soff = S.get<int64_t>(hcc[1] + 2);
-            FNN_LAUNCH(k_long_sizes, dim3(cdiv(hcc[1], 256)), dim3(256), 0,
-                               s, C->row_ptr, lng, hcc[1], p2);
+            FNN_LAUNCH(k_long_sizes, dim3(grid_for(hcc[1], 256)), dim3(256), 0, s,
+                       C->row_ptr, lng, hcc[1], p2);
             scan_i64(p2, soff, hcc[1], S);
             const int64_t tot = read_scalar(soff + hcc[1], s);
             unsigned long long *scr = S.get<unsigned long long>(tot);
-            FNN_LAUNCH(k_sort_long, dim3(hcc[1]), dim3(256), 0, s,
-                               C->row_ptr, lng, soff, scr, C->col, C->dist);
+            FNN_LAUNCH(k_sort_long, dim3(hcc[1]), dim3(256), 0, s, C->row_ptr, lng,
+                       soff, scr, C->col, C->dist);
         }
     }
     tm.mark();  // 6
-    unsigned long long hc[2];
+
+    // ---- trace targets, prediction error ---------------------------------
+    if (opt.trace) {
+        int32_t *vis = S.get<int32_t>(T->npacks + 1);
+        fill(vis, 0, T->npacks + 1, s);
+        FNN_LAUNCH(k_visits, dim3(grid_for(ninter, 256)), dim3(256), 0, s, inter,
+                   ninter, (int)T->nnodes, vis);
+        Lm.targ = (float *)out_alloc(sizeof(float) * 2 * (size_t)n);
+        *trace_targ = Lm.targ;
+        FNN_LAUNCH(k_targets, dim3(grid_for(n, 256)), dim3(256), 0, s, vis,
+                   T->pack_of, T->perm, C->row_ptr, n, (int)T->nnodes, Lm.targ);
+    }
+    if (learned) {
+        double *acc = S.get<double>(3);
+        fill(acc, 0.0, 3, s);
+        FNN_LAUNCH(k_pred_err, dim3(grid_for(n, 256)), dim3(256), 0, s, Lm.pred,
+                   T->perm, C->row_ptr, n, acc);
+        double hacc[3];
+        FNN_HIP(hipMemcpyAsync(hacc, acc, sizeof hacc, hipMemcpyDeviceToHost, s));
+        FNN_HIP(hipStreamSynchronize(s));
+        st.pred_mae = hacc[0] / std::max(n, 1);
+        st.pred_sum_ratio = hacc[2] > 0 ? hacc[1] / hacc[2] : 0.0;
+    }
     int hbad = 0;
-    FNN_HIP(hipMemcpyAsync(hc, cnt, sizeof hc, hipMemcpyDeviceToHost, s));
     FNN_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s));
     FNN_HIP(hipStreamSynchronize(s));
     if (hbad)
@@ -952,6 +1249,7 @@ static void eps_graph_impl(const fnn_tree *T, double eps, const Options &opt,
         memcpy(&ef, &eb, 4);
         st.max_rel_err = ef;
     }
+    st.overflow_rows = novf;
     st.edges = nnz;
     st.traverse_ms = tm.ms(0, 1) + tm.ms(1, 2);
     st.count_ms = tm.ms(2, 3);
@@ -960,24 +1258,23 @@ static void eps_graph_impl(const fnn_tree *T, double eps, const Options &opt,
     st.sort_ms = tm.ms(5, 6);
     st.tile_ms = st.count_ms + st.fill_ms;
     st.total_ms = tm.ms(0, 6);
-    (void)opt;
 }
 
 void eps_graph(const fnn_tree *T, double eps, const Options &opt, fnn_csr *C,
-               fnn_stats &st, Scratch &S)
+               fnn_stats &st, Scratch &S, float **tf, float **tt)
 {
     switch (T->metric) {
     case M_L2:
-        eps_graph_impl<M_L2>(T, eps, opt, C, st, S);
+        eps_graph_impl<M_L2>(T, eps, opt, C, st, S, tf, tt);
         break;
     case M_ANG:
-        eps_graph_impl<M_ANG>(T, eps, opt, C, st, S);
+        eps_graph_impl<M_ANG>(T, eps, opt, C, st, S, tf, tt);
         break;
     case M_HAM:
-        eps_graph_impl<M_HAM>(T, eps, opt, C, st, S);
+        eps_graph_impl<M_HAM>(T, eps, opt, C, st, S, tf, tt);
         break;
     default:
-        eps_graph_impl<M_LEV>(T, eps, opt, C, st, S);
+        eps_graph_impl<M_LEV>(T, eps, opt, C, st, S, tf, tt);
         break;
     }
 }

@@ -23,6 +23,8 @@ struct Options {
     int sched = FNN_SCHED_TWO_PASS;
     int validate = 0;
     int kmax = 32;
+    int trace = 0;
+    int slack_pct = 30;
 };
 
 Options read_options(const fnn_options *o);
@@ -71,6 +73,12 @@ struct fnn_tree {
     int32_t *q_kbeg = nullptr;   // children list offsets (packs: count 0)
     int32_t *q_kcnt = nullptr;
     int32_t *q_kids = nullptr;
+
+    // auxiliary arrays of the learned schedule (built on first use)
+    int32_t *parent = nullptr;   // [nnodes], -1 at the root
+    int32_t *depth_v = nullptr;  // [nnodes]
+    int32_t *leaf_of = nullptr;  // [n] leaf block of each tree position
+    int32_t *pack_of = nullptr;  // [n] query-tree pack of each position
 
     int depth = 0;
     fnn_stats stats{};
