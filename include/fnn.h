@@ -125,12 +125,13 @@ typedef struct fnn_stats {
     int64_t edges;            /* nnz (ordered pairs)                          */
     int64_t overflow_rows;    /* learned schedule: rows re-done in two pass  */
     int64_t validate_mismatch;/* validate: filter false negatives (must be 0)*/
+    int64_t spilled;          /* learned: entries past their predicted slots */
     double max_rel_err;       /* validate: max |dist32 - dist64| / dist64    */
     double build_ms, traverse_ms, tile_ms, count_ms, scan_ms, fill_ms,
            sort_ms, total_ms;
     double pred_mae;          /* learned: mean |predicted - true| log1p(deg) */
     double pred_sum_ratio;    /* learned: sum predicted / sum true degrees    */
-    double reserved[6];
+    double reserved[5];
 } fnn_stats;
 
 /* Build the cover tree of n points (Algorithms 1-2).  points: device

@@ -54,7 +54,8 @@ class fnn_csr(ctypes.Structure):
 _STAT_I64 = ["n", "nodes", "leaf_blocks", "packs", "rounds", "netsel_passes",
              "build_dist_evals", "traverse_tests", "interactions",
              "tile_pairs", "filter_pairs", "filter_survivors",
-             "fp64_rechecks", "edges", "overflow_rows", "validate_mismatch"]
+             "fp64_rechecks", "edges", "overflow_rows", "validate_mismatch",
+             "spilled"]
 _STAT_F64 = ["max_rel_err", "build_ms", "traverse_ms", "tile_ms", "count_ms",
              "scan_ms", "fill_ms", "sort_ms", "total_ms", "pred_mae",
              "pred_sum_ratio"]
@@ -63,7 +64,7 @@ _STAT_F64 = ["max_rel_err", "build_ms", "traverse_ms", "tile_ms", "count_ms",
 class fnn_stats(ctypes.Structure):
     _fields_ = ([(k, ctypes.c_int64) for k in _STAT_I64] +
                 [(k, ctypes.c_double) for k in _STAT_F64] +
-                [("reserved", ctypes.c_double * 6)])
+                [("reserved", ctypes.c_double * 5)])
 
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)

@@ -24,6 +24,11 @@ struct TileOut {
     int32_t *ovf;
     // restricted fill: only rows with row_filter[r] != 0 are written
     const int32_t *row_filter;
+    // learned schedule: entries beyond a row's slots go to a spill list
+    int2 *spill;                  // (row, col) input ids
+    float *spill_dist;
+    unsigned long long *spill_cnt;
+    unsigned long long spill_cap;
 };
 
 struct GramArgs {

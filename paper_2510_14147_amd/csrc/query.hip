@@ -280,6 +280,53 @@ struct TileSmem<M_LEV> {
     int dummy;
 };
 
+// Destination of the c entries a tile adds to one row: slots [o, o+c) of
+// the CSR (or of the learned schedule's slot array, up to lim); with a spill
+// list, entries past lim go there.  Returns the spill base (or ~0 if none);
+// c is set to 0 when the row cannot take them (overflow flag / error).
+__device__ __forceinline__ unsigned long long place(const TileOut &out, int row,
+                                                    int &c,
+                                                    unsigned long long &o,
+                                                    unsigned long long &lim)
+{
+    o = atomicAdd(&out.cursor[row], (unsigned long long)c);
+    lim = out.row_end ? (unsigned long long)out.row_end[row] : out.nnz;
+    if (o + c <= lim)
+        return ~0ull;
+    if (out.row_end && out.spill) {
+        const unsigned long long first = o > lim ? o : lim;
+        const unsigned long long nsp = o + c - first;
+        const unsigned long long sp = atomicAdd(out.spill_cnt, nsp);
+        if (sp + nsp <= out.spill_cap)
+            return sp - (first - o);  // entry k >= lim lands at sp0 + k
+        out.ovf[row] = 1;
+        c = 0;
+        return ~0ull;
+    }
+    if (out.row_end)
+        out.ovf[row] = 1;
+    else
+        atomicOr(out.err, ERR_INDEX);
+    c = 0;
+    return ~0ull;
+}
+
+__device__ __forceinline__ void put(const TileOut &out, int row, int col,
+                                    float d, unsigned long long idx,
+                                    unsigned long long o, unsigned long long lim,
+                                    unsigned long long spb)
+{
+    // idx = o + k for the k-th entry of this placement
+    if (idx < lim) {
+        out.col[idx] = col;
+        out.dist[idx] = d;
+    } else {
+        const unsigned long long q = spb + (idx - o);
+        out.spill[q] = make_int2(row, col);
+        out.spill_dist[q] = d;
+    }
+}
+
 template <int M, bool FILL>
 __global__ void __launch_bounds__(TT)
 k_tile(Pts P, const int2 *__restrict__ inter, long long ninter,
@@ -462,24 +509,16 @@ k_tile(Pts P, const int2 *__restrict__ inter, long long ninter,
                     if constexpr (!FILL) {
                         atomicAdd(&out.deg[orow], c);
                     } else {
-                        unsigned long long o = atomicAdd(&out.cursor[orow],
-                                                         (unsigned long long)c);
-                        const unsigned long long lim =
-                            out.row_end ? (unsigned long long)out.row_end[orow] : out.nnz;
-                        if (o + c > lim) {
-                            if (out.row_end)
-                                out.ovf[orow] = 1;
-                            else
-                                atomicOr(out.err, ERR_INDEX);
-                            c = 0;
-                        }
+                        unsigned long long o, lim;
+                        const unsigned long long spb = place(out, orow, c, o, lim);
                         unsigned long long bb = c ? bits : 0ull;
+                        unsigned long long idx = o;
                         while (bb) {
                             const int j = __ffsll((long long)bb) - 1;
                             bb &= bb - 1;
-                            out.col[o] = perm[pb + j];
-                            out.dist[o] = dt[r * (TS + 1) + j];
-                            ++o;
+                            put(out, orow, perm[pb + j], dt[r * (TS + 1) + j], idx,
+                                o, lim, spb);
+                            ++idx;
                         }
                     }
                 }
@@ -496,23 +535,14 @@ k_tile(Pts P, const int2 *__restrict__ inter, long long ninter,
                         if constexpr (!FILL) {
                             atomicAdd(&out.deg[ocol], c);
                         } else {
-                            unsigned long long o = atomicAdd(&out.cursor[ocol],
-                                                             (unsigned long long)c);
-                            const unsigned long long lim =
-                                out.row_end ? (unsigned long long)out.row_end[ocol]
-                                            : out.nnz;
-                            if (o + c > lim) {
-                                if (out.row_end)
-                                    out.ovf[ocol] = 1;
-                                else
-                                    atomicOr(out.err, ERR_INDEX);
-                                c = 0;
-                            }
+                            unsigned long long o, lim;
+                            const unsigned long long spb = place(out, ocol, c, o, lim);
+                            unsigned long long idx = o;
                             for (int r = 0; c && r < ra; ++r)
                                 if ((mask[r] >> cc) & 1ull) {
-                                    out.col[o] = perm[pa + r];
-                                    out.dist[o] = dt[r * (TS + 1) + cc];
-                                    ++o;
+                                    put(out, ocol, perm[pa + r], dt[r * (TS + 1) + cc],
+                                        idx, o, lim, spb);
+                                    ++idx;
                                 }
                         }
                     }
@@ -730,7 +760,8 @@ __global__ void k_compact(const int64_t *__restrict__ sb, const int32_t *__restr
             cnt += lane == 0;
             continue;
         }
-        const int64_t b = row_ptr[r], len = row_ptr[r + 1] - b, s0 = sb[r];
+        const int64_t b = row_ptr[r], s0 = sb[r];
+        const int64_t len = min(row_ptr[r + 1] - b, sb[r + 1] - s0);
         for (int64_t i = lane; i < len; i += WAVE) {
             col[b + i] = scol[s0 + i];
             dist[b + i] = sdist[s0 + i];
@@ -738,6 +769,50 @@ __global__ void k_compact(const int64_t *__restrict__ sb, const int32_t *__restr
     }
     if (lane == 0 && cnt)
         atomicAdd(novf, cnt);
+}
+
+// Spilled entries go after the row's slot entries (cursor starts there).
+__global__ void k_spill_init(const int64_t *__restrict__ row_ptr,
+                             const int64_t *__restrict__ sb, int n,
+                             unsigned long long *__restrict__ cur)
+{
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n;
+         r += gridDim.x * blockDim.x) {
+        const int64_t len = row_ptr[r + 1] - row_ptr[r];
+        const int64_t cap = sb[r + 1] - sb[r];
+        cur[r] = (unsigned long long)(row_ptr[r] + (len < cap ? len : cap));
+    }
+}
+
+// A reservation that did not fit leaves its slots below the capacity
+// unwritten: the list is initialised with row -1 and such entries are
+// skipped.
+__global__ void k_spill_scatter(const int2 *__restrict__ sp, const float *__restrict__ sd,
+                                long long ns, int n, const int32_t *__restrict__ ovf,
+                                unsigned long long *__restrict__ cur,
+                                const int64_t *__restrict__ row_ptr,
+                                int32_t *__restrict__ col, float *__restrict__ dist,
+                                int *__restrict__ err)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < ns;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int2 e = sp[i];
+        if (e.x < 0)
+            continue;
+        if (e.x >= n) {
+            atomicOr(err, ERR_INDEX);
+            continue;
+        }
+        if (ovf[e.x])
+            continue;
+        const unsigned long long p = atomicAdd(&cur[e.x], 1ull);
+        if ((long long)p >= row_ptr[e.x + 1]) {
+            atomicOr(err, ERR_INDEX);
+            continue;
+        }
+        col[p] = e.y;
+        dist[p] = sd[i];
+    }
 }
 
 // Packs holding an overflowed row, then the block pairs touching them.
@@ -762,6 +837,13 @@ __global__ void k_sublist(const int2 *__restrict__ inter, long long ni,
         if (flag[e.x] || flag[e.y])
             out[atomicAdd(cnt, 1ull)] = e;
     }
+}
+
+__global__ void k_not(const int32_t *__restrict__ a, int n, int32_t *__restrict__ b)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += gridDim.x * blockDim.x)
+        b[i] = !a[i];
 }
 
 __global__ void k_cursor_check_rows(const int64_t *__restrict__ row_ptr, int n,
@@ -1131,6 +1213,13 @@ static void eps_graph_impl(const fnn_tree *Tc, double eps, const Options &opt,
         o.nnz = (unsigned long long)nslot;
         o.row_end = sb + 1;
         o.ovf = ovf;
+        const long long spcap = std::max<long long>(1ll << 16, nslot / 2);
+        o.spill = S.get<int2>(spcap);
+        fill(o.spill, make_int2(-1, -1), spcap, s);
+        o.spill_dist = S.get<float>(spcap);
+        o.spill_cnt = S.get<unsigned long long>(1);
+        fill(o.spill_cnt, 0ull, 1, s);
+        o.spill_cap = (unsigned long long)spcap;
         launch_tiles<M>(true, P, plain, nplain, T, E, fp64_dist, o, s);
         tm.mark();  // 3
         // cursors advanced by every edge, written or not: exact degrees
@@ -1149,6 +1238,23 @@ static void eps_graph_impl(const fnn_tree *Tc, double eps, const Options &opt,
         FNN_LAUNCH(k_compact, dim3(grid_for(n, 4)), dim3(256), 0, s, sb, scol, sdist,
                    ovf, C->row_ptr, n, C->col, C->dist, nov);
         novf = read_scalar(nov, s);
+        {
+            const long long nsp = std::min<long long>(
+                (long long)read_scalar(o.spill_cnt, s), spcap);
+            unsigned long long *cur3 = S.get<unsigned long long>(n);
+            FNN_LAUNCH(k_spill_init, dim3(grid_for(n, 256)), dim3(256), 0, s,
+                       C->row_ptr, sb, n, cur3);
+            if (nsp > 0)
+                FNN_LAUNCH(k_spill_scatter, dim3(grid_for(nsp, 256)), dim3(256), 0,
+                           s, o.spill, o.spill_dist, nsp, n, ovf, cur3, C->row_ptr,
+                           C->col, C->dist, bad);
+            // rows that were not re-done must now be complete
+            int32_t *keep = S.get<int32_t>(n);
+            FNN_LAUNCH(k_not, dim3(grid_for(n, 256)), dim3(256), 0, s, ovf, n, keep);
+            FNN_LAUNCH(k_cursor_check_rows, dim3(grid_for(n, 256)), dim3(256), 0,
+                       s, C->row_ptr, n, cur3, keep, bad);
+            st.spilled = nsp;
+        }
         if (novf > 0) {
             // overflowed rows: re-run the tiles of the packs holding them,
             // writing only those rows, straight into the CSR

@@ -63,4 +63,4 @@ def test_options_struct_matches_header():
     from paper_2510_14147_amd import fnn_options, fnn_stats, fnn_csr
     assert ctypes.sizeof(fnn_options) == 16 * 4
     assert ctypes.sizeof(fnn_csr) == 8 + 8 + 8 + 3 * 8
-    assert ctypes.sizeof(fnn_stats) == 16 * 8 + 9 * 8 + 8 * 8
+    assert ctypes.sizeof(fnn_stats) == 17 * 8 + 11 * 8 + 5 * 8

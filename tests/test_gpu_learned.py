@@ -122,7 +122,9 @@ def test_learned_schedule_same_graph(fnn, case, slack):
     st = g.stats
     assert st["pred_mae"] >= 0.0 and st["pred_sum_ratio"] > 0.0
     if slack == -90:
-        assert st["overflow_rows"] > 0
+        # rows outgrow their slots: entries spill, and rows whose spill does
+        # not fit are re-done by the restricted fill
+        assert st["spilled"] > 0 or st["overflow_rows"] > 0
 
 
 def test_learned_mfma_same_graph(fnn):
