@@ -152,6 +152,33 @@ int fnn_eps_graph(const fnn_tree *tree, double eps, fnn_csr **out);
 int fnn_eps_graph_ex(const fnn_tree *tree, double eps,
                      const fnn_options *opt, fnn_csr **out);
 
+/* ---- many independent clouds in one batch ---------------------------------
+ * The level-synchronous build (Algorithm 2 processes every hub of a level
+ * together) and the batched query (Algorithm 3 over query batches) extend to
+ * a forest: each cloud gets its own cover tree, and the hubs and vertex
+ * pairs of all clouds share every kernel launch.  This is also the shape of
+ * the per-cell trees of the landmark partitioning (Section IV-C).
+ *
+ * fnn_tree_build_batch: points holds the rows of all clouds back to back
+ * (device, layout per metric, one dim for all); cloud c is rows
+ * [offsets[c], offsets[c+1]).  offsets: host array of nclouds + 1 values,
+ * offsets[0] = 0, non-decreasing; empty clouds are allowed, but the total
+ * must be >= 1.  The handle works with every tree call; in fnn_tree_export
+ * of a batch of two or more non-empty clouds, vertex 0 is a virtual root
+ * (radius +inf) whose children are the cloud roots in cloud order.
+ *
+ * fnn_eps_graph_batch: eps is a host array of nclouds thresholds (entries of
+ * empty clouds are ignored).  The result is one symmetric CSR over all rows
+ * (global row indices): cloud c's rows hold exactly the eps[c]-graph of
+ * cloud c; no edge joins two clouds.  fnn_eps_graph on a batch tree applies
+ * one eps to every cloud. */
+int fnn_tree_build_batch(const void *points, const int64_t *offsets,
+                         int32_t nclouds, int32_t dim, fnn_metric metric,
+                         const fnn_options *opt, fnn_tree **out);
+int fnn_eps_graph_batch(const fnn_tree *tree, const double *eps,
+                        int32_t nclouds, const fnn_options *opt,
+                        fnn_csr **out);
+
 /* Release a fnn_tree* or fnn_csr* (NULL is ignored). */
 void fnn_free(void *handle);
 

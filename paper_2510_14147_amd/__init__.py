@@ -121,6 +121,12 @@ def lib():
                                        ctypes.POINTER(ctypes.POINTER(fnn_csr))]
         L.fnn_eps_graph.argtypes = [vp, ctypes.c_double,
                                     ctypes.POINTER(ctypes.POINTER(fnn_csr))]
+        L.fnn_tree_build_batch.argtypes = [vp, ctypes.POINTER(i64), i32, i32,
+                                           ctypes.c_int, ctypes.POINTER(fnn_options),
+                                           ctypes.POINTER(vp)]
+        L.fnn_eps_graph_batch.argtypes = [vp, ctypes.POINTER(ctypes.c_double), i32,
+                                          ctypes.POINTER(fnn_options),
+                                          ctypes.POINTER(ctypes.POINTER(fnn_csr))]
         L.fnn_free.argtypes = [vp]
         L.fnn_free.restype = None
         L.fnn_get_stats.argtypes = [vp, ctypes.POINTER(fnn_stats)]
@@ -261,6 +267,45 @@ def fnn_tree_build(points, metric: str = "l2", zeta=None, pack=None,
                                    dim, m, ctypes.byref(o), ctypes.byref(h)))
     tree = Tree(h, t.shape[0], dim, metric)
     return tree
+
+
+def fnn_tree_build_batch(points, offsets, metric: str = "l2", zeta=None,
+                         pack=None, kmax=None) -> Tree:
+    """One forest over many clouds: ``points`` holds the clouds' rows back to
+    back, cloud c = rows [offsets[c], offsets[c+1])."""
+    m = METRICS[metric]
+    t, dim = _as_device_points(points, metric)
+    off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+    if off.ndim != 1 or off.size < 2:
+        raise ValueError("offsets must hold nclouds + 1 values")
+    if int(off[-1]) != t.shape[0]:
+        raise ValueError("offsets[-1] must equal the number of rows")
+    _bind_stream()
+    h = ctypes.c_void_p()
+    o = _options(zeta=zeta, pack=pack, kmax=kmax)
+    _check(lib().fnn_tree_build_batch(
+        ctypes.c_void_p(t.data_ptr()),
+        off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), off.size - 1, dim, m,
+        ctypes.byref(o), ctypes.byref(h)))
+    tree = Tree(h, t.shape[0], dim, metric)
+    tree.nclouds = off.size - 1
+    return tree
+
+
+def fnn_eps_graph_batch(tree: Tree, eps, precision="fp32", sched="two_pass",
+                        validate=False, trace=False, slack_pct=None) -> Graph:
+    """Per-cloud thresholds ``eps[c]``; one block-diagonal CSR over all rows."""
+    if sched == "learned" and not _model_set and os.path.exists(COST_MODEL_PATH):
+        fnn_set_cost_model(load_cost_model())
+    e = np.ascontiguousarray(np.asarray(eps, dtype=np.float64).ravel())
+    _bind_stream()
+    out = ctypes.POINTER(fnn_csr)()
+    o = _options(precision=precision, sched=sched, validate=int(validate),
+                 trace=int(trace), slack_pct=slack_pct)
+    _check(lib().fnn_eps_graph_batch(
+        tree.handle, e.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), e.size,
+        ctypes.byref(o), ctypes.byref(out)))
+    return Graph(out)
 
 
 MLP_NPARAMS, MLP_NFEAT = 5378, 16

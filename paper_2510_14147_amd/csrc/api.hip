@@ -14,8 +14,8 @@ namespace fnn {
 extern thread_local hipStream_t g_stream;
 void set_alloc_hook(fnn_alloc_fn a, fnn_free_fn f, void *ctx);
 void build_tree(fnn_tree *T, const void *points, Scratch &S);
-void eps_graph(const fnn_tree *T, double eps, const Options &opt, fnn_csr *C,
-               fnn_stats &st, Scratch &S, float **tf, float **tt);
+void eps_graph(const fnn_tree *T, const double *eps, const Options &opt,
+               fnn_csr *C, fnn_stats &st, Scratch &S, float **tf, float **tt);
 
 // The installed cost model: one device copy per device.
 static std::mutex g_model_mu;
@@ -121,8 +121,9 @@ int fnn_set_allocator(fnn_alloc_fn alloc, fnn_free_fn free_, void *ctx)
     return FNN_OK;
 }
 
-int fnn_tree_build_ex(const void *points, int64_t n, int32_t dim,
-                      fnn_metric metric, const fnn_options *opt, fnn_tree **out)
+static int tree_build_any(const void *points, int64_t n, const int64_t *offsets,
+                          int32_t nclouds, int32_t dim, fnn_metric metric,
+                          const fnn_options *opt, fnn_tree **out)
 {
     if (!out)
         return set_err(FNN_EINVAL, "out is NULL");
@@ -145,6 +146,23 @@ int fnn_tree_build_ex(const void *points, int64_t n, int32_t dim,
         T->n = n;
         T->dim = dim;
         T->opt = o;
+        T->ncloud_in = nclouds;
+        if (offsets) {
+            // compact the non-empty clouds
+            for (int32_t c = 0; c < nclouds; ++c) {
+                if (offsets[c + 1] < offsets[c])
+                    fail(FNN_EINVAL, "offsets must be non-decreasing");
+                if (offsets[c + 1] > offsets[c]) {
+                    T->cloud_off_h.push_back(offsets[c]);
+                    T->cloud_src.push_back(c);
+                }
+            }
+            T->cloud_off_h.push_back(n);
+        } else {
+            T->cloud_off_h = {0, n};
+            T->cloud_src = {0};
+        }
+        T->ncloud = (int)T->cloud_src.size();
         switch (metric) {
         case FNN_L2:
         case FNN_ANGULAR:
@@ -181,14 +199,36 @@ int fnn_tree_build_ex(const void *points, int64_t n, int32_t dim,
     }
 }
 
+int fnn_tree_build_ex(const void *points, int64_t n, int32_t dim,
+                      fnn_metric metric, const fnn_options *opt, fnn_tree **out)
+{
+    return tree_build_any(points, n, nullptr, 1, dim, metric, opt, out);
+}
+
+int fnn_tree_build_batch(const void *points, const int64_t *offsets,
+                         int32_t nclouds, int32_t dim, fnn_metric metric,
+                         const fnn_options *opt, fnn_tree **out)
+{
+    if (out)
+        *out = nullptr;
+    if (!offsets)
+        return set_err(FNN_EINVAL, "offsets is NULL");
+    if (nclouds < 1)
+        return set_err(FNN_EINVAL, "nclouds must be >= 1");
+    if (offsets[0] != 0)
+        return set_err(FNN_EINVAL, "offsets[0] must be 0");
+    return tree_build_any(points, offsets[nclouds], offsets, nclouds, dim, metric,
+                          opt, out);
+}
+
 int fnn_tree_build(const void *points, int64_t n, int32_t dim,
                    fnn_metric metric, fnn_tree **out)
 {
     return fnn_tree_build_ex(points, n, dim, metric, nullptr, out);
 }
 
-int fnn_eps_graph_ex(const fnn_tree *tree, double eps, const fnn_options *opt,
-                     fnn_csr **out)
+static int eps_graph_any(const fnn_tree *tree, const double *eps, int32_t neps,
+                         bool per_cloud, const fnn_options *opt, fnn_csr **out)
 {
     if (!out)
         return set_err(FNN_EINVAL, "out is NULL");
@@ -197,8 +237,19 @@ int fnn_eps_graph_ex(const fnn_tree *tree, double eps, const fnn_options *opt,
     try {
         if (!tree || tree->kind != KIND_TREE)
             fail(FNN_EINVAL, "not a tree handle");
-        if (!(eps > 0.0) || !isfinite(eps))
-            fail(FNN_EINVAL, "eps must be finite and > 0");
+        if (!eps)
+            fail(FNN_EINVAL, "eps is NULL");
+        if (per_cloud && neps != tree->ncloud_in)
+            fail(FNN_EINVAL, "nclouds (%d) differs from the tree's (%d)", (int)neps,
+                 (int)tree->ncloud_in);
+        // thresholds of the non-empty clouds, in the tree's compact order
+        std::vector<double> ev(tree->ncloud);
+        for (int c = 0; c < tree->ncloud; ++c) {
+            const double e = per_cloud ? eps[tree->cloud_src[c]] : eps[0];
+            if (!(e > 0.0) || !isfinite(e))
+                fail(FNN_EINVAL, "eps must be finite and > 0");
+            ev[c] = e;
+        }
         Options o = read_options(opt);
         B = new CsrBox();
         memset(&B->pub, 0, sizeof B->pub);
@@ -207,7 +258,7 @@ int fnn_eps_graph_ex(const fnn_tree *tree, double eps, const fnn_options *opt,
         B->pub.kind = KIND_CSR;
         {
             Scratch S(current_stream());
-            eps_graph(tree, eps, o, &B->pub, B->stats, S, &B->trace_feat,
+            eps_graph(tree, ev.data(), o, &B->pub, B->stats, S, &B->trace_feat,
                       &B->trace_targ);
         }
         *out = &B->pub;
@@ -216,6 +267,10 @@ int fnn_eps_graph_ex(const fnn_tree *tree, double eps, const fnn_options *opt,
         if (B)
             free_box(B);
         return set_err(e.code, e.msg);
+    } catch (const std::bad_alloc &) {
+        if (B)
+            free_box(B);
+        return set_err(FNN_ENOMEM, "host allocation failed");
     } catch (...) {
         if (B)
             free_box(B);
@@ -223,9 +278,21 @@ int fnn_eps_graph_ex(const fnn_tree *tree, double eps, const fnn_options *opt,
     }
 }
 
+int fnn_eps_graph_ex(const fnn_tree *tree, double eps, const fnn_options *opt,
+                     fnn_csr **out)
+{
+    return eps_graph_any(tree, &eps, 1, false, opt, out);
+}
+
 int fnn_eps_graph(const fnn_tree *tree, double eps, fnn_csr **out)
 {
     return fnn_eps_graph_ex(tree, eps, nullptr, out);
+}
+
+int fnn_eps_graph_batch(const fnn_tree *tree, const double *eps, int32_t nclouds,
+                        const fnn_options *opt, fnn_csr **out)
+{
+    return eps_graph_any(tree, eps, nclouds, true, opt, out);
 }
 
 void fnn_free(void *handle)

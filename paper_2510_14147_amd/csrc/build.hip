@@ -206,6 +206,51 @@ __global__ void k_root_keys(Pts P, int32_t *__restrict__ perm,
         atomicMax(kmax, __float_as_uint(k));
 }
 
+// Forest of independent clouds: cloud id of every position, and each point's
+// key to the first point of its cloud (that cloud's root centre).
+__global__ void k_cloud_ids(const int32_t *__restrict__ off, int C,
+                            int32_t *__restrict__ pcl)
+{
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wpb = blockDim.x / WAVE;
+    for (int c = blockIdx.x * wpb + threadIdx.x / WAVE; c < C;
+         c += gridDim.x * wpb)
+        for (int p = off[c] + lane; p < off[c + 1]; p += WAVE)
+            pcl[p] = c;
+}
+
+template <int M>
+__global__ void k_forest_keys(Pts P, const int32_t *__restrict__ off,
+                              const int32_t *__restrict__ pcl,
+                              int32_t *__restrict__ perm, float *__restrict__ D,
+                              unsigned *__restrict__ kmax)
+{
+    const int lane = threadIdx.x & (WAVE - 1);
+    const long long lim = ((long long)P.n + WAVE - 1) / WAVE * WAVE;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < lim;
+         i += (long long)gridDim.x * blockDim.x) {
+        const bool ok = i < P.n;
+        int c = -1;
+        float k = 0.f;
+        if (ok) {
+            c = pcl[i];
+            perm[i] = (int32_t)i;
+            k = key32<M>(P, (int)i, off[c]);
+            D[i] = k;
+        }
+        // one atomic per wave when the wave lies inside one cloud
+        const int c0 = __shfl(c, 0, WAVE);
+        const bool same = __ballot(ok && c != c0) == 0ull;
+        if (same) {
+            const float m = wave_max(k);
+            if (lane == 0 && c0 >= 0)
+                atomicMax(&kmax[c0], __float_as_uint(m));
+        } else if (ok) {
+            atomicMax(&kmax[c], __float_as_uint(k));
+        }
+    }
+}
+
 // -------------------------------------------------------------- chunks ---
 
 struct Hubs {
@@ -611,6 +656,33 @@ __global__ void k_next_hubs(int C, int node_base,
     cent[nd.pb[v]] = nd.center[v];
 }
 
+// Forest: cloud roots are the children 1..C of the virtual vertex 0, each
+// centred on the first point of its cloud at its own top level (the smallest
+// l with 2^l >= its radius).
+__global__ void k_forest_roots(int C, const int32_t *__restrict__ off,
+                               const unsigned *__restrict__ kmax, int metric,
+                               int dp, int zeta, NodeArrays nd,
+                               int32_t *__restrict__ hubflag)
+{
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < C;
+         c += gridDim.x * blockDim.x) {
+        const int v = 1 + c;
+        const int pb = off[c], pe = off[c + 1];
+        const float km = __uint_as_float(kmax[c]);
+        const float r = radius_from_key(metric, dp, km);
+        const int l = r > 0.f ? level_of(r) : 0;
+        nd.center[v] = pb;
+        nd.radius[v] = r;
+        nd.level[v] = l;
+        nd.pb[v] = pb;
+        nd.pe[v] = pe;
+        nd.cbeg[v] = 0;
+        nd.ccnt[v] = 0;
+        hubflag[c] = (pe - pb > zeta && km > 0.f) ? 1 : 0;
+        atomicMax(&nd.level[0], l + 1);
+    }
+}
+
 // ------------------------------------------------------------ finalize ---
 
 __global__ void k_inverse(const int32_t *__restrict__ perm, int n,
@@ -650,13 +722,17 @@ __global__ void k_gather_rows(const T *__restrict__ in, const int32_t *__restric
 __global__ void k_qt_count(int nn, const int32_t *__restrict__ ccnt,
                            const int32_t *__restrict__ cbeg,
                            const int32_t *__restrict__ pb,
-                           const int32_t *__restrict__ pe, int P,
+                           const int32_t *__restrict__ pe, int P, int solo,
                            int32_t *__restrict__ npk, int32_t *__restrict__ nqk)
 {
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= nn)
         return;
     const int cc = ccnt[v];
+    // leaf children of the forest's virtual root (one per cloud) never share
+    // a pack: packs stay inside one cloud
+    if (v == solo)
+        P = 0;
     int packs = 0, kids = 0, run = -1;
     for (int a = 0; a < cc; ++a) {
         const int u = cbeg[v] + a;
@@ -683,7 +759,7 @@ __global__ void k_qt_fill(int nn, const int32_t *__restrict__ ccnt,
                           const int32_t *__restrict__ pb,
                           const int32_t *__restrict__ pe,
                           const int32_t *__restrict__ cpos,
-                          const float *__restrict__ radius, int P,
+                          const float *__restrict__ radius, int P, int solo,
                           const int32_t *__restrict__ pkoff,
                           const int32_t *__restrict__ kidoff,
                           int32_t *__restrict__ q_cpos, float *__restrict__ q_rad,
@@ -706,6 +782,8 @@ __global__ void k_qt_fill(int nn, const int32_t *__restrict__ ccnt,
     q_kcnt[v] = kidoff[v + 1] - kidoff[v];
     if (cc == 0)
         return;
+    if (v == solo)
+        P = 0;
     int pk = nn + pkoff[v] - 1;  // id of the current pack
     int kd = kidoff[v];
     int run = -1;
@@ -837,7 +915,7 @@ static void build_impl(fnn_tree *T, const void *points, Scratch &S)
                            st));
 
     // ---- node arrays (at most 2n - 1 vertices) ------------------------------
-    const size_t cap = 2 * (size_t)n + 1;
+    const size_t cap = 2 * (size_t)n + 2 + (size_t)T->ncloud;
     NodeArrays nd;
     nd.center = S.get<int32_t>(cap);
     nd.level = S.get<int32_t>(cap);
@@ -886,21 +964,63 @@ static void build_impl(fnn_tree *T, const void *points, Scratch &S)
     int32_t *choff = S.get<int32_t>(hub_cap + 2), *itemoff = S.get<int32_t>(hub_cap + 2);
     int32_t *child_base = S.get<int32_t>(hub_cap + 2);
 
-    // ---- root: D[p] = d(p, p_0) (Algorithm 1's pre-initialised D) ---------
-    unsigned *rk = S.get<unsigned>(1);
-    fill(rk, 0u, 1, st);
-    FNN_LAUNCH((k_root_keys<M>), dim3(cdiv(n, 256)), dim3(256), 0, st,
-                       P, perm, D, rk);
-    const unsigned r0bits = read_scalar(rk, st);
-    float r0key;
-    memcpy(&r0key, &r0bits, sizeof r0key);
-    const float r0 = radius_from_key(M, T->dp, r0key);
-    const int l0 = r0 > 0.f ? level_of(r0) : 0;
+    int H = 0;
+    int64_t node_count = 1;
     // host staging values stay alive until the synchronisation below
-    int32_t h0[7] = {0, l0, 0, 0, 0, n, 0};
-    int32_t one[10] = {0, 0, n, l0, 1, 1, 1, 0, 0, 0};
     int32_t zero = 0;
-    {
+    const int NCL = T->ncloud;
+    std::vector<int32_t> offh;
+    int32_t v0[5] = {0, 1, NCL, 0, n};
+    const float inf = INFINITY;
+    int32_t h0[7] = {0, 0, 0, 0, 0, n, 0};
+    int32_t one[10] = {0, 0, n, 0, 1, 1, 1, 0, 0, 0};
+    float r0 = 0.f;
+    if (NCL > 1) {
+        // ---- forest: one root per cloud, all clouds share every launch ---
+        offh.resize(NCL + 1);
+        for (int c = 0; c <= NCL; ++c)
+            offh[c] = (int32_t)T->cloud_off_h[c];
+        int32_t *off = S.get<int32_t>(NCL + 1);
+        FNN_HIP(hipMemcpyAsync(off, offh.data(), sizeof(int32_t) * (NCL + 1),
+                               hipMemcpyHostToDevice, st));
+        T->pcl = (int32_t *)T->own(sizeof(int32_t) * n);
+        FNN_LAUNCH(k_cloud_ids, dim3(grid_for(NCL, 4)), dim3(256), 0, st, off,
+                   NCL, T->pcl);
+        unsigned *ck = S.get<unsigned>(NCL);
+        fill(ck, 0u, NCL, st);
+        FNN_LAUNCH((k_forest_keys<M>), dim3(grid_for(n, 256)), dim3(256), 0, st,
+                   P, off, T->pcl, perm, D, ck);
+        fill(nd.level, INT_MIN, 1, st);
+        int32_t *cflag = S.get<int32_t>(NCL + 1), *cscan = S.get<int32_t>(NCL + 2);
+        FNN_LAUNCH(k_forest_roots, dim3(grid_for(NCL, 256)), dim3(256), 0, st,
+                   NCL, off, ck, M, T->dp, T->opt.zeta, nd, cflag);
+        // vertex 0: the virtual root (never part of a query pair)
+        FNN_HIP(hipMemcpyAsync(nd.center, &v0[0], 4, hipMemcpyHostToDevice, st));
+        FNN_HIP(hipMemcpyAsync(nd.cbeg, &v0[1], 4, hipMemcpyHostToDevice, st));
+        FNN_HIP(hipMemcpyAsync(nd.ccnt, &v0[2], 4, hipMemcpyHostToDevice, st));
+        FNN_HIP(hipMemcpyAsync(nd.pb, &v0[3], 4, hipMemcpyHostToDevice, st));
+        FNN_HIP(hipMemcpyAsync(nd.pe, &v0[4], 4, hipMemcpyHostToDevice, st));
+        FNN_HIP(hipMemcpyAsync(nd.radius, &inf, 4, hipMemcpyHostToDevice, st));
+        scan_i32(cflag, cscan, NCL, S);
+        H = read_scalar(cscan + NCL, st);
+        if (H > hub_cap)
+            fail(FNN_EINTERNAL, "hub capacity exceeded");
+        FNN_LAUNCH(k_next_hubs, dim3(cdiv(NCL, 256)), dim3(256), 0, st, NCL, 1,
+                   cflag, cscan, nd, hubs, cent);
+        node_count = 1 + NCL;
+    } else {
+        // ---- root: D[p] = d(p, p_0) (Algorithm 1's pre-initialised D) -----
+        unsigned *rk = S.get<unsigned>(1);
+        fill(rk, 0u, 1, st);
+        FNN_LAUNCH((k_root_keys<M>), dim3(cdiv(n, 256)), dim3(256), 0, st,
+                           P, perm, D, rk);
+        const unsigned r0bits = read_scalar(rk, st);
+        float r0key;
+        memcpy(&r0key, &r0bits, sizeof r0key);
+        r0 = radius_from_key(M, T->dp, r0key);
+        const int l0 = r0 > 0.f ? level_of(r0) : 0;
+        h0[1] = l0;
+        one[3] = l0;
         // root vertex: centre 0, all points
         FNN_HIP(hipMemcpyAsync(nd.center, &h0[0], 4, hipMemcpyHostToDevice, st));
         FNN_HIP(hipMemcpyAsync(nd.level, &h0[1], 4, hipMemcpyHostToDevice, st));
@@ -909,16 +1029,14 @@ static void build_impl(fnn_tree *T, const void *points, Scratch &S)
         FNN_HIP(hipMemcpyAsync(nd.pb, &h0[4], 4, hipMemcpyHostToDevice, st));
         FNN_HIP(hipMemcpyAsync(nd.pe, &h0[5], 4, hipMemcpyHostToDevice, st));
         FNN_HIP(hipMemcpyAsync(nd.radius, &r0, 4, hipMemcpyHostToDevice, st));
-    }
-    int H = 0;
-    int64_t node_count = 1;
-    if (n > T->opt.zeta && r0key > 0.f) {
-        int32_t *dst[10] = {hubs.node, hubs.b, hubs.e, hubs.lvl, hubs.m,
-                            hubs.ma, hubs.act, hubs.cb, hubs.ce, hubs.kof};
-        for (int i = 0; i < 10; ++i)
-            FNN_HIP(hipMemcpyAsync(dst[i], &one[i], 4, hipMemcpyHostToDevice, st));
-        FNN_HIP(hipMemcpyAsync(cent, &zero, 4, hipMemcpyHostToDevice, st));
-        H = 1;
+        if (n > T->opt.zeta && r0key > 0.f) {
+            int32_t *dst[10] = {hubs.node, hubs.b, hubs.e, hubs.lvl, hubs.m,
+                                hubs.ma, hubs.act, hubs.cb, hubs.ce, hubs.kof};
+            for (int i = 0; i < 10; ++i)
+                FNN_HIP(hipMemcpyAsync(dst[i], &one[i], 4, hipMemcpyHostToDevice, st));
+            FNN_HIP(hipMemcpyAsync(cent, &zero, 4, hipMemcpyHostToDevice, st));
+            H = 1;
+        }
     }
     FNN_HIP(hipStreamSynchronize(st));
 
@@ -1050,10 +1168,11 @@ static void build_impl(fnn_tree *T, const void *points, Scratch &S)
 
     // ---- query tree with packs ------------------------------------------
     const int PK = T->opt.pack;
+    const int solo = NCL > 1 ? 0 : -1;
     int32_t *npk = S.get<int32_t>(nn + 1), *nqk = S.get<int32_t>(nn + 1);
     int32_t *pkoff = S.get<int32_t>(nn + 2), *kidoff = S.get<int32_t>(nn + 2);
     FNN_LAUNCH(k_qt_count, dim3(cdiv(nn, 256)), dim3(256), 0, st, nn,
-                       nd.ccnt, nd.cbeg, nd.pb, nd.pe, PK, npk, nqk);
+                       nd.ccnt, nd.cbeg, nd.pb, nd.pe, PK, solo, npk, nqk);
     scan_i32(npk, pkoff, nn, S);
     scan_i32(nqk, kidoff, nn, S);
     int32_t tots[2];
@@ -1076,7 +1195,7 @@ static void build_impl(fnn_tree *T, const void *points, Scratch &S)
     T->q_kids = (int32_t *)T->own(sizeof(int32_t) * (nkids + 1));
     FNN_LAUNCH(k_qt_fill, dim3(cdiv(nn, 256)), dim3(256), 0, st, nn,
                        nd.ccnt, nd.cbeg, nd.pb, nd.pe, T->center_pos, nd.radius, PK,
-                       pkoff, kidoff, T->q_center_pos, T->q_radius, T->q_pt_begin,
+                       solo, pkoff, kidoff, T->q_center_pos, T->q_radius, T->q_pt_begin,
                        T->q_pt_end, T->q_kbeg, T->q_kcnt, T->q_kids);
     int32_t vals[5] = {0, n, 0, 0, 0};
     if (root_leaf) {

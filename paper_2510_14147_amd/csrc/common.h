@@ -54,6 +54,14 @@ struct LevelTab {
     Thr t[NLEV];
 };
 
+// Per-cloud query thresholds (a batch of independent clouds, each with its
+// own eps): the exact comparison, the pruning eps as a distance, the MFMA
+// filter's eps^2 in key space and the eps the cost-model features divide by.
+struct CloudThr {
+    Thr E;
+    float peps, e2f, feps, pad_;
+};
+
 // ---------------------------------------------------------------------------
 // FP32 keys.  L2: squared distance (direct differences, fused multiply-add).
 // Angular: squared chord between unit vectors, 2 - 2 cos(theta).  Hamming,

@@ -38,6 +38,10 @@ struct GramArgs {
     float e2f;            // eps^2 in key space, slightly enlarged
     float gscale;         // 1 / scale^2 (FP8 global scale)
     Thr E;
+    // batch of clouds: per-cloud thresholds by the cloud of a tree position
+    // (null for a single cloud: e2f and E above apply)
+    const CloudThr *ct;
+    const int32_t *pcl;
     int fp64_dist, validate;
     const int32_t *lg, *lb, *ubeg;  // work lists: group, B pack, unit starts
     const int32_t *q_pb, *q_pe, *perm;
@@ -55,6 +59,10 @@ void survivors_launch(int metric, const Pts &P, const GramArgs &G,
                       hipStream_t s);
 void edges_scatter(const int2 *edges, const float *edist, long long ne,
                    const TileOut &o, hipStream_t s);
+
+// eps^2 in the filter's key space, slightly enlarged so that the FP32
+// evaluation of the filter test itself cannot flip a true edge.
+float gram_eps2(int metric, double eps, const Thr &E);
 
 void gram_prepare(const fnn_tree *T, int prec, double eps, const Thr &E,
                   const int2 *inter, long long ninter, Scratch &S, GramArgs &G,

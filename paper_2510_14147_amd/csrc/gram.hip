@@ -265,9 +265,13 @@ k_gram(Pts P, GramArgs G, TileOut out)
                 }
             }
         }
-        // row terms of the filter: ax = (hx - eps2') / 2
+        // row terms of the filter: ax = (hx - eps2') / 2, with this pack's
+        // cloud threshold in a batch of clouds (packs of one group may come
+        // from different clouds; pairs across clouds are skipped below)
+        const int ca = (G.pcl && has_a) ? G.pcl[pa] : -1;
+        const float e2 = ca >= 0 ? G.ct[ca].e2f : G.e2f;
         for (int r = lane; r < GP; r += WAVE)
-            axS[w * GP + r] = (r < na) ? 0.5f * (G.hx[pa + r] - G.e2f) : FLT_MAX;
+            axS[w * GP + r] = (r < na) ? 0.5f * (G.hx[pa + r] - e2) : FLT_MAX;
 
         // B tiles are software-pipelined: the rows of entry e+1 are loaded
         // into registers while entry e is on the matrix cores.
@@ -310,6 +314,8 @@ k_gram(Pts P, GramArgs G, TileOut out)
                 load_b(e + 1);
             if (!has_a || b < a)
                 continue;                      // pair handled elsewhere
+            if (ca >= 0 && G.pcl[pb] != ca)
+                continue;                      // different clouds never connect
             const bool self = (b == a);
 #pragma unroll
             for (int cb = 0; cb < 2; ++cb) {
@@ -442,19 +448,20 @@ k_survive(Pts P, GramArgs G, long long ns, int2 *__restrict__ edges,
             const int pi = e.x, pj = e.y & 0x7FFFFFFF;
             const bool passed = (e.y >> 31) & 1;
             npass += passed;
+            const Thr E = G.pcl ? G.ct[G.pcl[pi]].E : G.E;
             const float k = key32<M>(P, pi, pj);
-            if (k < G.E.lo) {
+            if (k < E.lo) {
                 edge = true;
-            } else if (k > G.E.hi) {
+            } else if (k > E.hi) {
                 edge = false;
             } else {
                 ++nrc;
                 if constexpr (M == M_L2)
                     edge = l2_sq64(P.x + (size_t)pi * P.dp, P.x + (size_t)pj * P.dp,
-                                   P.dim) <= G.E.p64;
+                                   P.dim) <= E.p64;
                 else
                     edge = ang_within64(P.x + (size_t)pi * P.dp,
-                                        P.x + (size_t)pj * P.dp, P.dim, G.E.p64);
+                                        P.x + (size_t)pj * P.dp, P.dim, E.p64);
             }
             if (edge) {
                 if (!passed)
@@ -607,6 +614,13 @@ void gram_launch(int metric, int prec, bool fill_pass, const Pts &P,
 
 // ------------------------------------------------------------- host side --
 
+float gram_eps2(int metric, double eps, const Thr &E)
+{
+    const double u32 = 1.0 / 16777216.0;
+    const double T2 = metric == M_L2 ? eps * eps : 2.0 - 2.0 * E.p64;
+    return (float)(T2 * (1.0 + 64.0 * u32) + 1e-30);
+}
+
 // Quantised copy + per-point terms, and the MFMA work lists, for one query.
 void gram_prepare(const fnn_tree *T, int prec, double eps, const Thr &E,
                   const int2 *inter, long long ninter, Scratch &S, GramArgs &G,
@@ -661,10 +675,7 @@ void gram_prepare(const fnn_tree *T, int prec, double eps, const Thr &E,
         FNN_LAUNCH((k_quant<FNN_PREC_FP8>), dim3(grid_for(n, 4)), dim3(256), 0,
                    s, X, n, dp, kq, sums, 1.0f / n, scale, (float)(1.0 - c1), qbuf,
                    hxbuf);
-    // the filter compares against eps^2 in key space, slightly enlarged so
-    // the FP32 evaluation of the test itself cannot flip a true edge
-    const double T2 = T->metric == M_L2 ? eps * eps : 2.0 - 2.0 * E.p64;
-    G.e2f = (float)(T2 * (1.0 + 64.0 * u32) + 1e-30);
+    G.e2f = gram_eps2(T->metric, eps, E);
     G.E = E;
 
     // ---- lists: canonical pairs, routed, unique per (group, B) ----------

@@ -14,11 +14,15 @@ struct FeatArgs {
         *ccnt, *q_cpos, *q_pb, *q_pe;
     const float *radius, *q_rad;
     float eps;
+    // batch of clouds: per-cloud eps (CloudThr::feps) and the cloud of each
+    // position, whose root is vertex 1 + cloud; null for a single cloud
+    const CloudThr *ct;
+    const int32_t *pcl;
 };
 
 void tree_aux(fnn_tree *T, Scratch &S);
-void compute_features(const fnn_tree *T, const Pts &P, float eps, float *feat,
-                      hipStream_t s);
+void compute_features(const fnn_tree *T, const Pts &P, float eps,
+                      const CloudThr *ct, float *feat, hipStream_t s);
 void mlp_forward(const float *theta, const float *X, long long n, float *Y,
                  hipStream_t s);
 double mlp_loss_grad(const float *theta, const float *X, const float *T,

@@ -85,7 +85,9 @@ __global__ void k_features(Pts P, FeatArgs A, float *__restrict__ feat)
         float f[MLP_F];
         const int pk = A.pack_of[p];
         const int v0 = A.leaf_of[p];
-        const float eps = A.eps;
+        const int cl = A.pcl ? A.pcl[p] : -1;
+        const float eps = cl >= 0 ? A.ct[cl].feps : A.eps;
+        const int root = cl >= 0 ? 1 + cl : 0;
         const float tiny = 1.0f / 1048576.0f;
         f[0] = log2f(1.f + (float)(A.q_pe[pk] - A.q_pb[pk])) / 6.f;
         f[1] = (float)A.depth[v0] / 8.f;
@@ -100,7 +102,7 @@ __global__ void k_features(Pts P, FeatArgs A, float *__restrict__ feat)
             const float d = key_to_dist<M>(key32<M>(P, p, A.center_pos[v]));
             f[7 + k] = fminf(d / (r + 1e-30f), 2.f);
         }
-        f[12] = log2f(eps / (A.radius[0] + 1e-30f) + tiny);
+        f[12] = log2f(eps / (A.radius[root] + 1e-30f) + tiny);
         int u = v0;
         while (A.radius[u] < eps && A.parent[u] >= 0)
             u = A.parent[u];
@@ -373,6 +375,8 @@ void tree_aux(fnn_tree *T, Scratch &S)
     T->pack_of = (int32_t *)T->own(sizeof(int32_t) * n);
     FNN_LAUNCH(k_parent, dim3(grid_for(nn, 256)), dim3(256), 0, s, T->child_begin,
                T->child_count, nn, T->parent);
+    if (T->ncloud > 1)  // cloud roots are roots: the virtual vertex 0 is no parent
+        fill(T->parent + 1, -1, T->ncloud, s);
     FNN_LAUNCH(k_depth, dim3(grid_for(nn, 256)), dim3(256), 0, s, T->parent, nn,
                T->depth_v);
     FNN_LAUNCH(k_owner, dim3(grid_for(nn, 4)), dim3(256), 0, s, T->pt_begin,
@@ -382,8 +386,8 @@ void tree_aux(fnn_tree *T, Scratch &S)
                (int)T->npacks, 0, T->pack_of);
 }
 
-void compute_features(const fnn_tree *T, const Pts &P, float eps, float *feat,
-                      hipStream_t s)
+void compute_features(const fnn_tree *T, const Pts &P, float eps,
+                      const CloudThr *ct, float *feat, hipStream_t s)
 {
     FeatArgs A;
     A.pack_of = T->pack_of;
@@ -400,6 +404,8 @@ void compute_features(const fnn_tree *T, const Pts &P, float eps, float *feat,
     A.q_pb = T->q_pt_begin;
     A.q_pe = T->q_pt_end;
     A.eps = eps;
+    A.ct = ct;
+    A.pcl = ct ? T->pcl : nullptr;
     const dim3 g(grid_for(T->n, 256));
     switch (T->metric) {
     case M_L2:

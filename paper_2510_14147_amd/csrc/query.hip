@@ -47,6 +47,10 @@ struct Prune {
     float rel;   // relative slack on r_A + r_B + eps
     float abs_;  // absolute slack
     float eps;   // eps as a distance (floor(eps) for integer metrics)
+    // batch of clouds: per-cloud eps (CloudThr::peps) by the cloud of the
+    // vertex's first position; null for a single cloud
+    const CloudThr *ct;
+    const int32_t *pcl;
 };
 
 template <int M>
@@ -55,7 +59,8 @@ __device__ __forceinline__ bool may_touch(const Pts &P, const QView &Q,
 {
     const float k = key32<M>(P, Q.cpos[a], Q.cpos[b]);
     const float d = key_to_dist<M>(k);
-    const float lim = Q.rad[a] + Q.rad[b] + pr.eps;
+    const float e = pr.pcl ? pr.ct[pr.pcl[Q.pb[a]]].peps : pr.eps;
+    const float lim = Q.rad[a] + Q.rad[b] + e;
     if constexpr (M == M_HAM || M == M_LEV)
         return d <= lim;
     else
@@ -331,7 +336,8 @@ template <int M, bool FILL>
 __global__ void __launch_bounds__(TT)
 k_tile(Pts P, const int2 *__restrict__ inter, long long ninter,
        const int32_t *__restrict__ q_pb, const int32_t *__restrict__ q_pe,
-       const int32_t *__restrict__ perm, Thr E, int fp64_dist, TileOut out)
+       const int32_t *__restrict__ perm, Thr E0, const CloudThr *__restrict__ ct,
+       const int32_t *__restrict__ pcl, int fp64_dist, TileOut out)
 {
     __shared__ TileSmem<M> sm;
     __shared__ unsigned long long mask[TS];
@@ -343,6 +349,7 @@ k_tile(Pts P, const int2 *__restrict__ inter, long long ninter,
     const int A = pr.x, B = pr.y;
     const bool diag = A == B;
     const int a0 = q_pb[A], na = q_pe[A] - a0;
+    const Thr E = pcl ? ct[pcl[a0]].E : E0;  // both packs lie in one cloud
     const int b0 = q_pb[B], nb = q_pe[B] - b0;
 
     for (int ia = 0; ia < na; ia += TS) {
@@ -936,21 +943,38 @@ struct Timer {
     }
 };
 
+// Forest: the traversal starts from the self pair of every cloud root (the
+// children of the virtual vertex 0); pairs of different clouds never form.
+__global__ void k_forest_frontier(QView Q, int2 *__restrict__ cur, int cap)
+{
+    const int m = min(Q.kcnt[0], cap), k0 = Q.kbeg[0];
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m;
+         i += gridDim.x * blockDim.x) {
+        const int k = Q.kids[k0 + i];
+        cur[i] = make_int2(k, k);
+    }
+}
+
 template <int M>
 static void traverse(const fnn_tree *T, const Pts &P, const QView &Q,
                      const Prune &pr, Scratch &S, int2 **inter_out,
                      long long *ninter_out, fnn_stats &st)
 {
     hipStream_t s = S.stream();
-    long long cap_cur = 1 << 16, cap_next = 1 << 16;
+    const long long nroot = T->ncloud > 1 ? T->ncloud : 1;
+    long long cap_cur = std::max<long long>(1 << 16, nroot), cap_next = 1 << 16;
     long long cap_int = std::max<long long>(1 << 20, T->npacks * 16);
     int2 *cur = S.get<int2>(cap_cur), *next = S.get<int2>(cap_next);
     int2 *inter = S.get<int2>(cap_int);
     unsigned long long *cnt = S.get<unsigned long long>(4);
     int *ovf = S.get<int>(1);
     int2 root = make_int2(T->qroot, T->qroot);
-    FNN_HIP(hipMemcpyAsync(cur, &root, sizeof(int2), hipMemcpyHostToDevice, s));
-    long long ncur = 1, ninter = 0, tests = 0;
+    if (T->ncloud > 1)
+        FNN_LAUNCH(k_forest_frontier, dim3(grid_for(nroot, 256)), dim3(256), 0, s,
+                   Q, cur, (int)nroot);
+    else
+        FNN_HIP(hipMemcpyAsync(cur, &root, sizeof(int2), hipMemcpyHostToDevice, s));
+    long long ncur = nroot, ninter = 0, tests = 0;
     while (ncur > 0) {
         // bound the level's output and size both buffers before running it
         fill(cnt + 3, 0ull, 1, s);
@@ -1000,17 +1024,20 @@ static void traverse(const fnn_tree *T, const Pts &P, const QView &Q,
 template <int M>
 static void launch_tiles(bool fill_pass, const Pts &P, const int2 *inter,
                          long long ninter, const fnn_tree *T, const Thr &E,
-                         int fp64_dist, const TileOut &o, hipStream_t s)
+                         const CloudThr *ct, int fp64_dist, const TileOut &o,
+                         hipStream_t s)
 {
     if (ninter <= 0)
         return;
     const dim3 g(grid_for(ninter, 1));
     if (fill_pass)
         FNN_LAUNCH((k_tile<M, true>), g, dim3(TT), 0, s, P, inter, ninter,
-                   T->q_pt_begin, T->q_pt_end, T->perm, E, fp64_dist, o);
+                   T->q_pt_begin, T->q_pt_end, T->perm, E, ct, T->pcl, fp64_dist,
+                   o);
     else
         FNN_LAUNCH((k_tile<M, false>), g, dim3(TT), 0, s, P, inter, ninter,
-                   T->q_pt_begin, T->q_pt_end, T->perm, E, fp64_dist, o);
+                   T->q_pt_begin, T->q_pt_end, T->perm, E, ct, T->pcl, fp64_dist,
+                   o);
 }
 
 // Learned-schedule state of one query.
@@ -1024,9 +1051,9 @@ struct Learned {
 const float *cost_model_device();
 
 template <int M>
-static void eps_graph_impl(const fnn_tree *Tc, double eps, const Options &opt,
-                           fnn_csr *C, fnn_stats &st, Scratch &S,
-                           float **trace_feat, float **trace_targ)
+static void eps_graph_impl(const fnn_tree *Tc, const double *epsv,
+                           const Options &opt, fnn_csr *C, fnn_stats &st,
+                           Scratch &S, float **trace_feat, float **trace_targ)
 {
     fnn_tree *T = const_cast<fnn_tree *>(Tc);  // lazily built caches only
     hipStream_t s = S.stream();
@@ -1050,14 +1077,32 @@ static void eps_graph_impl(const fnn_tree *Tc, double eps, const Options &opt,
 
     QView Q{T->q_center_pos, T->q_pt_begin, T->q_pt_end, T->q_kbeg,
             T->q_kcnt,       T->q_kids,     T->q_radius, (int)T->nnodes};
-    const Thr E = make_thr_eps(M, T->dp, eps);
+    // thresholds of every cloud (one entry for an ordinary tree)
+    const int ncl = T->ncloud;
+    std::vector<CloudThr> ct_h(ncl);
+    for (int c = 0; c < ncl; ++c) {
+        const double e = epsv[c];
+        CloudThr &t = ct_h[c];
+        t.E = make_thr_eps(M, T->dp, e);
+        t.peps = (M == M_HAM || M == M_LEV) ? t.E.lo : (float)e;
+        if (M == M_ANG && e >= M_PI)
+            t.peps = 4.f;  // every pair may touch
+        t.e2f = gram_eps2(M, e, t.E);
+        t.feps = std::max(t.peps, 0.5f);
+        t.pad_ = 0.f;
+    }
+    CloudThr *ct_d = S.get<CloudThr>(ncl);
+    FNN_HIP(hipMemcpyAsync(ct_d, ct_h.data(), sizeof(CloudThr) * ncl,
+                           hipMemcpyHostToDevice, s));
+    const Thr E = ct_h[0].E;
+    const double eps = epsv[0];
     Prune pr;
     const double u = 1.0 / 16777216.0;
     pr.rel = (float)std::max(1e-4, 8.0 * (T->dp + 4) * u);
     pr.abs_ = M == M_ANG ? 1e-5f : (M == M_L2 ? 1e-30f : 0.f);
-    pr.eps = (M == M_HAM || M == M_LEV) ? E.lo : (float)eps;
-    if (M == M_ANG && eps >= M_PI)
-        pr.eps = 4.f;  // every pair may touch
+    pr.eps = ct_h[0].peps;
+    pr.ct = ncl > 1 ? ct_d : nullptr;
+    pr.pcl = ncl > 1 ? T->pcl : nullptr;
     const int fp64_dist = (M == M_ANG) || (M == M_L2 && (T->dim + 2) * u > 1e-5);
     const bool learned = opt.sched == FNN_SCHED_LEARNED;
 
@@ -1065,12 +1110,11 @@ static void eps_graph_impl(const fnn_tree *Tc, double eps, const Options &opt,
     Learned Lm;
     if (learned || opt.trace) {
         tree_aux(T, S);
-        const float feps = std::max(pr.eps, 0.5f);
         Lm.feat = opt.trace ? (float *)out_alloc(sizeof(float) * MLP_F * (size_t)n)
                             : S.get<float>((size_t)n * MLP_F);
         if (opt.trace)
             *trace_feat = Lm.feat;
-        compute_features(T, P, feps, Lm.feat, s);
+        compute_features(T, P, ct_h[0].feps, ncl > 1 ? ct_d : nullptr, Lm.feat, s);
     }
     if (learned) {
         Lm.model = cost_model_device();
@@ -1100,6 +1144,8 @@ static void eps_graph_impl(const fnn_tree *Tc, double eps, const Options &opt,
             G.q_pb = T->q_pt_begin;
             G.q_pe = T->q_pt_end;
             G.perm = T->perm;
+            G.ct = ncl > 1 ? ct_d : nullptr;
+            G.pcl = ncl > 1 ? T->pcl : nullptr;
         }
     }
     tm.mark();  // 2
@@ -1166,7 +1212,7 @@ static void eps_graph_impl(const fnn_tree *Tc, double eps, const Options &opt,
                 ++novf;  // a second filter pass was needed
             }
         }
-        launch_tiles<M>(false, P, plain, nplain, T, E, fp64_dist, o, s);
+        launch_tiles<M>(false, P, plain, nplain, T, E, ct_d, fp64_dist, o, s);
         tm.mark();  // 3
 
         scan_i32_to_i64(o.deg, C->row_ptr, n, S);
@@ -1187,7 +1233,7 @@ static void eps_graph_impl(const fnn_tree *Tc, double eps, const Options &opt,
         if (nnz > 0) {
             if (use_gram)
                 edges_scatter(gedges, gedist, ngedges, o, s);
-            launch_tiles<M>(true, P, plain, nplain, T, E, fp64_dist, o, s);
+            launch_tiles<M>(true, P, plain, nplain, T, E, ct_d, fp64_dist, o, s);
         }
         FNN_LAUNCH(k_cursor_check_rows, dim3(grid_for(n, 256)), dim3(256), 0, s,
                    C->row_ptr, n, o.cursor, (const int32_t *)nullptr, bad);
@@ -1220,7 +1266,7 @@ static void eps_graph_impl(const fnn_tree *Tc, double eps, const Options &opt,
         o.spill_cnt = S.get<unsigned long long>(1);
         fill(o.spill_cnt, 0ull, 1, s);
         o.spill_cap = (unsigned long long)spcap;
-        launch_tiles<M>(true, P, plain, nplain, T, E, fp64_dist, o, s);
+        launch_tiles<M>(true, P, plain, nplain, T, E, ct_d, fp64_dist, o, s);
         tm.mark();  // 3
         // cursors advanced by every edge, written or not: exact degrees
         o.deg = S.get<int32_t>(n);
@@ -1279,7 +1325,7 @@ static void eps_graph_impl(const fnn_tree *Tc, double eps, const Options &opt,
             o2.cursor = S.get<unsigned long long>(n);
             FNN_LAUNCH(k_cursor_init, dim3(grid_for(n, 256)), dim3(256), 0, s,
                        C->row_ptr, n, o2.cursor);
-            launch_tiles<M>(true, P, sub, nsub, T, E, fp64_dist, o2, s);
+            launch_tiles<M>(true, P, sub, nsub, T, E, ct_d, fp64_dist, o2, s);
             FNN_LAUNCH(k_cursor_check_rows, dim3(grid_for(n, 256)), dim3(256), 0,
                        s, C->row_ptr, n, o2.cursor, ovf, bad);
         }
@@ -1366,8 +1412,8 @@ static void eps_graph_impl(const fnn_tree *Tc, double eps, const Options &opt,
     st.total_ms = tm.ms(0, 6);
 }
 
-void eps_graph(const fnn_tree *T, double eps, const Options &opt, fnn_csr *C,
-               fnn_stats &st, Scratch &S, float **tf, float **tt)
+void eps_graph(const fnn_tree *T, const double *eps, const Options &opt,
+               fnn_csr *C, fnn_stats &st, Scratch &S, float **tf, float **tt)
 {
     switch (T->metric) {
     case M_L2:

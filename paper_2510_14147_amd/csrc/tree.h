@@ -80,6 +80,16 @@ struct fnn_tree {
     int32_t *leaf_of = nullptr;  // [n] leaf block of each tree position
     int32_t *pack_of = nullptr;  // [n] query-tree pack of each position
 
+    // batch of independent clouds (forest): vertex 0 is a virtual root whose
+    // children 1..ncloud are the cloud roots; cloud c holds the input rows
+    // and tree positions [cloud_off_h[c], cloud_off_h[c + 1]).  With one
+    // cloud the tree is an ordinary cover tree and pcl is null.
+    int ncloud = 1;
+    std::vector<int64_t> cloud_off_h;  // compact (non-empty) clouds
+    std::vector<int32_t> cloud_src;    // caller's index of each compact cloud
+    int32_t ncloud_in = 1;             // clouds as the caller numbered them
+    int32_t *pcl = nullptr;            // [n] cloud of each tree position
+
     int depth = 0;
     fnn_stats stats{};
     std::vector<void *> owned;

@@ -55,6 +55,32 @@ def test_argument_errors_without_gpu(lib):
     assert lib.fnn_eps_graph(None, 1.0, ctypes.byref(out)) == -1
     lib.fnn_free.argtypes = [vp]
     lib.fnn_free(None)
+    # batch of clouds: offsets are checked on the host before any device work
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    lib.fnn_tree_build_batch.argtypes = [vp, i64p, ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.c_int, vp, ctypes.POINTER(vp)]
+
+    def offs(*v):
+        return (ctypes.c_int64 * len(v))(*v)
+
+    assert lib.fnn_tree_build_batch(vp(16), None, 2, 4, 0, None, ctypes.byref(out)) == -1
+    assert b"offsets" in lib.fnn_last_error()
+    assert lib.fnn_tree_build_batch(vp(16), offs(0, 5), 0, 4, 0, None,
+                                    ctypes.byref(out)) == -1
+    assert lib.fnn_tree_build_batch(vp(16), offs(1, 5, 9), 2, 4, 0, None,
+                                    ctypes.byref(out)) == -1
+    assert lib.fnn_tree_build_batch(vp(16), offs(0, 7, 5, 9), 3, 4, 0, None,
+                                    ctypes.byref(out)) == -1
+    assert b"non-decreasing" in lib.fnn_last_error()
+    assert lib.fnn_tree_build_batch(vp(16), offs(0, 0, 0), 2, 4, 0, None,
+                                    ctypes.byref(out)) == -1  # every cloud empty
+    assert lib.fnn_tree_build_batch(None, offs(0, 3), 1, 4, 0, None,
+                                    ctypes.byref(out)) == -1
+    assert out.value is None
+    lib.fnn_eps_graph_batch.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
+                                        ctypes.c_int32, vp, ctypes.POINTER(vp)]
+    e2 = (ctypes.c_double * 2)(1.0, 2.0)
+    assert lib.fnn_eps_graph_batch(None, e2, 2, None, ctypes.byref(out)) == -1
     lib.fnn_set_allocator.argtypes = [vp, vp, vp]
     assert lib.fnn_set_allocator(vp(1), None, None) == -1
 
