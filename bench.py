@@ -54,6 +54,56 @@ def workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
+def c5_groups(max_clouds: int | None = None):
+    """The many-clouds workload as one batch per dimension (a batch shares
+    one row layout): [(points, offsets, eps list, dim)]."""
+    specs = G.c5_cloud_specs()
+    if max_clouds:
+        specs = specs[:max_clouds]
+    groups = []
+    for d in (3, 16, 64):
+        sel = [s for s in specs if s["dim"] == d]
+        if not sel:
+            continue
+        xs = [G.c5_cloud(s) for s in sel]
+        off = np.concatenate([[0], np.cumsum([len(x) for x in xs])]).astype(np.int64)
+        groups.append((np.concatenate(xs, axis=0), off,
+                       [W["c5"]["eps"][s["cloud"]] for s in sel], d))
+    return groups
+
+
+def cpu_baseline_c5(groups, rows: int, seed: int = 7):
+    """The FP64 oracle (brute force) on seeded sample rows of the clouds,
+    each row against all points of its own cloud."""
+    from oracle import oracle as O
+    rng = np.random.default_rng(seed)
+    O.lib()
+    ntot = sum(g[0].shape[0] for g in groups)
+    edges, pairs, dt, nrows = 0, 0, 0.0, 0
+    for x, off, eps, _ in groups:
+        k = max(1, int(round(rows * x.shape[0] / ntot)))
+        sample = np.sort(rng.choice(x.shape[0], size=min(k, x.shape[0]), replace=False))
+        cl = np.searchsorted(off, sample, side="right") - 1
+        for c in np.unique(cl):
+            lo, hi = int(off[c]), int(off[c + 1])
+            r = sample[cl == c] - lo
+            t0 = time.perf_counter()
+            rp, _, _ = O.bruteforce(x[lo:hi], 0, eps[c], rows=r)
+            dt += time.perf_counter() - t0
+            edges += int(rp[-1])
+            pairs += r.size * (hi - lo)
+            nrows += r.size
+    cores = len(os.sched_getaffinity(0))
+    omp = os.environ.get("OMP_NUM_THREADS")
+    if omp:
+        cores = min(cores, int(omp))
+    return {"value": edges / dt, "unit": "edges/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"{nrows} seeded rows, each vs all points of its cloud, "
+                      f"FP64 brute force ({edges} edges in {dt:.2f} s); "
+                      f"pair evals/s {pairs / dt:.3e}"}
+
+
 def cpu_baseline(x, metric, eps, rows: int, seed: int = 7):
     """The FP64 oracle (brute force, as it stands) on a bounded sample of
     rows against all points, on this host's cores."""
@@ -78,15 +128,46 @@ def cpu_baseline(x, metric, eps, rows: int, seed: int = 7):
                       f"pair evals/s {sample.size * x.shape[0] / dt:.3e}"}
 
 
+def roofline(dim, precision, tq):
+    """Roofline of the dominant kernel of one query: the leaf-tile count pass
+    (plain FP32: 3*d flops per pair -- difference, square, accumulate) or the
+    MFMA Gram filter (2*k flops per screened pair, k = padded dim), timed with
+    HIP events inside the library on the stream it runs on."""
+    if tq["count_ms"] <= 0:
+        return None
+    if precision != "fp32":
+        kq = -(-dim // 16) * 16 if precision == "bf16" else -(-dim // 64) * 64
+        flops = 2.0 * kq * tq["filter_pairs"]
+        ach = flops / (tq["count_ms"] / 1e3) / 1e12
+        peak = PEAK_BF16_TFLOPS if precision == "bf16" else PEAK_FP8_TFLOPS
+        return {"bound": "mfma", "achieved": round(ach, 3), "peak": peak,
+                "unit": "TFLOP/s", "frac": round(ach / peak, 4), "traffic": None,
+                "kernel": f"k_gram<L2,{precision}>+k_survive",
+                "kernel_ms": round(tq["count_ms"], 3), "flops_per_launch": flops}
+    flops = 3.0 * dim * tq["tile_pairs"]
+    ach = flops / (tq["count_ms"] / 1e3) / 1e12
+    return {"bound": "alu", "achieved": round(ach, 3),
+            "peak": PEAK_FP32_VEC_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(ach / PEAK_FP32_VEC_TFLOPS, 4), "traffic": None,
+            "kernel": "k_tile<L2,count>", "kernel_ms": round(tq["count_ms"], 3),
+            "flops_per_launch": flops}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2a")
-    ap.add_argument("--precision", default="fp32")
+    ap.add_argument("--workload", default="c2a",
+                    help="c2a c2b c2_50k c1 c3 c4 ang | c5 (many clouds, one "
+                         "batch per dim) | c5_loop (one call per cloud)")
+    ap.add_argument("--precision", default="fp32",
+                    help="fp32 | bf16 | fp8 | auto (c5: fp32 below dim 16, "
+                         "else bf16)")
     ap.add_argument("--sched", default="two_pass")
     ap.add_argument("--cpu-rows", type=int, default=1500)
+    ap.add_argument("--c5-clouds", type=int, default=0,
+                    help="use only the first K clouds of c5 (0: all 256)")
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -97,93 +178,116 @@ def main():
     import torch
     import paper_2510_14147_amd as fnn
 
-    x, metric, eps, desc = workload(args.workload)
-    print(f"[bench] workload {desc} n={x.shape[0]} metric={metric} eps={eps}",
-          file=sys.stderr, flush=True)
-    if metric == "hamming":
-        xd = torch.from_numpy(x.view(np.int64)).cuda()
+    def prec_for(dim):
+        if args.precision == "auto":
+            return "fp32" if dim < 16 else "bf16"
+        return args.precision
+
+    # jobs: (device points, offsets or None, metric, eps, dim, precision)
+    jobs, groups = [], None
+    if args.workload in ("c5", "c5_loop"):
+        groups = c5_groups(args.c5_clouds or None)
+        metric = "l2"
+        n_all = sum(g[0].shape[0] for g in groups)
+        desc = (f"c5_many_clouds_{sum(len(g[2]) for g in groups)}_sum_n{n_all}_"
+                f"d3_16_64_{'batched' if args.workload == 'c5' else 'per_cloud'}")
+        for x, off, eps, d in groups:
+            xd = torch.from_numpy(x).cuda()
+            if args.workload == "c5":
+                jobs.append((xd, off, metric, eps, d, prec_for(d)))
+            else:
+                for c in range(len(eps)):
+                    jobs.append((xd[int(off[c]):int(off[c + 1])], None, metric,
+                                 eps[c], d, prec_for(d)))
+        eps_desc = "per-cloud"
+        x = None
     else:
-        xd = torch.from_numpy(x).cuda()
+        x, metric, eps, desc = workload(args.workload)
+        n_all = x.shape[0]
+        if metric == "hamming":
+            xd = torch.from_numpy(x.view(np.int64)).cuda()
+        else:
+            xd = torch.from_numpy(x).cuda()
+        dim = x.shape[1] if metric in ("l2", "angular") else None
+        jobs.append((xd, None, metric, eps, dim, prec_for(dim or 0)))
+        eps_desc = eps
+    print(f"[bench] workload {desc} n={n_all} metric={metric} eps={eps_desc} "
+          f"jobs={len(jobs)}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
 
     def step():
-        tree = fnn.fnn_tree_build(xd, metric)
-        g = fnn.fnn_eps_graph(tree, eps, precision=args.precision,
-                              sched=args.sched)
-        return tree, g
+        res = []
+        for xd, off, m, e, d, p in jobs:
+            if off is None:
+                tree = fnn.fnn_tree_build(xd, m)
+                g = fnn.fnn_eps_graph(tree, e, precision=p, sched=args.sched)
+            else:
+                tree = fnn.fnn_tree_build_batch(xd, off, m)
+                g = fnn.fnn_eps_graph_batch(tree, e, precision=p, sched=args.sched)
+            res.append((tree.stats, g.stats, g.nnz, d, p))
+            del tree, g
+        return res
 
     for i in range(args.warmup):
-        tree, g = step()
-        print(f"[bench] warmup {i}: nnz={g.nnz} build={tree.stats['build_ms']:.1f} ms "
-              f"query={g.stats['total_ms']:.1f} ms", file=sys.stderr, flush=True)
-        del tree, g
+        r = step()
+        print(f"[bench] warmup {i}: nnz={sum(x[2] for x in r)} "
+              f"build={sum(x[0]['build_ms'] for x in r):.1f} ms "
+              f"query={sum(x[1]['total_ms'] for x in r):.1f} ms",
+              file=sys.stderr, flush=True)
     torch.cuda.synchronize()
-    times, stats = [], []
+    stats = []
     t_all = time.perf_counter()
     for i in range(args.steps):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        tree, g = step()
+        r = step()
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        times.append(dt)
-        stats.append((tree.stats, g.stats, g.nnz))
-        print(f"[bench] step {i}: {dt * 1e3:.1f} ms nnz={g.nnz}",
+        stats.append(r)
+        print(f"[bench] step {i}: {dt * 1e3:.1f} ms nnz={sum(x[2] for x in r)}",
               file=sys.stderr, flush=True)
-        del tree, g
     total = time.perf_counter() - t_all
     ms = 1e3 * total / args.steps
-    tb, tq, nnz = stats[-1]
-    evals = tb["build_dist_evals"] + tq["traverse_tests"] + 2 * tq["tile_pairs"]
+    last = stats[-1]
+    nnz = sum(x[2] for x in last)
+    agg = lambda k, j: sum(x[j][k] for x in last)  # noqa: E731
+    evals = agg("build_dist_evals", 0) + agg("traverse_tests", 1) + 2 * agg("tile_pairs", 1)
     value = nnz / (ms / 1e3)
-    dim = x.shape[1] if metric in ("l2", "angular") else None
-
-    # Dominant kernel: the leaf-tile count pass (event-timed in the library
-    # on the stream it runs on).  Algorithmic work: 3*d flops per pair
-    # (difference, square, accumulate) for the vector metrics.
-    roof = None
-    if metric in ("l2", "angular") and args.precision != "fp32" and tq["count_ms"] > 0:
-        # MFMA Gram filter: 2*k flops per screened pair (k = padded dim)
-        kq = -(-dim // 16) * 16 if args.precision == "bf16" else -(-dim // 64) * 64
-        flops = 2.0 * kq * tq["filter_pairs"]
-        ach = flops / (tq["count_ms"] / 1e3) / 1e12
-        peak = PEAK_BF16_TFLOPS if args.precision == "bf16" else PEAK_FP8_TFLOPS
-        roof = {"bound": "mfma", "achieved": round(ach, 3), "peak": peak,
-                "unit": "TFLOP/s", "frac": round(ach / peak, 4), "traffic": None,
-                "kernel": f"k_gram<L2,{args.precision},count>",
-                "kernel_ms": round(tq["count_ms"], 3), "flops_per_launch": flops}
-    elif metric in ("l2", "angular") and tq["count_ms"] > 0:
-        flops = 3.0 * dim * tq["tile_pairs"]
-        ach = flops / (tq["count_ms"] / 1e3) / 1e12
-        roof = {"bound": "alu", "achieved": round(ach, 3),
-                "peak": PEAK_FP32_VEC_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(ach / PEAK_FP32_VEC_TFLOPS, 4), "traffic": None,
-                "kernel": "k_tile<L2,count>", "kernel_ms": round(tq["count_ms"], 3),
-                "flops_per_launch": flops}
+    # dominant kernel: that of the job with the longest count pass
+    dom = max(last, key=lambda x: x[1]["count_ms"])
+    roof = roofline(dom[3], dom[4], dom[1]) if metric in ("l2", "angular") else None
+    if roof is not None and len(last) > 1:
+        roof["job"] = f"dim {dom[3]}, {dom[4]}"
+    precs = sorted({x[4] for x in last})
     out = {
         "metric": "epsilon-graph edges/s (exact, symmetric CSR)",
         "value": value, "unit": "edges/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
-        "config": {"workload": desc, "n": int(x.shape[0]), "dim": dim,
-                   "metric": metric, "eps": eps, "precision": args.precision,
+        "config": {"workload": desc, "n": int(n_all),
+                   "dim": None if groups else jobs[0][4], "metric": metric,
+                   "eps": None if groups else eps, "precision": "+".join(precs),
                    "sched": args.sched, "nnz": int(nnz),
-                   "mean_neighbors": nnz / x.shape[0]},
+                   "mean_neighbors": nnz / n_all, "calls": len(jobs)},
         "dist_evals_per_s": evals / (ms / 1e3),
-        "phases_ms": {"build": tb["build_ms"], "traverse": tq["traverse_ms"],
-                      "count": tq["count_ms"], "scan": tq["scan_ms"],
-                      "fill": tq["fill_ms"], "sort": tq["sort_ms"]},
-        "counters": {k: tq[k] for k in ("interactions", "tile_pairs",
-                                        "traverse_tests", "fp64_rechecks",
-                                        "filter_pairs", "filter_survivors",
-                                        "packs", "nodes")} |
-                    {"build_dist_evals": tb["build_dist_evals"],
-                     "rounds": tb["rounds"], "netsel_passes": tb["netsel_passes"]},
+        "phases_ms": {"build": agg("build_ms", 0), "traverse": agg("traverse_ms", 1),
+                      "count": agg("count_ms", 1), "scan": agg("scan_ms", 1),
+                      "fill": agg("fill_ms", 1), "sort": agg("sort_ms", 1)},
+        "counters": {k: agg(k, 1) for k in ("interactions", "tile_pairs",
+                                            "traverse_tests", "fp64_rechecks",
+                                            "filter_pairs", "filter_survivors",
+                                            "packs", "nodes")} |
+                    {"build_dist_evals": agg("build_dist_evals", 0),
+                     "rounds": max(x[0]["rounds"] for x in last),
+                     "netsel_passes": agg("netsel_passes", 0)},
         "roofline": roof,
     }
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(x, metric, eps, args.cpu_rows)
+        if groups:
+            out["cpu_baseline"] = cpu_baseline_c5(groups, args.cpu_rows)
+        else:
+            out["cpu_baseline"] = cpu_baseline(x, metric, eps, args.cpu_rows)
     print(json.dumps(out), flush=True)
 
 
