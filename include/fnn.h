@@ -82,12 +82,17 @@ typedef struct fnn_options {
     int32_t sched;        /* fnn_sched; default FNN_SCHED_TWO_PASS           */
     int32_t validate;     /* 1: also measure the max FP32 distance error     */
                           /* against FP64 and count filter false negatives    */
-    int32_t kmax;         /* centres accepted per net-selection pass (1..64) */
+    int32_t kmax;         /* candidates examined per net-selection pass     */
+                          /* and hub (1..256; default 64)                   */
     int32_t trace;        /* 1: keep per-point features and targets of this  */
                           /* query for training the cost model               */
     int32_t slack_pct;    /* learned schedule: slot slack in percent of the  */
                           /* predicted row length (default 30; may be < 0)   */
-    int32_t reserved[7];
+    int32_t graph_passes; /* build: net-selection passes recorded into one  */
+                          /* hipGraph and replayed between host checks      */
+                          /* (default 4, rounded up to even; 1 = one eager  */
+                          /* pass per host check)                           */
+    int32_t reserved[6];
 } fnn_options;
 
 typedef struct fnn_tree fnn_tree;  /* opaque; device-resident cover tree */

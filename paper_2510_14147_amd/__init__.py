@@ -41,7 +41,8 @@ class fnn_options(ctypes.Structure):
                 ("pack", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("sched", ctypes.c_int32), ("validate", ctypes.c_int32),
                 ("kmax", ctypes.c_int32), ("trace", ctypes.c_int32),
-                ("slack_pct", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+                ("slack_pct", ctypes.c_int32), ("graph_passes", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 6)]
 
 
 class fnn_csr(ctypes.Structure):
@@ -256,13 +257,13 @@ def _as_device_points(points, metric: str):
 
 
 def fnn_tree_build(points, metric: str = "l2", zeta=None, pack=None,
-                   kmax=None) -> Tree:
+                   kmax=None, graph_passes=None) -> Tree:
     """Cover tree of ``points`` (numpy array or tensor; moved to the GPU)."""
     m = METRICS[metric]
     t, dim = _as_device_points(points, metric)
     _bind_stream()
     h = ctypes.c_void_p()
-    o = _options(zeta=zeta, pack=pack, kmax=kmax)
+    o = _options(zeta=zeta, pack=pack, kmax=kmax, graph_passes=graph_passes)
     _check(lib().fnn_tree_build_ex(ctypes.c_void_p(t.data_ptr()), t.shape[0],
                                    dim, m, ctypes.byref(o), ctypes.byref(h)))
     tree = Tree(h, t.shape[0], dim, metric)
@@ -270,7 +271,7 @@ def fnn_tree_build(points, metric: str = "l2", zeta=None, pack=None,
 
 
 def fnn_tree_build_batch(points, offsets, metric: str = "l2", zeta=None,
-                         pack=None, kmax=None) -> Tree:
+                         pack=None, kmax=None, graph_passes=None) -> Tree:
     """One forest over many clouds: ``points`` holds the clouds' rows back to
     back, cloud c = rows [offsets[c], offsets[c+1])."""
     m = METRICS[metric]
@@ -282,7 +283,7 @@ def fnn_tree_build_batch(points, offsets, metric: str = "l2", zeta=None,
         raise ValueError("offsets[-1] must equal the number of rows")
     _bind_stream()
     h = ctypes.c_void_p()
-    o = _options(zeta=zeta, pack=pack, kmax=kmax)
+    o = _options(zeta=zeta, pack=pack, kmax=kmax, graph_passes=graph_passes)
     _check(lib().fnn_tree_build_batch(
         ctypes.c_void_p(t.data_ptr()),
         off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), off.size - 1, dim, m,

@@ -72,10 +72,14 @@ Options read_options(const fnn_options *o)
     r.sched = o->sched;
     r.validate = o->validate ? 1 : 0;
     if (o->kmax)
-        r.kmax = o->kmax > 64 ? 64 : o->kmax;
+        r.kmax = o->kmax > 256 ? 256 : o->kmax;
     r.trace = o->trace ? 1 : 0;
     if (o->slack_pct)
         r.slack_pct = o->slack_pct < -90 ? -90 : o->slack_pct;
+    if (o->graph_passes < 0)
+        fail(FNN_EINVAL, "negative graph_passes");
+    if (o->graph_passes)
+        r.graph_passes = o->graph_passes > 64 ? 64 : o->graph_passes;
     return r;
 }
 

@@ -315,20 +315,33 @@ __device__ __forceinline__ bool better(float d, int id, float d2, int id2)
     return d > d2 || (d == d2 && id < id2);
 }
 
-constexpr int UPD_K = 32;   // centres staged per pass
+constexpr int UPD_K = 32;   // centres staged per batch
+constexpr int CAND_R = 8;   // most candidates reported per chunk and pass
+
+// Candidates per chunk of a hub with nch chunks: about 2 kmax per hub when
+// the hub is small, one per chunk once it has that many chunks.
+__device__ __forceinline__ int cand_per_chunk(int nch, int kmax)
+{
+    return min(CAND_R, max(1, (2 * kmax + nch - 1) / nch));
+}
 constexpr int UPD_D = 128;  // largest row stride staged in LDS
 
 template <int M>
 __global__ void __launch_bounds__(CH)
 k_update(Pts P, const int32_t *__restrict__ ch_hub, const int32_t *__restrict__ ch_s,
-         const int32_t *__restrict__ ch_e, int NC, Hubs hb,
+         const int32_t *__restrict__ ch_e, const int32_t *__restrict__ queue,
+         const int32_t *__restrict__ qlen, Hubs hb,
          const int32_t *__restrict__ cent, const int32_t *__restrict__ perm,
          float *__restrict__ D, int32_t *__restrict__ L,
          const LevelTab *__restrict__ tab, float *__restrict__ cb_D,
-         int32_t *__restrict__ cb_id, unsigned long long *__restrict__ cnt)
+         int32_t *__restrict__ cb_id, int kmax, unsigned long long *__restrict__ cnt)
 {
     __shared__ __align__(16) float cen[UPD_K * UPD_D];
-    for (int c = blockIdx.x; c < NC; c += gridDim.x) {
+    // the queue lists the chunks of the hubs still active (device-resident
+    // length, so passes need no host round trip)
+    const int nq = *qlen;
+    for (int t = blockIdx.x; t < nq; t += gridDim.x) {
+    const int c = queue[t];
     const int h = ch_hub[c];
     if (!hb.act[h])
         continue;
@@ -339,56 +352,56 @@ k_update(Pts P, const int32_t *__restrict__ ch_hub, const int32_t *__restrict__ 
     const int j0 = hb.ma[h], j1 = hb.m[h];
     float dv = -1.f;
     int id = INT_MAX;
+    const int o = valid ? perm[p] : 0;
+    float dcur = valid ? D[p] : 0.f;
+    int lcur = valid ? L[p] : 0;
     bool staged = false;
     if constexpr (M == M_L2 || M == M_ANG) {
-        // vector metrics: the pass's new centres go to LDS once per chunk and
-        // every point row is read once for all of them
-        staged = (j1 > j0) && (j1 - j0) <= UPD_K && P.dp <= UPD_D;
+        // vector metrics: the pass's new centres go to LDS in batches of
+        // UPD_K, and every point row is read once per batch
+        staged = (j1 > j0) && P.dp <= UPD_D;
         if (staged) {
             const float *X = (M == M_ANG) ? P.xn : P.x;
-            const int nj = j1 - j0, dp = P.dp;
-            for (int e = threadIdx.x; e < nj * dp; e += CH)
-                cen[e] = X[(size_t)cent[b + j0 + e / dp] * dp + (e % dp)];
-        }
-        __syncthreads();
-    }
-    if (valid) {
-        const int o = perm[p];
-        float dcur = D[p];
-        int lcur = L[p];
-        if constexpr (M == M_L2 || M == M_ANG) {
-            if (staged) {
-                const float *X = (M == M_ANG) ? P.xn : P.x;
-                const float *row = X + (size_t)o * P.dp;
-                const int nj = j1 - j0;
-                float acc[UPD_K];
+            const int dp = P.dp;
+            const float *row = X + (size_t)o * dp;
+            for (int jb = j0; jb < j1; jb += UPD_K) {
+                const int nj = min(UPD_K, j1 - jb);
+                __syncthreads();  // the previous batch is consumed
+                for (int e = threadIdx.x; e < nj * dp; e += CH)
+                    cen[e] = X[(size_t)cent[b + jb + e / dp] * dp + (e % dp)];
+                __syncthreads();
+                if (valid) {
+                    float acc[UPD_K];
 #pragma unroll
-                for (int j = 0; j < UPD_K; ++j)
-                    acc[j] = 0.f;
-                for (int k = 0; k < P.dp; k += 4) {
-                    const float4 v = *reinterpret_cast<const float4 *>(row + k);
+                    for (int j = 0; j < UPD_K; ++j)
+                        acc[j] = 0.f;
+                    for (int k = 0; k < dp; k += 4) {
+                        const float4 v = *reinterpret_cast<const float4 *>(row + k);
 #pragma unroll
-                    for (int j = 0; j < UPD_K; ++j) {
-                        if (j < nj) {
-                            const float4 c = *reinterpret_cast<const float4 *>(
-                                cen + j * P.dp + k);
-                            const float d0 = v.x - c.x, d1 = v.y - c.y,
-                                        d2 = v.z - c.z, d3 = v.w - c.w;
-                            acc[j] = fmaf(d0, d0, acc[j]);
-                            acc[j] = fmaf(d1, d1, acc[j]);
-                            acc[j] = fmaf(d2, d2, acc[j]);
-                            acc[j] = fmaf(d3, d3, acc[j]);
+                        for (int j = 0; j < UPD_K; ++j) {
+                            if (j < nj) {
+                                const float4 c = *reinterpret_cast<const float4 *>(
+                                    cen + j * dp + k);
+                                const float d0 = v.x - c.x, d1 = v.y - c.y,
+                                            d2 = v.z - c.z, d3 = v.w - c.w;
+                                acc[j] = fmaf(d0, d0, acc[j]);
+                                acc[j] = fmaf(d1, d1, acc[j]);
+                                acc[j] = fmaf(d2, d2, acc[j]);
+                                acc[j] = fmaf(d3, d3, acc[j]);
+                            }
                         }
                     }
-                }
 #pragma unroll
-                for (int j = 0; j < UPD_K; ++j)
-                    if (j < nj && acc[j] < dcur) {
-                        dcur = acc[j];
-                        lcur = j0 + j;
-                    }
+                    for (int j = 0; j < UPD_K; ++j)
+                        if (j < nj && acc[j] < dcur) {
+                            dcur = acc[j];
+                            lcur = jb + j;
+                        }
+                }
             }
         }
+    }
+    if (valid) {
         if (!staged)
             for (int j = j0; j < j1; ++j) {
                 float k = key32<M>(P, o, cent[b + j]);
@@ -407,124 +420,191 @@ k_update(Pts P, const int32_t *__restrict__ ch_hub, const int32_t *__restrict__ 
             id = o;
         }
     }
+    // the chunk's R farthest uncovered points, farthest first
+    const int R = cand_per_chunk(hb.ce[h] - hb.cb[h], kmax);
+    for (int r = 0; r < R; ++r) {
+        float bd = dv;
+        int bi = id;
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        float d2 = __shfl_xor(dv, off, WAVE);
-        int i2 = __shfl_xor(id, off, WAVE);
-        if (better(d2, i2, dv, id)) {
-            dv = d2;
-            id = i2;
+        for (int off = 32; off > 0; off >>= 1) {
+            float d2 = __shfl_xor(bd, off, WAVE);
+            int i2 = __shfl_xor(bi, off, WAVE);
+            if (better(d2, i2, bd, bi)) {
+                bd = d2;
+                bi = i2;
+            }
+        }
+        if (threadIdx.x == 0) {
+            cb_D[(size_t)c * CAND_R + r] = bd;
+            cb_id[(size_t)c * CAND_R + r] = bi;
+        }
+        if (id == bi && bd >= 0.f) {  // the winner leaves the race
+            dv = -1.f;
+            id = INT_MAX;
         }
     }
-    if (threadIdx.x == 0) {
-        cb_D[c] = dv;
-        cb_id[c] = id;
-        if (j1 > j0)
-            atomicAdd(cnt, (unsigned long long)(j1 - j0) * (unsigned)(e - s));
-    }
+    if (threadIdx.x == 0 && j1 > j0)
+        atomicAdd(cnt, (unsigned long long)(j1 - j0) * (unsigned)(e - s));
     }
 }
 
 constexpr int SEL_T = 256;
-constexpr int MAX_K = 64;
+constexpr int MAX_K = 256;     // candidates examined per hub and pass
+constexpr int SEL_BUF = 2048;  // LDS sort buffer (candidate keys)
+constexpr int SEL_W = MAX_K / 64;
 
+// Sort key of a chunk candidate: farther first, then the smaller input id
+// (0 = no candidate).
+__device__ __forceinline__ unsigned long long cand_key(float d, int id)
+{
+    if (!(d >= 0.f))
+        return 0ull;
+    return ((unsigned long long)__float_as_uint(d) << 32) |
+           (unsigned long long)(uint32_t)(0x7FFFFFFF - id);
+}
+
+// Bitonic sort of buf[0..m) (m a power of two), descending.
+__device__ void sort_desc(unsigned long long *buf, int m)
+{
+    for (int k = 2; k <= m; k <<= 1)
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < m; i += blockDim.x) {
+                const int ixj = i ^ j;
+                if (ixj > i) {
+                    const unsigned long long a = buf[i], b = buf[ixj];
+                    const bool desc = (i & k) == 0;
+                    if (desc ? (a < b) : (a > b)) {
+                        buf[i] = b;
+                        buf[ixj] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+}
+
+// One net-selection pass for every active hub (one work-group per hub): the
+// up to kmax farthest chunk candidates, in order (distance descending, id
+// ascending), are accepted greedily when more than 2^{l-1} from every
+// candidate accepted before them in this pass.  The pairwise conflicts of
+// the candidates are evaluated in parallel, then the greedy scan runs on
+// bit masks.
 template <int M>
 __global__ void __launch_bounds__(SEL_T)
-k_select(Pts P, Hubs hb, int H, int32_t *__restrict__ cent, float *__restrict__ cb_D,
-         const int32_t *__restrict__ cb_id, const LevelTab *__restrict__ tab,
-         int kmax, int32_t *__restrict__ n_active,
-         unsigned long long *__restrict__ cnt)
+k_select(Pts P, Hubs hb, int H, int32_t *__restrict__ cent,
+         const float *__restrict__ cb_D, const int32_t *__restrict__ cb_id,
+         const LevelTab *__restrict__ tab, int kmax, int32_t *__restrict__ qnext,
+         int32_t *__restrict__ qnext_len, unsigned long long *__restrict__ cnt)
 {
+    __shared__ unsigned long long buf[SEL_BUF];
+    __shared__ unsigned long long conf[MAX_K][SEL_W];
     __shared__ int acc[MAX_K];
-    __shared__ int nacc, ok;
-    __shared__ float rd[SEL_T / WAVE];
-    __shared__ int ri[SEL_T / WAVE], rc[SEL_T / WAVE];
-    __shared__ float bd_s;
-    __shared__ int bid_s, bc_s;
-    const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
+    __shared__ int nacc_s, nk_s, qb_s;
+    const int K = min(kmax, MAX_K);
     for (int h = blockIdx.x; h < H; h += gridDim.x) {
     if (!hb.act[h])
         continue;
-    const int c0 = hb.cb[h], c1 = hb.ce[h];
+    const int R = cand_per_chunk(hb.ce[h] - hb.cb[h], kmax);
+    const long long c0 = (long long)hb.cb[h] * R, c1 = (long long)hb.ce[h] * R;
     const int b = hb.b[h], m0 = hb.m[h];
     const Thr T = tab->t[hb.lvl[h] - 1 + LOFF];
-    if (threadIdx.x == 0)
-        nacc = 0;
-    __syncthreads();
-    for (int it = 0; it < kmax; ++it) {
-        float bd = -1.f;
-        int bid = INT_MAX, bc = -1;
-        for (int c = c0 + threadIdx.x; c < c1; c += SEL_T) {
-            float d = cb_D[c];
-            int id = cb_id[c];
-            if (d >= 0.f && better(d, id, bd, bid)) {
-                bd = d;
-                bid = id;
-                bc = c;
+
+    // ---- top-K candidates: sort blocks of chunks, keep the best K -------
+    int nk = 0;
+    for (long long base = c0; base < c1; base += SEL_BUF - K) {
+        const int m = (int)min((long long)(SEL_BUF - K), c1 - base);
+        const int tot = nk + m;
+        int p2 = 1;
+        while (p2 < tot)
+            p2 <<= 1;
+        for (int i = nk + threadIdx.x; i < p2; i += SEL_T) {
+            unsigned long long kv = 0ull;
+            if (i < tot) {
+                // candidate q of the hub: slot q % R of its chunk q / R
+                const long long q = base + i - nk;
+                const size_t at = (size_t)(q / R) * CAND_R + (size_t)(q % R);
+                kv = cand_key(cb_D[at], cb_id[at]);
             }
-        }
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-            float d2 = __shfl_xor(bd, off, WAVE);
-            int i2 = __shfl_xor(bid, off, WAVE);
-            int c2 = __shfl_xor(bc, off, WAVE);
-            if (better(d2, i2, bd, bid)) {
-                bd = d2;
-                bid = i2;
-                bc = c2;
-            }
-        }
-        if (lane == 0) {
-            rd[wid] = bd;
-            ri[wid] = bid;
-            rc[wid] = bc;
+            buf[i] = kv;
         }
         __syncthreads();
-        if (threadIdx.x == 0) {
-            for (int w = 1; w < SEL_T / WAVE; ++w)
-                if (better(rd[w], ri[w], bd, bid)) {
-                    bd = rd[w];
-                    bid = ri[w];
-                    bc = rc[w];
-                }
-            bd_s = bd;
-            bid_s = bid;
-            bc_s = bc;
-            ok = 1;
-        }
-        __syncthreads();
-        if (bd_s < 0.f)
-            break;
-        const int cand = bid_s;
-        const int na = nacc;
-        for (int a = threadIdx.x; a < na; a += SEL_T) {
-            float k = key32<M>(P, cand, acc[a]);
-            if (within<M>(P, cand, acc[a], k, T, cnt + 1))
-                ok = 0;
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            if (ok && nacc < MAX_K)
-                acc[nacc++] = cand;
-            cb_D[bc_s] = -1.f;
-            if (na > 0)
-                atomicAdd(cnt, (unsigned long long)na);
-        }
-        __syncthreads();
+        sort_desc(buf, p2);
+        nk = min(K, tot);
     }
+    // valid candidates are a prefix of buf (key 0 sorts last)
+    if (threadIdx.x == 0) {
+        int v = 0;
+        while (v < nk && buf[v] != 0ull)
+            ++v;
+        nk_s = v;
+    }
+    for (int i = threadIdx.x; i < MAX_K * SEL_W; i += SEL_T)
+        conf[i / SEL_W][i % SEL_W] = 0ull;
+    __syncthreads();
+    nk = nk_s;
+
+    // ---- pairwise conflicts (j < i): within 2^{l-1} ----------------------
+    unsigned long long tests = 0;
+    for (int q = threadIdx.x; q < nk * nk; q += SEL_T) {
+        const int i = q / nk, j = q % nk;
+        if (j >= i)
+            continue;
+        const int a = 0x7FFFFFFF - (int)(uint32_t)buf[i];
+        const int c = 0x7FFFFFFF - (int)(uint32_t)buf[j];
+        ++tests;
+        const float k = key32<M>(P, a, c);
+        if (within<M>(P, a, c, k, T, cnt + 1))
+            atomicOr(&conf[i][j >> 6], 1ull << (j & 63));
+    }
+    __syncthreads();
+
+    // ---- greedy acceptance in candidate order ------------------------------
+    if (threadIdx.x == 0) {
+        unsigned long long am[SEL_W];
+#pragma unroll
+        for (int w = 0; w < SEL_W; ++w)
+            am[w] = 0ull;
+        int na = 0;
+        for (int i = 0; i < nk; ++i) {
+            bool ok = true;
+#pragma unroll
+            for (int w = 0; w < SEL_W; ++w)
+                ok &= (conf[i][w] & am[w]) == 0ull;
+            if (ok) {
+                am[i >> 6] |= 1ull << (i & 63);
+                acc[na++] = 0x7FFFFFFF - (int)(uint32_t)buf[i];
+            }
+        }
+        nacc_s = na;
+    }
+    __syncthreads();
+    const int nacc = nacc_s;
     for (int a = threadIdx.x; a < nacc; a += SEL_T)
         cent[b + m0 + a] = acc[a];
-    __syncthreads();
+    tests = wave_sum(tests);
+    if ((threadIdx.x & (WAVE - 1)) == 0 && tests)
+        atomicAdd(cnt, tests);
     if (threadIdx.x == 0) {
         hb.ma[h] = m0;
         hb.m[h] = m0 + nacc;
         if (nacc == 0)
             hb.act[h] = 0;
-        else
-            atomicAdd(n_active, 1);
+        else  // the hub's chunks go to the next pass's queue
+            qb_s = atomicAdd(qnext_len, hb.ce[h] - hb.cb[h]);
     }
     __syncthreads();
+    if (nacc > 0)
+        for (int i = threadIdx.x; i < hb.ce[h] - hb.cb[h]; i += SEL_T)
+            qnext[qb_s + i] = hb.cb[h] + i;
+    __syncthreads();
     }
+}
+
+__global__ void k_iota(int32_t *__restrict__ q, int n)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += gridDim.x * blockDim.x)
+        q[i] = i;
 }
 
 // ----------------------------------------------------------- partition ---
@@ -940,9 +1020,13 @@ static void build_impl(fnn_tree *T, const void *points, Scratch &S)
     const int maxch = (int)cdiv(n, CH) + n / 2 + 2;  // chunks over all hubs
     int32_t *ch_hub = S.get<int32_t>(maxch), *ch_s = S.get<int32_t>(maxch),
             *ch_e = S.get<int32_t>(maxch), *ch_k = S.get<int32_t>(maxch);
-    float *cb_D = S.get<float>(maxch);
-    int32_t *cb_id = S.get<int32_t>(maxch);
-    int32_t *n_active = S.get<int32_t>(1);
+    float *cb_D = S.get<float>((size_t)maxch * CAND_R);
+    int32_t *cb_id = S.get<int32_t>((size_t)maxch * CAND_R);
+    int32_t *qa = S.get<int32_t>(maxch), *qb = S.get<int32_t>(maxch);
+    int32_t *qlen = S.get<int32_t>(2);
+    // net-selection passes per graph replay (even: the live queue returns
+    // to qa); 1 = one eager pass per host check
+    const int GP = T->opt.graph_passes <= 1 ? 1 : (T->opt.graph_passes + 1) / 2 * 2;
 
     auto alloc_hubs = [&](int cnt_) {
         Hubs hb;
@@ -1061,17 +1145,42 @@ static void build_impl(fnn_tree *T, const void *points, Scratch &S)
                    ch_e, ch_k, NC, L, hpos);
 
         // ---- net selection passes ----------------------------------------
-        for (;;) {
-            ++passes;
-            fill(n_active, 0, 1, st);
-            FNN_LAUNCH((k_update<M>), dim3(grid_for(NC, 1)), dim3(CH), 0, st, P,
-                               ch_hub, ch_s, ch_e, NC, hubs, cent, perm, D, L, tab,
-                               cb_D, cb_id, cnt);
-            FNN_LAUNCH((k_select<M>), dim3(grid_for(H, 1)), dim3(SEL_T), 0, st, P,
-                               hubs, H, cent, cb_D, cb_id, tab, T->opt.kmax,
-                               n_active, cnt);
-            if (read_scalar(n_active, st) == 0)
-                break;
+        // Pass p: k_update over the queue of active chunks, k_select writes
+        // the next queue.  Once every hub is done both kernels do nothing,
+        // so passes can run ahead of the host: G passes are recorded into a
+        // graph once per level and replayed until the queue is empty.
+        FNN_LAUNCH(k_iota, dim3(grid_for(NC, 256)), dim3(256), 0, st, qa, NC);
+        fill(qlen, NC, 1, st);
+        const unsigned gu = grid_for(NC, 1) < 16384u ? grid_for(NC, 1) : 16384u;
+        auto pass = [&](hipStream_t s, int k) {
+            int32_t *qc = k ? qb : qa, *qx = k ? qa : qb;
+            fill(qlen + (1 - k), 0, 1, s);
+            FNN_LAUNCH((k_update<M>), dim3(gu), dim3(CH), 0, s, P, ch_hub, ch_s,
+                       ch_e, qc, qlen + k, hubs, cent, perm, D, L, tab, cb_D,
+                       cb_id, T->opt.kmax, cnt);
+            FNN_LAUNCH((k_select<M>), dim3(grid_for(H, 1)), dim3(SEL_T), 0, s, P,
+                       hubs, H, cent, cb_D, cb_id, tab, T->opt.kmax, qx,
+                       qlen + (1 - k), cnt);
+        };
+        if (GP <= 1) {
+            for (int k = 0;; k ^= 1) {
+                pass(st, k);
+                ++passes;
+                if (read_scalar(qlen + (1 - k), st) == 0)
+                    break;
+            }
+        } else {
+            GraphRun gr;
+            gr.begin();
+            for (int k = 0; k < GP; ++k)
+                pass(gr.cs, k & 1);
+            gr.end();
+            for (;;) {
+                gr.launch(st);
+                passes += GP;
+                if (read_scalar(qlen, st) == 0)
+                    break;
+            }
         }
 
         // ---- partition into children ---------------------------------------

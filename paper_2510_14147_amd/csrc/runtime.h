@@ -35,6 +35,24 @@ struct Error {
 
 hipStream_t current_stream();
 
+// A launch sequence recorded once (begin(); launches on `cs`; end()) and
+// replayed on any stream.  Recorded sequences hold only kernel launches:
+// clears are fill kernels, never memset nodes.
+hipStream_t capture_stream();
+struct GraphRun {
+    hipStream_t cs = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    bool capturing = false;
+    GraphRun() = default;
+    GraphRun(const GraphRun &) = delete;
+    GraphRun &operator=(const GraphRun &) = delete;
+    ~GraphRun();
+    void begin();
+    void end();
+    void launch(hipStream_t s);
+};
+
 // Stream-ordered scratch allocations released (stream-ordered) on scope
 // exit.  Backed by the device's default memory pool, whose release
 // threshold is raised once so freed blocks are reused.

@@ -29,6 +29,58 @@ thread_local hipStream_t g_stream = nullptr;
 
 hipStream_t current_stream() { return g_stream; }
 
+// One non-blocking stream per device on which launch sequences are recorded
+// into graphs (recording never runs them; the caller's stream, which may be
+// the null stream, runs the instantiated graph).  Default priority.
+static std::mutex g_cap_mu;
+static hipStream_t g_cap_stream[64] = {nullptr};
+
+hipStream_t capture_stream()
+{
+    int dev = 0;
+    FNN_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64)
+        fail(-4, "device id %d", dev);
+    std::lock_guard<std::mutex> lk(g_cap_mu);
+    if (!g_cap_stream[dev])
+        FNN_HIP(hipStreamCreateWithFlags(&g_cap_stream[dev], hipStreamNonBlocking));
+    return g_cap_stream[dev];
+}
+
+GraphRun::~GraphRun()
+{
+    if (capturing) {  // an error left the recording open: close and drop it
+        hipGraph_t g = nullptr;
+        (void)hipStreamEndCapture(cs, &g);
+        if (g)
+            (void)hipGraphDestroy(g);
+    }
+    if (exec)
+        (void)hipGraphExecDestroy(exec);
+    if (graph)
+        (void)hipGraphDestroy(graph);
+}
+
+void GraphRun::begin()
+{
+    cs = capture_stream();
+    FNN_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    capturing = true;
+}
+
+void GraphRun::end()
+{
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(cs, &g);
+    capturing = false;
+    if (e != hipSuccess || !g)
+        fail(-3, "graph capture failed: %s", hipGetErrorString(e));
+    graph = g;
+    FNN_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+}
+
+void GraphRun::launch(hipStream_t s) { FNN_HIP(hipGraphLaunch(exec, s)); }
+
 static std::once_flag g_pool_once[64];
 
 static void ensure_pool()

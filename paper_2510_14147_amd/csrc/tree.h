@@ -22,9 +22,10 @@ struct Options {
     int precision = FNN_PREC_FP32;
     int sched = FNN_SCHED_TWO_PASS;
     int validate = 0;
-    int kmax = 32;
+    int kmax = 64;
     int trace = 0;
     int slack_pct = 30;
+    int graph_passes = 4;
 };
 
 Options read_options(const fnn_options *o);

@@ -85,8 +85,27 @@ def test_argument_errors_without_gpu(lib):
     assert lib.fnn_set_allocator(vp(1), None, None) == -1
 
 
+def _header_fields(struct):
+    import re
+    h = open(os.path.join(ROOT, "include", "fnn.h")).read()
+    body = h[h.index("typedef struct %s {" % struct):]
+    body = body[:body.index("}")]
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    names = []
+    for decl in body.split("{", 1)[1].split(";"):
+        decl = decl.strip()
+        if not decl:
+            continue
+        for part in decl.split(","):
+            nm = re.findall(r"(\w+)\s*(?:\[\d+\])?\s*$", part.strip())
+            names.append(nm[0])
+    return names
+
+
 def test_options_struct_matches_header():
     from paper_2510_14147_amd import fnn_options, fnn_stats, fnn_csr
+    assert [f[0] for f in fnn_options._fields_] == _header_fields("fnn_options")
+    assert [f[0] for f in fnn_stats._fields_] == _header_fields("fnn_stats")
     assert ctypes.sizeof(fnn_options) == 16 * 4
     assert ctypes.sizeof(fnn_csr) == 8 + 8 + 8 + 3 * 8
     assert ctypes.sizeof(fnn_stats) == 17 * 8 + 11 * 8 + 5 * 8
