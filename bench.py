@@ -168,6 +168,9 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=1500)
     ap.add_argument("--c5-clouds", type=int, default=0,
                     help="use only the first K clouds of c5 (0: all 256)")
+    ap.add_argument("--tune", action="store_true",
+                    help="autotune every batch first (untimed) and run the "
+                         "tuned options")
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -215,16 +218,36 @@ def main():
           f"jobs={len(jobs)}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
 
+    # options per job: defaults with --precision / --sched, or tuned
+    opts, tuning = [], []
+    for xd, off, m, e, d, p in jobs:
+        o = {"precision": p, "sched": args.sched}
+        if args.tune:
+            t0 = time.perf_counter()
+            o2 = off if off is not None else np.array([0, xd.shape[0]], np.int64)
+            r = fnn.fnn_autotune(xd, o2, m, e, reps=2)
+            o = {k: v for k, v in r["best"].items()
+                 if k in ("zeta", "kmax", "precision", "sched")}
+            tuning.append({"dim": d, "best": o, "best_ms": r["best_ms"],
+                           "base_ms": r["base_ms"], "candidates": r["ncand"],
+                           "tune_s": time.perf_counter() - t0})
+            print(f"[bench] tuned dim={d}: {tuning[-1]}", file=sys.stderr, flush=True)
+        opts.append(o)
+    BUILD_KEYS = ("zeta", "kmax")
+
     def step():
         res = []
-        for xd, off, m, e, d, p in jobs:
+        for (xd, off, m, e, d, _), o in zip(jobs, opts):
+            bo = {k: v for k, v in o.items() if k in BUILD_KEYS}
             if off is None:
-                tree = fnn.fnn_tree_build(xd, m)
-                g = fnn.fnn_eps_graph(tree, e, precision=p, sched=args.sched)
+                tree = fnn.fnn_tree_build(xd, m, **bo)
+                g = fnn.fnn_eps_graph(tree, e, precision=o["precision"],
+                                      sched=o["sched"])
             else:
-                tree = fnn.fnn_tree_build_batch(xd, off, m)
-                g = fnn.fnn_eps_graph_batch(tree, e, precision=p, sched=args.sched)
-            res.append((tree.stats, g.stats, g.nnz, d, p))
+                tree = fnn.fnn_tree_build_batch(xd, off, m, **bo)
+                g = fnn.fnn_eps_graph_batch(tree, e, precision=o["precision"],
+                                            sched=o["sched"])
+            res.append((tree.stats, g.stats, g.nnz, d, o["precision"]))
             del tree, g
         return res
 
@@ -268,7 +291,8 @@ def main():
         "config": {"workload": desc, "n": int(n_all),
                    "dim": None if groups else jobs[0][4], "metric": metric,
                    "eps": None if groups else eps, "precision": "+".join(precs),
-                   "sched": args.sched, "nnz": int(nnz),
+                   "sched": "+".join(sorted({o["sched"] for o in opts})),
+                   "nnz": int(nnz),
                    "mean_neighbors": nnz / n_all, "calls": len(jobs)},
         "dist_evals_per_s": evals / (ms / 1e3),
         "phases_ms": {"build": agg("build_ms", 0), "traverse": agg("traverse_ms", 1),
@@ -283,6 +307,8 @@ def main():
                      "netsel_passes": agg("netsel_passes", 0)},
         "roofline": roof,
     }
+    if tuning:
+        out["tuned"] = tuning
     if not args.no_cpu:
         if groups:
             out["cpu_baseline"] = cpu_baseline_c5(groups, args.cpu_rows)

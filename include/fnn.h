@@ -184,6 +184,33 @@ int fnn_eps_graph_batch(const fnn_tree *tree, const double *eps,
                         int32_t nclouds, const fnn_options *opt,
                         fnn_csr **out);
 
+/* ---- autotuner ------------------------------------------------------------
+ * Times the whole path (build + query, wall clock, median of `reps` runs
+ * after one untimed run) under candidate options on the caller's input and
+ * returns the fastest.  Candidates differ only in options that never change
+ * the graph: filter precision (FP32 / BF16 for vector metrics with
+ * dim <= 128), schedule (two-pass / learned, when a cost model is
+ * installed), zeta in {32, 64, 128} and kmax in {32, 64, 128}, searched by
+ * coordinate descent from `base` (NULL: defaults; its trace and validate
+ * are ignored).  points / offsets / nclouds / dim / metric / eps as in
+ * fnn_tree_build_batch and fnn_eps_graph_batch (one cloud: offsets =
+ * {0, n}).  Answers are cached in-process per (metric, dim, log2 n,
+ * log2 nclouds, base zeta / kmax / precision / sched); a cached answer is
+ * returned at once with cached = 1.  fnn_autotune_clear empties the cache. */
+typedef struct fnn_tune_result {
+    fnn_options best;     /* fastest options found                           */
+    double best_ms;       /* their median build + query time                 */
+    double base_ms;       /* the base options' median time                   */
+    int32_t ncand;        /* option sets timed                               */
+    int32_t cached;       /* 1: answer from the cache, nothing was timed     */
+    double reserved[4];
+} fnn_tune_result;
+
+int fnn_autotune(const void *points, const int64_t *offsets, int32_t nclouds,
+                 int32_t dim, fnn_metric metric, const double *eps,
+                 const fnn_options *base, int32_t reps, fnn_tune_result *out);
+void fnn_autotune_clear(void);
+
 /* Release a fnn_tree* or fnn_csr* (NULL is ignored). */
 void fnn_free(void *handle);
 

@@ -45,6 +45,12 @@ class fnn_options(ctypes.Structure):
                 ("reserved", ctypes.c_int32 * 6)]
 
 
+class fnn_tune_result(ctypes.Structure):
+    _fields_ = [("best", fnn_options), ("best_ms", ctypes.c_double),
+                ("base_ms", ctypes.c_double), ("ncand", ctypes.c_int32),
+                ("cached", ctypes.c_int32), ("reserved", ctypes.c_double * 4)]
+
+
 class fnn_csr(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_uint32), ("pad_", ctypes.c_uint32),
                 ("n", ctypes.c_int64), ("nnz", ctypes.c_int64),
@@ -128,6 +134,12 @@ def lib():
         L.fnn_eps_graph_batch.argtypes = [vp, ctypes.POINTER(ctypes.c_double), i32,
                                           ctypes.POINTER(fnn_options),
                                           ctypes.POINTER(ctypes.POINTER(fnn_csr))]
+        L.fnn_autotune.argtypes = [vp, ctypes.POINTER(i64), i32, i32, ctypes.c_int,
+                                   ctypes.POINTER(ctypes.c_double),
+                                   ctypes.POINTER(fnn_options), i32,
+                                   ctypes.POINTER(fnn_tune_result)]
+        L.fnn_autotune_clear.argtypes = []
+        L.fnn_autotune_clear.restype = None
         L.fnn_free.argtypes = [vp]
         L.fnn_free.restype = None
         L.fnn_get_stats.argtypes = [vp, ctypes.POINTER(fnn_stats)]
@@ -307,6 +319,43 @@ def fnn_eps_graph_batch(tree: Tree, eps, precision="fp32", sched="two_pass",
         tree.handle, e.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), e.size,
         ctypes.byref(o), ctypes.byref(out)))
     return Graph(out)
+
+
+_OPT_KEYS = ("zeta", "pack", "precision", "sched", "kmax", "graph_passes")
+
+
+def fnn_autotune(points, offsets, metric: str, eps, reps: int = 2, **base) -> dict:
+    """Fastest options for this input (see fnn_autotune in fnn.h).  A single
+    cloud is offsets = [0, n].  Returns the options as keyword arguments of
+    the build / query calls, with the timings."""
+    # the learned schedule is a candidate when the shipped cost model exists
+    if not _model_set and os.path.exists(COST_MODEL_PATH):
+        fnn_set_cost_model(load_cost_model())
+    m = METRICS[metric]
+    t, dim = _as_device_points(points, metric)
+    off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+    e = np.ascontiguousarray(np.atleast_1d(np.asarray(eps, dtype=np.float64)))
+    if off.size - 1 != e.size or int(off[-1]) != t.shape[0]:
+        raise ValueError("offsets / eps do not match the points")
+    _bind_stream()
+    o = _options(**base)
+    r = fnn_tune_result()
+    _check(lib().fnn_autotune(
+        ctypes.c_void_p(t.data_ptr()),
+        off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), off.size - 1, dim, m,
+        e.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(o),
+        int(reps), ctypes.byref(r)))
+    inv_p = {v: k for k, v in PRECISIONS.items()}
+    inv_s = {v: k for k, v in SCHEDS.items()}
+    best = {k: getattr(r.best, k) for k in _OPT_KEYS}
+    best["precision"] = inv_p[best["precision"]]
+    best["sched"] = inv_s[best["sched"]]
+    return {"best": best, "best_ms": r.best_ms, "base_ms": r.base_ms,
+            "ncand": r.ncand, "cached": bool(r.cached)}
+
+
+def fnn_autotune_clear() -> None:
+    lib().fnn_autotune_clear()
 
 
 MLP_NPARAMS, MLP_NFEAT = 5378, 16

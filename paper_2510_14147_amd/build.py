@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libfnn.so")
-SOURCES = ["runtime.hip", "build.hip", "query.hip", "gram.hip", "learn.hip",
+SOURCES = ["runtime.hip", "build.hip", "query.hip", "gram.hip", "learn.hip", "tune.hip",
            "api.hip"]
 
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -50,6 +50,8 @@ static int set_err(int code, const std::string &m)
     return code;
 }
 
+int api_error(int code, const char *msg) { return set_err(code, msg); }
+
 Options read_options(const fnn_options *o)
 {
     Options r;

@@ -167,6 +167,34 @@ __device__ inline int lev_dispatch(const uint64_t *peq, int m,
     }
 }
 
+// The squared difference accumulated in index order (one running sum), the order of
+// the leaf tiles: an edge's FP32 distance then has the same bits whichever
+// kernel decided it.
+__device__ __forceinline__ float sqdiff_seq(const float *__restrict__ a,
+                                            const float *__restrict__ b, int dp)
+{
+    float s = 0.f;
+    for (int k = 0; k < dp; k += 4) {
+        float4 u = *reinterpret_cast<const float4 *>(a + k);
+        float4 v = *reinterpret_cast<const float4 *>(b + k);
+        float d0 = u.x - v.x, d1 = u.y - v.y, d2 = u.z - v.z, d3 = u.w - v.w;
+        s = fmaf(d0, d0, s);
+        s = fmaf(d1, d1, s);
+        s = fmaf(d2, d2, s);
+        s = fmaf(d3, d3, s);
+    }
+    return s;
+}
+
+template <int M>
+__device__ __forceinline__ float key32_seq(const Pts &P, int i, int j)
+{
+    if constexpr (M == M_L2)
+        return sqdiff_seq(P.x + (size_t)i * P.dp, P.x + (size_t)j * P.dp, P.dp);
+    else
+        return sqdiff_seq(P.xn + (size_t)i * P.dp, P.xn + (size_t)j * P.dp, P.dp);
+}
+
 // FP32 key between rows i and j of P.
 template <int M>
 __device__ __forceinline__ float key32(const Pts &P, int i, int j)

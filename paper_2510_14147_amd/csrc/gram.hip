@@ -449,7 +449,7 @@ k_survive(Pts P, GramArgs G, long long ns, int2 *__restrict__ edges,
             const bool passed = (e.y >> 31) & 1;
             npass += passed;
             const Thr E = G.pcl ? G.ct[G.pcl[pi]].E : G.E;
-            const float k = key32<M>(P, pi, pj);
+            const float k = key32_seq<M>(P, pi, pj);
             if (k < E.lo) {
                 edge = true;
             } else if (k > E.hi) {

@@ -81,6 +81,13 @@ def test_argument_errors_without_gpu(lib):
                                         ctypes.c_int32, vp, ctypes.POINTER(vp)]
     e2 = (ctypes.c_double * 2)(1.0, 2.0)
     assert lib.fnn_eps_graph_batch(None, e2, 2, None, ctypes.byref(out)) == -1
+    lib.fnn_autotune.argtypes = [vp, i64p, ctypes.c_int32, ctypes.c_int32,
+                                 ctypes.c_int, ctypes.POINTER(ctypes.c_double), vp,
+                                 ctypes.c_int32, vp]
+    res = ctypes.create_string_buffer(256)
+    assert lib.fnn_autotune(vp(16), None, 1, 4, 0, e2, None, 1, res) == -1
+    assert lib.fnn_autotune(vp(16), offs(3, 9), 1, 4, 0, e2, None, 1, res) == -1
+    assert b"offsets" in lib.fnn_last_error()
     lib.fnn_set_allocator.argtypes = [vp, vp, vp]
     assert lib.fnn_set_allocator(vp(1), None, None) == -1
 
@@ -107,5 +114,8 @@ def test_options_struct_matches_header():
     assert [f[0] for f in fnn_options._fields_] == _header_fields("fnn_options")
     assert [f[0] for f in fnn_stats._fields_] == _header_fields("fnn_stats")
     assert ctypes.sizeof(fnn_options) == 16 * 4
+    from paper_2510_14147_amd import fnn_tune_result
+    assert [f[0] for f in fnn_tune_result._fields_] == _header_fields("fnn_tune_result")
+    assert ctypes.sizeof(fnn_tune_result) == 64 + 8 + 8 + 4 + 4 + 4 * 8
     assert ctypes.sizeof(fnn_csr) == 8 + 8 + 8 + 3 * 8
     assert ctypes.sizeof(fnn_stats) == 17 * 8 + 11 * 8 + 5 * 8
