@@ -128,7 +128,25 @@ def cpu_baseline(x, metric, eps, rows: int, seed: int = 7):
                       f"pair evals/s {sample.size * x.shape[0] / dt:.3e}"}
 
 
-def roofline(dim, precision, tq):
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` on `workload` from the committed
+    rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE measurement (scaled by the
+    copy-kernel factors recorded with it), or None when there is none or the
+    kernel's source has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path)).get(f"{kernel}|{workload}")
+    if not rec:
+        return None
+    src = os.path.join(ROOT, rec["source"])
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["source_sha256"]:
+        return None
+    return rec["bytes_per_launch"]
+
+
+def roofline(dim, precision, tq, workload=""):
     """Roofline of the dominant kernel of one query: the leaf-tile count pass
     (plain FP32: 3*d flops per pair -- difference, square, accumulate) or the
     MFMA Gram filter (2*k flops per screened pair, k = padded dim), timed with
@@ -136,19 +154,24 @@ def roofline(dim, precision, tq):
     if tq["count_ms"] <= 0:
         return None
     if precision != "fp32":
+        # the MFMA filter kernel alone, event-timed inside the library
         kq = -(-dim // 16) * 16 if precision == "bf16" else -(-dim // 64) * 64
         flops = 2.0 * kq * tq["filter_pairs"]
-        ach = flops / (tq["count_ms"] / 1e3) / 1e12
+        kms = tq["filter_ms"] if tq.get("filter_ms", 0) > 0 else tq["count_ms"]
+        ach = flops / (kms / 1e3) / 1e12
         peak = PEAK_BF16_TFLOPS if precision == "bf16" else PEAK_FP8_TFLOPS
+        kname = f"k_gram<L2,{precision}>"
         return {"bound": "mfma", "achieved": round(ach, 3), "peak": peak,
-                "unit": "TFLOP/s", "frac": round(ach / peak, 4), "traffic": None,
-                "kernel": f"k_gram<L2,{precision}>+k_survive",
-                "kernel_ms": round(tq["count_ms"], 3), "flops_per_launch": flops}
+                "unit": "TFLOP/s", "frac": round(ach / peak, 4),
+                "traffic": measured_traffic(kname, workload),
+                "kernel": kname, "kernel_ms": round(kms, 3),
+                "flops_per_launch": flops}
     flops = 3.0 * dim * tq["tile_pairs"]
     ach = flops / (tq["count_ms"] / 1e3) / 1e12
     return {"bound": "alu", "achieved": round(ach, 3),
             "peak": PEAK_FP32_VEC_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(ach / PEAK_FP32_VEC_TFLOPS, 4), "traffic": None,
+            "frac": round(ach / PEAK_FP32_VEC_TFLOPS, 4),
+            "traffic": measured_traffic("k_tile<L2,count>", workload),
             "kernel": "k_tile<L2,count>", "kernel_ms": round(tq["count_ms"], 3),
             "flops_per_launch": flops}
 
@@ -161,7 +184,7 @@ def main():
     ap.add_argument("--workload", default="c2a",
                     help="c2a c2b c2_50k c1 c3 c4 ang | c5 (many clouds, one "
                          "batch per dim) | c5_loop (one call per cloud)")
-    ap.add_argument("--precision", default="fp32",
+    ap.add_argument("--precision", default="bf16",
                     help="fp32 | bf16 | fp8 | auto (c5: fp32 below dim 16, "
                          "else bf16)")
     ap.add_argument("--sched", default="two_pass")
@@ -172,6 +195,8 @@ def main():
                     help="autotune every batch first (untimed) and run the "
                          "tuned options")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="skip the plain FP32 comparison step")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the epsilon-graph path has no "
@@ -278,7 +303,7 @@ def main():
     value = nnz / (ms / 1e3)
     # dominant kernel: that of the job with the longest count pass
     dom = max(last, key=lambda x: x[1]["count_ms"])
-    roof = roofline(dom[3], dom[4], dom[1]) if metric in ("l2", "angular") else None
+    roof = roofline(dom[3], dom[4], dom[1], desc) if metric in ("l2", "angular") else None
     if roof is not None and len(last) > 1:
         roof["job"] = f"dim {dom[3]}, {dom[4]}"
     precs = sorted({x[4] for x in last})
@@ -309,6 +334,31 @@ def main():
     }
     if tuning:
         out["tuned"] = tuning
+    out["dtype"] = {"fp32": "f32", "bf16": "bf16 filter + f32", "fp8": "fp8 filter + f32"}.get(
+        "+".join(precs), "+".join(precs))
+    if not args.no_plain and any(o["precision"] != "fp32" for o in opts):
+        # one step of the same workload on the plain FP32 tiles, for the
+        # MFMA-vs-plain ratio (the edge counts must agree)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pnnz = 0
+        for (xd, off, m, e, d, _), o in zip(jobs, opts):
+            bo = {k: v for k, v in o.items() if k in BUILD_KEYS}
+            if off is None:
+                tree = fnn.fnn_tree_build(xd, m, **bo)
+                g = fnn.fnn_eps_graph(tree, e, precision="fp32", sched=o["sched"])
+            else:
+                tree = fnn.fnn_tree_build_batch(xd, off, m, **bo)
+                g = fnn.fnn_eps_graph_batch(tree, e, precision="fp32", sched=o["sched"])
+            pnnz += g.nnz
+            del tree, g
+        torch.cuda.synchronize()
+        pms = 1e3 * (time.perf_counter() - t0)
+        if pnnz != nnz:
+            raise SystemExit(f"plain FP32 and MFMA paths disagree: {pnnz} vs {nnz} edges")
+        out["plain_fp32"] = {"ms_per_step": pms, "value": nnz / (pms / 1e3),
+                             "speedup_of_value": pms / ms}
+        print(f"[bench] plain fp32 step: {pms:.1f} ms", file=sys.stderr, flush=True)
     if not args.no_cpu:
         if groups:
             out["cpu_baseline"] = cpu_baseline_c5(groups, args.cpu_rows)

@@ -136,7 +136,8 @@ typedef struct fnn_stats {
            sort_ms, total_ms;
     double pred_mae;          /* learned: mean |predicted - true| log1p(deg) */
     double pred_sum_ratio;    /* learned: sum predicted / sum true degrees    */
-    double reserved[5];
+    double filter_ms;         /* MFMA filter kernel alone (last launch)       */
+    double reserved[4];
 } fnn_stats;
 
 /* Build the cover tree of n points (Algorithms 1-2).  points: device

@@ -65,13 +65,13 @@ _STAT_I64 = ["n", "nodes", "leaf_blocks", "packs", "rounds", "netsel_passes",
              "spilled"]
 _STAT_F64 = ["max_rel_err", "build_ms", "traverse_ms", "tile_ms", "count_ms",
              "scan_ms", "fill_ms", "sort_ms", "total_ms", "pred_mae",
-             "pred_sum_ratio"]
+             "pred_sum_ratio", "filter_ms"]
 
 
 class fnn_stats(ctypes.Structure):
     _fields_ = ([(k, ctypes.c_int64) for k in _STAT_I64] +
                 [(k, ctypes.c_double) for k in _STAT_F64] +
-                [("reserved", ctypes.c_double * 5)])
+                [("reserved", ctypes.c_double * 4)])
 
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)

@@ -7,7 +7,12 @@
 // FP32 accumulation and the rounding of the norms; all of it is below
 // c1 * (|x|^2 + |y|^2).  A pair is rejected only if
 //     (1 - c1)(|x|^2 + |y|^2) - 2 g~ > eps^2,
-// which implies d^2 > eps^2: the filter never drops an edge.  A surviving
+// which implies d^2 > eps^2: the filter never drops an edge.  On the GPU the
+// test reads g~ - ax < ay with ax = ((1 - c1)|x|^2 - eps^2') / 2 and
+// ay = (1 - c1)|y|^2 / 2; the accumulators start at -ax, so the matrix
+// cores produce g~ - ax directly (the FP32 accumulation then runs over
+// kq + 1 terms, which the FP32 part of c1 and the enlargement of eps^2'
+// cover), and a wave compares the largest value of each lane with its ay.  A surviving
 // pair is recomputed by direct FP32 difference and decided exactly like the
 // plain tiles (rounding band -> FP64 reference predicate).
 //
@@ -110,16 +115,36 @@ __global__ void k_route(const int2 *__restrict__ inter, long long ninter,
                         unsigned long long *__restrict__ cnt,
                         int2 *__restrict__ rest)
 {
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-         i < ninter; i += (long long)gridDim.x * blockDim.x) {
-        int2 p = inter[i];
-        int a = min(p.x, p.y), b = max(p.x, p.y);
-        const bool big = (q_pe[a] - q_pb[a] > pack) || (q_pe[b] - q_pb[b] > pack);
-        if (big) {
-            unsigned long long o = atomicAdd(&cnt[1], 1ull);
-            rest[o] = make_int2(a, b);
-        } else {
-            unsigned long long o = atomicAdd(&cnt[0], 1ull);
+    // one reservation per wave and destination (whole waves iterate, so the
+    // ballots see every lane)
+    const int lane = threadIdx.x & (WAVE - 1);
+    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    const long long lim = (ninter + WAVE - 1) / WAVE * WAVE;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < lim;
+         i += (long long)gridDim.x * blockDim.x) {
+        const bool valid = i < ninter;
+        int a = 0, b = 0;
+        bool big = false;
+        if (valid) {
+            const int2 p = inter[i];
+            a = min(p.x, p.y);
+            b = max(p.x, p.y);
+            big = (q_pe[a] - q_pb[a] > pack) || (q_pe[b] - q_pb[b] > pack);
+        }
+        const uint64_t mb = __ballot(valid && big), ms = __ballot(valid && !big);
+        unsigned long long ob = 0, os = 0;
+        if (lane == 0) {
+            if (mb)
+                ob = atomicAdd(&cnt[1], (unsigned long long)__popcll(mb));
+            if (ms)
+                os = atomicAdd(&cnt[0], (unsigned long long)__popcll(ms));
+        }
+        ob = __shfl(ob, 0, WAVE);
+        os = __shfl(os, 0, WAVE);
+        if (valid && big) {
+            rest[ob + __popcll(mb & lt)] = make_int2(a, b);
+        } else if (valid) {
+            const unsigned long long o = os + __popcll(ms & lt);
             key[o] = (uint32_t)(b - nn);
             val[o] = (uint32_t)((a - nn) >> 2);
         }
@@ -197,7 +222,7 @@ struct GramCfg<FNN_PREC_FP8> {
 };
 
 template <int M, int PREC, int NKS>
-__global__ void __launch_bounds__(GT)
+__global__ void __launch_bounds__(GT, 2)
 k_gram(Pts P, GramArgs G, TileOut out)
 {
     using C = GramCfg<PREC>;
@@ -214,6 +239,8 @@ k_gram(Pts P, GramArgs G, TileOut out)
 
     const int t = threadIdx.x, lane = t & (WAVE - 1), w = t / WAVE;
     const int l32 = lane & 31, hi = lane >> 5;
+    // products carry the FP8 scale; gscale and its inverse are powers of 2
+    const float ginv = PREC == FNN_PREC_BF16 ? 1.f : 1.f / G.gscale;
     unsigned long long npairs = 0;
     const uint64_t ltmask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
 
@@ -265,9 +292,11 @@ k_gram(Pts P, GramArgs G, TileOut out)
                 }
             }
         }
-        // row terms of the filter: ax = (hx - eps2') / 2, with this pack's
-        // cloud threshold in a batch of clouds (packs of one group may come
-        // from different clouds; pairs across clouds are skipped below)
+        // row terms of the filter, ax = (hx - eps2') / 2, per row of this
+        // wave's pack (LDS; a lane's 4 consecutive accumulator rows are one
+        // aligned float4); in a batch of clouds eps2' is this pack's cloud's (packs of one
+        // group may come from different clouds; pairs across clouds are
+        // skipped below)
         const int ca = (G.pcl && has_a) ? G.pcl[pa] : -1;
         const float e2 = ca >= 0 ? G.ct[ca].e2f : G.e2f;
         for (int r = lane; r < GP; r += WAVE)
@@ -321,9 +350,20 @@ k_gram(Pts P, GramArgs G, TileOut out)
             for (int cb = 0; cb < 2; ++cb) {
                 if (cb * 32 >= nb)
                     break;
+                // accumulators start at -ax (in the scaled units of the
+                // products), so they end at g~ - ax
                 f32x16 acc[2];
-                acc[0] = (f32x16){};
-                acc[1] = (f32x16){};
+#pragma unroll
+                for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+                    for (int q4 = 0; q4 < 4; ++q4) {
+                        const float4 a4 = *reinterpret_cast<const float4 *>(
+                            axS + w * GP + rb * 32 + 8 * q4 + 4 * hi);
+                        acc[rb][4 * q4 + 0] = -a4.x * ginv;
+                        acc[rb][4 * q4 + 1] = -a4.y * ginv;
+                        acc[rb][4 * q4 + 2] = -a4.z * ginv;
+                        acc[rb][4 * q4 + 3] = -a4.w * ginv;
+                    }
                 const unsigned char *brow = Bs + (cb * 32 + l32) * ldb;
                 #pragma unroll
                         for (int ks = 0; ks < nks; ++ks) {
@@ -354,19 +394,34 @@ k_gram(Pts P, GramArgs G, TileOut out)
                                 Areg[rb][ks], bb, acc[rb], 0, 0, 0, 127, 0, 127);
                     }
                 }
-                // ---- filter: one pass bit per accumulator ------------------
+                // ---- filter -----------------------------------------------
+                // A pair passes when g~ - ax >= ay.  Fast test per lane: the
+                // largest g~ - ax over its 32 rows against its column's ay
+                // (rows past na carry ax = FLT_MAX, columns past nb carry
+                // ay = FLT_MAX, so neither can pass).  Only when some lane
+                // may hold a survivor (rare), on a self pair, or when
+                // validating does the wave build per-pair masks.
                 const int col = cb * 32 + l32;
                 const float ay = ayS[col];
+                float mx = -FLT_MAX;
+#pragma unroll
+                for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+                    for (int q = 0; q < 16; ++q)
+                        mx = fmaxf(mx, acc[rb][q]);
+                if (PREC != FNN_PREC_BF16)
+                    mx *= G.gscale;
+                if (__any(mx >= ay) || self || G.validate) {
                 unsigned pm = 0, om = 0;
 #pragma unroll
                 for (int rb = 0; rb < 2; ++rb) {
 #pragma unroll
                     for (int q = 0; q < 16; ++q) {
                         const int row = rb * 32 + 8 * (q >> 2) + 4 * hi + (q & 3);
-                        const float ax = axS[w * GP + row];
                         const bool ok = row < na && col < nb && (!self || row < col);
-                        const float gq = PREC == FNN_PREC_BF16 ? acc[rb][q] : acc[rb][q] * G.gscale;
-                        const bool pass = ok && (gq - ay >= ax);
+                        const float gq = PREC == FNN_PREC_BF16 ? acc[rb][q]
+                                                               : acc[rb][q] * G.gscale;
+                        const bool pass = ok && (gq >= ay);
                         pm |= (unsigned)pass << (rb * 16 + q);
                         om |= (unsigned)ok << (rb * 16 + q);
                     }
@@ -399,6 +454,7 @@ k_gram(Pts P, GramArgs G, TileOut out)
                                                   (pb + col) | (int)(((pm >> bit) & 1u) << 31));
                         ++o;
                     }
+                }
                 }
                 // pairs screened by this wave in this column block
                 if (lane == 0) {
@@ -618,7 +674,7 @@ float gram_eps2(int metric, double eps, const Thr &E)
 {
     const double u32 = 1.0 / 16777216.0;
     const double T2 = metric == M_L2 ? eps * eps : 2.0 - 2.0 * E.p64;
-    return (float)(T2 * (1.0 + 64.0 * u32) + 1e-30);
+    return (float)(T2 * (1.0 + 320.0 * u32) + 1e-30);
 }
 
 // Quantised copy + per-point terms, and the MFMA work lists, for one query.
@@ -639,7 +695,7 @@ void gram_prepare(const fnn_tree *T, int prec, double eps, const Thr &E,
     // margin coefficient (see the header comment); the FP8 subnormal terms
     // are absorbed by the global scale that maps the largest |coordinate| to
     // at least 224.
-    const double c1 = 2.25 * u + (3.0 * kq + 2.0 * d + 64.0) * u32 +
+    const double c1 = 2.25 * u + (4.0 * kq + 2.0 * d + 72.0) * u32 +
                       (prec == FNN_PREC_FP8 ? 4.0 * d / 224.0 / 512.0 : 0.0);
     // mean, scale
     float *sums = S.get<float>(dp);

@@ -920,6 +920,22 @@ __global__ void k_pred_err(const float *__restrict__ pred,
 
 // -------------------------------------------------------------- driver ---
 
+// Two events around one launch (the MFMA filter's own duration).
+struct Events {
+    hipEvent_t e[2];
+    explicit Events(hipStream_t)
+    {
+        FNN_HIP(hipEventCreate(&e[0]));
+        FNN_HIP(hipEventCreate(&e[1]));
+    }
+    ~Events()
+    {
+        (void)hipEventDestroy(e[0]);
+        (void)hipEventDestroy(e[1]);
+    }
+    hipEvent_t operator[](int i) const { return e[i]; }
+};
+
 struct Timer {
     hipEvent_t e[8];
     int k = 0;
@@ -1172,6 +1188,7 @@ static void eps_graph_impl(const fnn_tree *Tc, const double *epsv,
         long long ngedges = 0;
         if (use_gram) {
             unsigned long long *ns = S.get<unsigned long long>(2);
+            Events fev(s);
             long long cap = std::max<long long>(1ll << 24, 64ll * n);
             if (learned) {
                 // predicted ordered edges / 2, times the filter's survivor
@@ -1196,13 +1213,21 @@ static void eps_graph_impl(const fnn_tree *Tc, const double *epsv,
                 G.nsurv = ns;
                 fill(ns, 0ull, 2, s);
                 fill(cnt + 2, 0ull, 1, s);
+                FNN_HIP(hipEventRecord(fev[0], s));
                 gram_launch(M, opt.precision, false, P, G, o, s);
+                FNN_HIP(hipEventRecord(fev[1], s));
                 const long long got = (long long)read_scalar(ns, s);
                 if (got <= cap || attempt > 0) {
                     if (got > cap)
                         fail(FNN_EINTERNAL, "survivor list overflow");
                     gedges = S.get<int2>(got + 1);
                     gedist = S.get<float>(got + 1);
+                    {
+                        float fms = 0.f;
+                        FNN_HIP(hipEventSynchronize(fev[1]));
+                        FNN_HIP(hipEventElapsedTime(&fms, fev[0], fev[1]));
+                        st.filter_ms = fms;
+                    }
                     survivors_launch(M, P, G, got, gedges, gedist, ns + 1, o, s);
                     ngedges = (long long)read_scalar(ns + 1, s);
                     break;
