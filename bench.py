@@ -207,6 +207,8 @@ def main():
     import paper_2510_14147_amd as fnn
 
     def prec_for(dim):
+        if dim == 0:
+            return "fp32"  # integer metrics: no filter precision to choose
         if args.precision == "auto":
             return "fp32" if dim < 16 else "bf16"
         return args.precision
@@ -336,6 +338,10 @@ def main():
         out["tuned"] = tuning
     out["dtype"] = {"fp32": "f32", "bf16": "bf16 filter + f32", "fp8": "fp8 filter + f32"}.get(
         "+".join(precs), "+".join(precs))
+    if metric == "hamming":
+        out["dtype"] = "u64 (xor + popcount)"
+    elif metric == "levenshtein":
+        out["dtype"] = "u64 (bit-parallel edit distance)"
     if not args.no_plain and any(o["precision"] != "fp32" for o in opts):
         # one step of the same workload on the plain FP32 tiles, for the
         # MFMA-vs-plain ratio (the edge counts must agree)

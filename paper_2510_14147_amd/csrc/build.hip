@@ -953,7 +953,7 @@ static void build_impl(fnn_tree *T, const void *points, Scratch &S)
         x_in = S.get<float>((size_t)n * T->dp);
         if (M == M_ANG)
             xn_in = S.get<float>((size_t)n * T->dp);
-        FNN_LAUNCH(k_ingest_vec, dim3(grid_for(n, 4)), dim3(256), 0, st,
+        FNN_LAUNCH(k_ingest_vec, dim3(grid_cap(n, 4, 16384)), dim3(256), 0, st,
                            (const float *)points, n, T->dim, T->dp,
                            M == M_ANG ? 1 : 0, x_in, xn_in, err);
         P.x = x_in;
@@ -1139,9 +1139,9 @@ static void build_impl(fnn_tree *T, const void *points, Scratch &S)
         const int NC = tot[0], NH = tot[1];
         if (NC > maxch || NH > n)
             fail(FNN_EINTERNAL, "chunk table overflow (%d > %d)", NC, maxch);
-        FNN_LAUNCH(k_make_chunks, dim3(grid_for(H, 1)), dim3(64), 0, st, hubs, H,
+        FNN_LAUNCH(k_make_chunks, dim3(grid_cap(H, 1, 8192)), dim3(64), 0, st, hubs, H,
                            choff, itemoff, ch_hub, ch_s, ch_e, ch_k);
-        FNN_LAUNCH(k_round_init, dim3(grid_for(NC, 1)), dim3(CH), 0, st, ch_s,
+        FNN_LAUNCH(k_round_init, dim3(grid_cap(NC, 1, 16384)), dim3(CH), 0, st, ch_s,
                    ch_e, ch_k, NC, L, hpos);
 
         // ---- net selection passes ----------------------------------------
@@ -1158,7 +1158,7 @@ static void build_impl(fnn_tree *T, const void *points, Scratch &S)
             FNN_LAUNCH((k_update<M>), dim3(gu), dim3(CH), 0, s, P, ch_hub, ch_s,
                        ch_e, qc, qlen + k, hubs, cent, perm, D, L, tab, cb_D,
                        cb_id, T->opt.kmax, cnt);
-            FNN_LAUNCH((k_select<M>), dim3(grid_for(H, 1)), dim3(SEL_T), 0, s, P,
+            FNN_LAUNCH((k_select<M>), dim3(grid_cap(H, 1, 4096)), dim3(SEL_T), 0, s, P,
                        hubs, H, cent, cb_D, cb_id, tab, T->opt.kmax, qx,
                        qlen + (1 - k), cnt);
         };
@@ -1188,7 +1188,7 @@ static void build_impl(fnn_tree *T, const void *points, Scratch &S)
         const int C = read_scalar(child_base + H, st);
         if (node_count + C > (int64_t)cap)
             fail(FNN_EINTERNAL, "vertex capacity exceeded");
-        FNN_LAUNCH(k_part_keys, dim3(grid_for(NC, 1)), dim3(CH), 0, st, ch_hub,
+        FNN_LAUNCH(k_part_keys, dim3(grid_cap(NC, 1, 16384)), dim3(CH), 0, st, ch_hub,
                    ch_s, ch_e, ch_k, NC, child_base, L, key, val);
         radix_sort_pairs(key, val, skey, sval, NH, bitlen((uint32_t)C), S);
         FNN_LAUNCH(k_part_gather, dim3(cdiv(NH, 256)), dim3(256), 0, st,
@@ -1197,7 +1197,7 @@ static void build_impl(fnn_tree *T, const void *points, Scratch &S)
         FNN_LAUNCH(k_part_store, dim3(cdiv(NH, 256)), dim3(256), 0, st,
                            skey, NH, hpos, tperm, tD, perm, D, cfirst, clast,
                            ckmax);
-        FNN_LAUNCH(k_children, dim3(grid_for(H, 1)), dim3(64), 0, st, hubs, H, M,
+        FNN_LAUNCH(k_children, dim3(grid_cap(H, 1, 8192)), dim3(64), 0, st, hubs, H, M,
                            T->dp, T->opt.zeta, (int)node_count, child_base, cent,
                            cfirst, clast, ckmax, nd, hubflag);
         scan_i32(hubflag, fscan, C, S);
@@ -1245,29 +1245,29 @@ static void build_impl(fnn_tree *T, const void *points, Scratch &S)
     Pts Q = P;
     if (M == M_L2 || M == M_ANG) {
         T->x = (float *)T->own(sizeof(float) * (size_t)n * T->dp);
-        FNN_LAUNCH((k_gather_rows<float>), dim3(grid_for(n, 4)), dim3(256), 0,
+        FNN_LAUNCH((k_gather_rows<float>), dim3(grid_cap(n, 4, 16384)), dim3(256), 0,
                            st, x_in, perm, n, T->dp, T->x);
         Q.x = T->x;
         if (M == M_ANG) {
             T->xn = (float *)T->own(sizeof(float) * (size_t)n * T->dp);
-            FNN_LAUNCH((k_gather_rows<float>), dim3(grid_for(n, 4)),
+            FNN_LAUNCH((k_gather_rows<float>), dim3(grid_cap(n, 4, 16384)),
                                dim3(256), 0, st, xn_in, perm, n, T->dp, T->xn);
             Q.xn = T->xn;
         }
     } else if (M == M_HAM) {
         T->h = (uint64_t *)T->own(sizeof(uint64_t) * (size_t)n * T->dp);
-        FNN_LAUNCH((k_gather_rows<uint64_t>), dim3(grid_for(n, 4)),
+        FNN_LAUNCH((k_gather_rows<uint64_t>), dim3(grid_cap(n, 4, 16384)),
                            dim3(256), 0, st, P.h, perm, n, T->dp, T->h);
         Q.h = T->h;
     } else {
         T->s = (uint8_t *)T->own((size_t)n * T->dp);
         T->len = (int32_t *)T->own(sizeof(int32_t) * n);
         T->peq = (uint64_t *)T->own(sizeof(uint64_t) * (size_t)n * T->sigma * T->W);
-        FNN_LAUNCH((k_gather_rows<uint8_t>), dim3(grid_for(n, 4)), dim3(256),
+        FNN_LAUNCH((k_gather_rows<uint8_t>), dim3(grid_cap(n, 4, 16384)), dim3(256),
                            0, st, P.s, perm, n, T->dp, T->s);
-        FNN_LAUNCH((k_gather_rows<int32_t>), dim3(grid_for(n, 4)), dim3(256),
+        FNN_LAUNCH((k_gather_rows<int32_t>), dim3(grid_cap(n, 4, 16384)), dim3(256),
                            0, st, P.len, perm, n, 1, T->len);
-        FNN_LAUNCH((k_gather_rows<uint64_t>), dim3(grid_for(n, 4)),
+        FNN_LAUNCH((k_gather_rows<uint64_t>), dim3(grid_cap(n, 4, 16384)),
                            dim3(256), 0, st, P.peq, perm, n, T->sigma * T->W,
                            T->peq);
         Q.s = T->s;

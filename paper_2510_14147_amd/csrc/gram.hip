@@ -28,6 +28,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <vector>
 
 #include <string.h>
 
@@ -148,6 +149,36 @@ __global__ void k_route(const int2 *__restrict__ inter, long long ninter,
             key[o] = (uint32_t)(b - nn);
             val[o] = (uint32_t)((a - nn) >> 2);
         }
+    }
+}
+
+// Any pack with more than `pack` points (duplicate groups)?
+__global__ void k_max_pack(const int32_t *__restrict__ pb, const int32_t *__restrict__ pe,
+                           int npk, int pack, int32_t *__restrict__ big)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < npk;
+         i += gridDim.x * blockDim.x)
+        if (pe[i] - pb[i] > pack)
+            *big = 1;
+}
+
+// Closed-form work list: entry e of group g (goff[g] <= e < goff[g+1]) pairs
+// the group with pack 4g + (e - goff[g]).
+__global__ void k_dense_list(const int64_t *__restrict__ goff, int ngr, long long mu,
+                             int32_t *__restrict__ lg, int32_t *__restrict__ lb)
+{
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < mu;
+         e += (long long)gridDim.x * blockDim.x) {
+        int lo = 0, hi = ngr - 1;  // last g with goff[g] <= e
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (goff[mid] <= e)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        lg[e] = lo;
+        lb[e] = (int32_t)(4 * lo + (e - goff[lo]));
     }
 }
 
@@ -299,8 +330,9 @@ k_gram(Pts P, GramArgs G, TileOut out)
         // skipped below)
         const int ca = (G.pcl && has_a) ? G.pcl[pa] : -1;
         const float e2 = ca >= 0 ? G.ct[ca].e2f : G.e2f;
+        // stored as the accumulators' start value -ax (scaled units)
         for (int r = lane; r < GP; r += WAVE)
-            axS[w * GP + r] = (r < na) ? 0.5f * (G.hx[pa + r] - e2) : FLT_MAX;
+            axS[w * GP + r] = (r < na) ? -0.5f * (G.hx[pa + r] - e2) * ginv : -FLT_MAX;
 
         // B tiles are software-pipelined: the rows of entry e+1 are loaded
         // into registers while entry e is on the matrix cores.
@@ -359,16 +391,24 @@ k_gram(Pts P, GramArgs G, TileOut out)
                     for (int q4 = 0; q4 < 4; ++q4) {
                         const float4 a4 = *reinterpret_cast<const float4 *>(
                             axS + w * GP + rb * 32 + 8 * q4 + 4 * hi);
-                        acc[rb][4 * q4 + 0] = -a4.x * ginv;
-                        acc[rb][4 * q4 + 1] = -a4.y * ginv;
-                        acc[rb][4 * q4 + 2] = -a4.z * ginv;
-                        acc[rb][4 * q4 + 3] = -a4.w * ginv;
+                        acc[rb][4 * q4 + 0] = a4.x;
+                        acc[rb][4 * q4 + 1] = a4.y;
+                        acc[rb][4 * q4 + 2] = a4.z;
+                        acc[rb][4 * q4 + 3] = a4.w;
                     }
                 const unsigned char *brow = Bs + (cb * 32 + l32) * ldb;
+                // this column block's B fragments, all read before the
+                // matrix-core chain (no LDS wait between k-steps)
+                int4 bfr[PREC == FNN_PREC_BF16 ? nks : 1];
+                if constexpr (PREC == FNN_PREC_BF16) {
+#pragma unroll
+                    for (int ks = 0; ks < nks; ++ks)
+                        bfr[ks] = *(const int4 *)(brow + (ks * 16 + hi * 8) * 2);
+                }
                 #pragma unroll
                         for (int ks = 0; ks < nks; ++ks) {
                     if constexpr (PREC == FNN_PREC_BF16) {
-                        const int4 bv = *(const int4 *)(brow + (ks * 16 + hi * 8) * 2);
+                        const int4 bv = bfr[ks];
                         bf16x8 bb;
                         __builtin_memcpy(&bb, &bv, 16);
                         const int slot = ks >> 1, half = ks & 1;
@@ -724,19 +764,70 @@ void gram_prepare(const fnn_tree *T, int prec, double eps, const Thr &E,
     G.q = qbuf;
     G.hx = hxbuf;
     if (prec == FNN_PREC_BF16)
-        FNN_LAUNCH((k_quant<FNN_PREC_BF16>), dim3(grid_for(n, 4)), dim3(256), 0,
+        FNN_LAUNCH((k_quant<FNN_PREC_BF16>), dim3(grid_cap(n, 4, 16384)), dim3(256), 0,
                    s, X, n, dp, kq, sums, 1.0f / n, scale, (float)(1.0 - c1), qbuf,
                    hxbuf);
     else
-        FNN_LAUNCH((k_quant<FNN_PREC_FP8>), dim3(grid_for(n, 4)), dim3(256), 0,
+        FNN_LAUNCH((k_quant<FNN_PREC_FP8>), dim3(grid_cap(n, 4, 16384)), dim3(256), 0,
                    s, X, n, dp, kq, sums, 1.0f / n, scale, (float)(1.0 - c1), qbuf,
                    hxbuf);
     G.e2f = gram_eps2(T->metric, eps, E);
     G.E = E;
 
-    // ---- lists: canonical pairs, routed, unique per (group, B) ----------
     const int nn = (int)T->nnodes;
     const int npk = (int)T->npacks;
+    const int RUN = 64;  // work unit: at most RUN list entries of one group
+
+    // ---- near-complete interaction lists: closed-form work list ----------
+    // When the traversal kept (almost) every pack pair and no pack is larger
+    // than GP, the work list is every (group g, B >= 4g) pair; the few pairs
+    // the traversal pruned are evaluated too, which changes no edge.
+    {
+        const int ngr = (npk + 3) / 4;
+        const long long allp = (long long)npk * (npk + 1) / 2;
+        long long mu = 0;
+        for (int g = 0; g < ngr; ++g)
+            mu += npk - 4 * g;
+        if (npk > 0 && (double)ninter >= 0.95 * (double)allp && mu < INT32_MAX) {
+            int32_t *big = S.get<int32_t>(1);
+            fill(big, 0, 1, s);
+            FNN_LAUNCH(k_max_pack, dim3(grid_for(npk, 256)), dim3(256), 0, s,
+                       T->q_pt_begin + nn, T->q_pt_end + nn, npk, GP, big);
+            if (read_scalar(big, s) == 0) {
+                std::vector<int64_t> goff(ngr + 1);
+                std::vector<int32_t> ub;
+                goff[0] = 0;
+                for (int g = 0; g < ngr; ++g) {
+                    goff[g + 1] = goff[g] + (npk - 4 * g);
+                    for (int64_t e = goff[g]; e < goff[g + 1]; e += RUN)
+                        ub.push_back((int32_t)e);
+                }
+                ub.push_back((int32_t)mu);
+                int64_t *goff_d = S.get<int64_t>(ngr + 1);
+                int32_t *lg = S.get<int32_t>(mu + 1), *lb = S.get<int32_t>(mu + 1);
+                int32_t *ubeg = S.get<int32_t>(ub.size());
+                FNN_HIP(hipMemcpyAsync(goff_d, goff.data(), sizeof(int64_t) * (ngr + 1),
+                                       hipMemcpyHostToDevice, s));
+                FNN_HIP(hipMemcpyAsync(ubeg, ub.data(), sizeof(int32_t) * ub.size(),
+                                       hipMemcpyHostToDevice, s));
+                FNN_LAUNCH(k_dense_list, dim3(grid_for(mu, 256)), dim3(256), 0, s,
+                           goff_d, ngr, mu, lg, lb);
+                FNN_HIP(hipStreamSynchronize(s));  // host vectors go out of scope
+                *rest = nullptr;
+                *nrest = 0;
+                G.nn = nn;
+                G.npacks = npk;
+                G.lg = lg;
+                G.lb = lb;
+                G.ubeg = ubeg;
+                G.nunits = (int)ub.size() - 1;
+                G.nlist = (int)mu;
+                return;
+            }
+        }
+    }
+
+    // ---- lists: canonical pairs, routed, unique per (group, B) ----------
     uint32_t *k1 = S.get<uint32_t>(ninter + 1), *v1 = S.get<uint32_t>(ninter + 1);
     int2 *rs = S.get<int2>(ninter + 1);
     unsigned long long *cnt = S.get<unsigned long long>(2);
@@ -779,7 +870,6 @@ void gram_prepare(const fnn_tree *T, int prec, double eps, const Thr &E,
     FNN_LAUNCH(k_uniq_write, dim3(grid_for(m, 256)), dim3(256), 0, s, gk, bv, m,
                flag, pos, lg, lb);
     // units of at most RUN entries of one group
-    const int RUN = 64;
     int32_t *uf = S.get<int32_t>(mu + 1), *up = S.get<int32_t>(mu + 2);
     int32_t *gfirst = S.get<int32_t>(npk / 4 + 2);
     FNN_LAUNCH(k_group_first, dim3(grid_for(mu, 256)), dim3(256), 0, s, lg, mu,

@@ -130,14 +130,56 @@ __device__ __forceinline__ void emit_pair(const Emit &E, Stage &sg,
     }
 }
 
-// Expand one vertex pair (whole wave).  Returns the number of tests made by
-// this lane.
-template <int M>
+// Pruning test by TG cooperating lanes (vector metrics): each lane sums a
+// TG-th of the coordinates (16-byte slices, so the TG lanes of a test read
+// contiguous memory), the partial sums meet by shuffles.  Every lane of the
+// group returns the same answer.  The test only has to be conservative; the
+// relative slack in Prune covers any summation order.
+template <int M, int TG>
+__device__ __forceinline__ bool may_touch_coop(const Pts &P, const QView &Q,
+                                               const Prune &pr, int a, int b,
+                                               bool active)
+{
+    const int sl = threadIdx.x & (TG - 1);
+    float part = 0.f;
+    if (active) {
+        const float *X = (M == M_ANG) ? P.xn : P.x;
+        const float *ra = X + (size_t)Q.cpos[a] * P.dp;
+        const float *rb = X + (size_t)Q.cpos[b] * P.dp;
+        for (int k = sl * 4; k < P.dp; k += TG * 4) {
+            const float4 u = *reinterpret_cast<const float4 *>(ra + k);
+            const float4 v = *reinterpret_cast<const float4 *>(rb + k);
+            const float d0 = u.x - v.x, d1 = u.y - v.y, d2 = u.z - v.z,
+                        d3 = u.w - v.w;
+            part = fmaf(d0, d0, part);
+            part = fmaf(d1, d1, part);
+            part = fmaf(d2, d2, part);
+            part = fmaf(d3, d3, part);
+        }
+    }
+#pragma unroll
+    for (int o = 1; o < TG; o <<= 1)
+        part += __shfl_xor(part, o, WAVE);
+    if (!active)
+        return false;
+    const float d = key_to_dist<M>(part);
+    const float e = pr.pcl ? pr.ct[pr.pcl[Q.pb[a]]].peps : pr.eps;
+    const float lim = Q.rad[a] + Q.rad[b] + e;
+    return d <= lim * (1.f + pr.rel) + pr.abs_;
+}
+
+// Expand one vertex pair (whole wave).  With TG > 1 (vector metrics), TG
+// lanes share each test and the group's first lane emits the result.
+// Returns the number of tests made by this lane.
+template <int M, int TG>
 __device__ unsigned long long expand_one(const Pts &P, const QView &Q,
                                          const Prune &pr, int a, int b,
                                          const Emit &E, Stage &sg)
 {
     const int lane = threadIdx.x & (WAVE - 1);
+    const int sub = lane / TG;                 // test slot of this lane
+    const bool lead = (lane & (TG - 1)) == 0;  // the slot's emitting lane
+    constexpr int NS = WAVE / TG;              // tests per wave step
     unsigned long long tests = 0;
     if (a == b) {
         if (a >= Q.nn) {  // a single pack against itself
@@ -146,8 +188,8 @@ __device__ unsigned long long expand_one(const Pts &P, const QView &Q,
         }
         const int m = Q.kcnt[a], k0 = Q.kbeg[a];
         const long long tot = (long long)m * (m + 1) / 2;
-        for (long long base = 0; base < tot; base += WAVE) {
-            const long long t = base + lane;
+        for (long long base = 0; base < tot; base += NS) {
+            const long long t = base + sub;
             bool valid = t < tot;
             int i = 0, j = 0;
             if (valid) {
@@ -166,12 +208,21 @@ __device__ unsigned long long expand_one(const Pts &P, const QView &Q,
             if (valid) {
                 ka = Q.kids[k0 + i];
                 kb = Q.kids[k0 + j];
-                if (i != j) {
+            }
+            const bool test = valid && i != j;
+            if constexpr (TG == 1) {
+                if (test) {
                     ++tests;
                     valid = may_touch<M>(P, Q, pr, ka, kb);
                 }
+            } else {
+                const bool ok = may_touch_coop<M, TG>(P, Q, pr, ka, kb, test);
+                if (test) {
+                    tests += lead;
+                    valid = ok;
+                }
             }
-            emit_pair(E, sg, Q, valid, ka, kb);
+            emit_pair(E, sg, Q, valid && lead, ka, kb);
         }
     } else {
         const bool at = a >= Q.nn, bt_ = b >= Q.nn;
@@ -189,16 +240,23 @@ __device__ unsigned long long expand_one(const Pts &P, const QView &Q,
         else
             s = b, o = a;
         const int m = Q.kcnt[s], k0 = Q.kbeg[s];
-        for (int base = 0; base < m; base += WAVE) {
-            const int t = base + lane;
+        for (int base = 0; base < m; base += NS) {
+            const int t = base + sub;
             bool valid = t < m;
-            int ka = 0;
-            if (valid) {
-                ka = Q.kids[k0 + t];
-                ++tests;
-                valid = may_touch<M>(P, Q, pr, ka, o);
+            const int ka = valid ? Q.kids[k0 + t] : 0;
+            if constexpr (TG == 1) {
+                if (valid) {
+                    ++tests;
+                    valid = may_touch<M>(P, Q, pr, ka, o);
+                }
+            } else {
+                const bool ok = may_touch_coop<M, TG>(P, Q, pr, ka, o, valid);
+                if (valid) {
+                    tests += lead;
+                    valid = ok;
+                }
             }
-            emit_pair(E, sg, Q, valid, ka, o);
+            emit_pair(E, sg, Q, valid && lead, ka, o);
         }
     }
     return tests;
@@ -237,7 +295,7 @@ __global__ void k_expand_bound(QView Q, const int2 *__restrict__ cur,
         atomicAdd(bound, b);
 }
 
-template <int M>
+template <int M, int TG>
 __global__ void __launch_bounds__(256)
 k_expand(Pts P, QView Q, Prune pr, const int2 *__restrict__ cur, long long ncur,
          Emit E)
@@ -253,7 +311,7 @@ k_expand(Pts P, QView Q, Prune pr, const int2 *__restrict__ cur, long long ncur,
     for (long long w = (long long)blockIdx.x * wpb + wid; w < ncur;
          w += (long long)gridDim.x * wpb) {
         const int2 pr2 = cur[w];
-        tests += expand_one<M>(P, Q, pr, pr2.x, pr2.y, E, sg);
+        tests += expand_one<M, TG>(P, Q, pr, pr2.x, pr2.y, E, sg);
     }
     stage_flush(E, sg, 0);
     stage_flush(E, sg, 1);
@@ -971,6 +1029,8 @@ __global__ void k_forest_frontier(QView Q, int2 *__restrict__ cur, int cap)
     }
 }
 
+constexpr unsigned EXPAND_GRID = 4096;  // work-groups of the expansion
+
 template <int M>
 static void traverse(const fnn_tree *T, const Pts &P, const QView &Q,
                      const Prune &pr, Scratch &S, int2 **inter_out,
@@ -1016,8 +1076,22 @@ static void traverse(const fnn_tree *T, const Pts &P, const QView &Q,
         FNN_HIP(hipMemcpyAsync(cnt, init, sizeof init, hipMemcpyHostToDevice, s));
         fill(ovf, 0, 1, s);
         Emit E{next, inter, cnt, cap_next, cap_int, ovf};
-        FNN_LAUNCH((k_expand<M>), dim3(grid_for(ncur, 4)), dim3(256), 0, s, P, Q,
-                   pr, cur, ncur, E);
+        // a bounded grid that strides over the pairs: one short-lived
+        // work-group per few pairs is dispatch-bound (few resident waves);
+        // vector metrics: lanes share each pruning test (coalesced rows)
+        const dim3 g(std::min<unsigned>(grid_for(ncur, 4), EXPAND_GRID)), blk(256);
+        if constexpr (M == M_L2 || M == M_ANG) {
+            if (P.dp >= 32)
+                FNN_LAUNCH((k_expand<M, 8>), g, blk, 0, s, P, Q, pr, cur, ncur, E);
+            else if (P.dp >= 16)
+                FNN_LAUNCH((k_expand<M, 4>), g, blk, 0, s, P, Q, pr, cur, ncur, E);
+            else if (P.dp >= 8)
+                FNN_LAUNCH((k_expand<M, 2>), g, blk, 0, s, P, Q, pr, cur, ncur, E);
+            else
+                FNN_LAUNCH((k_expand<M, 1>), g, blk, 0, s, P, Q, pr, cur, ncur, E);
+        } else {
+            FNN_LAUNCH((k_expand<M, 1>), g, blk, 0, s, P, Q, pr, cur, ncur, E);
+        }
         unsigned long long hc[3];
         int hov = 0;
         FNN_HIP(hipMemcpyAsync(hc, cnt, sizeof hc, hipMemcpyDeviceToHost, s));
@@ -1045,7 +1119,7 @@ static void launch_tiles(bool fill_pass, const Pts &P, const int2 *inter,
 {
     if (ninter <= 0)
         return;
-    const dim3 g(grid_for(ninter, 1));
+    const dim3 g(grid_cap(ninter, 1, 65536));
     if (fill_pass)
         FNN_LAUNCH((k_tile<M, true>), g, dim3(TT), 0, s, P, inter, ninter,
                    T->q_pt_begin, T->q_pt_end, T->perm, E, ct, T->pcl, fp64_dist,
@@ -1306,7 +1380,7 @@ static void eps_graph_impl(const fnn_tree *Tc, const double *epsv,
         tm.mark();  // 4
         int32_t *nov = S.get<int32_t>(1);
         fill(nov, 0, 1, s);
-        FNN_LAUNCH(k_compact, dim3(grid_for(n, 4)), dim3(256), 0, s, sb, scol, sdist,
+        FNN_LAUNCH(k_compact, dim3(grid_cap(n, 4, 16384)), dim3(256), 0, s, sb, scol, sdist,
                    ovf, C->row_ptr, n, C->col, C->dist, nov);
         novf = read_scalar(nov, s);
         {
@@ -1362,13 +1436,13 @@ static void eps_graph_impl(const fnn_tree *Tc, const double *epsv,
     int32_t *cc = S.get<int32_t>(2);
     fill(cc, 0, 2, s);
     if (nnz > 0) {
-        FNN_LAUNCH(k_sort_small, dim3(grid_for(n, 4)), dim3(256), 0, s,
+        FNN_LAUNCH(k_sort_small, dim3(grid_cap(n, 4, 16384)), dim3(256), 0, s,
                    C->row_ptr, n, C->col, C->dist, mid, lng, cc);
         int32_t hcc[2];
         FNN_HIP(hipMemcpyAsync(hcc, cc, sizeof hcc, hipMemcpyDeviceToHost, s));
         FNN_HIP(hipStreamSynchronize(s));
         if (hcc[0] > 0)
-            FNN_LAUNCH(k_sort_mid, dim3(grid_for(hcc[0], 1)), dim3(256), 0, s,
+            FNN_LAUNCH(k_sort_mid, dim3(grid_cap(hcc[0], 1, 4096)), dim3(256), 0, s,
                        C->row_ptr, mid, hcc[0], C->col, C->dist);
         if (hcc[1] > 0) {
             int64_t *p2 = S.get<int64_t>(hcc[1] + 1);

@@ -139,4 +139,14 @@ inline unsigned grid_for(int64_t items, int64_t items_per_block)
     return (unsigned)b;
 }
 
+// Grid for kernels that stride over their items: at most `cap` work-groups.
+// Launching one short-lived work-group per small item leaves the chip
+// bound by work-group dispatch (few resident waves); a bounded grid keeps
+// every CU busy with long-lived waves.
+inline unsigned grid_cap(int64_t items, int64_t items_per_block, unsigned cap)
+{
+    const unsigned g = grid_for(items, items_per_block);
+    return g < cap ? g : cap;
+}
+
 }  // namespace fnn
