@@ -16,11 +16,11 @@
 // pair is recomputed by direct FP32 difference and decided exactly like the
 // plain tiles (rounding band -> FP64 reference predicate).
 //
-// Work decomposition: query packs are grouped four at a time (consecutive
-// pack ids).  A work-group (4 waves) takes one group and a run of the union
-// of its members' interaction lists; wave w holds pack 4g+w (<= 64 rows) in
+// Work decomposition: query packs are grouped GW (4) at a time (consecutive
+// pack ids).  A work-group (GW waves) takes one group and a run of the union
+// of its members' interaction lists; wave w holds pack GW*g+w (<= 64 rows) in
 // registers, the B pack of each step is staged once in LDS and read by all
-// four waves.  Every unordered point pair is evaluated once: a wave skips B
+// GW waves.  Every unordered point pair is evaluated once: a wave skips B
 // packs with a smaller id, and inside its own pack keeps only pairs whose
 // first point precedes the second in tree order.
 #include <float.h>
@@ -41,6 +41,7 @@ typedef __attribute__((ext_vector_type(16))) float f32x16;
 typedef __attribute__((ext_vector_type(8))) int i32x8;
 
 constexpr int GP = 64;           // rows per pack (max) on the MFMA path
+constexpr int GW = 4;            // packs per group = waves per work-group
 
 // ---------------------------------------------------------------- prep ---
 
@@ -147,7 +148,7 @@ __global__ void k_route(const int2 *__restrict__ inter, long long ninter,
         } else if (valid) {
             const unsigned long long o = os + __popcll(ms & lt);
             key[o] = (uint32_t)(b - nn);
-            val[o] = (uint32_t)((a - nn) >> 2);
+            val[o] = (uint32_t)((a - nn) / GW);
         }
     }
 }
@@ -162,24 +163,20 @@ __global__ void k_max_pack(const int32_t *__restrict__ pb, const int32_t *__rest
             *big = 1;
 }
 
-// Closed-form work list: entry e of group g (goff[g] <= e < goff[g+1]) pairs
-// the group with pack 4g + (e - goff[g]).
-__global__ void k_dense_list(const int64_t *__restrict__ goff, int ngr, long long mu,
-                             int32_t *__restrict__ lg, int32_t *__restrict__ lb)
+// Closed-form work list: unit u pairs group ug[u] with the consecutive B
+// packs ulo[u], ulo[u] + 1, ... (entries ubeg[u] .. ubeg[u+1]); one wave
+// per unit.
+__global__ void k_dense_units(const int32_t *__restrict__ ubeg,
+                              const int32_t *__restrict__ ug,
+                              const int32_t *__restrict__ ulo, int nu,
+                              int32_t *__restrict__ lg, int32_t *__restrict__ lb)
 {
-    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < mu;
-         e += (long long)gridDim.x * blockDim.x) {
-        int lo = 0, hi = ngr - 1;  // last g with goff[g] <= e
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (goff[mid] <= e)
-                lo = mid;
-            else
-                hi = mid - 1;
+    const int lane = threadIdx.x & (WAVE - 1), wpb = blockDim.x / WAVE;
+    for (int u = blockIdx.x * wpb + threadIdx.x / WAVE; u < nu; u += gridDim.x * wpb)
+        for (int e = ubeg[u] + lane; e < ubeg[u + 1]; e += WAVE) {
+            lg[e] = ug[u];
+            lb[e] = ulo[u] + (e - ubeg[u]);
         }
-        lg[e] = lo;
-        lb[e] = (int32_t)(4 * lo + (e - goff[lo]));
-    }
 }
 
 // After sorting by (group, B): mark the first of each distinct pair.
@@ -237,7 +234,7 @@ __global__ void k_units_write(const int32_t *__restrict__ flag,
 
 // ------------------------------------------------------------ the tile ---
 
-constexpr int GT = 256;          // 4 waves
+constexpr int GT = 64 * GW;      // one wave per pack of a group
 
 template <int PREC>
 struct GramCfg;
@@ -253,7 +250,7 @@ struct GramCfg<FNN_PREC_FP8> {
 };
 
 template <int M, int PREC, int NKS>
-__global__ void __launch_bounds__(GT, 2)
+__global__ void __launch_bounds__(GT, 8 / GW)
 k_gram(Pts P, GramArgs G, TileOut out)
 {
     using C = GramCfg<PREC>;
@@ -266,7 +263,7 @@ k_gram(Pts P, GramArgs G, TileOut out)
     extern __shared__ __align__(16) unsigned char smem[];
     unsigned char *Bs = smem;                  // [GP][ldb]
     float *ayS = (float *)(smem + GP * ldb);   // [GP]
-    float *axS = ayS + GP;                     // [4][GP]
+    float *axS = ayS + GP;                     // [GW][GP]
 
     const int t = threadIdx.x, lane = t & (WAVE - 1), w = t / WAVE;
     const int l32 = lane & 31, hi = lane >> 5;
@@ -275,12 +272,20 @@ k_gram(Pts P, GramArgs G, TileOut out)
     unsigned long long npairs = 0;
     const uint64_t ltmask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
 
-    for (int u = blockIdx.x; u < G.nunits; u += gridDim.x) {
+    // XCD-aware order: the dispatcher hands consecutive work-groups to the 8
+    // XCDs in turn, so physical block b runs on XCD b % 8.  XCD x takes the
+    // contiguous slice of the unit order starting at xs (units that share B
+    // tiles are adjacent in that order and then meet in one XCD's L2).
+    const int nbk = gridDim.x, xq = nbk / 8, xr = nbk % 8;
+    const int xcd = blockIdx.x % 8;
+    const int xs = xcd * xq + min(xcd, xr);
+    const int u0 = xs + (int)(blockIdx.x / 8);
+    for (int u = u0; u < G.nunits; u += gridDim.x) {
         const int e0 = G.ubeg[u], e1 = G.ubeg[u + 1];
         const int g = G.lg[e0];
-        const int a = G.nn + 4 * g + w;        // this wave's pack
+        const int a = G.nn + GW * g + w;       // this wave's pack
         // packs larger than GP (duplicate groups) are tiled by the plain path
-        const bool has_a = (4 * g + w) < G.npacks && G.q_pe[a] - G.q_pb[a] <= GP;
+        const bool has_a = (GW * g + w) < G.npacks && G.q_pe[a] - G.q_pb[a] <= GP;
         const int pa = has_a ? G.q_pb[a] : 0;
         const int na = has_a ? G.q_pe[a] - pa : 0;
 
@@ -378,40 +383,37 @@ k_gram(Pts P, GramArgs G, TileOut out)
             if (ca >= 0 && G.pcl[pb] != ca)
                 continue;                      // different clouds never connect
             const bool self = (b == a);
+            // both 32-column blocks at once: four independent accumulator
+            // chains [cb][rb] per k-step.  The accumulators start at -ax (in
+            // the scaled units of the products), so they end at g~ - ax.
+            f32x16 acc[2][2];
 #pragma unroll
-            for (int cb = 0; cb < 2; ++cb) {
-                if (cb * 32 >= nb)
-                    break;
-                // accumulators start at -ax (in the scaled units of the
-                // products), so they end at g~ - ax
-                f32x16 acc[2];
+            for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
-                for (int rb = 0; rb < 2; ++rb)
+                for (int q4 = 0; q4 < 4; ++q4) {
+                    const float4 a4 = *reinterpret_cast<const float4 *>(
+                        axS + w * GP + rb * 32 + 8 * q4 + 4 * hi);
 #pragma unroll
-                    for (int q4 = 0; q4 < 4; ++q4) {
-                        const float4 a4 = *reinterpret_cast<const float4 *>(
-                            axS + w * GP + rb * 32 + 8 * q4 + 4 * hi);
-                        acc[rb][4 * q4 + 0] = a4.x;
-                        acc[rb][4 * q4 + 1] = a4.y;
-                        acc[rb][4 * q4 + 2] = a4.z;
-                        acc[rb][4 * q4 + 3] = a4.w;
+                    for (int cb = 0; cb < 2; ++cb) {
+                        acc[cb][rb][4 * q4 + 0] = a4.x;
+                        acc[cb][rb][4 * q4 + 1] = a4.y;
+                        acc[cb][rb][4 * q4 + 2] = a4.z;
+                        acc[cb][rb][4 * q4 + 3] = a4.w;
                     }
-                const unsigned char *brow = Bs + (cb * 32 + l32) * ldb;
-                // this column block's B fragments, all read before the
-                // matrix-core chain (no LDS wait between k-steps)
-                int4 bfr[PREC == FNN_PREC_BF16 ? nks : 1];
-                if constexpr (PREC == FNN_PREC_BF16) {
-#pragma unroll
-                    for (int ks = 0; ks < nks; ++ks)
-                        bfr[ks] = *(const int4 *)(brow + (ks * 16 + hi * 8) * 2);
                 }
-                #pragma unroll
-                        for (int ks = 0; ks < nks; ++ks) {
-                    if constexpr (PREC == FNN_PREC_BF16) {
-                        const int4 bv = bfr[ks];
+            const unsigned char *brow0 = Bs + l32 * ldb;
+            const unsigned char *brow1 = Bs + (32 + l32) * ldb;
+#pragma unroll
+            for (int ks = 0; ks < nks; ++ks) {
+                if constexpr (PREC == FNN_PREC_BF16) {
+                    const int off = (ks * 16 + hi * 8) * 2;
+                    const int4 bv[2] = {*(const int4 *)(brow0 + off),
+                                        *(const int4 *)(brow1 + off)};
+                    const int slot = ks >> 1, half = ks & 1;
+#pragma unroll
+                    for (int cb = 0; cb < 2; ++cb) {
                         bf16x8 bb;
-                        __builtin_memcpy(&bb, &bv, 16);
-                        const int slot = ks >> 1, half = ks & 1;
+                        __builtin_memcpy(&bb, &bv[cb], 16);
 #pragma unroll
                         for (int rb = 0; rb < 2; ++rb) {
                             const int4 av = make_int4(Areg[rb][slot][half * 4 + 0],
@@ -420,38 +422,52 @@ k_gram(Pts P, GramArgs G, TileOut out)
                                                       Areg[rb][slot][half * 4 + 3]);
                             bf16x8 aa;
                             __builtin_memcpy(&aa, &av, 16);
-                            acc[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                                aa, bb, acc[rb], 0, 0, 0);
+                            acc[cb][rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                                aa, bb, acc[cb][rb], 0, 0, 0);
                         }
-                    } else {
+                    }
+                } else {
+#pragma unroll
+                    for (int cb = 0; cb < 2; ++cb) {
+                        const unsigned char *brow = cb ? brow1 : brow0;
                         const int4 b0 = *(const int4 *)(brow + ks * 64 + hi * 32);
                         const int4 b1 = *(const int4 *)(brow + ks * 64 + hi * 32 + 16);
                         const i32x8 bb = (i32x8){b0.x, b0.y, b0.z, b0.w,
                                                  b1.x, b1.y, b1.z, b1.w};
 #pragma unroll
                         for (int rb = 0; rb < 2; ++rb)
-                            acc[rb] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
-                                Areg[rb][ks], bb, acc[rb], 0, 0, 0, 127, 0, 127);
+                            acc[cb][rb] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+                                Areg[rb][ks], bb, acc[cb][rb], 0, 0, 0, 127, 0, 127);
                     }
                 }
-                // ---- filter -----------------------------------------------
-                // A pair passes when g~ - ax >= ay.  Fast test per lane: the
-                // largest g~ - ax over its 32 rows against its column's ay
-                // (rows past na carry ax = FLT_MAX, columns past nb carry
-                // ay = FLT_MAX, so neither can pass).  Only when some lane
-                // may hold a survivor (rare), on a self pair, or when
-                // validating does the wave build per-pair masks.
-                const int col = cb * 32 + l32;
-                const float ay = ayS[col];
-                float mx = -FLT_MAX;
+            }
+            // ---- filter ---------------------------------------------------
+            // A pair passes when g~ - ax >= ay.  Fast test per lane: the
+            // largest g~ - ax over its 32 rows against its column's ay, for
+            // both column blocks (rows past na carry ax = FLT_MAX, columns
+            // past nb carry ay = FLT_MAX, so neither can pass).  Only when
+            // some lane may hold a survivor (rare), on a self pair, or when
+            // validating does the wave build per-pair masks.
+            float ayc[2], mx[2];
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb) {
+                ayc[cb] = ayS[cb * 32 + l32];
+                mx[cb] = -FLT_MAX;
 #pragma unroll
                 for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
                     for (int q = 0; q < 16; ++q)
-                        mx = fmaxf(mx, acc[rb][q]);
+                        mx[cb] = fmaxf(mx[cb], acc[cb][rb][q]);
                 if (PREC != FNN_PREC_BF16)
-                    mx *= G.gscale;
-                if (__any(mx >= ay) || self || G.validate) {
+                    mx[cb] *= G.gscale;
+            }
+            if (__any(mx[0] >= ayc[0] || mx[1] >= ayc[1]) || self || G.validate) {
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb) {
+                if (cb * 32 >= nb)
+                    break;
+                const int col = cb * 32 + l32;
+                const float ay = ayc[cb];
                 unsigned pm = 0, om = 0;
 #pragma unroll
                 for (int rb = 0; rb < 2; ++rb) {
@@ -459,8 +475,8 @@ k_gram(Pts P, GramArgs G, TileOut out)
                     for (int q = 0; q < 16; ++q) {
                         const int row = rb * 32 + 8 * (q >> 2) + 4 * hi + (q & 3);
                         const bool ok = row < na && col < nb && (!self || row < col);
-                        const float gq = PREC == FNN_PREC_BF16 ? acc[rb][q]
-                                                               : acc[rb][q] * G.gscale;
+                        const float gq = PREC == FNN_PREC_BF16 ? acc[cb][rb][q]
+                                                               : acc[cb][rb][q] * G.gscale;
                         const bool pass = ok && (gq >= ay);
                         pm |= (unsigned)pass << (rb * 16 + q);
                         om |= (unsigned)ok << (rb * 16 + q);
@@ -495,9 +511,14 @@ k_gram(Pts P, GramArgs G, TileOut out)
                         ++o;
                     }
                 }
-                }
-                // pairs screened by this wave in this column block
-                if (lane == 0) {
+            }
+            }
+            // pairs screened by this wave (both column blocks)
+            if (lane == 0) {
+#pragma unroll
+                for (int cb = 0; cb < 2; ++cb) {
+                    if (cb * 32 >= nb)
+                        break;
                     // rows r < na against columns c0 .. c0+nc-1 (r < c if self)
                     const long long nc = min(32, nb - cb * 32), c0 = cb * 32;
                     if (!self) {
@@ -660,7 +681,7 @@ static void launch_gram_k(bool fill_pass, const Pts &P, const GramArgs &G,
                           const TileOut &o, hipStream_t s)
 {
     const int rowb = NKS * GramCfg<PREC>::KSTEP * GramCfg<PREC>::EB;
-    const size_t sh = (size_t)GP * (rowb + 16) + sizeof(float) * GP * 5;
+    const size_t sh = (size_t)GP * (rowb + 16) + sizeof(float) * GP * (GW + 1);
     const dim3 grid(grid_for(G.nunits, 1));
     (void)fill_pass;
     FNN_LAUNCH((k_gram<M, PREC, NKS>), grid, dim3(GT), sh, s, P, G, o);
@@ -783,35 +804,45 @@ void gram_prepare(const fnn_tree *T, int prec, double eps, const Thr &E,
     // than GP, the work list is every (group g, B >= 4g) pair; the few pairs
     // the traversal pruned are evaluated too, which changes no edge.
     {
-        const int ngr = (npk + 3) / 4;
+        const int ngr = (npk + GW - 1) / GW;
         const long long allp = (long long)npk * (npk + 1) / 2;
-        long long mu = 0;
+        long long mu = 0;  // entries: every (group, B >= its first pack)
         for (int g = 0; g < ngr; ++g)
-            mu += npk - 4 * g;
+            mu += npk - GW * g;
         if (npk > 0 && (double)ninter >= 0.95 * (double)allp && mu < INT32_MAX) {
             int32_t *big = S.get<int32_t>(1);
             fill(big, 0, 1, s);
             FNN_LAUNCH(k_max_pack, dim3(grid_for(npk, 256)), dim3(256), 0, s,
                        T->q_pt_begin + nn, T->q_pt_end + nn, npk, GP, big);
             if (read_scalar(big, s) == 0) {
-                std::vector<int64_t> goff(ngr + 1);
-                std::vector<int32_t> ub;
-                goff[0] = 0;
-                for (int g = 0; g < ngr; ++g) {
-                    goff[g + 1] = goff[g] + (npk - 4 * g);
-                    for (int64_t e = goff[g]; e < goff[g + 1]; e += RUN)
+                // units ordered by B run (runs aligned to RUN packs), then by
+                // group: the units of one run read the same B tiles
+                std::vector<int32_t> ub, ug, ulo;
+                int64_t e = 0;
+                for (int k = 0; (int64_t)k * RUN < npk; ++k)
+                    for (int g = 0; g < ngr; ++g) {
+                        const int lo = std::max(k * RUN, GW * g);
+                        const int hi = std::min((k + 1) * RUN, npk);
+                        if (lo >= hi)
+                            continue;
                         ub.push_back((int32_t)e);
-                }
-                ub.push_back((int32_t)mu);
-                int64_t *goff_d = S.get<int64_t>(ngr + 1);
+                        ug.push_back(g);
+                        ulo.push_back(lo);
+                        e += hi - lo;
+                    }
+                ub.push_back((int32_t)e);
+                const int nu = (int)ug.size();
                 int32_t *lg = S.get<int32_t>(mu + 1), *lb = S.get<int32_t>(mu + 1);
-                int32_t *ubeg = S.get<int32_t>(ub.size());
-                FNN_HIP(hipMemcpyAsync(goff_d, goff.data(), sizeof(int64_t) * (ngr + 1),
+                int32_t *ubeg = S.get<int32_t>(nu + 1);
+                int32_t *ug_d = S.get<int32_t>(nu), *ulo_d = S.get<int32_t>(nu);
+                FNN_HIP(hipMemcpyAsync(ubeg, ub.data(), sizeof(int32_t) * (nu + 1),
                                        hipMemcpyHostToDevice, s));
-                FNN_HIP(hipMemcpyAsync(ubeg, ub.data(), sizeof(int32_t) * ub.size(),
+                FNN_HIP(hipMemcpyAsync(ug_d, ug.data(), sizeof(int32_t) * nu,
                                        hipMemcpyHostToDevice, s));
-                FNN_LAUNCH(k_dense_list, dim3(grid_for(mu, 256)), dim3(256), 0, s,
-                           goff_d, ngr, mu, lg, lb);
+                FNN_HIP(hipMemcpyAsync(ulo_d, ulo.data(), sizeof(int32_t) * nu,
+                                       hipMemcpyHostToDevice, s));
+                FNN_LAUNCH(k_dense_units, dim3(grid_cap(nu, 4, 16384)), dim3(256), 0, s,
+                           ubeg, ug_d, ulo_d, nu, lg, lb);
                 FNN_HIP(hipStreamSynchronize(s));  // host vectors go out of scope
                 *rest = nullptr;
                 *nrest = 0;
@@ -820,8 +851,8 @@ void gram_prepare(const fnn_tree *T, int prec, double eps, const Thr &E,
                 G.lg = lg;
                 G.lb = lb;
                 G.ubeg = ubeg;
-                G.nunits = (int)ub.size() - 1;
-                G.nlist = (int)mu;
+                G.nunits = nu;
+                G.nlist = (int)e;
                 return;
             }
         }
@@ -858,7 +889,7 @@ void gram_prepare(const fnn_tree *T, int prec, double eps, const Thr &E,
     // sort by B, then stably by group: (group, B) order
     radix_sort_pairs(k1, v1, k2, v2, m, bits((uint32_t)npk), S);
     uint32_t *gk = S.get<uint32_t>(m), *bv = S.get<uint32_t>(m);
-    radix_sort_pairs(v2, k2, gk, bv, m, bits((uint32_t)(npk / 4 + 1)), S);
+    radix_sort_pairs(v2, k2, gk, bv, m, bits((uint32_t)(npk / GW + 1)), S);
     int32_t *flag = S.get<int32_t>(m + 1), *pos = S.get<int32_t>(m + 2);
     FNN_LAUNCH(k_uniq_flags, dim3(grid_for(m, 256)), dim3(256), 0, s, gk, bv, m,
                flag);
@@ -871,7 +902,7 @@ void gram_prepare(const fnn_tree *T, int prec, double eps, const Thr &E,
                flag, pos, lg, lb);
     // units of at most RUN entries of one group
     int32_t *uf = S.get<int32_t>(mu + 1), *up = S.get<int32_t>(mu + 2);
-    int32_t *gfirst = S.get<int32_t>(npk / 4 + 2);
+    int32_t *gfirst = S.get<int32_t>(npk / GW + 2);
     FNN_LAUNCH(k_group_first, dim3(grid_for(mu, 256)), dim3(256), 0, s, lg, mu,
                gfirst);
     FNN_LAUNCH(k_units, dim3(grid_for(mu, 256)), dim3(256), 0, s, lg, mu, RUN,
