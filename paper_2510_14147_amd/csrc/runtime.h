@@ -7,6 +7,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <utility>
 #include <vector>
 
 namespace fnn {
@@ -53,12 +54,12 @@ struct GraphRun {
     void launch(hipStream_t s);
 };
 
-// Stream-ordered scratch allocations released (stream-ordered) on scope
-// exit.  Backed by the device's default memory pool, whose release
-// threshold is raised once so freed blocks are reused.
+// Scratch memory of one call: bump-allocated from device chunks taken from
+// a per-device cache and returned to it (after the stream drains) on scope
+// exit.
 class Scratch {
   public:
-    explicit Scratch(hipStream_t s) : s_(s) {}
+    explicit Scratch(hipStream_t s);
     ~Scratch();
     Scratch(const Scratch &) = delete;
     Scratch &operator=(const Scratch &) = delete;
@@ -73,7 +74,9 @@ class Scratch {
 
   private:
     hipStream_t s_;
-    std::vector<void *> ptrs_;
+    int dev_ = 0;
+    std::vector<std::pair<void *, size_t>> chunks_;  // held by this scope
+    size_t used_ = 0;                                // bump offset in the last
 };
 
 // Memory handed to the caller (tree / CSR arrays): the user allocator if one

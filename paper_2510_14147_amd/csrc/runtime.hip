@@ -3,6 +3,7 @@
 #include <stdarg.h>
 #include <stdio.h>
 
+#include <algorithm>
 #include <mutex>
 
 #include "../../include/fnn.h"
@@ -81,55 +82,101 @@ void GraphRun::end()
 
 void GraphRun::launch(hipStream_t s) { FNN_HIP(hipGraphLaunch(exec, s)); }
 
-static std::once_flag g_pool_once[64];
-
-static void ensure_pool()
-{
-    int dev = 0;
-    FNN_HIP(hipGetDevice(&dev));
-    if (dev < 0 || dev >= 64)
-        return;
-    std::call_once(g_pool_once[dev], [dev]() {
-        hipMemPool_t pool;
-        if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
-            uint64_t thr = UINT64_MAX;
-            (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold,
-                                         &thr);
-        }
-    });
-}
-
 // --------------------------------------------------------------- scratch --
+//
+// Scratch memory is bump-allocated from large chunks.  A call's chunks come
+// from a per-device cache of idle chunks (best fit, so a repeated call
+// reuses the same chunks) and go back to it when the call's scope ends,
+// after its stream has drained; a steady stream of calls therefore makes no
+// device allocation at all.  Idle chunks beyond a cap are freed.
+
+namespace {
+struct Chunk {
+    char *base;
+    size_t cap;
+};
+std::mutex g_chunk_mu;
+std::vector<Chunk> g_idle[64];
+size_t g_idle_bytes[64] = {0};
+constexpr size_t CHUNK = (size_t)256 << 20;         // usual chunk size
+constexpr size_t IDLE_CAP = (size_t)32 << 30;       // idle bytes kept per device
+constexpr size_t ALIGN = 256;
+}  // namespace
+
+Scratch::Scratch(hipStream_t s) : s_(s)
+{
+    FNN_HIP(hipGetDevice(&dev_));
+    if (dev_ < 0 || dev_ >= 64)
+        fail(FNN_EUNSUPPORTED, "device id %d", dev_);
+}
 
 void *Scratch::raw(size_t bytes)
 {
-    ensure_pool();
-    void *p = nullptr;
-    if (bytes == 0)
-        bytes = 16;
-    hipError_t e = hipMallocAsync(&p, bytes, s_);
-    if (e != hipSuccess || !p)
-        fail(FNN_ENOMEM, "device scratch allocation of %zu bytes failed: %s",
-             bytes, hipGetErrorString(e));
-    ptrs_.push_back(p);
-    return p;
+    bytes = (std::max<size_t>(bytes, 16) + ALIGN - 1) / ALIGN * ALIGN;
+    if (!chunks_.empty() && used_ + bytes <= chunks_.back().second) {
+        void *p = static_cast<char *>(chunks_.back().first) + used_;
+        used_ += bytes;
+        return p;
+    }
+    const size_t want = std::max(bytes, CHUNK);
+    void *base = nullptr;
+    size_t cap = 0;
+    {
+        std::lock_guard<std::mutex> lk(g_chunk_mu);
+        auto &idle = g_idle[dev_];
+        int best = -1;
+        for (int i = 0; i < (int)idle.size(); ++i)
+            if (idle[i].cap >= bytes && (best < 0 || idle[i].cap < idle[best].cap))
+                best = i;
+        if (best >= 0) {
+            base = idle[best].base;
+            cap = idle[best].cap;
+            g_idle_bytes[dev_] -= cap;
+            idle[best] = idle.back();
+            idle.pop_back();
+        }
+    }
+    if (!base) {
+        hipError_t e = hipMalloc(&base, want);
+        if (e != hipSuccess || !base) {
+            (void)hipGetLastError();
+            fail(FNN_ENOMEM, "device scratch allocation of %zu bytes failed: %s",
+                 want, hipGetErrorString(e));
+        }
+        cap = want;
+    }
+    chunks_.emplace_back(base, cap);
+    used_ = bytes;
+    return base;
 }
 
-void Scratch::release(void *p)
+void Scratch::release(void *)
 {
-    for (size_t i = 0; i < ptrs_.size(); ++i)
-        if (ptrs_[i] == p) {
-            (void)hipFreeAsync(p, s_);
-            ptrs_[i] = ptrs_.back();
-            ptrs_.pop_back();
-            return;
-        }
+    // bump allocation: the space returns with the scope's chunks
 }
 
 Scratch::~Scratch()
 {
-    for (void *p : ptrs_)
-        (void)hipFreeAsync(p, s_);
+    if (chunks_.empty())
+        return;
+    // the chunks may be reused by any stream once this one has drained
+    (void)hipStreamSynchronize(s_);
+    std::lock_guard<std::mutex> lk(g_chunk_mu);
+    for (auto &c : chunks_) {
+        g_idle[dev_].push_back(Chunk{static_cast<char *>(c.first), c.second});
+        g_idle_bytes[dev_] += c.second;
+    }
+    auto &idle = g_idle[dev_];
+    while (g_idle_bytes[dev_] > IDLE_CAP && !idle.empty()) {
+        int big = 0;
+        for (int i = 1; i < (int)idle.size(); ++i)
+            if (idle[i].cap > idle[big].cap)
+                big = i;
+        (void)hipFree(idle[big].base);
+        g_idle_bytes[dev_] -= idle[big].cap;
+        idle[big] = idle.back();
+        idle.pop_back();
+    }
 }
 
 // ------------------------------------------------------ output allocator --
