@@ -29,6 +29,12 @@ struct TileOut {
     float *spill_dist;
     unsigned long long *spill_cnt;
     unsigned long long spill_cap;
+    // edge-list count pass: every unordered edge (input ids, distance) is
+    // appended while it fits; the running count may exceed the capacity
+    int2 *elist;
+    float *edist;
+    unsigned long long *ecnt;
+    unsigned long long ecap;
 };
 
 struct GramArgs {

@@ -390,7 +390,11 @@ __device__ __forceinline__ void put(const TileOut &out, int row, int col,
     }
 }
 
-template <int M, bool FILL>
+// Tile pass modes: count row degrees; fill CSR slots; or count and append
+// every unordered edge to an edge list (which replaces the fill pass).
+enum { TILE_COUNT = 0, TILE_FILL = 1, TILE_LIST = 2 };
+
+template <int M, int MODE>
 __global__ void __launch_bounds__(TT)
 k_tile(Pts P, const int2 *__restrict__ inter, long long ninter,
        const int32_t *__restrict__ q_pb, const int32_t *__restrict__ q_pe,
@@ -399,7 +403,9 @@ k_tile(Pts P, const int2 *__restrict__ inter, long long ninter,
 {
     __shared__ TileSmem<M> sm;
     __shared__ unsigned long long mask[TS];
-    __shared__ float dt[FILL ? TS * (TS + 1) : 1];
+    constexpr bool FILL = MODE == TILE_FILL, LIST = MODE == TILE_LIST;
+    constexpr bool DIST = FILL || LIST;  // keep the tile's edge distances
+    __shared__ float dt[DIST ? TS * (TS + 1) : 1];
     const int t = threadIdx.x, ty = t / 16, tx = t % 16;
     unsigned long long rechecks = 0, pairs = 0;
     for (long long it = blockIdx.x; it < ninter; it += gridDim.x) {
@@ -547,7 +553,7 @@ k_tile(Pts P, const int2 *__restrict__ inter, long long ninter,
                         }
                         if (e) {
                             nib |= 1u << j;
-                            if constexpr (FILL)
+                            if constexpr (DIST)
                                 dt[ri * (TS + 1) + cj] =
                                     edge_dist<M>(P, pa + ri, pb + cj, k, fp64_dist);
                         }
@@ -585,6 +591,32 @@ k_tile(Pts P, const int2 *__restrict__ inter, long long ninter,
                                 o, lim, spb);
                             ++idx;
                         }
+                    }
+                }
+                if constexpr (LIST) {
+                    // this row's edges, once per unordered pair (threads
+                    // 0..63 are one wave: one reservation for all of them)
+                    int incl = c;
+#pragma unroll
+                    for (int o = 1; o < WAVE; o <<= 1) {
+                        const int v = __shfl_up(incl, o, WAVE);
+                        if ((t & (WAVE - 1)) >= o)
+                            incl += v;
+                    }
+                    const int tot = __shfl(incl, WAVE - 1, WAVE);
+                    unsigned long long base = 0;
+                    if (t == 0 && tot)
+                        base = atomicAdd(out.ecnt, (unsigned long long)tot);
+                    base = __shfl(base, 0, WAVE) + (unsigned long long)(incl - c);
+                    unsigned long long bb = bits;
+                    while (bb) {
+                        const int j = __ffsll((long long)bb) - 1;
+                        bb &= bb - 1;
+                        if (base < out.ecap) {
+                            out.elist[base] = make_int2(orow, perm[pb + j]);
+                            out.edist[base] = dt[r * (TS + 1) + j];
+                        }
+                        ++base;
                     }
                 }
             } else if (t < 2 * TS) {
@@ -631,7 +663,61 @@ __device__ __forceinline__ unsigned long long pack_entry(int32_t c, float d)
     return ((unsigned long long)(uint32_t)c << 32) | __float_as_uint(d);
 }
 
-// Rows of at most 64 entries: one wave per row, bitonic sort across lanes.
+// One row of up to 64*V entries sorted by one wave: element v*64 + lane
+// lives in register v of that lane; bitonic stages with stride >= 64 swap
+// registers within a lane, shorter strides exchange across lanes.
+template <int V>
+__device__ __forceinline__ void wave_sort_row(int32_t *__restrict__ col,
+                                              float *__restrict__ dist, int64_t b,
+                                              int len, int lane)
+{
+    unsigned long long x[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        const int i = v * WAVE + lane;
+        x[v] = i < len ? pack_entry(col[b + i], dist[b + i]) : ~0ull;
+    }
+#pragma unroll
+    for (int k = 2; k <= WAVE * V; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            if (j >= WAVE) {
+                const int jv = j / WAVE;
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    if (v & jv)
+                        continue;
+                    const int w = v | jv;
+                    const bool up = ((v * WAVE + lane) & k) == 0;
+                    const unsigned long long a = x[v], c = x[w];
+                    if ((a > c) == up) {
+                        x[v] = c;
+                        x[w] = a;
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    const unsigned long long o = __shfl_xor(x[v], j, WAVE);
+                    const bool up = ((v * WAVE + lane) & k) == 0;
+                    const bool lower = (lane & j) == 0;
+                    x[v] = (lower == up) ? (o < x[v] ? o : x[v]) : (o > x[v] ? o : x[v]);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        const int i = v * WAVE + lane;
+        if (i < len) {
+            col[b + i] = (int32_t)(x[v] >> 32);
+            dist[b + i] = __uint_as_float((uint32_t)x[v]);
+        }
+    }
+}
+
+// Rows of at most 512 entries: one wave per row (register bitonic sort);
+// longer rows are listed for the work-group and global sorts.
 __global__ void __launch_bounds__(256)
 k_sort_small(const int64_t *__restrict__ row_ptr, int n, int32_t *__restrict__ col,
              float *__restrict__ dist, int32_t *__restrict__ mid_list,
@@ -645,13 +731,25 @@ k_sort_small(const int64_t *__restrict__ row_ptr, int n, int32_t *__restrict__ c
     const int64_t len = row_ptr[r + 1] - b;
     if (len <= 1)
         continue;
-    if (len > WAVE) {
+    if (len > 8 * WAVE) {
         if (lane == 0) {
             if (len <= 4096)
                 mid_list[atomicAdd(&counts[0], 1)] = r;
             else
                 long_list[atomicAdd(&counts[1], 1)] = r;
         }
+        continue;
+    }
+    if (len > 4 * WAVE) {
+        wave_sort_row<8>(col, dist, b, (int)len, lane);
+        continue;
+    }
+    if (len > 2 * WAVE) {
+        wave_sort_row<4>(col, dist, b, (int)len, lane);
+        continue;
+    }
+    if (len > WAVE) {
+        wave_sort_row<2>(col, dist, b, (int)len, lane);
         continue;
     }
     unsigned long long v = lane < len ? pack_entry(col[b + lane], dist[b + lane])
@@ -672,7 +770,7 @@ k_sort_small(const int64_t *__restrict__ row_ptr, int n, int32_t *__restrict__ c
     }
 }
 
-// Rows of 65..4096 entries: one work-group per row, bitonic sort in LDS.
+// Rows of 513..4096 entries: one work-group per row, bitonic sort in LDS.
 __global__ void __launch_bounds__(256)
 k_sort_mid(const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ list,
            int nl, int32_t *__restrict__ col, float *__restrict__ dist)
@@ -1112,7 +1210,7 @@ static void traverse(const fnn_tree *T, const Pts &P, const QView &Q,
 }
 
 template <int M>
-static void launch_tiles(bool fill_pass, const Pts &P, const int2 *inter,
+static void launch_tiles(int mode, const Pts &P, const int2 *inter,
                          long long ninter, const fnn_tree *T, const Thr &E,
                          const CloudThr *ct, int fp64_dist, const TileOut &o,
                          hipStream_t s)
@@ -1120,14 +1218,36 @@ static void launch_tiles(bool fill_pass, const Pts &P, const int2 *inter,
     if (ninter <= 0)
         return;
     const dim3 g(grid_cap(ninter, 1, 65536));
-    if (fill_pass)
-        FNN_LAUNCH((k_tile<M, true>), g, dim3(TT), 0, s, P, inter, ninter,
+    if (mode == TILE_FILL)
+        FNN_LAUNCH((k_tile<M, TILE_FILL>), g, dim3(TT), 0, s, P, inter, ninter,
+                   T->q_pt_begin, T->q_pt_end, T->perm, E, ct, T->pcl, fp64_dist,
+                   o);
+    else if (mode == TILE_LIST)
+        FNN_LAUNCH((k_tile<M, TILE_LIST>), g, dim3(TT), 0, s, P, inter, ninter,
                    T->q_pt_begin, T->q_pt_end, T->perm, E, ct, T->pcl, fp64_dist,
                    o);
     else
-        FNN_LAUNCH((k_tile<M, false>), g, dim3(TT), 0, s, P, inter, ninter,
+        FNN_LAUNCH((k_tile<M, TILE_COUNT>), g, dim3(TT), 0, s, P, inter, ninter,
                    T->q_pt_begin, T->q_pt_end, T->perm, E, ct, T->pcl, fp64_dist,
                    o);
+}
+
+// Upper bound of the point pairs the tiles of an interaction list evaluate.
+__global__ void k_pair_bound(const int2 *__restrict__ inter, long long ni,
+                             const int32_t *__restrict__ q_pb,
+                             const int32_t *__restrict__ q_pe,
+                             unsigned long long *__restrict__ out)
+{
+    unsigned long long b = 0;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < ni;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int2 p = inter[i];
+        const unsigned long long na = q_pe[p.x] - q_pb[p.x], nb = q_pe[p.y] - q_pb[p.y];
+        b += p.x == p.y ? na * (na - 1) / 2 : na * nb;
+    }
+    b = wave_sum(b);
+    if ((threadIdx.x & (WAVE - 1)) == 0 && b)
+        atomicAdd(out, b);
 }
 
 // Learned-schedule state of one query.
@@ -1311,7 +1431,32 @@ static void eps_graph_impl(const fnn_tree *Tc, const double *epsv,
                 ++novf;  // a second filter pass was needed
             }
         }
-        launch_tiles<M>(false, P, plain, nplain, T, E, ct_d, fp64_dist, o, s);
+        // Plain tiles: count degrees and append each unordered edge to an
+        // edge list, so the fill needs no second tile pass.  The list holds
+        // up to 256 edges per point (bounded by the pairs the tiles can
+        // evaluate and by an eighth of the free device memory); if it
+        // overflows, the fill pass runs instead.
+        bool listed = false;
+        long long nlisted = 0;
+        if (nplain > 0) {
+            unsigned long long *pb_ = S.get<unsigned long long>(1);
+            fill(pb_, 0ull, 1, s);
+            FNN_LAUNCH(k_pair_bound, dim3(grid_for(nplain, 256)), dim3(256), 0, s,
+                       plain, nplain, T->q_pt_begin, T->q_pt_end, pb_);
+            const unsigned long long bound = read_scalar(pb_, s);
+            size_t freeb = 0, totb = 0;
+            FNN_HIP(hipMemGetInfo(&freeb, &totb));
+            const unsigned long long room = (unsigned long long)(freeb / 8 / 12);
+            o.ecap = std::max<unsigned long long>(
+                1024, std::min({bound, room, 256ull * (unsigned long long)n}));
+            o.elist = S.get<int2>(o.ecap);
+            o.edist = S.get<float>(o.ecap);
+            o.ecnt = S.get<unsigned long long>(1);
+            fill(o.ecnt, 0ull, 1, s);
+            launch_tiles<M>(TILE_LIST, P, plain, nplain, T, E, ct_d, fp64_dist, o, s);
+            nlisted = (long long)read_scalar(o.ecnt, s);
+            listed = (unsigned long long)nlisted <= o.ecap;
+        }
         tm.mark();  // 3
 
         scan_i32_to_i64(o.deg, C->row_ptr, n, S);
@@ -1332,7 +1477,11 @@ static void eps_graph_impl(const fnn_tree *Tc, const double *epsv,
         if (nnz > 0) {
             if (use_gram)
                 edges_scatter(gedges, gedist, ngedges, o, s);
-            launch_tiles<M>(true, P, plain, nplain, T, E, ct_d, fp64_dist, o, s);
+            if (listed)
+                edges_scatter(o.elist, o.edist, nlisted, o, s);
+            else
+                launch_tiles<M>(TILE_FILL, P, plain, nplain, T, E, ct_d, fp64_dist,
+                                o, s);
         }
         FNN_LAUNCH(k_cursor_check_rows, dim3(grid_for(n, 256)), dim3(256), 0, s,
                    C->row_ptr, n, o.cursor, (const int32_t *)nullptr, bad);
@@ -1365,7 +1514,7 @@ static void eps_graph_impl(const fnn_tree *Tc, const double *epsv,
         o.spill_cnt = S.get<unsigned long long>(1);
         fill(o.spill_cnt, 0ull, 1, s);
         o.spill_cap = (unsigned long long)spcap;
-        launch_tiles<M>(true, P, plain, nplain, T, E, ct_d, fp64_dist, o, s);
+        launch_tiles<M>(TILE_FILL, P, plain, nplain, T, E, ct_d, fp64_dist, o, s);
         tm.mark();  // 3
         // cursors advanced by every edge, written or not: exact degrees
         o.deg = S.get<int32_t>(n);
@@ -1424,7 +1573,7 @@ static void eps_graph_impl(const fnn_tree *Tc, const double *epsv,
             o2.cursor = S.get<unsigned long long>(n);
             FNN_LAUNCH(k_cursor_init, dim3(grid_for(n, 256)), dim3(256), 0, s,
                        C->row_ptr, n, o2.cursor);
-            launch_tiles<M>(true, P, sub, nsub, T, E, ct_d, fp64_dist, o2, s);
+            launch_tiles<M>(TILE_FILL, P, sub, nsub, T, E, ct_d, fp64_dist, o2, s);
             FNN_LAUNCH(k_cursor_check_rows, dim3(grid_for(n, 256)), dim3(256), 0,
                        s, C->row_ptr, n, o2.cursor, ovf, bad);
         }
