@@ -42,6 +42,10 @@ typedef __attribute__((ext_vector_type(8))) int i32x8;
 
 constexpr int GP = 64;           // rows per pack (max) on the MFMA path
 constexpr int GW = 4;            // packs per group = waves per work-group
+// two waves per SIMD: the second wave hides the first one's LDS and MFMA
+// dependency stalls (one wave per SIMD with 512 registers measured 1.7x
+// slower)
+constexpr int GRAM_WAVES_PER_SIMD = 2;
 
 // ---------------------------------------------------------------- prep ---
 
@@ -250,7 +254,7 @@ struct GramCfg<FNN_PREC_FP8> {
 };
 
 template <int M, int PREC, int NKS>
-__global__ void __launch_bounds__(GT, 8 / GW)
+__global__ void __launch_bounds__(GT, GRAM_WAVES_PER_SIMD)
 k_gram(Pts P, GramArgs G, TileOut out)
 {
     using C = GramCfg<PREC>;
@@ -403,12 +407,21 @@ k_gram(Pts P, GramArgs G, TileOut out)
                 }
             const unsigned char *brow0 = Bs + l32 * ldb;
             const unsigned char *brow1 = Bs + (32 + l32) * ldb;
+            // all of this step's B fragments, read before the matrix-core
+            // chain so no k-step waits on LDS
+            int4 bfrag[PREC == FNN_PREC_BF16 ? nks : 1][2];
+            if constexpr (PREC == FNN_PREC_BF16) {
+#pragma unroll
+                for (int ks = 0; ks < nks; ++ks) {
+                    const int off = (ks * 16 + hi * 8) * 2;
+                    bfrag[ks][0] = *(const int4 *)(brow0 + off);
+                    bfrag[ks][1] = *(const int4 *)(brow1 + off);
+                }
+            }
 #pragma unroll
             for (int ks = 0; ks < nks; ++ks) {
                 if constexpr (PREC == FNN_PREC_BF16) {
-                    const int off = (ks * 16 + hi * 8) * 2;
-                    const int4 bv[2] = {*(const int4 *)(brow0 + off),
-                                        *(const int4 *)(brow1 + off)};
+                    const int4 bv[2] = {bfrag[ks][0], bfrag[ks][1]};
                     const int slot = ks >> 1, half = ks & 1;
 #pragma unroll
                     for (int cb = 0; cb < 2; ++cb) {
