@@ -42,6 +42,7 @@ typedef __attribute__((ext_vector_type(8))) int i32x8;
 
 constexpr int GP = 64;           // rows per pack (max) on the MFMA path
 constexpr int GW = 4;            // packs per group = waves per work-group
+constexpr int UNIT_MAX = 64;     // list entries per work unit (at most)
 // two waves per SIMD: the second wave hides the first one's LDS and MFMA
 // dependency stalls (one wave per SIMD with 512 registers measured 1.7x
 // slower)
@@ -268,6 +269,7 @@ k_gram(Pts P, GramArgs G, TileOut out)
     unsigned char *Bs = smem;                  // [GP][ldb]
     float *ayS = (float *)(smem + GP * ldb);   // [GP]
     float *axS = ayS + GP;                     // [GW][GP]
+    __shared__ int eB[UNIT_MAX], eP[UNIT_MAX], eN[UNIT_MAX], eC[UNIT_MAX];
 
     const int t = threadIdx.x, lane = t & (WAVE - 1), w = t / WAVE;
     const int l32 = lane & 31, hi = lane >> 5;
@@ -285,7 +287,9 @@ k_gram(Pts P, GramArgs G, TileOut out)
     const int xs = xcd * xq + min(xcd, xr);
     const int u0 = xs + (int)(blockIdx.x / 8);
     for (int u = u0; u < G.nunits; u += gridDim.x) {
-        const int e0 = G.ubeg[u], e1 = G.ubeg[u + 1];
+        const int e0 = G.ubeg[u], e1 = min(G.ubeg[u + 1], e0 + UNIT_MAX);
+        if (G.ubeg[u + 1] - e0 > UNIT_MAX && t == 0)
+            atomicOr(out.err, ERR_INDEX);  // the list builders never do this
         const int g = G.lg[e0];
         const int a = G.nn + GW * g + w;       // this wave's pack
         // packs larger than GP (duplicate groups) are tiled by the plain path
@@ -349,10 +353,20 @@ k_gram(Pts P, GramArgs G, TileOut out)
         constexpr int NCH = (GP * CPR + GT - 1) / GT;       // chunks per thread
         int4 pre[NCH];
         float pre_ay = FLT_MAX;
-        auto load_b = [&](int e) {
-            const int bb = G.nn + G.lb[e];
+        // this unit's B packs (id, first point, size, cloud) in LDS: the
+        // entry loop then never waits on a chain of dependent global loads
+        for (int i = t; i < e1 - e0; i += GT) {
+            const int bb = G.nn + G.lb[e0 + i];
             const int pbb = G.q_pb[bb];
-            const int nbb = G.q_pe[bb] - pbb;
+            eB[i] = bb;
+            eP[i] = pbb;
+            eN[i] = G.q_pe[bb] - pbb;
+            eC[i] = G.pcl ? G.pcl[pbb] : -1;
+        }
+        __syncthreads();
+        auto load_b = [&](int e) {
+            const int pbb = eP[e - e0];
+            const int nbb = eN[e - e0];
 #pragma unroll
             for (int i = 0; i < NCH; ++i) {
                 const int c = t + i * GT;
@@ -367,9 +381,9 @@ k_gram(Pts P, GramArgs G, TileOut out)
         };
         load_b(e0);
         for (int e = e0; e < e1; ++e) {
-            const int b = G.nn + G.lb[e];
-            const int pb = G.q_pb[b];
-            const int nb = G.q_pe[b] - pb;
+            const int b = eB[e - e0];
+            const int pb = eP[e - e0];
+            const int nb = eN[e - e0];
             __syncthreads();
 #pragma unroll
             for (int i = 0; i < NCH; ++i) {
@@ -384,7 +398,7 @@ k_gram(Pts P, GramArgs G, TileOut out)
                 load_b(e + 1);
             if (!has_a || b < a)
                 continue;                      // pair handled elsewhere
-            if (ca >= 0 && G.pcl[pb] != ca)
+            if (ca >= 0 && eC[e - e0] != ca)
                 continue;                      // different clouds never connect
             const bool self = (b == a);
             // both 32-column blocks at once: four independent accumulator
@@ -810,7 +824,7 @@ void gram_prepare(const fnn_tree *T, int prec, double eps, const Thr &E,
 
     const int nn = (int)T->nnodes;
     const int npk = (int)T->npacks;
-    const int RUN = 64;  // work unit: at most RUN list entries of one group
+    const int RUN = UNIT_MAX;  // work unit: at most RUN list entries of one group
 
     // ---- near-complete interaction lists: closed-form work list ----------
     // When the traversal kept (almost) every pack pair and no pack is larger
