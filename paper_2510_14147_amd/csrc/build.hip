@@ -336,7 +336,9 @@ k_update(Pts P, const int32_t *__restrict__ ch_hub, const int32_t *__restrict__ 
          const LevelTab *__restrict__ tab, float *__restrict__ cb_D,
          int32_t *__restrict__ cb_id, int kmax, unsigned long long *__restrict__ cnt)
 {
-    __shared__ __align__(16) float cen[UPD_K * UPD_D];
+    // staged centres: UPD_K rows of the point stride (sized at launch, so
+    // low-dimensional inputs keep many work-groups resident)
+    extern __shared__ __align__(16) float cen[];
     // the queue lists the chunks of the hubs still active (device-resident
     // length, so passes need no host round trip)
     const int nq = *qlen;
@@ -1152,10 +1154,12 @@ static void build_impl(fnn_tree *T, const void *points, Scratch &S)
         FNN_LAUNCH(k_iota, dim3(grid_for(NC, 256)), dim3(256), 0, st, qa, NC);
         fill(qlen, NC, 1, st);
         const unsigned gu = grid_for(NC, 1) < 16384u ? grid_for(NC, 1) : 16384u;
+        const size_t upd_lds =
+            (M == M_L2 || M == M_ANG) && T->dp <= UPD_D ? sizeof(float) * UPD_K * T->dp : 16;
         auto pass = [&](hipStream_t s, int k) {
             int32_t *qc = k ? qb : qa, *qx = k ? qa : qb;
             fill(qlen + (1 - k), 0, 1, s);
-            FNN_LAUNCH((k_update<M>), dim3(gu), dim3(CH), 0, s, P, ch_hub, ch_s,
+            FNN_LAUNCH((k_update<M>), dim3(gu), dim3(CH), upd_lds, s, P, ch_hub, ch_s,
                        ch_e, qc, qlen + k, hubs, cent, perm, D, L, tab, cb_D,
                        cb_id, T->opt.kmax, cnt);
             FNN_LAUNCH((k_select<M>), dim3(grid_cap(H, 1, 4096)), dim3(SEL_T), 0, s, P,
