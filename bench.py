@@ -32,6 +32,7 @@ PEAK_HBM_GBS = 8000.0
 PEAK_FP32_VEC_TFLOPS = 157.3
 PEAK_BF16_TFLOPS = 2500.0
 PEAK_FP8_TFLOPS = 5000.0
+PEAK_INT8_TOPS = 5000.0
 
 
 def workload(name: str):
@@ -149,10 +150,21 @@ def measured_traffic(kernel: str, workload: str):
 def roofline(dim, precision, tq, workload=""):
     """Roofline of the dominant kernel of one query: the leaf-tile count pass
     (plain FP32: 3*d flops per pair -- difference, square, accumulate) or the
-    MFMA Gram filter (2*k flops per screened pair, k = padded dim), timed with
-    HIP events inside the library on the stream it runs on."""
+    MFMA Gram filter (2*k flops per screened pair, k = padded dim; on Hamming
+    codes 2*k integer ops, k = code bits), timed with HIP events inside the
+    library on the stream it runs on."""
     if tq["count_ms"] <= 0:
         return None
+    if precision == "i8":
+        ops = 2.0 * dim * tq["filter_pairs"]
+        kms = tq["filter_ms"] if tq.get("filter_ms", 0) > 0 else tq["count_ms"]
+        ach = ops / (kms / 1e3) / 1e12
+        kname = "k_gram<HAM,i8>"
+        return {"bound": "mfma", "achieved": round(ach, 3), "peak": PEAK_INT8_TOPS,
+                "unit": "TOP/s", "frac": round(ach / PEAK_INT8_TOPS, 4),
+                "traffic": measured_traffic(kname, workload),
+                "kernel": kname, "kernel_ms": round(kms, 3),
+                "ops_per_launch": ops}
     if precision != "fp32":
         # the MFMA filter kernel alone, event-timed inside the library
         kq = -(-dim // 16) * 16 if precision == "bf16" else -(-dim // 64) * 64
@@ -185,8 +197,8 @@ def main():
                     help="c2a c2b c2_50k c1 c3 c4 ang | c5 (many clouds, one "
                          "batch per dim) | c5_loop (one call per cloud)")
     ap.add_argument("--precision", default="bf16",
-                    help="fp32 | bf16 | fp8 | auto (c5: fp32 below dim 16, "
-                         "else bf16)")
+                    help="fp32 | bf16 | fp8 | i8 (Hamming codes) | auto (fp32 "
+                         "below dim 16, else bf16; i8 on Hamming codes)")
     ap.add_argument("--sched", default="two_pass")
     ap.add_argument("--cpu-rows", type=int, default=1500)
     ap.add_argument("--c5-clouds", type=int, default=0,
@@ -206,11 +218,17 @@ def main():
     import torch
     import paper_2510_14147_amd as fnn
 
-    def prec_for(dim):
-        if dim == 0:
-            return "fp32"  # integer metrics: no filter precision to choose
+    def prec_for(metric, dim):
+        if metric == "hamming":
+            # the integer filter covers codes of <= 256 bits
+            ok = args.precision in ("i8", "auto") and dim <= 256
+            return "i8" if ok else "fp32"
+        if metric == "levenshtein":
+            return "fp32"  # no filter precision to choose
         if args.precision == "auto":
             return "fp32" if dim < 16 else "bf16"
+        if args.precision == "i8":
+            raise SystemExit("--precision i8 applies to Hamming codes only")
         return args.precision
 
     # jobs: (device points, offsets or None, metric, eps, dim, precision)
@@ -224,11 +242,11 @@ def main():
         for x, off, eps, d in groups:
             xd = torch.from_numpy(x).cuda()
             if args.workload == "c5":
-                jobs.append((xd, off, metric, eps, d, prec_for(d)))
+                jobs.append((xd, off, metric, eps, d, prec_for(metric, d)))
             else:
                 for c in range(len(eps)):
                     jobs.append((xd[int(off[c]):int(off[c + 1])], None, metric,
-                                 eps[c], d, prec_for(d)))
+                                 eps[c], d, prec_for(metric, d)))
         eps_desc = "per-cloud"
         x = None
     else:
@@ -238,8 +256,10 @@ def main():
             xd = torch.from_numpy(x.view(np.int64)).cuda()
         else:
             xd = torch.from_numpy(x).cuda()
-        dim = x.shape[1] if metric in ("l2", "angular") else None
-        jobs.append((xd, None, metric, eps, dim, prec_for(dim or 0)))
+        # coordinates, or code bits on Hamming
+        dim = {"l2": x.shape[1], "angular": x.shape[1],
+               "hamming": 64 * x.shape[1]}.get(metric)
+        jobs.append((xd, None, metric, eps, dim, prec_for(metric, dim or 0)))
         eps_desc = eps
     print(f"[bench] workload {desc} n={n_all} metric={metric} eps={eps_desc} "
           f"jobs={len(jobs)}", file=sys.stderr, flush=True)
@@ -305,7 +325,8 @@ def main():
     value = nnz / (ms / 1e3)
     # dominant kernel: that of the job with the longest count pass
     dom = max(last, key=lambda x: x[1]["count_ms"])
-    roof = roofline(dom[3], dom[4], dom[1], desc) if metric in ("l2", "angular") else None
+    roof = (roofline(dom[3], dom[4], dom[1], desc)
+            if metric in ("l2", "angular") or dom[4] == "i8" else None)
     if roof is not None and len(last) > 1:
         roof["job"] = f"dim {dom[3]}, {dom[4]}"
     precs = sorted({x[4] for x in last})
@@ -339,7 +360,8 @@ def main():
     out["dtype"] = {"fp32": "f32", "bf16": "bf16 filter + f32", "fp8": "fp8 filter + f32"}.get(
         "+".join(precs), "+".join(precs))
     if metric == "hamming":
-        out["dtype"] = "u64 (xor + popcount)"
+        out["dtype"] = ("i8 MFMA (exact integer Gram)" if "i8" in precs
+                        else "u64 (xor + popcount)")
     elif metric == "levenshtein":
         out["dtype"] = "u64 (bit-parallel edit distance)"
     if not args.no_plain and any(o["precision"] != "fp32" for o in opts):

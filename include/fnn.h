@@ -62,7 +62,9 @@ enum {
 typedef enum {
     FNN_PREC_FP32 = 0,   /* direct-difference FP32 tiles (the plain path)      */
     FNN_PREC_BF16 = 1,   /* MFMA BF16 Gram filter, FP32 recompute of survivors */
-    FNN_PREC_FP8 = 2     /* MFMA FP8 (E4M3) Gram filter, FP32 recompute        */
+    FNN_PREC_FP8 = 2,    /* MFMA FP8 (E4M3) Gram filter, FP32 recompute        */
+    FNN_PREC_I8 = 3      /* Hamming codes of <= 256 bits: exact int8 MFMA Gram */
+                         /* (bits as +-1 bytes: s.t = K - 2 d over K bits)     */
 } fnn_precision;
 
 /* How CSR rows are sized. */
@@ -78,7 +80,11 @@ typedef struct fnn_options {
     int32_t struct_size;  /* sizeof(fnn_options)                             */
     int32_t zeta;         /* leaf size (Algorithm 2); default 64             */
     int32_t pack;         /* points per query/leaf tile block; default 64    */
-    int32_t precision;    /* fnn_precision; default FNN_PREC_FP32            */
+    int32_t precision;    /* fnn_precision; default FNN_PREC_FP32.  BF16 and */
+                          /* FP8 apply to L2 / angular with dim <= 128 (else */
+                          /* FNN_EUNSUPPORTED), I8 to Hamming codes of <= 256 */
+                          /* bits (else FNN_EUNSUPPORTED); BF16 / FP8 on      */
+                          /* integer metrics run the plain tiles             */
     int32_t sched;        /* fnn_sched; default FNN_SCHED_TWO_PASS           */
     int32_t validate;     /* 1: also measure the max FP32 distance error     */
                           /* against FP64 and count filter false negatives    */
@@ -190,7 +196,7 @@ int fnn_eps_graph_batch(const fnn_tree *tree, const double *eps,
  * after one untimed run) under candidate options on the caller's input and
  * returns the fastest.  Candidates differ only in options that never change
  * the graph: filter precision (FP32 / BF16 for vector metrics with
- * dim <= 128), schedule (two-pass / learned, when a cost model is
+ * dim <= 128, FP32 / I8 for Hamming codes of <= 256 bits), schedule (two-pass / learned, when a cost model is
  * installed), zeta in {32, 64, 128} and kmax in {32, 64, 128}, searched by
  * coordinate descent from `base` (NULL: defaults; its trace and validate
  * are ignored).  points / offsets / nclouds / dim / metric / eps as in

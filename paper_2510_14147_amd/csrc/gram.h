@@ -55,6 +55,10 @@ struct GramArgs {
     int2 *surv;
     unsigned long long *nsurv;     // running count (may exceed cap)
     long long surv_cap;
+    // exact integer filter (Hamming codes, not validating): the survivors
+    // are the edges, and degp counts the edges of each tree position; null
+    // otherwise
+    int32_t *degp;
 };
 
 // Exact decision of the survivor list: edge list (input ids, FP32 distance)
@@ -63,8 +67,16 @@ void survivors_launch(int metric, const Pts &P, const GramArgs &G,
                       long long nsurv, int2 *edges, float *edist,
                       unsigned long long *nedges, const TileOut &o,
                       hipStream_t s);
+// Unordered edge list (input ids, distance) into the CSR.
 void edges_scatter(const int2 *edges, const float *edist, long long ne,
                    const TileOut &o, hipStream_t s);
+// Survivors of the exact integer filter (tree positions) into the CSR, with
+// their Hamming distances.
+void edges_scatter_ham(const int2 *surv, long long ne, const Pts &P,
+                       const int32_t *perm, const TileOut &o, hipStream_t s);
+// deg[perm[p]] += degp[p] for every tree position p.
+void degrees_from_positions(const int32_t *degp, const int32_t *perm, int n,
+                            int32_t *deg, hipStream_t s);
 
 // eps^2 in the filter's key space, slightly enlarged so that the FP32
 // evaluation of the filter test itself cannot flip a true edge.

@@ -28,6 +28,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <vector>
 
 #include <string.h>
@@ -108,6 +109,23 @@ __global__ void k_absmax(const float *__restrict__ x, int n, int dp,
     m = wave_max(m);
     if ((threadIdx.x & (WAVE - 1)) == 0)
         atomicMax(mx, __float_as_uint(m));
+}
+
+// Hamming codes as signed bytes for the integer Gram: bit b of a code
+// becomes byte b, +1 if set and -1 if not.  Over K = 64 W bits the product
+// of two such rows is s.t = K - 2 d_H, so d_H <= k exactly when
+// s.t >= K - 2k: one integer threshold, no per-point terms.
+__global__ void k_quant_ham(const uint64_t *__restrict__ h, int n, int W,
+                            int8_t *__restrict__ q)
+{
+    const int kq = 64 * W;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+         e < (long long)n * kq; e += (long long)gridDim.x * blockDim.x) {
+        const long long i = e / kq;
+        const int k = (int)(e - i * kq);
+        const int bit = (int)((h[i * W + (k >> 6)] >> (k & 63)) & 1ull);
+        q[e] = (int8_t)(2 * bit - 1);
+    }
 }
 
 // ---------------------------------------------------- interaction lists ---
@@ -253,6 +271,17 @@ struct GramCfg<FNN_PREC_FP8> {
     static constexpr int KSTEP = 64;
     static constexpr int EB = 1;
 };
+template <>
+struct GramCfg<FNN_PREC_I8> {
+    static constexpr int KSTEP = 32;  // code bits (one signed byte each) per MFMA
+    static constexpr int EB = 1;
+};
+
+typedef __attribute__((ext_vector_type(4))) int i32x4;
+typedef __attribute__((ext_vector_type(16))) int i32x16;
+
+__device__ __forceinline__ float vmax(float a, float b) { return fmaxf(a, b); }
+__device__ __forceinline__ int vmax(int a, int b) { return max(a, b); }
 
 template <int M, int PREC, int NKS>
 __global__ void __launch_bounds__(GT, GRAM_WAVES_PER_SIMD)
@@ -267,8 +296,11 @@ k_gram(Pts P, GramArgs G, TileOut out)
     constexpr int ldb = rowb + 16;             // LDS row stride (bytes)
     extern __shared__ __align__(16) unsigned char smem[];
     unsigned char *Bs = smem;                  // [GP][ldb]
-    float *ayS = (float *)(smem + GP * ldb);   // [GP]
-    float *axS = ayS + GP;                     // [GW][GP]
+    // filter terms (integers on the Hamming path, where the test is exact)
+    using V = typename std::conditional<PREC == FNN_PREC_I8, int, float>::type;
+    using ACC = typename std::conditional<PREC == FNN_PREC_I8, i32x16, f32x16>::type;
+    V *ayS = (V *)(smem + GP * ldb);           // [GP]
+    V *axS = ayS + GP;                         // [GW][GP]
     __shared__ int eB[UNIT_MAX], eP[UNIT_MAX], eN[UNIT_MAX], eC[UNIT_MAX];
 
     const int t = threadIdx.x, lane = t & (WAVE - 1), w = t / WAVE;
@@ -313,8 +345,10 @@ k_gram(Pts P, GramArgs G, TileOut out)
                 if (r < na) {
                     const unsigned char *src =
                         (const unsigned char *)G.q + (size_t)(pa + r) * rowb;
-                    if constexpr (PREC == FNN_PREC_BF16) {
-                        // k-step ks: elements ks*16 + hi*8 .. +8 (16 bytes)
+                    if constexpr (PREC == FNN_PREC_BF16 || PREC == FNN_PREC_I8) {
+                        // k-step ks: bytes ks*32 + hi*16 .. +16 (BF16
+                        // elements ks*16 + hi*8 .. +8, or Hamming bits
+                        // ks*32 + hi*16 .. +16 as bytes)
                         #pragma unroll
                         for (int ks = 0; ks < nks; ++ks) {
                             const int4 v = *(const int4 *)(src + (ks * 16 + hi * 8) * 2);
@@ -343,16 +377,22 @@ k_gram(Pts P, GramArgs G, TileOut out)
         // skipped below)
         const int ca = (G.pcl && has_a) ? G.pcl[pa] : -1;
         const float e2 = ca >= 0 ? G.ct[ca].e2f : G.e2f;
-        // stored as the accumulators' start value -ax (scaled units)
-        for (int r = lane; r < GP; r += WAVE)
-            axS[w * GP + r] = (r < na) ? -0.5f * (G.hx[pa + r] - e2) * ginv : -FLT_MAX;
+        // stored as the accumulators' start value -ax (scaled units); on
+        // the Hamming path 2k - K with k = floor(eps), K = code bits, and
+        // the pass test s.t + 2k - K >= 0 is exact
+        for (int r = lane; r < GP; r += WAVE) {
+            if constexpr (PREC == FNN_PREC_I8)
+                axS[w * GP + r] = (r < na) ? 2 * (int)e2 - kq : -(1 << 29);
+            else
+                axS[w * GP + r] = (r < na) ? -0.5f * (G.hx[pa + r] - e2) * ginv : -FLT_MAX;
+        }
 
         // B tiles are software-pipelined: the rows of entry e+1 are loaded
         // into registers while entry e is on the matrix cores.
         constexpr int CPR = rowb / 16;                      // 16-byte chunks per row
         constexpr int NCH = (GP * CPR + GT - 1) / GT;       // chunks per thread
         int4 pre[NCH];
-        float pre_ay = FLT_MAX;
+        V pre_ay = PREC == FNN_PREC_I8 ? (V)(1 << 29) : (V)FLT_MAX;
         // this unit's B packs (id, first point, size, cloud) in LDS: the
         // entry loop then never waits on a chain of dependent global loads
         for (int i = t; i < e1 - e0; i += GT) {
@@ -376,8 +416,12 @@ k_gram(Pts P, GramArgs G, TileOut out)
                     pre[i] = *(const int4 *)((const unsigned char *)G.q +
                                              (size_t)(pbb + r) * rowb + o);
             }
-            if (t < GP)
-                pre_ay = (t < nbb) ? 0.5f * G.hx[pbb + t] : FLT_MAX;
+            if (t < GP) {
+                if constexpr (PREC == FNN_PREC_I8)
+                    pre_ay = (t < nbb) ? (V)0 : (V)(1 << 29);
+                else
+                    pre_ay = (t < nbb) ? (V)(0.5f * G.hx[pbb + t]) : (V)FLT_MAX;
+            }
         };
         load_b(e0);
         for (int e = e0; e < e1; ++e) {
@@ -404,12 +448,13 @@ k_gram(Pts P, GramArgs G, TileOut out)
             // both 32-column blocks at once: four independent accumulator
             // chains [cb][rb] per k-step.  The accumulators start at -ax (in
             // the scaled units of the products), so they end at g~ - ax.
-            f32x16 acc[2][2];
+            ACC acc[2][2];
 #pragma unroll
             for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
                 for (int q4 = 0; q4 < 4; ++q4) {
-                    const float4 a4 = *reinterpret_cast<const float4 *>(
+                    using V4 = typename std::conditional<PREC == FNN_PREC_I8, int4, float4>::type;
+                    const V4 a4 = *reinterpret_cast<const V4 *>(
                         axS + w * GP + rb * 32 + 8 * q4 + 4 * hi);
 #pragma unroll
                     for (int cb = 0; cb < 2; ++cb) {
@@ -423,8 +468,9 @@ k_gram(Pts P, GramArgs G, TileOut out)
             const unsigned char *brow1 = Bs + (32 + l32) * ldb;
             // all of this step's B fragments, read before the matrix-core
             // chain so no k-step waits on LDS
-            int4 bfrag[PREC == FNN_PREC_BF16 ? nks : 1][2];
-            if constexpr (PREC == FNN_PREC_BF16) {
+            constexpr bool B16 = PREC == FNN_PREC_BF16 || PREC == FNN_PREC_I8;
+            int4 bfrag[B16 ? nks : 1][2];
+            if constexpr (B16) {
 #pragma unroll
                 for (int ks = 0; ks < nks; ++ks) {
                     const int off = (ks * 16 + hi * 8) * 2;
@@ -434,7 +480,24 @@ k_gram(Pts P, GramArgs G, TileOut out)
             }
 #pragma unroll
             for (int ks = 0; ks < nks; ++ks) {
-                if constexpr (PREC == FNN_PREC_BF16) {
+                if constexpr (PREC == FNN_PREC_I8) {
+                    // 16 bytes per lane and k-step, the BF16 byte layout
+                    const int slot = ks >> 1, half = ks & 1;
+#pragma unroll
+                    for (int cb = 0; cb < 2; ++cb) {
+                        i32x4 bb;
+                        __builtin_memcpy(&bb, &bfrag[ks][cb], 16);
+#pragma unroll
+                        for (int rb = 0; rb < 2; ++rb) {
+                            const i32x4 aa = (i32x4){Areg[rb][slot][half * 4 + 0],
+                                                     Areg[rb][slot][half * 4 + 1],
+                                                     Areg[rb][slot][half * 4 + 2],
+                                                     Areg[rb][slot][half * 4 + 3]};
+                            acc[cb][rb] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
+                                aa, bb, acc[cb][rb], 0, 0, 0);
+                        }
+                    }
+                } else if constexpr (PREC == FNN_PREC_BF16) {
                     const int4 bv[2] = {bfrag[ks][0], bfrag[ks][1]};
                     const int slot = ks >> 1, half = ks & 1;
 #pragma unroll
@@ -475,17 +538,17 @@ k_gram(Pts P, GramArgs G, TileOut out)
             // past nb carry ay = FLT_MAX, so neither can pass).  Only when
             // some lane may hold a survivor (rare), on a self pair, or when
             // validating does the wave build per-pair masks.
-            float ayc[2], mx[2];
+            V ayc[2], mx[2];
 #pragma unroll
             for (int cb = 0; cb < 2; ++cb) {
                 ayc[cb] = ayS[cb * 32 + l32];
-                mx[cb] = -FLT_MAX;
+                mx[cb] = acc[cb][0][0];
 #pragma unroll
                 for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
                     for (int q = 0; q < 16; ++q)
-                        mx[cb] = fmaxf(mx[cb], acc[cb][rb][q]);
-                if (PREC != FNN_PREC_BF16)
+                        mx[cb] = vmax(mx[cb], acc[cb][rb][q]);
+                if constexpr (PREC == FNN_PREC_FP8)
                     mx[cb] *= G.gscale;
             }
             if (__any(mx[0] >= ayc[0] || mx[1] >= ayc[1]) || self || G.validate) {
@@ -494,7 +557,7 @@ k_gram(Pts P, GramArgs G, TileOut out)
                 if (cb * 32 >= nb)
                     break;
                 const int col = cb * 32 + l32;
-                const float ay = ayc[cb];
+                const V ay = ayc[cb];
                 unsigned pm = 0, om = 0;
 #pragma unroll
                 for (int rb = 0; rb < 2; ++rb) {
@@ -502,8 +565,8 @@ k_gram(Pts P, GramArgs G, TileOut out)
                     for (int q = 0; q < 16; ++q) {
                         const int row = rb * 32 + 8 * (q >> 2) + 4 * hi + (q & 3);
                         const bool ok = row < na && col < nb && (!self || row < col);
-                        const float gq = PREC == FNN_PREC_BF16 ? acc[cb][rb][q]
-                                                               : acc[cb][rb][q] * G.gscale;
+                        const V gq = PREC == FNN_PREC_FP8 ? (V)(acc[cb][rb][q] * G.gscale)
+                                                          : (V)acc[cb][rb][q];
                         const bool pass = ok && (gq >= ay);
                         pm |= (unsigned)pass << (rb * 16 + q);
                         om |= (unsigned)ok << (rb * 16 + q);
@@ -536,7 +599,18 @@ k_gram(Pts P, GramArgs G, TileOut out)
                             G.surv[o] = make_int2(pa + row,
                                                   (pb + col) | (int)(((pm >> bit) & 1u) << 31));
                         ++o;
+                        if constexpr (PREC == FNN_PREC_I8)
+                            if (G.degp)
+                                atomicAdd(&G.degp[pa + row], 1);
                     }
+                }
+                if constexpr (PREC == FNN_PREC_I8) {
+                    // exact filter, not validating: the survivors are the
+                    // edges; column degrees summed over the two row halves
+                    // of each column (lanes l and l + 32)
+                    const int cdeg = mine + __shfl_xor(mine, 32, WAVE);
+                    if (G.degp && hi == 0 && cdeg)
+                        atomicAdd(&G.degp[pb + col], cdeg);
                 }
             }
             }
@@ -593,8 +667,14 @@ k_survive(Pts P, GramArgs G, long long ns, int2 *__restrict__ edges,
             const bool passed = (e.y >> 31) & 1;
             npass += passed;
             const Thr E = G.pcl ? G.ct[G.pcl[pi]].E : G.E;
-            const float k = key32_seq<M>(P, pi, pj);
-            if (k < E.lo) {
+            float k;
+            if constexpr (M == M_HAM)
+                k = key32<M>(P, pi, pj);
+            else
+                k = key32_seq<M>(P, pi, pj);
+            if constexpr (M == M_HAM) {
+                edge = k <= E.lo;  // integer distance, exact
+            } else if (k < E.lo) {
                 edge = true;
             } else if (k > E.hi) {
                 edge = false;
@@ -611,11 +691,13 @@ k_survive(Pts P, GramArgs G, long long ns, int2 *__restrict__ edges,
                 if (!passed)
                     ++nmis;  // validate: the filter would have lost this edge
                 dd = edge_dist<M>(P, pi, pj, k, G.fp64_dist);
-                if (G.validate) {
+                if (M != M_HAM && G.validate) {
                     float ref;
                     if constexpr (M == M_L2)
                         ref = (float)sqrt(l2_sq64(P.x + (size_t)pi * P.dp,
                                                   P.x + (size_t)pj * P.dp, P.dim));
+                    else if constexpr (M == M_HAM)
+                        ref = dd;
                     else
                         ref = (float)ang_dist64(P.x + (size_t)pi * P.dp,
                                                 P.x + (size_t)pj * P.dp, P.dim);
@@ -657,6 +739,8 @@ k_survive(Pts P, GramArgs G, long long ns, int2 *__restrict__ edges,
     }
 }
 
+// Writes an unordered edge list (input ids, distance) into the CSR slots of
+// both endpoints.
 __global__ void k_edges_scatter(const int2 *__restrict__ edges,
                                 const float *__restrict__ edist, long long ne,
                                 TileOut out)
@@ -689,6 +773,9 @@ void survivors_launch(int metric, const Pts &P, const GramArgs &G,
     if (metric == M_L2)
         FNN_LAUNCH((k_survive<M_L2>), g, dim3(256), 0, s, P, G, nsurv, edges,
                    edist, nedges, o);
+    else if (metric == M_HAM)
+        FNN_LAUNCH((k_survive<M_HAM>), g, dim3(256), 0, s, P, G, nsurv, edges,
+                   edist, nedges, o);
     else
         FNN_LAUNCH((k_survive<M_ANG>), g, dim3(256), 0, s, P, G, nsurv, edges,
                    edist, nedges, o);
@@ -701,6 +788,59 @@ void edges_scatter(const int2 *edges, const float *edist, long long ne,
         return;
     FNN_LAUNCH(k_edges_scatter, dim3(grid_for(ne, 256)), dim3(256), 0, s, edges,
                edist, ne, o);
+}
+
+// Edges of the exact integer filter (tree positions, passed flag in bit 31
+// of .y) into the CSR: distance from the codes, positions mapped to input
+// ids.
+__global__ void k_edges_scatter_ham(const int2 *__restrict__ surv, long long ne,
+                                    const uint64_t *__restrict__ h, int W,
+                                    const int32_t *__restrict__ perm, TileOut out)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < ne;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int2 e = surv[i];
+        const int pi = e.x, pj = e.y & 0x7FFFFFFF;
+        const float d = (float)ham_words(h + (size_t)pi * W, h + (size_t)pj * W, W);
+        const int oi = perm[pi], oj = perm[pj];
+        const unsigned long long s1 = atomicAdd(&out.cursor[oi], 1ull);
+        const unsigned long long s2 = atomicAdd(&out.cursor[oj], 1ull);
+        if (s1 < out.nnz && s2 < out.nnz) {
+            out.col[s1] = oj;
+            out.dist[s1] = d;
+            out.col[s2] = oi;
+            out.dist[s2] = d;
+        } else {
+            atomicOr(out.err, ERR_INDEX);
+        }
+    }
+}
+
+void edges_scatter_ham(const int2 *surv, long long ne, const Pts &P,
+                       const int32_t *perm, const TileOut &o, hipStream_t s)
+{
+    if (ne <= 0)
+        return;
+    FNN_LAUNCH(k_edges_scatter_ham, dim3(grid_for(ne, 256)), dim3(256), 0, s, surv,
+               ne, P.h, P.dp, perm, o);
+}
+
+__global__ void k_deg_from_positions(const int32_t *__restrict__ degp,
+                                     const int32_t *__restrict__ perm, int n,
+                                     int32_t *__restrict__ deg)
+{
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < n;
+         p += gridDim.x * blockDim.x)
+        deg[perm[p]] += degp[p];
+}
+
+void degrees_from_positions(const int32_t *degp, const int32_t *perm, int n,
+                            int32_t *deg, hipStream_t s)
+{
+    if (n <= 0)
+        return;
+    FNN_LAUNCH(k_deg_from_positions, dim3(grid_cap(n, 256, 16384)), dim3(256), 0, s,
+               degp, perm, n, deg);
 }
 
 template <int M, int PREC, int NKS>
@@ -721,7 +861,14 @@ static void launch_gram(bool fill_pass, const Pts &P, const GramArgs &G,
     if (G.nunits <= 0)
         return;
     const int nks = G.kq / GramCfg<PREC>::KSTEP;
-    if constexpr (PREC == FNN_PREC_BF16) {
+    if constexpr (PREC == FNN_PREC_I8) {
+        switch (nks) {
+        case 2: launch_gram_k<M, PREC, 2>(fill_pass, P, G, o, s); break;
+        case 4: launch_gram_k<M, PREC, 4>(fill_pass, P, G, o, s); break;
+        case 6: launch_gram_k<M, PREC, 6>(fill_pass, P, G, o, s); break;
+        default: launch_gram_k<M, PREC, 8>(fill_pass, P, G, o, s); break;
+        }
+    } else if constexpr (PREC == FNN_PREC_BF16) {
         switch (nks) {
         case 1: launch_gram_k<M, PREC, 1>(fill_pass, P, G, o, s); break;
         case 2: launch_gram_k<M, PREC, 2>(fill_pass, P, G, o, s); break;
@@ -743,7 +890,9 @@ static void launch_gram(bool fill_pass, const Pts &P, const GramArgs &G,
 void gram_launch(int metric, int prec, bool fill_pass, const Pts &P,
                  const GramArgs &G, const TileOut &o, hipStream_t s)
 {
-    if (metric == M_L2) {
+    if (metric == M_HAM) {
+        launch_gram<M_HAM, FNN_PREC_I8>(fill_pass, P, G, o, s);
+    } else if (metric == M_L2) {
         if (prec == FNN_PREC_BF16)
             launch_gram<M_L2, FNN_PREC_BF16>(fill_pass, P, G, o, s);
         else
@@ -760,20 +909,41 @@ void gram_launch(int metric, int prec, bool fill_pass, const Pts &P,
 
 float gram_eps2(int metric, double eps, const Thr &E)
 {
+    if (metric == M_HAM)
+        return std::min(E.lo, 1048576.f);  // floor(eps); beyond any code length
     const double u32 = 1.0 / 16777216.0;
     const double T2 = metric == M_L2 ? eps * eps : 2.0 - 2.0 * E.p64;
     return (float)(T2 * (1.0 + 320.0 * u32) + 1e-30);
 }
 
-// Quantised copy + per-point terms, and the MFMA work lists, for one query.
-void gram_prepare(const fnn_tree *T, int prec, double eps, const Thr &E,
-                  const int2 *inter, long long ninter, Scratch &S, GramArgs &G,
-                  int2 **rest, long long *nrest)
+// Hamming codes as +-1 bytes for the integer filter; no centring or
+// scaling, the test is exact.
+static void quantise_ham(const fnn_tree *T, int prec, Scratch &S, GramArgs &G)
+{
+    hipStream_t s = S.stream();
+    const int n = (int)T->n, dp = T->dp;
+    const int kq = dp * 64;
+    if (prec != FNN_PREC_I8 || kq > 256)
+        fail(FNN_EUNSUPPORTED, "integer MFMA filter supports codes of <= 256 bits");
+    G.gscale = 1.f;
+    G.kq = kq;
+    int8_t *qb = (int8_t *)S.raw((size_t)n * kq + 64);
+    G.q = qb;
+    G.hx = nullptr;  // no per-point terms
+    FNN_LAUNCH(k_quant_ham, dim3(grid_cap((int64_t)n * kq, 256, 16384)), dim3(256), 0,
+               s, T->h, n, dp, qb);
+}
+
+// Centred, shrunk BF16 or FP8 copy of the coordinates and the per-point
+// norms of the filter.
+static void quantise_real(const fnn_tree *T, int prec, Scratch &S, GramArgs &G)
 {
     hipStream_t s = S.stream();
     const int n = (int)T->n, dp = T->dp;
     const int d = T->dim;
     const float *X = T->metric == M_ANG ? T->xn : T->x;
+    if (prec == FNN_PREC_I8)
+        fail(FNN_EUNSUPPORTED, "integer MFMA filter is for Hamming codes");
     const int KS = prec == FNN_PREC_BF16 ? 16 : 64;
     const int kq = (int)cdiv(dp, KS) * KS;
     if (kq > 128)
@@ -819,6 +989,18 @@ void gram_prepare(const fnn_tree *T, int prec, double eps, const Thr &E,
         FNN_LAUNCH((k_quant<FNN_PREC_FP8>), dim3(grid_cap(n, 4, 16384)), dim3(256), 0,
                    s, X, n, dp, kq, sums, 1.0f / n, scale, (float)(1.0 - c1), qbuf,
                    hxbuf);
+}
+
+// Quantised copy + per-point terms, and the MFMA work lists, for one query.
+void gram_prepare(const fnn_tree *T, int prec, double eps, const Thr &E,
+                  const int2 *inter, long long ninter, Scratch &S, GramArgs &G,
+                  int2 **rest, long long *nrest)
+{
+    hipStream_t s = S.stream();
+    if (T->metric == M_HAM)
+        quantise_ham(T, prec, S, G);
+    else
+        quantise_real(T, prec, S, G);
     G.e2f = gram_eps2(T->metric, eps, E);
     G.E = E;
 

@@ -1266,6 +1266,8 @@ static void eps_graph_impl(const fnn_tree *Tc, const double *epsv,
                            Scratch &S, float **trace_feat, float **trace_targ)
 {
     fnn_tree *T = const_cast<fnn_tree *>(Tc);  // lazily built caches only
+    if (opt.precision == FNN_PREC_I8 && (M != M_HAM || T->dp > 4))
+        fail(FNN_EUNSUPPORTED, "integer MFMA filter is for Hamming codes of <= 256 bits");
     hipStream_t s = S.stream();
     const int n = (int)T->n;
     Timer tm(s);
@@ -1340,12 +1342,14 @@ static void eps_graph_impl(const fnn_tree *Tc, const double *epsv,
     traverse<M>(T, P, Q, pr, S, &inter, &ninter, st);
     tm.mark();  // 1
 
-    // ---- MFMA filter set-up (vector metrics, dim <= 128) ----------------
-    const bool use_gram = (M == M_L2 || M == M_ANG) && opt.precision != FNN_PREC_FP32;
+    // ---- MFMA filter set-up (vector metrics with dim <= 128, Hamming codes
+    // of <= 256 bits) ------------------------------------------------------
+    const bool use_gram = ((M == M_L2 || M == M_ANG) && opt.precision != FNN_PREC_FP32) ||
+                          (M == M_HAM && opt.precision == FNN_PREC_I8);
     GramArgs G{};
     int2 *plain = inter;
     long long nplain = ninter;
-    if constexpr (M == M_L2 || M == M_ANG) {
+    if constexpr (M == M_L2 || M == M_ANG || M == M_HAM) {
         if (use_gram) {
             gram_prepare(T, opt.precision, eps, E, inter, ninter, S, G, &plain,
                          &nplain);
@@ -1383,7 +1387,12 @@ static void eps_graph_impl(const fnn_tree *Tc, const double *epsv,
         if (use_gram) {
             unsigned long long *ns = S.get<unsigned long long>(2);
             Events fev(s);
-            long long cap = std::max<long long>(1ll << 24, 64ll * n);
+            // survivor list: up to 256 entries per point while they fit in
+            // an eighth of the free device memory, at least 64 per point
+            size_t freeb = 0, totb = 0;
+            FNN_HIP(hipMemGetInfo(&freeb, &totb));
+            const long long room = (long long)(freeb / 8 / sizeof(int2));
+            long long cap = std::max({1ll << 24, 64ll * n, std::min(room, 256ll * n)});
             if (learned) {
                 // predicted ordered edges / 2, times the filter's survivor
                 // factor (BF16 ~1.5, FP8 tens on high-dimensional data)
@@ -1396,15 +1405,25 @@ static void eps_graph_impl(const fnn_tree *Tc, const double *epsv,
                 double hacc[3];
                 FNN_HIP(hipMemcpyAsync(hacc, acc, sizeof hacc, hipMemcpyDeviceToHost, s));
                 FNN_HIP(hipStreamSynchronize(s));
-                const double fac = opt.precision == FNN_PREC_BF16 ? 2.0 : 40.0;
+                const double fac = opt.precision == FNN_PREC_I8     ? 1.25
+                                   : opt.precision == FNN_PREC_BF16 ? 2.0
+                                                                    : 40.0;
                 cap = std::max<long long>(1ll << 20, (long long)(0.5 * hacc[1] * fac));
             }
             if (opt.validate)
                 cap = std::max<long long>(cap, (long long)n * (n - 1) / 2 + 1);
+            // the integer filter on Hamming codes is exact: unless validating,
+            // it writes the edges, their distances and the degrees itself
+            const bool direct = M == M_HAM && !opt.validate;
+            int32_t *degp = direct ? S.get<int32_t>(n) : nullptr;
             for (int attempt = 0;; ++attempt) {
                 G.surv = S.get<int2>(cap);
                 G.surv_cap = cap;
                 G.nsurv = ns;
+                if (direct) {
+                    G.degp = degp;
+                    fill(degp, 0, n, s);
+                }
                 fill(ns, 0ull, 2, s);
                 fill(cnt + 2, 0ull, 1, s);
                 FNN_HIP(hipEventRecord(fev[0], s));
@@ -1414,16 +1433,23 @@ static void eps_graph_impl(const fnn_tree *Tc, const double *epsv,
                 if (got <= cap || attempt > 0) {
                     if (got > cap)
                         fail(FNN_EINTERNAL, "survivor list overflow");
-                    gedges = S.get<int2>(got + 1);
-                    gedist = S.get<float>(got + 1);
                     {
                         float fms = 0.f;
                         FNN_HIP(hipEventSynchronize(fev[1]));
                         FNN_HIP(hipEventElapsedTime(&fms, fev[0], fev[1]));
                         st.filter_ms = fms;
                     }
-                    survivors_launch(M, P, G, got, gedges, gedist, ns + 1, o, s);
-                    ngedges = (long long)read_scalar(ns + 1, s);
+                    if (direct) {
+                        degrees_from_positions(degp, T->perm, n, o.deg, s);
+                        fill(cnt + 3, (unsigned long long)got, 1, s);
+                        gedges = G.surv;
+                        ngedges = got;
+                    } else {
+                        gedges = S.get<int2>(got + 1);
+                        gedist = S.get<float>(got + 1);
+                        survivors_launch(M, P, G, got, gedges, gedist, ns + 1, o, s);
+                        ngedges = (long long)read_scalar(ns + 1, s);
+                    }
                     break;
                 }
                 S.release(G.surv);
@@ -1475,7 +1501,9 @@ static void eps_graph_impl(const fnn_tree *Tc, const double *epsv,
         o.dist = C->dist;
         o.nnz = (unsigned long long)nnz;
         if (nnz > 0) {
-            if (use_gram)
+            if (G.degp)
+                edges_scatter_ham(gedges, ngedges, P, T->perm, o, s);
+            else if (use_gram)
                 edges_scatter(gedges, gedist, ngedges, o, s);
             if (listed)
                 edges_scatter(o.elist, o.edist, nlisted, o, s);

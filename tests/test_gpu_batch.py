@@ -157,6 +157,16 @@ def test_batch_hamming(fnn, orc):
     run_batch(fnn, orc, clouds, "hamming", eps, zeta=8)
 
 
+def test_batch_hamming_int8(fnn, orc):
+    # integer MFMA filter over clouds of 256-bit codes, each with its own
+    # radius; groups of packs that span clouds skip the cross-cloud pairs
+    clouds = [G.random_codes(n, 256, seed=80 + i, flip=0.06) if n else
+              np.zeros((0, 4), np.uint64)
+              for i, n in enumerate([2000, 1, 0, 900, 3000, 70])]
+    eps = [30, 3, 9, 20, 26, 40]
+    run_batch(fnn, orc, clouds, "hamming", eps, zeta=8, precision="i8", validate=1)
+
+
 def test_batch_levenshtein(fnn, orc):
     clouds = [G.random_strings(n, seed=60 + i, stride=64, min_len=20, max_len=60)
               for i, n in enumerate([400, 2, 700, 300])]

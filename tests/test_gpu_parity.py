@@ -146,3 +146,46 @@ def test_mfma_filter_screens(fnn, orc):
     st = g.stats
     assert st["filter_survivors"] < 0.05 * st["filter_pairs"]
     assert st["filter_survivors"] >= g.nnz // 2
+
+
+# ---- integer MFMA filter (Hamming codes as bytes) ---------------------------
+
+@pytest.mark.parametrize("bits", [64, 128, 192, 256])
+@pytest.mark.parametrize("validate", [False, True])
+def test_int8_hamming_parity(fnn, orc, bits, validate):
+    # 3001 codes: a ragged last tile; clustered so that the graph is not empty
+    x = G.random_codes(3001, bits, seed=900 + bits, n_centers=12, flip=0.08)
+    tree, g, cmp = check(fnn, orc, x, "hamming", 0.12 * bits, tree_check=False,
+                         precision="i8", validate=validate)
+    st = g.stats
+    assert st["filter_pairs"] > 0
+    assert st["validate_mismatch"] == 0
+    # the integer test is exact: every pair it passes is an edge
+    assert 0 < st["filter_survivors"] <= g.nnz // 2
+
+
+@pytest.mark.parametrize("eps", [0.5, 5.5, 1e9])
+def test_int8_hamming_edge_radii(fnn, orc, eps):
+    # eps < 1 keeps exact duplicates only, a fractional eps rounds down,
+    # eps beyond the code length connects every pair
+    x = G.random_codes(700, 128, seed=31, n_centers=5, flip=0.03)
+    x[100:140] = x[7]
+    check(fnn, orc, x, "hamming", eps, tree_check=False, precision="i8", validate=True)
+
+
+def test_int8_hamming_duplicates(fnn, orc):
+    x = np.repeat(G.random_codes(3, 256, seed=8), 150, axis=0)
+    check(fnn, orc, x, "hamming", 2.0, tree_check=False, precision="i8")
+
+
+def test_int8_rejects_other_inputs(fnn, orc):
+    x = G.random_points(300, 8, seed=1)
+    tree = fnn.fnn_tree_build(x, "l2")
+    with pytest.raises(fnn.FnnError) as e:
+        fnn.fnn_eps_graph(tree, 0.5, precision="i8")
+    assert e.value.code == fnn.FNN_EUNSUPPORTED
+    codes = G.random_codes(300, 512, seed=2)
+    tree = fnn.fnn_tree_build(codes, "hamming")
+    with pytest.raises(fnn.FnnError) as e:
+        fnn.fnn_eps_graph(tree, 40, precision="i8")
+    assert e.value.code == fnn.FNN_EUNSUPPORTED

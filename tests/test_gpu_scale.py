@@ -94,3 +94,10 @@ def test_c3_full_size_sampled(fnn, orc):
 def test_c4_full_size_sampled(fnn, orc):
     x = G.c4_strings()
     sampled_rows(fnn, orc, x, "levenshtein", 6.0, 100, 24)
+
+
+def test_c3_full_size_sampled_int8(fnn, orc):
+    # the integer MFMA filter on the 2M x 256-bit workload
+    x = G.c3_hamming()
+    g = sampled_rows(fnn, orc, x, "hamming", 24.0, 100, 25, precision="i8")
+    assert g.stats["filter_survivors"] <= g.nnz // 2
