@@ -159,24 +159,30 @@ def roofline(dim, precision, tq, workload=""):
         ops = 2.0 * dim * tq["filter_pairs"]
         kms = tq["filter_ms"] if tq.get("filter_ms", 0) > 0 else tq["count_ms"]
         ach = ops / (kms / 1e3) / 1e12
-        kname = "k_gram<HAM,i8>"
+        kname = f"k_gram<HAM,i8,k{dim}>"
         return {"bound": "mfma", "achieved": round(ach, 3), "peak": PEAK_INT8_TOPS,
                 "unit": "TOP/s", "frac": round(ach / PEAK_INT8_TOPS, 4),
                 "traffic": measured_traffic(kname, workload),
                 "kernel": kname, "kernel_ms": round(kms, 3),
                 "ops_per_launch": ops}
     if precision != "fp32":
-        # the MFMA filter kernel alone, event-timed inside the library
-        kq = -(-dim // 16) * 16 if precision == "bf16" else -(-dim // 64) * 64
+        # the MFMA filter kernel alone, event-timed inside the library; k is
+        # the padded width it ran on: the leading principal coordinates when
+        # the library projected (proj_dim), else the coordinates
+        k = tq.get("proj_dim", 0) or dim
+        kq = -(-k // 16) * 16 if precision == "bf16" else -(-k // 64) * 64
         flops = 2.0 * kq * tq["filter_pairs"]
         kms = tq["filter_ms"] if tq.get("filter_ms", 0) > 0 else tq["count_ms"]
         ach = flops / (kms / 1e3) / 1e12
         peak = PEAK_BF16_TFLOPS if precision == "bf16" else PEAK_FP8_TFLOPS
-        kname = f"k_gram<L2,{precision}>"
+        if precision == "bf16" and kq <= 32:
+            kname = f"k_gram_direct<L2,bf16,k{kq}>"
+        else:
+            kname = f"k_gram<L2,{precision},k{kq}>"
         return {"bound": "mfma", "achieved": round(ach, 3), "peak": peak,
                 "unit": "TFLOP/s", "frac": round(ach / peak, 4),
                 "traffic": measured_traffic(kname, workload),
-                "kernel": kname, "kernel_ms": round(kms, 3),
+                "kernel": kname, "kernel_ms": round(kms, 3), "k": kq,
                 "flops_per_launch": flops}
     flops = 3.0 * dim * tq["tile_pairs"]
     ach = flops / (tq["count_ms"] / 1e3) / 1e12
@@ -200,6 +206,9 @@ def main():
                     help="fp32 | bf16 | fp8 | i8 (Hamming codes) | auto (fp32 "
                          "below dim 16, else bf16; i8 on Hamming codes)")
     ap.add_argument("--sched", default="two_pass")
+    ap.add_argument("--proj", type=int, default=0,
+                    help="filter on leading principal coordinates: 0 automatic, "
+                         "-1 off, else their number (multiple of 16)")
     ap.add_argument("--cpu-rows", type=int, default=1500)
     ap.add_argument("--c5-clouds", type=int, default=0,
                     help="use only the first K clouds of c5 (0: all 256)")
@@ -268,7 +277,7 @@ def main():
     # options per job: defaults with --precision / --sched, or tuned
     opts, tuning = [], []
     for xd, off, m, e, d, p in jobs:
-        o = {"precision": p, "sched": args.sched}
+        o = {"precision": p, "sched": args.sched, "proj": args.proj}
         if args.tune:
             t0 = time.perf_counter()
             o2 = off if off is not None else np.array([0, xd.shape[0]], np.int64)
@@ -289,11 +298,11 @@ def main():
             if off is None:
                 tree = fnn.fnn_tree_build(xd, m, **bo)
                 g = fnn.fnn_eps_graph(tree, e, precision=o["precision"],
-                                      sched=o["sched"])
+                                      sched=o["sched"], proj=o.get("proj", 0))
             else:
                 tree = fnn.fnn_tree_build_batch(xd, off, m, **bo)
                 g = fnn.fnn_eps_graph_batch(tree, e, precision=o["precision"],
-                                            sched=o["sched"])
+                                            sched=o["sched"], proj=o.get("proj", 0))
             res.append((tree.stats, g.stats, g.nnz, d, o["precision"]))
             del tree, g
         return res
@@ -340,6 +349,7 @@ def main():
                    "dim": None if groups else jobs[0][4], "metric": metric,
                    "eps": None if groups else eps, "precision": "+".join(precs),
                    "sched": "+".join(sorted({o["sched"] for o in opts})),
+                   "filter_proj_dim": sorted({int(x[1].get("proj_dim", 0)) for x in last}),
                    "nnz": int(nnz),
                    "mean_neighbors": nnz / n_all, "calls": len(jobs)},
         "dist_evals_per_s": evals / (ms / 1e3),

@@ -98,7 +98,14 @@ typedef struct fnn_options {
                           /* hipGraph and replayed between host checks      */
                           /* (default 4, rounded up to even; 1 = one eager  */
                           /* pass per host check)                           */
-    int32_t reserved[6];
+    int32_t proj;         /* BF16 / FP8 filter on the K leading principal    */
+                          /* coordinates (a conservative bound: |Q^T(x-y)|   */
+                          /* <= ||Q|| |x-y|): 0 = K the smallest multiple of */
+                          /* 16 with twice the residual variance <= eps^2/2, */
+                          /* if below the padded dim, else none (default);   */
+                          /* -1 = none; 16..128 in steps of 16 = that K;     */
+                          /* else EINVAL                                     */
+    int32_t reserved[5];
 } fnn_options;
 
 typedef struct fnn_tree fnn_tree;  /* opaque; device-resident cover tree */
@@ -143,7 +150,10 @@ typedef struct fnn_stats {
     double pred_mae;          /* learned: mean |predicted - true| log1p(deg) */
     double pred_sum_ratio;    /* learned: sum predicted / sum true degrees    */
     double filter_ms;         /* MFMA filter kernel alone (last launch)       */
-    double reserved[4];
+    int64_t proj_dim;         /* principal coordinates the filter used (0:   */
+                              /* the coordinates themselves)                 */
+    double proj_captured;     /* their share of the variance                  */
+    double reserved[2];
 } fnn_stats;
 
 /* Build the cover tree of n points (Algorithms 1-2).  points: device

@@ -42,7 +42,7 @@ class fnn_options(ctypes.Structure):
                 ("sched", ctypes.c_int32), ("validate", ctypes.c_int32),
                 ("kmax", ctypes.c_int32), ("trace", ctypes.c_int32),
                 ("slack_pct", ctypes.c_int32), ("graph_passes", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 6)]
+                ("proj", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
 
 
 class fnn_tune_result(ctypes.Structure):
@@ -71,7 +71,8 @@ _STAT_F64 = ["max_rel_err", "build_ms", "traverse_ms", "tile_ms", "count_ms",
 class fnn_stats(ctypes.Structure):
     _fields_ = ([(k, ctypes.c_int64) for k in _STAT_I64] +
                 [(k, ctypes.c_double) for k in _STAT_F64] +
-                [("reserved", ctypes.c_double * 4)])
+                [("proj_dim", ctypes.c_int64), ("proj_captured", ctypes.c_double),
+                 ("reserved", ctypes.c_double * 2)])
 
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -185,7 +186,7 @@ def _options(**kw) -> fnn_options:
 def _stats(handle) -> dict:
     s = fnn_stats()
     _check(lib().fnn_get_stats(handle, ctypes.byref(s)))
-    return {k: getattr(s, k) for k in _STAT_I64 + _STAT_F64}
+    return {k: getattr(s, k) for k in _STAT_I64 + _STAT_F64 + ["proj_dim", "proj_captured"]}
 
 
 class Tree:
@@ -306,7 +307,8 @@ def fnn_tree_build_batch(points, offsets, metric: str = "l2", zeta=None,
 
 
 def fnn_eps_graph_batch(tree: Tree, eps, precision="fp32", sched="two_pass",
-                        validate=False, trace=False, slack_pct=None) -> Graph:
+                        validate=False, trace=False, slack_pct=None,
+                        proj=None) -> Graph:
     """Per-cloud thresholds ``eps[c]``; one block-diagonal CSR over all rows."""
     if sched == "learned" and not _model_set and os.path.exists(COST_MODEL_PATH):
         fnn_set_cost_model(load_cost_model())
@@ -314,14 +316,14 @@ def fnn_eps_graph_batch(tree: Tree, eps, precision="fp32", sched="two_pass",
     _bind_stream()
     out = ctypes.POINTER(fnn_csr)()
     o = _options(precision=precision, sched=sched, validate=int(validate),
-                 trace=int(trace), slack_pct=slack_pct)
+                 trace=int(trace), slack_pct=slack_pct, proj=proj)
     _check(lib().fnn_eps_graph_batch(
         tree.handle, e.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), e.size,
         ctypes.byref(o), ctypes.byref(out)))
     return Graph(out)
 
 
-_OPT_KEYS = ("zeta", "pack", "precision", "sched", "kmax", "graph_passes")
+_OPT_KEYS = ("zeta", "pack", "precision", "sched", "kmax", "graph_passes", "proj")
 
 
 def fnn_autotune(points, offsets, metric: str, eps, reps: int = 2, **base) -> dict:
@@ -379,13 +381,15 @@ def load_cost_model(path: str = COST_MODEL_PATH) -> np.ndarray:
 
 def fnn_eps_graph(tree: Tree, eps: float, precision="fp32",
                   sched="two_pass", validate=False, trace=False,
-                  slack_pct=None) -> Graph:
+                  slack_pct=None, proj=None) -> Graph:
+    """proj: filter on leading principal coordinates (None / 0 automatic,
+    -1 off, else their number, a multiple of 16)."""
     if sched == "learned" and not _model_set and os.path.exists(COST_MODEL_PATH):
         fnn_set_cost_model(load_cost_model())
     _bind_stream()
     out = ctypes.POINTER(fnn_csr)()
     o = _options(precision=precision, sched=sched, validate=int(validate),
-                 trace=int(trace), slack_pct=slack_pct)
+                 trace=int(trace), slack_pct=slack_pct, proj=proj)
     _check(lib().fnn_eps_graph_ex(tree.handle, float(eps), ctypes.byref(o),
                                   ctypes.byref(out)))
     return Graph(out)

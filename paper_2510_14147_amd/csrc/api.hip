@@ -82,6 +82,10 @@ Options read_options(const fnn_options *o)
         fail(FNN_EINVAL, "negative graph_passes");
     if (o->graph_passes)
         r.graph_passes = o->graph_passes > 64 ? 64 : o->graph_passes;
+    if (o->proj < -1 || o->proj > 128 || (o->proj > 0 && o->proj % 16))
+        fail(FNN_EINVAL, "proj must be -1, 0 or a multiple of 16 up to 128 (got %d)",
+             (int)o->proj);
+    r.proj = o->proj;
     return r;
 }
 

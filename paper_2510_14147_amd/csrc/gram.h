@@ -59,6 +59,11 @@ struct GramArgs {
     // are the edges, and degp counts the edges of each tree position; null
     // otherwise
     int32_t *degp;
+    // filter on leading principal coordinates: their number (0: off), the
+    // factor applied to eps^2 (1 when off) and the captured variance
+    int proj;
+    double t2mul;
+    double captured;
 };
 
 // Exact decision of the survivor list: edge list (input ids, FP32 distance)
@@ -74,17 +79,26 @@ void edges_scatter(const int2 *edges, const float *edist, long long ne,
 // their Hamming distances.
 void edges_scatter_ham(const int2 *surv, long long ne, const Pts &P,
                        const int32_t *perm, const TileOut &o, hipStream_t s);
-// deg[perm[p]] += degp[p] for every tree position p.
+// deg[perm[p]] += degp[p] for every tree position p; *dsum += sum degp.
 void degrees_from_positions(const int32_t *degp, const int32_t *perm, int n,
-                            int32_t *deg, hipStream_t s);
+                            int32_t *deg, unsigned long long *dsum, hipStream_t s);
 
-// eps^2 in the filter's key space, slightly enlarged so that the FP32
-// evaluation of the filter test itself cannot flip a true edge.
-float gram_eps2(int metric, double eps, const Thr &E);
+// True when no query pack exceeds the filter's tile height (the work list
+// of every pack pair then exists in closed form).
+bool gram_packs_fit(const fnn_tree *T, Scratch &S);
 
-void gram_prepare(const fnn_tree *T, int prec, double eps, const Thr &E,
-                  const int2 *inter, long long ninter, Scratch &S, GramArgs &G,
-                  int2 **rest, long long *nrest);
+// Squared threshold of the filter's key (eps^2, or the squared chord of
+// the angular threshold).
+double gram_t2(int metric, double eps, const Thr &E);
+// eps^2 in the filter's key space times t2mul, slightly enlarged so that the
+// FP32 evaluation of the filter test itself cannot flip a true edge.
+float gram_eps2(int metric, double eps, const Thr &E, double t2mul = 1.0);
+
+// proj: leading principal coordinates for the filter (-1 off, 0 automatic,
+// else their number); t2min: smallest squared threshold of the query.
+void gram_prepare(const fnn_tree *T, int prec, int proj, double eps, const Thr &E,
+                  double t2min, const int2 *inter, long long ninter, Scratch &S,
+                  GramArgs &G, int2 **rest, long long *nrest);
 void gram_launch(int metric, int prec, bool fill_pass, const Pts &P,
                  const GramArgs &G, const TileOut &o, hipStream_t s);
 

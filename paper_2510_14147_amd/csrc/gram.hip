@@ -28,6 +28,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <atomic>
 #include <type_traits>
 #include <vector>
 
@@ -48,6 +49,9 @@ constexpr int UNIT_MAX = 64;     // list entries per work unit (at most)
 // dependency stalls (one wave per SIMD with 512 registers measured 1.7x
 // slower)
 constexpr int GRAM_WAVES_PER_SIMD = 2;
+// survivor-list slots a wave reserves per atomic on the shared count (one
+// atomic per tile with survivors serialised the whole filter on that count)
+constexpr int SURV_CHUNK = 512;
 
 // ---------------------------------------------------------------- prep ---
 
@@ -97,6 +101,257 @@ __global__ void k_quant(const float *__restrict__ x, int n, int dp, int kq,
     }
 }
 
+// ------------------------------------- leading principal coordinates ---
+//
+// The filter may run on z = Q^T (x - mu), Q a dp x K matrix whose columns
+// approximate the K leading principal directions of the point set.  For any
+// Q, |Q^T (x - y)|^2 <= rho |x - y|^2 with rho >= ||Q||_2^2, so a pair with
+// d(x, y) <= eps has |z(x) - z(y)|^2 <= rho eps^2: the filter stays
+// conservative with eps^2 scaled by rho (and the rounding terms below).  Q
+// only decides how selective it is.  rho is the Gershgorin bound of Q^T Q
+// (largest absolute row sum) evaluated in FP64.
+
+constexpr int PCA_MAXK = 64;     // principal directions examined (at most)
+constexpr int PCA_ROWS = 65536;  // covariance sample (rows, at most)
+
+// Partial sums of (x - mu)(x - mu)^T over the sample rows j * stride; block
+// b takes sample rows in chunks of 32 starting at 32 b; thread t owns an
+// 8 x 8 block of the dp x dp matrix (dp <= 128).
+__global__ void __launch_bounds__(256)
+k_cov_partial(const float *__restrict__ x, int n, int dp, int stride,
+              const float *__restrict__ sums, float inv_n, double *__restrict__ part)
+{
+    __shared__ float xs[32][128 + 1];
+    __shared__ float mu[128];
+    const int t = threadIdx.x;
+    for (int c = t; c < dp; c += blockDim.x)
+        mu[c] = sums[c] * inv_n;
+    const int bi = t / 16, bj = t % 16;
+    const bool mine = 8 * bi < dp && 8 * bj < dp;
+    float acc[8][8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            acc[i][j] = 0.f;
+    const long long m = ((long long)n + stride - 1) / stride;
+    __syncthreads();
+    for (long long j0 = (long long)blockIdx.x * 32; j0 < m;
+         j0 += (long long)gridDim.x * 32) {
+        for (int e = t; e < 32 * dp; e += blockDim.x) {
+            const int r = e / dp, c = e % dp;
+            const long long j = j0 + r;
+            xs[r][c] = j < m ? x[(size_t)(j * stride) * dp + c] - mu[c] : 0.f;
+        }
+        __syncthreads();
+        if (mine) {
+            for (int r = 0; r < 32; ++r) {
+                float a[8], b[8];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    a[k] = 8 * bi + k < dp ? xs[r][8 * bi + k] : 0.f;
+                    b[k] = 8 * bj + k < dp ? xs[r][8 * bj + k] : 0.f;
+                }
+#pragma unroll
+                for (int i = 0; i < 8; ++i)
+#pragma unroll
+                    for (int j = 0; j < 8; ++j)
+                        acc[i][j] = fmaf(a[i], b[j], acc[i][j]);
+            }
+        }
+        __syncthreads();
+    }
+    if (mine)
+        for (int i = 0; i < 8; ++i)
+            for (int j = 0; j < 8; ++j) {
+                const int r = 8 * bi + i, c = 8 * bj + j;
+                if (r < dp && c < dp)
+                    part[(size_t)blockIdx.x * dp * dp + (size_t)r * dp + c] = acc[i][j];
+            }
+}
+
+__global__ void k_cov_reduce(const double *__restrict__ part, int nparts, int dd,
+                             double inv_m, double *__restrict__ C)
+{
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < dd;
+         e += gridDim.x * blockDim.x) {
+        double v = 0.0;
+        for (int b = 0; b < nparts; ++b)
+            v += part[(size_t)b * dd + e];
+        C[e] = v * inv_m;
+    }
+}
+
+__device__ __forceinline__ double block_sum256(double v, double *red)
+{
+    v = wave_sum(v);
+    const int t = threadIdx.x;
+    __syncthreads();
+    if ((t & (WAVE - 1)) == 0)
+        red[t / WAVE] = v;
+    __syncthreads();
+    return red[0] + red[1] + red[2] + red[3];
+}
+
+__device__ __forceinline__ double pm_one(int j, int c, int salt)
+{
+    unsigned h = (unsigned)j * 0x9E3779B1u ^ (unsigned)c * 0x85EBCA77u ^
+                 (unsigned)salt * 0xC2B2AE3Du;
+    h ^= h >> 15;
+    h *= 0x2C1B3C6Du;
+    h ^= h >> 12;
+    return (h & 1u) ? 1.0 : -1.0;
+}
+
+// Leading principal directions of the covariance C (dp x dp, FP64), one
+// work-group of 256 threads: a randomized range finder (three products of C
+// with a fixed +-1 start block, scaled by 1 / trace) followed by Gram-Schmidt
+// (two passes per column; a column that cancels to below 1e-6 of its norm
+// lies numerically in the span of the previous ones and is replaced by a
+// fresh +-1 vector, so the columns stay orthonormal to rounding).  After
+// every 16 columns the residual variance trace(C) - sum q_j^T C q_j is
+// compared with the query's scale: the first K with 2 (trace - captured) <=
+// beta * t2 (or K = kfix) is written to kout (0 if none up to kmax).  Q is
+// returned row-major [dp][K]; info[0] = rho (Gershgorin bound of Q^T Q,
+// enlarged by 1e-12 for its own rounding), info[1] = captured fraction.  Y
+// and Z are scratch blocks of kmax * dp doubles.
+__global__ void __launch_bounds__(256)
+k_pca(const double *__restrict__ C, int dp, int kmax, int kfix, double t2, double beta,
+      double *__restrict__ Y, double *__restrict__ Z, double *__restrict__ Q,
+      int *__restrict__ kout, double *__restrict__ info)
+{
+    __shared__ double red[4];
+    __shared__ double sdot[PCA_MAXK];
+    __shared__ double grow[PCA_MAXK];
+    const int t = threadIdx.x, lane = t & (WAVE - 1), wv = t / WAVE;
+    double tr = 0.0;
+    for (int c = t; c < dp; c += 256)
+        tr += C[(size_t)c * dp + c];
+    tr = block_sum256(tr, red);
+    if (!(tr > 0.0)) {
+        if (t == 0) {
+            *kout = 0;
+            info[0] = info[1] = 0.0;
+        }
+        return;
+    }
+    for (int e = t; e < kmax * dp; e += 256)
+        Y[e] = pm_one(e / dp, e % dp, 0);
+    __syncthreads();
+    const double itr = 1.0 / tr;
+    for (int it = 0; it < 3; ++it) {
+        for (int e = t; e < kmax * dp; e += 256) {
+            const int j = e / dp, c = e % dp;
+            double v = 0.0;
+            for (int r = 0; r < dp; ++r)
+                v += C[(size_t)c * dp + r] * Y[(size_t)j * dp + r];
+            Z[e] = v * itr;
+        }
+        __syncthreads();
+        double *sw = Y;
+        Y = Z;
+        Z = sw;
+    }
+    double cum = 0.0;
+    int K = 0;
+    for (int j = 0; j < kmax; ++j) {
+        double *y = Y + (size_t)j * dp;
+        double nn = 0.0;
+        for (int attempt = 0; attempt < 4; ++attempt) {
+            double n0 = 0.0;
+            for (int c = t; c < dp; c += 256)
+                n0 += y[c] * y[c];
+            n0 = block_sum256(n0, red);
+            for (int pass = 0; pass < 2; ++pass) {
+                for (int i = wv; i < j; i += 4) {
+                    double d = 0.0;
+                    for (int c = lane; c < dp; c += WAVE)
+                        d += Y[(size_t)i * dp + c] * y[c];
+                    d = wave_sum(d);
+                    if (lane == 0)
+                        sdot[i] = d;
+                }
+                __syncthreads();
+                for (int c = t; c < dp; c += 256) {
+                    double v = y[c];
+                    for (int i = 0; i < j; ++i)
+                        v -= sdot[i] * Y[(size_t)i * dp + c];
+                    y[c] = v;
+                }
+                __syncthreads();
+            }
+            nn = 0.0;
+            for (int c = t; c < dp; c += 256)
+                nn += y[c] * y[c];
+            nn = block_sum256(nn, red);
+            if (nn > 1e-12 * n0 && nn > 1e-280)
+                break;
+            for (int c = t; c < dp; c += 256)
+                y[c] = pm_one(j, c, attempt + 1);
+            __syncthreads();
+            nn = 0.0;
+        }
+        const double inv = nn > 1e-280 ? 1.0 / sqrt(nn) : 0.0;
+        for (int c = t; c < dp; c += 256)
+            y[c] *= inv;
+        __syncthreads();
+        double cap = 0.0;
+        for (int c = t; c < dp; c += 256) {
+            double v = 0.0;
+            for (int r = 0; r < dp; ++r)
+                v += C[(size_t)c * dp + r] * y[r];
+            cap += y[c] * v;
+        }
+        cum += block_sum256(cap, red);
+        if ((j + 1) % 16 == 0 && (kfix ? j + 1 == kfix : 2.0 * (tr - cum) <= beta * t2)) {
+            K = j + 1;
+            break;
+        }
+    }
+    // rho >= ||Q||_2^2: largest absolute row sum of Q^T Q
+    for (int a = t; a < K; a += 256)
+        grow[a] = 0.0;
+    __syncthreads();
+    for (int e = t; e < K * K; e += 256) {
+        const int a = e / K, b = e % K;
+        double g = 0.0;
+        for (int c = 0; c < dp; ++c)
+            g += Y[(size_t)a * dp + c] * Y[(size_t)b * dp + c];
+        atomicAdd(&grow[a], fabs(g));
+    }
+    __syncthreads();
+    for (int e = t; e < K * dp; e += 256) {
+        const int c = e / K, k = e % K;
+        Q[e] = Y[(size_t)k * dp + c];
+    }
+    if (t == 0) {
+        double rho = 0.0;
+        for (int a = 0; a < K; ++a)
+            rho = fmax(rho, grow[a]);
+        *kout = K;
+        info[0] = rho * (1.0 + 1e-12);
+        info[1] = cum / tr;
+    }
+}
+
+// z = Q^T (x - mu) in FP64, stored as FP32 rows [n][K] (tree order).
+__global__ void __launch_bounds__(256)
+k_project(const float *__restrict__ x, int n, int dp, const float *__restrict__ sums,
+          double inv_n, const double *__restrict__ Q, int K, float *__restrict__ z)
+{
+    const long long tot = (long long)n * K;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
+         e += (long long)gridDim.x * blockDim.x) {
+        const long long i = e / K;
+        const int k = (int)(e - i * K);
+        const float *xr = x + (size_t)i * dp;
+        double v = 0.0;
+        for (int c = 0; c < dp; ++c)
+            v += Q[(size_t)c * K + k] * ((double)xr[c] - (double)sums[c] * inv_n);
+        z[e] = (float)v;
+    }
+}
+
 __global__ void k_absmax(const float *__restrict__ x, int n, int dp,
                          const float *__restrict__ sums, float inv_n,
                          unsigned *__restrict__ mx)
@@ -106,6 +361,7 @@ __global__ void k_absmax(const float *__restrict__ x, int n, int dp,
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
          e += (int64_t)gridDim.x * blockDim.x)
         m = fmaxf(m, fabsf(x[e] - sums[e % dp] * inv_n));
+    // one atomic per wave; the grid is capped so that few waves contend
     m = wave_max(m);
     if ((threadIdx.x & (WAVE - 1)) == 0)
         atomicMax(mx, __float_as_uint(m));
@@ -280,6 +536,143 @@ struct GramCfg<FNN_PREC_I8> {
 typedef __attribute__((ext_vector_type(4))) int i32x4;
 typedef __attribute__((ext_vector_type(16))) int i32x16;
 
+// Marks this wave's unused reserved survivor slots [cpos, cend) (-1, -1).
+__device__ __forceinline__ void pad_surv(const GramArgs &G, unsigned long long cpos,
+                                         unsigned long long cend)
+{
+    const int lane = threadIdx.x & (WAVE - 1);
+    for (unsigned long long q = cpos + lane; q < cend; q += WAVE)
+        if ((long long)q < G.surv_cap)
+            G.surv[q] = make_int2(-1, -1);
+}
+
+// End of one 64-row x 32-column block (column block cb) of a wave's tile:
+// the pairs that pass the filter (all valid pairs with their pass flag when
+// validating) go to the survivor list through the wave's reserved slots
+// [cpos, cend); the exact integer filter also counts degrees; npairs counts
+// the screened pairs.  mx is the lane's largest accumulator (scaled) and ay
+// its column term.
+template <int PREC, typename V, typename ACC>
+__device__ __forceinline__ void block_finish(const GramArgs &G, const ACC (&accb)[2], V ay,
+                                             V mx, int cb, int na, int nb, bool self,
+                                             int pa, int pb, unsigned long long &cpos,
+                                             unsigned long long &cend,
+                                             unsigned long long &npairs)
+{
+    const int lane = threadIdx.x & (WAVE - 1), l32 = lane & 31, hi = lane >> 5;
+    const uint64_t ltmask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    if (cb * 32 >= nb)
+        return;
+    // rows r < na against columns c0 .. c0+nc-1 (r < c if self)
+    if (lane == 0) {
+        const long long nc = min(32, nb - cb * 32), c0 = cb * 32;
+        if (!self) {
+            npairs += (unsigned long long)(na * nc);
+        } else {
+            // sum_{c=c0}^{c0+nc-1} min(na, c)
+            const long long lo = c0, hi2 = c0 + nc;  // [lo, hi2)
+            const long long mid = max(lo, min(hi2, (long long)na));
+            npairs += (unsigned long long)((mid - lo) * (lo + mid - 1) / 2 + (hi2 - mid) * na);
+        }
+    }
+    // this column block may hold no survivor at all
+    if (!self && !G.validate && !__any(mx >= ay))
+        return;
+    const int col = cb * 32 + l32;
+    // Accumulator position i = 16 rb + q holds row r0(i) + 4 hi of
+    // column col in every lane, r0(i) = 32 rb + 8 (q / 4) + q % 4.
+    // Bit i of pm (om) says whether that pair passes (is valid: row
+    // < na, and row < col on a self tile; as r0 < rl with rl per
+    // tile, since a per-position mask would be hoisted out of the
+    // entry loop and spilled).
+    const int rl = (col < nb ? (self ? min(na, col) : na) : 0) - 4 * hi;
+    unsigned pm = 0, om = 0;
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const bool ok = rb * 32 + 8 * (q >> 2) + (q & 3) < rl;
+            const V gq = PREC == FNN_PREC_FP8 ? (V)(accb[rb][q] * G.gscale)
+                                              : (V)accb[rb][q];
+            pm |= (unsigned)(ok && gq >= ay) << (rb * 16 + q);
+            om |= (unsigned)ok << (rb * 16 + q);
+        }
+    // ---- survivors: appended for the exact decision kernel -----
+    // Emitted: the passes, or (validating) every valid pair with
+    // its pass flag.  One ballot per position that some lane has
+    // set gives the pairs of rows r0 (lanes 0..31) and r0 + 4
+    // (lanes 32..63).
+    const unsigned todo = G.validate ? om : pm;
+    unsigned any = todo;
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1)
+        any |= __shfl_xor(any, o, WAVE);
+    int cdeg = 0;  // exact integer filter: edges of this lane's column
+    while (any) {
+        const int i = __ffs(any) - 1;
+        any &= any - 1;
+        const bool emit = (todo >> i) & 1u;
+        const uint64_t m = __ballot(emit);
+        const int r0 = (i >> 4) * 32 + 8 * ((i & 15) >> 2) + (i & 3);
+        const int cnt = __popcll(m);
+        if (cpos + (unsigned long long)cnt > cend) {
+            pad_surv(G, cpos, cend);
+            unsigned long long b0 = 0;
+            if (lane == 0)
+                b0 = atomicAdd(G.nsurv, (unsigned long long)SURV_CHUNK);
+            cpos = __shfl(b0, 0, WAVE);
+            cend = cpos + SURV_CHUNK;
+        }
+        const unsigned long long o = cpos + __popcll(m & ltmask);
+        if (emit && (long long)o < G.surv_cap)
+            G.surv[o] = make_int2(pa + r0 + 4 * hi,
+                                  (pb + col) | (int)(((pm >> i) & 1u) << 31));
+        cpos += (unsigned long long)cnt;
+        if constexpr (PREC == FNN_PREC_I8) {
+            if (G.degp) {
+                // row degrees from the two halves of the ballot
+                const int lo = __popcll(m & 0xFFFFFFFFull);
+                const int hi2 = __popcll(m >> 32);
+                if (lane == 0 && lo)
+                    atomicAdd(&G.degp[pa + r0], lo);
+                if (lane == 32 && hi2)
+                    atomicAdd(&G.degp[pa + r0 + 4], hi2);
+                cdeg += emit;
+            }
+        }
+    }
+    if constexpr (PREC == FNN_PREC_I8) {
+        // column degrees: lanes l and l + 32 hold the two row halves
+        // of column l
+        cdeg += __shfl_xor(cdeg, 32, WAVE);
+        if (G.degp && hi == 0 && cdeg)
+            atomicAdd(&G.degp[pb + col], cdeg);
+    }
+}
+
+// End of one 64 x 64 tile of a wave (both column blocks).
+template <int PREC, typename V, typename ACC>
+__device__ __forceinline__ void tile_finish(const GramArgs &G, const ACC (&acc)[2][2],
+                                            const V (&ayc)[2], const V (&mx)[2], int na,
+                                            int nb, bool self, int pa, int pb,
+                                            unsigned long long &cpos,
+                                            unsigned long long &cend,
+                                            unsigned long long &npairs)
+{
+    if (!__any(mx[0] >= ayc[0] || mx[1] >= ayc[1]) && !self && !G.validate) {
+        // no survivor: only the pair count
+        if ((threadIdx.x & (WAVE - 1)) == 0) {
+            const long long nc = min(64, nb);
+            npairs += (unsigned long long)(na * nc);
+        }
+        return;
+    }
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb)
+        block_finish<PREC>(G, acc[cb], ayc[cb], mx[cb], cb, na, nb, self, pa, pb, cpos, cend,
+                           npairs);
+}
+
 __device__ __forceinline__ float vmax(float a, float b) { return fmaxf(a, b); }
 __device__ __forceinline__ int vmax(int a, int b) { return max(a, b); }
 
@@ -309,16 +702,21 @@ k_gram(Pts P, GramArgs G, TileOut out)
     const float ginv = PREC == FNN_PREC_BF16 ? 1.f : 1.f / G.gscale;
     unsigned long long npairs = 0;
     const uint64_t ltmask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    // this wave's reserved survivor slots [cpos, cend) (wave-uniform); slots
+    // it leaves unused are marked (-1, -1) for the consumers to skip
+    unsigned long long cpos = 0, cend = 0;
 
     // XCD-aware order: the dispatcher hands consecutive work-groups to the 8
-    // XCDs in turn, so physical block b runs on XCD b % 8.  XCD x takes the
-    // contiguous slice of the unit order starting at xs (units that share B
-    // tiles are adjacent in that order and then meet in one XCD's L2).
-    const int nbk = gridDim.x, xq = nbk / 8, xr = nbk % 8;
-    const int xcd = blockIdx.x % 8;
-    const int xs = xcd * xq + min(xcd, xr);
-    const int u0 = xs + (int)(blockIdx.x / 8);
-    for (int u = u0; u < G.nunits; u += gridDim.x) {
+    // XCDs in turn, so physical block b runs on XCD b % 8.  The grid is a
+    // multiple of 8 work-groups, all resident; XCD x takes the x-th of 8
+    // contiguous slices of the unit order (units that share B tiles are
+    // adjacent in that order and then meet in one XCD's L2) and its
+    // work-groups stride through it.
+    const int bpx = (int)gridDim.x / 8, jb = (int)blockIdx.x / 8;
+    const int per = (G.nunits + 7) / 8;
+    const int ub = min(G.nunits, (int)(blockIdx.x % 8) * per);
+    const int ue = min(G.nunits, ub + per);
+    for (int u = ub + jb; u < ue; u += bpx) {
         const int e0 = G.ubeg[u], e1 = min(G.ubeg[u + 1], e0 + UNIT_MAX);
         if (G.ubeg[u + 1] - e0 > UNIT_MAX && t == 0)
             atomicOr(out.err, ERR_INDEX);  // the list builders never do this
@@ -551,91 +949,143 @@ k_gram(Pts P, GramArgs G, TileOut out)
                 if constexpr (PREC == FNN_PREC_FP8)
                     mx[cb] *= G.gscale;
             }
-            if (__any(mx[0] >= ayc[0] || mx[1] >= ayc[1]) || self || G.validate) {
+            tile_finish<PREC>(G, acc, ayc, mx, na, nb, self, pa, pb, cpos, cend, npairs);
+        }
+        __syncthreads();
+    }
+    pad_surv(G, cpos, cend);
+    if (lane == 0 && npairs)
+        atomicAdd(&out.cnt[2], npairs);
+}
+
+// Filter for narrow BF16 rows (kq <= 32: the leading principal
+// coordinates).  Same work units and tile layout as k_gram, but no LDS
+// staging and no barrier in the entry loop: each wave reads its B fragments
+// (16 bytes per lane, k-step and column block) from L2 into registers one
+// entry ahead.  A wave that emits survivors then never holds up the other
+// waves of its work-group; the four waves of a group read the same B rows
+// at about the same time, so most of those reads hit L1.
+template <int M, int NKS>
+__global__ void __launch_bounds__(GT, 2)
+k_gram_direct(Pts P, GramArgs G, TileOut out)
+{
+    static_assert(NKS >= 1 && NKS <= 2, "narrow rows only");
+    constexpr int rowb = NKS * 32;  // bytes per quantised row
+    __shared__ int eB[UNIT_MAX], eP[UNIT_MAX], eN[UNIT_MAX], eC[UNIT_MAX];
+    const int t = threadIdx.x, lane = t & (WAVE - 1), w = t / WAVE;
+    const int l32 = lane & 31, hi = lane >> 5;
+    const unsigned char *Q = (const unsigned char *)G.q;
+    unsigned long long npairs = 0, cpos = 0, cend = 0;
+    // XCD slices of the unit order, as in k_gram
+    const int bpx = (int)gridDim.x / 8, jb = (int)blockIdx.x / 8;
+    const int per = (G.nunits + 7) / 8;
+    const int ub = min(G.nunits, (int)(blockIdx.x % 8) * per);
+    const int ue = min(G.nunits, ub + per);
+    for (int u = ub + jb; u < ue; u += bpx) {
+        const int e0 = G.ubeg[u], e1 = min(G.ubeg[u + 1], e0 + UNIT_MAX);
+        if (G.ubeg[u + 1] - e0 > UNIT_MAX && t == 0)
+            atomicOr(out.err, ERR_INDEX);  // the list builders never do this
+        const int g = G.lg[e0];
+        const int a = G.nn + GW * g + w;
+        const bool has_a = (GW * g + w) < G.npacks && G.q_pe[a] - G.q_pb[a] <= GP;
+        const int pa = has_a ? G.q_pb[a] : 0;
+        const int na = has_a ? G.q_pe[a] - pa : 0;
+        // A fragments: rows 32 rb + l32, bytes 32 ks + 16 hi
+        bf16x8 Af[2][NKS];
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+            for (int ks = 0; ks < NKS; ++ks) {
+                const int r = rb * 32 + l32;
+                int4 v = make_int4(0, 0, 0, 0);
+                if (r < na)
+                    v = *(const int4 *)(Q + (size_t)(pa + r) * rowb + ks * 32 + hi * 16);
+                __builtin_memcpy(&Af[rb][ks], &v, 16);
+            }
+        // accumulator start values -ax of this lane's rows
+        const int ca = (G.pcl && has_a) ? G.pcl[pa] : -1;
+        const float e2 = ca >= 0 ? G.ct[ca].e2f : G.e2f;
+        f32x16 ax0[2];
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int r = rb * 32 + 8 * (q >> 2) + 4 * hi + (q & 3);
+                ax0[rb][q] = r < na ? -0.5f * (G.hx[pa + r] - e2) : -FLT_MAX;
+            }
+        for (int i = t; i < e1 - e0; i += GT) {
+            const int bb = G.nn + G.lb[e0 + i];
+            const int pbb = G.q_pb[bb];
+            eB[i] = bb;
+            eP[i] = pbb;
+            eN[i] = G.q_pe[bb] - pbb;
+            eC[i] = G.pcl ? G.pcl[pbb] : -1;
+        }
+        __syncthreads();
+        // B fragments and column terms of one entry (columns 32 cb + l32)
+        int4 Bn[2][NKS];
+        float ayn[2];
+        auto load_b = [&](int e) {
+            const int pbb = eP[e - e0], nbb = eN[e - e0];
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb) {
+                const int c = cb * 32 + l32;
+                const bool ok = c < nbb;
+#pragma unroll
+                for (int ks = 0; ks < NKS; ++ks)
+                    Bn[cb][ks] = ok ? *(const int4 *)(Q + (size_t)(pbb + c) * rowb + ks * 32 +
+                                                      hi * 16)
+                                    : make_int4(0, 0, 0, 0);
+                ayn[cb] = ok ? 0.5f * G.hx[pbb + c] : FLT_MAX;
+            }
+        };
+        load_b(e0);
+        for (int e = e0; e < e1; ++e) {
+            int4 Bc[2][NKS];
+            float ayc[2];
+#pragma unroll
+            for (int cb = 0; cb < 2; ++cb) {
+                ayc[cb] = ayn[cb];
+#pragma unroll
+                for (int ks = 0; ks < NKS; ++ks)
+                    Bc[cb][ks] = Bn[cb][ks];
+            }
+            const int b = eB[e - e0], pb = eP[e - e0], nb = eN[e - e0];
+            const bool skip = !has_a || b < a || (ca >= 0 && eC[e - e0] != ca);
+            if (e + 1 < e1)
+                load_b(e + 1);
+            if (skip)
+                continue;
+            const bool self = (b == a);
+            // one 32-column block at a time: the second block's matrix-core
+            // work overlaps the first block's filter
 #pragma unroll
             for (int cb = 0; cb < 2; ++cb) {
                 if (cb * 32 >= nb)
                     break;
-                const int col = cb * 32 + l32;
-                const V ay = ayc[cb];
-                unsigned pm = 0, om = 0;
+                f32x16 acc[2];
 #pragma unroll
-                for (int rb = 0; rb < 2; ++rb) {
+                for (int ks = 0; ks < NKS; ++ks) {
+                    bf16x8 bb;
+                    __builtin_memcpy(&bb, &Bc[cb][ks], 16);
 #pragma unroll
-                    for (int q = 0; q < 16; ++q) {
-                        const int row = rb * 32 + 8 * (q >> 2) + 4 * hi + (q & 3);
-                        const bool ok = row < na && col < nb && (!self || row < col);
-                        const V gq = PREC == FNN_PREC_FP8 ? (V)(acc[cb][rb][q] * G.gscale)
-                                                          : (V)acc[cb][rb][q];
-                        const bool pass = ok && (gq >= ay);
-                        pm |= (unsigned)pass << (rb * 16 + q);
-                        om |= (unsigned)ok << (rb * 16 + q);
-                    }
+                    for (int rb = 0; rb < 2; ++rb)
+                        acc[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                            Af[rb][ks], bb, ks == 0 ? ax0[rb] : acc[rb], 0, 0, 0);
                 }
-                // ---- survivors: appended for the exact decision kernel -----
-                const unsigned todo = G.validate ? om : pm;
-                const int mine = __popc(todo);
-                int incl = mine;
+                float mx = acc[0][0];
 #pragma unroll
-                for (int o = 1; o < WAVE; o <<= 1) {
-                    const int v = __shfl_up(incl, o, WAVE);
-                    if (lane >= o)
-                        incl += v;
-                }
-                const int total = __shfl(incl, WAVE - 1, WAVE);
-                if (total) {
-                    unsigned long long base = 0;
-                    if (lane == 0)
-                        base = atomicAdd(G.nsurv, (unsigned long long)total);
-                    base = __shfl(base, 0, WAVE);
-                    unsigned long long o = base + (unsigned long long)(incl - mine);
-                    unsigned tb = todo;
-                    while (tb) {
-                        const int bit = __ffs(tb) - 1;
-                        tb &= tb - 1;
-                        const int rb = bit >> 4, q = bit & 15;
-                        const int row = rb * 32 + 8 * (q >> 2) + 4 * hi + (q & 3);
-                        if ((long long)o < G.surv_cap)
-                            G.surv[o] = make_int2(pa + row,
-                                                  (pb + col) | (int)(((pm >> bit) & 1u) << 31));
-                        ++o;
-                        if constexpr (PREC == FNN_PREC_I8)
-                            if (G.degp)
-                                atomicAdd(&G.degp[pa + row], 1);
-                    }
-                }
-                if constexpr (PREC == FNN_PREC_I8) {
-                    // exact filter, not validating: the survivors are the
-                    // edges; column degrees summed over the two row halves
-                    // of each column (lanes l and l + 32)
-                    const int cdeg = mine + __shfl_xor(mine, 32, WAVE);
-                    if (G.degp && hi == 0 && cdeg)
-                        atomicAdd(&G.degp[pb + col], cdeg);
-                }
-            }
-            }
-            // pairs screened by this wave (both column blocks)
-            if (lane == 0) {
+                for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
-                for (int cb = 0; cb < 2; ++cb) {
-                    if (cb * 32 >= nb)
-                        break;
-                    // rows r < na against columns c0 .. c0+nc-1 (r < c if self)
-                    const long long nc = min(32, nb - cb * 32), c0 = cb * 32;
-                    if (!self) {
-                        npairs += (unsigned long long)(na * nc);
-                    } else {
-                        // sum_{c=c0}^{c0+nc-1} min(na, c)
-                        const long long lo = c0, hi2 = c0 + nc;  // [lo, hi2)
-                        const long long mid = max(lo, min(hi2, (long long)na));
-                        npairs += (unsigned long long)((mid - lo) * (lo + mid - 1) / 2 +
-                                                       (hi2 - mid) * na);
-                    }
-                }
+                    for (int q = 0; q < 16; ++q)
+                        mx = fmaxf(mx, acc[rb][q]);
+                block_finish<FNN_PREC_BF16>(G, acc, ayc[cb], mx, cb, na, nb, self, pa, pb,
+                                            cpos, cend, npairs);
             }
         }
-        __syncthreads();
+        __syncthreads();  // eB.. are rewritten by the next unit
     }
+    pad_surv(G, cpos, cend);
     if (lane == 0 && npairs)
         atomicAdd(&out.cnt[2], npairs);
 }
@@ -661,7 +1111,7 @@ k_survive(Pts P, GramArgs G, long long ns, int2 *__restrict__ edges,
         bool edge = false;
         float dd = 0.f;
         int oi = 0, oj = 0;
-        if (i < ns) {
+        if (i < ns && G.surv[i].x >= 0) {  // (-1, -1): an unused slot
             const int2 e = G.surv[i];
             const int pi = e.x, pj = e.y & 0x7FFFFFFF;
             const bool passed = (e.y >> 31) & 1;
@@ -800,6 +1250,8 @@ __global__ void k_edges_scatter_ham(const int2 *__restrict__ surv, long long ne,
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < ne;
          i += (long long)gridDim.x * blockDim.x) {
         const int2 e = surv[i];
+        if (e.x < 0)
+            continue;  // an unused slot
         const int pi = e.x, pj = e.y & 0x7FFFFFFF;
         const float d = (float)ham_words(h + (size_t)pi * W, h + (size_t)pj * W, W);
         const int oi = perm[pi], oj = perm[pj];
@@ -821,26 +1273,33 @@ void edges_scatter_ham(const int2 *surv, long long ne, const Pts &P,
 {
     if (ne <= 0)
         return;
-    FNN_LAUNCH(k_edges_scatter_ham, dim3(grid_for(ne, 256)), dim3(256), 0, s, surv,
+    FNN_LAUNCH(k_edges_scatter_ham, dim3(grid_cap(ne, 256, 4096)), dim3(256), 0, s, surv,
                ne, P.h, P.dp, perm, o);
 }
 
 __global__ void k_deg_from_positions(const int32_t *__restrict__ degp,
                                      const int32_t *__restrict__ perm, int n,
-                                     int32_t *__restrict__ deg)
+                                     int32_t *__restrict__ deg,
+                                     unsigned long long *__restrict__ dsum)
 {
+    unsigned long long t = 0;
     for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < n;
-         p += gridDim.x * blockDim.x)
+         p += gridDim.x * blockDim.x) {
         deg[perm[p]] += degp[p];
+        t += (unsigned long long)degp[p];
+    }
+    t = wave_sum(t);
+    if ((threadIdx.x & (WAVE - 1)) == 0 && t)
+        atomicAdd(dsum, t);
 }
 
 void degrees_from_positions(const int32_t *degp, const int32_t *perm, int n,
-                            int32_t *deg, hipStream_t s)
+                            int32_t *deg, unsigned long long *dsum, hipStream_t s)
 {
     if (n <= 0)
         return;
-    FNN_LAUNCH(k_deg_from_positions, dim3(grid_cap(n, 256, 16384)), dim3(256), 0, s,
-               degp, perm, n, deg);
+    FNN_LAUNCH(k_deg_from_positions, dim3(grid_cap(n, 256, 2048)), dim3(256), 0, s,
+               degp, perm, n, deg, dsum);
 }
 
 template <int M, int PREC, int NKS>
@@ -849,9 +1308,38 @@ static void launch_gram_k(bool fill_pass, const Pts &P, const GramArgs &G,
 {
     const int rowb = NKS * GramCfg<PREC>::KSTEP * GramCfg<PREC>::EB;
     const size_t sh = (size_t)GP * (rowb + 16) + sizeof(float) * GP * (GW + 1);
-    const dim3 grid(grid_for(G.nunits, 1));
+    // every work-group resident at once (a multiple of 8: one share per XCD)
+    static std::atomic<int> resident{0};  // work-groups per CU (this instance)
+    int rb = resident.load();
+    if (rb == 0) {
+        FNN_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &rb, reinterpret_cast<const void *>(&k_gram<M, PREC, NKS>), GT, sh));
+        rb = std::max(1, rb);
+        resident.store(rb);
+    }
+    const long long want = std::max<long long>(8, (long long)rb * num_cus() / 8 * 8);
+    const long long need = ((long long)G.nunits + 7) / 8 * 8;
+    const dim3 grid((unsigned)std::max<long long>(8, std::min(want, need)));
     (void)fill_pass;
     FNN_LAUNCH((k_gram<M, PREC, NKS>), grid, dim3(GT), sh, s, P, G, o);
+}
+
+template <int M, int NKS>
+static void launch_gram_direct(const Pts &P, const GramArgs &G, const TileOut &o,
+                               hipStream_t s)
+{
+    static std::atomic<int> resident{0};  // work-groups per CU (this instance)
+    int rb = resident.load();
+    if (rb == 0) {
+        FNN_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &rb, reinterpret_cast<const void *>(&k_gram_direct<M, NKS>), GT, 0));
+        rb = std::max(1, rb);
+        resident.store(rb);
+    }
+    const long long want = std::max<long long>(8, (long long)rb * num_cus() / 8 * 8);
+    const long long need = ((long long)G.nunits + 7) / 8 * 8;
+    const dim3 grid((unsigned)std::max<long long>(8, std::min(want, need)));
+    FNN_LAUNCH((k_gram_direct<M, NKS>), grid, dim3(GT), 0, s, P, G, o);
 }
 
 template <int M, int PREC>
@@ -870,8 +1358,8 @@ static void launch_gram(bool fill_pass, const Pts &P, const GramArgs &G,
         }
     } else if constexpr (PREC == FNN_PREC_BF16) {
         switch (nks) {
-        case 1: launch_gram_k<M, PREC, 1>(fill_pass, P, G, o, s); break;
-        case 2: launch_gram_k<M, PREC, 2>(fill_pass, P, G, o, s); break;
+        case 1: launch_gram_direct<M, 1>(P, G, o, s); break;
+        case 2: launch_gram_direct<M, 2>(P, G, o, s); break;
         case 3: launch_gram_k<M, PREC, 3>(fill_pass, P, G, o, s); break;
         case 4: launch_gram_k<M, PREC, 4>(fill_pass, P, G, o, s); break;
         case 5: launch_gram_k<M, PREC, 5>(fill_pass, P, G, o, s); break;
@@ -907,12 +1395,12 @@ void gram_launch(int metric, int prec, bool fill_pass, const Pts &P,
 
 // ------------------------------------------------------------- host side --
 
-float gram_eps2(int metric, double eps, const Thr &E)
+float gram_eps2(int metric, double eps, const Thr &E, double t2mul)
 {
     if (metric == M_HAM)
         return std::min(E.lo, 1048576.f);  // floor(eps); beyond any code length
     const double u32 = 1.0 / 16777216.0;
-    const double T2 = metric == M_L2 ? eps * eps : 2.0 - 2.0 * E.p64;
+    const double T2 = gram_t2(metric, eps, E) * t2mul;
     return (float)(T2 * (1.0 + 320.0 * u32) + 1e-30);
 }
 
@@ -934,37 +1422,129 @@ static void quantise_ham(const fnn_tree *T, int prec, Scratch &S, GramArgs &G)
                s, T->h, n, dp, qb);
 }
 
-// Centred, shrunk BF16 or FP8 copy of the coordinates and the per-point
-// norms of the filter.
-static void quantise_real(const fnn_tree *T, int prec, Scratch &S, GramArgs &G)
+// Leading principal coordinates of X for the filter (see k_pca): returns K
+// (0: the filter runs on X itself) and, when K > 0, z [n][K] FP32, rho and
+// the captured variance fraction.  proj: -1 off, 0 the smallest multiple of
+// 16 whose residual variance, doubled (a pair's expected residual squared
+// distance), is at most half the squared threshold, else that many
+// coordinates.  kq_full is the padded width of X in the filter's format;
+// only K < kq_full helps.  t2min is the smallest squared threshold of the
+// query (FP64 rounding of the projection must also stay below 5e-7 of its
+// root, else K = 0).
+static int project_pca(const float *X, int n, int dp, int kq_full, int proj,
+                       double t2min, const float *sums, Scratch &S, float **z,
+                       double *rho, double *captured)
 {
     hipStream_t s = S.stream();
-    const int n = (int)T->n, dp = T->dp;
-    const int d = T->dim;
+    const int kmax = std::min({PCA_MAXK, (kq_full - 1) / 16 * 16, dp / 16 * 16});
+    if (proj < 0 || kmax < 16 || (proj > 0 && proj > kmax))
+        return 0;
+    const int stride = (int)cdiv(n, PCA_ROWS);
+    const long long m = cdiv(n, stride);
+    const int nparts = (int)std::min<long long>(64, cdiv(m, 32));
+    const int dd = dp * dp;
+    double *part = S.get<double>((size_t)nparts * dd);
+    double *C = S.get<double>(dd);
+    FNN_LAUNCH(k_cov_partial, dim3(nparts), dim3(256), 0, s, X, n, dp, stride, sums,
+               1.0f / n, part);
+    FNN_LAUNCH(k_cov_reduce, dim3(grid_for(dd, 256)), dim3(256), 0, s, part, nparts, dd,
+               1.0 / (double)m, C);
+    double *Y = S.get<double>((size_t)kmax * dp), *Z = S.get<double>((size_t)kmax * dp);
+    double *Qd = S.get<double>((size_t)kmax * dp);
+    int *kout = S.get<int>(1);
+    double *info = S.get<double>(2);
+    FNN_LAUNCH(k_pca, dim3(1), dim3(256), 0, s, C, dp, kmax, proj, t2min, 0.5, Y, Z, Qd,
+               kout, info);
+    const int K = read_scalar(kout, s);
+    double hinfo[2];
+    FNN_HIP(hipMemcpyAsync(hinfo, info, sizeof hinfo, hipMemcpyDeviceToHost, s));
+    FNN_HIP(hipStreamSynchronize(s));
+    if (K <= 0)
+        return 0;
+    // FP64 rounding of the projection: |z~_k - z_k| <= gamma sum_c |Q_ck| |v_c|
+    // <= gamma sqrt(rho) |v|, |v| <= sqrt(dp) max |x_c - mu_c|
+    unsigned *mx = S.get<unsigned>(1);
+    fill(mx, 0u, 1, s);
+    FNN_LAUNCH(k_absmax, dim3(grid_cap((int64_t)n * dp, 256, 2048)), dim3(256), 0, s, X, n, dp,
+               sums, 1.0f / n, mx);
+    const unsigned mb = read_scalar(mx, s);
+    float am;
+    memcpy(&am, &mb, 4);
+    const double u64 = 1.1102230246251565e-16;
+    const double gam = (dp + 2) * u64 / (1.0 - (dp + 2) * u64);
+    const double V = std::sqrt((double)dp) * (double)am * (1.0 + 1e-6);
+    const double emax = std::sqrt((double)K) * gam * std::sqrt(hinfo[0]) * V;
+    if (!(2.0 * emax <= 5e-7 * std::sqrt(hinfo[0]) * std::sqrt(t2min)))
+        return 0;
+    *z = S.get<float>((size_t)n * K);
+    FNN_LAUNCH(k_project, dim3(grid_cap((int64_t)n * K, 256, 16384)), dim3(256), 0, s, X, n,
+               dp, sums, 1.0 / n, Qd, K, *z);
+    *rho = hinfo[0];
+    *captured = hinfo[1];
+    return K;
+}
+
+// Centred, shrunk BF16 or FP8 copy of the coordinates (or of their leading
+// principal coordinates) and the per-point norms of the filter.
+//
+// With principal coordinates z~ (FP32 roundings of z = Q^T (x - mu)
+// computed in FP64): |z~(x) - z~(y)| <= sqrt(rho) d(x, y) + 2 e + u'(|z~(x)|
+// + |z~(y)|), e the FP64 bound above (<= 5e-7 sqrt(rho) eps) and u' =
+// u32 (1 + u32).  Squaring with (a + b)^2 <= (1 + tau) a^2 + (1 + 1/tau) b^2,
+// tau = 1e-6, gives |z~(x) - z~(y)|^2 <= rho eps^2 (1 + 4e-6) + 1e-7
+// (|z~(x)|^2 + |z~(y)|^2): eps^2 is scaled by t2mul = rho (1 + 4e-6) and
+// c1 grows by 1e-7.
+static void quantise_real(const fnn_tree *T, int prec, int proj, double t2min,
+                          Scratch &S, GramArgs &G)
+{
+    hipStream_t s = S.stream();
+    const int n = (int)T->n;
+    int dp = T->dp, d = T->dim;
     const float *X = T->metric == M_ANG ? T->xn : T->x;
     if (prec == FNN_PREC_I8)
         fail(FNN_EUNSUPPORTED, "integer MFMA filter is for Hamming codes");
     const int KS = prec == FNN_PREC_BF16 ? 16 : 64;
-    const int kq = (int)cdiv(dp, KS) * KS;
-    if (kq > 128)
+    if (cdiv(dp, KS) * KS > 128)
         fail(FNN_EUNSUPPORTED, "MFMA filter supports dim <= 128 (got %d)", d);
+    float *sums = S.get<float>(dp);
+    fill(sums, 0.f, dp, s);
+    FNN_LAUNCH(k_colsum, dim3((unsigned)cdiv(n, 1024)), dim3(256), 0, s, X, n,
+               dp, sums);
+    G.t2mul = 1.0;
+    G.proj = 0;
+    G.captured = 0.0;
+    double c_extra = 0.0;
+    {
+        float *z = nullptr;
+        double rho = 1.0, cap = 0.0;
+        const int K = project_pca(X, n, dp, (int)cdiv(dp, KS) * KS, proj, t2min, sums, S,
+                                  &z, &rho, &cap);
+        if (K > 0) {
+            X = z;
+            dp = d = K;
+            G.t2mul = rho * (1.0 + 4e-6);
+            G.proj = K;
+            G.captured = cap;
+            c_extra = 1e-7;
+            sums = S.get<float>(dp);
+            fill(sums, 0.f, dp, s);
+            FNN_LAUNCH(k_colsum, dim3((unsigned)cdiv(n, 1024)), dim3(256), 0, s, X, n,
+                       dp, sums);
+        }
+    }
+    const int kq = (int)cdiv(dp, KS) * KS;
     const double u32 = 1.0 / 16777216.0;
     const double u = prec == FNN_PREC_BF16 ? 1.0 / 256.0 : 1.0 / 16.0;
     // margin coefficient (see the header comment); the FP8 subnormal terms
     // are absorbed by the global scale that maps the largest |coordinate| to
     // at least 224.
     const double c1 = 2.25 * u + (4.0 * kq + 2.0 * d + 72.0) * u32 +
-                      (prec == FNN_PREC_FP8 ? 4.0 * d / 224.0 / 512.0 : 0.0);
-    // mean, scale
-    float *sums = S.get<float>(dp);
-    fill(sums, 0.f, dp, s);
-    FNN_LAUNCH(k_colsum, dim3((unsigned)cdiv(n, 1024)), dim3(256), 0, s, X, n,
-               dp, sums);
+                      (prec == FNN_PREC_FP8 ? 4.0 * d / 224.0 / 512.0 : 0.0) + c_extra;
     float scale = 1.f;
     if (prec == FNN_PREC_FP8) {
         unsigned *mx = S.get<unsigned>(1);
         fill(mx, 0u, 1, s);
-        FNN_LAUNCH(k_absmax, dim3(grid_for((int64_t)n * dp, 256)), dim3(256), 0,
+        FNN_LAUNCH(k_absmax, dim3(grid_cap((int64_t)n * dp, 256, 2048)), dim3(256), 0,
                    s, X, n, dp, sums, 1.0f / n, mx);
         unsigned mb = read_scalar(mx, s);
         float m;
@@ -991,17 +1571,39 @@ static void quantise_real(const fnn_tree *T, int prec, Scratch &S, GramArgs &G)
                    hxbuf);
 }
 
-// Quantised copy + per-point terms, and the MFMA work lists, for one query.
-void gram_prepare(const fnn_tree *T, int prec, double eps, const Thr &E,
-                  const int2 *inter, long long ninter, Scratch &S, GramArgs &G,
-                  int2 **rest, long long *nrest)
+bool gram_packs_fit(const fnn_tree *T, Scratch &S)
 {
     hipStream_t s = S.stream();
-    if (T->metric == M_HAM)
+    const int nn = (int)T->nnodes, npk = (int)T->npacks;
+    if (npk <= 0)
+        return true;
+    int32_t *big = S.get<int32_t>(1);
+    fill(big, 0, 1, s);
+    FNN_LAUNCH(k_max_pack, dim3(grid_for(npk, 256)), dim3(256), 0, s, T->q_pt_begin + nn,
+               T->q_pt_end + nn, npk, GP, big);
+    return read_scalar(big, s) == 0;
+}
+
+double gram_t2(int metric, double eps, const Thr &E)
+{
+    return metric == M_L2 ? eps * eps : 2.0 - 2.0 * E.p64;
+}
+
+// Quantised copy + per-point terms, and the MFMA work lists, for one query.
+void gram_prepare(const fnn_tree *T, int prec, int proj, double eps, const Thr &E,
+                  double t2min, const int2 *inter, long long ninter, Scratch &S,
+                  GramArgs &G, int2 **rest, long long *nrest)
+{
+    hipStream_t s = S.stream();
+    if (T->metric == M_HAM) {
         quantise_ham(T, prec, S, G);
-    else
-        quantise_real(T, prec, S, G);
-    G.e2f = gram_eps2(T->metric, eps, E);
+        G.t2mul = 1.0;
+        G.proj = 0;
+        G.captured = 0.0;
+    } else {
+        quantise_real(T, prec, proj, t2min, S, G);
+    }
+    G.e2f = gram_eps2(T->metric, eps, E, G.t2mul);
     G.E = E;
 
     const int nn = (int)T->nnodes;

@@ -67,6 +67,29 @@ __device__ __forceinline__ bool may_touch(const Pts &P, const QView &Q,
         return d <= lim * (1.f + pr.rel) + pr.abs_;
 }
 
+// Seeded sample of pack pairs under the traversal's pack-level test: counts
+// the pairs it would prune.
+template <int M>
+__global__ void k_prune_sample(Pts P, QView Q, Prune pr, int npk, int ns,
+                               unsigned long long *__restrict__ pruned)
+{
+    unsigned long long c = 0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < ns;
+         i += gridDim.x * blockDim.x) {
+        unsigned h = (unsigned)i * 0x9E3779B1u + 0x7F4A7C15u;
+        h ^= h >> 16;
+        h *= 0x85EBCA6Bu;
+        h ^= h >> 13;
+        const unsigned h2 = h * 0xC2B2AE35u ^ (h >> 16);
+        const int a = Q.nn + (int)(h % (unsigned)npk);
+        const int b = Q.nn + (int)(h2 % (unsigned)npk);
+        c += (a != b && !may_touch<M>(P, Q, pr, a, b)) ? 1 : 0;
+    }
+    c = wave_sum(c);
+    if ((threadIdx.x & (WAVE - 1)) == 0 && c)
+        atomicAdd(pruned, c);
+}
+
 // ------------------------------------------------------------ traversal --
 
 struct Emit {
@@ -1336,23 +1359,47 @@ static void eps_graph_impl(const fnn_tree *Tc, const double *epsv,
         mlp_forward(Lm.model, Lm.feat, n, Lm.pred, s);
     }
 
+    const bool use_gram = ((M == M_L2 || M == M_ANG) && opt.precision != FNN_PREC_FP32) ||
+                          (M == M_HAM && opt.precision == FNN_PREC_I8);
+
     // ---- traversal ------------------------------------------------------
+    // Where the traversal's own pack-level test would keep nearly every pack
+    // pair (high-dimensional data), the MFMA filter takes every pair from a
+    // closed-form list instead; a seeded sample of pack pairs decides.  Any
+    // pair set that contains the needed ones gives the exact graph.
     int2 *inter = nullptr;
     long long ninter = 0;
-    traverse<M>(T, P, Q, pr, S, &inter, &ninter, st);
+    bool dense = false;
+    if (use_gram && ncl == 1 && !opt.trace && T->npacks >= 256 && gram_packs_fit(T, S)) {
+        const int ns = 8192;
+        unsigned long long *pc = S.get<unsigned long long>(1);
+        fill(pc, 0ull, 1, s);
+        FNN_LAUNCH((k_prune_sample<M>), dim3(ns / 256), dim3(256), 0, s, P, Q, pr,
+                   (int)T->npacks, ns, pc);
+        const unsigned long long pruned = read_scalar(pc, s);
+        dense = pruned * 100 <= (unsigned long long)ns;  // at most 1 % prunable
+        st.traverse_tests = ns;
+    }
+    if (dense) {
+        ninter = (long long)T->npacks * (T->npacks + 1) / 2;
+        st.interactions = ninter;
+    } else {
+        traverse<M>(T, P, Q, pr, S, &inter, &ninter, st);
+    }
     tm.mark();  // 1
 
     // ---- MFMA filter set-up (vector metrics with dim <= 128, Hamming codes
     // of <= 256 bits) ------------------------------------------------------
-    const bool use_gram = ((M == M_L2 || M == M_ANG) && opt.precision != FNN_PREC_FP32) ||
-                          (M == M_HAM && opt.precision == FNN_PREC_I8);
     GramArgs G{};
     int2 *plain = inter;
     long long nplain = ninter;
     if constexpr (M == M_L2 || M == M_ANG || M == M_HAM) {
         if (use_gram) {
-            gram_prepare(T, opt.precision, eps, E, inter, ninter, S, G, &plain,
-                         &nplain);
+            double t2min = HUGE_VAL;
+            for (int c = 0; c < ncl; ++c)
+                t2min = std::min(t2min, gram_t2(M, epsv[c], ct_h[c].E));
+            gram_prepare(T, opt.precision, opt.proj, eps, E, t2min, inter, ninter, S, G,
+                         &plain, &nplain);
             G.fp64_dist = fp64_dist;
             G.validate = opt.validate;
             G.q_pb = T->q_pt_begin;
@@ -1360,12 +1407,27 @@ static void eps_graph_impl(const fnn_tree *Tc, const double *epsv,
             G.perm = T->perm;
             G.ct = ncl > 1 ? ct_d : nullptr;
             G.pcl = ncl > 1 ? T->pcl : nullptr;
+            if (ncl > 1 && G.t2mul != 1.0) {
+                // the filter's per-cloud eps^2 on principal coordinates
+                std::vector<CloudThr> cg(ct_h);
+                for (int c = 0; c < ncl; ++c)
+                    cg[c].e2f = gram_eps2(M, epsv[c], cg[c].E, G.t2mul);
+                CloudThr *cg_d = S.get<CloudThr>(ncl);
+                FNN_HIP(hipMemcpyAsync(cg_d, cg.data(), sizeof(CloudThr) * ncl,
+                                       hipMemcpyHostToDevice, s));
+                FNN_HIP(hipStreamSynchronize(s));  // cg goes out of scope
+                G.ct = cg_d;
+            }
+            st.proj_dim = G.proj;
+            st.proj_captured = G.captured;
         }
     }
     tm.mark();  // 2
 
-    unsigned long long *cnt = S.get<unsigned long long>(8);
-    fill(cnt, 0ull, 8, s);
+    // [0..5] see TileOut, [6..7] the learned path's re-fill, [8] sum of the
+    // exact integer filter's position degrees (twice its edges)
+    unsigned long long *cnt = S.get<unsigned long long>(9);
+    fill(cnt, 0ull, 9, s);
     TileOut o{};
     o.cnt = cnt;
     int *bad = S.get<int>(1);
@@ -1375,7 +1437,7 @@ static void eps_graph_impl(const fnn_tree *Tc, const double *epsv,
     C->row_ptr = (int64_t *)out_alloc(sizeof(int64_t) * ((size_t)n + 1));
     int64_t nnz = 0;
     int64_t novf = 0;
-    unsigned long long hc0[8] = {0};
+    unsigned long long hc0[9] = {0};
 
     if (use_gram || !learned) {
         // ---- count pass (plain tiles) / filter + exact survivors (MFMA) ---
@@ -1440,8 +1502,7 @@ static void eps_graph_impl(const fnn_tree *Tc, const double *epsv,
                         st.filter_ms = fms;
                     }
                     if (direct) {
-                        degrees_from_positions(degp, T->perm, n, o.deg, s);
-                        fill(cnt + 3, (unsigned long long)got, 1, s);
+                        degrees_from_positions(degp, T->perm, n, o.deg, cnt + 8, s);
                         gedges = G.surv;
                         ngedges = got;
                     } else {
@@ -1666,6 +1727,7 @@ static void eps_graph_impl(const fnn_tree *Tc, const double *epsv,
     st.n = n;
     st.nodes = T->nnodes;
     st.packs = T->npacks;
+    hc0[3] += hc0[8] / 2;  // exact integer filter: its edges are its survivors
     st.tile_pairs = (int64_t)(hc0[0] + hc0[3]);
     st.fp64_rechecks = (int64_t)hc0[1];
     st.filter_pairs = (int64_t)hc0[2];

@@ -40,6 +40,9 @@ hipStream_t current_stream();
 // replayed on any stream.  Recorded sequences hold only kernel launches:
 // clears are fill kernels, never memset nodes.
 hipStream_t capture_stream();
+
+// Compute units of the current device (cached per device id).
+int num_cus();
 struct GraphRun {
     hipStream_t cs = nullptr;
     hipGraph_t graph = nullptr;

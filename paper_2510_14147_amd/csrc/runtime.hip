@@ -4,6 +4,7 @@
 #include <stdio.h>
 
 #include <algorithm>
+#include <atomic>
 #include <mutex>
 
 #include "../../include/fnn.h"
@@ -46,6 +47,22 @@ hipStream_t capture_stream()
     if (!g_cap_stream[dev])
         FNN_HIP(hipStreamCreateWithFlags(&g_cap_stream[dev], hipStreamNonBlocking));
     return g_cap_stream[dev];
+}
+
+int num_cus()
+{
+    static std::atomic<int> cus[64];
+    int dev = 0;
+    FNN_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64)
+        fail(-4, "device id %d", dev);
+    int c = cus[dev].load();
+    if (c == 0) {
+        FNN_HIP(hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev));
+        c = std::max(1, c);
+        cus[dev].store(c);
+    }
+    return c;
 }
 
 GraphRun::~GraphRun()

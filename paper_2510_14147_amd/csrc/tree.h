@@ -26,6 +26,7 @@ struct Options {
     int trace = 0;
     int slack_pct = 30;
     int graph_passes = 4;
+    int proj = 0;
 };
 
 Options read_options(const fnn_options *o);

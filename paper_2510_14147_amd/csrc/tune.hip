@@ -115,7 +115,7 @@ extern "C" int fnn_autotune(const void *points, const int64_t *offsets,
     }
 
     const Key key{(int)metric, (int)dim, ilog2(n), ilog2(nclouds), o0.zeta, o0.kmax,
-                  o0.precision * 8 + o0.sched};
+                  (o0.precision * 8 + o0.sched) * 256 + (o0.proj + 1)};
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune_cache.find(key);

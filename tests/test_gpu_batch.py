@@ -82,7 +82,7 @@ def run_batch(fnn, orc, clouds, metric, eps, tree_check=True, per_cloud=True,
     print(f"[case] batch metric={metric} clouds={len(clouds)} n={len(X)} "
           f"kw={kw}", flush=True)
     bkw = {k: v for k, v in kw.items() if k in ("zeta", "pack", "kmax")}
-    qkw = {k: v for k, v in kw.items() if k in ("precision", "sched", "validate")}
+    qkw = {k: v for k, v in kw.items() if k in ("precision", "sched", "validate", "proj")}
     tree = fnn.fnn_tree_build_batch(X, off, metric, **bkw)
     g = fnn.fnn_eps_graph_batch(tree, eps, **qkw)
     rp, col, dist = g.to_numpy()
@@ -181,6 +181,14 @@ def test_batch_mfma(fnn, orc, precision):
     clouds = [mixture(n, 64, 500 + i) for i, n in enumerate([3000, 70, 1, 2500, 900, 130])]
     eps = eps_for(clouds, 9, 0.02, 0.08)
     run_batch(fnn, orc, clouds, "l2", eps, precision=precision, validate=1)
+
+
+def test_batch_projected_filter(fnn, orc):
+    # one principal basis for all clouds; each cloud's filter eps^2 is scaled
+    # by the same bound and the survivors decided with the cloud's own eps
+    clouds = [mixture(n, 64, 800 + i) for i, n in enumerate([2500, 90, 1, 3000, 700])]
+    eps = eps_for(clouds, 13, 0.02, 0.08)
+    run_batch(fnn, orc, clouds, "l2", eps, precision="bf16", validate=1, proj=32)
 
 
 def test_batch_learned(fnn, orc):

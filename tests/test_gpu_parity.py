@@ -33,7 +33,7 @@ def gpu_graph(fnn, x, metric, eps, **kw):
     tree = fnn.fnn_tree_build(x, metric, **{k: v for k, v in kw.items()
                                            if k in ("zeta", "pack", "kmax")})
     g = fnn.fnn_eps_graph(tree, eps, **{k: v for k, v in kw.items()
-                                        if k in ("precision", "sched", "validate")})
+                                        if k in ("precision", "sched", "validate", "proj")})
     return tree, g
 
 
@@ -189,3 +189,50 @@ def test_int8_rejects_other_inputs(fnn, orc):
     with pytest.raises(fnn.FnnError) as e:
         fnn.fnn_eps_graph(tree, 40, precision="i8")
     assert e.value.code == fnn.FNN_EUNSUPPORTED
+
+
+# ---- filter on leading principal coordinates ---------------------------------
+
+@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+@pytest.mark.parametrize("proj", [16, 32, 64])
+def test_projected_filter_parity(fnn, orc, prec, proj):
+    # a fixed number of principal coordinates: the filter must stay
+    # conservative (no false negatives) and the graph exact
+    x = G.c2_manifold(n=8000)
+    tree, g, cmp = check(fnn, orc, x, "l2", W["c2_50k"]["eps"][1], tree_check=False,
+                         precision=prec, validate=True, proj=proj)
+    st = g.stats
+    assert st["proj_dim"] == proj
+    assert 0.0 < st["proj_captured"] <= 1.0 + 1e-9
+    assert st["filter_survivors"] < 0.05 * st["filter_pairs"]
+    assert st["validate_mismatch"] == 0
+    assert st["max_rel_err"] <= 1e-5
+
+
+def test_projected_filter_auto_and_off(fnn, orc):
+    x = G.c2_manifold(n=20000)
+    eps = W["c2_50k"]["eps"][0]
+    _, ga, _ = check(fnn, orc, x, "l2", eps, tree_check=False, precision="bf16")
+    _, go, _ = check(fnn, orc, x, "l2", eps, tree_check=False, precision="bf16", proj=-1)
+    # the manifold data puts ~98 % of the variance in 16 coordinates, far
+    # more than the automatic rule needs at this eps
+    assert ga.stats["proj_dim"] == 16 and 0.97 <= ga.stats["proj_captured"] <= 1.0
+    assert go.stats["proj_dim"] == 0
+    # the projected filter screens nearly as well as the full one
+    assert ga.stats["filter_survivors"] < 3 * go.stats["filter_survivors"]
+    for u, v in zip(ga.to_numpy(), go.to_numpy()):
+        assert np.array_equal(u, v)
+
+
+def test_projected_filter_angular(fnn, orc):
+    x = G.c2_manifold(n=6000)
+    check(fnn, orc, x, "angular", 0.35, tree_check=False, precision="bf16",
+          validate=True, proj=16)
+
+
+def test_projected_filter_rejects_bad_width(fnn, orc):
+    x = G.random_points(300, 32, seed=4)
+    tree = fnn.fnn_tree_build(x, "l2")
+    with pytest.raises(fnn.FnnError) as e:
+        fnn.fnn_eps_graph(tree, 0.5, precision="bf16", proj=24)
+    assert e.value.code == fnn.FNN_EINVAL
