@@ -536,6 +536,41 @@ struct GramCfg<FNN_PREC_I8> {
 typedef __attribute__((ext_vector_type(4))) int i32x4;
 typedef __attribute__((ext_vector_type(16))) int i32x16;
 
+// OR of v over the wave, in every lane (DPP within rows of 16 lanes, then
+// row broadcasts; no LDS round trips).
+__device__ __forceinline__ unsigned wave_or_u32(unsigned v)
+{
+    v |= (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false);   // quad [1,0,3,2]
+    v |= (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false);   // quad [2,3,0,1]
+    v |= (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false);  // half mirror
+    v |= (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false);  // row mirror
+    v |= (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false);  // row bcast 15
+    v |= (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false);  // row bcast 31
+    return (unsigned)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+// Valid-row masks of a lane's accumulator positions: bit i is set when
+// r0(i) = 32 (i / 16) + 8 ((i % 16) / 4) + i % 4 is below rl, entry rl + 4
+// for rl = -4 .. 64.
+struct RowMaskTable {
+    unsigned m[69];
+};
+constexpr RowMaskTable make_rowmask()
+{
+    RowMaskTable t{};
+    for (int k = 0; k < 69; ++k) {
+        unsigned v = 0;
+        for (int i = 0; i < 32; ++i) {
+            const int r0 = (i >> 4) * 32 + 8 * ((i & 15) >> 2) + (i & 3);
+            if (r0 < k - 4)
+                v |= 1u << i;
+        }
+        t.m[k] = v;
+    }
+    return t;
+}
+__constant__ RowMaskTable c_rowmask = make_rowmask();
+
 // Marks this wave's unused reserved survivor slots [cpos, cend) (-1, -1).
 __device__ __forceinline__ void pad_surv(const GramArgs &G, unsigned long long cpos,
                                          unsigned long long cend)
@@ -579,34 +614,28 @@ __device__ __forceinline__ void block_finish(const GramArgs &G, const ACC (&accb
     if (!self && !G.validate && !__any(mx >= ay))
         return;
     const int col = cb * 32 + l32;
-    // Accumulator position i = 16 rb + q holds row r0(i) + 4 hi of
-    // column col in every lane, r0(i) = 32 rb + 8 (q / 4) + q % 4.
-    // Bit i of pm (om) says whether that pair passes (is valid: row
-    // < na, and row < col on a self tile; as r0 < rl with rl per
-    // tile, since a per-position mask would be hoisted out of the
-    // entry loop and spilled).
+    // Accumulator position i = 16 rb + q holds row r0(i) + 4 hi of column
+    // col in every lane, r0(i) = 32 rb + 8 (q / 4) + q % 4.  Bit i of om says
+    // whether that pair is valid (row < na, and row < col on a self tile:
+    // r0(i) < rl, looked up per tile), bit i of pm whether it also passes.
     const int rl = (col < nb ? (self ? min(na, col) : na) : 0) - 4 * hi;
-    unsigned pm = 0, om = 0;
+    const unsigned om = c_rowmask.m[min(max(rl + 4, 0), 68)];
+    unsigned pm = 0;
 #pragma unroll
     for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
-            const bool ok = rb * 32 + 8 * (q >> 2) + (q & 3) < rl;
             const V gq = PREC == FNN_PREC_FP8 ? (V)(accb[rb][q] * G.gscale)
                                               : (V)accb[rb][q];
-            pm |= (unsigned)(ok && gq >= ay) << (rb * 16 + q);
-            om |= (unsigned)ok << (rb * 16 + q);
+            pm |= (unsigned)(gq >= ay) << (rb * 16 + q);
         }
-    // ---- survivors: appended for the exact decision kernel -----
-    // Emitted: the passes, or (validating) every valid pair with
-    // its pass flag.  One ballot per position that some lane has
-    // set gives the pairs of rows r0 (lanes 0..31) and r0 + 4
-    // (lanes 32..63).
+    pm &= om;
+    // ---- survivors: appended for the exact decision kernel ---------------
+    // Emitted: the passes, or (validating) every valid pair with its pass
+    // flag.  One ballot per position that some lane has set gives the pairs
+    // of rows r0 (lanes 0..31) and r0 + 4 (lanes 32..63).
     const unsigned todo = G.validate ? om : pm;
-    unsigned any = todo;
-#pragma unroll
-    for (int o = 1; o < WAVE; o <<= 1)
-        any |= __shfl_xor(any, o, WAVE);
+    unsigned any = wave_or_u32(todo);
     int cdeg = 0;  // exact integer filter: edges of this lane's column
     while (any) {
         const int i = __ffs(any) - 1;
@@ -1022,10 +1051,12 @@ k_gram_direct(Pts P, GramArgs G, TileOut out)
             eC[i] = G.pcl ? G.pcl[pbb] : -1;
         }
         __syncthreads();
-        // B fragments and column terms of one entry (columns 32 cb + l32)
-        int4 Bn[2][NKS];
-        float ayn[2];
-        auto load_b = [&](int e) {
+        // B fragments and column terms of one entry (columns 32 cb + l32), in
+        // two register sets: entry e uses set e % 2, whose load was issued
+        // two entries earlier (no copy of a register with a load in flight)
+        int4 BA[2][NKS], BB[2][NKS];
+        float ayA[2], ayB[2];
+        auto load_b = [&](int e, int4 (&B)[2][NKS], float (&ay)[2]) {
             const int pbb = eP[e - e0], nbb = eN[e - e0];
 #pragma unroll
             for (int cb = 0; cb < 2; ++cb) {
@@ -1033,55 +1064,53 @@ k_gram_direct(Pts P, GramArgs G, TileOut out)
                 const bool ok = c < nbb;
 #pragma unroll
                 for (int ks = 0; ks < NKS; ++ks)
-                    Bn[cb][ks] = ok ? *(const int4 *)(Q + (size_t)(pbb + c) * rowb + ks * 32 +
-                                                      hi * 16)
-                                    : make_int4(0, 0, 0, 0);
-                ayn[cb] = ok ? 0.5f * G.hx[pbb + c] : FLT_MAX;
+                    B[cb][ks] = ok ? *(const int4 *)(Q + (size_t)(pbb + c) * rowb + ks * 32 +
+                                                     hi * 16)
+                                   : make_int4(0, 0, 0, 0);
+                ay[cb] = ok ? 0.5f * G.hx[pbb + c] : FLT_MAX;
             }
         };
-        load_b(e0);
-        for (int e = e0; e < e1; ++e) {
-            int4 Bc[2][NKS];
-            float ayc[2];
-#pragma unroll
-            for (int cb = 0; cb < 2; ++cb) {
-                ayc[cb] = ayn[cb];
-#pragma unroll
-                for (int ks = 0; ks < NKS; ++ks)
-                    Bc[cb][ks] = Bn[cb][ks];
-            }
+        auto step = [&](int e, int4 (&B)[2][NKS], float (&ay)[2]) {
             const int b = eB[e - e0], pb = eP[e - e0], nb = eN[e - e0];
             const bool skip = !has_a || b < a || (ca >= 0 && eC[e - e0] != ca);
-            if (e + 1 < e1)
-                load_b(e + 1);
-            if (skip)
-                continue;
-            const bool self = (b == a);
-            // one 32-column block at a time: the second block's matrix-core
-            // work overlaps the first block's filter
+            if (!skip) {
+                const bool self = (b == a);
+                // one 32-column block at a time: the second block's
+                // matrix-core work overlaps the first block's filter
 #pragma unroll
-            for (int cb = 0; cb < 2; ++cb) {
-                if (cb * 32 >= nb)
-                    break;
-                f32x16 acc[2];
+                for (int cb = 0; cb < 2; ++cb) {
+                    if (cb * 32 >= nb)
+                        break;
+                    f32x16 acc[2];
 #pragma unroll
-                for (int ks = 0; ks < NKS; ++ks) {
-                    bf16x8 bb;
-                    __builtin_memcpy(&bb, &Bc[cb][ks], 16);
+                    for (int ks = 0; ks < NKS; ++ks) {
+                        bf16x8 bb;
+                        __builtin_memcpy(&bb, &B[cb][ks], 16);
+#pragma unroll
+                        for (int rb = 0; rb < 2; ++rb)
+                            acc[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                                Af[rb][ks], bb, ks == 0 ? ax0[rb] : acc[rb], 0, 0, 0);
+                    }
+                    float mx = acc[0][0];
 #pragma unroll
                     for (int rb = 0; rb < 2; ++rb)
-                        acc[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                            Af[rb][ks], bb, ks == 0 ? ax0[rb] : acc[rb], 0, 0, 0);
+#pragma unroll
+                        for (int q = 0; q < 16; ++q)
+                            mx = fmaxf(mx, acc[rb][q]);
+                    block_finish<FNN_PREC_BF16>(G, acc, ay[cb], mx, cb, na, nb, self, pa,
+                                                pb, cpos, cend, npairs);
                 }
-                float mx = acc[0][0];
-#pragma unroll
-                for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-                    for (int q = 0; q < 16; ++q)
-                        mx = fmaxf(mx, acc[rb][q]);
-                block_finish<FNN_PREC_BF16>(G, acc, ayc[cb], mx, cb, na, nb, self, pa, pb,
-                                            cpos, cend, npairs);
             }
+            if (e + 2 < e1)
+                load_b(e + 2, B, ay);
+        };
+        load_b(e0, BA, ayA);
+        if (e0 + 1 < e1)
+            load_b(e0 + 1, BB, ayB);
+        for (int e = e0; e < e1; e += 2) {
+            step(e, BA, ayA);
+            if (e + 1 < e1)
+                step(e + 1, BB, ayB);
         }
         __syncthreads();  // eB.. are rewritten by the next unit
     }
