@@ -202,9 +202,11 @@ def main():
     ap.add_argument("--workload", default="c2a",
                     help="c2a c2b c2_50k c1 c3 c4 ang | c5 (many clouds, one "
                          "batch per dim) | c5_loop (one call per cloud)")
-    ap.add_argument("--precision", default="bf16",
-                    help="fp32 | bf16 | fp8 | i8 (Hamming codes) | auto (fp32 "
-                         "below dim 16, else bf16; i8 on Hamming codes)")
+    ap.add_argument("--precision", default="auto",
+                    help="auto (the library chooses per query: i8 on Hamming "
+                         "codes of <= 256 bits, bf16 on vector data where the "
+                         "filter's margin is small against eps^2, else fp32) "
+                         "| fp32 | bf16 | fp8 | i8 (Hamming codes)")
     ap.add_argument("--sched", default="two_pass")
     ap.add_argument("--proj", type=int, default=0,
                     help="filter on leading principal coordinates: 0 automatic, "
@@ -228,14 +230,13 @@ def main():
     import paper_2510_14147_amd as fnn
 
     def prec_for(metric, dim):
+        if args.precision == "auto":
+            return "auto"
         if metric == "hamming":
             # the integer filter covers codes of <= 256 bits
-            ok = args.precision in ("i8", "auto") and dim <= 256
-            return "i8" if ok else "fp32"
+            return "i8" if args.precision == "i8" and dim <= 256 else "fp32"
         if metric == "levenshtein":
             return "fp32"  # no filter precision to choose
-        if args.precision == "auto":
-            return "fp32" if dim < 16 else "bf16"
         if args.precision == "i8":
             raise SystemExit("--precision i8 applies to Hamming codes only")
         return args.precision
@@ -291,6 +292,8 @@ def main():
         opts.append(o)
     BUILD_KEYS = ("zeta", "kmax")
 
+    INV_PREC = {v: k for k, v in fnn.PRECISIONS.items()}
+
     def step():
         res = []
         for (xd, off, m, e, d, _), o in zip(jobs, opts):
@@ -303,7 +306,9 @@ def main():
                 tree = fnn.fnn_tree_build_batch(xd, off, m, **bo)
                 g = fnn.fnn_eps_graph_batch(tree, e, precision=o["precision"],
                                             sched=o["sched"], proj=o.get("proj", 0))
-            res.append((tree.stats, g.stats, g.nnz, d, o["precision"]))
+            # the precision the query ran with (the library resolves auto)
+            used = INV_PREC[int(g.stats["precision_used"])]
+            res.append((tree.stats, g.stats, g.nnz, d, used))
             del tree, g
         return res
 
@@ -374,7 +379,7 @@ def main():
                         else "u64 (xor + popcount)")
     elif metric == "levenshtein":
         out["dtype"] = "u64 (bit-parallel edit distance)"
-    if not args.no_plain and any(o["precision"] != "fp32" for o in opts):
+    if not args.no_plain and any(p != "fp32" for p in precs):
         # one step of the same workload on the plain FP32 tiles, for the
         # MFMA-vs-plain ratio (the edge counts must agree)
         torch.cuda.synchronize()

@@ -63,8 +63,13 @@ typedef enum {
     FNN_PREC_FP32 = 0,   /* direct-difference FP32 tiles (the plain path)      */
     FNN_PREC_BF16 = 1,   /* MFMA BF16 Gram filter, FP32 recompute of survivors */
     FNN_PREC_FP8 = 2,    /* MFMA FP8 (E4M3) Gram filter, FP32 recompute        */
-    FNN_PREC_I8 = 3      /* Hamming codes of <= 256 bits: exact int8 MFMA Gram */
+    FNN_PREC_I8 = 3,     /* Hamming codes of <= 256 bits: exact int8 MFMA Gram */
                          /* (bits as +-1 bytes: s.t = K - 2 d over K bits)     */
+    FNN_PREC_AUTO = 4    /* chosen per query: I8 for Hamming codes of <= 256  */
+                         /* bits; BF16 for L2 / angular with 16 <= dim <= 128 */
+                         /* when the filter's margin is small against eps^2   */
+                         /* (2 c1 mean|x - mu|^2 <= eps^2 / 2, mu per cloud); */
+                         /* FP32 tiles otherwise (stats: precision_used)      */
 } fnn_precision;
 
 /* How CSR rows are sized. */
@@ -153,7 +158,8 @@ typedef struct fnn_stats {
     int64_t proj_dim;         /* principal coordinates the filter used (0:   */
                               /* the coordinates themselves)                 */
     double proj_captured;     /* their share of the variance                  */
-    double reserved[2];
+    int64_t precision_used;   /* fnn_precision the query ran with            */
+    double reserved[1];
 } fnn_stats;
 
 /* Build the cover tree of n points (Algorithms 1-2).  points: device

@@ -23,7 +23,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfnn.so")
 
 METRICS = {"l2": 0, "angular": 1, "hamming": 2, "levenshtein": 3}
-PRECISIONS = {"fp32": 0, "bf16": 1, "fp8": 2, "i8": 3}
+PRECISIONS = {"fp32": 0, "bf16": 1, "fp8": 2, "i8": 3, "auto": 4}
 SCHEDS = {"two_pass": 0, "learned": 1}
 
 FNN_OK, FNN_EINVAL, FNN_ENOMEM, FNN_EHIP, FNN_EUNSUPPORTED, FNN_EINTERNAL = \
@@ -72,7 +72,7 @@ class fnn_stats(ctypes.Structure):
     _fields_ = ([(k, ctypes.c_int64) for k in _STAT_I64] +
                 [(k, ctypes.c_double) for k in _STAT_F64] +
                 [("proj_dim", ctypes.c_int64), ("proj_captured", ctypes.c_double),
-                 ("reserved", ctypes.c_double * 2)])
+                 ("precision_used", ctypes.c_int64), ("reserved", ctypes.c_double * 1)])
 
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -186,7 +186,8 @@ def _options(**kw) -> fnn_options:
 def _stats(handle) -> dict:
     s = fnn_stats()
     _check(lib().fnn_get_stats(handle, ctypes.byref(s)))
-    return {k: getattr(s, k) for k in _STAT_I64 + _STAT_F64 + ["proj_dim", "proj_captured"]}
+    return {k: getattr(s, k) for k in _STAT_I64 + _STAT_F64 +
+            ["proj_dim", "proj_captured", "precision_used"]}
 
 
 class Tree:

@@ -83,6 +83,11 @@ void edges_scatter_ham(const int2 *surv, long long ne, const Pts &P,
 void degrees_from_positions(const int32_t *degp, const int32_t *perm, int n,
                             int32_t *deg, unsigned long long *dsum, hipStream_t s);
 
+// 2 c1 mean|x - mu|^2 / t2min for the BF16 filter (mu per cloud): how much
+// its rounding margin widens the test against the smallest squared
+// threshold; small values mean a selective filter.
+double gram_margin_ratio(const fnn_tree *T, double t2min, Scratch &S);
+
 // True when no query pack exceeds the filter's tile height (the work list
 // of every pack pair then exists in closed form).
 bool gram_packs_fit(const fnn_tree *T, Scratch &S);

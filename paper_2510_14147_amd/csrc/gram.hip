@@ -1,9 +1,10 @@
 // MFMA Gram filter for the Euclidean and angular leaf tiles.
 //
 // d(x,y)^2 = |x|^2 + |y|^2 - 2 x.y.  The inner products of a tile are taken
-// on the matrix cores from BF16 (or FP8 E4M3) copies of the globally centred
-// points, accumulated in FP32.  With u the unit roundoff of the input
-// format, |q(x).q(y) - x.y| <= (2u + u^2)|x||y| (Cauchy-Schwarz), plus the
+// on the matrix cores from BF16 (or FP8 E4M3) copies of the centred points
+// (each cloud of a batch about its own mean), accumulated in FP32.  With u
+// the unit roundoff of the input format, |q(x).q(y) - x.y| <= (2u + u^2)
+// |x||y| (Cauchy-Schwarz), plus the
 // FP32 accumulation and the rounding of the norms; all of it is below
 // c1 * (|x|^2 + |y|^2).  A pair is rejected only if
 //     (1 - c1)(|x|^2 + |y|^2) - 2 g~ > eps^2,
@@ -55,25 +56,50 @@ constexpr int SURV_CHUNK = 512;
 
 // ---------------------------------------------------------------- prep ---
 
+// Centre of each point: the mean of its cloud (tree positions of a cloud are
+// contiguous; one cloud: pcl null).  Every pair the filter compares lies in
+// one cloud, so per-cloud centring changes none of its distances and keeps
+// the quantisation margin relative to the cloud's own spread.
+struct Centre {
+    const float *sums;     // [clouds][dp] column sums
+    const float *inv;      // [clouds] 1 / cloud size
+    const int32_t *pcl;    // [n] cloud of a tree position, or null
+    int dp;
+    __device__ __forceinline__ int cloud(long long i) const { return pcl ? pcl[i] : 0; }
+    __device__ __forceinline__ float mu(int cl, int c) const
+    {
+        return sums[(size_t)cl * dp + c] * inv[cl];
+    }
+};
+
+// Column sums per cloud: block b takes rows [b*R, (b+1)*R) and flushes a
+// partial sum whenever the cloud changes (clouds are contiguous).
 __global__ void k_colsum(const float *__restrict__ x, int n, int dp,
-                         float *__restrict__ sums)
+                         const int32_t *__restrict__ pcl, float *__restrict__ sums)
 {
-    // block b takes rows [b*R, (b+1)*R); thread t sums columns t, t+256..
     const int R = 1024;
     const int r0 = blockIdx.x * R, r1 = min(n, r0 + R);
     for (int c = threadIdx.x; c < dp; c += blockDim.x) {
         float s = 0.f;
-        for (int r = r0; r < r1; ++r)
+        int cc = (pcl && r0 < r1) ? pcl[r0] : 0;
+        for (int r = r0; r < r1; ++r) {
+            const int cl = pcl ? pcl[r] : 0;
+            if (cl != cc) {
+                atomicAdd(&sums[(size_t)cc * dp + c], s);
+                s = 0.f;
+                cc = cl;
+            }
             s += x[(size_t)r * dp + c];
-        atomicAdd(&sums[c], s);
+        }
+        if (r0 < r1)
+            atomicAdd(&sums[(size_t)cc * dp + c], s);
     }
 }
 
 // Quantised rows of x - mu (tree order) and the per-point norm term.
 template <int PREC>
 __global__ void k_quant(const float *__restrict__ x, int n, int dp, int kq,
-                        const float *__restrict__ sums, float inv_n,
-                        float scale, float one_minus_c1, void *__restrict__ q,
+                        Centre C, float scale, float one_minus_c1, void *__restrict__ q,
                         float *__restrict__ hx)
 {
     const int lane = threadIdx.x & (WAVE - 1);
@@ -81,10 +107,11 @@ __global__ void k_quant(const float *__restrict__ x, int n, int dp, int kq,
     for (int i = blockIdx.x * wpb + threadIdx.x / WAVE; i < n;
          i += gridDim.x * wpb) {
         float ss = 0.f;
+        const int cl = C.cloud(i);
         for (int k = lane; k < kq; k += WAVE) {
             float v = 0.f;
             if (k < dp) {
-                v = x[(size_t)i * dp + k] - sums[k] * inv_n;
+                v = x[(size_t)i * dp + k] - C.mu(cl, k);
                 ss = fmaf(v, v, ss);
             }
             if constexpr (PREC == FNN_PREC_BF16) {
@@ -118,14 +145,11 @@ constexpr int PCA_ROWS = 65536;  // covariance sample (rows, at most)
 // b takes sample rows in chunks of 32 starting at 32 b; thread t owns an
 // 8 x 8 block of the dp x dp matrix (dp <= 128).
 __global__ void __launch_bounds__(256)
-k_cov_partial(const float *__restrict__ x, int n, int dp, int stride,
-              const float *__restrict__ sums, float inv_n, double *__restrict__ part)
+k_cov_partial(const float *__restrict__ x, int n, int dp, int stride, Centre C,
+              double *__restrict__ part)
 {
     __shared__ float xs[32][128 + 1];
-    __shared__ float mu[128];
     const int t = threadIdx.x;
-    for (int c = t; c < dp; c += blockDim.x)
-        mu[c] = sums[c] * inv_n;
     const int bi = t / 16, bj = t % 16;
     const bool mine = 8 * bi < dp && 8 * bj < dp;
     float acc[8][8];
@@ -141,7 +165,8 @@ k_cov_partial(const float *__restrict__ x, int n, int dp, int stride,
         for (int e = t; e < 32 * dp; e += blockDim.x) {
             const int r = e / dp, c = e % dp;
             const long long j = j0 + r;
-            xs[r][c] = j < m ? x[(size_t)(j * stride) * dp + c] - mu[c] : 0.f;
+            xs[r][c] = j < m ? x[(size_t)(j * stride) * dp + c] - C.mu(C.cloud(j * stride), c)
+                             : 0.f;
         }
         __syncthreads();
         if (mine) {
@@ -336,8 +361,8 @@ k_pca(const double *__restrict__ C, int dp, int kmax, int kfix, double t2, doubl
 
 // z = Q^T (x - mu) in FP64, stored as FP32 rows [n][K] (tree order).
 __global__ void __launch_bounds__(256)
-k_project(const float *__restrict__ x, int n, int dp, const float *__restrict__ sums,
-          double inv_n, const double *__restrict__ Q, int K, float *__restrict__ z)
+k_project(const float *__restrict__ x, int n, int dp, Centre C,
+          const double *__restrict__ Q, int K, float *__restrict__ z)
 {
     const long long tot = (long long)n * K;
     for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
@@ -345,26 +370,48 @@ k_project(const float *__restrict__ x, int n, int dp, const float *__restrict__ 
         const long long i = e / K;
         const int k = (int)(e - i * K);
         const float *xr = x + (size_t)i * dp;
+        const int cl = C.cloud(i);
         double v = 0.0;
         for (int c = 0; c < dp; ++c)
-            v += Q[(size_t)c * K + k] * ((double)xr[c] - (double)sums[c] * inv_n);
+            v += Q[(size_t)c * K + k] *
+                 ((double)xr[c] - (double)C.sums[(size_t)cl * dp + c] * (double)C.inv[cl]);
         z[e] = (float)v;
     }
 }
 
-__global__ void k_absmax(const float *__restrict__ x, int n, int dp,
-                         const float *__restrict__ sums, float inv_n,
+__global__ void k_absmax(const float *__restrict__ x, int n, int dp, Centre C,
                          unsigned *__restrict__ mx)
 {
     float m = 0.f;
     const int64_t tot = (int64_t)n * dp;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
          e += (int64_t)gridDim.x * blockDim.x)
-        m = fmaxf(m, fabsf(x[e] - sums[e % dp] * inv_n));
+        m = fmaxf(m, fabsf(x[e] - C.mu(C.cloud(e / dp), (int)(e % dp))));
     // one atomic per wave; the grid is capped so that few waves contend
     m = wave_max(m);
     if ((threadIdx.x & (WAVE - 1)) == 0)
         atomicMax(mx, __float_as_uint(m));
+}
+
+// Sum over points of |x - mu|^2 (mu per cloud), one atomic per wave.
+__global__ void k_sqdev(const float *__restrict__ x, int n, int dp, Centre C,
+                        double *__restrict__ out)
+{
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wpb = blockDim.x / WAVE;
+    double acc = 0.0;
+    for (int i = blockIdx.x * wpb + threadIdx.x / WAVE; i < n; i += gridDim.x * wpb) {
+        const int cl = C.cloud(i);
+        float ss = 0.f;
+        for (int k = lane; k < dp; k += WAVE) {
+            const float v = x[(size_t)i * dp + k] - C.mu(cl, k);
+            ss = fmaf(v, v, ss);
+        }
+        acc += (double)ss;
+    }
+    acc = wave_sum(acc);
+    if (lane == 0 && acc != 0.0)
+        atomicAdd(out, acc);
 }
 
 // Hamming codes as signed bytes for the integer Gram: bit b of a code
@@ -1461,7 +1508,7 @@ static void quantise_ham(const fnn_tree *T, int prec, Scratch &S, GramArgs &G)
 // query (FP64 rounding of the projection must also stay below 5e-7 of its
 // root, else K = 0).
 static int project_pca(const float *X, int n, int dp, int kq_full, int proj,
-                       double t2min, const float *sums, Scratch &S, float **z,
+                       double t2min, const Centre &CX, Scratch &S, float **z,
                        double *rho, double *captured)
 {
     hipStream_t s = S.stream();
@@ -1473,16 +1520,15 @@ static int project_pca(const float *X, int n, int dp, int kq_full, int proj,
     const int nparts = (int)std::min<long long>(64, cdiv(m, 32));
     const int dd = dp * dp;
     double *part = S.get<double>((size_t)nparts * dd);
-    double *C = S.get<double>(dd);
-    FNN_LAUNCH(k_cov_partial, dim3(nparts), dim3(256), 0, s, X, n, dp, stride, sums,
-               1.0f / n, part);
+    double *Cv = S.get<double>(dd);
+    FNN_LAUNCH(k_cov_partial, dim3(nparts), dim3(256), 0, s, X, n, dp, stride, CX, part);
     FNN_LAUNCH(k_cov_reduce, dim3(grid_for(dd, 256)), dim3(256), 0, s, part, nparts, dd,
-               1.0 / (double)m, C);
+               1.0 / (double)m, Cv);
     double *Y = S.get<double>((size_t)kmax * dp), *Z = S.get<double>((size_t)kmax * dp);
     double *Qd = S.get<double>((size_t)kmax * dp);
     int *kout = S.get<int>(1);
     double *info = S.get<double>(2);
-    FNN_LAUNCH(k_pca, dim3(1), dim3(256), 0, s, C, dp, kmax, proj, t2min, 0.5, Y, Z, Qd,
+    FNN_LAUNCH(k_pca, dim3(1), dim3(256), 0, s, Cv, dp, kmax, proj, t2min, 0.5, Y, Z, Qd,
                kout, info);
     const int K = read_scalar(kout, s);
     double hinfo[2];
@@ -1495,7 +1541,7 @@ static int project_pca(const float *X, int n, int dp, int kq_full, int proj,
     unsigned *mx = S.get<unsigned>(1);
     fill(mx, 0u, 1, s);
     FNN_LAUNCH(k_absmax, dim3(grid_cap((int64_t)n * dp, 256, 2048)), dim3(256), 0, s, X, n, dp,
-               sums, 1.0f / n, mx);
+               CX, mx);
     const unsigned mb = read_scalar(mx, s);
     float am;
     memcpy(&am, &mb, 4);
@@ -1507,10 +1553,55 @@ static int project_pca(const float *X, int n, int dp, int kq_full, int proj,
         return 0;
     *z = S.get<float>((size_t)n * K);
     FNN_LAUNCH(k_project, dim3(grid_cap((int64_t)n * K, 256, 16384)), dim3(256), 0, s, X, n,
-               dp, sums, 1.0 / n, Qd, K, *z);
+               dp, CX, Qd, K, *z);
     *rho = hinfo[0];
     *captured = hinfo[1];
     return K;
+}
+
+// Per-cloud centres of the rows X [n][dp] (one cloud: the global mean).
+static Centre make_centre(const fnn_tree *T, const float *X, int dp, const float *inv,
+                          Scratch &S)
+{
+    hipStream_t s = S.stream();
+    const int n = (int)T->n, ncl = T->ncloud;
+    const int32_t *pcl = ncl > 1 ? T->pcl : nullptr;
+    float *sums = S.get<float>((size_t)ncl * dp);
+    fill(sums, 0.f, (int64_t)ncl * dp, s);
+    FNN_LAUNCH(k_colsum, dim3((unsigned)cdiv(n, 1024)), dim3(256), 0, s, X, n, dp, pcl, sums);
+    return Centre{sums, inv, pcl, dp};
+}
+
+// 1 / size of every cloud, on the device.
+static float *cloud_inv_sizes(const fnn_tree *T, Scratch &S)
+{
+    hipStream_t s = S.stream();
+    const int ncl = T->ncloud;
+    float *inv = S.get<float>(ncl);
+    std::vector<float> ih(ncl);
+    for (int c = 0; c < ncl; ++c) {
+        const int64_t sz = ncl == 1 ? T->n : T->cloud_off_h[c + 1] - T->cloud_off_h[c];
+        ih[c] = 1.0f / (float)std::max<int64_t>(sz, 1);
+    }
+    FNN_HIP(hipMemcpyAsync(inv, ih.data(), sizeof(float) * ncl, hipMemcpyHostToDevice, s));
+    FNN_HIP(hipStreamSynchronize(s));  // ih goes out of scope
+    return inv;
+}
+
+double gram_margin_ratio(const fnn_tree *T, double t2min, Scratch &S)
+{
+    hipStream_t s = S.stream();
+    const int n = (int)T->n, dp = T->dp, d = T->dim;
+    const float *X = T->metric == M_ANG ? T->xn : T->x;
+    const Centre CX = make_centre(T, X, dp, cloud_inv_sizes(T, S), S);
+    double *acc = S.get<double>(1);
+    fill(acc, 0.0, 1, s);
+    FNN_LAUNCH(k_sqdev, dim3(grid_cap(n, 4, 4096)), dim3(256), 0, s, X, n, dp, CX, acc);
+    const double mean = read_scalar(acc, s) / std::max(n, 1);
+    const double u32 = 1.0 / 16777216.0;
+    const int kq = (int)cdiv(dp, 16) * 16;
+    const double c1 = 2.25 / 256.0 + (4.0 * kq + 2.0 * d + 72.0) * u32;
+    return t2min > 0 ? 2.0 * c1 * mean / t2min : HUGE_VAL;
 }
 
 // Centred, shrunk BF16 or FP8 copy of the coordinates (or of their leading
@@ -1535,10 +1626,9 @@ static void quantise_real(const fnn_tree *T, int prec, int proj, double t2min,
     const int KS = prec == FNN_PREC_BF16 ? 16 : 64;
     if (cdiv(dp, KS) * KS > 128)
         fail(FNN_EUNSUPPORTED, "MFMA filter supports dim <= 128 (got %d)", d);
-    float *sums = S.get<float>(dp);
-    fill(sums, 0.f, dp, s);
-    FNN_LAUNCH(k_colsum, dim3((unsigned)cdiv(n, 1024)), dim3(256), 0, s, X, n,
-               dp, sums);
+    // per-cloud centres (one cloud: the global mean)
+    const float *inv = cloud_inv_sizes(T, S);
+    Centre CX = make_centre(T, X, dp, inv, S);
     G.t2mul = 1.0;
     G.proj = 0;
     G.captured = 0.0;
@@ -1546,7 +1636,7 @@ static void quantise_real(const fnn_tree *T, int prec, int proj, double t2min,
     {
         float *z = nullptr;
         double rho = 1.0, cap = 0.0;
-        const int K = project_pca(X, n, dp, (int)cdiv(dp, KS) * KS, proj, t2min, sums, S,
+        const int K = project_pca(X, n, dp, (int)cdiv(dp, KS) * KS, proj, t2min, CX, S,
                                   &z, &rho, &cap);
         if (K > 0) {
             X = z;
@@ -1555,10 +1645,7 @@ static void quantise_real(const fnn_tree *T, int prec, int proj, double t2min,
             G.proj = K;
             G.captured = cap;
             c_extra = 1e-7;
-            sums = S.get<float>(dp);
-            fill(sums, 0.f, dp, s);
-            FNN_LAUNCH(k_colsum, dim3((unsigned)cdiv(n, 1024)), dim3(256), 0, s, X, n,
-                       dp, sums);
+            CX = make_centre(T, X, dp, inv, S);
         }
     }
     const int kq = (int)cdiv(dp, KS) * KS;
@@ -1574,7 +1661,7 @@ static void quantise_real(const fnn_tree *T, int prec, int proj, double t2min,
         unsigned *mx = S.get<unsigned>(1);
         fill(mx, 0u, 1, s);
         FNN_LAUNCH(k_absmax, dim3(grid_cap((int64_t)n * dp, 256, 2048)), dim3(256), 0,
-                   s, X, n, dp, sums, 1.0f / n, mx);
+                   s, X, n, dp, CX, mx);
         unsigned mb = read_scalar(mx, s);
         float m;
         memcpy(&m, &mb, 4);
@@ -1592,12 +1679,10 @@ static void quantise_real(const fnn_tree *T, int prec, int proj, double t2min,
     G.hx = hxbuf;
     if (prec == FNN_PREC_BF16)
         FNN_LAUNCH((k_quant<FNN_PREC_BF16>), dim3(grid_cap(n, 4, 16384)), dim3(256), 0,
-                   s, X, n, dp, kq, sums, 1.0f / n, scale, (float)(1.0 - c1), qbuf,
-                   hxbuf);
+                   s, X, n, dp, kq, CX, scale, (float)(1.0 - c1), qbuf, hxbuf);
     else
         FNN_LAUNCH((k_quant<FNN_PREC_FP8>), dim3(grid_cap(n, 4, 16384)), dim3(256), 0,
-                   s, X, n, dp, kq, sums, 1.0f / n, scale, (float)(1.0 - c1), qbuf,
-                   hxbuf);
+                   s, X, n, dp, kq, CX, scale, (float)(1.0 - c1), qbuf, hxbuf);
 }
 
 bool gram_packs_fit(const fnn_tree *T, Scratch &S)

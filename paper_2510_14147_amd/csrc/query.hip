@@ -1359,8 +1359,24 @@ static void eps_graph_impl(const fnn_tree *Tc, const double *epsv,
         mlp_forward(Lm.model, Lm.feat, n, Lm.pred, s);
     }
 
-    const bool use_gram = ((M == M_L2 || M == M_ANG) && opt.precision != FNN_PREC_FP32) ||
-                          (M == M_HAM && opt.precision == FNN_PREC_I8);
+    double t2min = HUGE_VAL;  // smallest squared threshold of the filter's key
+    for (int c = 0; c < ncl; ++c)
+        t2min = std::min(t2min, gram_t2(M, epsv[c], ct_h[c].E));
+    // filter precision: the caller's, or (automatic) the MFMA filter where it
+    // pays: int8 on short Hamming codes; BF16 on vector data of 16..128
+    // coordinates when its rounding margin is small against eps^2
+    int prec = opt.precision;
+    if (prec == FNN_PREC_AUTO) {
+        prec = FNN_PREC_FP32;
+        if (M == M_HAM && T->dp <= 4)
+            prec = FNN_PREC_I8;
+        if ((M == M_L2 || M == M_ANG) && T->dim >= 16 && T->dp <= 128 &&
+            gram_margin_ratio(T, t2min, S) <= 0.5)
+            prec = FNN_PREC_BF16;
+    }
+    st.precision_used = prec;
+    const bool use_gram = ((M == M_L2 || M == M_ANG) && prec != FNN_PREC_FP32) ||
+                          (M == M_HAM && prec == FNN_PREC_I8);
 
     // ---- traversal ------------------------------------------------------
     // Where the traversal's own pack-level test would keep nearly every pack
@@ -1395,10 +1411,7 @@ static void eps_graph_impl(const fnn_tree *Tc, const double *epsv,
     long long nplain = ninter;
     if constexpr (M == M_L2 || M == M_ANG || M == M_HAM) {
         if (use_gram) {
-            double t2min = HUGE_VAL;
-            for (int c = 0; c < ncl; ++c)
-                t2min = std::min(t2min, gram_t2(M, epsv[c], ct_h[c].E));
-            gram_prepare(T, opt.precision, opt.proj, eps, E, t2min, inter, ninter, S, G,
+            gram_prepare(T, prec, opt.proj, eps, E, t2min, inter, ninter, S, G,
                          &plain, &nplain);
             G.fp64_dist = fp64_dist;
             G.validate = opt.validate;
@@ -1467,8 +1480,8 @@ static void eps_graph_impl(const fnn_tree *Tc, const double *epsv,
                 double hacc[3];
                 FNN_HIP(hipMemcpyAsync(hacc, acc, sizeof hacc, hipMemcpyDeviceToHost, s));
                 FNN_HIP(hipStreamSynchronize(s));
-                const double fac = opt.precision == FNN_PREC_I8     ? 1.25
-                                   : opt.precision == FNN_PREC_BF16 ? 2.0
+                const double fac = prec == FNN_PREC_I8     ? 1.25
+                                   : prec == FNN_PREC_BF16 ? 2.0
                                                                     : 40.0;
                 cap = std::max<long long>(1ll << 20, (long long)(0.5 * hacc[1] * fac));
             }
@@ -1489,7 +1502,7 @@ static void eps_graph_impl(const fnn_tree *Tc, const double *epsv,
                 fill(ns, 0ull, 2, s);
                 fill(cnt + 2, 0ull, 1, s);
                 FNN_HIP(hipEventRecord(fev[0], s));
-                gram_launch(M, opt.precision, false, P, G, o, s);
+                gram_launch(M, prec, false, P, G, o, s);
                 FNN_HIP(hipEventRecord(fev[1], s));
                 const long long got = (long long)read_scalar(ns, s);
                 if (got <= cap || attempt > 0) {

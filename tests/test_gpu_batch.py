@@ -191,6 +191,15 @@ def test_batch_projected_filter(fnn, orc):
     run_batch(fnn, orc, clouds, "l2", eps, precision="bf16", validate=1, proj=32)
 
 
+def test_batch_auto_precision(fnn, orc):
+    # wide mixture clouds: the filter's margin is large against each cloud's
+    # eps, so the automatic choice may fall back to the plain tiles; either
+    # way the graph is exact
+    clouds = [mixture(n, 64, 900 + i) for i, n in enumerate([2500, 90, 1, 3000, 700])]
+    eps = eps_for(clouds, 17, 0.02, 0.08)
+    run_batch(fnn, orc, clouds, "l2", eps, precision="auto", per_cloud=False)
+
+
 def test_batch_learned(fnn, orc):
     clouds = [mixture(n, 16, 700 + i) for i, n in enumerate([4000, 3, 2500, 65, 1800])]
     eps = eps_for(clouds, 11)

@@ -236,3 +236,26 @@ def test_projected_filter_rejects_bad_width(fnn, orc):
     with pytest.raises(fnn.FnnError) as e:
         fnn.fnn_eps_graph(tree, 0.5, precision="bf16", proj=24)
     assert e.value.code == fnn.FNN_EINVAL
+
+
+# ---- automatic precision ------------------------------------------------------
+
+@pytest.mark.parametrize("case,want", [("c2_20k", "bf16"), ("rand8", "fp32"),
+                                       ("ham256", "i8"), ("ham512", "fp32"),
+                                       ("lev", "fp32")])
+def test_auto_precision(fnn, orc, case, want):
+    # the library picks the filter per query; the graph stays exact
+    if case == "c2_20k":
+        x, metric, eps = G.c2_manifold(n=20000), "l2", W["c2_50k"]["eps"][0]
+    elif case == "rand8":
+        x, metric, eps = G.random_points(3000, 8, seed=9), "l2", 0.3
+    elif case == "ham256":
+        x, metric, eps = G.random_codes(3000, 256, seed=10, flip=0.06), "hamming", 20
+    elif case == "ham512":
+        x, metric, eps = G.random_codes(1500, 512, seed=11, flip=0.06), "hamming", 40
+    else:
+        x = G.random_strings(800, seed=12, n_seeds=20, min_len=30, max_len=60)
+        metric, eps = "levenshtein", 5
+    tree, g, cmp = check(fnn, orc, x, metric, eps, tree_check=False, precision="auto")
+    names = {v: k for k, v in fnn.PRECISIONS.items()}
+    assert names[int(g.stats["precision_used"])] == want
