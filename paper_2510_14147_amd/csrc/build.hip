@@ -454,6 +454,10 @@ constexpr int SEL_T = 256;
 constexpr int MAX_K = 256;     // candidates examined per hub and pass
 constexpr int SEL_BUF = 2048;  // LDS sort buffer (candidate keys)
 constexpr int SEL_W = MAX_K / 64;
+// candidates read per round of the top-K stream: at most SEL_BUF - MAX_K, so
+// a round always fits after a sort has cut buf to K keys
+constexpr int SEL_STEP = 4 * SEL_T;
+static_assert(SEL_STEP <= SEL_BUF - MAX_K, "top-K stream round too large");
 
 // Sort key of a chunk candidate: farther first, then the smaller input id
 // (0 = no candidate).
@@ -501,7 +505,7 @@ k_select(Pts P, Hubs hb, int H, int32_t *__restrict__ cent,
     __shared__ unsigned long long buf[SEL_BUF];
     __shared__ unsigned long long conf[MAX_K][SEL_W];
     __shared__ int acc[MAX_K];
-    __shared__ int nacc_s, nk_s, qb_s;
+    __shared__ int nacc_s, nk_s, qb_s, fill_s;
     const int K = min(kmax, MAX_K);
     for (int h = blockIdx.x; h < H; h += gridDim.x) {
     if (!hb.act[h])
@@ -511,35 +515,52 @@ k_select(Pts P, Hubs hb, int H, int32_t *__restrict__ cent,
     const int b = hb.b[h], m0 = hb.m[h];
     const Thr T = tab->t[hb.lvl[h] - 1 + LOFF];
 
-    // ---- top-K candidates: sort blocks of chunks, keep the best K -------
+    // ---- top-K candidates ------------------------------------------------
+    // The candidates stream through once; a key enters buf only when it is
+    // above thr, the K-th best key of the last sort (keys are distinct), and
+    // buf is sorted and cut to its best K only when it fills.  Exactly the
+    // K largest keys remain, in order.
+    if (threadIdx.x == 0)
+        fill_s = 0;
+    unsigned long long thr = 0ull;  // no candidate has key 0
     int nk = 0;
-    for (long long base = c0; base < c1; base += SEL_BUF - K) {
-        const int m = (int)min((long long)(SEL_BUF - K), c1 - base);
-        const int tot = nk + m;
+    __syncthreads();
+    auto compact = [&]() {
+        const int tot = fill_s;
         int p2 = 1;
         while (p2 < tot)
             p2 <<= 1;
-        for (int i = nk + threadIdx.x; i < p2; i += SEL_T) {
-            unsigned long long kv = 0ull;
-            if (i < tot) {
-                // candidate q of the hub: slot q % R of its chunk q / R
-                const long long q = base + i - nk;
-                const size_t at = (size_t)(q / R) * CAND_R + (size_t)(q % R);
-                kv = cand_key(cb_D[at], cb_id[at]);
-            }
-            buf[i] = kv;
-        }
+        for (int i = tot + threadIdx.x; i < p2; i += SEL_T)
+            buf[i] = 0ull;
         __syncthreads();
         sort_desc(buf, p2);
         nk = min(K, tot);
+        if (nk == K)
+            thr = buf[K - 1];
+        __syncthreads();
+        if (threadIdx.x == 0)
+            fill_s = nk;
+        __syncthreads();
+    };
+    for (long long base = c0; base < c1; base += SEL_STEP) {
+#pragma unroll
+        for (int r = 0; r < SEL_STEP / SEL_T; ++r) {
+            // candidate q of the hub: slot q % R of its chunk q / R
+            const long long q = base + r * SEL_T + threadIdx.x;
+            if (q < c1) {
+                const size_t at = (size_t)(q / R) * CAND_R + (size_t)(q % R);
+                const unsigned long long kv = cand_key(cb_D[at], cb_id[at]);
+                if (kv > thr)
+                    buf[atomicAdd(&fill_s, 1)] = kv;  // fill_s <= SEL_BUF - SEL_STEP before
+            }
+        }
+        __syncthreads();
+        if (fill_s > SEL_BUF - SEL_STEP)
+            compact();
     }
-    // valid candidates are a prefix of buf (key 0 sorts last)
-    if (threadIdx.x == 0) {
-        int v = 0;
-        while (v < nk && buf[v] != 0ull)
-            ++v;
-        nk_s = v;
-    }
+    compact();
+    if (threadIdx.x == 0)
+        nk_s = nk;
     for (int i = threadIdx.x; i < MAX_K * SEL_W; i += SEL_T)
         conf[i / SEL_W][i % SEL_W] = 0ull;
     __syncthreads();
