@@ -1042,7 +1042,7 @@ k_gram(Pts P, GramArgs G, TileOut out)
 // waves of its work-group; the four waves of a group read the same B rows
 // at about the same time, so most of those reads hit L1.
 template <int M, int NKS>
-__global__ void __launch_bounds__(GT, 2)
+__global__ void __launch_bounds__(GT, NKS == 1 ? 3 : 2)  // 3 waves / SIMD fit at k = 16
 k_gram_direct(Pts P, GramArgs G, TileOut out)
 {
     static_assert(NKS >= 1 && NKS <= 2, "narrow rows only");
