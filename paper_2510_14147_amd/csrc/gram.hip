@@ -1042,12 +1042,13 @@ k_gram(Pts P, GramArgs G, TileOut out)
 // waves of its work-group; the four waves of a group read the same B rows
 // at about the same time, so most of those reads hit L1.
 template <int M, int NKS>
-__global__ void __launch_bounds__(GT, NKS == 1 ? 3 : 2)  // 3 waves / SIMD fit at k = 16
+__global__ void __launch_bounds__(GT, NKS == 1 ? 4 : 3)  // waves / SIMD that fit unspilled
 k_gram_direct(Pts P, GramArgs G, TileOut out)
 {
     static_assert(NKS >= 1 && NKS <= 2, "narrow rows only");
     constexpr int rowb = NKS * 32;  // bytes per quantised row
     __shared__ int eB[UNIT_MAX], eP[UNIT_MAX], eN[UNIT_MAX], eC[UNIT_MAX];
+    __shared__ __align__(16) float axS[GW][GP];  // accumulator start -ax per row
     const int t = threadIdx.x, lane = t & (WAVE - 1), w = t / WAVE;
     const int l32 = lane & 31, hi = lane >> 5;
     const unsigned char *Q = (const unsigned char *)G.q;
@@ -1078,17 +1079,13 @@ k_gram_direct(Pts P, GramArgs G, TileOut out)
                     v = *(const int4 *)(Q + (size_t)(pa + r) * rowb + ks * 32 + hi * 16);
                 __builtin_memcpy(&Af[rb][ks], &v, 16);
             }
-        // accumulator start values -ax of this lane's rows
+        // accumulator start values -ax of the wave's rows, in LDS (read as
+        // the first MFMA's addend of every block, so they hold no registers
+        // across the entry loop)
         const int ca = (G.pcl && has_a) ? G.pcl[pa] : -1;
         const float e2 = ca >= 0 ? G.ct[ca].e2f : G.e2f;
-        f32x16 ax0[2];
-#pragma unroll
-        for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                const int r = rb * 32 + 8 * (q >> 2) + 4 * hi + (q & 3);
-                ax0[rb][q] = r < na ? -0.5f * (G.hx[pa + r] - e2) : -FLT_MAX;
-            }
+        for (int r = lane; r < GP; r += WAVE)
+            axS[w][r] = r < na ? -0.5f * (G.hx[pa + r] - e2) : -FLT_MAX;
         for (int i = t; i < e1 - e0; i += GT) {
             const int bb = G.nn + G.lb[e0 + i];
             const int pbb = G.q_pb[bb];
@@ -1130,13 +1127,24 @@ k_gram_direct(Pts P, GramArgs G, TileOut out)
                         break;
                     f32x16 acc[2];
 #pragma unroll
+                    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+                        for (int q4 = 0; q4 < 4; ++q4) {
+                            const float4 a4 = *reinterpret_cast<const float4 *>(
+                                &axS[w][rb * 32 + 8 * q4 + 4 * hi]);
+                            acc[rb][4 * q4 + 0] = a4.x;
+                            acc[rb][4 * q4 + 1] = a4.y;
+                            acc[rb][4 * q4 + 2] = a4.z;
+                            acc[rb][4 * q4 + 3] = a4.w;
+                        }
+#pragma unroll
                     for (int ks = 0; ks < NKS; ++ks) {
                         bf16x8 bb;
                         __builtin_memcpy(&bb, &B[cb][ks], 16);
 #pragma unroll
                         for (int rb = 0; rb < 2; ++rb)
                             acc[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                                Af[rb][ks], bb, ks == 0 ? ax0[rb] : acc[rb], 0, 0, 0);
+                                Af[rb][ks], bb, acc[rb], 0, 0, 0);
                     }
                     float mx = acc[0][0];
 #pragma unroll
