@@ -180,6 +180,21 @@ int fnn_eps_graph(const fnn_tree *tree, double eps, fnn_csr **out);
 int fnn_eps_graph_ex(const fnn_tree *tree, double eps,
                      const fnn_options *opt, fnn_csr **out);
 
+/* Bichromatic range query: every pair (q, p), q a row of `queries`, p a point
+ * of `tree`, with d(q, p) <= eps (the query of foreign points against a local
+ * tree that Algorithms 4-6 run on each rank; here on one GPU).  queries:
+ * device pointer, nq rows in the tree's metric layout and dim, caller-owned,
+ * only read during the call.  The queries get a cover tree of their own
+ * (built with `opt`); Algorithm 3 then runs on the pair of trees, visiting
+ * only pairs across them.  *out: CSR with nq rows (query order), columns =
+ * the tree's input indices, ascending, dist as in fnn_eps_graph; the same
+ * exactness.  The tree must hold one cloud (FNN_EUNSUPPORTED for a batch);
+ * the learned schedule and traces are not available (FNN_EUNSUPPORTED);
+ * eps must be finite and > 0 (FNN_EINVAL).  Stats (fnn_get_stats on the
+ * CSR) count the query tree's build as well. */
+int fnn_eps_query(const fnn_tree *tree, const void *queries, int64_t nq, double eps,
+                  const fnn_options *opt, fnn_csr **out);
+
 /* ---- many independent clouds in one batch ---------------------------------
  * The level-synchronous build (Algorithm 2 processes every hub of a level
  * together) and the batched query (Algorithm 3 over query batches) extend to

@@ -129,6 +129,9 @@ def lib():
                                        ctypes.POINTER(ctypes.POINTER(fnn_csr))]
         L.fnn_eps_graph.argtypes = [vp, ctypes.c_double,
                                     ctypes.POINTER(ctypes.POINTER(fnn_csr))]
+        L.fnn_eps_query.argtypes = [vp, vp, i64, ctypes.c_double,
+                                    ctypes.POINTER(fnn_options),
+                                    ctypes.POINTER(ctypes.POINTER(fnn_csr))]
         L.fnn_tree_build_batch.argtypes = [vp, ctypes.POINTER(i64), i32, i32,
                                            ctypes.c_int, ctypes.POINTER(fnn_options),
                                            ctypes.POINTER(vp)]
@@ -393,6 +396,24 @@ def fnn_eps_graph(tree: Tree, eps: float, precision="fp32",
                  trace=int(trace), slack_pct=slack_pct, proj=proj)
     _check(lib().fnn_eps_graph_ex(tree.handle, float(eps), ctypes.byref(o),
                                   ctypes.byref(out)))
+    return Graph(out)
+
+
+def fnn_eps_query(tree: Tree, queries, eps: float, precision="fp32",
+                  sched="two_pass", validate=False, proj=None, zeta=None,
+                  pack=None, kmax=None) -> Graph:
+    """Bichromatic range query: rows of ``queries`` (the tree's metric and
+    dim) against the tree's points; a CSR with one row per query, columns =
+    the tree's input indices."""
+    t, dim = _as_device_points(queries, tree.metric)
+    if dim != tree.dim:
+        raise ValueError(f"queries have dim {dim}, the tree {tree.dim}")
+    _bind_stream()
+    out = ctypes.POINTER(fnn_csr)()
+    o = _options(precision=precision, sched=sched, validate=int(validate), proj=proj,
+                 zeta=zeta, pack=pack, kmax=kmax)
+    _check(lib().fnn_eps_query(tree.handle, ctypes.c_void_p(t.data_ptr()), t.shape[0],
+                               float(eps), ctypes.byref(o), ctypes.byref(out)))
     return Graph(out)
 
 

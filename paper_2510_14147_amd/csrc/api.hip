@@ -14,6 +14,7 @@ namespace fnn {
 extern thread_local hipStream_t g_stream;
 void set_alloc_hook(fnn_alloc_fn a, fnn_free_fn f, void *ctx);
 void build_tree(fnn_tree *T, const void *points, Scratch &S);
+fnn_tree *forest_pair(const fnn_tree *A, const fnn_tree *B, Scratch &S);
 void eps_graph(const fnn_tree *T, const double *eps, const Options &opt,
                fnn_csr *C, fnn_stats &st, Scratch &S, float **tf, float **tt);
 
@@ -95,6 +96,16 @@ struct CsrBox {
     float *trace_feat;
     float *trace_targ;
 };
+
+// Rows [r0, r0 + m) of a CSR: row_ptr shifted to start at 0.
+__global__ void k_row_slice(const int64_t *__restrict__ rp, int64_t r0, int64_t m,
+                            int64_t *__restrict__ out)
+{
+    const int64_t b = rp[r0];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= m;
+         i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = rp[r0 + i] - b;
+}
 
 static void free_box(CsrBox *B)
 {
@@ -284,6 +295,104 @@ static int eps_graph_any(const fnn_tree *tree, const double *eps, int32_t neps,
     } catch (...) {
         if (B)
             free_box(B);
+        return set_err(FNN_EINTERNAL, "unexpected exception");
+    }
+}
+
+int fnn_eps_query(const fnn_tree *tree, const void *queries, int64_t nq, double eps,
+                  const fnn_options *opt, fnn_csr **out)
+{
+    if (!out)
+        return set_err(FNN_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!tree || tree->kind != KIND_TREE)
+        return set_err(FNN_EINVAL, "not a tree handle");
+    if (tree->ncloud != 1 || tree->ncloud_in != 1)
+        return set_err(FNN_EUNSUPPORTED, "bichromatic queries need a single-cloud tree");
+    if (!(eps > 0.0) || !isfinite(eps))
+        return set_err(FNN_EINVAL, "eps must be finite and > 0");
+    // the query points get a cover tree of their own (same options)
+    fnn_tree *TQ = nullptr;
+    const int rc = tree_build_any(queries, nq, nullptr, 1, tree->dim,
+                                  (fnn_metric)tree->metric, opt, &TQ);
+    if (rc != FNN_OK)
+        return rc;
+    fnn_tree *F = nullptr;
+    CsrBox *full = nullptr, *B = nullptr;
+    try {
+        Options o = read_options(opt);
+        Scratch S(current_stream());
+        hipStream_t s = S.stream();
+        F = forest_pair(tree, TQ, S);
+        full = new CsrBox();
+        memset(&full->pub, 0, sizeof full->pub);
+        memset(&full->stats, 0, sizeof full->stats);
+        full->trace_feat = full->trace_targ = nullptr;
+        full->pub.kind = KIND_CSR;
+        const double ev[2] = {eps, eps};
+        float *tf = nullptr, *tt = nullptr;
+        eps_graph(F, ev, o, &full->pub, full->stats, S, &tf, &tt);
+        // the query rows: input rows nA .. nA + nq - 1 of the pair forest,
+        // whose columns are the tree's points (only pairs across clouds)
+        const int64_t nA = tree->n;
+        int64_t se[2];
+        FNN_HIP(hipMemcpyAsync(se, full->pub.row_ptr + nA, sizeof(int64_t),
+                               hipMemcpyDeviceToHost, s));
+        FNN_HIP(hipMemcpyAsync(se + 1, full->pub.row_ptr + nA + nq, sizeof(int64_t),
+                               hipMemcpyDeviceToHost, s));
+        FNN_HIP(hipStreamSynchronize(s));
+        const int64_t nnz = se[1] - se[0];
+        B = new CsrBox();
+        memset(&B->pub, 0, sizeof B->pub);
+        B->stats = full->stats;
+        B->stats.n = nq;
+        B->stats.build_ms += TQ->stats.build_ms;
+        B->stats.build_dist_evals += TQ->stats.build_dist_evals;
+        B->stats.edges = nnz;
+        B->trace_feat = B->trace_targ = nullptr;
+        B->pub.kind = KIND_CSR;
+        B->pub.n = nq;
+        B->pub.nnz = nnz;
+        B->pub.row_ptr = (int64_t *)out_alloc(sizeof(int64_t) * (size_t)(nq + 1));
+        B->pub.col = (int32_t *)out_alloc(sizeof(int32_t) * (size_t)std::max<int64_t>(nnz, 1));
+        B->pub.dist = (float *)out_alloc(sizeof(float) * (size_t)std::max<int64_t>(nnz, 1));
+        FNN_LAUNCH(k_row_slice, dim3(grid_cap(nq + 1, 256, 4096)), dim3(256), 0, s,
+                   full->pub.row_ptr, nA, nq, B->pub.row_ptr);
+        if (nnz > 0) {
+            FNN_HIP(hipMemcpyAsync(B->pub.col, full->pub.col + se[0], sizeof(int32_t) * nnz,
+                                   hipMemcpyDeviceToDevice, s));
+            FNN_HIP(hipMemcpyAsync(B->pub.dist, full->pub.dist + se[0], sizeof(float) * nnz,
+                                   hipMemcpyDeviceToDevice, s));
+        }
+        FNN_HIP(hipStreamSynchronize(s));
+        free_box(full);
+        delete F;
+        delete TQ;
+        *out = &B->pub;
+        return FNN_OK;
+    } catch (const Error &e) {
+        if (full)
+            free_box(full);
+        if (B)
+            free_box(B);
+        delete F;
+        delete TQ;
+        return set_err(e.code, e.msg);
+    } catch (const std::bad_alloc &) {
+        if (full)
+            free_box(full);
+        if (B)
+            free_box(B);
+        delete F;
+        delete TQ;
+        return set_err(FNN_ENOMEM, "host allocation failed");
+    } catch (...) {
+        if (full)
+            free_box(full);
+        if (B)
+            free_box(B);
+        delete F;
+        delete TQ;
         return set_err(FNN_EINTERNAL, "unexpected exception");
     }
 }

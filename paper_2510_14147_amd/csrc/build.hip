@@ -1380,6 +1380,176 @@ static void build_impl(fnn_tree *T, const void *points, Scratch &S)
     T->depth = rounds;
 }
 
+// ------------------------------------------------- two-tree forest ------
+//
+// A bichromatic query (foreign points against a tree) runs as the self-join
+// of a two-cloud forest restricted to pairs across the clouds: vertex 0 is a
+// virtual root, the data tree A and the query tree B keep their shapes, and
+// the traversal starts from the pair of their query-tree roots.  Only the
+// arrays the query reads are assembled: points (tree order, A then B),
+// perm (B's input indices shifted by nA), the query tree and the cloud
+// tables.  Internal-vertex ids: 0 virtual, then A's (id v -> 1 + v), then
+// B's (v -> 1 + nnA + v); packs: A's, then B's, after all internal ids.
+
+__global__ void k_pair_qtree(int nq_src, int nn_src, int vbase, int pbase, int pos_off,
+                             int kid_off, const int32_t *__restrict__ cpos,
+                             const float *__restrict__ rad, const int32_t *__restrict__ pb,
+                             const int32_t *__restrict__ pe, const int32_t *__restrict__ kbeg,
+                             const int32_t *__restrict__ kcnt, int32_t *__restrict__ ocpos,
+                             float *__restrict__ orad, int32_t *__restrict__ opb,
+                             int32_t *__restrict__ ope, int32_t *__restrict__ okbeg,
+                             int32_t *__restrict__ okcnt)
+{
+    for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < nq_src;
+         v += gridDim.x * blockDim.x) {
+        const int d = v < nn_src ? vbase + v : pbase + (v - nn_src);
+        ocpos[d] = cpos[v] + pos_off;
+        orad[d] = rad[v];
+        opb[d] = pb[v] + pos_off;
+        ope[d] = pe[v] + pos_off;
+        okbeg[d] = kbeg[v] + kid_off;
+        okcnt[d] = kcnt[v];
+    }
+}
+
+__global__ void k_pair_kids(int nk, int nn_src, int vbase, int pbase,
+                            const int32_t *__restrict__ kids, int32_t *__restrict__ okids)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nk;
+         i += gridDim.x * blockDim.x) {
+        const int v = kids[i];
+        okids[i] = v < nn_src ? vbase + v : pbase + (v - nn_src);
+    }
+}
+
+__global__ void k_add_i32(const int32_t *__restrict__ src, int n, int add,
+                          int32_t *__restrict__ dst)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        dst[i] = src[i] + add;
+}
+
+static int total_kids(const fnn_tree *T, hipStream_t s)
+{
+    std::vector<int32_t> kb(T->nq), kc(T->nq);
+    FNN_HIP(hipMemcpyAsync(kb.data(), T->q_kbeg, sizeof(int32_t) * T->nq,
+                           hipMemcpyDeviceToHost, s));
+    FNN_HIP(hipMemcpyAsync(kc.data(), T->q_kcnt, sizeof(int32_t) * T->nq,
+                           hipMemcpyDeviceToHost, s));
+    FNN_HIP(hipStreamSynchronize(s));
+    int64_t m = 0;
+    for (int64_t v = 0; v < T->nq; ++v)
+        if (kc[v] > 0)
+            m = std::max<int64_t>(m, (int64_t)kb[v] + kc[v]);
+    return (int)m;
+}
+
+fnn_tree *forest_pair(const fnn_tree *A, const fnn_tree *B, Scratch &S)
+{
+    hipStream_t s = S.stream();
+    if (A->metric != B->metric || A->dp != B->dp || A->dim != B->dim || A->W != B->W ||
+        A->sigma != B->sigma)
+        fail(FNN_EINVAL, "query rows do not match the tree's metric and dimension");
+    if (A->ncloud != 1 || B->ncloud != 1)
+        fail(FNN_EUNSUPPORTED, "bichromatic queries need single-cloud trees");
+    if ((int64_t)A->n + B->n >= INT32_MAX)
+        fail(FNN_EUNSUPPORTED, "too many points");
+    fnn_tree *F = new fnn_tree();
+    try {
+        const int nA = (int)A->n, nB = (int)B->n, n = nA + nB;
+        F->metric = A->metric;
+        F->n = n;
+        F->dim = A->dim;
+        F->dp = A->dp;
+        F->W = A->W;
+        F->sigma = A->sigma;
+        F->opt = A->opt;
+        auto cat = [&](const void *a, const void *b, size_t row_bytes) -> void * {
+            if (!a)
+                return nullptr;
+            char *d = (char *)F->own(row_bytes * (size_t)n);
+            FNN_HIP(hipMemcpyAsync(d, a, row_bytes * nA, hipMemcpyDeviceToDevice, s));
+            FNN_HIP(hipMemcpyAsync(d + row_bytes * nA, b, row_bytes * nB,
+                                   hipMemcpyDeviceToDevice, s));
+            return d;
+        };
+        F->x = (float *)cat(A->x, B->x, sizeof(float) * A->dp);
+        F->xn = (float *)cat(A->xn, B->xn, sizeof(float) * A->dp);
+        F->h = (uint64_t *)cat(A->h, B->h, sizeof(uint64_t) * A->dp);
+        F->s = (uint8_t *)cat(A->s, B->s, (size_t)A->dp);
+        F->len = (int32_t *)cat(A->len, B->len, sizeof(int32_t));
+        F->peq = (uint64_t *)cat(A->peq, B->peq, sizeof(uint64_t) * A->sigma * A->W);
+        F->perm = (int32_t *)F->own(sizeof(int32_t) * n);
+        FNN_HIP(hipMemcpyAsync(F->perm, A->perm, sizeof(int32_t) * nA,
+                               hipMemcpyDeviceToDevice, s));
+        FNN_LAUNCH(k_add_i32, dim3(grid_cap(nB, 256, 4096)), dim3(256), 0, s, B->perm, nB, nA,
+                   F->perm + nA);
+
+        // query tree
+        const int nnA = (int)A->nnodes, nnB = (int)B->nnodes;
+        const int npA = (int)A->npacks, npB = (int)B->npacks;
+        const int nn = 1 + nnA + nnB;
+        const int nq = nn + npA + npB;
+        const int kA = total_kids(A, s), kB = total_kids(B, s);
+        F->nnodes = nn;
+        F->npacks = npA + npB;
+        F->nq = nq;
+        F->qroot = 0;
+        F->q_center_pos = (int32_t *)F->own(sizeof(int32_t) * nq);
+        F->q_radius = (float *)F->own(sizeof(float) * nq);
+        F->q_pt_begin = (int32_t *)F->own(sizeof(int32_t) * nq);
+        F->q_pt_end = (int32_t *)F->own(sizeof(int32_t) * nq);
+        F->q_kbeg = (int32_t *)F->own(sizeof(int32_t) * nq);
+        F->q_kcnt = (int32_t *)F->own(sizeof(int32_t) * nq);
+        F->q_kids = (int32_t *)F->own(sizeof(int32_t) * (kA + kB + 2));
+        FNN_LAUNCH(k_pair_qtree, dim3(grid_cap(A->nq, 256, 4096)), dim3(256), 0, s,
+                   (int)A->nq, nnA, 1, nn, 0, 0, A->q_center_pos, A->q_radius,
+                   A->q_pt_begin, A->q_pt_end, A->q_kbeg, A->q_kcnt, F->q_center_pos,
+                   F->q_radius, F->q_pt_begin, F->q_pt_end, F->q_kbeg, F->q_kcnt);
+        FNN_LAUNCH(k_pair_qtree, dim3(grid_cap(B->nq, 256, 4096)), dim3(256), 0, s,
+                   (int)B->nq, nnB, 1 + nnA, nn + npA, nA, kA, B->q_center_pos, B->q_radius,
+                   B->q_pt_begin, B->q_pt_end, B->q_kbeg, B->q_kcnt, F->q_center_pos,
+                   F->q_radius, F->q_pt_begin, F->q_pt_end, F->q_kbeg, F->q_kcnt);
+        if (kA > 0)
+            FNN_LAUNCH(k_pair_kids, dim3(grid_cap(kA, 256, 4096)), dim3(256), 0, s, kA, nnA,
+                       1, nn, A->q_kids, F->q_kids);
+        if (kB > 0)
+            FNN_LAUNCH(k_pair_kids, dim3(grid_cap(kB, 256, 4096)), dim3(256), 0, s, kB, nnB,
+                       1 + nnA, nn + npA, B->q_kids, F->q_kids + kA);
+        // the virtual root: the two query-tree roots as its children
+        const int ra = A->qroot < nnA ? 1 + A->qroot : nn + (A->qroot - nnA);
+        const int rb = B->qroot < nnB ? 1 + nnA + B->qroot : nn + npA + (B->qroot - nnB);
+        const int32_t kids2[2] = {ra, rb};
+        const int32_t root_i[5] = {0, 0, n, kA + kB, 2};  // cpos, pb, pe, kbeg, kcnt
+        const float inf = INFINITY;
+        FNN_HIP(hipMemcpyAsync(F->q_kids + kA + kB, kids2, sizeof kids2,
+                               hipMemcpyHostToDevice, s));
+        FNN_HIP(hipMemcpyAsync(F->q_center_pos, &root_i[0], 4, hipMemcpyHostToDevice, s));
+        FNN_HIP(hipMemcpyAsync(F->q_pt_begin, &root_i[1], 4, hipMemcpyHostToDevice, s));
+        FNN_HIP(hipMemcpyAsync(F->q_pt_end, &root_i[2], 4, hipMemcpyHostToDevice, s));
+        FNN_HIP(hipMemcpyAsync(F->q_kbeg, &root_i[3], 4, hipMemcpyHostToDevice, s));
+        FNN_HIP(hipMemcpyAsync(F->q_kcnt, &root_i[4], 4, hipMemcpyHostToDevice, s));
+        FNN_HIP(hipMemcpyAsync(F->q_radius, &inf, 4, hipMemcpyHostToDevice, s));
+        F->cross_a = ra;
+        F->cross_b = rb;
+
+        // clouds: A's positions [0, nA), B's [nA, n)
+        F->ncloud = 2;
+        F->cloud_off_h = {0, (int64_t)nA, (int64_t)n};
+        F->cloud_src = {0, 1};
+        F->ncloud_in = 2;
+        F->pcl = (int32_t *)F->own(sizeof(int32_t) * n);
+        fill(F->pcl, 0, nA, s);
+        fill(F->pcl + nA, 1, nB, s);
+        F->depth = std::max(A->depth, B->depth) + 1;
+        FNN_HIP(hipStreamSynchronize(s));  // host arrays above go out of scope
+        return F;
+    } catch (...) {
+        delete F;
+        throw;
+    }
+}
+
 void build_tree(fnn_tree *T, const void *points, Scratch &S)
 {
     switch (T->metric) {

@@ -64,6 +64,8 @@ struct GramArgs {
     int proj;
     double t2mul;
     double captured;
+    // bichromatic query: only pairs across the two clouds are evaluated
+    int cross;
 };
 
 // Exact decision of the survivor list: edge list (input ids, FP32 distance)

@@ -916,8 +916,8 @@ k_gram(Pts P, GramArgs G, TileOut out)
                 load_b(e + 1);
             if (!has_a || b < a)
                 continue;                      // pair handled elsewhere
-            if (ca >= 0 && eC[e - e0] != ca)
-                continue;                      // different clouds never connect
+            if (ca >= 0 && (eC[e - e0] == ca) == (bool)G.cross)
+                continue;  // pairs never cross clouds (a bichromatic query: always do)
             const bool self = (b == a);
             // both 32-column blocks at once: four independent accumulator
             // chains [cb][rb] per k-step.  The accumulators start at -ax (in
@@ -1116,7 +1116,8 @@ k_gram_direct(Pts P, GramArgs G, TileOut out)
         };
         auto step = [&](int e, int4 (&B)[2][NKS], float (&ay)[2]) {
             const int b = eB[e - e0], pb = eP[e - e0], nb = eN[e - e0];
-            const bool skip = !has_a || b < a || (ca >= 0 && eC[e - e0] != ca);
+            const bool skip =
+                !has_a || b < a || (ca >= 0 && (eC[e - e0] == ca) == (bool)G.cross);
             if (!skip) {
                 const bool self = (b == a);
                 // one 32-column block at a time: the second block's
@@ -1567,12 +1568,19 @@ static int project_pca(const float *X, int n, int dp, int kq_full, int proj,
     return K;
 }
 
+// Clouds that get their own centre: every cloud of a batch; one for a
+// single tree and for a bichromatic query (its pairs cross the clouds).
+static int centre_clouds(const fnn_tree *T)
+{
+    return T->cross_a >= 0 ? 1 : T->ncloud;
+}
+
 // Per-cloud centres of the rows X [n][dp] (one cloud: the global mean).
 static Centre make_centre(const fnn_tree *T, const float *X, int dp, const float *inv,
                           Scratch &S)
 {
     hipStream_t s = S.stream();
-    const int n = (int)T->n, ncl = T->ncloud;
+    const int n = (int)T->n, ncl = centre_clouds(T);
     const int32_t *pcl = ncl > 1 ? T->pcl : nullptr;
     float *sums = S.get<float>((size_t)ncl * dp);
     fill(sums, 0.f, (int64_t)ncl * dp, s);
@@ -1584,7 +1592,7 @@ static Centre make_centre(const fnn_tree *T, const float *X, int dp, const float
 static float *cloud_inv_sizes(const fnn_tree *T, Scratch &S)
 {
     hipStream_t s = S.stream();
-    const int ncl = T->ncloud;
+    const int ncl = centre_clouds(T);
     float *inv = S.get<float>(ncl);
     std::vector<float> ih(ncl);
     for (int c = 0; c < ncl; ++c) {

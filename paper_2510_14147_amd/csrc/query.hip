@@ -1158,15 +1158,16 @@ static void traverse(const fnn_tree *T, const Pts &P, const QView &Q,
                      long long *ninter_out, fnn_stats &st)
 {
     hipStream_t s = S.stream();
-    const long long nroot = T->ncloud > 1 ? T->ncloud : 1;
+    const bool cross = T->cross_a >= 0;  // bichromatic: the pair of cloud roots
+    const long long nroot = cross ? 1 : (T->ncloud > 1 ? T->ncloud : 1);
     long long cap_cur = std::max<long long>(1 << 16, nroot), cap_next = 1 << 16;
     long long cap_int = std::max<long long>(1 << 20, T->npacks * 16);
     int2 *cur = S.get<int2>(cap_cur), *next = S.get<int2>(cap_next);
     int2 *inter = S.get<int2>(cap_int);
     unsigned long long *cnt = S.get<unsigned long long>(4);
     int *ovf = S.get<int>(1);
-    int2 root = make_int2(T->qroot, T->qroot);
-    if (T->ncloud > 1)
+    int2 root = cross ? make_int2(T->cross_a, T->cross_b) : make_int2(T->qroot, T->qroot);
+    if (T->ncloud > 1 && !cross)
         FNN_LAUNCH(k_forest_frontier, dim3(grid_for(nroot, 256)), dim3(256), 0, s,
                    Q, cur, (int)nroot);
     else
@@ -1289,6 +1290,8 @@ static void eps_graph_impl(const fnn_tree *Tc, const double *epsv,
                            Scratch &S, float **trace_feat, float **trace_targ)
 {
     fnn_tree *T = const_cast<fnn_tree *>(Tc);  // lazily built caches only
+    if (T->cross_a >= 0 && (opt.sched == FNN_SCHED_LEARNED || opt.trace))
+        fail(FNN_EUNSUPPORTED, "bichromatic queries run the two-pass schedule, without traces");
     if (opt.precision == FNN_PREC_I8 && (M != M_HAM || T->dp > 4))
         fail(FNN_EUNSUPPORTED, "integer MFMA filter is for Hamming codes of <= 256 bits");
     hipStream_t s = S.stream();
@@ -1407,6 +1410,7 @@ static void eps_graph_impl(const fnn_tree *Tc, const double *epsv,
     // ---- MFMA filter set-up (vector metrics with dim <= 128, Hamming codes
     // of <= 256 bits) ------------------------------------------------------
     GramArgs G{};
+    G.cross = T->cross_a >= 0;
     int2 *plain = inter;
     long long nplain = ninter;
     if constexpr (M == M_L2 || M == M_ANG || M == M_HAM) {

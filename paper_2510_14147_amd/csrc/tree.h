@@ -91,6 +91,9 @@ struct fnn_tree {
     std::vector<int32_t> cloud_src;    // caller's index of each compact cloud
     int32_t ncloud_in = 1;             // clouds as the caller numbered them
     int32_t *pcl = nullptr;            // [n] cloud of each tree position
+    // two-tree forest of a bichromatic query: the query-tree roots of the
+    // two clouds, whose pair seeds the traversal (-1 otherwise)
+    int32_t cross_a = -1, cross_b = -1;
 
     int depth = 0;
     fnn_stats stats{};

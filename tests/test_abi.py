@@ -90,6 +90,14 @@ def test_argument_errors_without_gpu(lib):
     assert b"offsets" in lib.fnn_last_error()
     lib.fnn_set_allocator.argtypes = [vp, vp, vp]
     assert lib.fnn_set_allocator(vp(1), None, None) == -1
+    # bichromatic query: the tree handle and out are checked first
+    lib.fnn_eps_query.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_double, vp,
+                                  ctypes.POINTER(vp)]
+    out = vp(123)
+    assert lib.fnn_eps_query(None, vp(16), 4, 1.0, None, ctypes.byref(out)) == -1
+    assert out.value is None
+    assert b"tree" in lib.fnn_last_error()
+    assert lib.fnn_eps_query(None, vp(16), 4, 1.0, None, None) == -1
 
 
 def _header_fields(struct):
