@@ -44,6 +44,12 @@ def workload(name: str):
     if name == "c2_50k":
         return (G.c2_manifold(n=50_000), "l2", W["c2_50k"]["eps"][0],
                 "c2_manifold_50k_d128_eps70")
+    if name == "c2q":
+        # the C2 set as the tree, 100K more draws from the same manifold as
+        # queries (prefixes of one seeded stream)
+        x = G.c2_manifold(n=1_100_000)
+        return (x, "l2", W["c2"]["eps"][0],
+                "c2_manifold_1m_d128_eps70_query_100k")
     if name == "c1":
         return G.c1_clusters(), "l2", W["c1"]["eps"], "c1_clusters_20k_d8"
     if name == "c3":
@@ -200,7 +206,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c2a",
-                    help="c2a c2b c2_50k c1 c3 c4 ang | c5 (many clouds, one "
+                    help="c2a c2b c2_50k c1 c3 c4 ang | c2q (bichromatic: 100K "
+                         "queries against the C2 tree) | c5 (many clouds, one "
                          "batch per dim) | c5_loop (one call per cloud)")
     ap.add_argument("--precision", default="auto",
                     help="auto (the library chooses per query: i8 on Hamming "
@@ -294,18 +301,28 @@ def main():
 
     INV_PREC = {v: k for k, v in fnn.PRECISIONS.items()}
 
+    def run_job(xd, off, m, e, o, precision):
+        """Build + query of one job: (tree, graph)."""
+        bo = {k: v for k, v in o.items() if k in BUILD_KEYS}
+        if args.workload == "c2q":
+            # tree over the first 1M rows, bichromatic query of the rest
+            tree = fnn.fnn_tree_build(xd[:1_000_000], m, **bo)
+            g = fnn.fnn_eps_query(tree, xd[1_000_000:], e, precision=precision,
+                                  proj=o.get("proj", 0))
+        elif off is None:
+            tree = fnn.fnn_tree_build(xd, m, **bo)
+            g = fnn.fnn_eps_graph(tree, e, precision=precision, sched=o["sched"],
+                                  proj=o.get("proj", 0))
+        else:
+            tree = fnn.fnn_tree_build_batch(xd, off, m, **bo)
+            g = fnn.fnn_eps_graph_batch(tree, e, precision=precision, sched=o["sched"],
+                                        proj=o.get("proj", 0))
+        return tree, g
+
     def step():
         res = []
         for (xd, off, m, e, d, _), o in zip(jobs, opts):
-            bo = {k: v for k, v in o.items() if k in BUILD_KEYS}
-            if off is None:
-                tree = fnn.fnn_tree_build(xd, m, **bo)
-                g = fnn.fnn_eps_graph(tree, e, precision=o["precision"],
-                                      sched=o["sched"], proj=o.get("proj", 0))
-            else:
-                tree = fnn.fnn_tree_build_batch(xd, off, m, **bo)
-                g = fnn.fnn_eps_graph_batch(tree, e, precision=o["precision"],
-                                            sched=o["sched"], proj=o.get("proj", 0))
+            tree, g = run_job(xd, off, m, e, o, o["precision"])
             # the precision the query ran with (the library resolves auto)
             used = INV_PREC[int(g.stats["precision_used"])]
             res.append((tree.stats, g.stats, g.nnz, d, used))
@@ -386,13 +403,7 @@ def main():
         t0 = time.perf_counter()
         pnnz = 0
         for (xd, off, m, e, d, _), o in zip(jobs, opts):
-            bo = {k: v for k, v in o.items() if k in BUILD_KEYS}
-            if off is None:
-                tree = fnn.fnn_tree_build(xd, m, **bo)
-                g = fnn.fnn_eps_graph(tree, e, precision="fp32", sched=o["sched"])
-            else:
-                tree = fnn.fnn_tree_build_batch(xd, off, m, **bo)
-                g = fnn.fnn_eps_graph_batch(tree, e, precision="fp32", sched=o["sched"])
+            tree, g = run_job(xd, off, m, e, o, "fp32")
             pnnz += g.nnz
             del tree, g
         torch.cuda.synchronize()
