@@ -326,8 +326,10 @@ __device__ __forceinline__ int cand_per_chunk(int nch, int kmax)
 }
 constexpr int UPD_D = 128;  // largest row stride staged in LDS
 
+constexpr int UPD_W = 4;  // queue entries (one wave each) per work-group
+
 template <int M>
-__global__ void __launch_bounds__(CH)
+__global__ void __launch_bounds__(CH * UPD_W)
 k_update(Pts P, const int32_t *__restrict__ ch_hub, const int32_t *__restrict__ ch_s,
          const int32_t *__restrict__ ch_e, const int32_t *__restrict__ queue,
          const int32_t *__restrict__ qlen, Hubs hb,
@@ -337,21 +339,25 @@ k_update(Pts P, const int32_t *__restrict__ ch_hub, const int32_t *__restrict__ 
          int32_t *__restrict__ cb_id, int kmax, unsigned long long *__restrict__ cnt)
 {
     // staged centres: UPD_K rows of the point stride (sized at launch, so
-    // low-dimensional inputs keep many work-groups resident)
+    // low-dimensional inputs keep many work-groups resident), shared by the
+    // work-group's waves whose chunks belong to the same hub (a hub's chunks
+    // are consecutive in the queue)
     extern __shared__ __align__(16) float cen[];
+    __shared__ int hub_s[UPD_W];
+    const int w = threadIdx.x / CH, lane = threadIdx.x % CH;
     // the queue lists the chunks of the hubs still active (device-resident
     // length, so passes need no host round trip)
     const int nq = *qlen;
-    for (int t = blockIdx.x; t < nq; t += gridDim.x) {
-    const int c = queue[t];
-    const int h = ch_hub[c];
-    if (!hb.act[h])
-        continue;
-    const int s = ch_s[c], e = ch_e[c];
-    const int p = s + threadIdx.x;
-    const bool valid = p < e;
-    const int b = hb.b[h];
-    const int j0 = hb.ma[h], j1 = hb.m[h];
+    for (int t0 = blockIdx.x * UPD_W; t0 < nq; t0 += gridDim.x * UPD_W) {
+    const int t = t0 + w;
+    const int c = t < nq ? queue[t] : 0;
+    const int h = t < nq ? ch_hub[c] : 0;
+    const bool act = t < nq && hb.act[h];
+    const int s = act ? ch_s[c] : 0, e = act ? ch_e[c] : 0;
+    const int p = s + lane;
+    const bool valid = act && p < e;
+    const int b = act ? hb.b[h] : 0;
+    const int j0 = act ? hb.ma[h] : 0, j1 = act ? hb.m[h] : 0;
     float dv = -1.f;
     int id = INT_MAX;
     const int o = valid ? perm[p] : 0;
@@ -360,45 +366,60 @@ k_update(Pts P, const int32_t *__restrict__ ch_hub, const int32_t *__restrict__ 
     bool staged = false;
     if constexpr (M == M_L2 || M == M_ANG) {
         // vector metrics: the pass's new centres go to LDS in batches of
-        // UPD_K, and every point row is read once per batch
-        staged = (j1 > j0) && P.dp <= UPD_D;
+        // UPD_K, once per distinct hub of the work-group, and every point
+        // row is read once per batch
+        staged = P.dp <= UPD_D;
         if (staged) {
             const float *X = (M == M_ANG) ? P.xn : P.x;
             const int dp = P.dp;
             const float *row = X + (size_t)o * dp;
-            for (int jb = j0; jb < j1; jb += UPD_K) {
-                const int nj = min(UPD_K, j1 - jb);
-                __syncthreads();  // the previous batch is consumed
-                for (int e = threadIdx.x; e < nj * dp; e += CH)
-                    cen[e] = X[(size_t)cent[b + jb + e / dp] * dp + (e % dp)];
-                __syncthreads();
-                if (valid) {
-                    float acc[UPD_K];
+            __syncthreads();  // hub_s of the previous entries is consumed
+            if (lane == 0)
+                hub_s[w] = act && j1 > j0 ? h : -1;
+            __syncthreads();
+            for (int r = 0; r < UPD_W; ++r) {
+                const int hr = hub_s[r];
+                bool first = hr >= 0;
+                for (int q = 0; q < r; ++q)
+                    first = first && hub_s[q] != hr;
+                if (!first)
+                    continue;  // no hub, or staged in an earlier round
+                const bool mine = valid && h == hr;
+                const int br = hb.b[hr], j0r = hb.ma[hr], j1r = hb.m[hr];
+                for (int jb = j0r; jb < j1r; jb += UPD_K) {
+                    const int nj = min(UPD_K, j1r - jb);
+                    __syncthreads();  // the previous batch is consumed
+                    for (int x = threadIdx.x; x < nj * dp; x += CH * UPD_W)
+                        cen[x] = X[(size_t)cent[br + jb + x / dp] * dp + (x % dp)];
+                    __syncthreads();
+                    if (mine) {
+                        float acc[UPD_K];
 #pragma unroll
-                    for (int j = 0; j < UPD_K; ++j)
-                        acc[j] = 0.f;
-                    for (int k = 0; k < dp; k += 4) {
-                        const float4 v = *reinterpret_cast<const float4 *>(row + k);
+                        for (int j = 0; j < UPD_K; ++j)
+                            acc[j] = 0.f;
+                        for (int k = 0; k < dp; k += 4) {
+                            const float4 v = *reinterpret_cast<const float4 *>(row + k);
 #pragma unroll
-                        for (int j = 0; j < UPD_K; ++j) {
-                            if (j < nj) {
-                                const float4 c = *reinterpret_cast<const float4 *>(
-                                    cen + j * dp + k);
-                                const float d0 = v.x - c.x, d1 = v.y - c.y,
-                                            d2 = v.z - c.z, d3 = v.w - c.w;
-                                acc[j] = fmaf(d0, d0, acc[j]);
-                                acc[j] = fmaf(d1, d1, acc[j]);
-                                acc[j] = fmaf(d2, d2, acc[j]);
-                                acc[j] = fmaf(d3, d3, acc[j]);
+                            for (int j = 0; j < UPD_K; ++j) {
+                                if (j < nj) {
+                                    const float4 cc = *reinterpret_cast<const float4 *>(
+                                        cen + j * dp + k);
+                                    const float d0 = v.x - cc.x, d1 = v.y - cc.y,
+                                                d2 = v.z - cc.z, d3 = v.w - cc.w;
+                                    acc[j] = fmaf(d0, d0, acc[j]);
+                                    acc[j] = fmaf(d1, d1, acc[j]);
+                                    acc[j] = fmaf(d2, d2, acc[j]);
+                                    acc[j] = fmaf(d3, d3, acc[j]);
+                                }
                             }
                         }
-                    }
 #pragma unroll
-                    for (int j = 0; j < UPD_K; ++j)
-                        if (j < nj && acc[j] < dcur) {
-                            dcur = acc[j];
-                            lcur = jb + j;
-                        }
+                        for (int j = 0; j < UPD_K; ++j)
+                            if (j < nj && acc[j] < dcur) {
+                                dcur = acc[j];
+                                lcur = jb + j;
+                            }
+                    }
                 }
             }
         }
@@ -422,31 +443,33 @@ k_update(Pts P, const int32_t *__restrict__ ch_hub, const int32_t *__restrict__ 
             id = o;
         }
     }
-    // the chunk's R farthest uncovered points, farthest first
-    const int R = cand_per_chunk(hb.ce[h] - hb.cb[h], kmax);
-    for (int r = 0; r < R; ++r) {
-        float bd = dv;
-        int bi = id;
+    if (act) {
+        // the chunk's R farthest uncovered points, farthest first
+        const int R = cand_per_chunk(hb.ce[h] - hb.cb[h], kmax);
+        for (int r = 0; r < R; ++r) {
+            float bd = dv;
+            int bi = id;
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-            float d2 = __shfl_xor(bd, off, WAVE);
-            int i2 = __shfl_xor(bi, off, WAVE);
-            if (better(d2, i2, bd, bi)) {
-                bd = d2;
-                bi = i2;
+            for (int off = 32; off > 0; off >>= 1) {
+                float d2 = __shfl_xor(bd, off, WAVE);
+                int i2 = __shfl_xor(bi, off, WAVE);
+                if (better(d2, i2, bd, bi)) {
+                    bd = d2;
+                    bi = i2;
+                }
+            }
+            if (lane == 0) {
+                cb_D[(size_t)c * CAND_R + r] = bd;
+                cb_id[(size_t)c * CAND_R + r] = bi;
+            }
+            if (id == bi && bd >= 0.f) {  // the winner leaves the race
+                dv = -1.f;
+                id = INT_MAX;
             }
         }
-        if (threadIdx.x == 0) {
-            cb_D[(size_t)c * CAND_R + r] = bd;
-            cb_id[(size_t)c * CAND_R + r] = bi;
-        }
-        if (id == bi && bd >= 0.f) {  // the winner leaves the race
-            dv = -1.f;
-            id = INT_MAX;
-        }
+        if (lane == 0 && j1 > j0)
+            atomicAdd(cnt, (unsigned long long)(j1 - j0) * (unsigned)(e - s));
     }
-    if (threadIdx.x == 0 && j1 > j0)
-        atomicAdd(cnt, (unsigned long long)(j1 - j0) * (unsigned)(e - s));
     }
 }
 
@@ -1174,13 +1197,13 @@ static void build_impl(fnn_tree *T, const void *points, Scratch &S)
         // graph once per level and replayed until the queue is empty.
         FNN_LAUNCH(k_iota, dim3(grid_for(NC, 256)), dim3(256), 0, st, qa, NC);
         fill(qlen, NC, 1, st);
-        const unsigned gu = grid_for(NC, 1) < 16384u ? grid_for(NC, 1) : 16384u;
+        const unsigned gu = grid_cap(NC, UPD_W, 4096);
         const size_t upd_lds =
             (M == M_L2 || M == M_ANG) && T->dp <= UPD_D ? sizeof(float) * UPD_K * T->dp : 16;
         auto pass = [&](hipStream_t s, int k) {
             int32_t *qc = k ? qb : qa, *qx = k ? qa : qb;
             fill(qlen + (1 - k), 0, 1, s);
-            FNN_LAUNCH((k_update<M>), dim3(gu), dim3(CH), upd_lds, s, P, ch_hub, ch_s,
+            FNN_LAUNCH((k_update<M>), dim3(gu), dim3(CH * UPD_W), upd_lds, s, P, ch_hub, ch_s,
                        ch_e, qc, qlen + k, hubs, cent, perm, D, L, tab, cb_D,
                        cb_id, T->opt.kmax, cnt);
             FNN_LAUNCH((k_select<M>), dim3(grid_cap(H, 1, 4096)), dim3(SEL_T), 0, s, P,
