@@ -639,7 +639,8 @@ __device__ __forceinline__ void block_finish(const GramArgs &G, const ACC (&accb
                                              V mx, int cb, int na, int nb, bool self,
                                              int pa, int pb, unsigned long long &cpos,
                                              unsigned long long &cend,
-                                             unsigned long long &npairs)
+                                             unsigned long long &npairs,
+                                             const unsigned *rmS)
 {
     const int lane = threadIdx.x & (WAVE - 1), l32 = lane & 31, hi = lane >> 5;
     const uint64_t ltmask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
@@ -666,17 +667,26 @@ __device__ __forceinline__ void block_finish(const GramArgs &G, const ACC (&accb
     // whether that pair is valid (row < na, and row < col on a self tile:
     // r0(i) < rl, looked up per tile), bit i of pm whether it also passes.
     const int rl = (col < nb ? (self ? min(na, col) : na) : 0) - 4 * hi;
-    const unsigned om = c_rowmask.m[min(max(rl + 4, 0), 68)];
-    unsigned pm = 0;
+    const unsigned om = rmS[min(max(rl + 4, 0), 68)];
+    // Fails as sign bits: gq < ay exactly when gq - ay is negative (integer
+    // codes: no overflow; floats: x - y rounds to +0 when x == y), shifted
+    // in from the top position down, one funnel shift per position.  (A
+    // float tie -0 against +0 counts as a fail; the real filters keep a
+    // positive slack above every true edge, so a tie is never one.)
+    unsigned nm = 0;
 #pragma unroll
-    for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const V gq = PREC == FNN_PREC_FP8 ? (V)(accb[rb][q] * G.gscale)
-                                              : (V)accb[rb][q];
-            pm |= (unsigned)(gq >= ay) << (rb * 16 + q);
-        }
-    pm &= om;
+    for (int i = 31; i >= 0; --i) {
+        const int rb = i >> 4, q = i & 15;
+        unsigned d;
+        if constexpr (PREC == FNN_PREC_I8)
+            d = (unsigned)((int)accb[rb][q] - (int)ay);
+        else if constexpr (PREC == FNN_PREC_FP8)
+            d = __float_as_uint(__fsub_rn(__fmul_rn(accb[rb][q], G.gscale), ay));
+        else
+            d = __float_as_uint(__fsub_rn((float)accb[rb][q], ay));
+        nm = __builtin_amdgcn_alignbit(nm, d, 31);
+    }
+    const unsigned pm = ~nm & om;
     // ---- survivors: appended for the exact decision kernel ---------------
     // Emitted: the passes, or (validating) every valid pair with its pass
     // flag.  One ballot per position that some lane has set gives the pairs
@@ -733,7 +743,8 @@ __device__ __forceinline__ void tile_finish(const GramArgs &G, const ACC (&acc)[
                                             int nb, bool self, int pa, int pb,
                                             unsigned long long &cpos,
                                             unsigned long long &cend,
-                                            unsigned long long &npairs)
+                                            unsigned long long &npairs,
+                                            const unsigned *rmS)
 {
     if (!__any(mx[0] >= ayc[0] || mx[1] >= ayc[1]) && !self && !G.validate) {
         // no survivor: only the pair count
@@ -746,7 +757,7 @@ __device__ __forceinline__ void tile_finish(const GramArgs &G, const ACC (&acc)[
 #pragma unroll
     for (int cb = 0; cb < 2; ++cb)
         block_finish<PREC>(G, acc[cb], ayc[cb], mx[cb], cb, na, nb, self, pa, pb, cpos, cend,
-                           npairs);
+                           npairs, rmS);
 }
 
 __device__ __forceinline__ float vmax(float a, float b) { return fmaxf(a, b); }
@@ -771,6 +782,9 @@ k_gram(Pts P, GramArgs G, TileOut out)
     V *ayS = (V *)(smem + GP * ldb);           // [GP]
     V *axS = ayS + GP;                         // [GW][GP]
     __shared__ int eB[UNIT_MAX], eP[UNIT_MAX], eN[UNIT_MAX], eC[UNIT_MAX];
+    __shared__ unsigned rmS[69];               // row-mask table
+    for (int i = threadIdx.x; i < 69; i += GT)
+        rmS[i] = c_rowmask.m[i];
 
     const int t = threadIdx.x, lane = t & (WAVE - 1), w = t / WAVE;
     const int l32 = lane & 31, hi = lane >> 5;
@@ -1025,7 +1039,7 @@ k_gram(Pts P, GramArgs G, TileOut out)
                 if constexpr (PREC == FNN_PREC_FP8)
                     mx[cb] *= G.gscale;
             }
-            tile_finish<PREC>(G, acc, ayc, mx, na, nb, self, pa, pb, cpos, cend, npairs);
+            tile_finish<PREC>(G, acc, ayc, mx, na, nb, self, pa, pb, cpos, cend, npairs, rmS);
         }
         __syncthreads();
     }
@@ -1034,11 +1048,82 @@ k_gram(Pts P, GramArgs G, TileOut out)
         atomicAdd(&out.cnt[2], npairs);
 }
 
+// The first active lane's value (here always lane 0: called with every lane
+// active), held in scalar registers.
+__device__ __forceinline__ unsigned long long uniform_u64(unsigned long long v)
+{
+    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)v);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(v >> 32));
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+// End of one 32-row x 64-column block of the narrow kernel: rows
+// 32 rb + r (r < 32) of the wave's pack against the entry's columns c < 64.
+// Position q of acc[cb] in a lane holds row 32 rb + 8 (q / 4) + q % 4 + 4 hi
+// of column 32 cb + l32; acc[cb] starts at -ax of its row, ay[cb] is the
+// lane's column term (FLT_MAX past nb) and hm[cb] the lanes whose largest
+// sum of that block reaches it.  The pairs that pass (every valid pair with
+// its pass flag when validating) go to the survivor list through the wave's
+// reserved slots [cpos, cend) (wave-uniform).
+__device__ __forceinline__ void half_finish(const GramArgs &G, const f32x16 (&acc)[2],
+                                            const float (&ay)[2], const uint64_t (&hm)[2],
+                                            int rb, int na, int nb, bool self, int pa,
+                                            int pb, unsigned long long &cpos,
+                                            unsigned long long &cend, const unsigned *rmS)
+{
+    const int lane = threadIdx.x & (WAVE - 1), l32 = lane & 31, hi = lane >> 5;
+    const uint64_t ltmask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) {
+        if (!G.validate && hm[cb] == 0)
+            continue;  // no lane reaches its column term in this block
+        // valid rows of column col: below rl (na, or min(na, col) on a
+        // self pair; none past nb), counted from this lane's first row
+        // 32 rb + 4 hi; the low 16 bits of table entry rl + 4 mark the
+        // positions q whose row offset 8 (q / 4) + q % 4 is below rl
+        const int col = cb * 32 + l32;
+        const int rl = (col < nb ? (self ? min(na, col) : na) : 0) - 32 * rb - 4 * hi;
+        const unsigned om = rmS[min(max(rl + 4, 0), 68)] & 0xFFFFu;
+        // fails as sign bits of acc - ay (see block_finish), top position
+        // first
+        unsigned nm = 0;
+#pragma unroll
+        for (int q = 15; q >= 0; --q)
+            nm = __builtin_amdgcn_alignbit(
+                nm, __float_as_uint(__fsub_rn(acc[cb][q], ay[cb])), 31);
+        const unsigned pm = ~nm & om;
+        const unsigned todo = G.validate ? om : pm;
+        unsigned any = wave_or_u32(todo);
+        while (any) {
+            const int q = __ffs(any) - 1;
+            any &= any - 1;
+            const bool emit = (todo >> q) & 1u;
+            const uint64_t m = __ballot(emit);
+            const int r0 = 32 * rb + 8 * (q >> 2) + (q & 3);
+            const int cnt = __popcll(m);
+            if (cpos + (unsigned long long)cnt > cend) {
+                pad_surv(G, cpos, cend);
+                unsigned long long b0 = 0;
+                if (lane == 0)
+                    b0 = atomicAdd(G.nsurv, (unsigned long long)SURV_CHUNK);
+                cpos = uniform_u64(b0);  // lane 0's value, in scalar registers
+                cend = cpos + SURV_CHUNK;
+            }
+            const unsigned long long o = cpos + __popcll(m & ltmask);
+            if (emit && (long long)o < G.surv_cap)
+                G.surv[o] = make_int2(pa + r0 + 4 * hi,
+                                      (pb + col) | (int)(((pm >> q) & 1u) << 31));
+            cpos += (unsigned long long)cnt;
+        }
+    }
+}
+
 // Filter for narrow BF16 rows (kq <= 32: the leading principal
-// coordinates).  Same work units and tile layout as k_gram, but no LDS
-// staging and no barrier in the entry loop: each wave reads its B fragments
-// (16 bytes per lane, k-step and column block) from L2 into registers one
-// entry ahead.  A wave that emits survivors then never holds up the other
+// coordinates).  Same work units as k_gram, but no LDS staging and no
+// barrier in the entry loop: each wave reads its B fragments (16 bytes per
+// lane, k-step and column block) from L2 into registers two entries ahead,
+// and takes an entry as two 32-row halves (a half past na is skipped) by
+// both 32-column blocks.  A wave that emits survivors then never holds up the other
 // waves of its work-group; the four waves of a group read the same B rows
 // at about the same time, so most of those reads hit L1.
 template <int M, int NKS>
@@ -1049,7 +1134,11 @@ k_gram_direct(Pts P, GramArgs G, TileOut out)
     constexpr int rowb = NKS * 32;  // bytes per quantised row
     __shared__ int eB[UNIT_MAX], eP[UNIT_MAX], eN[UNIT_MAX], eC[UNIT_MAX];
     __shared__ __align__(16) float axS[GW][GP];  // accumulator start -ax per row
-    const int t = threadIdx.x, lane = t & (WAVE - 1), w = t / WAVE;
+    __shared__ unsigned rmS[69];                 // row-mask table
+    for (int i = threadIdx.x; i < 69; i += GT)
+        rmS[i] = c_rowmask.m[i];
+    const int t = threadIdx.x, lane = t & (WAVE - 1);
+    const int w = __builtin_amdgcn_readfirstlane(t / WAVE);  // wave-uniform
     const int l32 = lane & 31, hi = lane >> 5;
     const unsigned char *Q = (const unsigned char *)G.q;
     unsigned long long npairs = 0, cpos = 0, cend = 0;
@@ -1079,9 +1168,8 @@ k_gram_direct(Pts P, GramArgs G, TileOut out)
                     v = *(const int4 *)(Q + (size_t)(pa + r) * rowb + ks * 32 + hi * 16);
                 __builtin_memcpy(&Af[rb][ks], &v, 16);
             }
-        // accumulator start values -ax of the wave's rows, in LDS (read as
-        // the first MFMA's addend of every block, so they hold no registers
-        // across the entry loop)
+        // accumulator start values -ax of the wave's rows, in LDS: each row
+        // half reads its 16 per lane as the addend of both of its products
         const int ca = (G.pcl && has_a) ? G.pcl[pa] : -1;
         const float e2 = ca >= 0 ? G.ct[ca].e2f : G.e2f;
         for (int r = lane; r < GP; r += WAVE)
@@ -1095,7 +1183,7 @@ k_gram_direct(Pts P, GramArgs G, TileOut out)
             eC[i] = G.pcl ? G.pcl[pbb] : -1;
         }
         __syncthreads();
-        // B fragments and column terms of one entry (columns 32 cb + l32), in
+        // B fragments and column norms of one entry (columns 32 cb + l32), in
         // two register sets: entry e uses set e % 2, whose load was issued
         // two entries earlier (no copy of a register with a load in flight)
         int4 BA[2][NKS], BB[2][NKS];
@@ -1106,67 +1194,93 @@ k_gram_direct(Pts P, GramArgs G, TileOut out)
             for (int cb = 0; cb < 2; ++cb) {
                 const int c = cb * 32 + l32;
                 const bool ok = c < nbb;
+                // Every lane loads (columns past nb read the pack's first
+                // row: their ay = FLT_MAX and row mask 0 keep them out), so
+                // the loads of one entry are a fixed count and the next
+                // entry's stay in flight while this one computes.  32-bit
+                // byte offsets from the uniform bases (the launch checks
+                // that the rows fit).
+                const unsigned row = (unsigned)(ok ? pbb + c : min(pbb, P.n - 1));
 #pragma unroll
                 for (int ks = 0; ks < NKS; ++ks)
-                    B[cb][ks] = ok ? *(const int4 *)(Q + (size_t)(pbb + c) * rowb + ks * 32 +
-                                                     hi * 16)
-                                   : make_int4(0, 0, 0, 0);
-                ay[cb] = ok ? 0.5f * G.hx[pbb + c] : FLT_MAX;
+                    B[cb][ks] = *(const int4 *)(Q + (row * (unsigned)rowb +
+                                                     (unsigned)(ks * 32 + hi * 16)));
+                // the raw norm: used (and waited for) only when the entry
+                // is processed
+                ay[cb] = *(const float *)((const char *)G.hx + row * 4u);
             }
         };
         auto step = [&](int e, int4 (&B)[2][NKS], float (&ay)[2]) {
-            const int b = eB[e - e0], pb = eP[e - e0], nb = eN[e - e0];
-            const bool skip =
-                !has_a || b < a || (ca >= 0 && (eC[e - e0] == ca) == (bool)G.cross);
+            // the entry's fields are the same in every lane
+            const int b = __builtin_amdgcn_readfirstlane(eB[e - e0]);
+            const int pb = __builtin_amdgcn_readfirstlane(eP[e - e0]);
+            const int nb = __builtin_amdgcn_readfirstlane(eN[e - e0]);
+            const int cb_cl = __builtin_amdgcn_readfirstlane(eC[e - e0]);
+            const bool skip = !has_a || b < a || (ca >= 0 && (cb_cl == ca) == (bool)G.cross);
             if (!skip) {
                 const bool self = (b == a);
-                // one 32-column block at a time: the second block's
-                // matrix-core work overlaps the first block's filter
+                // screened pairs: r < c on a self pair (then nb == na)
+                npairs += self ? (unsigned long long)(na * (na - 1) / 2)
+                               : (unsigned long long)(na * nb);
+                const float ayc[2] = {l32 < nb ? 0.5f * ay[0] : FLT_MAX,
+                                      32 + l32 < nb ? 0.5f * ay[1] : FLT_MAX};
+                // one 32-row half at a time against both column blocks: the
+                // half's 16 start values feed both products
 #pragma unroll
-                for (int cb = 0; cb < 2; ++cb) {
-                    if (cb * 32 >= nb)
+                for (int rb = 0; rb < 2; ++rb) {
+                    if (rb * 32 >= na)
                         break;
-                    f32x16 acc[2];
+                    f32x16 sv, acc[2];
+                    asm volatile("" ::: "memory");  // re-read (no registers held)
 #pragma unroll
-                    for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-                        for (int q4 = 0; q4 < 4; ++q4) {
-                            const float4 a4 = *reinterpret_cast<const float4 *>(
-                                &axS[w][rb * 32 + 8 * q4 + 4 * hi]);
-                            acc[rb][4 * q4 + 0] = a4.x;
-                            acc[rb][4 * q4 + 1] = a4.y;
-                            acc[rb][4 * q4 + 2] = a4.z;
-                            acc[rb][4 * q4 + 3] = a4.w;
-                        }
-#pragma unroll
-                    for (int ks = 0; ks < NKS; ++ks) {
-                        bf16x8 bb;
-                        __builtin_memcpy(&bb, &B[cb][ks], 16);
-#pragma unroll
-                        for (int rb = 0; rb < 2; ++rb)
-                            acc[rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                                Af[rb][ks], bb, acc[rb], 0, 0, 0);
+                    for (int q4 = 0; q4 < 4; ++q4) {
+                        const float4 a4 = *reinterpret_cast<const float4 *>(
+                            &axS[w][rb * 32 + 8 * q4 + 4 * hi]);
+                        sv[4 * q4 + 0] = a4.x;
+                        sv[4 * q4 + 1] = a4.y;
+                        sv[4 * q4 + 2] = a4.z;
+                        sv[4 * q4 + 3] = a4.w;
                     }
-                    float mx = acc[0][0];
 #pragma unroll
-                    for (int rb = 0; rb < 2; ++rb)
+                    for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
-                        for (int q = 0; q < 16; ++q)
-                            mx = fmaxf(mx, acc[rb][q]);
-                    block_finish<FNN_PREC_BF16>(G, acc, ay[cb], mx, cb, na, nb, self, pa,
-                                                pb, cpos, cend, npairs);
+                        for (int ks = 0; ks < NKS; ++ks) {
+                            bf16x8 bb;
+                            __builtin_memcpy(&bb, &B[cb][ks], 16);
+                            acc[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                                Af[rb][ks], bb, ks == 0 ? sv : acc[cb], 0, 0, 0);
+                        }
+                    // fast test: the lane's largest sum per column block
+                    // against its column term (the second block only when
+                    // it holds columns)
+                    uint64_t hm[2] = {0, 0};
+#pragma unroll
+                    for (int cb = 0; cb < 2; ++cb) {
+                        if (cb * 32 >= nb)
+                            break;
+                        float mx = acc[cb][0];
+#pragma unroll
+                        for (int q = 1; q < 16; ++q)
+                            mx = fmaxf(mx, acc[cb][q]);
+                        hm[cb] = __ballot(mx >= ayc[cb]);
+                    }
+                    if ((hm[0] | hm[1]) != 0 || G.validate)
+                        half_finish(G, acc, ayc, hm, rb, na, nb, self, pa, pb, cpos, cend,
+                                    rmS);
                 }
             }
-            if (e + 2 < e1)
-                load_b(e + 2, B, ay);
+            // issued on every path (past the end: the last entry again),
+            // so the count of loads in flight never depends on the branch
+            load_b(min(e + 2, e1 - 1), B, ay);
         };
         load_b(e0, BA, ayA);
-        if (e0 + 1 < e1)
-            load_b(e0 + 1, BB, ayB);
+        load_b(min(e0 + 1, e1 - 1), BB, ayB);
         for (int e = e0; e < e1; e += 2) {
             step(e, BA, ayA);
             if (e + 1 < e1)
                 step(e + 1, BB, ayB);
+            else
+                load_b(e1 - 1, BB, ayB);  // same loads in flight on both paths
         }
         __syncthreads();  // eB.. are rewritten by the next unit
     }
@@ -1442,9 +1556,21 @@ static void launch_gram(bool fill_pass, const Pts &P, const GramArgs &G,
         default: launch_gram_k<M, PREC, 8>(fill_pass, P, G, o, s); break;
         }
     } else if constexpr (PREC == FNN_PREC_BF16) {
+        // the narrow kernel addresses rows with 32-bit byte offsets
+        const bool narrow_fits = (long long)P.n * 32 * nks < (1ll << 32);
         switch (nks) {
-        case 1: launch_gram_direct<M, 1>(P, G, o, s); break;
-        case 2: launch_gram_direct<M, 2>(P, G, o, s); break;
+        case 1:
+            if (narrow_fits)
+                launch_gram_direct<M, 1>(P, G, o, s);
+            else
+                launch_gram_k<M, PREC, 1>(fill_pass, P, G, o, s);
+            break;
+        case 2:
+            if (narrow_fits)
+                launch_gram_direct<M, 2>(P, G, o, s);
+            else
+                launch_gram_k<M, PREC, 2>(fill_pass, P, G, o, s);
+            break;
         case 3: launch_gram_k<M, PREC, 3>(fill_pass, P, G, o, s); break;
         case 4: launch_gram_k<M, PREC, 4>(fill_pass, P, G, o, s); break;
         case 5: launch_gram_k<M, PREC, 5>(fill_pass, P, G, o, s); break;
