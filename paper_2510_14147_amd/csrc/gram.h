@@ -68,13 +68,14 @@ struct GramArgs {
     int cross;
 };
 
-// Exact decision of the survivor list: edge list (input ids, FP32 distance)
-// and per-row degrees; returns nothing, counts land in out.cnt.
+// Exact decision of the survivor list: edges[i] and edist[i] (input ids,
+// FP32 distance) for survivor i, (-1, -1) when it is no edge, and per-row
+// degrees; counts land in out.cnt.
 void survivors_launch(int metric, const Pts &P, const GramArgs &G,
-                      long long nsurv, int2 *edges, float *edist,
-                      unsigned long long *nedges, const TileOut &o,
+                      long long nsurv, int2 *edges, float *edist, const TileOut &o,
                       hipStream_t s);
-// Unordered edge list (input ids, distance) into the CSR.
+// Unordered edge list (input ids, distance; (-1, -1) entries skipped) into
+// the CSR.
 void edges_scatter(const int2 *edges, const float *edist, long long ne,
                    const TileOut &o, hipStream_t s);
 // Survivors of the exact integer filter (tree positions) into the CSR, with

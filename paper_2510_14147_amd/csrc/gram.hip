@@ -1289,29 +1289,103 @@ k_gram_direct(Pts P, GramArgs G, TileOut out)
         atomicAdd(&out.cnt[2], npairs);
 }
 
+// FP32 key of every lane's pair (pi, pj), summed exactly as sqdiff_seq sums
+// it (one FMA per coordinate, coordinates in index order, zero padding
+// adding nothing), so the distances equal the FP32 tiles' bit for bit.  The
+// wave stages its 64 pairs' rows through LDS 16 coordinates at a time:
+// each load instruction then reads 64-byte row segments of 16 rows instead
+// of 64 scattered lines, and the next segment is in flight while this one
+// is summed.  sA, sB: the wave's LDS rows (64 x SV_LDR floats each).
+constexpr int SV_CH = 16;            // coordinates per staged segment
+constexpr int SV_LDR = SV_CH + 4;    // floats per staged row (bank spread)
+constexpr int SV_F = SV_CH / 4;      // float4 per row segment
+template <int M>
+__device__ __forceinline__ float key32_staged(const Pts &P, int pi, int pj, float *sA,
+                                              float *sB)
+{
+    const int lane = threadIdx.x & (WAVE - 1);
+    const float *X = M == M_L2 ? P.x : P.xn;
+    const int dp = P.dp, p4 = 4 * (lane % SV_F);
+    // this lane stages float4 p4 / 4 of the rows of pairs lane / F + 16 j
+    const float *ra[SV_F], *rbp[SV_F];
+    int so[SV_F];
+#pragma unroll
+    for (int j = 0; j < SV_F; ++j) {
+        const int r = lane / SV_F + (WAVE / SV_F) * j;
+        ra[j] = X + (size_t)__shfl(pi, r, WAVE) * dp + p4;
+        rbp[j] = X + (size_t)__shfl(pj, r, WAVE) * dp + p4;
+        so[j] = r * SV_LDR + p4;
+    }
+    float4 va[SV_F], vb[SV_F];
+    auto fetch = [&](int c0) {
+        const bool in = c0 + p4 < dp;
+#pragma unroll
+        for (int j = 0; j < SV_F; ++j) {
+            va[j] = in ? *(const float4 *)(ra[j] + c0) : make_float4(0.f, 0.f, 0.f, 0.f);
+            vb[j] = in ? *(const float4 *)(rbp[j] + c0) : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+    };
+    fetch(0);
+    float s = 0.f;
+    for (int c0 = 0; c0 < dp; c0 += SV_CH) {
+#pragma unroll
+        for (int j = 0; j < SV_F; ++j) {
+            *(float4 *)(sA + so[j]) = va[j];
+            *(float4 *)(sB + so[j]) = vb[j];
+        }
+        if (c0 + SV_CH < dp)
+            fetch(c0 + SV_CH);
+        // one wave's LDS accesses complete in order: only the compiler must
+        // keep the reads after the writes (and the next writes after them)
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+#pragma unroll
+        for (int k = 0; k < SV_CH; k += 4) {
+            const float4 u = *(const float4 *)(sA + lane * SV_LDR + k);
+            const float4 v = *(const float4 *)(sB + lane * SV_LDR + k);
+            const float d0 = u.x - v.x, d1 = u.y - v.y, d2 = u.z - v.z, d3 = u.w - v.w;
+            s = fmaf(d0, d0, s);
+            s = fmaf(d1, d1, s);
+            s = fmaf(d2, d2, s);
+            s = fmaf(d3, d3, s);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    }
+    return s;
+}
+
 // Exact decision of every survivor: direct-difference FP32 key, FP64 inside
-// the rounding band; edges go to an unordered list (input ids, distance) and
-// to the row degrees.
+// the rounding band; survivor i's edge (input ids, distance) goes to slot i
+// of an unordered list, (-1, -1) when it is none, and to the row degrees.
+// A grid of resident work-groups strides over the list.
 template <int M>
 __global__ void __launch_bounds__(256)
 k_survive(Pts P, GramArgs G, long long ns, int2 *__restrict__ edges,
-          float *__restrict__ edist, unsigned long long *__restrict__ nedges,
-          TileOut out)
+          float *__restrict__ edist, TileOut out)
 {
     const int lane = threadIdx.x & (WAVE - 1);
-    const uint64_t ltm = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     unsigned long long nrc = 0, npass = 0, nmis = 0;
     unsigned maxerr = 0;
     const long long stride = (long long)gridDim.x * blockDim.x;
     // the loop runs a whole number of waves so that ballots see every lane
     const long long lim = (ns + WAVE - 1) / WAVE * WAVE;
+    __shared__ __align__(16) float sAB[M == M_HAM ? 1 : 2 * 4 * WAVE * SV_LDR];
+    float *sA = sAB + (M == M_HAM ? 0 : (threadIdx.x / WAVE) * 2 * WAVE * SV_LDR);
+    float *sB = sA + WAVE * SV_LDR;
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < lim;
          i += stride) {
         bool edge = false;
         float dd = 0.f;
         int oi = 0, oj = 0;
-        if (i < ns && G.surv[i].x >= 0) {  // (-1, -1): an unused slot
-            const int2 e = G.surv[i];
+        int2 e = make_int2(-1, -1);  // (-1, -1): an unused slot
+        if (i < ns)
+            e = G.surv[i];
+        const bool live = e.x >= 0;
+        // every lane takes part in the staged key (a dead lane sums row 0
+        // against itself)
+        float ks = 0.f;
+        if constexpr (M != M_HAM)
+            ks = key32_staged<M>(P, live ? e.x : 0, live ? e.y & 0x7FFFFFFF : 0, sA, sB);
+        if (live) {
             const int pi = e.x, pj = e.y & 0x7FFFFFFF;
             const bool passed = (e.y >> 31) & 1;
             npass += passed;
@@ -1320,7 +1394,7 @@ k_survive(Pts P, GramArgs G, long long ns, int2 *__restrict__ edges,
             if constexpr (M == M_HAM)
                 k = key32<M>(P, pi, pj);
             else
-                k = key32_seq<M>(P, pi, pj);
+                k = ks;
             if constexpr (M == M_HAM) {
                 edge = k <= E.lo;  // integer distance, exact
             } else if (k < E.lo) {
@@ -1359,17 +1433,11 @@ k_survive(Pts P, GramArgs G, long long ns, int2 *__restrict__ edges,
                 atomicAdd(&out.deg[oj], 1);
             }
         }
-        const uint64_t m = __ballot(edge);
-        if (m) {
-            unsigned long long base = 0;
-            if (lane == 0)
-                base = atomicAdd(nedges, (unsigned long long)__popcll(m));
-            base = __shfl(base, 0, WAVE);
-            if (edge) {
-                const unsigned long long o = base + __popcll(m & ltm);
-                edges[o] = make_int2(oi, oj);
-                edist[o] = dd;
-            }
+        // the survivor's own slot: an edge, or a hole (-1, -1) that the
+        // scatter skips (no shared counter to contend on)
+        if (i < ns) {
+            edges[i] = edge ? make_int2(oi, oj) : make_int2(-1, -1);
+            edist[i] = dd;
         }
     }
     nrc = wave_sum(nrc);
@@ -1388,8 +1456,8 @@ k_survive(Pts P, GramArgs G, long long ns, int2 *__restrict__ edges,
     }
 }
 
-// Writes an unordered edge list (input ids, distance) into the CSR slots of
-// both endpoints.
+// Writes an unordered edge list (input ids, distance; entries (-1, -1) are
+// skipped) into the CSR slots of both endpoints.
 __global__ void k_edges_scatter(const int2 *__restrict__ edges,
                                 const float *__restrict__ edist, long long ne,
                                 TileOut out)
@@ -1397,6 +1465,8 @@ __global__ void k_edges_scatter(const int2 *__restrict__ edges,
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < ne;
          i += (long long)gridDim.x * blockDim.x) {
         const int2 e = edges[i];
+        if (e.x < 0)
+            continue;  // a survivor that is no edge
         const float d = edist[i];
         const unsigned long long s1 = atomicAdd(&out.cursor[e.x], 1ull);
         const unsigned long long s2 = atomicAdd(&out.cursor[e.y], 1ull);
@@ -1413,21 +1483,32 @@ __global__ void k_edges_scatter(const int2 *__restrict__ edges,
 
 void survivors_launch(int metric, const Pts &P, const GramArgs &G,
                       long long nsurv, int2 *edges, float *edist,
-                      unsigned long long *nedges, const TileOut &o,
+                      const TileOut &o,
                       hipStream_t s)
 {
     if (nsurv <= 0)
         return;
-    const dim3 g(grid_for(nsurv, 256));
+    // resident work-groups only: each wave's counters reach the shared
+    // totals once
+    static std::atomic<int> resident{0};
+    int rb = resident.load();
+    if (rb == 0) {
+        FNN_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &rb, reinterpret_cast<const void *>(&k_survive<M_L2>), 256, 0));
+        rb = std::max(1, rb);
+        resident.store(rb);
+    }
+    const dim3 g((unsigned)std::min<long long>(grid_for(nsurv, 256),
+                                               (long long)rb * num_cus()));
     if (metric == M_L2)
         FNN_LAUNCH((k_survive<M_L2>), g, dim3(256), 0, s, P, G, nsurv, edges,
-                   edist, nedges, o);
+                   edist, o);
     else if (metric == M_HAM)
         FNN_LAUNCH((k_survive<M_HAM>), g, dim3(256), 0, s, P, G, nsurv, edges,
-                   edist, nedges, o);
+                   edist, o);
     else
         FNN_LAUNCH((k_survive<M_ANG>), g, dim3(256), 0, s, P, G, nsurv, edges,
-                   edist, nedges, o);
+                   edist, o);
 }
 
 void edges_scatter(const int2 *edges, const float *edist, long long ne,

@@ -1525,8 +1525,9 @@ static void eps_graph_impl(const fnn_tree *Tc, const double *epsv,
                     } else {
                         gedges = S.get<int2>(got + 1);
                         gedist = S.get<float>(got + 1);
-                        survivors_launch(M, P, G, got, gedges, gedist, ns + 1, o, s);
-                        ngedges = (long long)read_scalar(ns + 1, s);
+                        // slot per survivor: holes where it is no edge
+                        survivors_launch(M, P, G, got, gedges, gedist, o, s);
+                        ngedges = got;
                     }
                     break;
                 }
