@@ -72,18 +72,42 @@ struct Centre {
     }
 };
 
-// Column sums per cloud: block b takes rows [b*R, (b+1)*R) and flushes a
+// Column sums per cloud: block b takes rows [b*R, (b+1)*R); with dp below
+// the block size its threads split into row phases (thread t: column
+// t % dp, rows r0 + t / dp + P j), so every thread reads.  A phase flushes a
 // partial sum whenever the cloud changes (clouds are contiguous).
 __global__ void k_colsum(const float *__restrict__ x, int n, int dp,
                          const int32_t *__restrict__ pcl, float *__restrict__ sums)
 {
     const int R = 1024;
     const int r0 = blockIdx.x * R, r1 = min(n, r0 + R);
-    for (int c = threadIdx.x; c < dp; c += blockDim.x) {
+    const int B = blockDim.x;
+    const int P = dp < B ? B / dp : 1;  // row phases
+    const int ph = dp < B ? (int)threadIdx.x / dp : 0;
+    if (ph >= P)
+        return;
+    for (int c = dp < B ? (int)threadIdx.x % dp : (int)threadIdx.x; c < dp;
+         c += dp < B ? dp : B) {
+        if (!pcl) {
+            // one cloud: four independent partial sums keep loads in flight
+            float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+            int r = r0 + ph;
+            for (; r + 3 * P < r1; r += 4 * P) {
+                s0 += x[(size_t)r * dp + c];
+                s1 += x[(size_t)(r + P) * dp + c];
+                s2 += x[(size_t)(r + 2 * P) * dp + c];
+                s3 += x[(size_t)(r + 3 * P) * dp + c];
+            }
+            for (; r < r1; r += P)
+                s0 += x[(size_t)r * dp + c];
+            if (r0 + ph < r1)
+                atomicAdd(&sums[c], (s0 + s1) + (s2 + s3));
+            continue;
+        }
         float s = 0.f;
-        int cc = (pcl && r0 < r1) ? pcl[r0] : 0;
-        for (int r = r0; r < r1; ++r) {
-            const int cl = pcl ? pcl[r] : 0;
+        int cc = r0 + ph < r1 ? pcl[r0 + ph] : 0;
+        for (int r = r0 + ph; r < r1; r += P) {
+            const int cl = pcl[r];
             if (cl != cc) {
                 atomicAdd(&sums[(size_t)cc * dp + c], s);
                 s = 0.f;
@@ -91,7 +115,7 @@ __global__ void k_colsum(const float *__restrict__ x, int n, int dp,
             }
             s += x[(size_t)r * dp + c];
         }
-        if (r0 < r1)
+        if (r0 + ph < r1)
             atomicAdd(&sums[(size_t)cc * dp + c], s);
     }
 }
@@ -228,54 +252,63 @@ __device__ __forceinline__ double pm_one(int j, int c, int salt)
     return (h & 1u) ? 1.0 : -1.0;
 }
 
+// Trace of the covariance C (dp x dp, FP64), one work-group.
+__global__ void __launch_bounds__(256)
+k_pca_trace(const double *__restrict__ C, int dp, double *__restrict__ tr)
+{
+    __shared__ double red[4];
+    double v = 0.0;
+    for (int c = threadIdx.x; c < dp; c += 256)
+        v += C[(size_t)c * dp + c];
+    v = block_sum256(v, red);
+    if (threadIdx.x == 0)
+        *tr = v;
+}
+
+// One product of the randomized range finder: Z = C Y / trace(C), Y the
+// fixed +-1 start block when null; kmax x dp outputs spread over the grid.
+__global__ void __launch_bounds__(256)
+k_pca_power(const double *__restrict__ C, int dp, int kmax, const double *__restrict__ tr,
+            const double *__restrict__ Y, double *__restrict__ Z)
+{
+    const double itr = *tr > 0.0 ? 1.0 / *tr : 0.0;
+    for (int e = blockIdx.x * 256 + threadIdx.x; e < kmax * dp; e += gridDim.x * 256) {
+        const int j = e / dp, c = e % dp;
+        double v = 0.0;
+        for (int r = 0; r < dp; ++r)
+            v += C[(size_t)c * dp + r] * (Y ? Y[(size_t)j * dp + r] : pm_one(j, r, 0));
+        Z[e] = v * itr;
+    }
+}
+
 // Leading principal directions of the covariance C (dp x dp, FP64), one
-// work-group of 256 threads: a randomized range finder (three products of C
-// with a fixed +-1 start block, scaled by 1 / trace) followed by Gram-Schmidt
-// (two passes per column; a column that cancels to below 1e-6 of its norm
-// lies numerically in the span of the previous ones and is replaced by a
-// fresh +-1 vector, so the columns stay orthonormal to rounding).  After
-// every 16 columns the residual variance trace(C) - sum q_j^T C q_j is
-// compared with the query's scale: the first K with 2 (trace - captured) <=
-// beta * t2 (or K = kfix) is written to kout (0 if none up to kmax).  Q is
-// returned row-major [dp][K]; info[0] = rho (Gershgorin bound of Q^T Q,
-// enlarged by 1e-12 for its own rounding), info[1] = captured fraction.  Y
-// and Z are scratch blocks of kmax * dp doubles.
+// work-group of 256 threads, from Y = the randomized range finder's block
+// (three products of C with a fixed +-1 start block, scaled by 1 / trace,
+// by k_pca_power): Gram-Schmidt (two passes per column; a column that
+// cancels to below 1e-6 of its norm lies numerically in the span of the
+// previous ones and is replaced by a fresh +-1 vector, so the columns stay
+// orthonormal to rounding).  After every 16 columns the residual variance
+// trace(C) - sum q_j^T C q_j is compared with the query's scale: the first
+// K with 2 (trace - captured) <= beta * t2 (or K = kfix) is written to kout
+// (0 if none up to kmax).  Q is returned row-major [dp][K]; info[0] = rho
+// (Gershgorin bound of Q^T Q, enlarged by 1e-12 for its own rounding),
+// info[1] = captured fraction.  Y (kmax * dp doubles) is overwritten.
 __global__ void __launch_bounds__(256)
 k_pca(const double *__restrict__ C, int dp, int kmax, int kfix, double t2, double beta,
-      double *__restrict__ Y, double *__restrict__ Z, double *__restrict__ Q,
+      const double *__restrict__ trp, double *__restrict__ Y, double *__restrict__ Q,
       int *__restrict__ kout, double *__restrict__ info)
 {
     __shared__ double red[4];
     __shared__ double sdot[PCA_MAXK];
     __shared__ double grow[PCA_MAXK];
     const int t = threadIdx.x, lane = t & (WAVE - 1), wv = t / WAVE;
-    double tr = 0.0;
-    for (int c = t; c < dp; c += 256)
-        tr += C[(size_t)c * dp + c];
-    tr = block_sum256(tr, red);
+    const double tr = *trp;
     if (!(tr > 0.0)) {
         if (t == 0) {
             *kout = 0;
             info[0] = info[1] = 0.0;
         }
         return;
-    }
-    for (int e = t; e < kmax * dp; e += 256)
-        Y[e] = pm_one(e / dp, e % dp, 0);
-    __syncthreads();
-    const double itr = 1.0 / tr;
-    for (int it = 0; it < 3; ++it) {
-        for (int e = t; e < kmax * dp; e += 256) {
-            const int j = e / dp, c = e % dp;
-            double v = 0.0;
-            for (int r = 0; r < dp; ++r)
-                v += C[(size_t)c * dp + r] * Y[(size_t)j * dp + r];
-            Z[e] = v * itr;
-        }
-        __syncthreads();
-        double *sw = Y;
-        Y = Z;
-        Z = sw;
     }
     double cum = 0.0;
     int K = 0;
@@ -359,23 +392,64 @@ k_pca(const double *__restrict__ C, int dp, int kmax, int kfix, double t2, doubl
     }
 }
 
-// z = Q^T (x - mu) in FP64, stored as FP32 rows [n][K] (tree order).
+// z = Q^T (x - mu) in FP64, stored as FP32 rows [n][K] (tree order).  One
+// thread per row and 16 outputs at a time; Q (and mu of a single cloud)
+// staged in LDS 64 coordinates at a time; each output sums its products in
+// coordinate order.
+constexpr int PJ_K = 16, PJ_C = 64;
 __global__ void __launch_bounds__(256)
 k_project(const float *__restrict__ x, int n, int dp, Centre C,
           const double *__restrict__ Q, int K, float *__restrict__ z)
 {
-    const long long tot = (long long)n * K;
-    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
-         e += (long long)gridDim.x * blockDim.x) {
-        const long long i = e / K;
-        const int k = (int)(e - i * K);
-        const float *xr = x + (size_t)i * dp;
-        const int cl = C.cloud(i);
-        double v = 0.0;
-        for (int c = 0; c < dp; ++c)
-            v += Q[(size_t)c * K + k] *
-                 ((double)xr[c] - (double)C.sums[(size_t)cl * dp + c] * (double)C.inv[cl]);
-        z[e] = (float)v;
+    __shared__ double Qs[PJ_C][PJ_K];
+    __shared__ double Ms[PJ_C];
+    // blocks stride over row blocks (the same trip count in every thread)
+    for (long long base = (long long)blockIdx.x * blockDim.x; base < n;
+         base += (long long)gridDim.x * blockDim.x) {
+    const long long i = base + threadIdx.x;
+    const bool row = i < n;
+    const int cl = row ? C.cloud(i) : 0;
+    const float *xr = x + (size_t)(row ? i : 0) * dp;
+    for (int kc = 0; kc < K; kc += PJ_K) {
+        double acc[PJ_K];
+#pragma unroll
+        for (int k = 0; k < PJ_K; ++k)
+            acc[k] = 0.0;
+        for (int c0 = 0; c0 < dp; c0 += PJ_C) {
+            const int nc = min(PJ_C, dp - c0);
+            __syncthreads();  // the previous slice is consumed
+            for (int e = threadIdx.x; e < PJ_C * PJ_K; e += blockDim.x) {
+                const int c = e / PJ_K, k = e % PJ_K;
+                Qs[c][k] = c < nc && kc + k < K ? Q[(size_t)(c0 + c) * K + kc + k] : 0.0;
+            }
+            if (!C.pcl)
+                for (int c = threadIdx.x; c < nc; c += blockDim.x)
+                    Ms[c] = (double)C.sums[c0 + c] * (double)C.inv[0];
+            __syncthreads();
+            if (row) {
+                for (int c = 0; c < nc; c += 4) {
+                    const float4 v = *(const float4 *)(xr + c0 + c);
+                    const float vv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const double mu =
+                            C.pcl ? (double)C.sums[(size_t)cl * dp + c0 + c + u] *
+                                        (double)C.inv[cl]
+                                  : Ms[c + u];
+                        const double d = (double)vv[u] - mu;
+#pragma unroll
+                        for (int k = 0; k < PJ_K; ++k)
+                            acc[k] += Qs[c + u][k] * d;
+                    }
+                }
+            }
+        }
+        if (row)
+#pragma unroll
+            for (int k = 0; k < PJ_K; ++k)
+                if (kc + k < K)
+                    z[(size_t)i * K + kc + k] = (float)acc[k];
+    }
     }
 }
 
@@ -1258,9 +1332,9 @@ k_gram_direct(Pts P, GramArgs G, TileOut out)
                     for (int cb = 0; cb < 2; ++cb) {
                         if (cb * 32 >= nb)
                             break;
-                        float mx = acc[cb][0];
+                        float mx = -FLT_MAX;
 #pragma unroll
-                        for (int q = 1; q < 16; ++q)
+                        for (int q = 0; q < 16; ++q)
                             mx = fmaxf(mx, acc[cb][q]);
                         hm[cb] = __ballot(mx >= ayc[cb]);
                     }
@@ -1743,8 +1817,14 @@ static int project_pca(const float *X, int n, int dp, int kq_full, int proj,
     double *Y = S.get<double>((size_t)kmax * dp), *Z = S.get<double>((size_t)kmax * dp);
     double *Qd = S.get<double>((size_t)kmax * dp);
     int *kout = S.get<int>(1);
-    double *info = S.get<double>(2);
-    FNN_LAUNCH(k_pca, dim3(1), dim3(256), 0, s, Cv, dp, kmax, proj, t2min, 0.5, Y, Z, Qd,
+    double *info = S.get<double>(3);
+    double *trd = info + 2;
+    FNN_LAUNCH(k_pca_trace, dim3(1), dim3(256), 0, s, Cv, dp, trd);
+    const dim3 gp(grid_for((int64_t)kmax * dp, 256));
+    FNN_LAUNCH(k_pca_power, gp, dim3(256), 0, s, Cv, dp, kmax, trd, (const double *)nullptr, Y);
+    FNN_LAUNCH(k_pca_power, gp, dim3(256), 0, s, Cv, dp, kmax, trd, (const double *)Y, Z);
+    FNN_LAUNCH(k_pca_power, gp, dim3(256), 0, s, Cv, dp, kmax, trd, (const double *)Z, Y);
+    FNN_LAUNCH(k_pca, dim3(1), dim3(256), 0, s, Cv, dp, kmax, proj, t2min, 0.5, trd, Y, Qd,
                kout, info);
     const int K = read_scalar(kout, s);
     double hinfo[2];
@@ -1768,7 +1848,7 @@ static int project_pca(const float *X, int n, int dp, int kq_full, int proj,
     if (!(2.0 * emax <= 5e-7 * std::sqrt(hinfo[0]) * std::sqrt(t2min)))
         return 0;
     *z = S.get<float>((size_t)n * K);
-    FNN_LAUNCH(k_project, dim3(grid_cap((int64_t)n * K, 256, 16384)), dim3(256), 0, s, X, n,
+    FNN_LAUNCH(k_project, dim3(grid_for(n, 256)), dim3(256), 0, s, X, n,
                dp, CX, Qd, K, *z);
     *rho = hinfo[0];
     *captured = hinfo[1];
