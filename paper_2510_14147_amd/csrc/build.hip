@@ -327,6 +327,8 @@ __device__ __forceinline__ int cand_per_chunk(int nch, int kmax)
 constexpr int UPD_D = 128;  // largest row stride staged in LDS
 
 constexpr int UPD_W = 4;  // queue entries (one wave each) per work-group
+constexpr int UPD_P = 4;  // points per lane in the distance loop (CH / 16)
+static_assert(CH == 64 && UPD_K % UPD_P == 0, "lane layout of the distance loop");
 
 template <int M>
 __global__ void __launch_bounds__(CH * UPD_W)
@@ -371,8 +373,25 @@ k_update(Pts P, const int32_t *__restrict__ ch_hub, const int32_t *__restrict__ 
         staged = P.dp <= UPD_D;
         if (staged) {
             const float *X = (M == M_ANG) ? P.xn : P.x;
-            const int dp = P.dp;
-            const float *row = X + (size_t)o * dp;
+            const int dp = P.dp, ldc = dp + 4;  // padded: quarters hit distinct banks
+            // Four points per lane against a quarter of every batch: lane l
+            // takes positions s + l % 16 + 16 k (k < UPD_P) and the batch's
+            // centres UPD_P i + l / 16, so each staged centre read serves
+            // four points.  Every distance is the same FMA chain over the
+            // coordinates in order; the quarters' nearest centres are merged
+            // at the end by (distance, index), which is the first minimum
+            // the sequential scan would keep.
+            const int i16 = lane & 15, qd = lane >> 4;
+            const float *rows[UPD_P];
+            float dq[UPD_P];
+            int lq[UPD_P];
+#pragma unroll
+            for (int k = 0; k < UPD_P; ++k) {
+                const int src = i16 + 16 * k;
+                rows[k] = X + (size_t)__shfl(o, src, WAVE) * dp;
+                dq[k] = __shfl(dcur, src, WAVE);
+                lq[k] = __shfl(lcur, src, WAVE);
+            }
             __syncthreads();  // hub_s of the previous entries is consumed
             if (lane == 0)
                 hub_s[w] = act && j1 > j0 ? h : -1;
@@ -384,44 +403,73 @@ k_update(Pts P, const int32_t *__restrict__ ch_hub, const int32_t *__restrict__ 
                     first = first && hub_s[q] != hr;
                 if (!first)
                     continue;  // no hub, or staged in an earlier round
-                const bool mine = valid && h == hr;
+                const bool mine = act && h == hr;  // the same in every lane
                 const int br = hb.b[hr], j0r = hb.ma[hr], j1r = hb.m[hr];
                 for (int jb = j0r; jb < j1r; jb += UPD_K) {
                     const int nj = min(UPD_K, j1r - jb);
                     __syncthreads();  // the previous batch is consumed
                     for (int x = threadIdx.x; x < nj * dp; x += CH * UPD_W)
-                        cen[x] = X[(size_t)cent[br + jb + x / dp] * dp + (x % dp)];
+                        cen[(x / dp) * ldc + x % dp] =
+                            X[(size_t)cent[br + jb + x / dp] * dp + (x % dp)];
                     __syncthreads();
                     if (mine) {
-                        float acc[UPD_K];
+                        constexpr int NI = UPD_K / UPD_P;
+                        float acc[UPD_P][NI];
 #pragma unroll
-                        for (int j = 0; j < UPD_K; ++j)
-                            acc[j] = 0.f;
-                        for (int k = 0; k < dp; k += 4) {
-                            const float4 v = *reinterpret_cast<const float4 *>(row + k);
+                        for (int k = 0; k < UPD_P; ++k)
 #pragma unroll
-                            for (int j = 0; j < UPD_K; ++j) {
+                            for (int i = 0; i < NI; ++i)
+                                acc[k][i] = 0.f;
+                        for (int c = 0; c < dp; c += 4) {
+                            float4 v[UPD_P];
+#pragma unroll
+                            for (int k = 0; k < UPD_P; ++k)
+                                v[k] = *reinterpret_cast<const float4 *>(rows[k] + c);
+#pragma unroll
+                            for (int i = 0; i < NI; ++i) {
+                                const int j = UPD_P * i + qd;
                                 if (j < nj) {
                                     const float4 cc = *reinterpret_cast<const float4 *>(
-                                        cen + j * dp + k);
-                                    const float d0 = v.x - cc.x, d1 = v.y - cc.y,
-                                                d2 = v.z - cc.z, d3 = v.w - cc.w;
-                                    acc[j] = fmaf(d0, d0, acc[j]);
-                                    acc[j] = fmaf(d1, d1, acc[j]);
-                                    acc[j] = fmaf(d2, d2, acc[j]);
-                                    acc[j] = fmaf(d3, d3, acc[j]);
+                                        cen + j * ldc + c);
+#pragma unroll
+                                    for (int k = 0; k < UPD_P; ++k) {
+                                        const float d0 = v[k].x - cc.x, d1 = v[k].y - cc.y,
+                                                    d2 = v[k].z - cc.z, d3 = v[k].w - cc.w;
+                                        acc[k][i] = fmaf(d0, d0, acc[k][i]);
+                                        acc[k][i] = fmaf(d1, d1, acc[k][i]);
+                                        acc[k][i] = fmaf(d2, d2, acc[k][i]);
+                                        acc[k][i] = fmaf(d3, d3, acc[k][i]);
+                                    }
                                 }
                             }
                         }
 #pragma unroll
-                        for (int j = 0; j < UPD_K; ++j)
-                            if (j < nj && acc[j] < dcur) {
-                                dcur = acc[j];
-                                lcur = jb + j;
-                            }
+                        for (int i = 0; i < NI; ++i) {
+                            const int j = UPD_P * i + qd;
+                            if (j < nj)
+#pragma unroll
+                                for (int k = 0; k < UPD_P; ++k)
+                                    if (acc[k][i] < dq[k]) {
+                                        dq[k] = acc[k][i];
+                                        lq[k] = jb + j;
+                                    }
+                        }
                     }
                 }
             }
+            // this lane's point is entry qd of the four quarters' lanes
+            // i16 + 16 q
+#pragma unroll
+            for (int k = 0; k < UPD_P; ++k)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const float d2 = __shfl(dq[k], i16 + 16 * q, WAVE);
+                    const int l2 = __shfl(lq[k], i16 + 16 * q, WAVE);
+                    if (qd == k && (d2 < dcur || (d2 == dcur && l2 < lcur))) {
+                        dcur = d2;
+                        lcur = l2;
+                    }
+                }
         }
     }
     if (valid) {
@@ -1199,7 +1247,8 @@ static void build_impl(fnn_tree *T, const void *points, Scratch &S)
         fill(qlen, NC, 1, st);
         const unsigned gu = grid_cap(NC, UPD_W, 4096);
         const size_t upd_lds =
-            (M == M_L2 || M == M_ANG) && T->dp <= UPD_D ? sizeof(float) * UPD_K * T->dp : 16;
+            (M == M_L2 || M == M_ANG) && T->dp <= UPD_D ? sizeof(float) * UPD_K * (T->dp + 4)
+                                                        : 16;
         auto pass = [&](hipStream_t s, int k) {
             int32_t *qc = k ? qb : qa, *qx = k ? qa : qb;
             fill(qlen + (1 - k), 0, 1, s);

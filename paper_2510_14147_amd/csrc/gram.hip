@@ -1201,7 +1201,7 @@ __device__ __forceinline__ void half_finish(const GramArgs &G, const f32x16 (&ac
 // waves of its work-group; the four waves of a group read the same B rows
 // at about the same time, so most of those reads hit L1.
 template <int M, int NKS>
-__global__ void __launch_bounds__(GT, NKS == 1 ? 4 : 3)  // waves / SIMD that fit unspilled
+__global__ void __launch_bounds__(GT, NKS == 1 ? 6 : 4)  // waves / SIMD that fit unspilled
 k_gram_direct(Pts P, GramArgs G, TileOut out)
 {
     static_assert(NKS >= 1 && NKS <= 2, "narrow rows only");
