@@ -563,6 +563,39 @@ __global__ void k_max_pack(const int32_t *__restrict__ pb, const int32_t *__rest
             *big = 1;
 }
 
+// Unit table of the closed-form work list from per-run tables.  Run k
+// covers B packs [k R, h_k), h_k = min((k + 1) R, npk); its units are
+// U[k] .. U[k+1] - 1, unit U[k] + g pairing group g with packs
+// max(k R, GW g) .. h_k - 1, and its entries start at E[k] plus the lengths
+// of the run's earlier units (a closed form: the first a = min(g,
+// floor(k R / GW) + 1) groups take the whole run, a later group g' takes
+// h_k - GW g').
+__global__ void k_dense_plan(const long long *__restrict__ U, const long long *__restrict__ E,
+                             int nrun, int R, int npk, int nu, int32_t *__restrict__ ubeg,
+                             int32_t *__restrict__ ug, int32_t *__restrict__ ulo)
+{
+    for (int u = blockIdx.x * blockDim.x + threadIdx.x; u < nu;
+         u += gridDim.x * blockDim.x) {
+        int lo = 0, hi = nrun;  // U[lo] <= u < U[hi]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (U[mid] <= u)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        const long long k = lo, g = u - U[lo];
+        const long long kR = k * R, h = min((k + 1) * R, (long long)npk);
+        const long long a = min(g, kR / GW + 1);
+        const long long len = a * (h - kR) + (g - a) * h - GW * ((a + g - 1) * (g - a) / 2);
+        ubeg[u] = (int32_t)(E[lo] + len);
+        ug[u] = (int32_t)g;
+        ulo[u] = (int32_t)max(kR, GW * g);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        ubeg[nu] = (int32_t)E[nrun];
+}
+
 // Closed-form work list: unit u pairs group ug[u] with the consecutive B
 // packs ulo[u], ulo[u] + 1, ... (entries ubeg[u] .. ubeg[u+1]); one wave
 // per unit.
@@ -2044,31 +2077,32 @@ void gram_prepare(const fnn_tree *T, int prec, int proj, double eps, const Thr &
                        T->q_pt_begin + nn, T->q_pt_end + nn, npk, GP, big);
             if (read_scalar(big, s) == 0) {
                 // units ordered by B run (runs aligned to RUN packs), then by
-                // group: the units of one run read the same B tiles
-                std::vector<int32_t> ub, ug, ulo;
-                int64_t e = 0;
-                for (int k = 0; (int64_t)k * RUN < npk; ++k)
-                    for (int g = 0; g < ngr; ++g) {
-                        const int lo = std::max(k * RUN, GW * g);
-                        const int hi = std::min((k + 1) * RUN, npk);
-                        if (lo >= hi)
-                            continue;
-                        ub.push_back((int32_t)e);
-                        ug.push_back(g);
-                        ulo.push_back(lo);
-                        e += hi - lo;
-                    }
-                ub.push_back((int32_t)e);
-                const int nu = (int)ug.size();
+                // group: the units of one run read the same B tiles.  The
+                // host sums the per-run counts; the unit table itself is
+                // filled on the device (k_dense_plan).
+                const int nrun = (npk + RUN - 1) / RUN;
+                std::vector<long long> U(nrun + 1, 0), E(nrun + 1, 0);
+                for (int k = 0; k < nrun; ++k) {
+                    const long long kR = (long long)k * RUN;
+                    const long long h = std::min<long long>(kR + RUN, npk);
+                    const long long c = std::min<long long>(ngr, (h + GW - 1) / GW);
+                    const long long a = std::min<long long>(c, kR / GW + 1);
+                    U[k + 1] = U[k] + c;
+                    E[k + 1] = E[k] + a * (h - kR) + (c - a) * h -
+                               (long long)GW * ((a + c - 1) * (c - a) / 2);
+                }
+                const int nu = (int)U[nrun];
+                const int64_t e = E[nrun];
                 int32_t *lg = S.get<int32_t>(mu + 1), *lb = S.get<int32_t>(mu + 1);
                 int32_t *ubeg = S.get<int32_t>(nu + 1);
                 int32_t *ug_d = S.get<int32_t>(nu), *ulo_d = S.get<int32_t>(nu);
-                FNN_HIP(hipMemcpyAsync(ubeg, ub.data(), sizeof(int32_t) * (nu + 1),
+                long long *UE = S.get<long long>(2 * (size_t)(nrun + 1));
+                FNN_HIP(hipMemcpyAsync(UE, U.data(), sizeof(long long) * (nrun + 1),
                                        hipMemcpyHostToDevice, s));
-                FNN_HIP(hipMemcpyAsync(ug_d, ug.data(), sizeof(int32_t) * nu,
+                FNN_HIP(hipMemcpyAsync(UE + nrun + 1, E.data(), sizeof(long long) * (nrun + 1),
                                        hipMemcpyHostToDevice, s));
-                FNN_HIP(hipMemcpyAsync(ulo_d, ulo.data(), sizeof(int32_t) * nu,
-                                       hipMemcpyHostToDevice, s));
+                FNN_LAUNCH(k_dense_plan, dim3(grid_for(nu, 256)), dim3(256), 0, s, UE,
+                           UE + nrun + 1, nrun, RUN, npk, nu, ubeg, ug_d, ulo_d);
                 FNN_LAUNCH(k_dense_units, dim3(grid_cap(nu, 4, 16384)), dim3(256), 0, s,
                            ubeg, ug_d, ulo_d, nu, lg, lb);
                 FNN_HIP(hipStreamSynchronize(s));  // host vectors go out of scope
