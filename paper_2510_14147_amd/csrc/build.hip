@@ -560,6 +560,108 @@ __device__ void sort_desc(unsigned long long *buf, int m)
         }
 }
 
+// Top-K (K <= MAX_K) of the keys key(v), v in [0, nv), for the whole
+// work-group: the keys stream through once; a key enters buf only when it is
+// above thr, the K-th best key of the last sort (keys are distinct), and buf
+// is sorted and cut to its best K only when it fills.  Returns nk <= K with
+// buf[0..nk) the best keys in descending order.
+template <class KeyF>
+__device__ int topk_stream(long long nv, int K, KeyF key, unsigned long long *buf,
+                           int *fill_s)
+{
+    if (threadIdx.x == 0)
+        *fill_s = 0;
+    unsigned long long thr = 0ull;  // no candidate has key 0
+    int nk = 0;
+    __syncthreads();
+    auto compact = [&]() {
+        const int tot = *fill_s;
+        int p2 = 1;
+        while (p2 < tot)
+            p2 <<= 1;
+        for (int i = tot + threadIdx.x; i < p2; i += SEL_T)
+            buf[i] = 0ull;
+        __syncthreads();
+        sort_desc(buf, p2);
+        nk = min(K, tot);
+        if (nk == K)
+            thr = buf[K - 1];
+        __syncthreads();
+        if (threadIdx.x == 0)
+            *fill_s = nk;
+        __syncthreads();
+    };
+    for (long long base = 0; base < nv; base += SEL_STEP) {
+#pragma unroll
+        for (int r = 0; r < SEL_STEP / SEL_T; ++r) {
+            const long long v = base + r * SEL_T + threadIdx.x;
+            if (v < nv) {
+                const unsigned long long kv = key(v);
+                if (kv > thr)
+                    buf[atomicAdd(fill_s, 1)] = kv;  // *fill_s <= SEL_BUF - SEL_STEP before
+            }
+        }
+        __syncthreads();
+        if (*fill_s > SEL_BUF - SEL_STEP)
+            compact();
+    }
+    compact();
+    return nk;
+}
+
+// Candidate slices of a hub with many candidates (more than SEL_PRE): nsl
+// slices of len candidates each (the last may be shorter); 0 when the hub
+// streams its candidates whole.
+constexpr int SEL_SL = 8;                // slices per hub at most
+constexpr long long SEL_PRE = 2 * SEL_STEP;
+__device__ __forceinline__ void sel_slices(long long ncand, int &nsl, long long &len)
+{
+    nsl = ncand > SEL_PRE ? (int)min<long long>(SEL_SL, (ncand + SEL_STEP - 1) / SEL_STEP) : 0;
+    len = nsl ? (ncand + nsl - 1) / nsl : 0;
+}
+
+// Pre-selection for hubs with many candidates, SEL_SL work-groups per hub:
+// slice s keeps its K best candidates in its own first K slots (the rest of
+// those slots become "no candidate"), so k_select streams nsl x K keys
+// instead of all.  The K best of the hub are among them (keys are distinct).
+__global__ void __launch_bounds__(SEL_T)
+k_select_pre(Hubs hb, int H, float *__restrict__ cb_D, int32_t *__restrict__ cb_id, int kmax)
+{
+    __shared__ unsigned long long buf[SEL_BUF];
+    __shared__ int fill_s;
+    const int K = min(kmax, MAX_K);
+    for (long long w = blockIdx.x; w < (long long)H * SEL_SL; w += gridDim.x) {
+        const int h = (int)(w / SEL_SL), sl = (int)(w % SEL_SL);
+        if (!hb.act[h])
+            continue;
+        const int R = cand_per_chunk(hb.ce[h] - hb.cb[h], kmax);
+        const long long c0 = (long long)hb.cb[h] * R, c1 = (long long)hb.ce[h] * R;
+        int nsl;
+        long long len;
+        sel_slices(c1 - c0, nsl, len);
+        if (sl >= nsl)
+            continue;
+        const long long qs = c0 + sl * len, qe = min(c1, qs + len);
+        auto at = [&](long long q) { return (size_t)(q / R) * CAND_R + (size_t)(q % R); };
+        const int nk = topk_stream(
+            qe - qs, K,
+            [&](long long v) { const size_t a = at(qs + v); return cand_key(cb_D[a], cb_id[a]); },
+            buf, &fill_s);
+        for (int j = threadIdx.x; j < K; j += SEL_T)
+            if (qs + j < qe) {
+                const size_t a = at(qs + j);
+                if (j < nk) {
+                    cb_D[a] = __uint_as_float((uint32_t)(buf[j] >> 32));
+                    cb_id[a] = 0x7FFFFFFF - (int)(uint32_t)buf[j];
+                } else {
+                    cb_D[a] = -1.f;
+                    cb_id[a] = INT_MAX;
+                }
+            }
+        __syncthreads();  // buf is reused by the next slice
+    }
+}
+
 // One net-selection pass for every active hub (one work-group per hub): the
 // up to kmax farthest chunk candidates, in order (distance descending, id
 // ascending), are accepted greedily when more than 2^{l-1} from every
@@ -587,49 +689,21 @@ k_select(Pts P, Hubs hb, int H, int32_t *__restrict__ cent,
     const Thr T = tab->t[hb.lvl[h] - 1 + LOFF];
 
     // ---- top-K candidates ------------------------------------------------
-    // The candidates stream through once; a key enters buf only when it is
-    // above thr, the K-th best key of the last sort (keys are distinct), and
-    // buf is sorted and cut to its best K only when it fills.  Exactly the
-    // K largest keys remain, in order.
-    if (threadIdx.x == 0)
-        fill_s = 0;
-    unsigned long long thr = 0ull;  // no candidate has key 0
-    int nk = 0;
-    __syncthreads();
-    auto compact = [&]() {
-        const int tot = fill_s;
-        int p2 = 1;
-        while (p2 < tot)
-            p2 <<= 1;
-        for (int i = tot + threadIdx.x; i < p2; i += SEL_T)
-            buf[i] = 0ull;
-        __syncthreads();
-        sort_desc(buf, p2);
-        nk = min(K, tot);
-        if (nk == K)
-            thr = buf[K - 1];
-        __syncthreads();
-        if (threadIdx.x == 0)
-            fill_s = nk;
-        __syncthreads();
-    };
-    for (long long base = c0; base < c1; base += SEL_STEP) {
-#pragma unroll
-        for (int r = 0; r < SEL_STEP / SEL_T; ++r) {
-            // candidate q of the hub: slot q % R of its chunk q / R
-            const long long q = base + r * SEL_T + threadIdx.x;
-            if (q < c1) {
-                const size_t at = (size_t)(q / R) * CAND_R + (size_t)(q % R);
-                const unsigned long long kv = cand_key(cb_D[at], cb_id[at]);
-                if (kv > thr)
-                    buf[atomicAdd(&fill_s, 1)] = kv;  // fill_s <= SEL_BUF - SEL_STEP before
-            }
-        }
-        __syncthreads();
-        if (fill_s > SEL_BUF - SEL_STEP)
-            compact();
-    }
-    compact();
+    // (a hub with many candidates streams its slices' pre-selected K each)
+    int nsl;
+    long long len;
+    sel_slices(c1 - c0, nsl, len);
+    const long long nv = nsl ? (long long)nsl * K : c1 - c0;
+    int nk = topk_stream(
+        nv, K,
+        [&](long long v) -> unsigned long long {
+            const long long q = nsl ? c0 + (v / K) * len + (v % K) : c0 + v;
+            if (q >= c1 || (nsl && (v % K) >= len))
+                return 0ull;
+            const size_t a = (size_t)(q / R) * CAND_R + (size_t)(q % R);
+            return cand_key(cb_D[a], cb_id[a]);
+        },
+        buf, &fill_s);
     if (threadIdx.x == 0)
         nk_s = nk;
     for (int i = threadIdx.x; i < MAX_K * SEL_W; i += SEL_T)
@@ -1255,6 +1329,8 @@ static void build_impl(fnn_tree *T, const void *points, Scratch &S)
             FNN_LAUNCH((k_update<M>), dim3(gu), dim3(CH * UPD_W), upd_lds, s, P, ch_hub, ch_s,
                        ch_e, qc, qlen + k, hubs, cent, perm, D, L, tab, cb_D,
                        cb_id, T->opt.kmax, cnt);
+            FNN_LAUNCH(k_select_pre, dim3(grid_cap((int64_t)H * SEL_SL, 1, 8192)),
+                       dim3(SEL_T), 0, s, hubs, H, cb_D, cb_id, T->opt.kmax);
             FNN_LAUNCH((k_select<M>), dim3(grid_cap(H, 1, 4096)), dim3(SEL_T), 0, s, P,
                        hubs, H, cent, cb_D, cb_id, tab, T->opt.kmax, qx,
                        qlen + (1 - k), cnt);
