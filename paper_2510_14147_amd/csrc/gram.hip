@@ -1897,14 +1897,16 @@ static int centre_clouds(const fnn_tree *T)
 
 // Per-cloud centres of the rows X [n][dp] (one cloud: the global mean).
 static Centre make_centre(const fnn_tree *T, const float *X, int dp, const float *inv,
-                          Scratch &S)
+                          Scratch &S, bool zero = false)
 {
     hipStream_t s = S.stream();
     const int n = (int)T->n, ncl = centre_clouds(T);
     const int32_t *pcl = ncl > 1 ? T->pcl : nullptr;
     float *sums = S.get<float>((size_t)ncl * dp);
     fill(sums, 0.f, (int64_t)ncl * dp, s);
-    FNN_LAUNCH(k_colsum, dim3((unsigned)cdiv(n, 1024)), dim3(256), 0, s, X, n, dp, pcl, sums);
+    if (!zero)
+        FNN_LAUNCH(k_colsum, dim3((unsigned)cdiv(n, 1024)), dim3(256), 0, s, X, n, dp, pcl,
+                   sums);
     return Centre{sums, inv, pcl, dp};
 }
 
@@ -1981,7 +1983,10 @@ static void quantise_real(const fnn_tree *T, int prec, int proj, double t2min,
             G.proj = K;
             G.captured = cap;
             c_extra = 1e-7;
-            CX = make_centre(T, X, dp, inv, S);
+            // z = Q^T (x - mu) is centred already (per cloud): its own mean
+            // is a rounding residue, and the filter's bound holds for any
+            // centre, so z is quantised about 0
+            CX = make_centre(T, X, dp, inv, S, true);
         }
     }
     const int kq = (int)cdiv(dp, KS) * KS;
