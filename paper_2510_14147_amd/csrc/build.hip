@@ -525,6 +525,7 @@ constexpr int SEL_T = 256;
 constexpr int MAX_K = 256;     // candidates examined per hub and pass
 constexpr int SEL_BUF = 2048;  // LDS sort buffer (candidate keys)
 constexpr int SEL_W = MAX_K / 64;
+constexpr int SEL_CR = 64;     // candidates whose rows are staged in LDS
 // candidates read per round of the top-K stream: at most SEL_BUF - MAX_K, so
 // a round always fits after a sort has cut buf to K keys
 constexpr int SEL_STEP = 4 * SEL_T;
@@ -540,24 +541,91 @@ __device__ __forceinline__ unsigned long long cand_key(float d, int id)
            (unsigned long long)(uint32_t)(0x7FFFFFFF - id);
 }
 
-// Bitonic sort of buf[0..m) (m a power of two), descending.
-__device__ void sort_desc(unsigned long long *buf, int m)
+__device__ __forceinline__ unsigned long long shfl_xor_u64(unsigned long long v, int m)
 {
-    for (int k = 2; k <= m; k <<= 1)
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = threadIdx.x; i < m; i += blockDim.x) {
-                const int ixj = i ^ j;
-                if (ixj > i) {
-                    const unsigned long long a = buf[i], b = buf[ixj];
-                    const bool desc = (i & k) == 0;
-                    if (desc ? (a < b) : (a > b)) {
-                        buf[i] = b;
-                        buf[ixj] = a;
+    const unsigned lo = __shfl_xor((unsigned)v, m, WAVE);
+    const unsigned hi = __shfl_xor((unsigned)(v >> 32), m, WAVE);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+// Bitonic sort, descending, of one wave's 512 keys held as x[j] = element
+// 64 j + lane: partners 64 or more apart sit in the same lane, nearer ones
+// in the same register of another lane (a shuffle).  No barrier.
+__device__ __forceinline__ void wave_sort512_desc(unsigned long long (&x)[8])
+{
+    const int lane = threadIdx.x & (WAVE - 1);
+#pragma unroll
+    for (int k = 2; k <= 512; k <<= 1)
+#pragma unroll
+        for (int d = k >> 1; d > 0; d >>= 1) {
+            if (d >= WAVE) {
+                const int m = d / WAVE;
+#pragma unroll
+                for (int j = 0; j < 8; ++j)
+                    if ((j & m) == 0) {
+                        // element 64 j + lane is the lower of the pair
+                        const bool up = ((j * WAVE) & k) == 0;
+                        const unsigned long long a = x[j], b = x[j | m];
+                        const unsigned long long hi = a > b ? a : b, lo = a > b ? b : a;
+                        x[j] = up ? hi : lo;
+                        x[j | m] = up ? lo : hi;
                     }
+            } else {
+                const bool lower = (lane & d) == 0;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const bool up = ((j * WAVE + lane) & k) == 0;
+                    const unsigned long long b = shfl_xor_u64(x[j], d);
+                    const unsigned long long a = x[j];
+                    const unsigned long long hi = a > b ? a : b, lo = a > b ? b : a;
+                    x[j] = lower == up ? hi : lo;
                 }
             }
-            __syncthreads();
         }
+}
+
+// buf[0..tot) (tot <= SEL_BUF = 4 x 512) to its min(K, tot) largest keys in
+// descending order at buf[0..): every wave sorts a 512-key segment in
+// registers and writes it back, then one thread merges the four sorted
+// segments.  out: LDS of MAX_K keys.  Called by the whole work-group.
+__device__ void topk_sorted(unsigned long long *buf, int tot, int K,
+                            unsigned long long *out)
+{
+    static_assert(SEL_BUF == 4 * 512 && SEL_T == 256, "four waves of 512 keys");
+    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+    unsigned long long x[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int i = w * 512 + j * WAVE + lane;
+        x[j] = i < tot ? buf[i] : 0ull;
+    }
+    wave_sort512_desc(x);
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+        buf[w * 512 + j * WAVE + lane] = x[j];
+    __syncthreads();
+    const int nk = min(K, tot);
+    if (threadIdx.x == 0) {
+        int h[4] = {0, 0, 0, 0};
+        for (int r = 0; r < nk; ++r) {
+            int best = 0;
+            unsigned long long bv = h[0] < 512 ? buf[h[0]] : 0ull;
+#pragma unroll
+            for (int q = 1; q < 4; ++q) {
+                const unsigned long long v = h[q] < 512 ? buf[q * 512 + h[q]] : 0ull;
+                if (v > bv) {
+                    bv = v;
+                    best = q;
+                }
+            }
+            out[r] = bv;
+            ++h[best];
+        }
+    }
+    __syncthreads();
+    for (int r = threadIdx.x; r < nk; r += SEL_T)
+        buf[r] = out[r];
+    __syncthreads();
 }
 
 // Top-K (K <= MAX_K) of the keys key(v), v in [0, nv), for the whole
@@ -567,7 +635,7 @@ __device__ void sort_desc(unsigned long long *buf, int m)
 // buf[0..nk) the best keys in descending order.
 template <class KeyF>
 __device__ int topk_stream(long long nv, int K, KeyF key, unsigned long long *buf,
-                           int *fill_s)
+                           int *fill_s, unsigned long long *out)
 {
     if (threadIdx.x == 0)
         *fill_s = 0;
@@ -576,13 +644,7 @@ __device__ int topk_stream(long long nv, int K, KeyF key, unsigned long long *bu
     __syncthreads();
     auto compact = [&]() {
         const int tot = *fill_s;
-        int p2 = 1;
-        while (p2 < tot)
-            p2 <<= 1;
-        for (int i = tot + threadIdx.x; i < p2; i += SEL_T)
-            buf[i] = 0ull;
-        __syncthreads();
-        sort_desc(buf, p2);
+        topk_sorted(buf, tot, K, out);
         nk = min(K, tot);
         if (nk == K)
             thr = buf[K - 1];
@@ -627,7 +689,7 @@ __device__ __forceinline__ void sel_slices(long long ncand, int &nsl, long long 
 __global__ void __launch_bounds__(SEL_T)
 k_select_pre(Hubs hb, int H, float *__restrict__ cb_D, int32_t *__restrict__ cb_id, int kmax)
 {
-    __shared__ unsigned long long buf[SEL_BUF];
+    __shared__ unsigned long long buf[SEL_BUF], out[MAX_K];
     __shared__ int fill_s;
     const int K = min(kmax, MAX_K);
     for (long long w = blockIdx.x; w < (long long)H * SEL_SL; w += gridDim.x) {
@@ -646,7 +708,7 @@ k_select_pre(Hubs hb, int H, float *__restrict__ cb_D, int32_t *__restrict__ cb_
         const int nk = topk_stream(
             qe - qs, K,
             [&](long long v) { const size_t a = at(qs + v); return cand_key(cb_D[a], cb_id[a]); },
-            buf, &fill_s);
+            buf, &fill_s, out);
         for (int j = threadIdx.x; j < K; j += SEL_T)
             if (qs + j < qe) {
                 const size_t a = at(qs + j);
@@ -675,8 +737,9 @@ k_select(Pts P, Hubs hb, int H, int32_t *__restrict__ cent,
          const LevelTab *__restrict__ tab, int kmax, int32_t *__restrict__ qnext,
          int32_t *__restrict__ qnext_len, unsigned long long *__restrict__ cnt)
 {
-    __shared__ unsigned long long buf[SEL_BUF];
+    __shared__ unsigned long long buf[SEL_BUF], out[MAX_K];
     __shared__ unsigned long long conf[MAX_K][SEL_W];
+    __shared__ __align__(16) float crow[SEL_CR * (UPD_D + 4)];  // staged candidate rows
     __shared__ int acc[MAX_K];
     __shared__ int nacc_s, nk_s, qb_s, fill_s;
     const int K = min(kmax, MAX_K);
@@ -703,7 +766,7 @@ k_select(Pts P, Hubs hb, int H, int32_t *__restrict__ cent,
             const size_t a = (size_t)(q / R) * CAND_R + (size_t)(q % R);
             return cand_key(cb_D[a], cb_id[a]);
         },
-        buf, &fill_s);
+        buf, &fill_s, out);
     if (threadIdx.x == 0)
         nk_s = nk;
     for (int i = threadIdx.x; i < MAX_K * SEL_W; i += SEL_T)
@@ -712,7 +775,22 @@ k_select(Pts P, Hubs hb, int H, int32_t *__restrict__ cent,
     nk = nk_s;
 
     // ---- pairwise conflicts (j < i): within 2^{l-1} ----------------------
+    // Vector rows of up to SEL_CR candidates are staged in LDS first (rows
+    // padded by 4 floats: neighbouring rows start in different banks); the
+    // FP32 key is the same sqdiff_key either way.
     unsigned long long tests = 0;
+    const bool lds_rows = (M == M_L2 || M == M_ANG) && P.dp <= UPD_D && nk <= SEL_CR;
+    const int ldr = P.dp + 4;
+    if (lds_rows) {
+        const float *X = M == M_ANG ? P.xn : P.x;
+        const int dp = P.dp;
+        for (int e = threadIdx.x; e < nk * dp; e += SEL_T) {
+            const int r = e / dp, c = e % dp;
+            const int id = 0x7FFFFFFF - (int)(uint32_t)buf[r];
+            crow[r * ldr + c] = X[(size_t)id * dp + c];
+        }
+        __syncthreads();
+    }
     for (int q = threadIdx.x; q < nk * nk; q += SEL_T) {
         const int i = q / nk, j = q % nk;
         if (j >= i)
@@ -720,7 +798,8 @@ k_select(Pts P, Hubs hb, int H, int32_t *__restrict__ cent,
         const int a = 0x7FFFFFFF - (int)(uint32_t)buf[i];
         const int c = 0x7FFFFFFF - (int)(uint32_t)buf[j];
         ++tests;
-        const float k = key32<M>(P, a, c);
+        const float k = lds_rows ? sqdiff_key(crow + i * ldr, crow + j * ldr, P.dp)
+                                 : key32<M>(P, a, c);
         if (within<M>(P, a, c, k, T, cnt + 1))
             atomicOr(&conf[i][j >> 6], 1ull << (j & 63));
     }
