@@ -327,7 +327,8 @@ __device__ __forceinline__ int cand_per_chunk(int nch, int kmax)
 constexpr int UPD_D = 128;  // largest row stride staged in LDS
 
 constexpr int UPD_W = 4;  // queue entries (one wave each) per work-group
-constexpr int UPD_P = 4;  // points per lane in the distance loop (CH / 16)
+constexpr int UPD_P = 4;  // points per lane in the distance loop (eight: fewer waves, slower)
+constexpr int UPD_LG = 64 / UPD_P;  // lanes per centre group
 static_assert(CH == 64 && UPD_K % UPD_P == 0, "lane layout of the distance loop");
 
 template <int M>
@@ -381,13 +382,13 @@ k_update(Pts P, const int32_t *__restrict__ ch_hub, const int32_t *__restrict__ 
             // coordinates in order; the quarters' nearest centres are merged
             // at the end by (distance, index), which is the first minimum
             // the sequential scan would keep.
-            const int i16 = lane & 15, qd = lane >> 4;
+            const int i16 = lane % UPD_LG, qd = lane / UPD_LG;
             const float *rows[UPD_P];
             float dq[UPD_P];
             int lq[UPD_P];
 #pragma unroll
             for (int k = 0; k < UPD_P; ++k) {
-                const int src = i16 + 16 * k;
+                const int src = i16 + UPD_LG * k;
                 rows[k] = X + (size_t)__shfl(o, src, WAVE) * dp;
                 dq[k] = __shfl(dcur, src, WAVE);
                 lq[k] = __shfl(lcur, src, WAVE);
@@ -457,14 +458,14 @@ k_update(Pts P, const int32_t *__restrict__ ch_hub, const int32_t *__restrict__ 
                     }
                 }
             }
-            // this lane's point is entry qd of the four quarters' lanes
-            // i16 + 16 q
+            // this lane's point is entry qd of the groups' lanes
+            // i16 + UPD_LG q
 #pragma unroll
             for (int k = 0; k < UPD_P; ++k)
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const float d2 = __shfl(dq[k], i16 + 16 * q, WAVE);
-                    const int l2 = __shfl(lq[k], i16 + 16 * q, WAVE);
+                for (int q = 0; q < UPD_P; ++q) {
+                    const float d2 = __shfl(dq[k], i16 + UPD_LG * q, WAVE);
+                    const int l2 = __shfl(lq[k], i16 + UPD_LG * q, WAVE);
                     if (qd == k && (d2 < dcur || (d2 == dcur && l2 < lcur))) {
                         dcur = d2;
                         lcur = l2;
