@@ -66,8 +66,17 @@ struct GramArgs {
     double captured;
     // bichromatic query: only pairs across the two clouds are evaluated
     int cross;
+    // narrow BF16 rows copied per pack (64 rows each, zero past the pack)
+    // and their column terms 0.5 hx (FLT_MAX past the pack); null when the
+    // staged kernel runs
+    const void *qp;
+    const float *ayp;
 };
 
+// Per-pack copies of the quantised rows and column terms for the narrow
+// BF16 kernel (G.qp, G.ayp), when that kernel applies; needs G.q, G.hx,
+// G.kq, G.q_pb, G.q_pe, G.nn, G.npacks.
+void gram_pad_packs(int metric, int prec, GramArgs &G, Scratch &S);
 // Exact decision of the survivor list: edges[i] and edist[i] (input ids,
 // FP32 distance) for survivor i, (-1, -1) when it is no edge, and per-row
 // degrees; counts land in out.cnt.

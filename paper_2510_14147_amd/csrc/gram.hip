@@ -1234,7 +1234,7 @@ __device__ __forceinline__ void half_finish(const GramArgs &G, const f32x16 (&ac
 // waves of its work-group; the four waves of a group read the same B rows
 // at about the same time, so most of those reads hit L1.
 template <int M, int NKS>
-__global__ void __launch_bounds__(GT, NKS == 1 ? 6 : 4)  // waves / SIMD that fit unspilled
+__global__ void __launch_bounds__(GT, NKS == 1 ? 5 : 4)  // waves / SIMD that fit unspilled
 k_gram_direct(Pts P, GramArgs G, TileOut out)
 {
     static_assert(NKS >= 1 && NKS <= 2, "narrow rows only");
@@ -1295,26 +1295,27 @@ k_gram_direct(Pts P, GramArgs G, TileOut out)
         // two entries earlier (no copy of a register with a load in flight)
         int4 BA[2][NKS], BB[2][NKS];
         float ayA[2], ayB[2];
+        // B side from the per-pack copies: pack k's 64 rows (zero past the
+        // pack) and column terms (FLT_MAX past the pack) at a scalar base,
+        // so every lane loads at a fixed offset and an entry costs no vector
+        // arithmetic; the loads of one entry are a fixed count, so the next
+        // entry's stay in flight while this one computes.
+        const unsigned char *QP = (const unsigned char *)G.qp;
+        const char *AYP = (const char *)G.ayp;
         auto load_b = [&](int e, int4 (&B)[2][NKS], float (&ay)[2]) {
-            const int pbb = eP[e - e0], nbb = eN[e - e0];
+            // 32-bit byte offsets from the fixed bases (gram_pad_packs checks
+            // that the copies fit)
+            const unsigned pk = (unsigned)(__builtin_amdgcn_readfirstlane(eB[e - e0]) - G.nn);
 #pragma unroll
             for (int cb = 0; cb < 2; ++cb) {
-                const int c = cb * 32 + l32;
-                const bool ok = c < nbb;
-                // Every lane loads (columns past nb read the pack's first
-                // row: their ay = FLT_MAX and row mask 0 keep them out), so
-                // the loads of one entry are a fixed count and the next
-                // entry's stay in flight while this one computes.  32-bit
-                // byte offsets from the uniform bases (the launch checks
-                // that the rows fit).
-                const unsigned row = (unsigned)(ok ? pbb + c : min(pbb, P.n - 1));
+                const unsigned c = (unsigned)(cb * 32 + l32);
 #pragma unroll
                 for (int ks = 0; ks < NKS; ++ks)
-                    B[cb][ks] = *(const int4 *)(Q + (row * (unsigned)rowb +
-                                                     (unsigned)(ks * 32 + hi * 16)));
-                // the raw norm: used (and waited for) only when the entry
-                // is processed
-                ay[cb] = *(const float *)((const char *)G.hx + row * 4u);
+                    B[cb][ks] = *(const int4 *)(QP + (pk * (unsigned)(GP * rowb) +
+                                                      c * (unsigned)rowb +
+                                                      (unsigned)(ks * 32 + hi * 16)));
+                // used (and waited for) only when processed
+                ay[cb] = *(const float *)(AYP + (pk * (unsigned)(GP * 4) + c * 4u));
             }
         };
         auto step = [&](int e, int4 (&B)[2][NKS], float (&ay)[2]) {
@@ -1329,8 +1330,7 @@ k_gram_direct(Pts P, GramArgs G, TileOut out)
                 // screened pairs: r < c on a self pair (then nb == na)
                 npairs += self ? (unsigned long long)(na * (na - 1) / 2)
                                : (unsigned long long)(na * nb);
-                const float ayc[2] = {l32 < nb ? 0.5f * ay[0] : FLT_MAX,
-                                      32 + l32 < nb ? 0.5f * ay[1] : FLT_MAX};
+                const float ayc[2] = {ay[0], ay[1]};
                 // one 32-row half at a time against both column blocks: the
                 // half's 16 start values feed both products
 #pragma unroll
@@ -1744,8 +1744,8 @@ static void launch_gram(bool fill_pass, const Pts &P, const GramArgs &G,
         default: launch_gram_k<M, PREC, 8>(fill_pass, P, G, o, s); break;
         }
     } else if constexpr (PREC == FNN_PREC_BF16) {
-        // the narrow kernel addresses rows with 32-bit byte offsets
-        const bool narrow_fits = (long long)P.n * 32 * nks < (1ll << 32);
+        // the narrow kernel reads the per-pack copies (made when it applies)
+        const bool narrow_fits = G.qp != nullptr;
         switch (nks) {
         case 1:
             if (narrow_fits)
@@ -1772,6 +1772,45 @@ static void launch_gram(bool fill_pass, const Pts &P, const GramArgs &G,
         else
             launch_gram_k<M, PREC, 2>(fill_pass, P, G, o, s);
     }
+}
+
+// Per-pack copies for the narrow kernel: row r of pack k at k * GP + r (the
+// pack's row when r < its size, else zero) and its column term 0.5 hx (else
+// FLT_MAX, which no accumulator reaches).
+__global__ void k_pad_packs(const int32_t *__restrict__ pb, const int32_t *__restrict__ pe,
+                            int npk, const unsigned char *__restrict__ q,
+                            const float *__restrict__ hx, int rowb,
+                            unsigned char *__restrict__ qp, float *__restrict__ ayp)
+{
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+         e < (long long)npk * GP; e += (long long)gridDim.x * blockDim.x) {
+        const int k = (int)(e / GP), r = (int)(e % GP);
+        const int b = pb[k];
+        const bool in = r < pe[k] - b;
+        for (int c = 0; c < rowb; c += 16)
+            *(int4 *)(qp + e * rowb + c) =
+                in ? *(const int4 *)(q + (size_t)(b + r) * rowb + c) : make_int4(0, 0, 0, 0);
+        ayp[e] = in ? 0.5f * hx[b + r] : FLT_MAX;
+    }
+}
+
+void gram_pad_packs(int metric, int prec, GramArgs &G, Scratch &S)
+{
+    G.qp = nullptr;
+    G.ayp = nullptr;
+    const int nks = G.kq / GramCfg<FNN_PREC_BF16>::KSTEP;
+    if (metric == M_HAM || prec != FNN_PREC_BF16 || nks < 1 || nks > 2 || G.npacks <= 0)
+        return;
+    const long long rowb = 32ll * nks;
+    if ((long long)G.npacks * GP * rowb >= (1ll << 32))
+        return;  // the staged kernel takes larger sets
+    unsigned char *qp = (unsigned char *)S.raw((size_t)G.npacks * GP * rowb + 64);
+    float *ayp = S.get<float>((size_t)G.npacks * GP);
+    FNN_LAUNCH(k_pad_packs, dim3(grid_for((int64_t)G.npacks * GP, 256)), dim3(256), 0,
+               S.stream(), G.q_pb + G.nn, G.q_pe + G.nn, G.npacks,
+               (const unsigned char *)G.q, G.hx, (int)rowb, qp, ayp);
+    G.qp = qp;
+    G.ayp = ayp;
 }
 
 void gram_launch(int metric, int prec, bool fill_pass, const Pts &P,

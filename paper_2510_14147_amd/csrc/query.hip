@@ -1422,6 +1422,7 @@ static void eps_graph_impl(const fnn_tree *Tc, const double *epsv,
             G.q_pb = T->q_pt_begin;
             G.q_pe = T->q_pt_end;
             G.perm = T->perm;
+            gram_pad_packs(M, prec, G, S);
             G.ct = ncl > 1 ? ct_d : nullptr;
             G.pcl = ncl > 1 ? T->pcl : nullptr;
             if (ncl > 1 && G.t2mul != 1.0) {
