@@ -152,9 +152,93 @@ __device__ inline int lev_bitpar(const uint64_t *__restrict__ peq, int m,
     return score;
 }
 
-__device__ inline int lev_dispatch(const uint64_t *peq, int m,
-                                   const uint8_t *text, int tl, int W)
+// The same recurrence for alphabets of at most 4 symbols: the pattern's
+// match masks sit in registers and the text is read four symbols per load,
+// so a step waits on no memory (the per-symbol loads of lev_bitpar make a
+// single distance a chain of dependent memory round trips).
+template <int W>
+__device__ inline int lev_bitpar4(const uint64_t *__restrict__ peq, int sigma, int m,
+                                  const uint8_t *__restrict__ text, int tl)
 {
+    if (m == 0)
+        return tl;
+    if (tl == 0)
+        return m;
+    uint64_t eqr[4][W], pv[W], mv[W];
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int w = 0; w < W; ++w)
+            eqr[c][w] = c < sigma ? peq[c * W + w] : 0ull;  // the table holds sigma rows
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        pv[w] = ~0ull;
+        mv[w] = 0ull;
+    }
+    const int lastw = (m - 1) >> 6;
+    const uint64_t lastbit = 1ull << ((m - 1) & 63);
+    int score = m;
+    auto step = [&](unsigned ch) {
+        uint64_t cadd = 0ull, cph = 1ull, cmh = 0ull;
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            if (w <= lastw) {
+                const uint64_t eq = ch == 0 ? eqr[0][w]
+                                    : ch == 1 ? eqr[1][w]
+                                    : ch == 2 ? eqr[2][w]
+                                              : eqr[3][w];
+                uint64_t xv = eq | mv[w];
+                uint64_t t = eq & pv[w];
+                uint64_t s1 = t + pv[w];
+                uint64_t c1 = s1 < t ? 1ull : 0ull;
+                uint64_t s2 = s1 + cadd;
+                uint64_t c2 = s2 < s1 ? 1ull : 0ull;
+                cadd = c1 | c2;
+                uint64_t xh = (s2 ^ pv[w]) | eq;
+                uint64_t ph = mv[w] | ~(xh | pv[w]);
+                uint64_t mh = pv[w] & xh;
+                if (w == lastw) {
+                    if (ph & lastbit)
+                        ++score;
+                    else if (mh & lastbit)
+                        --score;
+                }
+                uint64_t phs = (ph << 1) | cph;
+                uint64_t mhs = (mh << 1) | cmh;
+                cph = ph >> 63;
+                cmh = mh >> 63;
+                pv[w] = mhs | ~(xv | phs);
+                mv[w] = phs & xv;
+            }
+        }
+    };
+    int j = 0;
+    if (((uintptr_t)text & 3) == 0)
+        for (; j + 4 <= tl; j += 4) {
+            const unsigned wd = *(const unsigned *)(text + j);
+            step(wd & 255u);
+            step((wd >> 8) & 255u);
+            step((wd >> 16) & 255u);
+            step(wd >> 24);
+        }
+    for (; j < tl; ++j)
+        step(text[j]);
+    return score;
+}
+
+__device__ inline int lev_dispatch(const uint64_t *peq, int m,
+                                   const uint8_t *text, int tl, int W, int sigma)
+{
+    if (sigma <= 4) {
+        switch (W) {
+        case 1:
+            return lev_bitpar4<1>(peq, sigma, m, text, tl);
+        case 2:
+            return lev_bitpar4<2>(peq, sigma, m, text, tl);
+        default:
+            break;  // longer patterns: the general form
+        }
+    }
     switch (W) {
     case 1:
         return lev_bitpar<1>(peq, m, text, tl);
@@ -209,7 +293,7 @@ __device__ __forceinline__ float key32(const Pts &P, int i, int j)
                                 P.dp);
     } else {
         return (float)lev_dispatch(P.peq + (size_t)i * P.sigma * P.W, P.len[i],
-                                   P.s + (size_t)j * P.dp, P.len[j], P.W);
+                                   P.s + (size_t)j * P.dp, P.len[j], P.W, P.sigma);
     }
 }
 

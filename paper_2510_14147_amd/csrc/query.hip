@@ -194,6 +194,10 @@ __device__ __forceinline__ bool may_touch_coop(const Pts &P, const QView &Q,
 // Expand one vertex pair (whole wave).  With TG > 1 (vector metrics), TG
 // lanes share each test and the group's first lane emits the result.
 // Returns the number of tests made by this lane.
+// A self pair of more children than this is split into one item per child
+// row (frontier item (a, -1 - i)) so that many waves share its tests.
+constexpr int SELF_SPLIT = 64;
+
 template <int M, int TG>
 __device__ unsigned long long expand_one(const Pts &P, const QView &Q,
                                          const Prune &pr, int a, int b,
@@ -204,12 +208,45 @@ __device__ unsigned long long expand_one(const Pts &P, const QView &Q,
     const bool lead = (lane & (TG - 1)) == 0;  // the slot's emitting lane
     constexpr int NS = WAVE / TG;              // tests per wave step
     unsigned long long tests = 0;
+    if (b < 0) {
+        // row i of a split self pair of a: children (i, j), j >= i (the
+        // diagonal pair without a test)
+        const int i = -1 - b, m = Q.kcnt[a], k0 = Q.kbeg[a];
+        const int ka = Q.kids[k0 + i];
+        for (int base = 0; base < m - i; base += NS) {
+            const int t = base + sub;
+            bool valid = t < m - i;
+            const int kb = valid ? Q.kids[k0 + i + t] : 0;
+            const bool test = valid && t != 0;
+            if constexpr (TG == 1) {
+                if (test) {
+                    ++tests;
+                    valid = may_touch<M>(P, Q, pr, ka, kb);
+                }
+            } else {
+                const bool ok = may_touch_coop<M, TG>(P, Q, pr, ka, kb, test);
+                if (test) {
+                    tests += lead;
+                    valid = ok;
+                }
+            }
+            emit_pair(E, sg, Q, valid && lead, ka, kb);
+        }
+        return tests;
+    }
     if (a == b) {
         if (a >= Q.nn) {  // a single pack against itself
             emit_pair(E, sg, Q, lane == 0, a, a);
             return 0;
         }
         const int m = Q.kcnt[a], k0 = Q.kbeg[a];
+        if (m > SELF_SPLIT) {
+            // m (m + 1) / 2 tests are too many for one wave: the next round
+            // takes them as m row items (a, -1 - i), one wave each
+            for (int base = 0; base < m; base += WAVE)
+                emit_pair(E, sg, Q, base + lane < m, a, -1 - (base + lane));
+            return 0;
+        }
         const long long tot = (long long)m * (m + 1) / 2;
         for (long long base = 0; base < tot; base += NS) {
             const long long t = base + sub;
@@ -296,9 +333,12 @@ __global__ void k_expand_bound(QView Q, const int2 *__restrict__ cur,
          i += (long long)gridDim.x * blockDim.x) {
         const int2 p = cur[i];
         const int a = p.x, c = p.y;
-        if (a == c) {
+        if (c < 0) {  // row -1 - c of a split self pair: pairs (i, j), j >= i
+            b += (unsigned long long)(Q.kcnt[a] - (-1 - c));
+        } else if (a == c) {
             const long long m = a >= Q.nn ? 1 : Q.kcnt[a];
-            b += (unsigned long long)(m * (m + 1) / 2);
+            b += m > SELF_SPLIT ? (unsigned long long)m  // its row items
+                                : (unsigned long long)(m * (m + 1) / 2);
         } else {
             const bool at = a >= Q.nn, ct = c >= Q.nn;
             int s;
