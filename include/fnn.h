@@ -84,7 +84,8 @@ typedef enum {
 typedef struct fnn_options {
     int32_t struct_size;  /* sizeof(fnn_options)                             */
     int32_t zeta;         /* leaf size (Algorithm 2); default 64             */
-    int32_t pack;         /* points per query/leaf tile block; default 64    */
+    int32_t pack;         /* points per query/leaf tile block; default 64
+                             (Levenshtein: 1, one leaf block per pack)       */
     int32_t precision;    /* fnn_precision; default FNN_PREC_FP32.  BF16 and */
                           /* FP8 apply to L2 / angular with dim <= 128 (else */
                           /* FNN_EUNSUPPORTED), I8 to Hamming codes of <= 256 */
