@@ -474,7 +474,46 @@ k_update(Pts P, const int32_t *__restrict__ ch_hub, const int32_t *__restrict__ 
         }
     }
     if (valid) {
-        if (!staged)
+        bool scanned = staged;  // the new centres already compared
+        if constexpr (M == M_HAM) {
+            if (!scanned && P.dp <= 4) {
+                // codes of up to 256 bits: the point's words stay in
+                // registers and eight centres' indices and words are
+                // fetched at once (the scan order is unchanged)
+                uint64_t mine[4];
+#pragma unroll
+                for (int w = 0; w < 4; ++w)
+                    mine[w] = w < P.dp ? P.h[(size_t)o * P.dp + w] : 0ull;
+                for (int j = j0; j < j1; j += 8) {
+                    int cj[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u)
+                        cj[u] = j + u < j1 ? cent[b + j + u] : -1;
+                    uint64_t cw[8][4];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u)
+#pragma unroll
+                        for (int w = 0; w < 4; ++w)
+                            cw[u][w] = cj[u] >= 0 && w < P.dp ? P.h[(size_t)cj[u] * P.dp + w]
+                                                              : 0ull;
+#pragma unroll
+                    for (int u = 0; u < 8; ++u)
+                        if (cj[u] >= 0) {
+                            int dh = 0;
+#pragma unroll
+                            for (int w = 0; w < 4; ++w)
+                                dh += __popcll(mine[w] ^ cw[u][w]);
+                            const float k = (float)dh;
+                            if (k < dcur) {
+                                dcur = k;
+                                lcur = j + u;
+                            }
+                        }
+                }
+                scanned = true;
+            }
+        }
+        if (!scanned)
             for (int j = j0; j < j1; ++j) {
                 float k = key32<M>(P, o, cent[b + j]);
                 if (k < dcur) {
