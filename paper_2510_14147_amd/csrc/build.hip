@@ -633,6 +633,23 @@ __device__ void topk_sorted(unsigned long long *buf, int tot, int K,
 {
     static_assert(SEL_BUF == 4 * 512 && SEL_T == 256, "four waves of 512 keys");
     const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+    if (tot <= WAVE) {
+        // a small hub: one wave sorts a key per lane (no merge)
+        if (w == 0) {
+            unsigned long long v = lane < tot ? buf[lane] : 0ull;
+            for (int k = 2; k <= WAVE; k <<= 1)
+                for (int d = k >> 1; d > 0; d >>= 1) {
+                    const unsigned long long o = shfl_xor_u64(v, d);
+                    const bool lower = (lane & d) == 0, up = (lane & k) == 0;
+                    const unsigned long long hi = o > v ? o : v, lo = o > v ? v : o;
+                    v = lower == up ? hi : lo;
+                }
+            if (lane < tot)
+                buf[lane] = v;
+        }
+        __syncthreads();
+        return;
+    }
     unsigned long long x[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
