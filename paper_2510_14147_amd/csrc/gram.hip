@@ -513,12 +513,17 @@ __global__ void k_quant_ham(const uint64_t *__restrict__ h, int n, int W,
 __global__ void k_route(const int2 *__restrict__ inter, long long ninter,
                         const int32_t *__restrict__ q_pb,
                         const int32_t *__restrict__ q_pe, int nn, int pack,
+                        uint32_t kinf, uint32_t ginf,
                         uint32_t *__restrict__ key, uint32_t *__restrict__ val,
                         unsigned long long *__restrict__ cnt,
                         int2 *__restrict__ rest)
 {
-    // one reservation per wave and destination (whole waves iterate, so the
-    // ballots see every lane)
+    // Pair i of the list keeps slot i of (key, val): its B pack and group,
+    // or (kinf, ginf) when it goes to rest instead (both sentinels sort
+    // after every real key, so the real pairs come first).  Only the rare
+    // pairs with a pack larger than the tile reserve slots in rest, one
+    // reservation per wave (whole waves iterate, so the ballots see every
+    // lane).
     const int lane = threadIdx.x & (WAVE - 1);
     const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     const long long lim = (ninter + WAVE - 1) / WAVE * WAVE;
@@ -533,22 +538,18 @@ __global__ void k_route(const int2 *__restrict__ inter, long long ninter,
             b = max(p.x, p.y);
             big = (q_pe[a] - q_pb[a] > pack) || (q_pe[b] - q_pb[b] > pack);
         }
-        const uint64_t mb = __ballot(valid && big), ms = __ballot(valid && !big);
-        unsigned long long ob = 0, os = 0;
-        if (lane == 0) {
-            if (mb)
+        const uint64_t mb = __ballot(valid && big);
+        if (mb) {
+            unsigned long long ob = 0;
+            if (lane == 0)
                 ob = atomicAdd(&cnt[1], (unsigned long long)__popcll(mb));
-            if (ms)
-                os = atomicAdd(&cnt[0], (unsigned long long)__popcll(ms));
+            ob = __shfl(ob, 0, WAVE);
+            if (valid && big)
+                rest[ob + __popcll(mb & lt)] = make_int2(a, b);
         }
-        ob = __shfl(ob, 0, WAVE);
-        os = __shfl(os, 0, WAVE);
-        if (valid && big) {
-            rest[ob + __popcll(mb & lt)] = make_int2(a, b);
-        } else if (valid) {
-            const unsigned long long o = os + __popcll(ms & lt);
-            key[o] = (uint32_t)(b - nn);
-            val[o] = (uint32_t)((a - nn) / GW);
+        if (valid) {
+            key[i] = big ? kinf : (uint32_t)(b - nn);
+            val[i] = big ? ginf : (uint32_t)((a - nn) / GW);
         }
     }
 }
@@ -2169,12 +2170,14 @@ void gram_prepare(const fnn_tree *T, int prec, int proj, double eps, const Thr &
     int2 *rs = S.get<int2>(ninter + 1);
     unsigned long long *cnt = S.get<unsigned long long>(2);
     fill(cnt, 0ull, 2, s);
+    // sentinels past every B pack and every group (within the sort's bits)
+    const uint32_t kinf = (uint32_t)npk, ginf = (uint32_t)(npk / GW + 1);
     FNN_LAUNCH(k_route, dim3(grid_for(ninter, 256)), dim3(256), 0, s, inter,
-               ninter, T->q_pt_begin, T->q_pt_end, nn, GP, k1, v1, cnt, rs);
+               ninter, T->q_pt_begin, T->q_pt_end, nn, GP, kinf, ginf, k1, v1, cnt, rs);
     unsigned long long hc[2];
     FNN_HIP(hipMemcpyAsync(hc, cnt, sizeof hc, hipMemcpyDeviceToHost, s));
     FNN_HIP(hipStreamSynchronize(s));
-    const long long m = (long long)hc[0];
+    const long long m = ninter - (long long)hc[1];  // real pairs: sorted first
     *rest = rs;
     *nrest = (long long)hc[1];
     G.nn = nn;
@@ -2191,11 +2194,11 @@ void gram_prepare(const fnn_tree *T, int prec, int proj, double eps, const Thr &
         }
         return b;
     };
-    uint32_t *k2 = S.get<uint32_t>(m), *v2 = S.get<uint32_t>(m);
-    // sort by B, then stably by group: (group, B) order
-    radix_sort_pairs(k1, v1, k2, v2, m, bits((uint32_t)npk), S);
-    uint32_t *gk = S.get<uint32_t>(m), *bv = S.get<uint32_t>(m);
-    radix_sort_pairs(v2, k2, gk, bv, m, bits((uint32_t)(npk / GW + 1)), S);
+    uint32_t *k2 = S.get<uint32_t>(ninter), *v2 = S.get<uint32_t>(ninter);
+    // sort by B, then stably by group: (group, B) order, sentinels last
+    radix_sort_pairs(k1, v1, k2, v2, ninter, bits(kinf), S);
+    uint32_t *gk = S.get<uint32_t>(ninter), *bv = S.get<uint32_t>(ninter);
+    radix_sort_pairs(v2, k2, gk, bv, ninter, bits(ginf), S);
     int32_t *flag = S.get<int32_t>(m + 1), *pos = S.get<int32_t>(m + 2);
     FNN_LAUNCH(k_uniq_flags, dim3(grid_for(m, 256)), dim3(256), 0, s, gk, bv, m,
                flag);
