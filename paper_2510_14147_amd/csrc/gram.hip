@@ -1564,6 +1564,38 @@ k_survive(Pts P, GramArgs G, long long ns, int2 *__restrict__ edges,
     }
 }
 
+// One CSR slot of row `key` per lane (key < 0: none), claimed with one
+// cursor atomic per run of equal keys among the wave's active lanes (lanes
+// with key < 0 in between do not end a run): the filters write a row's
+// survivors within a column block next to each other, so runs are the
+// common case.  Called by every lane of the wave that is still in its loop;
+// returns the lane's slot where key >= 0.
+__device__ __forceinline__ unsigned long long claim_run_slot(unsigned long long *cursor,
+                                                             int key)
+{
+    const int lane = threadIdx.x & (WAVE - 1);
+    const bool act = key >= 0;
+    const uint64_t A = __ballot(act);
+    const uint64_t below = A & ((1ull << lane) - 1);  // lane < 64: no overflow
+    const int p = below ? 63 - __builtin_clzll(below) : lane;
+    const int pk = __shfl(key, p, WAVE);  // key of the previous active lane
+    const bool cont = act && below != 0 && pk == key;
+    const uint64_t Hd = A & ~__ballot(cont);  // run heads
+    const uint64_t upto = lane == WAVE - 1 ? ~0ull : ((2ull << lane) - 1);
+    const uint64_t hb = Hd & upto;
+    const int h = hb ? 63 - __builtin_clzll(hb) : 0;
+    const uint64_t from_h = ~((1ull << h) - 1);
+    unsigned long long base = 0;
+    if (act && h == lane) {
+        const uint64_t nxt = Hd & ~upto;  // next head above
+        const uint64_t run = nxt ? (nxt & (0 - nxt)) - 1 : ~0ull;
+        base = atomicAdd(&cursor[key], (unsigned long long)__popcll(A & from_h & run));
+    }
+    const unsigned blo = __shfl((unsigned)base, h, WAVE);
+    const unsigned bhi = __shfl((unsigned)(base >> 32), h, WAVE);
+    return (((unsigned long long)bhi << 32) | blo) + (unsigned)(__popcll(A & from_h & upto) - 1);
+}
+
 // Writes an unordered edge list (input ids, distance; entries (-1, -1) are
 // skipped) into the CSR slots of both endpoints.
 __global__ void k_edges_scatter(const int2 *__restrict__ edges,
@@ -1573,10 +1605,10 @@ __global__ void k_edges_scatter(const int2 *__restrict__ edges,
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < ne;
          i += (long long)gridDim.x * blockDim.x) {
         const int2 e = edges[i];
+        const unsigned long long s1 = claim_run_slot(out.cursor, e.x);
         if (e.x < 0)
             continue;  // a survivor that is no edge
         const float d = edist[i];
-        const unsigned long long s1 = atomicAdd(&out.cursor[e.x], 1ull);
         const unsigned long long s2 = atomicAdd(&out.cursor[e.y], 1ull);
         if (s1 < out.nnz && s2 < out.nnz) {
             out.col[s1] = e.y;
@@ -1638,12 +1670,13 @@ __global__ void k_edges_scatter_ham(const int2 *__restrict__ surv, long long ne,
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < ne;
          i += (long long)gridDim.x * blockDim.x) {
         const int2 e = surv[i];
+        const int oi = e.x < 0 ? -1 : perm[e.x];
+        const unsigned long long s1 = claim_run_slot(out.cursor, oi);
         if (e.x < 0)
             continue;  // an unused slot
         const int pi = e.x, pj = e.y & 0x7FFFFFFF;
         const float d = (float)ham_words(h + (size_t)pi * W, h + (size_t)pj * W, W);
-        const int oi = perm[pi], oj = perm[pj];
-        const unsigned long long s1 = atomicAdd(&out.cursor[oi], 1ull);
+        const int oj = perm[pj];
         const unsigned long long s2 = atomicAdd(&out.cursor[oj], 1ull);
         if (s1 < out.nnz && s2 < out.nnz) {
             out.col[s1] = oj;
