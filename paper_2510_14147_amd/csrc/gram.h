@@ -29,8 +29,9 @@ struct TileOut {
     float *spill_dist;
     unsigned long long *spill_cnt;
     unsigned long long spill_cap;
-    // edge-list count pass: every unordered edge (input ids, distance) is
-    // appended while it fits; the running count may exceed the capacity
+    // edge-list count pass: every edge (input ids, distance) is appended in
+    // both directions while it fits; the running count may exceed the
+    // capacity
     int2 *elist;
     float *edist;
     unsigned long long *ecnt;
@@ -83,9 +84,10 @@ void gram_pad_packs(int metric, int prec, GramArgs &G, Scratch &S);
 void survivors_launch(int metric, const Pts &P, const GramArgs &G,
                       long long nsurv, int2 *edges, float *edist, const TileOut &o,
                       hipStream_t s);
-// Unordered edge list (input ids, distance; (-1, -1) entries skipped) into
-// the CSR.
-void edges_scatter(const int2 *edges, const float *edist, long long ne,
+// Edge list (input ids, distance; (-1, -1) entries skipped) into the CSR:
+// both: every edge listed once, written into both rows; else every edge
+// listed in both directions, each entry written into its first id's row.
+void edges_scatter(const int2 *edges, const float *edist, long long ne, bool both,
                    const TileOut &o, hipStream_t s);
 // Survivors of the exact integer filter (tree positions) into the CSR, with
 // their Hamming distances.

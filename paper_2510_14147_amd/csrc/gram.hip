@@ -1596,11 +1596,13 @@ __device__ __forceinline__ unsigned long long claim_run_slot(unsigned long long 
     return (((unsigned long long)bhi << 32) | blo) + (unsigned)(__popcll(A & from_h & upto) - 1);
 }
 
-// Writes an unordered edge list (input ids, distance; entries (-1, -1) are
-// skipped) into the CSR slots of both endpoints.
+// Writes an edge list (input ids, distance; entries (-1, -1) are skipped)
+// into the CSR: each entry into the slots of both endpoints when the list
+// holds every edge once, else (every edge listed in both directions) into
+// its first endpoint's row only.
 __global__ void k_edges_scatter(const int2 *__restrict__ edges,
                                 const float *__restrict__ edist, long long ne,
-                                TileOut out)
+                                bool both, TileOut out)
 {
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < ne;
          i += (long long)gridDim.x * blockDim.x) {
@@ -1609,6 +1611,15 @@ __global__ void k_edges_scatter(const int2 *__restrict__ edges,
         if (e.x < 0)
             continue;  // a survivor that is no edge
         const float d = edist[i];
+        if (!both) {
+            if (s1 < out.nnz) {
+                out.col[s1] = e.y;
+                out.dist[s1] = d;
+            } else {
+                atomicOr(out.err, ERR_INDEX);
+            }
+            continue;
+        }
         const unsigned long long s2 = atomicAdd(&out.cursor[e.y], 1ull);
         if (s1 < out.nnz && s2 < out.nnz) {
             out.col[s1] = e.y;
@@ -1651,13 +1662,13 @@ void survivors_launch(int metric, const Pts &P, const GramArgs &G,
                    edist, o);
 }
 
-void edges_scatter(const int2 *edges, const float *edist, long long ne,
+void edges_scatter(const int2 *edges, const float *edist, long long ne, bool both,
                    const TileOut &o, hipStream_t s)
 {
     if (ne <= 0)
         return;
     FNN_LAUNCH(k_edges_scatter, dim3(grid_for(ne, 256)), dim3(256), 0, s, edges,
-               edist, ne, o);
+               edist, ne, both, o);
 }
 
 // Edges of the exact integer filter (tree positions, passed flag in bit 31

@@ -454,7 +454,9 @@ __device__ __forceinline__ void put(const TileOut &out, int row, int col,
 }
 
 // Tile pass modes: count row degrees; fill CSR slots; or count and append
-// every unordered edge to an edge list (which replaces the fill pass).
+// every edge to an edge list in both directions (which replaces the fill
+// pass): a row's entries, then a column's, lie next to each other, so the
+// scatter claims slots once per run.
 enum { TILE_COUNT = 0, TILE_FILL = 1, TILE_LIST = 2 };
 
 template <int M, int MODE>
@@ -657,8 +659,8 @@ k_tile(Pts P, const int2 *__restrict__ inter, long long ninter,
                     }
                 }
                 if constexpr (LIST) {
-                    // this row's edges, once per unordered pair (threads
-                    // 0..63 are one wave: one reservation for all of them)
+                    // this row's edges (threads 0..63 are one wave: one
+                    // reservation for all of them)
                     int incl = c;
 #pragma unroll
                     for (int o = 1; o < WAVE; o <<= 1) {
@@ -684,11 +686,36 @@ k_tile(Pts P, const int2 *__restrict__ inter, long long ninter,
                 }
             } else if (t < 2 * TS) {
                 const int cc = t - TS;
-                if (cc < rb) {
-                    int c = 0;
+                int c = 0;
+                if (cc < rb)
                     for (int r = 0; r < ra; ++r)
                         c += (int)((mask[r] >> cc) & 1ull);
-                    const int ocol = c ? perm[pb + cc] : 0;
+                const int ocol = c ? perm[pb + cc] : 0;
+                if constexpr (LIST) {
+                    // the same edges seen from this column (threads 64..127
+                    // are one wave)
+                    int incl = c;
+#pragma unroll
+                    for (int o = 1; o < WAVE; o <<= 1) {
+                        const int v = __shfl_up(incl, o, WAVE);
+                        if ((t & (WAVE - 1)) >= o)
+                            incl += v;
+                    }
+                    const int tot = __shfl(incl, WAVE - 1, WAVE);
+                    unsigned long long base = 0;
+                    if (cc == 0 && tot)
+                        base = atomicAdd(out.ecnt, (unsigned long long)tot);
+                    base = __shfl(base, 0, WAVE) + (unsigned long long)(incl - c);
+                    for (int r = 0; c && r < ra; ++r)
+                        if ((mask[r] >> cc) & 1ull) {
+                            if (base < out.ecap) {
+                                out.elist[base] = make_int2(ocol, perm[pa + r]);
+                                out.edist[base] = dt[r * (TS + 1) + cc];
+                            }
+                            ++base;
+                        }
+                }
+                if (cc < rb) {
                     if (c && FILL && out.row_filter && !out.row_filter[ocol])
                         c = 0;
                     if (c) {
@@ -1577,11 +1604,11 @@ static void eps_graph_impl(const fnn_tree *Tc, const double *epsv,
                 ++novf;  // a second filter pass was needed
             }
         }
-        // Plain tiles: count degrees and append each unordered edge to an
-        // edge list, so the fill needs no second tile pass.  The list holds
-        // up to 256 edges per point (bounded by the pairs the tiles can
-        // evaluate and by an eighth of the free device memory); if it
-        // overflows, the fill pass runs instead.
+        // Plain tiles: count degrees and append each edge, in both
+        // directions, to an edge list, so the fill needs no second tile
+        // pass.  The list holds up to 256 entries per point (bounded by
+        // twice the pairs the tiles can evaluate and by an eighth of the
+        // free device memory); if it overflows, the fill pass runs instead.
         bool listed = false;
         long long nlisted = 0;
         if (nplain > 0) {
@@ -1594,7 +1621,7 @@ static void eps_graph_impl(const fnn_tree *Tc, const double *epsv,
             FNN_HIP(hipMemGetInfo(&freeb, &totb));
             const unsigned long long room = (unsigned long long)(freeb / 8 / 12);
             o.ecap = std::max<unsigned long long>(
-                1024, std::min({bound, room, 256ull * (unsigned long long)n}));
+                1024, std::min({2 * bound, room, 256ull * (unsigned long long)n}));
             o.elist = S.get<int2>(o.ecap);
             o.edist = S.get<float>(o.ecap);
             o.ecnt = S.get<unsigned long long>(1);
@@ -1624,9 +1651,9 @@ static void eps_graph_impl(const fnn_tree *Tc, const double *epsv,
             if (G.degp)
                 edges_scatter_ham(gedges, ngedges, P, T->perm, o, s);
             else if (use_gram)
-                edges_scatter(gedges, gedist, ngedges, o, s);
+                edges_scatter(gedges, gedist, ngedges, true, o, s);
             if (listed)
-                edges_scatter(o.elist, o.edist, nlisted, o, s);
+                edges_scatter(o.elist, o.edist, nlisted, false, o, s);
             else
                 launch_tiles<M>(TILE_FILL, P, plain, nplain, T, E, ct_d, fp64_dist,
                                 o, s);
