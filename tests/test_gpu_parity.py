@@ -102,6 +102,17 @@ def test_all_duplicates(fnn, orc):
     check(fnn, orc, x, "l2", 1e-3)
 
 
+@pytest.mark.parametrize("prec", ["bf16", "fp32"])
+def test_complete_graph_scatter(fnn, orc, prec):
+    # every pair is an edge: whole waves of survivors (or listed tile
+    # edges) share one row, so the scatter's slot claims cover full runs,
+    # runs across wave boundaries and both directions of every edge
+    # (239 neighbours per point: the plain tiles' list holds them all)
+    x = np.repeat(G.random_points(3, 16, seed=5), 80, axis=0)
+    x += np.float32(1e-3) * G.random_points(240, 16, seed=6)
+    check(fnn, orc, x, "l2", 100.0, tree_check=False, precision=prec)
+
+
 def test_tiny_and_huge_eps(fnn, orc):
     x = G.random_points(700, 3, seed=3)
     check(fnn, orc, x, "l2", 1e-6)
