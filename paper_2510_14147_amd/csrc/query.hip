@@ -860,7 +860,28 @@ k_sort_small(const int64_t *__restrict__ row_ptr, int n, int32_t *__restrict__ c
     }
 }
 
-// Rows of 513..4096 entries: one work-group per row, bitonic sort in LDS.
+// Rows of 513..2048 entries (from the list of 513..4096): one wave per row,
+// the register sort with 16 or 32 entries per lane.
+__global__ void __launch_bounds__(256)
+k_sort_wave(const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ list,
+            int nl, int32_t *__restrict__ col, float *__restrict__ dist)
+{
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wpb = blockDim.x / WAVE;
+    for (int li = blockIdx.x * wpb + threadIdx.x / WAVE; li < nl; li += gridDim.x * wpb) {
+        const int r = list[li];
+        const int64_t b = row_ptr[r];
+        const int len = (int)(row_ptr[r + 1] - b);
+        if (len > 32 * WAVE)
+            continue;  // the work-group sort's
+        if (len > 16 * WAVE)
+            wave_sort_row<32>(col, dist, b, len, lane);
+        else
+            wave_sort_row<16>(col, dist, b, len, lane);
+    }
+}
+
+// Rows of 2049..4096 entries: one work-group per row, bitonic sort in LDS.
 __global__ void __launch_bounds__(256)
 k_sort_mid(const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ list,
            int nl, int32_t *__restrict__ col, float *__restrict__ dist)
@@ -870,6 +891,8 @@ k_sort_mid(const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ list
     const int r = list[li];
     const int64_t b = row_ptr[r];
     const int len = (int)(row_ptr[r + 1] - b);
+    if (len <= 32 * WAVE)
+        continue;  // sorted by one wave (the same for the whole work-group)
     int P2 = 1;
     while (P2 < len)
         P2 <<= 1;
@@ -1765,9 +1788,12 @@ static void eps_graph_impl(const fnn_tree *Tc, const double *epsv,
         int32_t hcc[2];
         FNN_HIP(hipMemcpyAsync(hcc, cc, sizeof hcc, hipMemcpyDeviceToHost, s));
         FNN_HIP(hipStreamSynchronize(s));
-        if (hcc[0] > 0)
+        if (hcc[0] > 0) {
+            FNN_LAUNCH(k_sort_wave, dim3(grid_cap(hcc[0], 4, 4096)), dim3(256), 0, s,
+                       C->row_ptr, mid, hcc[0], C->col, C->dist);
             FNN_LAUNCH(k_sort_mid, dim3(grid_cap(hcc[0], 1, 4096)), dim3(256), 0, s,
                        C->row_ptr, mid, hcc[0], C->col, C->dist);
+        }
         if (hcc[1] > 0) {
             int64_t *p2 = S.get<int64_t>(hcc[1] + 1);
             int64_t *soff = S.get<int64_t>(hcc[1] + 2);

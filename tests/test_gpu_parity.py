@@ -113,6 +113,19 @@ def test_complete_graph_scatter(fnn, orc, prec):
     check(fnn, orc, x, "l2", 100.0, tree_check=False, precision=prec)
 
 
+def test_row_sort_lengths(fnn, orc):
+    # separated tight clusters, complete inside: their rows take every path
+    # of the per-row sort (one entry per lane; a wave's registers up to 512,
+    # 1024 and 2048 entries; a work-group in LDS up to 4096; a global buffer
+    # beyond)
+    sizes = [50, 300, 600, 1100, 2100, 4200]
+    parts = [np.float32(100.0 * k) + G.random_points(m, 3, seed=20 + k, scale=0.01)
+             for k, m in enumerate(sizes)]
+    x = np.concatenate(parts).astype(np.float32)
+    x = x[np.random.default_rng(12).permutation(len(x))]
+    check(fnn, orc, x, "l2", 1.0, tree_check=False)
+
+
 def test_tiny_and_huge_eps(fnn, orc):
     x = G.random_points(700, 3, seed=3)
     check(fnn, orc, x, "l2", 1e-6)
