@@ -881,45 +881,81 @@ k_sort_wave(const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ lis
     }
 }
 
-// Rows of 2049..4096 entries: one work-group per row, bitonic sort in LDS.
+// Rows of 2049..4096 entries: one work-group per row, padded to 4096.  Entry
+// g = 1024 w + 64 v + lane lives in register v of that lane of wave w:
+// bitonic stages with strides below 64 exchange across lanes, strides up to
+// 512 swap registers, and only the three stages with strides of 1024 and
+// 2048 go through LDS.
 __global__ void __launch_bounds__(256)
 k_sort_mid(const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ list,
            int nl, int32_t *__restrict__ col, float *__restrict__ dist)
 {
-    __shared__ unsigned long long s[4096];
+    constexpr int V = 16, N = 4096;
+    static_assert(4 * V * WAVE == N, "four waves of 1024 entries");
+    __shared__ unsigned long long s[N];
+    const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+    const int g0 = w * V * WAVE + lane;  // entry of register 0
     for (int li = blockIdx.x; li < nl; li += gridDim.x) {
-    const int r = list[li];
-    const int64_t b = row_ptr[r];
-    const int len = (int)(row_ptr[r + 1] - b);
-    if (len <= 32 * WAVE)
-        continue;  // sorted by one wave (the same for the whole work-group)
-    int P2 = 1;
-    while (P2 < len)
-        P2 <<= 1;
-    for (int i = threadIdx.x; i < P2; i += blockDim.x)
-        s[i] = i < len ? pack_entry(col[b + i], dist[b + i]) : ~0ull;
-    __syncthreads();
-    for (int k = 2; k <= P2; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = threadIdx.x; i < P2; i += blockDim.x) {
-                const int l = i ^ j;
-                if (l > i) {
-                    const bool up = (i & k) == 0;
-                    unsigned long long x = s[i], y = s[l];
-                    if ((x > y) == up) {
-                        s[i] = y;
-                        s[l] = x;
+        const int r = list[li];
+        const int64_t b = row_ptr[r];
+        const int len = (int)(row_ptr[r + 1] - b);
+        if (len <= 32 * WAVE)
+            continue;  // sorted by one wave (the same for the whole work-group)
+        unsigned long long x[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const int g = g0 + v * WAVE;
+            x[v] = g < len ? pack_entry(col[b + g], dist[b + g]) : ~0ull;
+        }
+#pragma unroll
+        for (int k = 2; k <= N; k <<= 1) {
+#pragma unroll
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                if (j >= V * WAVE) {
+#pragma unroll
+                    for (int v = 0; v < V; ++v)
+                        s[g0 + v * WAVE] = x[v];
+                    __syncthreads();
+#pragma unroll
+                    for (int v = 0; v < V; ++v) {
+                        const int g = g0 + v * WAVE;
+                        const unsigned long long o = s[g ^ j];
+                        const bool up = (g & k) == 0, lower = (g & j) == 0;
+                        x[v] = (lower == up) ? (o < x[v] ? o : x[v]) : (o > x[v] ? o : x[v]);
+                    }
+                    __syncthreads();  // s is written again by the next such stage
+                } else if (j >= WAVE) {
+                    const int jv = j / WAVE;
+#pragma unroll
+                    for (int v = 0; v < V; ++v) {
+                        if (v & jv)
+                            continue;
+                        const bool up = ((g0 + v * WAVE) & k) == 0;
+                        const unsigned long long a = x[v], c = x[v | jv];
+                        if ((a > c) == up) {
+                            x[v] = c;
+                            x[v | jv] = a;
+                        }
+                    }
+                } else {
+#pragma unroll
+                    for (int v = 0; v < V; ++v) {
+                        const unsigned long long o = __shfl_xor(x[v], j, WAVE);
+                        const bool up = ((g0 + v * WAVE) & k) == 0;
+                        const bool lower = (lane & j) == 0;
+                        x[v] = (lower == up) ? (o < x[v] ? o : x[v]) : (o > x[v] ? o : x[v]);
                     }
                 }
             }
-            __syncthreads();
         }
-    }
-    for (int i = threadIdx.x; i < len; i += blockDim.x) {
-        col[b + i] = (int32_t)(s[i] >> 32);
-        dist[b + i] = __uint_as_float((uint32_t)s[i]);
-    }
-    __syncthreads();
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const int g = g0 + v * WAVE;
+            if (g < len) {
+                col[b + g] = (int32_t)(x[v] >> 32);
+                dist[b + g] = __uint_as_float((uint32_t)x[v]);
+            }
+        }
     }
 }
 
