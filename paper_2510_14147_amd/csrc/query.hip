@@ -881,26 +881,27 @@ k_sort_wave(const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ lis
     }
 }
 
-// Rows of 2049..4096 entries: one work-group per row, padded to 4096.  Entry
-// g = 1024 w + 64 v + lane lives in register v of that lane of wave w:
-// bitonic stages with strides below 64 exchange across lanes, strides up to
-// 512 swap registers, and only the three stages with strides of 1024 and
-// 2048 go through LDS.
-__global__ void __launch_bounds__(256)
-k_sort_mid(const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ list,
-           int nl, int32_t *__restrict__ col, float *__restrict__ dist)
+// Listed rows of lo+1 .. 1024 NW entries: one work-group of NW waves per
+// row, padded to N = 1024 NW.  Entry g = 1024 w + 64 v + lane lives in
+// register v of that lane of wave w: bitonic stages with strides below 64
+// exchange across lanes, strides up to 512 swap registers, and only the
+// stages with strides of 1024 and more go through LDS.
+template <int NW>
+__global__ void __launch_bounds__(NW * WAVE)
+k_sort_blk(const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ list,
+           int nl, int lo, int32_t *__restrict__ col, float *__restrict__ dist)
 {
-    constexpr int V = 16, N = 4096;
-    static_assert(4 * V * WAVE == N, "four waves of 1024 entries");
+    constexpr int V = 16, N = NW * V * WAVE;
     __shared__ unsigned long long s[N];
     const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
     const int g0 = w * V * WAVE + lane;  // entry of register 0
     for (int li = blockIdx.x; li < nl; li += gridDim.x) {
         const int r = list[li];
         const int64_t b = row_ptr[r];
-        const int len = (int)(row_ptr[r + 1] - b);
-        if (len <= 32 * WAVE)
-            continue;  // sorted by one wave (the same for the whole work-group)
+        const int64_t len64 = row_ptr[r + 1] - b;
+        if (len64 <= lo || len64 > N)
+            continue;  // another kernel's (the same for the whole work-group)
+        const int len = (int)len64;
         unsigned long long x[V];
 #pragma unroll
         for (int v = 0; v < V; ++v) {
@@ -959,8 +960,10 @@ k_sort_mid(const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ list
     }
 }
 
+constexpr int SORT_BLK_MAX = 16 * 16 * WAVE;  // longest row k_sort_blk<16> sorts
+
 // Longer rows: one work-group per row, bitonic sort in a global scratch
-// buffer (rare: only rows with more than 4096 neighbours).
+// buffer (rare: only rows with more than 16384 neighbours).
 __global__ void __launch_bounds__(256)
 k_sort_long(const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ list,
             const int64_t *__restrict__ soff, unsigned long long *__restrict__ scr,
@@ -969,6 +972,8 @@ k_sort_long(const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ lis
     const int r = list[blockIdx.x];
     const int64_t b = row_ptr[r];
     const int64_t len = row_ptr[r + 1] - b;
+    if (len <= SORT_BLK_MAX)
+        return;  // sorted in registers by k_sort_blk<16>
     unsigned long long *s = scr + soff[blockIdx.x];
     int64_t P2 = 1;
     while (P2 < len)
@@ -1827,8 +1832,8 @@ static void eps_graph_impl(const fnn_tree *Tc, const double *epsv,
         if (hcc[0] > 0) {
             FNN_LAUNCH(k_sort_wave, dim3(grid_cap(hcc[0], 4, 4096)), dim3(256), 0, s,
                        C->row_ptr, mid, hcc[0], C->col, C->dist);
-            FNN_LAUNCH(k_sort_mid, dim3(grid_cap(hcc[0], 1, 4096)), dim3(256), 0, s,
-                       C->row_ptr, mid, hcc[0], C->col, C->dist);
+            FNN_LAUNCH(k_sort_blk<4>, dim3(grid_cap(hcc[0], 1, 4096)), dim3(4 * WAVE), 0,
+                       s, C->row_ptr, mid, hcc[0], 32 * WAVE, C->col, C->dist);
         }
         if (hcc[1] > 0) {
             int64_t *p2 = S.get<int64_t>(hcc[1] + 1);
@@ -1838,6 +1843,8 @@ static void eps_graph_impl(const fnn_tree *Tc, const double *epsv,
             scan_i64(p2, soff, hcc[1], S);
             const int64_t tot = read_scalar(soff + hcc[1], s);
             unsigned long long *scr = S.get<unsigned long long>(tot);
+            FNN_LAUNCH(k_sort_blk<16>, dim3(grid_cap(hcc[1], 1, 4096)), dim3(16 * WAVE), 0,
+                       s, C->row_ptr, lng, hcc[1], 64 * WAVE, C->col, C->dist);
             FNN_LAUNCH(k_sort_long, dim3(hcc[1]), dim3(256), 0, s, C->row_ptr, lng,
                        soff, scr, C->col, C->dist);
         }

@@ -126,6 +126,27 @@ def test_row_sort_lengths(fnn, orc):
     check(fnn, orc, x, "l2", 1.0, tree_check=False)
 
 
+def test_long_rows_sorted(fnn):
+    # one tight cluster of 16500 points: every row holds all 16499 others,
+    # longer than the register sorts take.  Too large for the oracle's
+    # comparison; checked by what a complete graph fixes: the row offsets,
+    # each row strictly increasing without its own id, and sampled distances
+    # against FP64
+    n = 16500
+    x = G.random_points(n, 2, seed=31, scale=0.01)
+    _, g = gpu_graph(fnn, x, "l2", 1.0)
+    rp, col, dist = g.to_numpy()
+    assert np.array_equal(rp, np.arange(n + 1, dtype=np.int64) * (n - 1))
+    c = col.reshape(n, n - 1)
+    assert (np.diff(c, axis=1) > 0).all()
+    assert c.min() >= 0 and c.max() < n
+    assert (c != np.arange(n)[:, None]).all()
+    x64 = x.astype(np.float64)
+    for r in (0, 4321, n - 1):
+        ref = np.sqrt(((x64[c[r]] - x64[r]) ** 2).sum(axis=1))
+        np.testing.assert_allclose(dist[r * (n - 1):(r + 1) * (n - 1)], ref, rtol=RTOL)
+
+
 def test_tiny_and_huge_eps(fnn, orc):
     x = G.random_points(700, 3, seed=3)
     check(fnn, orc, x, "l2", 1e-6)
