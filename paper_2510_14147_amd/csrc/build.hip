@@ -650,26 +650,31 @@ __device__ void topk_sorted(unsigned long long *buf, int tot, int K,
         __syncthreads();
         return;
     }
-    unsigned long long x[8];
+    if (w * 512 < tot) {  // a segment wholly past tot holds no key: no sort
+        unsigned long long x[8];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        const int i = w * 512 + j * WAVE + lane;
-        x[j] = i < tot ? buf[i] : 0ull;
+        for (int j = 0; j < 8; ++j) {
+            const int i = w * 512 + j * WAVE + lane;
+            x[j] = i < tot ? buf[i] : 0ull;
+        }
+        wave_sort512_desc(x);
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            buf[w * 512 + j * WAVE + lane] = x[j];
     }
-    wave_sort512_desc(x);
-#pragma unroll
-    for (int j = 0; j < 8; ++j)
-        buf[w * 512 + j * WAVE + lane] = x[j];
     __syncthreads();
     const int nk = min(K, tot);
     if (threadIdx.x == 0) {
+        // segment q's keys (all nonzero) lead it after the sort: its head is
+        // past them once q 512 + h[q] reaches tot
         int h[4] = {0, 0, 0, 0};
         for (int r = 0; r < nk; ++r) {
             int best = 0;
-            unsigned long long bv = h[0] < 512 ? buf[h[0]] : 0ull;
+            unsigned long long bv = h[0] < min(512, tot) ? buf[h[0]] : 0ull;
 #pragma unroll
             for (int q = 1; q < 4; ++q) {
-                const unsigned long long v = h[q] < 512 ? buf[q * 512 + h[q]] : 0ull;
+                const unsigned long long v =
+                    h[q] < min(512, tot - q * 512) ? buf[q * 512 + h[q]] : 0ull;
                 if (v > bv) {
                     bv = v;
                     best = q;
