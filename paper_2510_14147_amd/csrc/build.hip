@@ -626,8 +626,8 @@ __device__ __forceinline__ void wave_sort512_desc(unsigned long long (&x)[8])
 
 // buf[0..tot) (tot <= SEL_BUF = 4 x 512) to its min(K, tot) largest keys in
 // descending order at buf[0..): every wave sorts a 512-key segment in
-// registers and writes it back, then one thread merges the four sorted
-// segments.  out: LDS of MAX_K keys.  Called by the whole work-group.
+// registers and writes it back, then the four sorted segments are merged by
+// rank.  out: LDS of MAX_K keys.  Called by the whole work-group.
 __device__ void topk_sorted(unsigned long long *buf, int tot, int K,
                             unsigned long long *out)
 {
@@ -664,25 +664,37 @@ __device__ void topk_sorted(unsigned long long *buf, int tot, int K,
     }
     __syncthreads();
     const int nk = min(K, tot);
-    if (threadIdx.x == 0) {
-        // segment q's keys (all nonzero) lead it after the sort: its head is
-        // past them once q 512 + h[q] reaches tot
-        int h[4] = {0, 0, 0, 0};
-        for (int r = 0; r < nk; ++r) {
-            int best = 0;
-            unsigned long long bv = h[0] < min(512, tot) ? buf[h[0]] : 0ull;
+    // Merge by rank: the best nk keys are among the first nk of each sorted
+    // segment (whose own keys, all nonzero, lead it); a key's rank in the
+    // union is its index plus the keys above it in the other segments
+    // (binary search; keys are distinct), and the keys ranked below nk go
+    // to out.
+    int cnt[4];
 #pragma unroll
-            for (int q = 1; q < 4; ++q) {
-                const unsigned long long v =
-                    h[q] < min(512, tot - q * 512) ? buf[q * 512 + h[q]] : 0ull;
-                if (v > bv) {
-                    bv = v;
-                    best = q;
-                }
+    for (int q = 0; q < 4; ++q)
+        cnt[q] = min(nk, max(0, min(512, tot - q * 512)));
+    for (int c = threadIdx.x; c < 4 * nk; c += SEL_T) {
+        const int q = c / nk, i = c % nk;
+        if (i >= cnt[q])
+            continue;
+        const unsigned long long v = buf[q * 512 + i];
+        int rank = i;
+#pragma unroll
+        for (int o = 0; o < 4; ++o) {
+            if (o == q)
+                continue;
+            int lo = 0, hi = cnt[o];  // keys of segment o above v: [0, lo)
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (buf[o * 512 + mid] > v)
+                    lo = mid + 1;
+                else
+                    hi = mid;
             }
-            out[r] = bv;
-            ++h[best];
+            rank += lo;
         }
+        if (rank < nk)
+            out[rank] = v;
     }
     __syncthreads();
     for (int r = threadIdx.x; r < nk; r += SEL_T)
