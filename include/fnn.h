@@ -309,6 +309,23 @@ int fnn_mlp_forward(const float *params, const float *X, int64_t n, float *Y);
 int fnn_mlp_loss_grad(const float *params, const float *X, const float *T,
                       int64_t n, float *grad, double *loss);
 
+/* Allocation-free variant of fnn_mlp_loss_grad, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same loss and gradient; params, X, T,
+ * grad and *loss are all DEVICE pointers (loss: one double, the mean loss),
+ * caller-owned.  Nothing is allocated and nothing waits on the stream: the
+ * work is enqueued on the bound stream and the results are valid once it
+ * completes.  Partial sums live in a fixed per-device array of the library
+ * (5.5 MB, held until the process ends): at most 256 work-groups, each
+ * owning one row of partial gradients and one partial loss, then reduced in
+ * a fixed order, so repeated calls on the same input give identical bits.
+ * Every call on a device shares that array, so calls that overlap on one
+ * device (two streams, two threads) race: serialize them.  n must be at
+ * most FNN_NOALLOC_MAX_SAMPLES, else FNN_EINVAL. */
+#define FNN_NOALLOC_MAX_SAMPLES (((int64_t)1) << 31)
+int fnn_mlp_loss_grad_noalloc(const float *params, const float *X, const float *T,
+                              int64_t n, float *grad, double *loss);
+
 /* Train in place with Adam (device params, X, T): `epochs` passes over a
  * seeded shuffle in batches of `batch`; epoch_loss (host, may be NULL)
  * receives the mean loss of each epoch. */

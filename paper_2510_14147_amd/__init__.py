@@ -155,6 +155,7 @@ def lib():
         L.fnn_mlp_forward.argtypes = [vp, vp, i64, vp]
         L.fnn_mlp_loss_grad.argtypes = [vp, vp, vp, i64, vp,
                                         ctypes.POINTER(ctypes.c_double)]
+        L.fnn_mlp_loss_grad_noalloc.argtypes = [vp, vp, vp, i64, vp, vp]
         L.fnn_mlp_train.argtypes = [vp, vp, vp, i64, i32, i32, ctypes.c_float,
                                     ctypes.c_uint64, vp]
         _lib = L
@@ -470,6 +471,22 @@ def fnn_mlp_loss_grad(params, X, T):
     _check(lib().fnn_mlp_loss_grad(_ptr(params), _ptr(X), _ptr(T), X.shape[0],
                                    _ptr(g), ctypes.byref(loss)))
     return loss.value, g
+
+
+def fnn_mlp_loss_grad_noalloc(params, X, T, grad=None, loss=None):
+    """The allocation-free gradient entry point: grad (5378 floats) and loss
+    (one float64) are caller-provided cuda tensors (allocated here when not
+    given); returns (loss tensor, grad tensor) without waiting on the
+    stream."""
+    torch = _torch()
+    if grad is None:
+        grad = torch.empty(MLP_NPARAMS, dtype=torch.float32, device=X.device)
+    if loss is None:
+        loss = torch.empty(1, dtype=torch.float64, device=X.device)
+    _bind_stream()
+    _check(lib().fnn_mlp_loss_grad_noalloc(_ptr(params), _ptr(X), _ptr(T), X.shape[0],
+                                           _ptr(grad), _ptr(loss)))
+    return loss, grad
 
 
 def fnn_mlp_train(params, X, T, epochs=4, batch=4096, lr=1e-3, seed=0):

@@ -552,6 +552,22 @@ int fnn_mlp_loss_grad(const float *params, const float *X, const float *T,
     }
 }
 
+int fnn_mlp_loss_grad_noalloc(const float *params, const float *X, const float *T,
+                              int64_t n, float *grad, double *loss)
+{
+    if (!params || !grad || !loss || n < 0 || (n > 0 && (!X || !T)))
+        return set_err(FNN_EINVAL, "bad argument");
+    if (n > FNN_NOALLOC_MAX_SAMPLES)
+        return set_err(FNN_EINVAL, "fnn_mlp_loss_grad_noalloc: n = " + std::to_string(n) +
+                                       " exceeds FNN_NOALLOC_MAX_SAMPLES");
+    try {
+        mlp_loss_grad_noalloc(params, X, T, n, grad, loss, current_stream());
+        return FNN_OK;
+    } catch (const Error &e) {
+        return set_err(e.code, e.msg);
+    }
+}
+
 int fnn_mlp_train(float *params, const float *X, const float *T, int64_t n,
                   int32_t epochs, int32_t batch, float lr, uint64_t seed,
                   double *epoch_loss)

@@ -27,6 +27,12 @@ void mlp_forward(const float *theta, const float *X, long long n, float *Y,
                  hipStream_t s);
 double mlp_loss_grad(const float *theta, const float *X, const float *T,
                      long long n, float *grad, Scratch &S);
+// Allocation-free full-batch gradient: partial sums in a fixed device array
+// (mlp_noalloc_scratch_bytes), grad and *loss (device) written in a fixed
+// summation order.
+void mlp_loss_grad_noalloc(const float *theta, const float *X, const float *T,
+                           long long n, float *grad, double *loss, hipStream_t s);
+size_t mlp_noalloc_scratch_bytes();
 void mlp_train(float *theta, const float *X, const float *T, long long n,
                int epochs, int batch, float lr, unsigned long long seed,
                double *epoch_loss, Scratch &S);

@@ -12,6 +12,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "learn.h"
@@ -157,16 +158,25 @@ k_mlp_fwd(const float *__restrict__ th, const float *__restrict__ X, long long n
 }
 
 // Gradient of the loss over the samples idx[0..B) (or 0..B if idx is
-// NULL), added to grad; the loss sum is added to *loss.  A block takes 32
-// samples: each thread runs one sample forward and backward into LDS, then
-// the block reduces the outer products parameter-major.
+// NULL).  A block takes 32 samples at a time: each thread runs one sample
+// forward and backward into LDS, then the block reduces the outer products
+// parameter-major.  PART = false: sums are added to grad and *loss with
+// atomics.  PART = true: work-group b owns row b of grad ([gridDim][NPAR])
+// and loss[b], written without atomics (thread t always owns the same
+// parameters), for a fixed-order reduction afterwards.
 constexpr int GS = 32;
+template <bool PART>
 __global__ void __launch_bounds__(256)
 k_mlp_grad(const float *__restrict__ th, const float *__restrict__ X,
            const float *__restrict__ T, const int32_t *__restrict__ idx,
            long long B, float invB, float *__restrict__ grad,
            double *__restrict__ loss)
 {
+    if (PART) {
+        grad += (size_t)blockIdx.x * MLP_NPAR;
+        for (int p = threadIdx.x; p < MLP_NPAR; p += blockDim.x)
+            grad[p] = 0.f;
+    }
     __shared__ float w[MLP_NPAR];
     __shared__ float sx[GS][MLP_F], sh1[GS][MLP_H], sh2[GS][MLP_H],
         sg1[GS][MLP_H], sg2[GS][MLP_H], sgy[GS][MLP_O];
@@ -256,14 +266,50 @@ k_mlp_grad(const float *__restrict__ th, const float *__restrict__ X,
                 for (int s = 0; s < ns; ++s)
                     g += sgy[s][o];
             }
-            if (g != 0.f)
+            if (PART)
+                grad[p] += g;
+            else if (g != 0.f)
                 atomicAdd(&grad[p], g);
         }
         __syncthreads();
     }
     lsum = wave_sum(lsum);
-    if ((threadIdx.x & (WAVE - 1)) == 0 && lsum != 0.0)
+    if (PART) {
+        __shared__ double wl[256 / WAVE];
+        if ((threadIdx.x & (WAVE - 1)) == 0)
+            wl[threadIdx.x / WAVE] = lsum;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double t = 0.0;
+            for (int w = 0; w < (int)(blockDim.x / WAVE); ++w)
+                t += wl[w];
+            loss[blockIdx.x] = t;
+        }
+    } else if ((threadIdx.x & (WAVE - 1)) == 0 && lsum != 0.0) {
         atomicAdd(loss, lsum);
+    }
+}
+
+// Fixed-order sum of the per-work-group partials: grad[p] = sum over g of
+// part[g][p]; *loss = (sum over g of ploss[g]) / n.
+__global__ void k_mlp_grad_reduce(const float *__restrict__ part,
+                                  const double *__restrict__ ploss, int groups,
+                                  long long n, float *__restrict__ grad,
+                                  double *__restrict__ loss)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < MLP_NPAR) {
+        float g = 0.f;
+        for (int k = 0; k < groups; ++k)
+            g += part[(size_t)k * MLP_NPAR + p];
+        grad[p] = g;
+    }
+    if (p == 0) {
+        double t = 0.0;
+        for (int k = 0; k < groups; ++k)
+            t += ploss[k];
+        *loss = n > 0 ? t / (double)n : 0.0;
+    }
 }
 
 // Adam (Kingma & Ba), bias-corrected; step counts from 1.
@@ -317,8 +363,8 @@ double mlp_loss_grad(const float *theta, const float *X, const float *T,
     fill(loss, 0.0, 1, s);
     fill(grad, 0.f, MLP_NPAR, s);
     if (n > 0)
-        FNN_LAUNCH(k_mlp_grad, dim3(grid_for(n, GS)), dim3(256), 0, s, theta, X,
-                   T, (const int32_t *)nullptr, n, 1.0f / (float)n, grad, loss);
+        FNN_LAUNCH(k_mlp_grad<false>, dim3(grid_for(n, GS)), dim3(256), 0, s, theta,
+                   X, T, (const int32_t *)nullptr, n, 1.0f / (float)n, grad, loss);
     return read_scalar(loss, s) / (double)std::max<long long>(n, 1);
 }
 
@@ -348,9 +394,9 @@ void mlp_train(float *theta, const float *X, const float *T, long long n,
         for (long long b0 = 0; b0 < n; b0 += batch) {
             const long long B = std::min<long long>(batch, n - b0);
             fill(g, 0.f, MLP_NPAR, s);
-            FNN_LAUNCH(k_mlp_grad, dim3(grid_for(B, GS)), dim3(256), 0, s, theta,
-                       X, T, (const int32_t *)(perm + b0), B, 1.0f / (float)B, g,
-                       loss);
+            FNN_LAUNCH(k_mlp_grad<false>, dim3(grid_for(B, GS)), dim3(256), 0, s,
+                       theta, X, T, (const int32_t *)(perm + b0), B, 1.0f / (float)B,
+                       g, loss);
             ++step;
             const float c1 = 1.f - powf(b1, (float)step);
             const float c2 = 1.f - powf(b2, (float)step);
@@ -361,6 +407,62 @@ void mlp_train(float *theta, const float *X, const float *T, long long n,
             epoch_loss[ep] = read_scalar(loss, s) / (double)n;
     }
     FNN_HIP(hipStreamSynchronize(s));
+}
+
+// ------------------------------------------- allocation-free gradient --
+//
+// fnn_mlp_loss_grad_noalloc keeps its partial sums in a fixed device array
+// instead of scratch memory from the pool: NA_GROUPS rows of per-work-group
+// partial gradients, then NA_GROUPS partial losses (doubles).  Host code
+// never passes `scratch` itself to a kernel (in host code the name is a
+// stand-in, not a device address); it uses the address that
+// hipGetSymbolAddress returns, looked up once per device.
+constexpr int NA_GROUPS = 256;
+constexpr size_t NA_GRAD_BYTES = sizeof(float) * (size_t)NA_GROUPS * MLP_NPAR;
+constexpr size_t NA_BYTES = NA_GRAD_BYTES + sizeof(double) * NA_GROUPS;
+static_assert(NA_GRAD_BYTES % alignof(double) == 0, "loss partials alignment");
+static __device__ __align__(256) unsigned char scratch[NA_BYTES];
+
+static std::mutex g_na_mu;
+static void *g_na_ptr[64] = {nullptr};
+
+static unsigned char *noalloc_scratch()
+{
+    int dev = 0;
+    FNN_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64)
+        fail(FNN_EUNSUPPORTED, "device id %d", dev);
+    std::lock_guard<std::mutex> lk(g_na_mu);
+    if (!g_na_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            fail(FNN_EHIP, "hipGetSymbolAddress(scratch) failed: %s",
+                 hipGetErrorString(e));
+        g_na_ptr[dev] = p;
+    }
+    return static_cast<unsigned char *>(g_na_ptr[dev]);
+}
+
+size_t mlp_noalloc_scratch_bytes() { return NA_BYTES; }
+
+void mlp_loss_grad_noalloc(const float *theta, const float *X, const float *T,
+                           long long n, float *grad, double *loss, hipStream_t s)
+{
+    unsigned char *base = noalloc_scratch();
+    float *part = reinterpret_cast<float *>(base);
+    double *ploss = reinterpret_cast<double *>(base + NA_GRAD_BYTES);
+    // every work-group clears and fills its own row, so no clear is needed
+    // before the launch; the reduction reads exactly `groups` rows
+    const long long want = cdiv(std::max<long long>(n, 1), GS);
+    const int groups = (int)std::min<long long>(want, NA_GROUPS);
+    if (groups < 1 || groups > NA_GROUPS)
+        fail(FNN_EINTERNAL, "gradient work-groups out of range");
+    FNN_LAUNCH(k_mlp_grad<true>, dim3(groups), dim3(256), 0, s, theta, X, T,
+               (const int32_t *)nullptr, n, n > 0 ? 1.0f / (float)n : 0.f, part,
+               ploss);
+    FNN_LAUNCH(k_mlp_grad_reduce, dim3(grid_for(MLP_NPAR, 256)), dim3(256), 0, s,
+               part, ploss, groups, n, grad, loss);
 }
 
 void tree_aux(fnn_tree *T, Scratch &S)
