@@ -124,15 +124,72 @@ def cpu_baseline(x, metric, eps, rows: int, seed: int = 7):
     rp, _, _ = O.bruteforce(x, mid, eps, rows=sample)
     dt = time.perf_counter() - t0
     edges = int(rp[-1])
+    cores = _cores()
+    out = {"value": edges / dt, "unit": "edges/s", "cores": cores,
+           "kind": "oracle",
+           "sample": f"{sample.size} seeded rows vs all {x.shape[0]} points, "
+                     f"FP64 brute force ({edges} edges in {dt:.2f} s); "
+                     f"pair evals/s {sample.size * x.shape[0] / dt:.3e}",
+           "cpu_model": _cpu_model()}
+    # one core: the first rows of the same sample, one thread
+    k1 = max(1, sample.size // 30)
+    if _omp_threads(1):
+        try:
+            t0 = time.perf_counter()
+            rp1, _, _ = O.bruteforce(x, mid, eps, rows=sample[:k1])
+            d1 = time.perf_counter() - t0
+        finally:
+            _omp_threads(None)
+        out["single_thread"] = {"edges_per_s": int(rp1[-1]) / d1,
+                                "pair_evals_per_s": k1 * x.shape[0] / d1,
+                                "rows": int(k1), "s": round(d1, 3)}
+    return out
+
+
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _omp_threads(k: int | None):
+    """Set the OpenMP thread count of the oracle's runtime (None: restore
+    the default).  Returns False when the runtime cannot be reached."""
+    import ctypes
+    try:
+        g = ctypes.CDLL("libgomp.so.1")
+    except OSError:
+        return False
+    g.omp_set_num_threads(int(k if k else _cores()))
+    return True
+
+
+def _cores() -> int:
     cores = len(os.sched_getaffinity(0))
     omp = os.environ.get("OMP_NUM_THREADS")
     if omp:
         cores = min(cores, int(omp))
-    return {"value": edges / dt, "unit": "edges/s", "cores": cores,
-            "kind": "oracle",
-            "sample": f"{sample.size} seeded rows vs all {x.shape[0]} points, "
-                      f"FP64 brute force ({edges} edges in {dt:.2f} s); "
-                      f"pair evals/s {sample.size * x.shape[0] / dt:.3e}"}
+    return cores
+
+
+def cpu_cover_tree(x, metric, eps_scaled, n: int):
+    """The oracle's own cover tree (Algorithms 1-3, FP64, as it stands) on
+    the first n points: build and all-points query timed apart."""
+    from oracle import oracle as O
+    mid = {"l2": 0, "angular": 1, "hamming": 2, "levenshtein": 3}[metric]
+    xs = np.ascontiguousarray(x[:n])
+    t0 = time.perf_counter()
+    t = O.tree_build(xs, mid, zeta=64)
+    t1 = time.perf_counter()
+    rp, _, _ = O.tree_query(xs, mid, eps_scaled, t)
+    t2 = time.perf_counter()
+    return {"n": int(n), "eps": eps_scaled, "build_s": round(t1 - t0, 3),
+            "query_s": round(t2 - t1, 3), "edges": int(rp[-1]),
+            "edges_per_s": int(rp[-1]) / (t2 - t0)}
 
 
 def measured_traffic(kernel: str, workload: str):
@@ -219,6 +276,8 @@ def main():
                     help="filter on leading principal coordinates: 0 automatic, "
                          "-1 off, else their number (multiple of 16)")
     ap.add_argument("--cpu-rows", type=int, default=1500)
+    ap.add_argument("--cpu-tree-n", type=int, default=20000,
+                    help="points of the oracle cover-tree timing (0: skip)")
     ap.add_argument("--c5-clouds", type=int, default=0,
                     help="use only the first K clouds of c5 (0: all 256)")
     ap.add_argument("--tune", action="store_true",
@@ -226,7 +285,12 @@ def main():
                          "tuned options")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true",
-                    help="skip the plain FP32 comparison step")
+                    help="skip the plain FP32 comparison steps")
+    ap.add_argument("--plain-steps", type=int, default=2,
+                    help="timed plain FP32 steps (after one untimed step)")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="c2a: skip the learned-schedule and ~500-neighbour rows")
+    ap.add_argument("--extra-steps", type=int, default=3)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the epsilon-graph path has no "
@@ -319,13 +383,17 @@ def main():
                                         proj=o.get("proj", 0))
         return tree, g
 
-    def step():
+    kept = []
+
+    def step(keep=False):
         res = []
         for (xd, off, m, e, d, _), o in zip(jobs, opts):
             tree, g = run_job(xd, off, m, e, o, o["precision"])
             # the precision the query ran with (the library resolves auto)
             used = INV_PREC[int(g.stats["precision_used"])]
             res.append((tree.stats, g.stats, g.nnz, d, used))
+            if keep:
+                kept.append(g)
             del tree, g
         return res
 
@@ -341,7 +409,7 @@ def main():
     for i in range(args.steps):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        r = step()
+        r = step(keep=(i == args.steps - 1))
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         stats.append(r)
@@ -352,7 +420,10 @@ def main():
     last = stats[-1]
     nnz = sum(x[2] for x in last)
     agg = lambda k, j: sum(x[j][k] for x in last)  # noqa: E731
-    evals = agg("build_dist_evals", 0) + agg("traverse_tests", 1) + 2 * agg("tile_pairs", 1)
+    # every metric evaluation once per unordered pair: build, traversal
+    # tests, exact leaf / survivor evaluations; the MFMA filter's screens
+    # are reported apart
+    evals = agg("build_dist_evals", 0) + agg("traverse_tests", 1) + agg("tile_pairs", 1)
     value = nnz / (ms / 1e3)
     # dominant kernel: that of the job with the longest count pass
     dom = max(last, key=lambda x: x[1]["count_ms"])
@@ -375,6 +446,7 @@ def main():
                    "nnz": int(nnz),
                    "mean_neighbors": nnz / n_all, "calls": len(jobs)},
         "dist_evals_per_s": evals / (ms / 1e3),
+        "filter_screens_per_s": agg("filter_pairs", 1) / (ms / 1e3),
         "phases_ms": {"build": agg("build_ms", 0), "traverse": agg("traverse_ms", 1),
                       "count": agg("count_ms", 1), "scan": agg("scan_ms", 1),
                       "fill": agg("fill_ms", 1), "sort": agg("sort_ms", 1)},
@@ -397,27 +469,82 @@ def main():
     elif metric == "levenshtein":
         out["dtype"] = "u64 (bit-parallel edit distance)"
     if not args.no_plain and any(p != "fp32" for p in precs):
-        # one step of the same workload on the plain FP32 tiles, for the
-        # MFMA-vs-plain ratio (the edge counts must agree)
+        # the same workload on the plain FP32 tiles, for the MFMA-vs-plain
+        # ratio: one untimed step, then the mean of --plain-steps; the last
+        # step's CSRs must equal the MFMA path's entry for entry
+        def plain_step(keep=False):
+            res, gs = [], []
+            for (xd, off, m, e, d, _), o in zip(jobs, opts):
+                tree, g = run_job(xd, off, m, e, o, "fp32")
+                res.append((tree.stats, g.stats, g.nnz, d, "fp32"))
+                if keep:
+                    gs.append(g)
+                del tree, g
+            return res, gs
+        plain_step()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        pnnz = 0
-        for (xd, off, m, e, d, _), o in zip(jobs, opts):
-            tree, g = run_job(xd, off, m, e, o, "fp32")
-            pnnz += g.nnz
-            del tree, g
+        for i in range(args.plain_steps):
+            pres, pgs = plain_step(keep=(i == args.plain_steps - 1))
         torch.cuda.synchronize()
-        pms = 1e3 * (time.perf_counter() - t0)
-        if pnnz != nnz:
-            raise SystemExit(f"plain FP32 and MFMA paths disagree: {pnnz} vs {nnz} edges")
-        out["plain_fp32"] = {"ms_per_step": pms, "value": nnz / (pms / 1e3),
-                             "speedup_of_value": pms / ms}
+        pms = 1e3 * (time.perf_counter() - t0) / args.plain_steps
+        pnnz = sum(x[2] for x in pres)
+        for ga, gb in zip(kept, pgs):
+            same = (ga.nnz == gb.nnz and torch.equal(ga.row_ptr, gb.row_ptr)
+                    and torch.equal(ga.col, gb.col)
+                    and torch.equal(ga.dist.view(torch.int32), gb.dist.view(torch.int32)))
+            if not same:
+                raise SystemExit("plain FP32 and MFMA paths give different CSRs")
+        del pgs
+        pdom = max(pres, key=lambda x: x[1]["count_ms"])
+        out["plain_fp32"] = {"ms_per_step": pms, "value": pnnz / (pms / 1e3),
+                             "speedup_of_value": pms / ms, "steps": args.plain_steps,
+                             "warmup": 1, "csr_identical": True,
+                             "roofline": (roofline(pdom[3], "fp32", pdom[1], desc)
+                                          if metric in ("l2", "angular") else None)}
         print(f"[bench] plain fp32 step: {pms:.1f} ms", file=sys.stderr, flush=True)
+    kept.clear()
+    if args.workload == "c2a" and not args.no_extra:
+        # the same points at the ~500-neighbour radius, both schedules, and
+        # the learned schedule at the headline radius
+        xd, _, m, _, d, p = jobs[0]
+        extra = {}
+        for key, e, sched in (("c2a_learned", eps, "learned"),
+                              ("c2b_two_pass", W["c2"]["eps"][1], "two_pass"),
+                              ("c2b_learned", W["c2"]["eps"][1], "learned")):
+            o = dict(opts[0], sched=sched)
+            run_job(xd, None, m, e, o, p)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.extra_steps):
+                tree, g = run_job(xd, None, m, e, o, p)
+                st, tst, nz = g.stats, tree.stats, g.nnz
+                del tree, g
+            torch.cuda.synchronize()
+            ems = 1e3 * (time.perf_counter() - t0) / args.extra_steps
+            used = INV_PREC[int(st["precision_used"])]
+            extra[key] = {"eps": e, "sched": sched, "nnz": int(nz),
+                          "mean_neighbors": nz / n_all, "ms_per_step": ems,
+                          "value": nz / (ems / 1e3), "steps": args.extra_steps,
+                          "phases_ms": {"build": tst["build_ms"], "count": st["count_ms"],
+                                        "fill": st["fill_ms"], "sort": st["sort_ms"]},
+                          "filter_passes": 1 + int(st["overflow_rows"]) if used != "fp32" else 0,
+                          "roofline": roofline(d, used, st, desc)}
+            if sched == "learned":
+                extra[key]["pred_mae_log1p_degree"] = st["pred_mae"]
+                extra[key]["pred_sum_ratio"] = st["pred_sum_ratio"]
+            print(f"[bench] {key}: {ems:.1f} ms nnz={nz}", file=sys.stderr, flush=True)
+        out["extra"] = extra
     if not args.no_cpu:
         if groups:
             out["cpu_baseline"] = cpu_baseline_c5(groups, args.cpu_rows)
         else:
             out["cpu_baseline"] = cpu_baseline(x, metric, eps, args.cpu_rows)
+            if args.workload in ("c2a", "c2b") and args.cpu_tree_n > 0:
+                # the oracle's cover tree (Algorithms 1-3) on a prefix it
+                # finishes in seconds, at the radius calibrated for 50K points
+                out["cpu_baseline"]["cover_tree"] = cpu_cover_tree(
+                    x, metric, W["c2_50k"]["eps"][0], args.cpu_tree_n)
     print(json.dumps(out), flush=True)
 
 

@@ -39,8 +39,9 @@ extern "C" {
  * the metrics the paper names; "cosine" is taken as the angle, which is a
  * metric, and edit distance as unit-cost Levenshtein). */
 typedef enum {
-    FNN_L2 = 0,          /* float32 rows [n x dim]                            */
-    FNN_ANGULAR = 1,     /* float32 rows [n x dim], no zero row               */
+    FNN_L2 = 0,          /* float32 rows [n x dim]; finite, |x| <= B(dim) =   */
+                         /* min(1e16, sqrt(1e37 / dim)), else EUNSUPPORTED    */
+    FNN_ANGULAR = 1,     /* float32 rows [n x dim], no zero row, same bound   */
     FNN_HAMMING = 2,     /* uint64 rows [n x dim/64]; dim = bits, % 64 == 0   */
     FNN_LEVENSHTEIN = 3  /* uint8 rows [n x dim]; dim = row stride in bytes,  */
                          /* symbols < 32, padded with 0xFF; length = index of */
@@ -111,7 +112,15 @@ typedef struct fnn_options {
                           /* if below the padded dim, else none (default);   */
                           /* -1 = none; 16..128 in steps of 16 = that K;     */
                           /* else EINVAL                                     */
-    int32_t reserved[5];
+    int32_t list_cap;     /* initial capacity (entries) of the MFMA filter's */
+                          /* survivor list and of the plain tiles' edge     */
+                          /* list; 0 = automatic (default).  A list that    */
+                          /* overflows is redone: the filter runs again     */
+                          /* into a list sized from its count, the tiles    */
+                          /* fall back to the count / fill pair of passes.  */
+                          /* Results never depend on it; small values force */
+                          /* those paths (tests).                           */
+    int32_t reserved[4];
 } fnn_options;
 
 typedef struct fnn_tree fnn_tree;  /* opaque; device-resident cover tree */
@@ -160,6 +169,11 @@ typedef struct fnn_stats {
                               /* the coordinates themselves)                 */
     double proj_captured;     /* their share of the variance                  */
     int64_t precision_used;   /* fnn_precision the query ran with            */
+    int64_t landmark_cells;   /* landmark mode: Voronoi cells                */
+    int64_t landmark_rows;    /* landmark mode: cell members + ghosts        */
+    double landmark_partition_ms; /* centres, cells, ghosts, gathered rows    */
+    double landmark_forest_ms;    /* per-cell forest build and self-join      */
+    double landmark_merge_ms;     /* pairs kept once, rows mapped and sorted  */
     double reserved[1];
 } fnn_stats;
 
@@ -250,16 +264,42 @@ int fnn_autotune(const void *points, const int64_t *offsets, int32_t nclouds,
                  const fnn_options *base, int32_t reps, fnn_tune_result *out);
 void fnn_autotune_clear(void);
 
+/* ---- landmark mode (Section IV-D, Algorithm 5; Section IV-E, Lemma 1 and
+ * Algorithm 6), on one GPU ----------------------------------------------------
+ * The same epsilon-graph as fnn_tree_build + fnn_eps_graph, assembled the
+ * way the paper's landmark algorithm does: `ncells` centres drawn from the
+ * points (seeded), the Voronoi cells of those centres, each cell's
+ * eps-ghosts (points of other cells p with d(p, c_i) <= d(p, C) + 2 eps,
+ * Lemma 1; widened by the FP32 rounding bound, so no ghost is missed), one
+ * cover tree per cell over its members and ghosts (built and queried as one
+ * batch), and every ordered pair kept once.  points / n / dim / metric as in
+ * fnn_tree_build (device, caller-owned, read during the call); eps as in
+ * fnn_eps_graph; ncells >= 1 (capped at n); opt applies to the per-cell
+ * build and query (traces are not available: FNN_EUNSUPPORTED).  *out: the
+ * symmetric CSR over the input indices, identical to fnn_eps_graph's.
+ * Stats: landmark_cells, landmark_rows (members + ghosts), phase times.
+ * FNN_EUNSUPPORTED when members + ghosts exceed 2^30 - 1 rows, or when a
+ * row is not a multiple of 4 bytes (strings: dim % 4 != 0). */
+int fnn_landmark_eps_graph(const void *points, int64_t n, int32_t dim,
+                           fnn_metric metric, double eps, int32_t ncells,
+                           uint64_t seed, const fnn_options *opt, fnn_csr **out);
+
 /* Release a fnn_tree* or fnn_csr* (NULL is ignored). */
 void fnn_free(void *handle);
 
 /* Stream for this thread's later calls (a hipStream_t; NULL = null stream). */
 int fnn_set_stream(void *stream);
 
-/* Optional allocator for the memory handed back to the caller (tree arrays
- * and CSR arrays).  alloc returns a device pointer or NULL; free releases it.
- * Scratch memory always comes from the library's stream-ordered pool.
- * Passing NULL functions restores hipMalloc / hipFree. */
+/* Optional device allocator (problem statement: the caller owns the memory
+ * system).  Once set, every device buffer of a call comes from it: the arrays
+ * handed back (tree and CSR arrays, released by fnn_free) and the call's
+ * scratch chunks (taken in pieces of at least 256 MB and returned before the
+ * call returns, after the stream has drained).  alloc returns a device
+ * pointer (256-byte aligned) or NULL; NULL makes the call fail with
+ * FNN_ENOMEM and free everything it took.  Not routed through it: the
+ * installed cost model's 21 KB device copy and the fixed array of
+ * fnn_mlp_loss_grad_noalloc.  Passing NULL functions restores hipMalloc /
+ * hipFree and the library's own cache of scratch chunks. */
 typedef void *(*fnn_alloc_fn)(size_t bytes, void *ctx);
 typedef void (*fnn_free_fn)(void *ptr, void *ctx);
 int fnn_set_allocator(fnn_alloc_fn alloc, fnn_free_fn free_, void *ctx);

@@ -42,7 +42,8 @@ class fnn_options(ctypes.Structure):
                 ("sched", ctypes.c_int32), ("validate", ctypes.c_int32),
                 ("kmax", ctypes.c_int32), ("trace", ctypes.c_int32),
                 ("slack_pct", ctypes.c_int32), ("graph_passes", ctypes.c_int32),
-                ("proj", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+                ("proj", ctypes.c_int32), ("list_cap", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
 
 
 class fnn_tune_result(ctypes.Structure):
@@ -72,7 +73,12 @@ class fnn_stats(ctypes.Structure):
     _fields_ = ([(k, ctypes.c_int64) for k in _STAT_I64] +
                 [(k, ctypes.c_double) for k in _STAT_F64] +
                 [("proj_dim", ctypes.c_int64), ("proj_captured", ctypes.c_double),
-                 ("precision_used", ctypes.c_int64), ("reserved", ctypes.c_double * 1)])
+                 ("precision_used", ctypes.c_int64),
+                 ("landmark_cells", ctypes.c_int64), ("landmark_rows", ctypes.c_int64),
+                 ("landmark_partition_ms", ctypes.c_double),
+                 ("landmark_forest_ms", ctypes.c_double),
+                 ("landmark_merge_ms", ctypes.c_double),
+                 ("reserved", ctypes.c_double * 1)])
 
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -132,6 +138,10 @@ def lib():
         L.fnn_eps_query.argtypes = [vp, vp, i64, ctypes.c_double,
                                     ctypes.POINTER(fnn_options),
                                     ctypes.POINTER(ctypes.POINTER(fnn_csr))]
+        L.fnn_landmark_eps_graph.argtypes = [vp, i64, i32, ctypes.c_int, ctypes.c_double,
+                                             i32, ctypes.c_uint64,
+                                             ctypes.POINTER(fnn_options),
+                                             ctypes.POINTER(ctypes.POINTER(fnn_csr))]
         L.fnn_tree_build_batch.argtypes = [vp, ctypes.POINTER(i64), i32, i32,
                                            ctypes.c_int, ctypes.POINTER(fnn_options),
                                            ctypes.POINTER(vp)]
@@ -191,7 +201,9 @@ def _stats(handle) -> dict:
     s = fnn_stats()
     _check(lib().fnn_get_stats(handle, ctypes.byref(s)))
     return {k: getattr(s, k) for k in _STAT_I64 + _STAT_F64 +
-            ["proj_dim", "proj_captured", "precision_used"]}
+            ["proj_dim", "proj_captured", "precision_used", "landmark_cells",
+             "landmark_rows", "landmark_partition_ms", "landmark_forest_ms",
+             "landmark_merge_ms"]}
 
 
 class Tree:
@@ -313,7 +325,7 @@ def fnn_tree_build_batch(points, offsets, metric: str = "l2", zeta=None,
 
 def fnn_eps_graph_batch(tree: Tree, eps, precision="fp32", sched="two_pass",
                         validate=False, trace=False, slack_pct=None,
-                        proj=None) -> Graph:
+                        proj=None, list_cap=None) -> Graph:
     """Per-cloud thresholds ``eps[c]``; one block-diagonal CSR over all rows."""
     if sched == "learned" and not _model_set and os.path.exists(COST_MODEL_PATH):
         fnn_set_cost_model(load_cost_model())
@@ -321,7 +333,7 @@ def fnn_eps_graph_batch(tree: Tree, eps, precision="fp32", sched="two_pass",
     _bind_stream()
     out = ctypes.POINTER(fnn_csr)()
     o = _options(precision=precision, sched=sched, validate=int(validate),
-                 trace=int(trace), slack_pct=slack_pct, proj=proj)
+                 trace=int(trace), slack_pct=slack_pct, proj=proj, list_cap=list_cap)
     _check(lib().fnn_eps_graph_batch(
         tree.handle, e.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), e.size,
         ctypes.byref(o), ctypes.byref(out)))
@@ -386,15 +398,17 @@ def load_cost_model(path: str = COST_MODEL_PATH) -> np.ndarray:
 
 def fnn_eps_graph(tree: Tree, eps: float, precision="fp32",
                   sched="two_pass", validate=False, trace=False,
-                  slack_pct=None, proj=None) -> Graph:
+                  slack_pct=None, proj=None, list_cap=None) -> Graph:
     """proj: filter on leading principal coordinates (None / 0 automatic,
-    -1 off, else their number, a multiple of 16)."""
+    -1 off, else their number, a multiple of 16).  list_cap: initial
+    survivor / edge list capacity (None: automatic; small values force the
+    overflow paths)."""
     if sched == "learned" and not _model_set and os.path.exists(COST_MODEL_PATH):
         fnn_set_cost_model(load_cost_model())
     _bind_stream()
     out = ctypes.POINTER(fnn_csr)()
     o = _options(precision=precision, sched=sched, validate=int(validate),
-                 trace=int(trace), slack_pct=slack_pct, proj=proj)
+                 trace=int(trace), slack_pct=slack_pct, proj=proj, list_cap=list_cap)
     _check(lib().fnn_eps_graph_ex(tree.handle, float(eps), ctypes.byref(o),
                                   ctypes.byref(out)))
     return Graph(out)
@@ -415,6 +429,26 @@ def fnn_eps_query(tree: Tree, queries, eps: float, precision="fp32",
                  zeta=zeta, pack=pack, kmax=kmax)
     _check(lib().fnn_eps_query(tree.handle, ctypes.c_void_p(t.data_ptr()), t.shape[0],
                                float(eps), ctypes.byref(o), ctypes.byref(out)))
+    return Graph(out)
+
+
+def fnn_landmark_eps_graph(points, eps: float, ncells: int, metric: str = "l2",
+                           seed: int = 0, precision="fp32", sched="two_pass",
+                           zeta=None, pack=None, kmax=None, proj=None) -> Graph:
+    """The epsilon-graph by the landmark scheme: ``ncells`` seeded centres,
+    Voronoi cells, eps-ghosts (Lemma 1), one batched forest over cells +
+    ghosts, every ordered pair kept once.  Same CSR as fnn_eps_graph."""
+    if sched == "learned" and not _model_set and os.path.exists(COST_MODEL_PATH):
+        fnn_set_cost_model(load_cost_model())
+    m = METRICS[metric]
+    t, dim = _as_device_points(points, metric)
+    _bind_stream()
+    out = ctypes.POINTER(fnn_csr)()
+    o = _options(precision=precision, sched=sched, zeta=zeta, pack=pack, kmax=kmax,
+                 proj=proj)
+    _check(lib().fnn_landmark_eps_graph(ctypes.c_void_p(t.data_ptr()), t.shape[0], dim, m,
+                                        float(eps), int(ncells), ctypes.c_uint64(seed),
+                                        ctypes.byref(o), ctypes.byref(out)))
     return Graph(out)
 
 

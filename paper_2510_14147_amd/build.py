@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 SRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libfnn.so")
 SOURCES = ["runtime.hip", "build.hip", "query.hip", "gram.hip", "learn.hip", "tune.hip",
-           "api.hip"]
+           "landmark.hip", "api.hip"]
 
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

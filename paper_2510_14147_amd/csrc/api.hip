@@ -17,6 +17,9 @@ void build_tree(fnn_tree *T, const void *points, Scratch &S);
 fnn_tree *forest_pair(const fnn_tree *A, const fnn_tree *B, Scratch &S);
 void eps_graph(const fnn_tree *T, const double *eps, const Options &opt,
                fnn_csr *C, fnn_stats &st, Scratch &S, float **tf, float **tt);
+void landmark_graph(fnn_tree *hdr, const void *points, double eps, int m,
+                    uint64_t seed, const fnn_options *opt, fnn_csr *C,
+                    fnn_stats &st, Scratch &S);
 
 // The installed cost model: one device copy per device.
 static std::mutex g_model_mu;
@@ -87,6 +90,9 @@ Options read_options(const fnn_options *o)
         fail(FNN_EINVAL, "proj must be -1, 0 or a multiple of 16 up to 128 (got %d)",
              (int)o->proj);
     r.proj = o->proj;
+    if (o->list_cap < 0)
+        fail(FNN_EINVAL, "negative list_cap");
+    r.list_cap = o->list_cap;
     return r;
 }
 
@@ -142,6 +148,29 @@ int fnn_set_allocator(fnn_alloc_fn alloc, fnn_free_fn free_, void *ctx)
     return FNN_OK;
 }
 
+// Row stride of the device copy (floats, words or bytes) under the
+// per-metric dimension rules.
+static int row_stride(fnn_metric metric, int32_t dim)
+{
+    switch (metric) {
+    case FNN_L2:
+    case FNN_ANGULAR:
+        if (dim > 65536)
+            fail(FNN_EUNSUPPORTED, "dim > 65536");
+        return (dim + 3) / 4 * 4;
+    case FNN_HAMMING:
+        if (dim % 64)
+            fail(FNN_EINVAL, "Hamming dim (bits) must be a multiple of 64");
+        if (dim / 64 > 16)
+            fail(FNN_EUNSUPPORTED, "Hamming codes longer than 1024 bits");
+        return dim / 64;
+    default:
+        if (dim > 64 * MAX_LEV_WORDS)
+            fail(FNN_EUNSUPPORTED, "Levenshtein stride > %d", 64 * MAX_LEV_WORDS);
+        return dim;
+    }
+}
+
 static int tree_build_any(const void *points, int64_t n, const int64_t *offsets,
                           int32_t nclouds, int32_t dim, fnn_metric metric,
                           const fnn_options *opt, fnn_tree **out)
@@ -191,26 +220,7 @@ static int tree_build_any(const void *points, int64_t n, const int64_t *offsets,
             T->cloud_src = {0};
         }
         T->ncloud = (int)T->cloud_src.size();
-        switch (metric) {
-        case FNN_L2:
-        case FNN_ANGULAR:
-            if (dim > 65536)
-                fail(FNN_EUNSUPPORTED, "dim > 65536");
-            T->dp = (dim + 3) / 4 * 4;
-            break;
-        case FNN_HAMMING:
-            if (dim % 64)
-                fail(FNN_EINVAL, "Hamming dim (bits) must be a multiple of 64");
-            if (dim / 64 > 16)
-                fail(FNN_EUNSUPPORTED, "Hamming codes longer than 1024 bits");
-            T->dp = dim / 64;
-            break;
-        default:
-            if (dim > 64 * MAX_LEV_WORDS)
-                fail(FNN_EUNSUPPORTED, "Levenshtein stride > %d", 64 * MAX_LEV_WORDS);
-            T->dp = dim;
-            break;
-        }
+        T->dp = row_stride(metric, dim);
         Scratch S(current_stream());
         build_tree(T, points, S);
         *out = T;
@@ -400,6 +410,62 @@ int fnn_eps_query(const fnn_tree *tree, const void *queries, int64_t nq, double 
             free_box(B);
         delete F;
         delete TQ;
+        return set_err(FNN_EINTERNAL, "unexpected exception");
+    }
+}
+
+int fnn_landmark_eps_graph(const void *points, int64_t n, int32_t dim,
+                           fnn_metric metric, double eps, int32_t ncells,
+                           uint64_t seed, const fnn_options *opt, fnn_csr **out)
+{
+    if (!out)
+        return set_err(FNN_EINVAL, "out is NULL");
+    *out = nullptr;
+    CsrBox *B = nullptr;
+    try {
+        if (!points)
+            fail(FNN_EINVAL, "points is NULL");
+        if (n < 1 || n > (int64_t)INT32_MAX / 2 - 1)
+            fail(FNN_EINVAL, "n must be in [1, 2^30 - 1] (got %lld)", (long long)n);
+        if (metric < FNN_L2 || metric > FNN_LEVENSHTEIN)
+            fail(FNN_EINVAL, "unknown metric %d", (int)metric);
+        if (dim < 1)
+            fail(FNN_EINVAL, "dim must be >= 1");
+        if (!(eps > 0.0) || !isfinite(eps))
+            fail(FNN_EINVAL, "eps must be finite and > 0");
+        if (ncells < 1)
+            fail(FNN_EINVAL, "ncells must be >= 1");
+        Options o = read_options(opt);
+        if (o.trace)
+            fail(FNN_EUNSUPPORTED, "traces are not available in landmark mode");
+        fnn_tree hdr;  // shape only: no tree is built on it
+        hdr.metric = metric;
+        hdr.n = n;
+        hdr.dim = dim;
+        hdr.dp = row_stride(metric, dim);
+        hdr.opt = o;
+        B = new CsrBox();
+        memset(&B->pub, 0, sizeof B->pub);
+        memset(&B->stats, 0, sizeof B->stats);
+        B->trace_feat = B->trace_targ = nullptr;
+        B->pub.kind = KIND_CSR;
+        {
+            Scratch S(current_stream());
+            landmark_graph(&hdr, points, eps, ncells, seed, opt, &B->pub, B->stats, S);
+        }
+        *out = &B->pub;
+        return FNN_OK;
+    } catch (const Error &e) {
+        if (B)
+            free_box(B);
+        return set_err(e.code, e.msg);
+    } catch (const std::bad_alloc &) {
+        if (B)
+            free_box(B);
+        return set_err(FNN_ENOMEM, "host allocation failed");
+    } catch (...) {
+        if (B)
+            free_box(B);
         return set_err(FNN_EINTERNAL, "unexpected exception");
     }
 }

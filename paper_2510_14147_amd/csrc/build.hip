@@ -110,9 +110,23 @@ void make_level_table(int metric, int dp, LevelTab *tab)
 
 // ------------------------------------------------------------- ingest ----
 
+// Largest coordinate magnitude accepted for vector metrics: every squared
+// difference sum over dim coordinates stays below 4 bound^2 dim <= 4e37,
+// well inside FP32 range.
+float coord_bound(int dim)
+{
+    return (float)std::min(1e16, sqrt(1e37 / std::max(dim, 1)));
+}
+
+// Coordinates are checked to be finite and at most `bound` in magnitude
+// (so that no FP32 squared distance or squared norm can overflow: the host
+// sets bound = min(1e16, sqrt(1e37 / dim))); angular rows must be non-zero.
+// The unit rows of the angular metric are computed from an FP64 norm, so
+// tiny rows whose FP32 squared norm would underflow are still accepted.
 __global__ void k_ingest_vec(const float *__restrict__ in, int n, int dim,
-                             int dp, int angular, float *__restrict__ x,
-                             float *__restrict__ xn, int *err)
+                             int dp, int angular, float bound,
+                             float *__restrict__ x, float *__restrict__ xn,
+                             int *err)
 {
     const int lane = threadIdx.x & (WAVE - 1);
     const int wpb = blockDim.x / WAVE;
@@ -120,12 +134,13 @@ __global__ void k_ingest_vec(const float *__restrict__ in, int n, int dim,
          i += gridDim.x * wpb) {
     const float *r = in + (size_t)i * dim;
     float *o = x + (size_t)i * dp;
-    float ss = 0.f;
-    bool bad = false;
+    double ss = 0.0;
+    bool bad = false, big = false;
     for (int k = lane; k < dp; k += WAVE) {
         float v = k < dim ? r[k] : 0.f;
         bad |= !isfinite(v);
-        ss = fmaf(v, v, ss);
+        big |= fabsf(v) > bound;
+        ss += (double)v * (double)v;
         o[k] = v;
     }
     if (__any(bad)) {
@@ -133,18 +148,23 @@ __global__ void k_ingest_vec(const float *__restrict__ in, int n, int dim,
             atomicOr(err, ERR_INPUT);
         continue;
     }
+    if (__any(big)) {
+        if (lane == 0)
+            atomicOr(err, ERR_RANGE);
+        continue;
+    }
     if (angular) {
         ss = wave_sum(ss);
-        if (!(ss > 0.f) || !isfinite(ss)) {
+        if (!(ss > 0.0)) {
             if (lane == 0)
                 atomicOr(err, ERR_INPUT);
             continue;
         }
         // unit row in FP32 (the key's error band allows for its rounding)
-        float inv = 1.0f / sqrtf(ss);
+        const double inv = 1.0 / sqrt(ss);
         float *on = xn + (size_t)i * dp;
         for (int k = lane; k < dp; k += WAVE)
-            on[k] = o[k] * inv;
+            on[k] = (float)((double)o[k] * inv);
     }
     }
 }
@@ -1248,22 +1268,18 @@ static int bitlen(uint32_t v)
     return b;
 }
 
+// Ingest (input order): rows validated (finite, within coord_bound; no zero
+// angular row; string symbols < MAX_SIGMA) and padded, plus the per-metric
+// preprocessing (unit rows, string lengths and match masks).  Sets T->sigma
+// and T->W for strings.  The returned view reads the caller's rows for
+// Hamming and Levenshtein.
 template <int M>
-static void build_impl(fnn_tree *T, const void *points, Scratch &S)
+static Pts ingest_impl(fnn_tree *T, const void *points, Scratch &S)
 {
     hipStream_t st = S.stream();
     const int n = (int)T->n;
     int *err = S.get<int>(1);
     fill(err, 0, 1, st);
-    unsigned long long *cnt = S.get<unsigned long long>(4);
-    fill(cnt, 0ull, 4, st);
-
-    hipEvent_t ev0, ev1;
-    FNN_HIP(hipEventCreate(&ev0));
-    FNN_HIP(hipEventCreate(&ev1));
-    FNN_HIP(hipEventRecord(ev0, st));
-
-    // ---- ingest (input order) -------------------------------------------
     Pts P{};
     P.metric = M;
     P.n = n;
@@ -1276,7 +1292,7 @@ static void build_impl(fnn_tree *T, const void *points, Scratch &S)
             xn_in = S.get<float>((size_t)n * T->dp);
         FNN_LAUNCH(k_ingest_vec, dim3(grid_cap(n, 4, 16384)), dim3(256), 0, st,
                            (const float *)points, n, T->dim, T->dp,
-                           M == M_ANG ? 1 : 0, x_in, xn_in, err);
+                           M == M_ANG ? 1 : 0, coord_bound(T->dim), x_in, xn_in, err);
         P.x = x_in;
         P.xn = xn_in;
     } else if (M == M_HAM) {
@@ -1307,7 +1323,46 @@ static void build_impl(fnn_tree *T, const void *points, Scratch &S)
         if (e & ERR_INPUT)
             fail(FNN_EINVAL, M == M_ANG ? "input has a NaN/Inf coordinate or a zero row"
                                         : "input has a NaN/Inf coordinate");
+        if (e & ERR_RANGE)
+            fail(FNN_EUNSUPPORTED,
+                 "input has a coordinate of magnitude above %g (FP32 squared "
+                 "distances could overflow)", (double)coord_bound(T->dim));
     }
+
+    return P;
+}
+
+Pts ingest_input(fnn_tree *T, const void *points, Scratch &S)
+{
+    switch (T->metric) {
+    case M_L2:
+        return ingest_impl<M_L2>(T, points, S);
+    case M_ANG:
+        return ingest_impl<M_ANG>(T, points, S);
+    case M_HAM:
+        return ingest_impl<M_HAM>(T, points, S);
+    default:
+        return ingest_impl<M_LEV>(T, points, S);
+    }
+}
+
+template <int M>
+static void build_impl(fnn_tree *T, const void *points, Scratch &S)
+{
+    hipStream_t st = S.stream();
+    const int n = (int)T->n;
+    int *err = S.get<int>(1);
+    fill(err, 0, 1, st);
+    unsigned long long *cnt = S.get<unsigned long long>(4);
+    fill(cnt, 0ull, 4, st);
+
+    hipEvent_t ev0, ev1;
+    FNN_HIP(hipEventCreate(&ev0));
+    FNN_HIP(hipEventCreate(&ev1));
+    FNN_HIP(hipEventRecord(ev0, st));
+
+    // ---- ingest (input order) -------------------------------------------
+    Pts P = ingest_impl<M>(T, points, S);
 
     LevelTab htab;
     make_level_table(M, T->dp, &htab);
@@ -1572,12 +1627,12 @@ static void build_impl(fnn_tree *T, const void *points, Scratch &S)
     if (M == M_L2 || M == M_ANG) {
         T->x = (float *)T->own(sizeof(float) * (size_t)n * T->dp);
         FNN_LAUNCH((k_gather_rows<float>), dim3(grid_cap(n, 4, 16384)), dim3(256), 0,
-                           st, x_in, perm, n, T->dp, T->x);
+                           st, P.x, perm, n, T->dp, T->x);
         Q.x = T->x;
         if (M == M_ANG) {
             T->xn = (float *)T->own(sizeof(float) * (size_t)n * T->dp);
             FNN_LAUNCH((k_gather_rows<float>), dim3(grid_cap(n, 4, 16384)),
-                               dim3(256), 0, st, xn_in, perm, n, T->dp, T->xn);
+                               dim3(256), 0, st, P.xn, perm, n, T->dp, T->xn);
             Q.xn = T->xn;
         }
     } else if (M == M_HAM) {

@@ -23,6 +23,7 @@ enum {
     ERR_CAPACITY = 1,    // an output buffer was too small (host resizes)
     ERR_INDEX = 2,       // an index left its buffer (internal bug)
     ERR_INPUT = 4,       // NaN / Inf coordinate, zero angular row, bad symbol
+    ERR_RANGE = 8,       // coordinate magnitude beyond what FP32 keys can hold
 };
 
 // Device view of a point set.  During the build the rows are in input

@@ -1405,6 +1405,44 @@ __global__ void k_pair_bound(const int2 *__restrict__ inter, long long ni,
         atomicAdd(out, b);
 }
 
+// Sorts every CSR row by column (entries are (column, distance) pairs):
+// rows of up to 512 entries by one wave, up to 4096 by one wave or four,
+// up to 16384 by sixteen waves, longer rows in a global buffer.
+void sort_csr_rows(const int64_t *row_ptr, int n, int32_t *col, float *dist,
+                   int64_t nnz, Scratch &S)
+{
+    hipStream_t s = S.stream();
+    int32_t *mid = S.get<int32_t>(n), *lng = S.get<int32_t>(n);
+    int32_t *cc = S.get<int32_t>(2);
+    fill(cc, 0, 2, s);
+    if (nnz > 0) {
+        FNN_LAUNCH(k_sort_small, dim3(grid_cap(n, 4, 16384)), dim3(256), 0, s,
+                   row_ptr, n, col, dist, mid, lng, cc);
+        int32_t hcc[2];
+        FNN_HIP(hipMemcpyAsync(hcc, cc, sizeof hcc, hipMemcpyDeviceToHost, s));
+        FNN_HIP(hipStreamSynchronize(s));
+        if (hcc[0] > 0) {
+            FNN_LAUNCH(k_sort_wave, dim3(grid_cap(hcc[0], 4, 4096)), dim3(256), 0, s,
+                       row_ptr, mid, hcc[0], col, dist);
+            FNN_LAUNCH(k_sort_blk<4>, dim3(grid_cap(hcc[0], 1, 4096)), dim3(4 * WAVE), 0,
+                       s, row_ptr, mid, hcc[0], 32 * WAVE, col, dist);
+        }
+        if (hcc[1] > 0) {
+            int64_t *p2 = S.get<int64_t>(hcc[1] + 1);
+            int64_t *soff = S.get<int64_t>(hcc[1] + 2);
+            FNN_LAUNCH(k_long_sizes, dim3(grid_for(hcc[1], 256)), dim3(256), 0, s,
+                       row_ptr, lng, hcc[1], p2);
+            scan_i64(p2, soff, hcc[1], S);
+            const int64_t tot = read_scalar(soff + hcc[1], s);
+            unsigned long long *scr = S.get<unsigned long long>(tot);
+            FNN_LAUNCH(k_sort_blk<16>, dim3(grid_cap(hcc[1], 1, 4096)), dim3(16 * WAVE), 0,
+                       s, row_ptr, lng, hcc[1], 64 * WAVE, col, dist);
+            FNN_LAUNCH(k_sort_long, dim3(hcc[1]), dim3(256), 0, s, row_ptr, lng,
+                       soff, scr, col, dist);
+        }
+    }
+}
+
 // Learned-schedule state of one query.
 struct Learned {
     const float *model = nullptr;  // device parameters (null: no model)
@@ -1598,12 +1636,14 @@ static void eps_graph_impl(const fnn_tree *Tc, const double *epsv,
         if (use_gram) {
             unsigned long long *ns = S.get<unsigned long long>(2);
             Events fev(s);
-            // survivor list: up to 256 entries per point while they fit in
-            // an eighth of the free device memory, at least 64 per point
+            // survivor list: up to 512 entries per point while they fit in
+            // a sixteenth of the free device memory, at least 64 per point
+            // (the ~500-neighbour C2 radius passes ~427 per point through
+            // the filter, so one filter pass suffices there)
             size_t freeb = 0, totb = 0;
             FNN_HIP(hipMemGetInfo(&freeb, &totb));
-            const long long room = (long long)(freeb / 8 / sizeof(int2));
-            long long cap = std::max({1ll << 24, 64ll * n, std::min(room, 256ll * n)});
+            const long long room = (long long)(freeb / 16 / sizeof(int2));
+            long long cap = std::max({1ll << 24, 64ll * n, std::min(room, 512ll * n)});
             if (learned) {
                 // predicted ordered edges / 2, times the filter's survivor
                 // factor (BF16 ~1.5, FP8 tens on high-dimensional data)
@@ -1623,6 +1663,8 @@ static void eps_graph_impl(const fnn_tree *Tc, const double *epsv,
             }
             if (opt.validate)
                 cap = std::max<long long>(cap, (long long)n * (n - 1) / 2 + 1);
+            if (opt.list_cap > 0)
+                cap = opt.list_cap;
             // the integer filter on Hamming codes is exact: unless validating,
             // it writes the edges, their distances and the degrees itself
             const bool direct = M == M_HAM && !opt.validate;
@@ -1686,6 +1728,8 @@ static void eps_graph_impl(const fnn_tree *Tc, const double *epsv,
             const unsigned long long room = (unsigned long long)(freeb / 8 / 12);
             o.ecap = std::max<unsigned long long>(
                 1024, std::min({2 * bound, room, 256ull * (unsigned long long)n}));
+            if (opt.list_cap > 0)
+                o.ecap = (unsigned long long)opt.list_cap;
             o.elist = S.get<int2>(o.ecap);
             o.edist = S.get<float>(o.ecap);
             o.ecnt = S.get<unsigned long long>(1);
@@ -1820,35 +1864,7 @@ static void eps_graph_impl(const fnn_tree *Tc, const double *epsv,
     }
 
     // ---- per-row sort ---------------------------------------------------
-    int32_t *mid = S.get<int32_t>(n), *lng = S.get<int32_t>(n);
-    int32_t *cc = S.get<int32_t>(2);
-    fill(cc, 0, 2, s);
-    if (nnz > 0) {
-        FNN_LAUNCH(k_sort_small, dim3(grid_cap(n, 4, 16384)), dim3(256), 0, s,
-                   C->row_ptr, n, C->col, C->dist, mid, lng, cc);
-        int32_t hcc[2];
-        FNN_HIP(hipMemcpyAsync(hcc, cc, sizeof hcc, hipMemcpyDeviceToHost, s));
-        FNN_HIP(hipStreamSynchronize(s));
-        if (hcc[0] > 0) {
-            FNN_LAUNCH(k_sort_wave, dim3(grid_cap(hcc[0], 4, 4096)), dim3(256), 0, s,
-                       C->row_ptr, mid, hcc[0], C->col, C->dist);
-            FNN_LAUNCH(k_sort_blk<4>, dim3(grid_cap(hcc[0], 1, 4096)), dim3(4 * WAVE), 0,
-                       s, C->row_ptr, mid, hcc[0], 32 * WAVE, C->col, C->dist);
-        }
-        if (hcc[1] > 0) {
-            int64_t *p2 = S.get<int64_t>(hcc[1] + 1);
-            int64_t *soff = S.get<int64_t>(hcc[1] + 2);
-            FNN_LAUNCH(k_long_sizes, dim3(grid_for(hcc[1], 256)), dim3(256), 0, s,
-                       C->row_ptr, lng, hcc[1], p2);
-            scan_i64(p2, soff, hcc[1], S);
-            const int64_t tot = read_scalar(soff + hcc[1], s);
-            unsigned long long *scr = S.get<unsigned long long>(tot);
-            FNN_LAUNCH(k_sort_blk<16>, dim3(grid_cap(hcc[1], 1, 4096)), dim3(16 * WAVE), 0,
-                       s, C->row_ptr, lng, hcc[1], 64 * WAVE, C->col, C->dist);
-            FNN_LAUNCH(k_sort_long, dim3(hcc[1]), dim3(256), 0, s, C->row_ptr, lng,
-                       soff, scr, C->col, C->dist);
-        }
-    }
+    sort_csr_rows(C->row_ptr, n, C->col, C->dist, nnz, S);
     tm.mark();  // 6
 
     // ---- trace targets, prediction error ---------------------------------

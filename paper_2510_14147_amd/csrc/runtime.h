@@ -57,9 +57,11 @@ struct GraphRun {
     void launch(hipStream_t s);
 };
 
-// Scratch memory of one call: bump-allocated from device chunks taken from
-// a per-device cache and returned to it (after the stream drains) on scope
-// exit.
+// Scratch memory of one call: bump-allocated from device chunks.  With a
+// caller allocator set (fnn_set_allocator) every chunk comes from it and
+// goes back to it on scope exit; otherwise chunks come from a per-device
+// cache of hipMalloc'd chunks and return to it.  Either way the stream
+// drains first.
 class Scratch {
   public:
     explicit Scratch(hipStream_t s);
@@ -79,6 +81,7 @@ class Scratch {
     hipStream_t s_;
     int dev_ = 0;
     std::vector<std::pair<void *, size_t>> chunks_;  // held by this scope
+    std::vector<bool> hooked_;  // chunk came from the caller's allocator
     size_t used_ = 0;                                // bump offset in the last
 };
 

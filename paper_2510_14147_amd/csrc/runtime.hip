@@ -101,11 +101,19 @@ void GraphRun::launch(hipStream_t s) { FNN_HIP(hipGraphLaunch(exec, s)); }
 
 // --------------------------------------------------------------- scratch --
 //
-// Scratch memory is bump-allocated from large chunks.  A call's chunks come
-// from a per-device cache of idle chunks (best fit, so a repeated call
-// reuses the same chunks) and go back to it when the call's scope ends,
-// after its stream has drained; a steady stream of calls therefore makes no
+// Scratch memory is bump-allocated from large chunks.  When the caller has
+// set an allocator (fnn_set_allocator), every chunk is taken from it and
+// handed back when the call's scope ends, after its stream has drained, so
+// all device memory of a call goes through the caller (a caching allocator
+// then keeps the chunks).  Otherwise a call's chunks come from a per-device
+// cache of idle hipMalloc'd chunks (best fit, so a repeated call reuses the
+// same chunks) and go back to it; a steady stream of calls then makes no
 // device allocation at all.  Idle chunks beyond a cap are freed.
+
+// The caller's allocator (defined with out_alloc below): true and *p set
+// when one is installed (fails with FNN_ENOMEM if it returns NULL).
+static bool hook_alloc(size_t bytes, void **p);
+static void hook_free(void *p);
 
 namespace {
 struct Chunk {
@@ -138,6 +146,12 @@ void *Scratch::raw(size_t bytes)
     const size_t want = std::max(bytes, CHUNK);
     void *base = nullptr;
     size_t cap = 0;
+    if (hook_alloc(want, &base)) {
+        chunks_.emplace_back(base, want);
+        hooked_.push_back(true);
+        used_ = bytes;
+        return base;
+    }
     {
         std::lock_guard<std::mutex> lk(g_chunk_mu);
         auto &idle = g_idle[dev_];
@@ -163,6 +177,7 @@ void *Scratch::raw(size_t bytes)
         cap = want;
     }
     chunks_.emplace_back(base, cap);
+    hooked_.push_back(false);
     used_ = bytes;
     return base;
 }
@@ -178,8 +193,14 @@ Scratch::~Scratch()
         return;
     // the chunks may be reused by any stream once this one has drained
     (void)hipStreamSynchronize(s_);
+    for (size_t i = 0; i < chunks_.size(); ++i)
+        if (hooked_[i])
+            hook_free(chunks_[i].first);
     std::lock_guard<std::mutex> lk(g_chunk_mu);
-    for (auto &c : chunks_) {
+    for (size_t i = 0; i < chunks_.size(); ++i) {
+        if (hooked_[i])
+            continue;
+        const auto &c = chunks_[i];
         g_idle[dev_].push_back(Chunk{static_cast<char *>(c.first), c.second});
         g_idle_bytes[dev_] += c.second;
     }
@@ -212,6 +233,32 @@ void set_alloc_hook(fnn_alloc_fn a, fnn_free_fn f, void *ctx)
     g_hook.alloc = a;
     g_hook.free_ = f;
     g_hook.ctx = ctx;
+}
+
+static bool hook_alloc(size_t bytes, void **p)
+{
+    AllocHook h;
+    {
+        std::lock_guard<std::mutex> lk(g_hook_mu);
+        h = g_hook;
+    }
+    if (!h.alloc)
+        return false;
+    *p = h.alloc(bytes, h.ctx);
+    if (!*p)
+        fail(FNN_ENOMEM, "user allocator returned NULL for %zu bytes of scratch", bytes);
+    return true;
+}
+
+static void hook_free(void *p)
+{
+    AllocHook h;
+    {
+        std::lock_guard<std::mutex> lk(g_hook_mu);
+        h = g_hook;
+    }
+    if (h.free_)
+        h.free_(p, h.ctx);
 }
 
 void *out_alloc(size_t bytes)

@@ -27,6 +27,7 @@ struct Options {
     int slack_pct = 30;
     int graph_passes = 4;
     int proj = 0;
+    long long list_cap = 0;  // initial survivor / edge list entries (0: automatic)
 };
 
 Options read_options(const fnn_options *o);

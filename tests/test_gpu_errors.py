@@ -1,0 +1,255 @@
+"""Failure handling and numeric range on the GPU, through the C ABI: invalid
+inputs are refused with the documented codes before any result is formed,
+an allocator that fails part-way makes the call fail with FNN_ENOMEM and
+give back everything it took, coordinates near the accepted magnitude bound
+still give the oracle's graph, forced list overflows take the redo paths and
+still give the oracle's graph, and the plain (non-_ex) entry points on raw
+device pointers agree with the oracle."""
+import ctypes
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_2510_14147_amd import datagen as G
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+W = json.load(open(os.path.join(ROOT, "paper_2510_14147_amd", "workloads.json")))
+EINVAL, ENOMEM, EUNSUPPORTED = -1, -2, -4
+
+
+@pytest.fixture(scope="module")
+def fnn():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2510_14147_amd as f
+    f.lib()
+    return f
+
+
+def _build_rc(fnn, x, metric="l2"):
+    """Return code of a build on device rows x (the handle is freed)."""
+    import torch
+    L = fnn.lib()
+    t = torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    h = ctypes.c_void_p()
+    fnn._bind_stream()
+    rc = L.fnn_tree_build(ctypes.c_void_p(t.data_ptr()), t.shape[0], t.shape[1],
+                          fnn.METRICS[metric], ctypes.byref(h))
+    if rc == 0:
+        L.fnn_free(h)
+    else:
+        assert h.value is None
+    return rc, L.fnn_last_error().decode()
+
+
+@pytest.mark.parametrize("bad", [np.nan, np.inf, -np.inf])
+@pytest.mark.parametrize("metric", ["l2", "angular"])
+def test_non_finite_coordinate_is_einval(fnn, bad, metric):
+    print(f"[case] non-finite {bad} {metric}", flush=True)
+    x = G.random_points(500, 6, seed=3)
+    x[417, 2] = bad
+    rc, msg = _build_rc(fnn, x, metric)
+    assert rc == EINVAL and "NaN/Inf" in msg
+
+
+def test_zero_angular_row_is_einval(fnn):
+    print("[case] zero angular row", flush=True)
+    x = G.random_points(300, 5, seed=4) + 0.1
+    x[123] = 0.0
+    rc, msg = _build_rc(fnn, x, "angular")
+    assert rc == EINVAL and "zero row" in msg
+    # the same row as the only zero is fine on L2
+    assert _build_rc(fnn, x, "l2")[0] == 0
+
+
+def test_coordinate_beyond_bound_is_unsupported(fnn):
+    print("[case] coordinate magnitude bound", flush=True)
+    x = G.random_points(200, 8, seed=5)
+    x[7, 3] = 3e17               # bound at d = 8: min(1e16, sqrt(1e37 / 8))
+    rc, msg = _build_rc(fnn, x)
+    assert rc == EUNSUPPORTED and "magnitude" in msg
+    x[7, 3] = 9.9e15
+    assert _build_rc(fnn, x)[0] == 0
+
+
+@pytest.mark.parametrize("eps", [0.0, -1.0, math.nan, math.inf, -math.inf])
+def test_bad_eps_is_einval(fnn, eps):
+    print(f"[case] eps={eps}", flush=True)
+    x = G.random_points(300, 4, seed=6)
+    tree = fnn.fnn_tree_build(x, "l2")
+    with pytest.raises(fnn.FnnError) as e:
+        fnn.fnn_eps_graph(tree, eps)
+    assert e.value.code == EINVAL
+    with pytest.raises(fnn.FnnError) as e:
+        fnn.fnn_eps_graph_batch(tree, [eps])
+    assert e.value.code == EINVAL
+
+
+def test_large_magnitudes_match_oracle(fnn, orc):
+    """Coordinates of order 1e15 (squared distances near 1e31..1e32) and an
+    eps of that size: the FP32 keys stay finite, every decision is the
+    oracle's."""
+    print("[case] magnitudes 1e15", flush=True)
+    x = (G.random_points(3000, 6, seed=7, duplicates=30) * 2e15 - 1e15).astype(np.float32)
+    eps = 6e14
+    tree = fnn.fnn_tree_build(x, "l2")
+    g = fnn.fnn_eps_graph(tree, eps)
+    ref = orc.bruteforce(x, 0, eps)
+    cmp = orc.compare_csr(*g.to_numpy(), *ref)
+    assert cmp["ok"] and cmp["ref_nnz"] > 10000, cmp
+
+
+def test_tiny_angular_rows_match_oracle(fnn, orc):
+    """Rows whose FP32 squared norm underflows are still directions."""
+    print("[case] tiny angular rows", flush=True)
+    x = G.angular_dirs(n=2000, dim=16)
+    x[::7] *= np.float32(1e-25)
+    tree = fnn.fnn_tree_build(x, "angular")
+    g = fnn.fnn_eps_graph(tree, W["ang"]["eps"])
+    ref = orc.bruteforce(x, 1, W["ang"]["eps"])
+    cmp = orc.compare_csr(*g.to_numpy(), *ref)
+    assert cmp["ok"], cmp
+
+
+class _FailingAllocator:
+    """Device allocator for fnn_set_allocator that fails after `k`
+    successful allocations and records what is live."""
+
+    def __init__(self, k):
+        import torch
+        self.torch, self.k, self.calls, self.live = torch, k, 0, {}
+        self.bad_free = 0
+        A = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+        F = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+        self.a = A(self._alloc)
+        self.f = F(self._free)
+
+    def _alloc(self, nbytes, ctx):
+        self.calls += 1
+        if self.calls > self.k:
+            return None
+        t = self.torch.empty(int(nbytes), dtype=self.torch.uint8, device="cuda")
+        self.live[t.data_ptr()] = t
+        return t.data_ptr()
+
+    def _free(self, ptr, ctx):
+        # (an assert would be swallowed inside a ctypes callback)
+        if self.live.pop(ptr, None) is None:
+            self.bad_free += 1
+
+
+def _with_allocator(fnn, alloc, fn):
+    L = fnn.lib()
+    L.fnn_set_allocator(alloc.a, alloc.f, None)
+    try:
+        return fn()
+    finally:
+        L.fnn_set_allocator(fnn._alloc_cb, fnn._free_cb, None)
+
+
+def test_allocator_failure_is_enomem_and_leaks_nothing(fnn, orc):
+    import torch
+    x = G.c2_manifold(n=6000)
+    eps = W["c2_50k"]["eps"][0]
+    xd = torch.from_numpy(x).cuda()
+    L = fnn.lib()
+
+    def build_and_query():
+        h = ctypes.c_void_p()
+        fnn._bind_stream()
+        rc = L.fnn_tree_build(ctypes.c_void_p(xd.data_ptr()), x.shape[0], x.shape[1], 0,
+                              ctypes.byref(h))
+        if rc != 0:
+            assert h.value is None
+            return rc, None
+        out = ctypes.POINTER(fnn.fnn_csr)()
+        o = fnn._options(precision="auto")
+        rc = L.fnn_eps_graph_ex(h, eps, ctypes.byref(o), ctypes.byref(out))
+        if rc != 0:
+            assert not out
+            L.fnn_free(h)
+            return rc, None
+        nnz = out.contents.nnz
+        L.fnn_free(ctypes.cast(out, ctypes.c_void_p))
+        L.fnn_free(h)
+        return 0, nnz
+
+    # how many allocations a whole build + query takes
+    probe = _FailingAllocator(10 ** 9)
+    rc, nnz = _with_allocator(fnn, probe, build_and_query)
+    assert rc == 0 and not probe.live and probe.bad_free == 0
+    total = probe.calls
+    assert total >= 4
+    ref = orc.bruteforce(x, 0, eps)
+    assert nnz == ref[0][-1]
+    for k in sorted({0, 1, 2, total // 3, total // 2, total - 2, total - 1}):
+        print(f"[case] allocator fails after {k} of {total}", flush=True)
+        a = _FailingAllocator(k)
+        rc, _ = _with_allocator(fnn, a, build_and_query)
+        assert rc == ENOMEM, (k, rc, L.fnn_last_error())
+        assert not a.live, f"{len(a.live)} allocations leaked after failure at {k}"
+        assert a.bad_free == 0
+    # and the library works normally afterwards
+    rc, nnz2 = build_and_query()
+    assert rc == 0 and nnz2 == nnz
+
+
+def test_plain_entry_points_on_device_pointers(fnn, orc):
+    """fnn_tree_build / fnn_eps_graph / fnn_free with raw device pointers,
+    no options: the defaults (FP32 tiles, two-pass)."""
+    import torch
+    print("[case] plain ABI", flush=True)
+    L = fnn.lib()
+    x = G.c1_clusters(n_centers=6, per_center=700)
+    eps = 0.09
+    xd = torch.from_numpy(x).cuda()
+    h = ctypes.c_void_p()
+    fnn._bind_stream()
+    assert L.fnn_tree_build(ctypes.c_void_p(xd.data_ptr()), x.shape[0], x.shape[1], 0,
+                            ctypes.byref(h)) == 0
+    out = ctypes.POINTER(fnn.fnn_csr)()
+    assert L.fnn_eps_graph(h, eps, ctypes.byref(out)) == 0
+    c = out.contents
+    n, nnz = int(c.n), int(c.nnz)
+    rp = torch.empty(n + 1, dtype=torch.int64, device="cuda")
+    col = torch.empty(max(nnz, 1), dtype=torch.int32, device="cuda")
+    dist = torch.empty(max(nnz, 1), dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    hip = ctypes.CDLL("libamdhip64.so")
+    hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+    for dst, src, nb in ((rp, c.row_ptr, 8 * (n + 1)), (col, c.col, 4 * nnz),
+                         (dist, c.dist, 4 * nnz)):
+        assert hip.hipMemcpy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src), nb, 3) == 0
+    L.fnn_free(ctypes.cast(out, ctypes.c_void_p))
+    L.fnn_free(h)
+    ref = orc.bruteforce(x, 0, eps)
+    cmp = orc.compare_csr(rp.cpu().numpy(), col[:nnz].cpu().numpy(),
+                          dist[:nnz].cpu().numpy(), *ref)
+    assert cmp["ok"], cmp
+
+
+@pytest.mark.parametrize("precision", ["bf16", "fp32"])
+def test_forced_list_overflow_matches_oracle(fnn, orc, precision):
+    """A tiny initial list forces the redo paths: a second filter pass into a
+    list sized from the first pass's count (MFMA), or the count / fill pair
+    of tile passes (plain tiles)."""
+    print(f"[case] forced list overflow {precision}", flush=True)
+    x = G.c2_manifold(n=9000)
+    eps = W["c2_50k"]["eps"][0]
+    tree = fnn.fnn_tree_build(x, "l2")
+    g = fnn.fnn_eps_graph(tree, eps, precision=precision, proj=-1 if precision == "bf16" else None,
+                          list_cap=1000)
+    ref = orc.bruteforce(x, 0, eps)
+    cmp = orc.compare_csr(*g.to_numpy(), *ref)
+    assert cmp["ok"], cmp
+    if precision == "bf16":
+        assert g.stats["overflow_rows"] == 1       # one more filter pass ran
+        assert g.stats["filter_survivors"] >= ref[0][-1] // 2
+    g2 = fnn.fnn_eps_graph(tree, eps, precision=precision)
+    for u, v in zip(g.to_numpy(), g2.to_numpy()):
+        assert np.array_equal(u.view(np.uint8), v.view(np.uint8))

@@ -137,3 +137,86 @@ def test_learned_mfma_same_graph(fnn):
     g2 = fnn.fnn_eps_graph(tree, eps, precision="fp32")
     for u, v in zip(g1.to_numpy()[:2], g2.to_numpy()[:2]):
         assert np.array_equal(u, v)
+
+
+def test_adam_steps_match_fp64_reference(fnn):
+    """Three full-batch Adam steps of the library's trainer (k_mlp_grad +
+    k_adam) against the FP64 reference's backward + adam_step from the same
+    FP32 start.  With one batch per epoch the shuffle only reorders a sum.
+    Parameters whose gradient is near zero at some step are left out: there
+    the normalised step m / sqrt(v) is decided by rounding of the gradient
+    itself."""
+    import torch
+    from oracle import mlp
+    th, x, t = _rand(11)
+    th32 = th.astype(np.float32)
+    x32, t32 = x.astype(np.float32), t.astype(np.float32)
+    lr, steps = 1e-3, 3
+    p = torch.from_numpy(th32.copy()).cuda()
+    fnn.fnn_mlp_train(p, torch.from_numpy(x32).cuda(), torch.from_numpy(t32).cuda(),
+                      epochs=steps, batch=len(x32), lr=lr, seed=3)
+    got = p.cpu().numpy().astype(np.float64)
+    ref = th32.astype(np.float64)
+    m = np.zeros_like(ref)
+    v = np.zeros_like(ref)
+    gmin = np.full_like(ref, np.inf)
+    gmax = 0.0
+    for k in range(1, steps + 1):
+        g = mlp.backward(ref, x32.astype(np.float64), t32.astype(np.float64))
+        gmin = np.minimum(gmin, np.abs(g))
+        gmax = max(gmax, float(np.abs(g).max()))
+        ref, m, v = mlp.adam_step(ref, g, m, v, k, lr=lr)
+    keep = gmin > 1e-3 * gmax
+    assert keep.mean() > 0.8
+    # each step moves a parameter by at most ~lr; agreement to a small
+    # fraction of one step
+    np.testing.assert_allclose(got[keep], ref[keep], rtol=0, atol=2e-3 * lr * steps + 1e-6)
+    # and every parameter, kept or not, moved by at most the Adam bound
+    assert np.all(np.abs(got - th32) <= steps * lr * 1.01 + 1e-6)
+
+
+def test_learned_schedule_gain_c2_held_out(fnn):
+    """What the shipped cost model (trained on traces of the 10^6-point C2
+    set) gains over the method without it, on 10^6 held-out draws of the
+    same manifold (rows 10^6 .. 2 10^6 of the seeded stream) at both radii:
+    its log1p(degree) error against the best constant predictor (the test
+    set's own median: the strongest no-model baseline), and the learned
+    schedule against the two-pass one on the same tree -- identical CSRs,
+    with time and peak device memory printed for the record."""
+    import time
+    import torch
+    x = G.c2_manifold(n=2_000_000)[1_000_000:]
+    th = torch.from_numpy(fnn.load_cost_model()).cuda()
+    fnn.fnn_set_cost_model(th.cpu().numpy())
+    tree = fnn.fnn_tree_build(x, "l2")
+    for eps in W["c2"]["eps"]:
+        print(f"[case] held-out C2 eps={eps}", flush=True)
+        g2 = fnn.fnn_eps_graph(tree, eps, precision="auto", trace=True)
+        y = fnn.fnn_mlp_forward(th, g2.features.clone())[:, 1]
+        true = g2.targets[:, 1]
+        mae_model = float((y - true).abs().mean())
+        mae_const = float((true - true.median()).abs().mean())
+        del g2
+        rec = {}
+        for sched in ("two_pass", "learned"):
+            fnn.fnn_eps_graph(tree, eps, precision="auto", sched=sched)   # warm
+            torch.cuda.synchronize()
+            torch.cuda.reset_peak_memory_stats()
+            base = torch.cuda.memory_allocated()
+            t0 = time.perf_counter()
+            g = fnn.fnn_eps_graph(tree, eps, precision="auto", sched=sched)
+            torch.cuda.synchronize()
+            rec[sched] = (g, 1e3 * (time.perf_counter() - t0),
+                          (torch.cuda.max_memory_allocated() - base) / 2 ** 30)
+        a, b = rec["two_pass"][0], rec["learned"][0]
+        assert torch.equal(a.row_ptr, b.row_ptr) and torch.equal(a.col, b.col)
+        assert torch.equal(a.dist.view(torch.int32), b.dist.view(torch.int32))
+        st = b.stats
+        print(f"[gain] eps={eps:.4f}: log1p(degree) MAE model {mae_model:.3f} vs best "
+              f"constant {mae_const:.3f}; two-pass {rec['two_pass'][1]:.1f} ms "
+              f"{rec['two_pass'][2]:.2f} GiB peak, {a.stats['overflow_rows']} extra filter "
+              f"passes; learned {rec['learned'][1]:.1f} ms {rec['learned'][2]:.2f} GiB peak, "
+              f"{st['overflow_rows']} extra filter passes, predicted/true edges "
+              f"{st['pred_sum_ratio']:.3f}", flush=True)
+        assert mae_model < mae_const
+        del a, b, rec
