@@ -120,7 +120,13 @@ typedef struct fnn_options {
                           /* fall back to the count / fill pair of passes.  */
                           /* Results never depend on it; small values force */
                           /* those paths (tests).                           */
-    int32_t reserved[4];
+    int32_t lpt;          /* learned schedule: 1 = the tile pass takes its   */
+                          /* pack pairs in LPT order of predicted cost,     */
+                          /* heaviest first, each work-group the next as it */
+                          /* finishes (Graham's rule, which the paper uses  */
+                          /* to place cells, Section IV-D); default 0: list */
+                          /* order, grid stride (measured faster)           */
+    int32_t reserved[3];
 } fnn_options;
 
 typedef struct fnn_tree fnn_tree;  /* opaque; device-resident cover tree */

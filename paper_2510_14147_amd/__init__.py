@@ -43,7 +43,7 @@ class fnn_options(ctypes.Structure):
                 ("kmax", ctypes.c_int32), ("trace", ctypes.c_int32),
                 ("slack_pct", ctypes.c_int32), ("graph_passes", ctypes.c_int32),
                 ("proj", ctypes.c_int32), ("list_cap", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("lpt", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 class fnn_tune_result(ctypes.Structure):
@@ -325,7 +325,7 @@ def fnn_tree_build_batch(points, offsets, metric: str = "l2", zeta=None,
 
 def fnn_eps_graph_batch(tree: Tree, eps, precision="fp32", sched="two_pass",
                         validate=False, trace=False, slack_pct=None,
-                        proj=None, list_cap=None) -> Graph:
+                        proj=None, list_cap=None, lpt=False) -> Graph:
     """Per-cloud thresholds ``eps[c]``; one block-diagonal CSR over all rows."""
     if sched == "learned" and not _model_set and os.path.exists(COST_MODEL_PATH):
         fnn_set_cost_model(load_cost_model())
@@ -333,7 +333,8 @@ def fnn_eps_graph_batch(tree: Tree, eps, precision="fp32", sched="two_pass",
     _bind_stream()
     out = ctypes.POINTER(fnn_csr)()
     o = _options(precision=precision, sched=sched, validate=int(validate),
-                 trace=int(trace), slack_pct=slack_pct, proj=proj, list_cap=list_cap)
+                 trace=int(trace), slack_pct=slack_pct, proj=proj, list_cap=list_cap,
+                 lpt=int(lpt))
     _check(lib().fnn_eps_graph_batch(
         tree.handle, e.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), e.size,
         ctypes.byref(o), ctypes.byref(out)))
@@ -398,7 +399,7 @@ def load_cost_model(path: str = COST_MODEL_PATH) -> np.ndarray:
 
 def fnn_eps_graph(tree: Tree, eps: float, precision="fp32",
                   sched="two_pass", validate=False, trace=False,
-                  slack_pct=None, proj=None, list_cap=None) -> Graph:
+                  slack_pct=None, proj=None, list_cap=None, lpt=False) -> Graph:
     """proj: filter on leading principal coordinates (None / 0 automatic,
     -1 off, else their number, a multiple of 16).  list_cap: initial
     survivor / edge list capacity (None: automatic; small values force the
@@ -408,7 +409,8 @@ def fnn_eps_graph(tree: Tree, eps: float, precision="fp32",
     _bind_stream()
     out = ctypes.POINTER(fnn_csr)()
     o = _options(precision=precision, sched=sched, validate=int(validate),
-                 trace=int(trace), slack_pct=slack_pct, proj=proj, list_cap=list_cap)
+                 trace=int(trace), slack_pct=slack_pct, proj=proj, list_cap=list_cap,
+                 lpt=int(lpt))
     _check(lib().fnn_eps_graph_ex(tree.handle, float(eps), ctypes.byref(o),
                                   ctypes.byref(out)))
     return Graph(out)

@@ -93,6 +93,7 @@ Options read_options(const fnn_options *o)
     if (o->list_cap < 0)
         fail(FNN_EINVAL, "negative list_cap");
     r.list_cap = o->list_cap;
+    r.lpt = o->lpt ? 1 : 0;
     return r;
 }
 

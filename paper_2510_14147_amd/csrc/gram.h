@@ -36,6 +36,11 @@ struct TileOut {
     float *edist;
     unsigned long long *ecnt;
     unsigned long long ecap;
+    // work order (learned schedule): item k of the pass is inter[order[k]],
+    // and work-groups take items through the counter next (each takes the
+    // next item as it becomes free); null: inter in order, grid stride
+    const uint32_t *order;
+    unsigned long long *next;
 };
 
 struct GramArgs {

@@ -1176,10 +1176,13 @@ __device__ __forceinline__ unsigned long long uniform_u64(unsigned long long v)
 __device__ __forceinline__ void half_finish(const GramArgs &G, const f32x16 (&acc)[2],
                                             const float (&ay)[2], const uint64_t (&hm)[2],
                                             int rb, int na, int nb, bool self, int pa,
-                                            int pb, unsigned long long &cpos,
-                                            unsigned long long &cend, const unsigned *rmS)
+                                            int pb, unsigned long long *curS,
+                                            const unsigned *rmS)
 {
     const int lane = threadIdx.x & (WAVE - 1), l32 = lane & 31, hi = lane >> 5;
+    // the wave's reserved slots, kept in LDS between calls so that the
+    // entry loop holds no cursor registers
+    unsigned long long cpos = uniform_u64(curS[0]), cend = uniform_u64(curS[1]);
     const uint64_t ltmask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
 #pragma unroll
     for (int cb = 0; cb < 2; ++cb) {
@@ -1224,6 +1227,10 @@ __device__ __forceinline__ void half_finish(const GramArgs &G, const f32x16 (&ac
             cpos += (unsigned long long)cnt;
         }
     }
+    if (lane == 0) {
+        curS[0] = cpos;
+        curS[1] = cend;
+    }
 }
 
 // Filter for narrow BF16 rows (kq <= 32: the leading principal
@@ -1249,7 +1256,9 @@ k_gram_direct(Pts P, GramArgs G, TileOut out)
     const int w = __builtin_amdgcn_readfirstlane(t / WAVE);  // wave-uniform
     const int l32 = lane & 31, hi = lane >> 5;
     const unsigned char *Q = (const unsigned char *)G.q;
-    unsigned long long npairs = 0, cpos = 0, cend = 0;
+    __shared__ unsigned long long curS[GW][2];  // each wave's survivor slots
+    if (lane == 0)
+        curS[w][0] = curS[w][1] = 0ull;
     // XCD slices of the unit order, as in k_gram
     const int bpx = (int)gridDim.x / 8, jb = (int)blockIdx.x / 8;
     const int per = (G.nunits + 7) / 8;
@@ -1328,16 +1337,14 @@ k_gram_direct(Pts P, GramArgs G, TileOut out)
             const bool skip = !has_a || b < a || (ca >= 0 && (cb_cl == ca) == (bool)G.cross);
             if (!skip) {
                 const bool self = (b == a);
-                // screened pairs: r < c on a self pair (then nb == na)
-                npairs += self ? (unsigned long long)(na * (na - 1) / 2)
-                               : (unsigned long long)(na * nb);
                 const float ayc[2] = {ay[0], ay[1]};
                 // one 32-row half at a time against both column blocks: the
-                // half's 16 start values feed both products
+                // half's 16 start values feed both products.  Rows past na
+                // start at -FLT_MAX and columns past nb have the column term
+                // FLT_MAX, so a partial pack needs no branch: its missing
+                // pairs never pass
 #pragma unroll
                 for (int rb = 0; rb < 2; ++rb) {
-                    if (rb * 32 >= na)
-                        break;
                     f32x16 sv, acc[2];
                     asm volatile("" ::: "memory");  // re-read (no registers held)
 #pragma unroll
@@ -1359,22 +1366,23 @@ k_gram_direct(Pts P, GramArgs G, TileOut out)
                                 Af[rb][ks], bb, ks == 0 ? sv : acc[cb], 0, 0, 0);
                         }
                     // fast test: the lane's largest sum per column block
-                    // against its column term (the second block only when
-                    // it holds columns)
-                    uint64_t hm[2] = {0, 0};
+                    // minus its column term (exact in sign: x - y >= 0 iff
+                    // x >= y), one vote for the whole half
+                    float mg[2];
 #pragma unroll
                     for (int cb = 0; cb < 2; ++cb) {
-                        if (cb * 32 >= nb)
-                            break;
                         float mx = -FLT_MAX;
 #pragma unroll
                         for (int q = 0; q < 16; ++q)
                             mx = fmaxf(mx, acc[cb][q]);
-                        hm[cb] = __ballot(mx >= ayc[cb]);
+                        mg[cb] = __fsub_rn(mx, ayc[cb]);
                     }
-                    if ((hm[0] | hm[1]) != 0 || G.validate)
-                        half_finish(G, acc, ayc, hm, rb, na, nb, self, pa, pb, cpos, cend,
+                    if (__any(fmaxf(mg[0], mg[1]) >= 0.f) || G.validate) {
+                        const uint64_t hm[2] = {__ballot(mg[0] >= 0.f),
+                                                __ballot(mg[1] >= 0.f)};
+                        half_finish(G, acc, ayc, hm, rb, na, nb, self, pa, pb, curS[w],
                                     rmS);
+                    }
                 }
             }
             // issued on every path (past the end: the last entry again),
@@ -1392,9 +1400,39 @@ k_gram_direct(Pts P, GramArgs G, TileOut out)
         }
         __syncthreads();  // eB.. are rewritten by the next unit
     }
-    pad_surv(G, cpos, cend);
-    if (lane == 0 && npairs)
-        atomicAdd(&out.cnt[2], npairs);
+    pad_surv(G, uniform_u64(curS[w][0]), uniform_u64(curS[w][1]));
+}
+
+// Pairs the narrow kernel screens (its entry loop does not count them): for
+// every list entry (group g, pack B) and every pack A = 4 g + w of the group
+// that the kernel does not skip, na nb pairs (na (na - 1) / 2 when A = B).
+__global__ void k_gram_pairs(GramArgs G, TileOut out)
+{
+    unsigned long long sum = 0;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < G.nlist;
+         e += (long long)gridDim.x * blockDim.x) {
+        const int g = G.lg[e];
+        const int b = G.nn + G.lb[e];
+        const int pbb = G.q_pb[b];
+        const long long nb = G.q_pe[b] - pbb;
+        const int cb_cl = G.pcl ? G.pcl[pbb] : -1;
+        for (int w = 0; w < GW; ++w) {
+            const int a = G.nn + GW * g + w;
+            if ((GW * g + w) >= G.npacks)
+                break;
+            const long long na = G.q_pe[a] - G.q_pb[a];
+            if (na > GP || b < a)
+                continue;
+            const int ca = G.pcl ? G.pcl[G.q_pb[a]] : -1;
+            if (ca >= 0 && (cb_cl == ca) == (bool)G.cross)
+                continue;
+            sum += b == a ? (unsigned long long)(na * (na - 1) / 2)
+                          : (unsigned long long)(na * nb);
+        }
+    }
+    sum = wave_sum(sum);
+    if ((threadIdx.x & (WAVE - 1)) == 0 && sum)
+        atomicAdd(&out.cnt[2], sum);
 }
 
 // FP32 key of every lane's pair (pi, pj), summed exactly as sqdiff_seq sums
@@ -1772,6 +1810,7 @@ static void launch_gram_direct(const Pts &P, const GramArgs &G, const TileOut &o
     const long long need = ((long long)G.nunits + 7) / 8 * 8;
     const dim3 grid((unsigned)std::max<long long>(8, std::min(want, need)));
     FNN_LAUNCH((k_gram_direct<M, NKS>), grid, dim3(GT), 0, s, P, G, o);
+    FNN_LAUNCH(k_gram_pairs, dim3(grid_cap(G.nlist, 256, 4096)), dim3(256), 0, s, G, o);
 }
 
 template <int M, int PREC>

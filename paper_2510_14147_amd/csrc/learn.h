@@ -18,6 +18,7 @@ struct FeatArgs {
     // position, whose root is vertex 1 + cloud; null for a single cloud
     const CloudThr *ct;
     const int32_t *pcl;
+    int first_pack, npacks;  // query-tree ids of the packs: first_pack + k
 };
 
 void tree_aux(fnn_tree *T, Scratch &S);

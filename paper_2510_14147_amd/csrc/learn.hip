@@ -78,8 +78,21 @@ __global__ void k_owner(const int32_t *__restrict__ pb, const int32_t *__restric
     }
 }
 
+// Per-point features (16, scale-free; eps is the point's own cloud's):
+//  0 log2(1 + pack size) / 6        1 depth of the point's leaf / 8
+//  2 log2(r_pack / eps)             3 d(p, pack centre) / eps (<= 16)
+//  4 log2(r / eps) of the parent    5 the same for the grandparent
+//  6 d(p, centre) / r of the parent 7 the same for the grandparent (<= 2)
+//  8, 9, 10 log1p(pack members within eps, 2 eps, eps / 2) / 6
+// 11 mean distance to the pack members / eps (each <= 16)
+// 12 log2(1 + size of the smallest ancestor with r >= eps) / 20
+// 13 log2(1 + the parent's child count) / 8
+// 14 log2(1 + the parent's size) / 20
+// 15 distance to the nearest other pack member / eps (<= 4)
+// No feature is constant over a whole tree (such a value would let the
+// network recognise the training set instead of the point's surroundings).
 template <int M>
-__global__ void k_features(Pts P, FeatArgs A, float *__restrict__ feat)
+__global__ void k_features(Pts P, FeatArgs A, int local_done, float *__restrict__ feat)
 {
     for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < P.n;
          p += gridDim.x * blockDim.x) {
@@ -88,32 +101,124 @@ __global__ void k_features(Pts P, FeatArgs A, float *__restrict__ feat)
         const int v0 = A.leaf_of[p];
         const int cl = A.pcl ? A.pcl[p] : -1;
         const float eps = cl >= 0 ? A.ct[cl].feps : A.eps;
-        const int root = cl >= 0 ? 1 + cl : 0;
         const float tiny = 1.0f / 1048576.0f;
-        f[0] = log2f(1.f + (float)(A.q_pe[pk] - A.q_pb[pk])) / 6.f;
+        const int qb = A.q_pb[pk], qe = A.q_pe[pk];
+        f[0] = log2f(1.f + (float)(qe - qb)) / 6.f;
         f[1] = (float)A.depth[v0] / 8.f;
         f[2] = log2f(A.q_rad[pk] / eps + tiny);
         f[3] = fminf(key_to_dist<M>(key32<M>(P, p, A.q_cpos[pk])) / eps, 16.f);
         int v = v0;
-        for (int k = 1; k <= 4; ++k) {
+        for (int k = 0; k < 2; ++k) {
             if (A.parent[v] >= 0)
                 v = A.parent[v];
             const float r = A.radius[v];
-            f[3 + k] = log2f(r / eps + tiny);
+            f[4 + k] = log2f(r / eps + tiny);
             const float d = key_to_dist<M>(key32<M>(P, p, A.center_pos[v]));
-            f[7 + k] = fminf(d / (r + 1e-30f), 2.f);
+            f[6 + k] = fminf(d / (r + 1e-30f), 2.f);
         }
-        f[12] = log2f(eps / (A.radius[root] + 1e-30f) + tiny);
+        // the point's own pack as a local sample of its neighbourhood: the
+        // whole pack when it holds at most 64 points (then the lanes of a
+        // pack read the same member rows in step), else 64 members around p
+        // (a duplicate leaf can be larger)
+        // packs of at most 64 points get these from k_pack_local when it runs
+        const bool mine = !local_done || qe - qb > 64;
+        const int lo = qe - qb <= 64 ? qb : max(qb, min(p - 32, qe - 64));
+        const int hi = mine ? min(qe, lo + 64) : lo;
+        int c1 = 0, c2 = 0, ch = 0;
+        float sum = 0.f, dmin = 4.f * eps;
+        for (int q = lo; q < hi; ++q) {
+            if (q == p)
+                continue;
+            const float d = key_to_dist<M>(key32<M>(P, p, q));
+            c1 += d <= eps;
+            c2 += d <= 2.f * eps;
+            ch += d <= 0.5f * eps;
+            sum += fminf(d, 16.f * eps);
+            dmin = fminf(dmin, d);
+        }
+        const int others = max(hi - lo - 1, 1);
+        f[8] = log1pf((float)c1) / 6.f;
+        f[9] = log1pf((float)c2) / 6.f;
+        f[10] = log1pf((float)ch) / 6.f;
+        f[11] = sum / ((float)others * eps);
         int u = v0;
         while (A.radius[u] < eps && A.parent[u] >= 0)
             u = A.parent[u];
-        f[13] = log2f(1.f + (float)(A.pe[u] - A.pb[u])) / 20.f;
+        f[12] = log2f(1.f + (float)(A.pe[u] - A.pb[u])) / 20.f;
         const int v1 = A.parent[v0] >= 0 ? A.parent[v0] : v0;
-        f[14] = log2f(1.f + (float)A.ccnt[v1]) / 8.f;
-        f[15] = log2f(1.f + (float)(A.pe[v1] - A.pb[v1])) / 20.f;
+        f[13] = log2f(1.f + (float)A.ccnt[v1]) / 8.f;
+        f[14] = log2f(1.f + (float)(A.pe[v1] - A.pb[v1])) / 20.f;
+        f[15] = dmin / eps;
 #pragma unroll
         for (int k = 0; k < MLP_F; ++k)
-            feat[(size_t)p * MLP_F + k] = f[k];
+            if (mine || (k != 8 && k != 9 && k != 10 && k != 11 && k != 15))
+                feat[(size_t)p * MLP_F + k] = f[k];
+    }
+}
+
+// Features 8-11 and 15 (the pack as a local sample) for vector rows of at
+// most LOC_MAXD floats: one work-group per pack of at most 64 points, its
+// rows staged in LDS (odd row stride: lanes reading one coordinate of
+// different rows hit different banks); thread t takes point t / 4 against
+// every fourth member, and the four partial results meet by shuffles.
+constexpr int LOC_MAXD = 128;
+template <int M>
+__global__ void __launch_bounds__(256)
+k_pack_local(Pts P, FeatArgs A, float *__restrict__ feat)
+{
+    __shared__ float rows[64 * (LOC_MAXD + 1)];
+    const float *X = M == M_L2 ? P.x : P.xn;
+    const int dp = P.dp, ld = dp + 1, t = threadIdx.x;
+    const int npk = A.npacks;
+    for (int k = blockIdx.x; k < npk; k += gridDim.x) {
+        const int pk = A.first_pack + k;
+        const int qb = A.q_pb[pk], qe = A.q_pe[pk], m = qe - qb;
+        __syncthreads();  // rows of the previous pack are no longer read
+        if (m > 64)
+            continue;     // k_features handles large packs
+        for (int e = t; e < m * dp; e += blockDim.x)
+            rows[(e / dp) * ld + e % dp] = X[(size_t)qb * dp + e];
+        __syncthreads();
+        const int i = t >> 2, j0 = t & 3;
+        const int p = qb + i;
+        const int cl = A.pcl ? A.pcl[min(p, qe - 1)] : -1;
+        const float eps = cl >= 0 ? A.ct[cl].feps : A.eps;
+        int c1 = 0, c2 = 0, ch = 0;
+        float sum = 0.f, dmin = 4.f * eps;
+        if (i < m)
+            for (int j = j0; j < m; j += 4) {
+                if (j == i)
+                    continue;
+                const float *a = rows + i * ld, *b = rows + j * ld;
+                float acc = 0.f;
+                for (int c = 0; c < dp; ++c) {
+                    const float d = a[c] - b[c];
+                    acc = fmaf(d, d, acc);
+                }
+                const float d = key_to_dist<M>(acc);
+                c1 += d <= eps;
+                c2 += d <= 2.f * eps;
+                ch += d <= 0.5f * eps;
+                sum += fminf(d, 16.f * eps);
+                dmin = fminf(dmin, d);
+            }
+        // the four threads of a point are adjacent lanes
+#pragma unroll
+        for (int o = 1; o < 4; o <<= 1) {
+            c1 += __shfl_xor(c1, o, WAVE);
+            c2 += __shfl_xor(c2, o, WAVE);
+            ch += __shfl_xor(ch, o, WAVE);
+            sum += __shfl_xor(sum, o, WAVE);
+            dmin = fminf(dmin, __shfl_xor(dmin, o, WAVE));
+        }
+        if (i < m && j0 == 0) {
+            float *f = feat + (size_t)p * MLP_F;
+            f[8] = log1pf((float)c1) / 6.f;
+            f[9] = log1pf((float)c2) / 6.f;
+            f[10] = log1pf((float)ch) / 6.f;
+            f[11] = sum / ((float)max(m - 1, 1) * eps);
+            f[15] = dmin / eps;
+        }
     }
 }
 
@@ -508,20 +613,34 @@ void compute_features(const fnn_tree *T, const Pts &P, float eps,
     A.eps = eps;
     A.ct = ct;
     A.pcl = ct ? T->pcl : nullptr;
+    A.first_pack = (int)T->nnodes;
+    A.npacks = (int)T->npacks;
     const dim3 g(grid_for(T->n, 256));
+    const bool vec = T->metric == M_L2 || T->metric == M_ANG;
+    // vector rows of at most 128 floats: the pack sample from LDS; larger
+    // packs (duplicates) are still taken by k_features, which then writes
+    // every feature of their points
+    const int local = vec && T->dp <= LOC_MAXD;
     switch (T->metric) {
     case M_L2:
-        FNN_LAUNCH((k_features<M_L2>), g, dim3(256), 0, s, P, A, feat);
+        FNN_LAUNCH((k_features<M_L2>), g, dim3(256), 0, s, P, A, local, feat);
         break;
     case M_ANG:
-        FNN_LAUNCH((k_features<M_ANG>), g, dim3(256), 0, s, P, A, feat);
+        FNN_LAUNCH((k_features<M_ANG>), g, dim3(256), 0, s, P, A, local, feat);
         break;
     case M_HAM:
-        FNN_LAUNCH((k_features<M_HAM>), g, dim3(256), 0, s, P, A, feat);
+        FNN_LAUNCH((k_features<M_HAM>), g, dim3(256), 0, s, P, A, 0, feat);
         break;
     default:
-        FNN_LAUNCH((k_features<M_LEV>), g, dim3(256), 0, s, P, A, feat);
+        FNN_LAUNCH((k_features<M_LEV>), g, dim3(256), 0, s, P, A, 0, feat);
         break;
+    }
+    if (local) {
+        const dim3 gp(grid_cap(T->npacks, 1, 16384));
+        if (T->metric == M_L2)
+            FNN_LAUNCH((k_pack_local<M_L2>), gp, dim3(256), 0, s, P, A, feat);
+        else
+            FNN_LAUNCH((k_pack_local<M_ANG>), gp, dim3(256), 0, s, P, A, feat);
     }
 }
 

@@ -36,6 +36,7 @@ constexpr int TT = 256;   // threads per tile work-group
 constexpr int TS = 64;    // tile side
 constexpr int KC = 32;    // coordinates per LDS stage
 constexpr int LDA = 68;   // padded LDS row (floats)
+constexpr int GP_TILE = 64;  // points of a full pack
 
 struct QView {
     const int32_t *cpos, *pb, *pe, *kbeg, *kcnt, *kids;
@@ -473,8 +474,9 @@ k_tile(Pts P, const int2 *__restrict__ inter, long long ninter,
     __shared__ float dt[DIST ? TS * (TS + 1) : 1];
     const int t = threadIdx.x, ty = t / 16, tx = t % 16;
     unsigned long long rechecks = 0, pairs = 0;
-    for (long long it = blockIdx.x; it < ninter; it += gridDim.x) {
-    const int2 pr = inter[it];
+    __shared__ long long s_next;
+    for (long long it = blockIdx.x; it < ninter;) {
+    const int2 pr = inter[out.order ? (long long)out.order[it] : it];
     const int A = pr.x, B = pr.y;
     const bool diag = A == B;
     const int a0 = q_pb[A], na = q_pe[A] - a0;
@@ -737,6 +739,16 @@ k_tile(Pts P, const int2 *__restrict__ inter, long long ninter,
             }
             __syncthreads();
         }
+    }
+    // next item: the grid stride, or (ordered work) the next free one
+    if (out.next) {
+        if (t == 0)
+            s_next = (long long)gridDim.x + (long long)atomicAdd(out.next, 1ull);
+        __syncthreads();
+        it = s_next;
+        __syncthreads();  // s_next is rewritten after the next item
+    } else {
+        it += gridDim.x;
     }
     }
     rechecks = wave_sum(rechecks);
@@ -1443,6 +1455,56 @@ void sort_csr_rows(const int64_t *row_ptr, int n, int32_t *col, float *dist,
     }
 }
 
+// ---- LPT work order from the cost model (learned schedule) ----------------
+//
+// Graham's LPT rule takes jobs in decreasing size and gives each to the
+// machine that becomes free first (the paper uses it to place Voronoi cells
+// on processes, Section IV-D); it is within 4/3 of the best makespan.  Here
+// the jobs are the tile pass's pack pairs, the machines its work-groups, and
+// the sizes the cost model's predictions, so heavy pairs start first and no
+// work-group is left with a long pair at the end.
+
+// Predicted edge density of every pack: its points' predicted degrees over
+// the point pairs its predicted block pairs hold.
+__global__ void k_pack_density(const float *__restrict__ pred,
+                               const int32_t *__restrict__ q_pb,
+                               const int32_t *__restrict__ q_pe, int nn, int npk,
+                               float *__restrict__ rho)
+{
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < npk;
+         k += gridDim.x * blockDim.x) {
+        const int b = q_pb[nn + k], e = q_pe[nn + k];
+        float deg = 0.f;
+        for (int p = b; p < e; ++p)
+            deg += fmaxf(expm1f(fminf(pred[2 * p + 1], 30.f)), 0.f);
+        const float vis = b < e ? fmaxf(expm1f(fminf(pred[2 * b], 30.f)), 1.f) : 1.f;
+        rho[k] = deg / ((float)max(e - b, 1) * (float)GP_TILE * vis);
+    }
+}
+
+// Sort key of every pack pair: its predicted cost (pair evaluations at
+// dp-proportional cost plus emitted edges), largest first.
+__global__ void k_item_cost(const int2 *__restrict__ inter, long long ni,
+                            const int32_t *__restrict__ q_pb,
+                            const int32_t *__restrict__ q_pe, int nn,
+                            const float *__restrict__ rho, float pair_cost,
+                            float edge_cost, uint32_t *__restrict__ key,
+                            uint32_t *__restrict__ val)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < ni;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int2 pr = inter[i];
+        const float na = (float)(q_pe[pr.x] - q_pb[pr.x]);
+        const float nb = (float)(q_pe[pr.y] - q_pb[pr.y]);
+        const float pairs = pr.x == pr.y ? 0.5f * na * (na - 1.f) : na * nb;
+        const float ra = pr.x >= nn ? rho[pr.x - nn] : 0.f;
+        const float rb = pr.y >= nn ? rho[pr.y - nn] : 0.f;
+        const float cost = pairs * (pair_cost + edge_cost * fminf(ra + rb, 2.f));
+        key[i] = ~__float_as_uint(fmaxf(cost, 0.f));  // descending
+        val[i] = (uint32_t)i;
+    }
+}
+
 // Learned-schedule state of one query.
 struct Learned {
     const float *model = nullptr;  // device parameters (null: no model)
@@ -1657,7 +1719,7 @@ static void eps_graph_impl(const fnn_tree *Tc, const double *epsv,
                 FNN_HIP(hipMemcpyAsync(hacc, acc, sizeof hacc, hipMemcpyDeviceToHost, s));
                 FNN_HIP(hipStreamSynchronize(s));
                 const double fac = prec == FNN_PREC_I8     ? 1.25
-                                   : prec == FNN_PREC_BF16 ? 2.0
+                                   : prec == FNN_PREC_BF16 ? 2.5
                                                                     : 40.0;
                 cap = std::max<long long>(1ll << 20, (long long)(0.5 * hacc[1] * fac));
             }
@@ -1797,7 +1859,29 @@ static void eps_graph_impl(const fnn_tree *Tc, const double *epsv,
         o.spill_cnt = S.get<unsigned long long>(1);
         fill(o.spill_cnt, 0ull, 1, s);
         o.spill_cap = (unsigned long long)spcap;
-        launch_tiles<M>(TILE_FILL, P, plain, nplain, T, E, ct_d, fp64_dist, o, s);
+        {
+            // LPT order of the pack pairs by predicted cost; work-groups take
+            // them through a counter
+            TileOut om = o;
+            if (nplain > 0 && opt.lpt) {
+                const int npk = (int)T->npacks;
+                float *rho = S.get<float>(npk + 1);
+                FNN_LAUNCH(k_pack_density, dim3(grid_for(npk, 256)), dim3(256), 0, s,
+                           Lm.pred, T->q_pt_begin, T->q_pt_end, (int)T->nnodes, npk, rho);
+                uint32_t *k1 = S.get<uint32_t>(nplain), *v1 = S.get<uint32_t>(nplain);
+                uint32_t *k2 = S.get<uint32_t>(nplain), *v2 = S.get<uint32_t>(nplain);
+                // a pair costs about dp multiply-adds, an emitted edge about
+                // 16 instructions (cursor atomic, two stores, bookkeeping)
+                FNN_LAUNCH(k_item_cost, dim3(grid_for(nplain, 256)), dim3(256), 0, s,
+                           plain, nplain, T->q_pt_begin, T->q_pt_end, (int)T->nnodes, rho,
+                           (float)std::max(T->dp, 4), 16.f, k1, v1);
+                radix_sort_pairs(k1, v1, k2, v2, nplain, 32, S);
+                om.order = v2;
+                om.next = S.get<unsigned long long>(1);
+                fill(om.next, 0ull, 1, s);
+            }
+            launch_tiles<M>(TILE_FILL, P, plain, nplain, T, E, ct_d, fp64_dist, om, s);
+        }
         tm.mark();  // 3
         // cursors advanced by every edge, written or not: exact degrees
         o.deg = S.get<int32_t>(n);
@@ -1846,6 +1930,8 @@ static void eps_graph_impl(const fnn_tree *Tc, const double *epsv,
                        plain, nplain, pflag, sub, sc);
             const long long nsub = (long long)read_scalar(sc, s);
             TileOut o2 = o;
+            o2.order = nullptr;  // the sub-list runs in its own order
+            o2.next = nullptr;
             o2.cnt = cnt + 6;  // keep the pass counters of the main pass
             o2.row_end = nullptr;
             o2.ovf = nullptr;

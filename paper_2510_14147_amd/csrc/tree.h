@@ -28,6 +28,7 @@ struct Options {
     int graph_passes = 4;
     int proj = 0;
     long long list_cap = 0;  // initial survivor / edge list entries (0: automatic)
+    int lpt = 0;             // learned schedule: LPT order of the tile pass
 };
 
 Options read_options(const fnn_options *o);

@@ -1,9 +1,11 @@
 """Train the cost model on traces of the 1M x 128 Euclidean workload.
 
-Runs the query with trace capture at the two calibrated radii (~70 and ~500
-mean neighbours), trains the 16-64-64-2 network on the GPU with the
-library's own backward and Adam kernels, and writes the parameters and a
-short report to ``cost_model.json``.
+Runs the query with trace capture at several radii around the calibrated
+~70- and ~500-neighbour ones and on a quarter-density prefix, trains the
+16-64-64-2 network on the GPU with the library's own backward and Adam
+kernels, and writes the parameters and a short report to
+``cost_model.json``.  The held-out check (other draws of the same manifold)
+is tests/test_gpu_learned.py.
 
     python -m paper_2510_14147_amd.train_cost_model [--out PATH] [--n N]
 """
@@ -57,12 +59,21 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=os.path.join(HERE, "cost_model.json"))
     ap.add_argument("--n", type=int, default=1_000_000)
-    ap.add_argument("--epochs", type=int, default=8)
+    ap.add_argument("--epochs", type=int, default=12)
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--lr", type=float, default=2e-3)
     args = ap.parse_args(argv)
+    # several radii and densities, so that no feature value identifies one
+    # trace: the 10^6 set at four radii between the ~70- and ~500-neighbour
+    # ones (and a little below), and a quarter of it (a quarter of the
+    # density) at two larger radii
     x = G.c2_manifold(n=args.n)
-    X, T = traces(x, W["c2"]["eps"])
+    e70, e500 = W["c2"]["eps"]
+    radii = [0.9 * e70, e70, (e70 * e500) ** 0.5, e500]
+    X1, T1 = traces(x, radii)
+    X2, T2 = traces(x[: args.n // 4], [e500, 1.15 * e500])
+    X, T = torch.cat([X1, X2]), torch.cat([T1, T2])
+    del X1, T1, X2, T2
     th = torch.from_numpy(init_params(7)).cuda()
     t0 = time.time()
     losses = fnn.fnn_mlp_train(th, X, T, epochs=args.epochs, batch=args.batch,
@@ -75,7 +86,8 @@ def main(argv=None):
           f"epoch losses {np.round(losses, 4).tolist()}; MAE {mae}", flush=True)
     rep = {"params": th.cpu().numpy().astype(float).tolist(),
            "layout": "W1[64][16] b1[64] W2[64][64] b2[64] W3[2][64] b3[2]",
-           "trained_on": f"c2_manifold n={args.n} d=128, eps={W['c2']['eps']}",
+           "trained_on": f"c2_manifold n={args.n} d=128 at eps={radii}, "
+                         f"and its first {args.n // 4} rows at eps={[e500, 1.15 * e500]}",
            "samples": int(X.shape[0]), "epochs": args.epochs,
            "batch": args.batch, "lr": args.lr, "epoch_loss": losses.tolist(),
            "mae_log1p": {"visits": mae[0], "neighbours": mae[1]},

@@ -220,3 +220,36 @@ def test_learned_schedule_gain_c2_held_out(fnn):
               f"{st['pred_sum_ratio']:.3f}", flush=True)
         assert mae_model < mae_const
         del a, b, rec
+
+
+@pytest.mark.parametrize("case", ["c1", "c5_part"])
+def test_lpt_order_same_graph(fnn, case):
+    """The learned schedule's tile pass in LPT order of predicted cost gives
+    the same CSR as in list order (timings printed for the record)."""
+    import time
+    import torch
+    if case == "c1":
+        x, eps = G.c1_clusters(), W["c1"]["eps"]
+        tree = fnn.fnn_tree_build(x, "l2")
+        run = lambda lpt: fnn.fnn_eps_graph(tree, eps, sched="learned", lpt=lpt)  # noqa: E731
+    else:
+        specs = [s for s in G.c5_cloud_specs() if s["dim"] == 16][:12]
+        xs = [G.c5_cloud(s) for s in specs]
+        off = np.concatenate([[0], np.cumsum([len(v) for v in xs])])
+        x = np.concatenate(xs)
+        eps = [W["c5"]["eps"][s["cloud"]] for s in specs]
+        tree = fnn.fnn_tree_build_batch(x, off, "l2")
+        run = lambda lpt: fnn.fnn_eps_graph_batch(tree, eps, sched="learned", lpt=lpt)  # noqa: E731
+    out = {}
+    for lpt in (False, True, False, True):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g = run(lpt)
+        torch.cuda.synchronize()
+        out.setdefault(lpt, []).append((1e3 * (time.perf_counter() - t0), g))
+    a, b = out[False][-1][1], out[True][-1][1]
+    assert torch.equal(a.row_ptr, b.row_ptr) and torch.equal(a.col, b.col)
+    assert torch.equal(a.dist.view(torch.int32), b.dist.view(torch.int32))
+    print(f"[lpt] {case}: list order {out[False][-1][0]:.1f} ms "
+          f"(tile pass {a.stats['count_ms']:.2f} ms), LPT order {out[True][-1][0]:.1f} ms "
+          f"(tile pass {b.stats['count_ms']:.2f} ms)", flush=True)
