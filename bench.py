@@ -257,6 +257,14 @@ def roofline(dim, precision, tq, workload=""):
             "flops_per_launch": flops}
 
 
+class _Stats:
+    """Stands in for the tree of a landmark run (its build happens inside
+    the call; the graph's stats carry the build figures)."""
+
+    def __init__(self, st):
+        self.stats = st
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -280,6 +288,9 @@ def main():
                     help="points of the oracle cover-tree timing (0: skip)")
     ap.add_argument("--c5-clouds", type=int, default=0,
                     help="use only the first K clouds of c5 (0: all 256)")
+    ap.add_argument("--landmark", type=int, default=0,
+                    help="run the landmark mode with this many Voronoi cells "
+                         "(single-cloud workloads; 0: the direct build + query)")
     ap.add_argument("--tune", action="store_true",
                     help="autotune every batch first (untimed) and run the "
                          "tuned options")
@@ -355,19 +366,27 @@ def main():
             o2 = off if off is not None else np.array([0, xd.shape[0]], np.int64)
             r = fnn.fnn_autotune(xd, o2, m, e, reps=2)
             o = {k: v for k, v in r["best"].items()
-                 if k in ("zeta", "kmax", "precision", "sched")}
+                 if k in ("zeta", "pack", "kmax", "graph_passes", "precision", "sched",
+                          "lpt")}
             tuning.append({"dim": d, "best": o, "best_ms": r["best_ms"],
                            "base_ms": r["base_ms"], "candidates": r["ncand"],
                            "tune_s": time.perf_counter() - t0})
             print(f"[bench] tuned dim={d}: {tuning[-1]}", file=sys.stderr, flush=True)
         opts.append(o)
-    BUILD_KEYS = ("zeta", "kmax")
+    BUILD_KEYS = ("zeta", "pack", "kmax", "graph_passes")
 
     INV_PREC = {v: k for k, v in fnn.PRECISIONS.items()}
 
     def run_job(xd, off, m, e, o, precision):
         """Build + query of one job: (tree, graph)."""
         bo = {k: v for k, v in o.items() if k in BUILD_KEYS}
+        if args.landmark > 0 and off is None and args.workload != "c2q":
+            g = fnn.fnn_landmark_eps_graph(xd, e, args.landmark, metric=m, seed=1,
+                                           precision=precision, sched=o["sched"],
+                                           proj=o.get("proj", 0),
+                                           **{k: v for k, v in bo.items()
+                                              if k in ("zeta", "pack", "kmax")})
+            return _Stats(g.stats), g
         if args.workload == "c2q":
             # tree over the first 1M rows, bichromatic query of the rest
             tree = fnn.fnn_tree_build(xd[:1_000_000], m, **bo)
@@ -376,11 +395,11 @@ def main():
         elif off is None:
             tree = fnn.fnn_tree_build(xd, m, **bo)
             g = fnn.fnn_eps_graph(tree, e, precision=precision, sched=o["sched"],
-                                  proj=o.get("proj", 0))
+                                  proj=o.get("proj", 0), lpt=bool(o.get("lpt", 0)))
         else:
             tree = fnn.fnn_tree_build_batch(xd, off, m, **bo)
             g = fnn.fnn_eps_graph_batch(tree, e, precision=precision, sched=o["sched"],
-                                        proj=o.get("proj", 0))
+                                        proj=o.get("proj", 0), lpt=bool(o.get("lpt", 0)))
         return tree, g
 
     kept = []
@@ -438,7 +457,8 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
-        "config": {"workload": desc, "n": int(n_all),
+        "config": {"workload": desc + (f"_landmark{args.landmark}" if args.landmark else ""),
+                   "n": int(n_all),
                    "dim": None if groups else jobs[0][4], "metric": metric,
                    "eps": None if groups else eps, "precision": "+".join(precs),
                    "sched": "+".join(sorted({o["sched"] for o in opts})),
@@ -458,6 +478,11 @@ def main():
                      "rounds": max(x[0]["rounds"] for x in last),
                      "netsel_passes": agg("netsel_passes", 0)},
         "roofline": roof,
+        # launches of one step: kernels launched eagerly, recorded launch
+        # sequences replayed, and the kernels those replays ran
+        "launches": {"kernels": agg("launches", 0) + agg("launches", 1),
+                     "graph_replays": agg("graph_launches", 0) + agg("graph_launches", 1),
+                     "graph_kernels": agg("graph_kernels", 0) + agg("graph_kernels", 1)},
     }
     if tuning:
         out["tuned"] = tuning

@@ -44,8 +44,8 @@ typedef enum {
     FNN_ANGULAR = 1,     /* float32 rows [n x dim], no zero row, same bound   */
     FNN_HAMMING = 2,     /* uint64 rows [n x dim/64]; dim = bits, % 64 == 0   */
     FNN_LEVENSHTEIN = 3  /* uint8 rows [n x dim]; dim = row stride in bytes,  */
-                         /* symbols < 32, padded with 0xFF; length = index of */
-                         /* the first 0xFF (or dim); dim <= 256               */
+                         /* symbols 0..254, padded with 0xFF; length = index  */
+                         /* of the first 0xFF (or dim); dim <= 256            */
 } fnn_metric;
 
 /* Error codes. */
@@ -180,6 +180,9 @@ typedef struct fnn_stats {
     double landmark_partition_ms; /* centres, cells, ghosts, gathered rows    */
     double landmark_forest_ms;    /* per-cell forest build and self-join      */
     double landmark_merge_ms;     /* pairs kept once, rows mapped and sorted  */
+    int64_t launches;         /* kernels launched eagerly by the call         */
+    int64_t graph_launches;   /* recorded launch sequences replayed           */
+    int64_t graph_kernels;    /* kernels those replays ran                    */
     double reserved[1];
 } fnn_stats;
 
@@ -221,7 +224,7 @@ int fnn_eps_query(const fnn_tree *tree, const void *queries, int64_t nq, double 
  * together) and the batched query (Algorithm 3 over query batches) extend to
  * a forest: each cloud gets its own cover tree, and the hubs and vertex
  * pairs of all clouds share every kernel launch.  This is also the shape of
- * the per-cell trees of the landmark partitioning (Section IV-C).
+ * the per-cell trees of the landmark partitioning (Section IV-D).
  *
  * fnn_tree_build_batch: points holds the rows of all clouds back to back
  * (device, layout per metric, one dim for all); cloud c is rows
@@ -248,14 +251,19 @@ int fnn_eps_graph_batch(const fnn_tree *tree, const double *eps,
  * after one untimed run) under candidate options on the caller's input and
  * returns the fastest.  Candidates differ only in options that never change
  * the graph: filter precision (FP32 / BF16 for vector metrics with
- * dim <= 128, FP32 / I8 for Hamming codes of <= 256 bits), schedule (two-pass / learned, when a cost model is
- * installed), zeta in {32, 64, 128} and kmax in {32, 64, 128}, searched by
- * coordinate descent from `base` (NULL: defaults; its trace and validate
- * are ignored).  points / offsets / nclouds / dim / metric / eps as in
+ * dim <= 128, FP32 / I8 for Hamming codes of <= 256 bits), schedule
+ * (two-pass / learned, when a cost model is installed), zeta in
+ * {32, 64, 128}, kmax in {32, 64, 128}, the tile block size pack in
+ * {32, 64} (not for strings), the net-selection passes per graph replay
+ * graph_passes in {2, 4, 8} (the granularity of the build's device queue)
+ * and, for the learned schedule, lpt in {0, 1}; searched by coordinate
+ * descent from `base` (NULL: defaults; its trace and validate are
+ * ignored).  points / offsets / nclouds / dim / metric / eps as in
  * fnn_tree_build_batch and fnn_eps_graph_batch (one cloud: offsets =
  * {0, n}).  Answers are cached in-process per (metric, dim, log2 n,
- * log2 nclouds, base zeta / kmax / precision / sched); a cached answer is
- * returned at once with cached = 1.  fnn_autotune_clear empties the cache. */
+ * log2 nclouds, base zeta / pack / kmax / graph_passes / precision / sched
+ * / proj / lpt); a cached answer is returned at once with cached = 1.
+ * fnn_autotune_clear empties the cache. */
 typedef struct fnn_tune_result {
     fnn_options best;     /* fastest options found                           */
     double best_ms;       /* their median build + query time                 */

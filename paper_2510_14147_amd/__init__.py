@@ -78,6 +78,8 @@ class fnn_stats(ctypes.Structure):
                  ("landmark_partition_ms", ctypes.c_double),
                  ("landmark_forest_ms", ctypes.c_double),
                  ("landmark_merge_ms", ctypes.c_double),
+                 ("launches", ctypes.c_int64), ("graph_launches", ctypes.c_int64),
+                 ("graph_kernels", ctypes.c_int64),
                  ("reserved", ctypes.c_double * 1)])
 
 
@@ -203,7 +205,7 @@ def _stats(handle) -> dict:
     return {k: getattr(s, k) for k in _STAT_I64 + _STAT_F64 +
             ["proj_dim", "proj_captured", "precision_used", "landmark_cells",
              "landmark_rows", "landmark_partition_ms", "landmark_forest_ms",
-             "landmark_merge_ms"]}
+             "landmark_merge_ms", "launches", "graph_launches", "graph_kernels"]}
 
 
 class Tree:
@@ -341,7 +343,7 @@ def fnn_eps_graph_batch(tree: Tree, eps, precision="fp32", sched="two_pass",
     return Graph(out)
 
 
-_OPT_KEYS = ("zeta", "pack", "precision", "sched", "kmax", "graph_passes", "proj")
+_OPT_KEYS = ("zeta", "pack", "precision", "sched", "kmax", "graph_passes", "proj", "lpt")
 
 
 def fnn_autotune(points, offsets, metric: str, eps, reps: int = 2, **base) -> dict:

@@ -97,6 +97,18 @@ Options read_options(const fnn_options *o)
     return r;
 }
 
+// Launches of one call, from the thread's counters.
+struct LaunchDelta {
+    LaunchCount c0 = launch_count();
+    void into(fnn_stats &st) const
+    {
+        const LaunchCount &c = launch_count();
+        st.launches = c.kernels - c0.kernels;
+        st.graph_launches = c.graphs - c0.graphs;
+        st.graph_kernels = c.graph_kernels - c0.graph_kernels;
+    }
+};
+
 struct CsrBox {
     fnn_csr pub;
     fnn_stats stats;
@@ -222,8 +234,12 @@ static int tree_build_any(const void *points, int64_t n, const int64_t *offsets,
         }
         T->ncloud = (int)T->cloud_src.size();
         T->dp = row_stride(metric, dim);
-        Scratch S(current_stream());
-        build_tree(T, points, S);
+        LaunchDelta ld;
+        {
+            Scratch S(current_stream());
+            build_tree(T, points, S);
+        }
+        ld.into(T->stats);
         *out = T;
         return FNN_OK;
     } catch (const Error &e) {
@@ -295,11 +311,13 @@ static int eps_graph_any(const fnn_tree *tree, const double *eps, int32_t neps,
         memset(&B->stats, 0, sizeof B->stats);
         B->trace_feat = B->trace_targ = nullptr;
         B->pub.kind = KIND_CSR;
+        LaunchDelta ld;
         {
             Scratch S(current_stream());
             eps_graph(tree, ev.data(), o, &B->pub, B->stats, S, &B->trace_feat,
                       &B->trace_targ);
         }
+        ld.into(B->stats);
         *out = &B->pub;
         return FNN_OK;
     } catch (const Error &e) {
@@ -450,10 +468,12 @@ int fnn_landmark_eps_graph(const void *points, int64_t n, int32_t dim,
         memset(&B->stats, 0, sizeof B->stats);
         B->trace_feat = B->trace_targ = nullptr;
         B->pub.kind = KIND_CSR;
+        LaunchDelta ld;
         {
             Scratch S(current_stream());
             landmark_graph(&hdr, points, eps, ncells, seed, opt, &B->pub, B->stats, S);
         }
+        ld.into(B->stats);
         *out = &B->pub;
         return FNN_OK;
     } catch (const Error &e) {

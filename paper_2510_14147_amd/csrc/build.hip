@@ -1800,12 +1800,27 @@ static int total_kids(const fnn_tree *T, hipStream_t s)
     return (int)m;
 }
 
+// Match-mask table of n strings widened from sigma_in to sigma_out symbols
+// (a symbol a string does not hold has an empty mask).
+__global__ void k_widen_peq(const uint64_t *__restrict__ in, int n, int sig_in, int W,
+                            int sig_out, uint64_t *__restrict__ out)
+{
+    const long long tot = (long long)n * sig_out * W;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < tot;
+         e += (long long)gridDim.x * blockDim.x) {
+        const long long i = e / ((long long)sig_out * W);
+        const int r = (int)(e % ((long long)sig_out * W));
+        const int c = r / W, w = r % W;
+        out[e] = c < sig_in ? in[(i * sig_in + c) * W + w] : 0ull;
+    }
+}
+
 fnn_tree *forest_pair(const fnn_tree *A, const fnn_tree *B, Scratch &S)
 {
     hipStream_t s = S.stream();
-    if (A->metric != B->metric || A->dp != B->dp || A->dim != B->dim || A->W != B->W ||
-        A->sigma != B->sigma)
-        fail(FNN_EINVAL, "query rows do not match the tree's metric and dimension");
+    if (A->metric != B->metric || A->dp != B->dp || A->dim != B->dim || A->W != B->W)
+        fail(FNN_EINVAL, "query rows do not match the tree's metric and dimension "
+             "(metric %d / %d, dim %d / %d)", A->metric, B->metric, A->dim, B->dim);
     if (A->ncloud != 1 || B->ncloud != 1)
         fail(FNN_EUNSUPPORTED, "bichromatic queries need single-cloud trees");
     if ((int64_t)A->n + B->n >= INT32_MAX)
@@ -1818,7 +1833,9 @@ fnn_tree *forest_pair(const fnn_tree *A, const fnn_tree *B, Scratch &S)
         F->dim = A->dim;
         F->dp = A->dp;
         F->W = A->W;
-        F->sigma = A->sigma;
+        // strings: one alphabet for both sets (each built its table for its
+        // own largest symbol)
+        F->sigma = std::max(A->sigma, B->sigma);
         F->opt = A->opt;
         auto cat = [&](const void *a, const void *b, size_t row_bytes) -> void * {
             if (!a)
@@ -1834,7 +1851,15 @@ fnn_tree *forest_pair(const fnn_tree *A, const fnn_tree *B, Scratch &S)
         F->h = (uint64_t *)cat(A->h, B->h, sizeof(uint64_t) * A->dp);
         F->s = (uint8_t *)cat(A->s, B->s, (size_t)A->dp);
         F->len = (int32_t *)cat(A->len, B->len, sizeof(int32_t));
-        F->peq = (uint64_t *)cat(A->peq, B->peq, sizeof(uint64_t) * A->sigma * A->W);
+        if (A->peq) {
+            const int sg = F->sigma, W = A->W;
+            F->peq = (uint64_t *)F->own(sizeof(uint64_t) * (size_t)n * sg * W);
+            FNN_LAUNCH(k_widen_peq, dim3(grid_cap((int64_t)nA * sg * W, 256, 8192)),
+                       dim3(256), 0, s, A->peq, nA, A->sigma, W, sg, F->peq);
+            FNN_LAUNCH(k_widen_peq, dim3(grid_cap((int64_t)nB * sg * W, 256, 8192)),
+                       dim3(256), 0, s, B->peq, nB, B->sigma, W, sg,
+                       F->peq + (size_t)nA * sg * W);
+        }
         F->perm = (int32_t *)F->own(sizeof(int32_t) * n);
         FNN_HIP(hipMemcpyAsync(F->perm, A->perm, sizeof(int32_t) * nA,
                                hipMemcpyDeviceToDevice, s));

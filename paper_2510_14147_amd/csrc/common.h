@@ -15,7 +15,7 @@ enum { M_L2 = 0, M_ANG = 1, M_HAM = 2, M_LEV = 3 };
 constexpr int LOFF = 200;
 constexpr int NLEV = 400;
 constexpr int MAX_LEV_WORDS = 4;   // strings of up to 256 symbols
-constexpr int MAX_SIGMA = 32;      // Levenshtein alphabet
+constexpr int MAX_SIGMA = 255;     // Levenshtein symbols 0..254 (0xFF pads)
 constexpr int WAVE = 64;
 
 // Error flags raised by kernels (bitmask in a device word).

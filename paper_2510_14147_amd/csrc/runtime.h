@@ -28,10 +28,21 @@ struct Error {
                         hipGetErrorString(e_), __FILE__, __LINE__);          \
     } while (0)
 
+// Launches issued by this thread (kernels launched eagerly, graphs
+// replayed); kernels recorded into a graph count when it is replayed.
+struct LaunchCount {
+    long long kernels = 0, graphs = 0, graph_kernels = 0;
+    bool capturing = false;
+};
+LaunchCount &launch_count();
+
 #define FNN_LAUNCH(kernel, grid, block, shmem, stream, ...)                  \
     do {                                                                     \
         hipLaunchKernelGGL(kernel, grid, block, shmem, stream, __VA_ARGS__); \
         FNN_HIP(hipGetLastError());                                          \
+        ::fnn::LaunchCount &lc_ = ::fnn::launch_count();                     \
+        if (!lc_.capturing)                                                  \
+            ++lc_.kernels;                                                   \
     } while (0)
 
 hipStream_t current_stream();
@@ -48,6 +59,7 @@ struct GraphRun {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     bool capturing = false;
+    long long nkernels = 0;  // kernel nodes recorded
     GraphRun() = default;
     GraphRun(const GraphRun &) = delete;
     GraphRun &operator=(const GraphRun &) = delete;

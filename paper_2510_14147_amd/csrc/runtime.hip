@@ -65,8 +65,16 @@ int num_cus()
     return c;
 }
 
+LaunchCount &launch_count()
+{
+    static thread_local LaunchCount c;
+    return c;
+}
+
 GraphRun::~GraphRun()
 {
+    if (capturing)
+        launch_count().capturing = false;
     if (capturing) {  // an error left the recording open: close and drop it
         hipGraph_t g = nullptr;
         (void)hipStreamEndCapture(cs, &g);
@@ -84,6 +92,7 @@ void GraphRun::begin()
     cs = capture_stream();
     FNN_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     capturing = true;
+    launch_count().capturing = true;
 }
 
 void GraphRun::end()
@@ -91,13 +100,23 @@ void GraphRun::end()
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(cs, &g);
     capturing = false;
+    launch_count().capturing = false;
     if (e != hipSuccess || !g)
         fail(-3, "graph capture failed: %s", hipGetErrorString(e));
     graph = g;
+    size_t nn = 0;
+    FNN_HIP(hipGraphGetNodes(graph, nullptr, &nn));
+    nkernels = (long long)nn;
     FNN_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
 }
 
-void GraphRun::launch(hipStream_t s) { FNN_HIP(hipGraphLaunch(exec, s)); }
+void GraphRun::launch(hipStream_t s)
+{
+    FNN_HIP(hipGraphLaunch(exec, s));
+    LaunchCount &c = launch_count();
+    ++c.graphs;
+    c.graph_kernels += nkernels;
+}
 
 // --------------------------------------------------------------- scratch --
 //

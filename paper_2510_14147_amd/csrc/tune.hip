@@ -4,8 +4,10 @@
 // candidate's result is the exact graph.
 //
 // Search: coordinate descent from the defaults (or the caller's base
-// options): filter precision, then CSR schedule, then leaf size zeta, then
-// the net-selection width kmax; each coordinate keeps its best value before
+// options): filter precision, then CSR schedule, then leaf size zeta, the
+// net-selection width kmax, the tile block (pack) size, the passes per
+// net-selection graph replay (queue granularity) and, for the learned
+// schedule, the LPT work order; each coordinate keeps its best value before
 // the next is tried.  Answers are cached in-process per input shape (metric,
 // dim, log2 n, log2 clouds, base options); a cached answer is returned
 // without timing.
@@ -112,10 +114,15 @@ extern "C" int fnn_autotune(const void *points, const int64_t *offsets,
             o0.zeta = d.zeta;
         if (!o0.kmax)
             o0.kmax = d.kmax;
+        if (!o0.pack && metric != FNN_LEVENSHTEIN)
+            o0.pack = d.pack;
+        if (!o0.graph_passes)
+            o0.graph_passes = d.graph_passes;
     }
 
-    const Key key{(int)metric, (int)dim, ilog2(n), ilog2(nclouds), o0.zeta, o0.kmax,
-                  (o0.precision * 8 + o0.sched) * 256 + (o0.proj + 1)};
+    const Key key{(int)metric, (int)dim, ilog2(n), ilog2(nclouds),
+                  o0.zeta * 4096 + o0.pack, o0.kmax * 256 + o0.graph_passes,
+                  ((o0.precision * 8 + o0.sched) * 256 + (o0.proj + 1)) * 2 + (o0.lpt ? 1 : 0)};
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune_cache.find(key);
@@ -170,6 +177,15 @@ extern "C" int fnn_autotune(const void *points, const int64_t *offsets,
         try_values(&fnn_options::sched, {FNN_SCHED_TWO_PASS, FNN_SCHED_LEARNED});
     try_values(&fnn_options::zeta, {32, 64, 128});
     try_values(&fnn_options::kmax, {32, 64, 128});
+    // tile shape of the leaf work: points per query / leaf block (strings
+    // keep one leaf block per pack)
+    if (metric != FNN_LEVENSHTEIN)
+        try_values(&fnn_options::pack, {32, 64});
+    // queue granularity of the build: net-selection passes per graph replay
+    // between host checks of the device queue
+    try_values(&fnn_options::graph_passes, {2, 4, 8});
+    if (best.sched == FNN_SCHED_LEARNED)
+        try_values(&fnn_options::lpt, {0, 1});
 
     out->best = best;
     out->best_ms = best_ms;

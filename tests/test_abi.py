@@ -126,4 +126,4 @@ def test_options_struct_matches_header():
     assert [f[0] for f in fnn_tune_result._fields_] == _header_fields("fnn_tune_result")
     assert ctypes.sizeof(fnn_tune_result) == 64 + 8 + 8 + 4 + 4 + 4 * 8
     assert ctypes.sizeof(fnn_csr) == 8 + 8 + 8 + 3 * 8
-    assert ctypes.sizeof(fnn_stats) == 17 * 8 + 12 * 8 + 8 + 8 + 8 + 5 * 8 + 8
+    assert ctypes.sizeof(fnn_stats) == 17 * 8 + 12 * 8 + 8 + 8 + 8 + 5 * 8 + 3 * 8 + 8

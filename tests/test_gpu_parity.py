@@ -114,11 +114,14 @@ def test_complete_graph_scatter(fnn, orc, prec):
 
 
 def test_row_sort_lengths(fnn, orc):
-    # separated tight clusters, complete inside: their rows take every path
-    # of the per-row sort (one entry per lane; a wave's registers up to 512,
-    # 1024 and 2048 entries; a work-group in LDS up to 4096; a global buffer
-    # beyond)
-    sizes = [50, 300, 600, 1100, 2100, 4200]
+    # separated tight clusters, complete inside, so a row of a cluster of m
+    # points holds m - 1 entries and takes one path of the per-row sort:
+    #   49 / 99 / 199 / 299 entries: one wave, 1 / 2 / 4 / 8 keys per lane
+    #   (k_sort_small); 599 and 1099: one wave, 16 and 32 keys per lane
+    #   (k_sort_wave); 2099: four waves in registers, the longest strides
+    #   through LDS (k_sort_blk<4>); 4199: sixteen waves (k_sort_blk<16>).
+    # Rows beyond 16384 entries (k_sort_long) are test_long_rows_sorted's.
+    sizes = [50, 100, 200, 300, 600, 1100, 2100, 4200]
     parts = [np.float32(100.0 * k) + G.random_points(m, 3, seed=20 + k, scale=0.01)
              for k, m in enumerate(sizes)]
     x = np.concatenate(parts).astype(np.float32)

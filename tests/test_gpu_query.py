@@ -83,6 +83,32 @@ def test_query_levenshtein(fnn, orc):
     check_query(fnn, orc, X[:1000], X[1000:], "levenshtein", 6)
 
 
+def test_query_levenshtein_alphabets_differ(fnn, orc):
+    """Queries over a smaller alphabet than the tree's, and queries holding a
+    symbol the tree never uses: the pair forest takes one alphabet for
+    both sets."""
+    X = G.random_strings(1200, seed=46, n_seeds=24, min_len=30, max_len=70, p_edit=0.04)
+    P, Q = X[:800].copy(), X[800:].copy()
+    P[P == 3] = 7                      # tree alphabet {0, 1, 2, 7}: sigma 8
+    check_query(fnn, orc, P, Q, "levenshtein", 6)      # queries: sigma 4
+    Q2 = Q.copy()
+    Q2[Q2 == 2] = 200                  # a symbol the tree lacks
+    check_query(fnn, orc, P, Q2, "levenshtein", 6)
+
+
+def test_levenshtein_large_alphabet(fnn, orc):
+    """Symbols up to 254 (0xFF pads the rows)."""
+    rng = np.random.default_rng(47)
+    X = G.random_strings(1500, seed=47, n_seeds=30, min_len=20, max_len=60, p_edit=0.05)
+    lut = rng.permutation(255).astype(np.uint8)
+    Y = np.where(X == 0xFF, X, lut[np.minimum(X, 254)]).astype(np.uint8)
+    tree = fnn.fnn_tree_build(Y, "levenshtein")
+    g = fnn.fnn_eps_graph(tree, 5.0)
+    ref = orc.bruteforce(Y, MID["levenshtein"], 5.0)
+    cmp = orc.compare_csr(*g.to_numpy(), *ref)
+    assert cmp["ok"] and cmp["ref_nnz"] > 1000, cmp
+
+
 def test_query_edge_cases(fnn, orc):
     P = G.random_points(2000, 3, seed=46)
     check_query(fnn, orc, P, P[7:8].copy(), "l2", 0.2)               # one query

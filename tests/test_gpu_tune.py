@@ -11,7 +11,7 @@ pytestmark = pytest.mark.gpu
 
 MID = {"l2": 0, "angular": 1, "hamming": 2, "levenshtein": 3}
 BUILD = ("zeta", "pack", "kmax", "graph_passes")
-QUERY = ("precision", "sched")
+QUERY = ("precision", "sched", "lpt")
 
 
 @pytest.fixture(scope="module")
@@ -62,7 +62,8 @@ def test_tune_batch_l2(fnn, orc):
     X = np.concatenate(clouds)
     eps = [0.1 + 0.05 * i for i in range(len(clouds))]
     cands = [dict(precision="bf16"), dict(sched="learned"), dict(zeta=32),
-             dict(zeta=128), dict(kmax=32), dict(kmax=128)]
+             dict(zeta=128), dict(kmax=32), dict(kmax=128), dict(pack=32),
+             dict(graph_passes=2), dict(graph_passes=8), dict(sched="learned", lpt=True)]
     rp, col, dist = check_tuner(fnn, orc, X, off, "l2", eps, cands)
     # and the graph is the oracle's (first cloud)
     n0 = int(off[1])
@@ -74,7 +75,21 @@ def test_tune_single_hamming(fnn, orc):
     x = G.random_codes(6000, 256, seed=8, flip=0.07)
     off = np.array([0, len(x)], np.int64)
     cands = [dict(zeta=32), dict(zeta=128), dict(kmax=32), dict(kmax=128),
-             dict(sched="learned")]
+             dict(sched="learned"), dict(pack=32), dict(graph_passes=2)]
     rp, col, dist = check_tuner(fnn, orc, x, off, "hamming", [20.0], cands)
     ref = orc.bruteforce(x, MID["hamming"], 20.0)
     assert np.array_equal(rp, ref[0]) and np.array_equal(col, ref[1])
+
+
+def test_launch_counts_reported(fnn):
+    """Stats carry the launches of a call: eager kernels, graph replays and
+    the kernels those replays ran."""
+    x = G.c1_clusters()
+    t = fnn.fnn_tree_build(x, "l2")
+    g = fnn.fnn_eps_graph(t, 0.1)
+    bs, qs = t.stats, g.stats
+    print(f"[launches] build: {bs['launches']} kernels + {bs['graph_launches']} graph "
+          f"replays ({bs['graph_kernels']} kernels); query: {qs['launches']} kernels",
+          flush=True)
+    assert bs["launches"] > 0 and qs["launches"] > 0
+    assert bs["graph_launches"] > 0 and bs["graph_kernels"] >= bs["graph_launches"]
