@@ -102,9 +102,12 @@ typedef struct fnn_options {
     int32_t slack_pct;    /* learned schedule: slot slack in percent of the  */
                           /* predicted row length (default 30; may be < 0)   */
     int32_t graph_passes; /* build: net-selection passes recorded into one  */
-                          /* hipGraph and replayed between host checks      */
-                          /* (default 4, rounded up to even; 1 = one eager  */
-                          /* pass per host check)                           */
+                          /* hipGraph and replayed between host checks;     */
+                          /* query: traversal levels recorded the same way  */
+                          /* over device-resident frontier queues (a level  */
+                          /* that may not fit stops them; eager levels      */
+                          /* finish).  Default 4, rounded up to even; 1 =   */
+                          /* one eager pass / level per host check          */
     int32_t proj;         /* BF16 / FP8 filter on the K leading principal    */
                           /* coordinates (a conservative bound: |Q^T(x-y)|   */
                           /* <= ||Q|| |x-y|): 0 = K the smallest multiple of */
@@ -113,11 +116,13 @@ typedef struct fnn_options {
                           /* -1 = none; 16..128 in steps of 16 = that K;     */
                           /* else EINVAL                                     */
     int32_t list_cap;     /* initial capacity (entries) of the MFMA filter's */
-                          /* survivor list and of the plain tiles' edge     */
-                          /* list; 0 = automatic (default).  A list that    */
-                          /* overflows is redone: the filter runs again     */
-                          /* into a list sized from its count, the tiles    */
-                          /* fall back to the count / fill pair of passes.  */
+                          /* survivor list, of the plain tiles' edge list   */
+                          /* and of the traversal's replayed frontier and   */
+                          /* interaction buffers; 0 = automatic (default).  */
+                          /* A list that overflows is redone: the filter    */
+                          /* runs again into a list sized from its count,   */
+                          /* the tiles fall back to the count / fill pair   */
+                          /* of passes, the traversal finishes eagerly.     */
                           /* Results never depend on it; small values force */
                           /* those paths (tests).                           */
     int32_t lpt;          /* learned schedule: 1 = the tile pass takes its   */

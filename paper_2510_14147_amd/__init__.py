@@ -327,7 +327,7 @@ def fnn_tree_build_batch(points, offsets, metric: str = "l2", zeta=None,
 
 def fnn_eps_graph_batch(tree: Tree, eps, precision="fp32", sched="two_pass",
                         validate=False, trace=False, slack_pct=None,
-                        proj=None, list_cap=None, lpt=False) -> Graph:
+                        proj=None, list_cap=None, lpt=False, graph_passes=None) -> Graph:
     """Per-cloud thresholds ``eps[c]``; one block-diagonal CSR over all rows."""
     if sched == "learned" and not _model_set and os.path.exists(COST_MODEL_PATH):
         fnn_set_cost_model(load_cost_model())
@@ -336,7 +336,7 @@ def fnn_eps_graph_batch(tree: Tree, eps, precision="fp32", sched="two_pass",
     out = ctypes.POINTER(fnn_csr)()
     o = _options(precision=precision, sched=sched, validate=int(validate),
                  trace=int(trace), slack_pct=slack_pct, proj=proj, list_cap=list_cap,
-                 lpt=int(lpt))
+                 lpt=int(lpt), graph_passes=graph_passes)
     _check(lib().fnn_eps_graph_batch(
         tree.handle, e.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), e.size,
         ctypes.byref(o), ctypes.byref(out)))
@@ -401,18 +401,20 @@ def load_cost_model(path: str = COST_MODEL_PATH) -> np.ndarray:
 
 def fnn_eps_graph(tree: Tree, eps: float, precision="fp32",
                   sched="two_pass", validate=False, trace=False,
-                  slack_pct=None, proj=None, list_cap=None, lpt=False) -> Graph:
+                  slack_pct=None, proj=None, list_cap=None, lpt=False,
+                  graph_passes=None) -> Graph:
     """proj: filter on leading principal coordinates (None / 0 automatic,
     -1 off, else their number, a multiple of 16).  list_cap: initial
     survivor / edge list capacity (None: automatic; small values force the
-    overflow paths)."""
+    overflow paths).  graph_passes: traversal levels per replayed graph (1:
+    every level eager)."""
     if sched == "learned" and not _model_set and os.path.exists(COST_MODEL_PATH):
         fnn_set_cost_model(load_cost_model())
     _bind_stream()
     out = ctypes.POINTER(fnn_csr)()
     o = _options(precision=precision, sched=sched, validate=int(validate),
                  trace=int(trace), slack_pct=slack_pct, proj=proj, list_cap=list_cap,
-                 lpt=int(lpt))
+                 lpt=int(lpt), graph_passes=graph_passes)
     _check(lib().fnn_eps_graph_ex(tree.handle, float(eps), ctypes.byref(o),
                                   ctypes.byref(out)))
     return Graph(out)
@@ -420,7 +422,7 @@ def fnn_eps_graph(tree: Tree, eps: float, precision="fp32",
 
 def fnn_eps_query(tree: Tree, queries, eps: float, precision="fp32",
                   sched="two_pass", validate=False, proj=None, zeta=None,
-                  pack=None, kmax=None) -> Graph:
+                  pack=None, kmax=None, graph_passes=None) -> Graph:
     """Bichromatic range query: rows of ``queries`` (the tree's metric and
     dim) against the tree's points; a CSR with one row per query, columns =
     the tree's input indices."""
@@ -430,7 +432,7 @@ def fnn_eps_query(tree: Tree, queries, eps: float, precision="fp32",
     _bind_stream()
     out = ctypes.POINTER(fnn_csr)()
     o = _options(precision=precision, sched=sched, validate=int(validate), proj=proj,
-                 zeta=zeta, pack=pack, kmax=kmax)
+                 zeta=zeta, pack=pack, kmax=kmax, graph_passes=graph_passes)
     _check(lib().fnn_eps_query(tree.handle, ctypes.c_void_p(t.data_ptr()), t.shape[0],
                                float(eps), ctypes.byref(o), ctypes.byref(out)))
     return Graph(out)

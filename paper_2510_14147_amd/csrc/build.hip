@@ -441,11 +441,19 @@ k_update(Pts P, const int32_t *__restrict__ ch_hub, const int32_t *__restrict__ 
 #pragma unroll
                             for (int i = 0; i < NI; ++i)
                                 acc[k][i] = 0.f;
+                        float4 vn[UPD_P];
+#pragma unroll
+                        for (int k = 0; k < UPD_P; ++k)
+                            vn[k] = *reinterpret_cast<const float4 *>(rows[k]);
                         for (int c = 0; c < dp; c += 4) {
                             float4 v[UPD_P];
 #pragma unroll
-                            for (int k = 0; k < UPD_P; ++k)
-                                v[k] = *reinterpret_cast<const float4 *>(rows[k] + c);
+                            for (int k = 0; k < UPD_P; ++k) {
+                                v[k] = vn[k];
+                                // next coordinates in flight while these are used
+                                vn[k] = *reinterpret_cast<const float4 *>(
+                                    rows[k] + (c + 4 < dp ? c + 4 : c));
+                            }
 #pragma unroll
                             for (int i = 0; i < NI; ++i) {
                                 const int j = UPD_P * i + qd;

@@ -96,7 +96,8 @@ __global__ void k_prune_sample(Pts P, QView Q, Prune pr, int npk, int ns,
 struct Emit {
     int2 *next;
     int2 *inter;
-    unsigned long long *cnt;  // [0] next, [1] inter, [2] tests
+    // running counts: next frontier, interactions, node tests
+    unsigned long long *cnt_next, *cnt_inter, *cnt_tests;
     long long next_cap, inter_cap;
     int *overflow;
 };
@@ -118,7 +119,7 @@ __device__ __forceinline__ void stage_flush(const Emit &E, Stage &sg, int k)
         return;
     unsigned long long base = 0;
     if (lane == 0)
-        base = atomicAdd(&E.cnt[k], (unsigned long long)c);
+        base = atomicAdd(k ? E.cnt_inter : E.cnt_next, (unsigned long long)c);
     base = __shfl(base, 0, WAVE);
     int2 *dst = k ? E.inter : E.next;
     const long long cap = k ? E.inter_cap : E.next_cap;
@@ -381,7 +382,106 @@ k_expand(Pts P, QView Q, Prune pr, const int2 *__restrict__ cur, long long ncur,
     stage_flush(E, sg, 1);
     tests = wave_sum(tests);
     if (lane == 0 && tests)
-        atomicAdd(&E.cnt[2], tests);
+        atomicAdd(E.cnt_tests, tests);
+}
+
+// ---- device-queue levels (replayed from a graph) ---------------------------
+//
+// The same expansion with the frontier's length in device memory: a level
+// reads its length, bounds its output, and stops (keeping its frontier, and
+// every later level with it) when the bound does not fit the buffers, so a
+// fixed sequence of levels can be recorded once into a graph and replayed
+// until the frontier is empty; the host only reads the length between
+// replays, and finishes with the eager loop after a stop.
+
+__global__ void k_expand_bound_d(QView Q, const int2 *__restrict__ cur,
+                                 const unsigned long long *__restrict__ ncur_p,
+                                 long long cap, const int *__restrict__ halt,
+                                 unsigned long long *__restrict__ bound)
+{
+    if (*halt)
+        return;
+    // (a length never exceeds the buffer: the guard stops a level whose
+    // bound does not fit; the clamp only keeps reads inside regardless)
+    const long long ncur = min((long long)*ncur_p, cap);
+    unsigned long long b = 0;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < ncur;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int2 p = cur[i];
+        const int a = p.x, c = p.y;
+        if (c < 0) {
+            b += (unsigned long long)(Q.kcnt[a] - (-1 - c));
+        } else if (a == c) {
+            const long long m = a >= Q.nn ? 1 : Q.kcnt[a];
+            b += m > SELF_SPLIT ? (unsigned long long)m : (unsigned long long)(m * (m + 1) / 2);
+        } else {
+            const bool at = a >= Q.nn, ct = c >= Q.nn;
+            int sv;
+            if (at && ct)
+                sv = -1;
+            else if (at)
+                sv = c;
+            else if (ct)
+                sv = a;
+            else
+                sv = Q.rad[a] >= Q.rad[c] ? a : c;
+            b += sv < 0 ? 1ull : (unsigned long long)Q.kcnt[sv];
+        }
+    }
+    b = wave_sum(b);
+    if ((threadIdx.x & (WAVE - 1)) == 0 && b)
+        atomicAdd(bound, b);
+}
+
+// One thread: stop at this level when its output may not fit (halt = 1 +
+// the parity of the level's frontier buffer), else clear the next length.
+__global__ void k_level_guard(const unsigned long long *__restrict__ ncur_p,
+                              unsigned long long *__restrict__ bound,
+                              const unsigned long long *__restrict__ ninter_p,
+                              long long next_cap, long long inter_cap, int parity,
+                              int *__restrict__ halt,
+                              unsigned long long *__restrict__ next_len)
+{
+    if (*halt)
+        return;
+    const unsigned long long ncur = *ncur_p, bd = *bound;
+    if (ncur > 0 && (bd > (unsigned long long)next_cap ||
+                     *ninter_p + bd > (unsigned long long)inter_cap)) {
+        *halt = 1 + parity;
+        return;
+    }
+    *next_len = 0ull;
+    *bound = 0ull;  // for the next level
+}
+
+template <int M, int TG>
+__global__ void __launch_bounds__(256)
+k_expand_d(Pts P, QView Q, Prune pr, const int2 *__restrict__ cur,
+           const unsigned long long *__restrict__ ncur_p, const int *__restrict__ halt,
+           Emit E)
+{
+    if (*halt)
+        return;
+    __shared__ int2 stg[256 / WAVE][2][STG];
+    const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
+    const long long wpb = blockDim.x / WAVE;
+    // both frontier buffers have next_cap entries
+    const long long ncur = min((long long)*ncur_p, E.next_cap);
+    Stage sg;
+    sg.buf[0] = stg[wid][0];
+    sg.buf[1] = stg[wid][1];
+    sg.n[0] = sg.n[1] = 0;
+    unsigned long long tests = 0;
+    for (long long w = (long long)blockIdx.x * wpb + wid; w < ncur;
+         w += (long long)gridDim.x * wpb) {
+        const int2 pr2 = cur[w];
+        tests += expand_one<M, TG>(P, Q, pr, pr2.x, pr2.y, E, sg);
+    }
+    stage_flush(E, sg, 0);
+    stage_flush(E, sg, 1);
+    tests = wave_sum(tests);
+    if (lane == 0 && tests)
+        atomicAdd(E.cnt_tests, tests);
 }
 
 // --------------------------------------------------------------- tiles ---
@@ -1295,20 +1395,82 @@ __global__ void k_forest_frontier(QView Q, int2 *__restrict__ cur, int cap)
 
 constexpr unsigned EXPAND_GRID = 4096;  // work-groups of the expansion
 
+// Launch of one level of the expansion (eager: ncur from the host; device:
+// ncur and the stop flag from device memory, a fixed grid).  Vector metrics:
+// lanes share each pruning test (coalesced rows).
+template <int M, int TG>
+static void launch_expand_tg(const Pts &P, const QView &Q, const Prune &pr,
+                             const int2 *cur, long long ncur,
+                             const unsigned long long *ncur_d, const int *halt,
+                             const Emit &E, hipStream_t s)
+{
+    const dim3 blk(256);
+    if (ncur_d)
+        FNN_LAUNCH((k_expand_d<M, TG>), dim3(EXPAND_GRID), blk, 0, s, P, Q, pr, cur, ncur_d,
+                   halt, E);
+    else
+        FNN_LAUNCH((k_expand<M, TG>), dim3(std::min<unsigned>(grid_for(ncur, 4), EXPAND_GRID)),
+                   blk, 0, s, P, Q, pr, cur, ncur, E);
+}
+
+template <int M>
+static void launch_expand(const Pts &P, const QView &Q, const Prune &pr, const int2 *cur,
+                          long long ncur, const unsigned long long *ncur_d,
+                          const int *halt, const Emit &E, hipStream_t s)
+{
+    if constexpr (M == M_L2 || M == M_ANG) {
+        if (P.dp >= 32)
+            launch_expand_tg<M, 8>(P, Q, pr, cur, ncur, ncur_d, halt, E, s);
+        else if (P.dp >= 16)
+            launch_expand_tg<M, 4>(P, Q, pr, cur, ncur, ncur_d, halt, E, s);
+        else if (P.dp >= 8)
+            launch_expand_tg<M, 2>(P, Q, pr, cur, ncur, ncur_d, halt, E, s);
+        else
+            launch_expand_tg<M, 1>(P, Q, pr, cur, ncur, ncur_d, halt, E, s);
+    } else {
+        launch_expand_tg<M, 1>(P, Q, pr, cur, ncur, ncur_d, halt, E, s);
+    }
+}
+
+// The level-synchronous expansion.  With gp > 1, levels first run as
+// device-queue passes: gp levels (even) recorded once into a graph and
+// replayed until the frontier is empty, one host read per replay; a level
+// whose output may not fit the fixed buffers stops the replays with its
+// frontier intact, and the eager loop below (one bound and one count read
+// per level, buffers grown to fit) finishes from there.
 template <int M>
 static void traverse(const fnn_tree *T, const Pts &P, const QView &Q,
-                     const Prune &pr, Scratch &S, int2 **inter_out,
-                     long long *ninter_out, fnn_stats &st)
+                     const Prune &pr, Scratch &S, int gp, long long list_cap,
+                     int2 **inter_out, long long *ninter_out, fnn_stats &st)
 {
     hipStream_t s = S.stream();
     const bool cross = T->cross_a >= 0;  // bichromatic: the pair of cloud roots
     const long long nroot = cross ? 1 : (T->ncloud > 1 ? T->ncloud : 1);
-    long long cap_cur = std::max<long long>(1 << 16, nroot), cap_next = 1 << 16;
-    long long cap_int = std::max<long long>(1 << 20, T->npacks * 16);
+    // [0], [1] frontier lengths (ping-pong), [2] interactions, [3] tests,
+    // [4] level bound
+    unsigned long long *cnt = S.get<unsigned long long>(5);
+    int *ovf = S.get<int>(2);  // [0] emission past a bound, [1] halt
+    long long cap_cur, cap_next, cap_int;
+    if (gp > 1) {
+        // fixed buffers for the replayed levels, sized from the tree and a
+        // sixteenth of the free memory
+        size_t freeb = 0, totb = 0;
+        FNN_HIP(hipMemGetInfo(&freeb, &totb));
+        const long long room = (long long)(freeb / 16 / sizeof(int2));
+        cap_cur = cap_next = std::max(nroot, std::min(room / 4,
+                                                      std::max<long long>(1ll << 20, 16 * T->nq)));
+        cap_int = std::min(room / 2, std::max<long long>(1ll << 22, 256 * T->npacks));
+        if (list_cap > 0) {  // small buffers force the stop and the eager finish
+            cap_cur = cap_next = std::max(nroot, list_cap);
+            cap_int = list_cap;
+        }
+    } else {
+        cap_cur = std::max<long long>(1 << 16, nroot);
+        cap_next = 1 << 16;
+        cap_int = std::max<long long>(1 << 20, T->npacks * 16);
+    }
     int2 *cur = S.get<int2>(cap_cur), *next = S.get<int2>(cap_next);
     int2 *inter = S.get<int2>(cap_int);
-    unsigned long long *cnt = S.get<unsigned long long>(4);
-    int *ovf = S.get<int>(1);
     int2 root = cross ? make_int2(T->cross_a, T->cross_b) : make_int2(T->qroot, T->qroot);
     if (T->ncloud > 1 && !cross)
         FNN_LAUNCH(k_forest_frontier, dim3(grid_for(nroot, 256)), dim3(256), 0, s,
@@ -1316,12 +1478,61 @@ static void traverse(const fnn_tree *T, const Pts &P, const QView &Q,
     else
         FNN_HIP(hipMemcpyAsync(cur, &root, sizeof(int2), hipMemcpyHostToDevice, s));
     long long ncur = nroot, ninter = 0, tests = 0;
+    fill(ovf, 0, 2, s);
+
+    if (gp > 1 && ncur > 0) {
+        const unsigned long long init[5] = {(unsigned long long)ncur, 0ull, 0ull, 0ull, 0ull};
+        FNN_HIP(hipMemcpyAsync(cnt, init, sizeof init, hipMemcpyHostToDevice, s));
+        int2 *buf[2] = {cur, next};
+        GraphRun gr;
+        gr.begin();
+        for (int k = 0; k < gp; ++k) {
+            const int a = k & 1;  // this level's frontier: buf[a], length cnt[a]
+            FNN_LAUNCH(k_expand_bound_d, dim3(256), dim3(256), 0, gr.cs, Q, buf[a], cnt + a,
+                       cap_cur, ovf + 1, cnt + 4);
+            FNN_LAUNCH(k_level_guard, dim3(1), dim3(1), 0, gr.cs, cnt + a, cnt + 4, cnt + 2,
+                       cap_cur, cap_int, a, ovf + 1, cnt + (1 - a));
+            Emit E{buf[1 - a], inter, cnt + (1 - a), cnt + 2, cnt + 3, cap_cur, cap_int, ovf};
+            launch_expand<M>(P, Q, pr, buf[a], 0, cnt + a, ovf + 1, E, gr.cs);
+        }
+        gr.end();
+        // a tree of depth D takes about 2 D levels; past a generous multiple
+        // the eager loop takes over from the frontier in buf[0]
+        const int max_replays = (int)(4 * (T->depth + 8) / gp + 4);
+        for (int r = 0;; ++r) {
+            if (r >= max_replays) {
+                cur = buf[0];
+                next = buf[1];
+                break;
+            }
+            gr.launch(s);
+            unsigned long long hc[5];
+            int hf[2];
+            FNN_HIP(hipMemcpyAsync(hc, cnt, sizeof hc, hipMemcpyDeviceToHost, s));
+            FNN_HIP(hipMemcpyAsync(hf, ovf, sizeof hf, hipMemcpyDeviceToHost, s));
+            FNN_HIP(hipStreamSynchronize(s));
+            if (hf[0])
+                fail(FNN_EINTERNAL, "traversal emitted more pairs than its bound");
+            ninter = (long long)hc[2];
+            tests = (long long)hc[3];
+            if (hf[1]) {  // continue eagerly from the stopped level's frontier
+                const int a = hf[1] - 1;
+                ncur = (long long)hc[a];
+                cur = buf[a];
+                next = buf[1 - a];
+                break;
+            }
+            ncur = (long long)hc[0];  // gp is even: the frontier is back in buf[0]
+            if (ncur == 0)
+                break;
+        }
+    }
     while (ncur > 0) {
         // bound the level's output and size both buffers before running it
-        fill(cnt + 3, 0ull, 1, s);
+        fill(cnt + 4, 0ull, 1, s);
         FNN_LAUNCH(k_expand_bound, dim3(grid_for(ncur, 256)), dim3(256), 0, s, Q,
-                   cur, ncur, cnt + 3);
-        const long long bnd = (long long)read_scalar(cnt + 3, s);
+                   cur, ncur, cnt + 4);
+        const long long bnd = (long long)read_scalar(cnt + 4, s);
         if (bnd > cap_next) {
             S.release(next);
             cap_next = bnd + bnd / 8 + 1024;
@@ -1337,29 +1548,14 @@ static void traverse(const fnn_tree *T, const Pts &P, const QView &Q,
             inter = ni;
             cap_int = nc;
         }
-        unsigned long long init[3] = {0ull, (unsigned long long)ninter, 0ull};
-        FNN_HIP(hipMemcpyAsync(cnt, init, sizeof init, hipMemcpyHostToDevice, s));
+        const unsigned long long init[3] = {0ull, (unsigned long long)ninter, 0ull};
+        FNN_HIP(hipMemcpyAsync(cnt + 1, init, sizeof init, hipMemcpyHostToDevice, s));
         fill(ovf, 0, 1, s);
-        Emit E{next, inter, cnt, cap_next, cap_int, ovf};
-        // a bounded grid that strides over the pairs: one short-lived
-        // work-group per few pairs is dispatch-bound (few resident waves);
-        // vector metrics: lanes share each pruning test (coalesced rows)
-        const dim3 g(std::min<unsigned>(grid_for(ncur, 4), EXPAND_GRID)), blk(256);
-        if constexpr (M == M_L2 || M == M_ANG) {
-            if (P.dp >= 32)
-                FNN_LAUNCH((k_expand<M, 8>), g, blk, 0, s, P, Q, pr, cur, ncur, E);
-            else if (P.dp >= 16)
-                FNN_LAUNCH((k_expand<M, 4>), g, blk, 0, s, P, Q, pr, cur, ncur, E);
-            else if (P.dp >= 8)
-                FNN_LAUNCH((k_expand<M, 2>), g, blk, 0, s, P, Q, pr, cur, ncur, E);
-            else
-                FNN_LAUNCH((k_expand<M, 1>), g, blk, 0, s, P, Q, pr, cur, ncur, E);
-        } else {
-            FNN_LAUNCH((k_expand<M, 1>), g, blk, 0, s, P, Q, pr, cur, ncur, E);
-        }
+        Emit E{next, inter, cnt + 1, cnt + 2, cnt + 3, cap_next, cap_int, ovf};
+        launch_expand<M>(P, Q, pr, cur, ncur, nullptr, nullptr, E, s);
         unsigned long long hc[3];
         int hov = 0;
-        FNN_HIP(hipMemcpyAsync(hc, cnt, sizeof hc, hipMemcpyDeviceToHost, s));
+        FNN_HIP(hipMemcpyAsync(hc, cnt + 1, sizeof hc, hipMemcpyDeviceToHost, s));
         FNN_HIP(hipMemcpyAsync(&hov, ovf, sizeof(int), hipMemcpyDeviceToHost, s));
         FNN_HIP(hipStreamSynchronize(s));
         if (hov)
@@ -1634,7 +1830,9 @@ static void eps_graph_impl(const fnn_tree *Tc, const double *epsv,
         ninter = (long long)T->npacks * (T->npacks + 1) / 2;
         st.interactions = ninter;
     } else {
-        traverse<M>(T, P, Q, pr, S, &inter, &ninter, st);
+        traverse<M>(T, P, Q, pr, S,
+                    opt.graph_passes <= 1 ? 1 : (opt.graph_passes + 1) / 2 * 2,
+                    opt.list_cap, &inter, &ninter, st);
     }
     tm.mark();  // 1
 
