@@ -347,9 +347,67 @@ __device__ __forceinline__ int cand_per_chunk(int nch, int kmax)
 constexpr int UPD_D = 128;  // largest row stride staged in LDS
 
 constexpr int UPD_W = 4;  // queue entries (one wave each) per work-group
-constexpr int UPD_P = 4;  // points per lane in the distance loop (eight: fewer waves, slower)
-constexpr int UPD_LG = 64 / UPD_P;  // lanes per centre group
-static_assert(CH == 64 && UPD_K % UPD_P == 0, "lane layout of the distance loop");
+static_assert(CH == 64 && UPD_K % 8 == 0, "lane layout of the distance loop");
+
+// One point per lane against a staged batch of nj (<= UPD_K) centres
+// (rows ldc apart in LDS; every lane reads the same centre row, a
+// broadcast): UPD_K FMA chains over the coordinates in order, the lane's
+// row read four coordinates at a time with UPD_PF reads in flight, then the
+// running nearest over the batch in centre order (strict '<': the first
+// minimum stays).  Groups of eight centres past nj are skipped (a
+// wave-uniform test); rows between nj and the group's end are staged data
+// that is never compared.
+constexpr int UPD_PF = 4;
+__device__ __forceinline__ void upd_lane(const float *__restrict__ row,
+                                         const float *__restrict__ cen, int ldc, int dp,
+                                         int jb, int nj, float &dcur, int &lcur)
+{
+    constexpr int NJ = UPD_K;
+    float acc[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j)
+        acc[j] = 0.f;
+    const int q4 = dp >> 2;
+    const float4 *r4 = reinterpret_cast<const float4 *>(row);
+    float4 pf[UPD_PF];
+#pragma unroll
+    for (int u = 0; u < UPD_PF; ++u)
+        pf[u] = r4[u < q4 ? u : q4 - 1];
+    for (int c4 = 0; c4 < q4; c4 += UPD_PF) {
+#pragma unroll
+        for (int u = 0; u < UPD_PF; ++u) {
+            const int cc4 = c4 + u;
+            const float4 v = pf[u];
+            const int nx = cc4 + UPD_PF;
+            pf[u] = r4[nx < q4 ? nx : q4 - 1];
+            if (cc4 < q4) {
+#pragma unroll
+                for (int g = 0; g < NJ / 8; ++g) {
+                    if (8 * g < nj) {
+#pragma unroll
+                        for (int jj = 0; jj < 8; ++jj) {
+                            const int j = 8 * g + jj;
+                            const float4 cc = *reinterpret_cast<const float4 *>(
+                                __builtin_assume_aligned(cen + j * ldc + 4 * cc4, 16));
+                            const float d0 = v.x - cc.x, d1 = v.y - cc.y, d2 = v.z - cc.z,
+                                        d3 = v.w - cc.w;
+                            acc[j] = fmaf(d0, d0, acc[j]);
+                            acc[j] = fmaf(d1, d1, acc[j]);
+                            acc[j] = fmaf(d2, d2, acc[j]);
+                            acc[j] = fmaf(d3, d3, acc[j]);
+                        }
+                    }
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < NJ; ++j)
+        if (j < nj && acc[j] < dcur) {
+            dcur = acc[j];
+            lcur = jb + j;
+        }
+}
 
 template <int M>
 __global__ void __launch_bounds__(CH * UPD_W)
@@ -394,25 +452,10 @@ k_update(Pts P, const int32_t *__restrict__ ch_hub, const int32_t *__restrict__ 
         staged = P.dp <= UPD_D;
         if (staged) {
             const float *X = (M == M_ANG) ? P.xn : P.x;
-            const int dp = P.dp, ldc = dp + 4;  // padded: quarters hit distinct banks
-            // Four points per lane against a quarter of every batch: lane l
-            // takes positions s + l % 16 + 16 k (k < UPD_P) and the batch's
-            // centres UPD_P i + l / 16, so each staged centre read serves
-            // four points.  Every distance is the same FMA chain over the
-            // coordinates in order; the quarters' nearest centres are merged
-            // at the end by (distance, index), which is the first minimum
-            // the sequential scan would keep.
-            const int i16 = lane % UPD_LG, qd = lane / UPD_LG;
-            const float *rows[UPD_P];
-            float dq[UPD_P];
-            int lq[UPD_P];
-#pragma unroll
-            for (int k = 0; k < UPD_P; ++k) {
-                const int src = i16 + UPD_LG * k;
-                rows[k] = X + (size_t)__shfl(o, src, WAVE) * dp;
-                dq[k] = __shfl(dcur, src, WAVE);
-                lq[k] = __shfl(lcur, src, WAVE);
-            }
+            const int dp = P.dp, ldc = dp + 4;  // rows 16-byte aligned
+            // one point per lane (its row read once per batch), the batch's
+            // centres broadcast from LDS
+            const float *row = X + (size_t)o * dp;
             __syncthreads();  // hub_s of the previous entries is consumed
             if (lane == 0)
                 hub_s[w] = act && j1 > j0 ? h : -1;
@@ -429,76 +472,38 @@ k_update(Pts P, const int32_t *__restrict__ ch_hub, const int32_t *__restrict__ 
                 for (int jb = j0r; jb < j1r; jb += UPD_K) {
                     const int nj = min(UPD_K, j1r - jb);
                     __syncthreads();  // the previous batch is consumed
-                    for (int x = threadIdx.x; x < nj * dp; x += CH * UPD_W)
-                        cen[(x / dp) * ldc + x % dp] =
-                            X[(size_t)cent[br + jb + x / dp] * dp + (x % dp)];
-                    __syncthreads();
-                    if (mine) {
-                        constexpr int NI = UPD_K / UPD_P;
-                        float acc[UPD_P][NI];
+                    {
+                        // nj rows of dp / 4 float4 each, at most UPD_K * UPD_D / 4
+                        // in all: every index load, then every row load, is
+                        // issued before the first wait
+                        constexpr int SU = UPD_K * UPD_D / 4 / (CH * UPD_W);
+                        static_assert(SU * CH * UPD_W * 4 == UPD_K * UPD_D, "staging split");
+                        const int q4 = dp >> 2, tot = nj * q4;
+                        int ci[SU], so[SU], c4[SU];
 #pragma unroll
-                        for (int k = 0; k < UPD_P; ++k)
-#pragma unroll
-                            for (int i = 0; i < NI; ++i)
-                                acc[k][i] = 0.f;
-                        float4 vn[UPD_P];
-#pragma unroll
-                        for (int k = 0; k < UPD_P; ++k)
-                            vn[k] = *reinterpret_cast<const float4 *>(rows[k]);
-                        for (int c = 0; c < dp; c += 4) {
-                            float4 v[UPD_P];
-#pragma unroll
-                            for (int k = 0; k < UPD_P; ++k) {
-                                v[k] = vn[k];
-                                // next coordinates in flight while these are used
-                                vn[k] = *reinterpret_cast<const float4 *>(
-                                    rows[k] + (c + 4 < dp ? c + 4 : c));
-                            }
-#pragma unroll
-                            for (int i = 0; i < NI; ++i) {
-                                const int j = UPD_P * i + qd;
-                                if (j < nj) {
-                                    const float4 cc = *reinterpret_cast<const float4 *>(
-                                        cen + j * ldc + c);
-#pragma unroll
-                                    for (int k = 0; k < UPD_P; ++k) {
-                                        const float d0 = v[k].x - cc.x, d1 = v[k].y - cc.y,
-                                                    d2 = v[k].z - cc.z, d3 = v[k].w - cc.w;
-                                        acc[k][i] = fmaf(d0, d0, acc[k][i]);
-                                        acc[k][i] = fmaf(d1, d1, acc[k][i]);
-                                        acc[k][i] = fmaf(d2, d2, acc[k][i]);
-                                        acc[k][i] = fmaf(d3, d3, acc[k][i]);
-                                    }
-                                }
-                            }
+                        for (int u = 0; u < SU; ++u) {
+                            const int f = threadIdx.x + u * CH * UPD_W;
+                            const int r = f < tot ? f / q4 : 0;
+                            ci[u] = f < tot ? cent[br + jb + r] : -1;
+                            c4[u] = 4 * (f - r * q4);
+                            so[u] = r * ldc + c4[u];
                         }
+                        float4 cv[SU];
 #pragma unroll
-                        for (int i = 0; i < NI; ++i) {
-                            const int j = UPD_P * i + qd;
-                            if (j < nj)
+                        for (int u = 0; u < SU; ++u)
+                            if (ci[u] >= 0)
+                                cv[u] = *reinterpret_cast<const float4 *>(
+                                    X + (size_t)ci[u] * dp + c4[u]);
 #pragma unroll
-                                for (int k = 0; k < UPD_P; ++k)
-                                    if (acc[k][i] < dq[k]) {
-                                        dq[k] = acc[k][i];
-                                        lq[k] = jb + j;
-                                    }
-                        }
+                        for (int u = 0; u < SU; ++u)
+                            if (ci[u] >= 0)
+                                *reinterpret_cast<float4 *>(cen + so[u]) = cv[u];
                     }
+                    __syncthreads();
+                    if (mine)
+                        upd_lane(row, cen, ldc, dp, jb, nj, dcur, lcur);
                 }
             }
-            // this lane's point is entry qd of the groups' lanes
-            // i16 + UPD_LG q
-#pragma unroll
-            for (int k = 0; k < UPD_P; ++k)
-#pragma unroll
-                for (int q = 0; q < UPD_P; ++q) {
-                    const float d2 = __shfl(dq[k], i16 + UPD_LG * q, WAVE);
-                    const int l2 = __shfl(lq[k], i16 + UPD_LG * q, WAVE);
-                    if (qd == k && (d2 < dcur || (d2 == dcur && l2 < lcur))) {
-                        dcur = d2;
-                        lcur = l2;
-                    }
-                }
         }
     }
     if (valid) {
