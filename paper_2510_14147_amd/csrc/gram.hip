@@ -1165,24 +1165,45 @@ __device__ __forceinline__ unsigned long long uniform_u64(unsigned long long v)
     return ((unsigned long long)hi << 32) | lo;
 }
 
+constexpr int SURV_BUF = 256;  // survivors buffered per wave in LDS
+
+// Appends a wave's n buffered survivors to the list: one atomic for their
+// slots, then coalesced stores.  Called with every lane of the wave active.
+__device__ __forceinline__ void surv_flush(const GramArgs &G, const int2 *sb, unsigned n)
+{
+    const int lane = threadIdx.x & (WAVE - 1);
+    // LDS writes of other lanes are read below: keep them in order
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    unsigned long long b0 = 0;
+    if (lane == 0 && n)
+        b0 = atomicAdd(G.nsurv, (unsigned long long)n);
+    b0 = uniform_u64(b0);
+    for (unsigned i = lane; i < n; i += WAVE) {
+        const unsigned long long q = b0 + i;
+        if ((long long)q < G.surv_cap)
+            G.surv[q] = sb[i];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+}
+
 // End of one 32-row x 64-column block of the narrow kernel: rows
 // 32 rb + r (r < 32) of the wave's pack against the entry's columns c < 64.
 // Position q of acc[cb] in a lane holds row 32 rb + 8 (q / 4) + q % 4 + 4 hi
 // of column 32 cb + l32; acc[cb] starts at -ax of its row, ay[cb] is the
 // lane's column term (FLT_MAX past nb) and hm[cb] the lanes whose largest
 // sum of that block reaches it.  The pairs that pass (every valid pair with
-// its pass flag when validating) go to the survivor list through the wave's
-// reserved slots [cpos, cend) (wave-uniform).
+// its pass flag when validating) are written column first, each lane's
+// next to each other, into the wave's LDS buffer sb (*fill entries held),
+// which goes to the list when it would overflow; more pairs than the
+// buffer holds (only when validating) go to the list directly.
 __device__ __forceinline__ void half_finish(const GramArgs &G, const f32x16 (&acc)[2],
                                             const float (&ay)[2], const uint64_t (&hm)[2],
                                             int rb, int na, int nb, bool self, int pa,
-                                            int pb, unsigned long long *curS,
+                                            int pb, unsigned *fillS, int2 *sb,
                                             const unsigned *rmS)
 {
     const int lane = threadIdx.x & (WAVE - 1), l32 = lane & 31, hi = lane >> 5;
-    // the wave's reserved slots, kept in LDS between calls so that the
-    // entry loop holds no cursor registers
-    unsigned long long cpos = uniform_u64(curS[0]), cend = uniform_u64(curS[1]);
+    unsigned fill = (unsigned)__builtin_amdgcn_readfirstlane((int)*fillS);
     const uint64_t ltmask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
 #pragma unroll
     for (int cb = 0; cb < 2; ++cb) {
@@ -1203,34 +1224,51 @@ __device__ __forceinline__ void half_finish(const GramArgs &G, const f32x16 (&ac
             nm = __builtin_amdgcn_alignbit(
                 nm, __float_as_uint(__fsub_rn(acc[cb][q], ay[cb])), 31);
         const unsigned pm = ~nm & om;
-        const unsigned todo = G.validate ? om : pm;
-        unsigned any = wave_or_u32(todo);
-        while (any) {
-            const int q = __ffs(any) - 1;
-            any &= any - 1;
-            const bool emit = (todo >> q) & 1u;
-            const uint64_t m = __ballot(emit);
-            const int r0 = 32 * rb + 8 * (q >> 2) + (q & 3);
-            const int cnt = __popcll(m);
-            if (cpos + (unsigned long long)cnt > cend) {
-                pad_surv(G, cpos, cend);
-                unsigned long long b0 = 0;
-                if (lane == 0)
-                    b0 = atomicAdd(G.nsurv, (unsigned long long)SURV_CHUNK);
-                cpos = uniform_u64(b0);  // lane 0's value, in scalar registers
-                cend = cpos + SURV_CHUNK;
-            }
-            const unsigned long long o = cpos + __popcll(m & ltmask);
-            if (emit && (long long)o < G.surv_cap)
-                G.surv[o] = make_int2(pa + r0 + 4 * hi,
-                                      (pb + col) | (int)(((pm >> q) & 1u) << 31));
-            cpos += (unsigned long long)cnt;
+        unsigned todo = G.validate ? om : pm;
+        // the lane's count (at most 16: five bits), its exclusive prefix
+        // over the wave and the wave's total, from one ballot per bit
+        const unsigned c = __popc(todo);
+        unsigned pre = 0, tot = 0;
+#pragma unroll
+        for (int b = 0; b < 5; ++b) {
+            const uint64_t m = __ballot((c >> b) & 1u);
+            pre += (unsigned)__popcll(m & ltmask) << b;
+            tot += (unsigned)__popcll(m) << b;
         }
+        if (tot == 0)
+            continue;
+        if (fill + tot > (unsigned)SURV_BUF) {
+            surv_flush(G, sb, fill);
+            fill = 0;
+        }
+        const int colp = pb + col;
+        if (tot > (unsigned)SURV_BUF) {
+            // straight to the list (validation only)
+            unsigned long long b0 = 0;
+            if (lane == 0)
+                b0 = atomicAdd(G.nsurv, (unsigned long long)tot);
+            unsigned long long o = uniform_u64(b0) + pre;
+            while (todo) {
+                const int q = __ffs(todo) - 1;
+                todo &= todo - 1;
+                const int r = 32 * rb + 8 * (q >> 2) + (q & 3) + 4 * hi;
+                if ((long long)o < G.surv_cap)
+                    G.surv[o] = make_int2(colp, (pa + r) | (int)(((pm >> q) & 1u) << 31));
+                ++o;
+            }
+            continue;
+        }
+        unsigned o = fill + pre;
+        while (todo) {
+            const int q = __ffs(todo) - 1;
+            todo &= todo - 1;
+            const int r = 32 * rb + 8 * (q >> 2) + (q & 3) + 4 * hi;
+            sb[o++] = make_int2(colp, (pa + r) | (int)(((pm >> q) & 1u) << 31));
+        }
+        fill += tot;
     }
-    if (lane == 0) {
-        curS[0] = cpos;
-        curS[1] = cend;
-    }
+    if (lane == 0)
+        *fillS = fill;
 }
 
 // Filter for narrow BF16 rows (kq <= 32: the leading principal
@@ -1256,9 +1294,10 @@ k_gram_direct(Pts P, GramArgs G, TileOut out)
     const int w = __builtin_amdgcn_readfirstlane(t / WAVE);  // wave-uniform
     const int l32 = lane & 31, hi = lane >> 5;
     const unsigned char *Q = (const unsigned char *)G.q;
-    __shared__ unsigned long long curS[GW][2];  // each wave's survivor slots
+    __shared__ unsigned fillS[GW];                     // each wave's buffered survivors
+    __shared__ __align__(16) int2 survS[GW][SURV_BUF];  // and the buffer
     if (lane == 0)
-        curS[w][0] = curS[w][1] = 0ull;
+        fillS[w] = 0u;
     // XCD slices of the unit order, as in k_gram
     const int bpx = (int)gridDim.x / 8, jb = (int)blockIdx.x / 8;
     const int per = (G.nunits + 7) / 8;
@@ -1380,7 +1419,7 @@ k_gram_direct(Pts P, GramArgs G, TileOut out)
                     if (__any(fmaxf(mg[0], mg[1]) >= 0.f) || G.validate) {
                         const uint64_t hm[2] = {__ballot(mg[0] >= 0.f),
                                                 __ballot(mg[1] >= 0.f)};
-                        half_finish(G, acc, ayc, hm, rb, na, nb, self, pa, pb, curS[w],
+                        half_finish(G, acc, ayc, hm, rb, na, nb, self, pa, pb, &fillS[w], survS[w],
                                     rmS);
                     }
                 }
@@ -1400,7 +1439,7 @@ k_gram_direct(Pts P, GramArgs G, TileOut out)
         }
         __syncthreads();  // eB.. are rewritten by the next unit
     }
-    pad_surv(G, uniform_u64(curS[w][0]), uniform_u64(curS[w][1]));
+    surv_flush(G, survS[w], (unsigned)__builtin_amdgcn_readfirstlane((int)fillS[w]));
 }
 
 // Pairs the narrow kernel screens (its entry loop does not count them): for
