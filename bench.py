@@ -8,7 +8,7 @@ evaluations/s and the per-phase split are extra fields), with the roofline of
 the dominant kernel and the CPU oracle's rate on a bounded sample.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2a]
-                    [--precision fp32|bf16|fp8] [--no-cpu]
+                    [--precision fp32|bf16|fp16|fp8] [--no-cpu]
 """
 from __future__ import annotations
 
@@ -233,13 +233,15 @@ def roofline(dim, precision, tq, workload=""):
         # the padded width it ran on: the leading principal coordinates when
         # the library projected (proj_dim), else the coordinates
         k = tq.get("proj_dim", 0) or dim
-        kq = -(-k // 16) * 16 if precision == "bf16" else -(-k // 64) * 64
+        b16 = precision in ("bf16", "fp16")
+        kq = -(-k // 16) * 16 if b16 else -(-k // 64) * 64
         flops = 2.0 * kq * tq["filter_pairs"]
         kms = tq["filter_ms"] if tq.get("filter_ms", 0) > 0 else tq["count_ms"]
         ach = flops / (kms / 1e3) / 1e12
-        peak = PEAK_BF16_TFLOPS if precision == "bf16" else PEAK_FP8_TFLOPS
-        if precision == "bf16" and kq <= 32:
-            kname = f"k_gram_direct<L2,bf16,k{kq}>"
+        # dense FP16 and BF16 MFMA share one peak
+        peak = PEAK_BF16_TFLOPS if b16 else PEAK_FP8_TFLOPS
+        if b16 and kq <= 32:
+            kname = f"k_gram_direct<L2,{precision},k{kq}>"
         else:
             kname = f"k_gram<L2,{precision},k{kq}>"
         return {"bound": "mfma", "achieved": round(ach, 3), "peak": peak,
@@ -276,9 +278,9 @@ def main():
                          "batch per dim) | c5_loop (one call per cloud)")
     ap.add_argument("--precision", default="auto",
                     help="auto (the library chooses per query: i8 on Hamming "
-                         "codes of <= 256 bits, bf16 on vector data where the "
+                         "codes of <= 256 bits, fp16 on vector data where the "
                          "filter's margin is small against eps^2, else fp32) "
-                         "| fp32 | bf16 | fp8 | i8 (Hamming codes)")
+                         "| fp32 | bf16 | fp16 | fp8 | i8 (Hamming codes)")
     ap.add_argument("--sched", default="two_pass")
     ap.add_argument("--proj", type=int, default=0,
                     help="filter on leading principal coordinates: 0 automatic, "
@@ -486,7 +488,8 @@ def main():
     }
     if tuning:
         out["tuned"] = tuning
-    out["dtype"] = {"fp32": "f32", "bf16": "bf16 filter + f32", "fp8": "fp8 filter + f32"}.get(
+    out["dtype"] = {"fp32": "f32", "bf16": "bf16 filter + f32", "fp16": "fp16 filter + f32",
+                    "fp8": "fp8 filter + f32"}.get(
         "+".join(precs), "+".join(precs))
     if metric == "hamming":
         out["dtype"] = ("i8 MFMA (exact integer Gram)" if "i8" in precs

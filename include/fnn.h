@@ -66,11 +66,14 @@ typedef enum {
     FNN_PREC_FP8 = 2,    /* MFMA FP8 (E4M3) Gram filter, FP32 recompute        */
     FNN_PREC_I8 = 3,     /* Hamming codes of <= 256 bits: exact int8 MFMA Gram */
                          /* (bits as +-1 bytes: s.t = K - 2 d over K bits)     */
-    FNN_PREC_AUTO = 4    /* chosen per query: I8 for Hamming codes of <= 256  */
-                         /* bits; BF16 for L2 / angular with 16 <= dim <= 128 */
+    FNN_PREC_AUTO = 4,   /* chosen per query: I8 for Hamming codes of <= 256  */
+                         /* bits; FP16 for L2 / angular with 16 <= dim <= 128 */
                          /* when the filter's margin is small against eps^2   */
                          /* (2 c1 mean|x - mu|^2 <= eps^2 / 2, mu per cloud); */
                          /* FP32 tiles otherwise (stats: precision_used)      */
+    FNN_PREC_FP16 = 5    /* MFMA FP16 Gram filter on rows scaled by a power   */
+                         /* of two (largest |coordinate| in [2^14, 2^15)):   */
+                         /* the BF16 filter with an 8x narrower margin        */
 } fnn_precision;
 
 /* How CSR rows are sized. */
@@ -87,11 +90,11 @@ typedef struct fnn_options {
     int32_t zeta;         /* leaf size (Algorithm 2); default 64             */
     int32_t pack;         /* points per query/leaf tile block; default 64
                              (Levenshtein: 1, one leaf block per pack)       */
-    int32_t precision;    /* fnn_precision; default FNN_PREC_FP32.  BF16 and */
-                          /* FP8 apply to L2 / angular with dim <= 128 (else */
-                          /* FNN_EUNSUPPORTED), I8 to Hamming codes of <= 256 */
-                          /* bits (else FNN_EUNSUPPORTED); BF16 / FP8 on      */
-                          /* integer metrics run the plain tiles             */
+    int32_t precision;    /* fnn_precision; default FNN_PREC_FP32.  BF16,    */
+                          /* FP16 and FP8 apply to L2 / angular with dim <=  */
+                          /* 128 (else FNN_EUNSUPPORTED), I8 to Hamming codes */
+                          /* of <= 256 bits (else FNN_EUNSUPPORTED); BF16 /   */
+                          /* FP16 / FP8 on integer metrics run the plain tiles */
     int32_t sched;        /* fnn_sched; default FNN_SCHED_TWO_PASS           */
     int32_t validate;     /* 1: also measure the max FP32 distance error     */
                           /* against FP64 and count filter false negatives    */

@@ -23,7 +23,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfnn.so")
 
 METRICS = {"l2": 0, "angular": 1, "hamming": 2, "levenshtein": 3}
-PRECISIONS = {"fp32": 0, "bf16": 1, "fp8": 2, "i8": 3, "auto": 4}
+PRECISIONS = {"fp32": 0, "bf16": 1, "fp8": 2, "i8": 3, "auto": 4, "fp16": 5}
 SCHEDS = {"two_pass": 0, "learned": 1}
 
 FNN_OK, FNN_EINVAL, FNN_ENOMEM, FNN_EHIP, FNN_EUNSUPPORTED, FNN_EINTERNAL = \

@@ -70,7 +70,7 @@ Options read_options(const fnn_options *o)
         r.zeta = o->zeta;
     if (o->pack)
         r.pack = o->pack;
-    if (o->precision < 0 || o->precision > FNN_PREC_AUTO)
+    if (o->precision < 0 || o->precision > FNN_PREC_FP16)
         fail(FNN_EINVAL, "unknown precision %d", (int)o->precision);
     r.precision = o->precision;
     if (o->sched < 0 || o->sched > FNN_SCHED_LEARNED)

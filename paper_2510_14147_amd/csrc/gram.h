@@ -69,6 +69,7 @@ struct GramArgs {
     // factor applied to eps^2 (1 when off) and the captured variance
     int proj;
     double t2mul;
+    double e2add;         // added to the filter's (scaled) eps^2 (FP16 subnormals)
     double captured;
     // bichromatic query: only pairs across the two clouds are evaluated
     int cross;
@@ -105,7 +106,7 @@ void degrees_from_positions(const int32_t *degp, const int32_t *perm, int n,
 // 2 c1 mean|x - mu|^2 / t2min for the BF16 filter (mu per cloud): how much
 // its rounding margin widens the test against the smallest squared
 // threshold; small values mean a selective filter.
-double gram_margin_ratio(const fnn_tree *T, double t2min, Scratch &S);
+double gram_margin_ratio(const fnn_tree *T, double t2min, int prec, Scratch &S);
 
 // True when no query pack exceeds the filter's tile height (the work list
 // of every pack pair then exists in closed form).
@@ -116,7 +117,7 @@ bool gram_packs_fit(const fnn_tree *T, Scratch &S);
 double gram_t2(int metric, double eps, const Thr &E);
 // eps^2 in the filter's key space times t2mul, slightly enlarged so that the
 // FP32 evaluation of the filter test itself cannot flip a true edge.
-float gram_eps2(int metric, double eps, const Thr &E, double t2mul = 1.0);
+float gram_eps2(int metric, double eps, const Thr &E, double t2mul = 1.0, double add = 0.0);
 
 // proj: leading principal coordinates for the filter (-1 off, 0 automatic,
 // else their number); t2min: smallest squared threshold of the query.

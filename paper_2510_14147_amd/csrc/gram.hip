@@ -40,6 +40,7 @@
 namespace fnn {
 
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(8))) _Float16 f16x8;
 typedef __attribute__((ext_vector_type(16))) float f32x16;
 typedef __attribute__((ext_vector_type(8))) int i32x8;
 
@@ -136,10 +137,15 @@ __global__ void k_quant(const float *__restrict__ x, int n, int dp, int kq,
             float v = 0.f;
             if (k < dp) {
                 v = x[(size_t)i * dp + k] - C.mu(cl, k);
+                // FP16: the filter works in units scaled by a power of two
+                if constexpr (PREC == FNN_PREC_FP16)
+                    v *= scale;
                 ss = fmaf(v, v, ss);
             }
             if constexpr (PREC == FNN_PREC_BF16) {
                 ((__bf16 *)q)[(size_t)i * kq + k] = (__bf16)v;
+            } else if constexpr (PREC == FNN_PREC_FP16) {
+                ((_Float16 *)q)[(size_t)i * kq + k] = (_Float16)v;
             } else {
                 float s = fminf(fmaxf(v * scale, -448.f), 448.f);
                 unsigned w = (unsigned)__builtin_amdgcn_cvt_pk_fp8_f32(s, 0.f, 0, false);
@@ -678,6 +684,11 @@ struct GramCfg<FNN_PREC_BF16> {
     static constexpr int EB = 2;      // bytes per element
 };
 template <>
+struct GramCfg<FNN_PREC_FP16> {
+    static constexpr int KSTEP = 16;
+    static constexpr int EB = 2;
+};
+template <>
 struct GramCfg<FNN_PREC_FP8> {
     static constexpr int KSTEP = 64;
     static constexpr int EB = 1;
@@ -687,6 +698,25 @@ struct GramCfg<FNN_PREC_I8> {
     static constexpr int KSTEP = 32;  // code bits (one signed byte each) per MFMA
     static constexpr int EB = 1;
 };
+
+// The 16-bit formats share the operand layout of the 32 x 32 x 16 products
+// (eight elements per lane); only the instruction differs.
+constexpr bool is16(int prec) { return prec == FNN_PREC_BF16 || prec == FNN_PREC_FP16; }
+template <int PREC>
+__device__ __forceinline__ f32x16 mfma16(const int4 &a, const int4 &b, const f32x16 &c)
+{
+    if constexpr (PREC == FNN_PREC_FP16) {
+        f16x8 x, y;
+        __builtin_memcpy(&x, &a, 16);
+        __builtin_memcpy(&y, &b, 16);
+        return __builtin_amdgcn_mfma_f32_32x32x16_f16(x, y, c, 0, 0, 0);
+    } else {
+        bf16x8 x, y;
+        __builtin_memcpy(&x, &a, 16);
+        __builtin_memcpy(&y, &b, 16);
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(x, y, c, 0, 0, 0);
+    }
+}
 
 typedef __attribute__((ext_vector_type(4))) int i32x4;
 typedef __attribute__((ext_vector_type(16))) int i32x16;
@@ -897,7 +927,7 @@ k_gram(Pts P, GramArgs G, TileOut out)
     const int t = threadIdx.x, lane = t & (WAVE - 1), w = t / WAVE;
     const int l32 = lane & 31, hi = lane >> 5;
     // products carry the FP8 scale; gscale and its inverse are powers of 2
-    const float ginv = PREC == FNN_PREC_BF16 ? 1.f : 1.f / G.gscale;
+    const float ginv = is16(PREC) ? 1.f : 1.f / G.gscale;
     unsigned long long npairs = 0;
     const uint64_t ltmask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     // this wave's reserved survivor slots [cpos, cend) (wave-uniform); slots
@@ -941,8 +971,8 @@ k_gram(Pts P, GramArgs G, TileOut out)
                 if (r < na) {
                     const unsigned char *src =
                         (const unsigned char *)G.q + (size_t)(pa + r) * rowb;
-                    if constexpr (PREC == FNN_PREC_BF16 || PREC == FNN_PREC_I8) {
-                        // k-step ks: bytes ks*32 + hi*16 .. +16 (BF16
+                    if constexpr (is16(PREC) || PREC == FNN_PREC_I8) {
+                        // k-step ks: bytes ks*32 + hi*16 .. +16 (16-bit
                         // elements ks*16 + hi*8 .. +8, or Hamming bits
                         // ks*32 + hi*16 .. +16 as bytes)
                         #pragma unroll
@@ -1064,7 +1094,7 @@ k_gram(Pts P, GramArgs G, TileOut out)
             const unsigned char *brow1 = Bs + (32 + l32) * ldb;
             // all of this step's B fragments, read before the matrix-core
             // chain so no k-step waits on LDS
-            constexpr bool B16 = PREC == FNN_PREC_BF16 || PREC == FNN_PREC_I8;
+            constexpr bool B16 = is16(PREC) || PREC == FNN_PREC_I8;
             int4 bfrag[B16 ? nks : 1][2];
             if constexpr (B16) {
 #pragma unroll
@@ -1093,23 +1123,18 @@ k_gram(Pts P, GramArgs G, TileOut out)
                                 aa, bb, acc[cb][rb], 0, 0, 0);
                         }
                     }
-                } else if constexpr (PREC == FNN_PREC_BF16) {
+                } else if constexpr (is16(PREC)) {
                     const int4 bv[2] = {bfrag[ks][0], bfrag[ks][1]};
                     const int slot = ks >> 1, half = ks & 1;
 #pragma unroll
                     for (int cb = 0; cb < 2; ++cb) {
-                        bf16x8 bb;
-                        __builtin_memcpy(&bb, &bv[cb], 16);
 #pragma unroll
                         for (int rb = 0; rb < 2; ++rb) {
                             const int4 av = make_int4(Areg[rb][slot][half * 4 + 0],
                                                       Areg[rb][slot][half * 4 + 1],
                                                       Areg[rb][slot][half * 4 + 2],
                                                       Areg[rb][slot][half * 4 + 3]);
-                            bf16x8 aa;
-                            __builtin_memcpy(&aa, &av, 16);
-                            acc[cb][rb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                                aa, bb, acc[cb][rb], 0, 0, 0);
+                            acc[cb][rb] = mfma16<PREC>(av, bv[cb], acc[cb][rb]);
                         }
                     }
                 } else {
@@ -1279,7 +1304,7 @@ __device__ __forceinline__ void half_finish(const GramArgs &G, const f32x16 (&ac
 // both 32-column blocks.  A wave that emits survivors then never holds up the other
 // waves of its work-group; the four waves of a group read the same B rows
 // at about the same time, so most of those reads hit L1.
-template <int M, int NKS>
+template <int M, int PREC, int NKS>
 __global__ void __launch_bounds__(GT, NKS == 1 ? 5 : 4)  // waves / SIMD that fit unspilled
 k_gram_direct(Pts P, GramArgs G, TileOut out)
 {
@@ -1313,7 +1338,7 @@ k_gram_direct(Pts P, GramArgs G, TileOut out)
         const int pa = has_a ? G.q_pb[a] : 0;
         const int na = has_a ? G.q_pe[a] - pa : 0;
         // A fragments: rows 32 rb + l32, bytes 32 ks + 16 hi
-        bf16x8 Af[2][NKS];
+        int4 Af[2][NKS];
 #pragma unroll
         for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
@@ -1322,7 +1347,7 @@ k_gram_direct(Pts P, GramArgs G, TileOut out)
                 int4 v = make_int4(0, 0, 0, 0);
                 if (r < na)
                     v = *(const int4 *)(Q + (size_t)(pa + r) * rowb + ks * 32 + hi * 16);
-                __builtin_memcpy(&Af[rb][ks], &v, 16);
+                Af[rb][ks] = v;
             }
         // accumulator start values -ax of the wave's rows, in LDS: each row
         // half reads its 16 per lane as the addend of both of its products
@@ -1399,10 +1424,8 @@ k_gram_direct(Pts P, GramArgs G, TileOut out)
                     for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
                         for (int ks = 0; ks < NKS; ++ks) {
-                            bf16x8 bb;
-                            __builtin_memcpy(&bb, &B[cb][ks], 16);
-                            acc[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                                Af[rb][ks], bb, ks == 0 ? sv : acc[cb], 0, 0, 0);
+                            acc[cb] = mfma16<PREC>(Af[rb][ks], B[cb][ks],
+                                                   ks == 0 ? sv : acc[cb]);
                         }
                     // fast test: the lane's largest sum per column block
                     // minus its column term (exact in sign: x - y >= 0 iff
@@ -1833,7 +1856,7 @@ static void launch_gram_k(bool fill_pass, const Pts &P, const GramArgs &G,
     FNN_LAUNCH((k_gram<M, PREC, NKS>), grid, dim3(GT), sh, s, P, G, o);
 }
 
-template <int M, int NKS>
+template <int M, int PREC, int NKS>
 static void launch_gram_direct(const Pts &P, const GramArgs &G, const TileOut &o,
                                hipStream_t s)
 {
@@ -1841,14 +1864,14 @@ static void launch_gram_direct(const Pts &P, const GramArgs &G, const TileOut &o
     int rb = resident.load();
     if (rb == 0) {
         FNN_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &rb, reinterpret_cast<const void *>(&k_gram_direct<M, NKS>), GT, 0));
+            &rb, reinterpret_cast<const void *>(&k_gram_direct<M, PREC, NKS>), GT, 0));
         rb = std::max(1, rb);
         resident.store(rb);
     }
     const long long want = std::max<long long>(8, (long long)rb * num_cus() / 8 * 8);
     const long long need = ((long long)G.nunits + 7) / 8 * 8;
     const dim3 grid((unsigned)std::max<long long>(8, std::min(want, need)));
-    FNN_LAUNCH((k_gram_direct<M, NKS>), grid, dim3(GT), 0, s, P, G, o);
+    FNN_LAUNCH((k_gram_direct<M, PREC, NKS>), grid, dim3(GT), 0, s, P, G, o);
     FNN_LAUNCH(k_gram_pairs, dim3(grid_cap(G.nlist, 256, 4096)), dim3(256), 0, s, G, o);
 }
 
@@ -1866,19 +1889,19 @@ static void launch_gram(bool fill_pass, const Pts &P, const GramArgs &G,
         case 6: launch_gram_k<M, PREC, 6>(fill_pass, P, G, o, s); break;
         default: launch_gram_k<M, PREC, 8>(fill_pass, P, G, o, s); break;
         }
-    } else if constexpr (PREC == FNN_PREC_BF16) {
+    } else if constexpr (is16(PREC)) {
         // the narrow kernel reads the per-pack copies (made when it applies)
         const bool narrow_fits = G.qp != nullptr;
         switch (nks) {
         case 1:
             if (narrow_fits)
-                launch_gram_direct<M, 1>(P, G, o, s);
+                launch_gram_direct<M, PREC, 1>(P, G, o, s);
             else
                 launch_gram_k<M, PREC, 1>(fill_pass, P, G, o, s);
             break;
         case 2:
             if (narrow_fits)
-                launch_gram_direct<M, 2>(P, G, o, s);
+                launch_gram_direct<M, PREC, 2>(P, G, o, s);
             else
                 launch_gram_k<M, PREC, 2>(fill_pass, P, G, o, s);
             break;
@@ -1922,7 +1945,7 @@ void gram_pad_packs(int metric, int prec, GramArgs &G, Scratch &S)
     G.qp = nullptr;
     G.ayp = nullptr;
     const int nks = G.kq / GramCfg<FNN_PREC_BF16>::KSTEP;
-    if (metric == M_HAM || prec != FNN_PREC_BF16 || nks < 1 || nks > 2 || G.npacks <= 0)
+    if (metric == M_HAM || !is16(prec) || nks < 1 || nks > 2 || G.npacks <= 0)
         return;
     const long long rowb = 32ll * nks;
     if ((long long)G.npacks * GP * rowb >= (1ll << 32))
@@ -1944,11 +1967,15 @@ void gram_launch(int metric, int prec, bool fill_pass, const Pts &P,
     } else if (metric == M_L2) {
         if (prec == FNN_PREC_BF16)
             launch_gram<M_L2, FNN_PREC_BF16>(fill_pass, P, G, o, s);
+        else if (prec == FNN_PREC_FP16)
+            launch_gram<M_L2, FNN_PREC_FP16>(fill_pass, P, G, o, s);
         else
             launch_gram<M_L2, FNN_PREC_FP8>(fill_pass, P, G, o, s);
     } else {
         if (prec == FNN_PREC_BF16)
             launch_gram<M_ANG, FNN_PREC_BF16>(fill_pass, P, G, o, s);
+        else if (prec == FNN_PREC_FP16)
+            launch_gram<M_ANG, FNN_PREC_FP16>(fill_pass, P, G, o, s);
         else
             launch_gram<M_ANG, FNN_PREC_FP8>(fill_pass, P, G, o, s);
     }
@@ -1956,12 +1983,12 @@ void gram_launch(int metric, int prec, bool fill_pass, const Pts &P,
 
 // ------------------------------------------------------------- host side --
 
-float gram_eps2(int metric, double eps, const Thr &E, double t2mul)
+float gram_eps2(int metric, double eps, const Thr &E, double t2mul, double add)
 {
     if (metric == M_HAM)
         return std::min(E.lo, 1048576.f);  // floor(eps); beyond any code length
     const double u32 = 1.0 / 16777216.0;
-    const double T2 = gram_t2(metric, eps, E) * t2mul;
+    const double T2 = gram_t2(metric, eps, E) * t2mul + add;
     return (float)(T2 * (1.0 + 320.0 * u32) + 1e-30);
 }
 
@@ -2088,7 +2115,7 @@ static float *cloud_inv_sizes(const fnn_tree *T, Scratch &S)
     return inv;
 }
 
-double gram_margin_ratio(const fnn_tree *T, double t2min, Scratch &S)
+double gram_margin_ratio(const fnn_tree *T, double t2min, int prec, Scratch &S)
 {
     hipStream_t s = S.stream();
     const int n = (int)T->n, dp = T->dp, d = T->dim;
@@ -2100,7 +2127,8 @@ double gram_margin_ratio(const fnn_tree *T, double t2min, Scratch &S)
     const double mean = read_scalar(acc, s) / std::max(n, 1);
     const double u32 = 1.0 / 16777216.0;
     const int kq = (int)cdiv(dp, 16) * 16;
-    const double c1 = 2.25 / 256.0 + (4.0 * kq + 2.0 * d + 72.0) * u32;
+    const double u = prec == FNN_PREC_FP16 ? 1.0 / 2048.0 : 1.0 / 256.0;
+    const double c1 = 2.25 * u + (4.0 * kq + 2.0 * d + 72.0) * u32;
     return t2min > 0 ? 2.0 * c1 * mean / t2min : HUGE_VAL;
 }
 
@@ -2123,7 +2151,7 @@ static void quantise_real(const fnn_tree *T, int prec, int proj, double t2min,
     const float *X = T->metric == M_ANG ? T->xn : T->x;
     if (prec == FNN_PREC_I8)
         fail(FNN_EUNSUPPORTED, "integer MFMA filter is for Hamming codes");
-    const int KS = prec == FNN_PREC_BF16 ? 16 : 64;
+    const int KS = is16(prec) ? 16 : 64;
     if (cdiv(dp, KS) * KS > 128)
         fail(FNN_EUNSUPPORTED, "MFMA filter supports dim <= 128 (got %d)", d);
     // per-cloud centres (one cloud: the global mean)
@@ -2153,13 +2181,42 @@ static void quantise_real(const fnn_tree *T, int prec, int proj, double t2min,
     }
     const int kq = (int)cdiv(dp, KS) * KS;
     const double u32 = 1.0 / 16777216.0;
-    const double u = prec == FNN_PREC_BF16 ? 1.0 / 256.0 : 1.0 / 16.0;
+    const double u = prec == FNN_PREC_BF16   ? 1.0 / 256.0
+                     : prec == FNN_PREC_FP16 ? 1.0 / 2048.0
+                                             : 1.0 / 16.0;
+    // FP16: the filter runs on s (x - mu), s = 2^e with the largest
+    // |coordinate| in [2^14, 2^15) (no overflow), eps^2 scaled by s^2 (exact).
+    // Below 2^-14 the format is subnormal: |q(v) - v| <= u |v| + eta, eta =
+    // 2^-25.  Per coordinate |q(a) q(b) - a b| <= (2u + u^2)|a||b| + 2.01 eta
+    // (|a| + |b|) + eta^2; summed, with |a|_1 <= sqrt(k) |a| and |a| <= (|a|^2
+    // + 1) / 2, the eta part of the error of 2 g~ is at most 2.01 eta sqrt(k)
+    // (|a|^2 + |b|^2) + 4.02 eta sqrt(k) + 2 k eta^2: the first term goes into
+    // c1, the rest is added to the scaled eps^2.
+    const double eta = prec == FNN_PREC_FP16 ? std::ldexp(1.0, -25) : 0.0;
+    G.e2add = prec == FNN_PREC_FP16 ? 4.02 * eta * std::sqrt((double)kq) + 2.0 * kq * eta * eta
+                                    : 0.0;
     // margin coefficient (see the header comment); the FP8 subnormal terms
     // are absorbed by the global scale that maps the largest |coordinate| to
     // at least 224.
     const double c1 = 2.25 * u + (4.0 * kq + 2.0 * d + 72.0) * u32 +
-                      (prec == FNN_PREC_FP8 ? 4.0 * d / 224.0 / 512.0 : 0.0) + c_extra;
+                      (prec == FNN_PREC_FP8 ? 4.0 * d / 224.0 / 512.0 : 0.0) +
+                      2.01 * eta * std::sqrt((double)kq) + c_extra;
     float scale = 1.f;
+    if (prec == FNN_PREC_FP16) {
+        unsigned *mx = S.get<unsigned>(1);
+        fill(mx, 0u, 1, s);
+        FNN_LAUNCH(k_absmax, dim3(grid_cap((int64_t)n * dp, 256, 2048)), dim3(256), 0,
+                   s, X, n, dp, CX, mx);
+        unsigned mb = read_scalar(mx, s);
+        float m;
+        memcpy(&m, &mb, 4);
+        if (m > 0.f) {
+            int e;
+            frexpf(m, &e);  // 2^(e-1) <= m < 2^e
+            scale = ldexpf(1.f, 15 - e);
+        }
+        G.t2mul *= (double)scale * (double)scale;
+    }
     if (prec == FNN_PREC_FP8) {
         unsigned *mx = S.get<unsigned>(1);
         fill(mx, 0u, 1, s);
@@ -2174,14 +2231,19 @@ static void quantise_real(const fnn_tree *T, int prec, int proj, double t2min,
             scale = ldexpf(1.f, e - 1);
         }
     }
-    G.gscale = 1.0f / (scale * scale);
+    // FP8 products are scaled back by gscale; the FP16 filter works in
+    // scaled units throughout (norms, eps^2)
+    G.gscale = prec == FNN_PREC_FP16 ? 1.f : 1.0f / (scale * scale);
     G.kq = kq;
-    void *qbuf = S.raw((size_t)n * kq * (prec == FNN_PREC_BF16 ? 2 : 1) + 64);
+    void *qbuf = S.raw((size_t)n * kq * (is16(prec) ? 2 : 1) + 64);
     float *hxbuf = S.get<float>(n);
     G.q = qbuf;
     G.hx = hxbuf;
     if (prec == FNN_PREC_BF16)
         FNN_LAUNCH((k_quant<FNN_PREC_BF16>), dim3(grid_cap(n, 4, 16384)), dim3(256), 0,
+                   s, X, n, dp, kq, CX, scale, (float)(1.0 - c1), qbuf, hxbuf);
+    else if (prec == FNN_PREC_FP16)
+        FNN_LAUNCH((k_quant<FNN_PREC_FP16>), dim3(grid_cap(n, 4, 16384)), dim3(256), 0,
                    s, X, n, dp, kq, CX, scale, (float)(1.0 - c1), qbuf, hxbuf);
     else
         FNN_LAUNCH((k_quant<FNN_PREC_FP8>), dim3(grid_cap(n, 4, 16384)), dim3(256), 0,
@@ -2212,6 +2274,7 @@ void gram_prepare(const fnn_tree *T, int prec, int proj, double eps, const Thr &
                   GramArgs &G, int2 **rest, long long *nrest)
 {
     hipStream_t s = S.stream();
+    G.e2add = 0.0;
     if (T->metric == M_HAM) {
         quantise_ham(T, prec, S, G);
         G.t2mul = 1.0;
@@ -2220,7 +2283,7 @@ void gram_prepare(const fnn_tree *T, int prec, int proj, double eps, const Thr &
     } else {
         quantise_real(T, prec, proj, t2min, S, G);
     }
-    G.e2f = gram_eps2(T->metric, eps, E, G.t2mul);
+    G.e2f = gram_eps2(T->metric, eps, E, G.t2mul, G.e2add);
     G.E = E;
 
     const int nn = (int)T->nnodes;

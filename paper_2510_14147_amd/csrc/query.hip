@@ -1793,7 +1793,7 @@ static void eps_graph_impl(const fnn_tree *Tc, const double *epsv,
     for (int c = 0; c < ncl; ++c)
         t2min = std::min(t2min, gram_t2(M, epsv[c], ct_h[c].E));
     // filter precision: the caller's, or (automatic) the MFMA filter where it
-    // pays: int8 on short Hamming codes; BF16 on vector data of 16..128
+    // pays: int8 on short Hamming codes; FP16 on vector data of 16..128
     // coordinates when its rounding margin is small against eps^2
     int prec = opt.precision;
     if (prec == FNN_PREC_AUTO) {
@@ -1801,8 +1801,8 @@ static void eps_graph_impl(const fnn_tree *Tc, const double *epsv,
         if (M == M_HAM && T->dp <= 4)
             prec = FNN_PREC_I8;
         if ((M == M_L2 || M == M_ANG) && T->dim >= 16 && T->dp <= 128 &&
-            gram_margin_ratio(T, t2min, S) <= 0.5)
-            prec = FNN_PREC_BF16;
+            gram_margin_ratio(T, t2min, FNN_PREC_FP16, S) <= 0.5)
+            prec = FNN_PREC_FP16;
     }
     st.precision_used = prec;
     const bool use_gram = ((M == M_L2 || M == M_ANG) && prec != FNN_PREC_FP32) ||
@@ -1854,11 +1854,12 @@ static void eps_graph_impl(const fnn_tree *Tc, const double *epsv,
             gram_pad_packs(M, prec, G, S);
             G.ct = ncl > 1 ? ct_d : nullptr;
             G.pcl = ncl > 1 ? T->pcl : nullptr;
-            if (ncl > 1 && G.t2mul != 1.0) {
-                // the filter's per-cloud eps^2 on principal coordinates
+            if (ncl > 1 && (G.t2mul != 1.0 || G.e2add != 0.0)) {
+                // the filter's per-cloud eps^2 on principal coordinates or
+                // in scaled units
                 std::vector<CloudThr> cg(ct_h);
                 for (int c = 0; c < ncl; ++c)
-                    cg[c].e2f = gram_eps2(M, epsv[c], cg[c].E, G.t2mul);
+                    cg[c].e2f = gram_eps2(M, epsv[c], cg[c].E, G.t2mul, G.e2add);
                 CloudThr *cg_d = S.get<CloudThr>(ncl);
                 FNN_HIP(hipMemcpyAsync(cg_d, cg.data(), sizeof(CloudThr) * ncl,
                                        hipMemcpyHostToDevice, s));
@@ -1917,7 +1918,7 @@ static void eps_graph_impl(const fnn_tree *Tc, const double *epsv,
                 FNN_HIP(hipMemcpyAsync(hacc, acc, sizeof hacc, hipMemcpyDeviceToHost, s));
                 FNN_HIP(hipStreamSynchronize(s));
                 const double fac = prec == FNN_PREC_I8     ? 1.25
-                                   : prec == FNN_PREC_BF16 ? 2.5
+                                   : prec == FNN_PREC_BF16 || prec == FNN_PREC_FP16 ? 2.5
                                                                     : 40.0;
                 cap = std::max<long long>(1ll << 20, (long long)(0.5 * hacc[1] * fac));
             }

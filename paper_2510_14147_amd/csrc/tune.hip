@@ -164,7 +164,7 @@ extern "C" int fnn_autotune(const void *points, const int64_t *offsets,
     };
     const bool vec = metric == FNN_L2 || metric == FNN_ANGULAR;
     if (vec && dim <= 128)
-        try_values(&fnn_options::precision, {FNN_PREC_FP32, FNN_PREC_BF16});
+        try_values(&fnn_options::precision, {FNN_PREC_FP32, FNN_PREC_FP16});
     else if (metric == FNN_HAMMING && dim <= 256)
         try_values(&fnn_options::precision, {FNN_PREC_FP32, FNN_PREC_I8});
     bool have_model = false;

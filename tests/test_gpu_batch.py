@@ -174,7 +174,7 @@ def test_batch_levenshtein(fnn, orc):
     run_batch(fnn, orc, clouds, "levenshtein", eps, zeta=8)
 
 
-@pytest.mark.parametrize("precision", ["bf16", "fp8"])
+@pytest.mark.parametrize("precision", ["bf16", "fp16", "fp8"])
 def test_batch_mfma(fnn, orc, precision):
     # MFMA groups of 4 packs may span clouds: pairs across clouds must be
     # skipped and each pack filtered with its own cloud's eps

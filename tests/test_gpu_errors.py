@@ -233,7 +233,7 @@ def test_plain_entry_points_on_device_pointers(fnn, orc):
     assert cmp["ok"], cmp
 
 
-@pytest.mark.parametrize("precision", ["bf16", "fp32"])
+@pytest.mark.parametrize("precision", ["bf16", "fp16", "fp32"])
 def test_forced_list_overflow_matches_oracle(fnn, orc, precision):
     """A tiny initial list forces the redo paths: a second filter pass into a
     list sized from the first pass's count (MFMA), or the count / fill pair
@@ -242,12 +242,12 @@ def test_forced_list_overflow_matches_oracle(fnn, orc, precision):
     x = G.c2_manifold(n=9000)
     eps = W["c2_50k"]["eps"][0]
     tree = fnn.fnn_tree_build(x, "l2")
-    g = fnn.fnn_eps_graph(tree, eps, precision=precision, proj=-1 if precision == "bf16" else None,
-                          list_cap=1000)
+    g = fnn.fnn_eps_graph(tree, eps, precision=precision,
+                          proj=-1 if precision in ("bf16", "fp16") else None, list_cap=1000)
     ref = orc.bruteforce(x, 0, eps)
     cmp = orc.compare_csr(*g.to_numpy(), *ref)
     assert cmp["ok"], cmp
-    if precision == "bf16":
+    if precision in ("bf16", "fp16"):
         assert g.stats["overflow_rows"] == 1       # one more filter pass ran
         assert g.stats["filter_survivors"] >= ref[0][-1] // 2
     g2 = fnn.fnn_eps_graph(tree, eps, precision=precision)

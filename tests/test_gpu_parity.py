@@ -165,9 +165,9 @@ def test_deterministic(fnn, orc):
         assert np.array_equal(u, v)
 
 
-# ---- MFMA Gram filter (BF16 / FP8) -----------------------------------------
+# ---- MFMA Gram filter (BF16 / FP16 / FP8) ----------------------------------
 
-@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+@pytest.mark.parametrize("prec", ["bf16", "fp16", "fp8"])
 @pytest.mark.parametrize("case", ["c1", "rand16", "c2_8k", "ang"])
 def test_mfma_filter_parity(fnn, orc, prec, case):
     if case == "c1":
@@ -184,6 +184,33 @@ def test_mfma_filter_parity(fnn, orc, prec, case):
     assert st["filter_pairs"] > 0
     assert st["validate_mismatch"] == 0
     assert st["max_rel_err"] <= 1e-5
+
+
+@pytest.mark.parametrize("offset,spread", [(1e6, 1.0), (0.0, 1e4), (0.0, 1e-6), (3.0, 1e-3)])
+def test_fp16_filter_scaled_ranges(fnn, orc, offset, spread):
+    """The FP16 filter scales the centred rows by a power of two: large
+    offsets and spreads must not overflow the format, tiny ones must not lose
+    edges to subnormals; zero false negatives and the exact graph."""
+    x = (G.random_points(3000, 16, seed=5, duplicates=20).astype(np.float64) * spread
+         + offset).astype(np.float32)
+    eps = 0.6 * spread
+    print(f"[case] fp16 ranges offset={offset} spread={spread}", flush=True)
+    tree, g, cmp = check(fnn, orc, x, "l2", eps, tree_check=False, precision="fp16",
+                         validate=True)
+    assert g.stats["validate_mismatch"] == 0
+
+
+def test_fp16_filter_narrower_than_bf16(fnn, orc):
+    """Same graph from both 16-bit filters; the FP16 margin is eight times
+    narrower, so it passes fewer non-edges."""
+    x = G.c2_manifold(n=20000)
+    eps = W["c2_50k"]["eps"][0]
+    _, gb, _ = check(fnn, orc, x, "l2", eps, tree_check=False, precision="bf16")
+    _, gh, _ = check(fnn, orc, x, "l2", eps, tree_check=False, precision="fp16")
+    assert gh.stats["proj_dim"] == gb.stats["proj_dim"] == 16
+    assert gh.nnz // 2 <= gh.stats["filter_survivors"] < gb.stats["filter_survivors"]
+    for u, v in zip(gb.to_numpy(), gh.to_numpy()):
+        assert np.array_equal(u.view(np.uint8), v.view(np.uint8))
 
 
 def test_mfma_filter_screens(fnn, orc):
@@ -241,7 +268,7 @@ def test_int8_rejects_other_inputs(fnn, orc):
 
 # ---- filter on leading principal coordinates ---------------------------------
 
-@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+@pytest.mark.parametrize("prec", ["bf16", "fp16", "fp8"])
 @pytest.mark.parametrize("proj", [16, 32, 64])
 def test_projected_filter_parity(fnn, orc, prec, proj):
     # a fixed number of principal coordinates: the filter must stay
@@ -288,7 +315,7 @@ def test_projected_filter_rejects_bad_width(fnn, orc):
 
 # ---- automatic precision ------------------------------------------------------
 
-@pytest.mark.parametrize("case,want", [("c2_20k", "bf16"), ("rand8", "fp32"),
+@pytest.mark.parametrize("case,want", [("c2_20k", "fp16"), ("rand8", "fp32"),
                                        ("ham256", "i8"), ("ham512", "fp32"),
                                        ("lev", "fp32")])
 def test_auto_precision(fnn, orc, case, want):

@@ -58,7 +58,7 @@ def test_query_l2_with_duplicates(fnn, orc):
     check_query(fnn, orc, P, Q, "l2", 0.25)
 
 
-@pytest.mark.parametrize("precision", ["fp32", "bf16", "auto"])
+@pytest.mark.parametrize("precision", ["fp32", "bf16", "fp16", "auto"])
 def test_query_manifold(fnn, orc, precision):
     X = G.c2_manifold(n=10000)
     g = check_query(fnn, orc, X[:8000], X[8000:], "l2", W["c2_50k"]["eps"][1],

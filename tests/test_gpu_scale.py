@@ -112,7 +112,7 @@ def _same_csr_on_device(g1, g2):
 
 
 def test_c2a_bench_path_sampled(fnn, orc):
-    """Exactly what the benchmark times: automatic precision (BF16 filter on
+    """Exactly what the benchmark times: automatic precision (FP16 filter on
     16 principal coordinates), the closed-form dense pack list, two-pass
     emission; sampled rows against the oracle, and every entry against the
     plain FP32 path on the same tree."""
@@ -122,7 +122,7 @@ def test_c2a_bench_path_sampled(fnn, orc):
     tree = fnn.fnn_tree_build(x, "l2")
     g = fnn.fnn_eps_graph(tree, eps, precision="auto", sched="two_pass", proj=0)
     st = g.stats
-    assert st["precision_used"] == fnn.PRECISIONS["bf16"]
+    assert st["precision_used"] == fnn.PRECISIONS["fp16"]
     assert st["proj_dim"] == 16
     # the dense list: every pack against every later pack, no traversal
     assert st["interactions"] == st["packs"] * (st["packs"] + 1) // 2
@@ -159,7 +159,7 @@ def test_c2b_two_pass_and_learned_sampled(fnn, orc):
     tree = fnn.fnn_tree_build(x, "l2")
     g = fnn.fnn_eps_graph(tree, eps, precision="auto", sched="two_pass")
     assert 350 < g.nnz / g.n < 700
-    assert g.stats["precision_used"] == fnn.PRECISIONS["bf16"]
+    assert g.stats["precision_used"] == fnn.PRECISIONS["fp16"]
     assert g.stats["overflow_rows"] == 0      # one filter pass
     whole_graph_properties(g)
     _check_rows(orc, x, "l2", eps, g, 150, 32)
