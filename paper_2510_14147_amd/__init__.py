@@ -98,11 +98,17 @@ def _torch():
 
 @_ALLOC_FN
 def _alloc_cb(nbytes, ctx):
-    torch = _torch()
-    t = torch.empty(int(nbytes), dtype=torch.uint8, device="cuda")
-    p = t.data_ptr()
-    _live[p] = t
-    return p
+    # an exception escaping a ctypes callback leaves its return value
+    # undefined (not NULL): report every failure as NULL, which the library
+    # turns into FNN_ENOMEM
+    try:
+        torch = _torch()
+        t = torch.empty(int(nbytes), dtype=torch.uint8, device="cuda")
+        p = t.data_ptr()
+        _live[p] = t
+        return p
+    except BaseException:
+        return None
 
 
 @_FREE_FN

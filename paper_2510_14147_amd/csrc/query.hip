@@ -1931,6 +1931,11 @@ static void eps_graph_impl(const fnn_tree *Tc, const double *epsv,
             const bool direct = M == M_HAM && !opt.validate;
             int32_t *degp = direct ? S.get<int32_t>(n) : nullptr;
             for (int attempt = 0;; ++attempt) {
+                // a list (and its decided edges) larger than the device
+                // cannot be allocated: say so before asking
+                if ((double)cap * (sizeof(int2) + sizeof(int2) + sizeof(float)) > (double)totb)
+                    fail(FNN_ENOMEM, "survivor list of %lld entries exceeds device memory",
+                         (long long)cap);
                 G.surv = S.get<int2>(cap);
                 G.surv_cap = cap;
                 G.nsurv = ns;

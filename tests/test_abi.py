@@ -127,3 +127,14 @@ def test_options_struct_matches_header():
     assert ctypes.sizeof(fnn_tune_result) == 64 + 8 + 8 + 4 + 4 + 4 * 8
     assert ctypes.sizeof(fnn_csr) == 8 + 8 + 8 + 3 * 8
     assert ctypes.sizeof(fnn_stats) == 17 * 8 + 12 * 8 + 8 + 8 + 8 + 5 * 8 + 3 * 8 + 8
+
+
+def test_alloc_callback_reports_failure_as_null():
+    """The Python allocator behind fnn_set_allocator must hand the library a
+    NULL (which it turns into FNN_ENOMEM) when torch cannot allocate: an
+    exception escaping a ctypes callback would leave an undefined pointer."""
+    import ctypes
+    import paper_2510_14147_amd as f
+    call = f._ALLOC_FN(ctypes.cast(f._alloc_cb, ctypes.c_void_p).value)
+    for _ in range(3):
+        assert call(1 << 62, None) in (None, 0)
