@@ -1228,6 +1228,9 @@ __device__ __forceinline__ void half_finish(const GramArgs &G, const f32x16 (&ac
                                             const unsigned *rmS)
 {
     const int lane = threadIdx.x & (WAVE - 1), l32 = lane & 31, hi = lane >> 5;
+    // keep the entry-dependent row and column arithmetic here: without this
+    // the compiler computes it ahead of the vote, on every half
+    asm volatile("" : "+v"(na), "+v"(nb), "+v"(pa), "+v"(pb));
     unsigned fill = (unsigned)__builtin_amdgcn_readfirstlane((int)*fillS);
     const uint64_t ltmask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
 #pragma unroll
