@@ -65,6 +65,10 @@ struct GramArgs {
     // are the edges, and degp counts the edges of each tree position; null
     // otherwise
     int32_t *degp;
+    // survivor decisions: where non-null, the ranks the degree counters
+    // returned for an edge's two endpoints (slot i, like the edge), so the
+    // fill places it without a cursor
+    int2 *erank;
     // filter on leading principal coordinates: their number (0: off), the
     // factor applied to eps^2 (1 when off) and the captured variance
     int proj;
@@ -95,6 +99,12 @@ void survivors_launch(int metric, const Pts &P, const GramArgs &G,
 // listed in both directions, each entry written into its first id's row.
 void edges_scatter(const int2 *edges, const float *edist, long long ne, bool both,
                    const TileOut &o, hipStream_t s);
+// Decided survivors into the CSR without cursors: edge i goes to slots
+// row_ptr[a] + ranks[i].x of row a and row_ptr[b] + ranks[i].y of row b, the
+// ranks its degree counters returned (each in [0, degree), so the rows
+// fill exactly); a rank past its row sets ERR_INDEX.
+void edges_place(const int2 *edges, const float *edist, const int2 *erank, long long ne,
+                 const int64_t *row_ptr, const TileOut &o, hipStream_t s);
 // Survivors of the exact integer filter (tree positions) into the CSR, with
 // their Hamming distances.
 void edges_scatter_ham(const int2 *surv, long long ne, const Pts &P,

@@ -1587,6 +1587,7 @@ k_survive(Pts P, GramArgs G, long long ns, int2 *__restrict__ edges,
         bool edge = false;
         float dd = 0.f;
         int oi = 0, oj = 0;
+        int2 rk = make_int2(0, 0);   // the edge's ranks in its two rows
         int2 e = make_int2(-1, -1);  // (-1, -1): an unused slot
         if (i < ns)
             e = G.surv[i];
@@ -1640,8 +1641,13 @@ k_survive(Pts P, GramArgs G, long long ns, int2 *__restrict__ edges,
                 }
                 oi = G.perm[pi];
                 oj = G.perm[pj];
-                atomicAdd(&out.deg[oi], 1);
-                atomicAdd(&out.deg[oj], 1);
+                if (G.erank) {
+                    rk.x = atomicAdd(&out.deg[oi], 1);
+                    rk.y = atomicAdd(&out.deg[oj], 1);
+                } else {
+                    atomicAdd(&out.deg[oi], 1);
+                    atomicAdd(&out.deg[oj], 1);
+                }
             }
         }
         // the survivor's own slot: an edge, or a hole (-1, -1) that the
@@ -1649,6 +1655,8 @@ k_survive(Pts P, GramArgs G, long long ns, int2 *__restrict__ edges,
         if (i < ns) {
             edges[i] = edge ? make_int2(oi, oj) : make_int2(-1, -1);
             edist[i] = dd;
+            if (G.erank)
+                G.erank[i] = rk;
         }
     }
     nrc = wave_sum(nrc);
@@ -1733,6 +1741,41 @@ __global__ void k_edges_scatter(const int2 *__restrict__ edges,
             atomicOr(out.err, ERR_INDEX);
         }
     }
+}
+
+__global__ void k_edges_place(const int2 *__restrict__ edges,
+                              const float *__restrict__ edist,
+                              const int2 *__restrict__ erank, long long ne,
+                              const int64_t *__restrict__ row_ptr, TileOut out)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < ne;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int2 e = edges[i];
+        if (e.x < 0)
+            continue;  // a survivor that is no edge
+        const int2 r = erank[i];
+        const float d = edist[i];
+        const int64_t a0 = row_ptr[e.x], a1 = row_ptr[e.x + 1];
+        const int64_t b0 = row_ptr[e.y], b1 = row_ptr[e.y + 1];
+        const int64_t s1 = a0 + r.x, s2 = b0 + r.y;
+        if (r.x >= 0 && r.y >= 0 && s1 < a1 && s2 < b1) {
+            out.col[s1] = e.y;
+            out.dist[s1] = d;
+            out.col[s2] = e.x;
+            out.dist[s2] = d;
+        } else {
+            atomicOr(out.err, ERR_INDEX);
+        }
+    }
+}
+
+void edges_place(const int2 *edges, const float *edist, const int2 *erank, long long ne,
+                 const int64_t *row_ptr, const TileOut &o, hipStream_t s)
+{
+    if (ne <= 0)
+        return;
+    FNN_LAUNCH(k_edges_place, dim3(grid_cap(ne, 256, 65536)), dim3(256), 0, s, edges, edist,
+               erank, ne, row_ptr, o);
 }
 
 void survivors_launch(int metric, const Pts &P, const GramArgs &G,
