@@ -533,19 +533,22 @@ def main():
         print(f"[bench] plain fp32 step: {pms:.1f} ms", file=sys.stderr, flush=True)
     kept.clear()
     if args.workload == "c2a" and not args.no_extra:
-        # the same points at the ~500-neighbour radius, both schedules, and
-        # the learned schedule at the headline radius
+        # the same points at the ~500-neighbour radius, both schedules, the
+        # learned schedule at the headline radius, and the BF16 and FP8
+        # filters in place of the automatic choice
         xd, _, m, _, d, p = jobs[0]
         extra = {}
-        for key, e, sched in (("c2a_learned", eps, "learned"),
-                              ("c2b_two_pass", W["c2"]["eps"][1], "two_pass"),
-                              ("c2b_learned", W["c2"]["eps"][1], "learned")):
-            o = dict(opts[0], sched=sched)
-            run_job(xd, None, m, e, o, p)
+        for key, e, sched, pr in (("c2a_learned", eps, "learned", p),
+                                  ("c2b_two_pass", W["c2"]["eps"][1], "two_pass", p),
+                                  ("c2b_learned", W["c2"]["eps"][1], "learned", p),
+                                  ("c2a_bf16", eps, "two_pass", "bf16"),
+                                  ("c2a_fp8", eps, "two_pass", "fp8")):
+            o = dict(opts[0], sched=sched, precision=pr)
+            run_job(xd, None, m, e, o, pr)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             for _ in range(args.extra_steps):
-                tree, g = run_job(xd, None, m, e, o, p)
+                tree, g = run_job(xd, None, m, e, o, pr)
                 st, tst, nz = g.stats, tree.stats, g.nnz
                 del tree, g
             torch.cuda.synchronize()
