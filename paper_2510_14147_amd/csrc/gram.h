@@ -65,6 +65,10 @@ struct GramArgs {
     // are the edges, and degp counts the edges of each tree position; null
     // otherwise
     int32_t *degp;
+    // screened pairs when the work list is every pair of one cloud
+    // (n (n - 1) / 2, known in closed form); -1 otherwise (counted on the
+    // device)
+    long long dense_pairs;
     // survivor decisions: where non-null, the ranks the degree counters
     // returned for an edge's two endpoints (slot i, like the edge), so the
     // fill places it without a cursor
@@ -116,7 +120,17 @@ void degrees_from_positions(const int32_t *degp, const int32_t *perm, int n,
 // 2 c1 mean|x - mu|^2 / t2min for the BF16 filter (mu per cloud): how much
 // its rounding margin widens the test against the smallest squared
 // threshold; small values mean a selective filter.
-double gram_margin_ratio(const fnn_tree *T, double t2min, int prec, Scratch &S);
+// Per-query statistics of the rows the filter quantises, computed once by
+// the automatic precision rule and reused by the quantisation: the cloud
+// centres (column sums and 1 / sizes) and the largest |x - mu|.
+struct GramPre {
+    const float *sums = nullptr;
+    const float *inv = nullptr;
+    float absmax = 0.f;
+    bool have = false;
+};
+double gram_margin_ratio(const fnn_tree *T, double t2min, int prec, Scratch &S,
+                         GramPre *pre = nullptr);
 
 // True when no query pack exceeds the filter's tile height (the work list
 // of every pack pair then exists in closed form).
@@ -133,7 +147,8 @@ float gram_eps2(int metric, double eps, const Thr &E, double t2mul = 1.0, double
 // else their number); t2min: smallest squared threshold of the query.
 void gram_prepare(const fnn_tree *T, int prec, int proj, double eps, const Thr &E,
                   double t2min, const int2 *inter, long long ninter, Scratch &S,
-                  GramArgs &G, int2 **rest, long long *nrest);
+                  GramArgs &G, int2 **rest, long long *nrest,
+                  const GramPre *pre = nullptr);
 void gram_launch(int metric, int prec, bool fill_pass, const Pts &P,
                  const GramArgs &G, const TileOut &o, hipStream_t s);
 

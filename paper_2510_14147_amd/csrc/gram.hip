@@ -405,10 +405,12 @@ k_pca(const double *__restrict__ C, int dp, int kmax, int kfix, double t2, doubl
 constexpr int PJ_K = 16, PJ_C = 64;
 __global__ void __launch_bounds__(256)
 k_project(const float *__restrict__ x, int n, int dp, Centre C,
-          const double *__restrict__ Q, int K, float *__restrict__ z)
+          const double *__restrict__ Q, int K, float *__restrict__ z,
+          unsigned *__restrict__ zmax)
 {
     __shared__ double Qs[PJ_C][PJ_K];
     __shared__ double Ms[PJ_C];
+    float zm = 0.f;  // largest |z| this thread wrote
     // blocks stride over row blocks (the same trip count in every thread)
     for (long long base = (long long)blockIdx.x * blockDim.x; base < n;
          base += (long long)gridDim.x * blockDim.x) {
@@ -453,10 +455,17 @@ k_project(const float *__restrict__ x, int n, int dp, Centre C,
         if (row)
 #pragma unroll
             for (int k = 0; k < PJ_K; ++k)
-                if (kc + k < K)
-                    z[(size_t)i * K + kc + k] = (float)acc[k];
+                if (kc + k < K) {
+                    const float zf = (float)acc[k];
+                    z[(size_t)i * K + kc + k] = zf;
+                    zm = fmaxf(zm, fabsf(zf));
+                }
     }
     }
+    // the largest |z| (the FP16 filter's scale), one atomic per wave
+    zm = wave_max(zm);
+    if (zmax && (threadIdx.x & (WAVE - 1)) == 0)
+        atomicMax(zmax, __float_as_uint(zm));
 }
 
 __global__ void k_absmax(const float *__restrict__ x, int n, int dp, Centre C,
@@ -475,23 +484,28 @@ __global__ void k_absmax(const float *__restrict__ x, int n, int dp, Centre C,
 
 // Sum over points of |x - mu|^2 (mu per cloud), one atomic per wave.
 __global__ void k_sqdev(const float *__restrict__ x, int n, int dp, Centre C,
-                        double *__restrict__ out)
+                        double *__restrict__ out, unsigned *__restrict__ amax)
 {
     const int lane = threadIdx.x & (WAVE - 1);
     const int wpb = blockDim.x / WAVE;
     double acc = 0.0;
+    float m = 0.f;  // and the largest |x - mu|
     for (int i = blockIdx.x * wpb + threadIdx.x / WAVE; i < n; i += gridDim.x * wpb) {
         const int cl = C.cloud(i);
         float ss = 0.f;
         for (int k = lane; k < dp; k += WAVE) {
             const float v = x[(size_t)i * dp + k] - C.mu(cl, k);
             ss = fmaf(v, v, ss);
+            m = fmaxf(m, fabsf(v));
         }
         acc += (double)ss;
     }
     acc = wave_sum(acc);
+    m = wave_max(m);
     if (lane == 0 && acc != 0.0)
         atomicAdd(out, acc);
+    if (lane == 0 && amax)
+        atomicMax(amax, __float_as_uint(m));
 }
 
 // Hamming codes as signed bytes for the integer Gram: bit b of a code
@@ -1918,7 +1932,10 @@ static void launch_gram_direct(const Pts &P, const GramArgs &G, const TileOut &o
     const long long need = ((long long)G.nunits + 7) / 8 * 8;
     const dim3 grid((unsigned)std::max<long long>(8, std::min(want, need)));
     FNN_LAUNCH((k_gram_direct<M, PREC, NKS>), grid, dim3(GT), 0, s, P, G, o);
-    FNN_LAUNCH(k_gram_pairs, dim3(grid_cap(G.nlist, 256, 4096)), dim3(256), 0, s, G, o);
+    if (G.dense_pairs >= 0)
+        fill(o.cnt + 2, (unsigned long long)G.dense_pairs, 1, s);
+    else
+        FNN_LAUNCH(k_gram_pairs, dim3(grid_cap(G.nlist, 256, 4096)), dim3(256), 0, s, G, o);
 }
 
 template <int M, int PREC>
@@ -2067,7 +2084,7 @@ static void quantise_ham(const fnn_tree *T, int prec, Scratch &S, GramArgs &G)
 // root, else K = 0).
 static int project_pca(const float *X, int n, int dp, int kq_full, int proj,
                        double t2min, const Centre &CX, Scratch &S, float **z,
-                       double *rho, double *captured)
+                       double *rho, double *captured, unsigned *zmax, float known_absmax)
 {
     hipStream_t s = S.stream();
     const int kmax = std::min({PCA_MAXK, (kq_full - 1) / 16 * 16, dp / 16 * 16});
@@ -2102,13 +2119,15 @@ static int project_pca(const float *X, int n, int dp, int kq_full, int proj,
         return 0;
     // FP64 rounding of the projection: |z~_k - z_k| <= gamma sum_c |Q_ck| |v_c|
     // <= gamma sqrt(rho) |v|, |v| <= sqrt(dp) max |x_c - mu_c|
-    unsigned *mx = S.get<unsigned>(1);
-    fill(mx, 0u, 1, s);
-    FNN_LAUNCH(k_absmax, dim3(grid_cap((int64_t)n * dp, 256, 2048)), dim3(256), 0, s, X, n, dp,
-               CX, mx);
-    const unsigned mb = read_scalar(mx, s);
-    float am;
-    memcpy(&am, &mb, 4);
+    float am = known_absmax;  // largest |x - mu| (negative: not known yet)
+    if (am < 0.f) {
+        unsigned *mx = S.get<unsigned>(1);
+        fill(mx, 0u, 1, s);
+        FNN_LAUNCH(k_absmax, dim3(grid_cap((int64_t)n * dp, 256, 2048)), dim3(256), 0, s, X,
+                   n, dp, CX, mx);
+        const unsigned mb = read_scalar(mx, s);
+        memcpy(&am, &mb, 4);
+    }
     const double u64 = 1.1102230246251565e-16;
     const double gam = (dp + 2) * u64 / (1.0 - (dp + 2) * u64);
     const double V = std::sqrt((double)dp) * (double)am * (1.0 + 1e-6);
@@ -2116,8 +2135,10 @@ static int project_pca(const float *X, int n, int dp, int kq_full, int proj,
     if (!(2.0 * emax <= 5e-7 * std::sqrt(hinfo[0]) * std::sqrt(t2min)))
         return 0;
     *z = S.get<float>((size_t)n * K);
+    if (zmax)
+        fill(zmax, 0u, 1, s);
     FNN_LAUNCH(k_project, dim3(grid_for(n, 256)), dim3(256), 0, s, X, n,
-               dp, CX, Qd, K, *z);
+               dp, CX, Qd, K, *z, zmax);
     *rho = hinfo[0];
     *captured = hinfo[1];
     return K;
@@ -2161,16 +2182,30 @@ static float *cloud_inv_sizes(const fnn_tree *T, Scratch &S)
     return inv;
 }
 
-double gram_margin_ratio(const fnn_tree *T, double t2min, int prec, Scratch &S)
+double gram_margin_ratio(const fnn_tree *T, double t2min, int prec, Scratch &S,
+                         GramPre *pre)
 {
     hipStream_t s = S.stream();
     const int n = (int)T->n, dp = T->dp, d = T->dim;
     const float *X = T->metric == M_ANG ? T->xn : T->x;
-    const Centre CX = make_centre(T, X, dp, cloud_inv_sizes(T, S), S);
-    double *acc = S.get<double>(1);
-    fill(acc, 0.0, 1, s);
-    FNN_LAUNCH(k_sqdev, dim3(grid_cap(n, 4, 4096)), dim3(256), 0, s, X, n, dp, CX, acc);
-    const double mean = read_scalar(acc, s) / std::max(n, 1);
+    const float *inv = cloud_inv_sizes(T, S);
+    const Centre CX = make_centre(T, X, dp, inv, S);
+    double *acc = S.get<double>(2);  // [0] sum of |x - mu|^2, [1] largest |x - mu|
+    fill(acc, 0.0, 2, s);
+    FNN_LAUNCH(k_sqdev, dim3(grid_cap(n, 4, 4096)), dim3(256), 0, s, X, n, dp, CX, acc,
+               reinterpret_cast<unsigned *>(acc + 1));
+    double h[2];
+    FNN_HIP(hipMemcpyAsync(h, acc, sizeof h, hipMemcpyDeviceToHost, s));
+    FNN_HIP(hipStreamSynchronize(s));
+    const double mean = h[0] / std::max(n, 1);
+    if (pre) {
+        unsigned mb;
+        memcpy(&mb, &h[1], 4);  // the low word holds the float bits
+        memcpy(&pre->absmax, &mb, 4);
+        pre->sums = CX.sums;
+        pre->inv = inv;
+        pre->have = true;
+    }
     const double u32 = 1.0 / 16777216.0;
     const int kq = (int)cdiv(dp, 16) * 16;
     const double u = prec == FNN_PREC_FP16 ? 1.0 / 2048.0 : 1.0 / 256.0;
@@ -2189,7 +2224,7 @@ double gram_margin_ratio(const fnn_tree *T, double t2min, int prec, Scratch &S)
 // (|z~(x)|^2 + |z~(y)|^2): eps^2 is scaled by t2mul = rho (1 + 4e-6) and
 // c1 grows by 1e-7.
 static void quantise_real(const fnn_tree *T, int prec, int proj, double t2min,
-                          Scratch &S, GramArgs &G)
+                          Scratch &S, GramArgs &G, const GramPre *pre)
 {
     hipStream_t s = S.stream();
     const int n = (int)T->n;
@@ -2200,19 +2235,25 @@ static void quantise_real(const fnn_tree *T, int prec, int proj, double t2min,
     const int KS = is16(prec) ? 16 : 64;
     if (cdiv(dp, KS) * KS > 128)
         fail(FNN_EUNSUPPORTED, "MFMA filter supports dim <= 128 (got %d)", d);
-    // per-cloud centres (one cloud: the global mean)
-    const float *inv = cloud_inv_sizes(T, S);
-    Centre CX = make_centre(T, X, dp, inv, S);
+    // per-cloud centres (one cloud: the global mean), from the automatic
+    // precision rule's pass when it ran
+    const bool known = pre && pre->have;
+    const float *inv = known ? pre->inv : cloud_inv_sizes(T, S);
+    Centre CX = known ? Centre{pre->sums, inv, centre_clouds(T) > 1 ? T->pcl : nullptr, dp}
+                      : make_centre(T, X, dp, inv, S);
     G.t2mul = 1.0;
     G.proj = 0;
     G.captured = 0.0;
     double c_extra = 0.0;
+    unsigned *zmax = nullptr;  // largest |z| (float bits), from the projection
     {
         float *z = nullptr;
         double rho = 1.0, cap = 0.0;
+        unsigned *zm = S.get<unsigned>(1);
         const int K = project_pca(X, n, dp, (int)cdiv(dp, KS) * KS, proj, t2min, CX, S,
-                                  &z, &rho, &cap);
+                                  &z, &rho, &cap, zm, known ? pre->absmax : -1.f);
         if (K > 0) {
+            zmax = zm;
             X = z;
             dp = d = K;
             G.t2mul = rho * (1.0 + 4e-6);
@@ -2249,10 +2290,15 @@ static void quantise_real(const fnn_tree *T, int prec, int proj, double t2min,
                       2.01 * eta * std::sqrt((double)kq) + c_extra;
     float scale = 1.f;
     if (prec == FNN_PREC_FP16) {
-        unsigned *mx = S.get<unsigned>(1);
-        fill(mx, 0u, 1, s);
-        FNN_LAUNCH(k_absmax, dim3(grid_cap((int64_t)n * dp, 256, 2048)), dim3(256), 0,
-                   s, X, n, dp, CX, mx);
+        // largest |x - mu|: from the projection (z is centred about 0), else
+        // one pass over the rows
+        unsigned *mx = zmax;
+        if (!mx) {
+            mx = S.get<unsigned>(1);
+            fill(mx, 0u, 1, s);
+            FNN_LAUNCH(k_absmax, dim3(grid_cap((int64_t)n * dp, 256, 2048)), dim3(256), 0,
+                       s, X, n, dp, CX, mx);
+        }
         unsigned mb = read_scalar(mx, s);
         float m;
         memcpy(&m, &mb, 4);
@@ -2317,17 +2363,18 @@ double gram_t2(int metric, double eps, const Thr &E)
 // Quantised copy + per-point terms, and the MFMA work lists, for one query.
 void gram_prepare(const fnn_tree *T, int prec, int proj, double eps, const Thr &E,
                   double t2min, const int2 *inter, long long ninter, Scratch &S,
-                  GramArgs &G, int2 **rest, long long *nrest)
+                  GramArgs &G, int2 **rest, long long *nrest, const GramPre *pre)
 {
     hipStream_t s = S.stream();
     G.e2add = 0.0;
+    G.dense_pairs = -1;
     if (T->metric == M_HAM) {
         quantise_ham(T, prec, S, G);
         G.t2mul = 1.0;
         G.proj = 0;
         G.captured = 0.0;
     } else {
-        quantise_real(T, prec, proj, t2min, S, G);
+        quantise_real(T, prec, proj, t2min, S, G, pre);
     }
     G.e2f = gram_eps2(T->metric, eps, E, G.t2mul, G.e2add);
     G.E = E;
@@ -2391,6 +2438,9 @@ void gram_prepare(const fnn_tree *T, int prec, int proj, double eps, const Thr &
                 G.ubeg = ubeg;
                 G.nunits = nu;
                 G.nlist = (int)e;
+                // every pair of one cloud: the narrow kernel screens each once
+                if (T->ncloud <= 1 && T->cross_a < 0)
+                    G.dense_pairs = T->n * (T->n - 1) / 2;
                 return;
             }
         }

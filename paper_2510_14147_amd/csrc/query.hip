@@ -1796,12 +1796,13 @@ static void eps_graph_impl(const fnn_tree *Tc, const double *epsv,
     // pays: int8 on short Hamming codes; FP16 on vector data of 16..128
     // coordinates when its rounding margin is small against eps^2
     int prec = opt.precision;
+    GramPre gpre;  // the rule's centres and largest |x - mu|, reused below
     if (prec == FNN_PREC_AUTO) {
         prec = FNN_PREC_FP32;
         if (M == M_HAM && T->dp <= 4)
             prec = FNN_PREC_I8;
         if ((M == M_L2 || M == M_ANG) && T->dim >= 16 && T->dp <= 128 &&
-            gram_margin_ratio(T, t2min, FNN_PREC_FP16, S) <= 0.5)
+            gram_margin_ratio(T, t2min, FNN_PREC_FP16, S, &gpre) <= 0.5)
             prec = FNN_PREC_FP16;
     }
     st.precision_used = prec;
@@ -1845,7 +1846,7 @@ static void eps_graph_impl(const fnn_tree *Tc, const double *epsv,
     if constexpr (M == M_L2 || M == M_ANG || M == M_HAM) {
         if (use_gram) {
             gram_prepare(T, prec, opt.proj, eps, E, t2min, inter, ninter, S, G,
-                         &plain, &nplain);
+                         &plain, &nplain, &gpre);
             G.fp64_dist = fp64_dist;
             G.validate = opt.validate;
             G.q_pb = T->q_pt_begin;
