@@ -218,7 +218,36 @@ __global__ void k_root_keys(Pts P, int32_t *__restrict__ perm,
     float k = 0.f;
     if (i < P.n) {
         perm[i] = i;
-        k = key32<M>(P, i, 0);
+        if constexpr (M == M_L2 || M == M_ANG) {
+            // key32's four chains in its order, the row read eight float4
+            // at a time (one thread per row: the loads, not the arithmetic,
+            // set the pace)
+            const float *X = M == M_L2 ? P.x : P.xn;
+            const float *a = X + (size_t)i * P.dp, *b = X;
+            float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+            for (int c = 0; c < P.dp; c += 32) {
+                float4 u[8], w[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    if (c + 4 * q < P.dp) {
+                        u[q] = *reinterpret_cast<const float4 *>(a + c + 4 * q);
+                        w[q] = *reinterpret_cast<const float4 *>(b + c + 4 * q);
+                    }
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    if (c + 4 * q < P.dp) {
+                        const float d0 = u[q].x - w[q].x, d1 = u[q].y - w[q].y,
+                                    d2 = u[q].z - w[q].z, d3 = u[q].w - w[q].w;
+                        s0 = fmaf(d0, d0, s0);
+                        s1 = fmaf(d1, d1, s1);
+                        s2 = fmaf(d2, d2, s2);
+                        s3 = fmaf(d3, d3, s3);
+                    }
+            }
+            k = (s0 + s1) + (s2 + s3);
+        } else {
+            k = key32<M>(P, i, 0);
+        }
         D[i] = k;
     }
     k = wave_max(k);
@@ -1153,6 +1182,8 @@ __global__ void k_gather_rows(const T *__restrict__ in, const int32_t *__restric
 
 // ---- query tree: packs of consecutive sibling leaf blocks ----------------
 
+constexpr int QT_PF = 8;  // children whose fields are loaded at once
+
 __global__ void k_qt_count(int nn, const int32_t *__restrict__ ccnt,
                            const int32_t *__restrict__ cbeg,
                            const int32_t *__restrict__ pb,
@@ -1168,20 +1199,34 @@ __global__ void k_qt_count(int nn, const int32_t *__restrict__ ccnt,
     if (v == solo)
         P = 0;
     int packs = 0, kids = 0, run = -1;
-    for (int a = 0; a < cc; ++a) {
-        const int u = cbeg[v] + a;
-        if (ccnt[u] > 0) {
-            ++kids;
-            run = -1;
-            continue;
+    const int c0 = cc > 0 ? cbeg[v] : 0;
+    // children read QT_PF at a time (the walk itself is sequential)
+    for (int a0 = 0; a0 < cc; a0 += QT_PF) {
+        int ck[QT_PF], szk[QT_PF];
+#pragma unroll
+        for (int j = 0; j < QT_PF; ++j) {
+            const int u = c0 + a0 + j;
+            const bool in = a0 + j < cc;
+            ck[j] = in ? ccnt[u] : 0;
+            szk[j] = in ? pe[u] - pb[u] : 0;
         }
-        const int sz = pe[u] - pb[u];
-        if (run >= 0 && run + sz <= P) {
-            run += sz;
-        } else {
-            ++packs;
-            ++kids;
-            run = sz;
+#pragma unroll
+        for (int j = 0; j < QT_PF; ++j) {
+            if (a0 + j >= cc)
+                break;
+            if (ck[j] > 0) {
+                ++kids;
+                run = -1;
+                continue;
+            }
+            const int sz = szk[j];
+            if (run >= 0 && run + sz <= P) {
+                run += sz;
+            } else {
+                ++packs;
+                ++kids;
+                run = sz;
+            }
         }
     }
     npk[v] = packs;
@@ -1221,27 +1266,43 @@ __global__ void k_qt_fill(int nn, const int32_t *__restrict__ ccnt,
     int pk = nn + pkoff[v] - 1;  // id of the current pack
     int kd = kidoff[v];
     int run = -1;
-    for (int a = 0; a < cc; ++a) {
-        const int u = cbeg[v] + a;
-        if (ccnt[u] > 0) {
-            q_kids[kd++] = u;
-            run = -1;
-            continue;
+    const int c0 = cbeg[v];
+    for (int a0 = 0; a0 < cc; a0 += QT_PF) {
+        int ck[QT_PF], pbk[QT_PF], pek[QT_PF], cpk[QT_PF];
+#pragma unroll
+        for (int j = 0; j < QT_PF; ++j) {
+            const int u = c0 + a0 + j;
+            const bool in = a0 + j < cc;
+            ck[j] = in ? ccnt[u] : 0;
+            pbk[j] = in ? pb[u] : 0;
+            pek[j] = in ? pe[u] : 0;
+            cpk[j] = in ? cpos[u] : 0;
         }
-        const int sz = pe[u] - pb[u];
-        if (run >= 0 && run + sz <= P) {
-            run += sz;
-            q_pe[pk] = pe[u];
-        } else {
-            ++pk;
-            q_kids[kd++] = pk;
-            run = sz;
-            q_cpos[pk] = cpos[u];
-            q_pb[pk] = pb[u];
-            q_pe[pk] = pe[u];
-            q_kbeg[pk] = 0;
-            q_kcnt[pk] = 0;
-            q_rad[pk] = 0.f;
+#pragma unroll
+        for (int j = 0; j < QT_PF; ++j) {
+            if (a0 + j >= cc)
+                break;
+            const int u = c0 + a0 + j;
+            if (ck[j] > 0) {
+                q_kids[kd++] = u;
+                run = -1;
+                continue;
+            }
+            const int sz = pek[j] - pbk[j];
+            if (run >= 0 && run + sz <= P) {
+                run += sz;
+                q_pe[pk] = pek[j];
+            } else {
+                ++pk;
+                q_kids[kd++] = pk;
+                run = sz;
+                q_cpos[pk] = cpk[j];
+                q_pb[pk] = pbk[j];
+                q_pe[pk] = pek[j];
+                q_kbeg[pk] = 0;
+                q_kcnt[pk] = 0;
+                q_rad[pk] = 0.f;
+            }
         }
     }
 }
