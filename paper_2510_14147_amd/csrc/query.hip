@@ -568,7 +568,8 @@ k_tile(Pts P, const int2 *__restrict__ inter, long long ninter,
        const int32_t *__restrict__ pcl, int fp64_dist, TileOut out)
 {
     __shared__ TileSmem<M> sm;
-    __shared__ unsigned long long mask[TS];
+    __shared__ unsigned long long mask[TS];   // edge bits of each row (bit = column)
+    __shared__ unsigned long long cmask[TS];  // and of each column (bit = row)
     constexpr bool FILL = MODE == TILE_FILL, LIST = MODE == TILE_LIST;
     constexpr bool DIST = FILL || LIST;  // keep the tile's edge distances
     __shared__ float dt[DIST ? TS * (TS + 1) : 1];
@@ -590,6 +591,8 @@ k_tile(Pts P, const int2 *__restrict__ inter, long long ninter,
             const int pa = a0 + ia, pb = b0 + jb;  // first tree positions
             if (t < TS)
                 mask[t] = 0ull;
+            else if (t < 2 * TS)
+                cmask[t - TS] = 0ull;
             float acc[4][4];
 #pragma unroll
             for (int i = 0; i < 4; ++i)
@@ -689,6 +692,7 @@ k_tile(Pts P, const int2 *__restrict__ inter, long long ninter,
 
             // ---- exactness guard and edge bits ----------------------------
             unsigned long long rc = 0;
+            unsigned cnib[4] = {0u, 0u, 0u, 0u};  // column j's rows (bit i)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int ri = ty * 4 + i;
@@ -720,6 +724,7 @@ k_tile(Pts P, const int2 *__restrict__ inter, long long ninter,
                         }
                         if (e) {
                             nib |= 1u << j;
+                            cnib[j] |= 1u << i;
                             if constexpr (DIST)
                                 dt[ri * (TS + 1) + cj] =
                                     edge_dist<M>(P, pa + ri, pb + cj, k, fp64_dist);
@@ -729,6 +734,10 @@ k_tile(Pts P, const int2 *__restrict__ inter, long long ninter,
                 if (nib)
                     atomicOr(&mask[ri], (unsigned long long)nib << (tx * 4));
             }
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (cnib[j])
+                    atomicOr(&cmask[tx * 4 + j], (unsigned long long)cnib[j] << (ty * 4));
             rechecks += rc;
             if (t == 0)
                 pairs += sdiag ? (unsigned long long)ra * (ra - 1) / 2
@@ -788,10 +797,8 @@ k_tile(Pts P, const int2 *__restrict__ inter, long long ninter,
                 }
             } else if (t < 2 * TS) {
                 const int cc = t - TS;
-                int c = 0;
-                if (cc < rb)
-                    for (int r = 0; r < ra; ++r)
-                        c += (int)((mask[r] >> cc) & 1ull);
+                const unsigned long long cbits = cc < rb ? cmask[cc] : 0ull;
+                int c = __popcll(cbits);
                 const int ocol = c ? perm[pb + cc] : 0;
                 if constexpr (LIST) {
                     // the same edges seen from this column (threads 64..127
@@ -808,14 +815,16 @@ k_tile(Pts P, const int2 *__restrict__ inter, long long ninter,
                     if (cc == 0 && tot)
                         base = atomicAdd(out.ecnt, (unsigned long long)tot);
                     base = __shfl(base, 0, WAVE) + (unsigned long long)(incl - c);
-                    for (int r = 0; c && r < ra; ++r)
-                        if ((mask[r] >> cc) & 1ull) {
-                            if (base < out.ecap) {
-                                out.elist[base] = make_int2(ocol, perm[pa + r]);
-                                out.edist[base] = dt[r * (TS + 1) + cc];
-                            }
-                            ++base;
+                    unsigned long long rbits = cbits;
+                    while (rbits) {
+                        const int r = __ffsll((long long)rbits) - 1;
+                        rbits &= rbits - 1;
+                        if (base < out.ecap) {
+                            out.elist[base] = make_int2(ocol, perm[pa + r]);
+                            out.edist[base] = dt[r * (TS + 1) + cc];
                         }
+                        ++base;
+                    }
                 }
                 if (cc < rb) {
                     if (c && FILL && out.row_filter && !out.row_filter[ocol])
@@ -827,12 +836,14 @@ k_tile(Pts P, const int2 *__restrict__ inter, long long ninter,
                             unsigned long long o, lim;
                             const unsigned long long spb = place(out, ocol, c, o, lim);
                             unsigned long long idx = o;
-                            for (int r = 0; c && r < ra; ++r)
-                                if ((mask[r] >> cc) & 1ull) {
-                                    put(out, ocol, perm[pa + r], dt[r * (TS + 1) + cc],
-                                        idx, o, lim, spb);
-                                    ++idx;
-                                }
+                            unsigned long long rbits = c ? cbits : 0ull;
+                            while (rbits) {
+                                const int r = __ffsll((long long)rbits) - 1;
+                                rbits &= rbits - 1;
+                                put(out, ocol, perm[pa + r], dt[r * (TS + 1) + cc], idx, o,
+                                    lim, spb);
+                                ++idx;
+                            }
                         }
                     }
                 }
