@@ -1247,6 +1247,38 @@ __device__ __forceinline__ void half_finish(const GramArgs &G, const f32x16 (&ac
     asm volatile("" : "+v"(na), "+v"(nb), "+v"(pa), "+v"(pb));
     unsigned fill = (unsigned)__builtin_amdgcn_readfirstlane((int)*fillS);
     const uint64_t ltmask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    if (!G.validate && !self) {
+        // Two different packs: rows past na start at -FLT_MAX and columns
+        // past nb carry the term FLT_MAX, so every pair that reaches its
+        // column term is valid.  One ballot per row position; the lanes of
+        // a position write their pairs row first (the lanes of one half
+        // share the row), next to each other.
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) {
+            if (hm[cb] == 0)
+                continue;
+            const int colp = (pb + cb * 32 + l32) | (int)0x80000000u;
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const bool ps = acc[cb][q] >= ay[cb];
+                const uint64_t m = __ballot(ps);
+                if (m == 0)
+                    continue;
+                const unsigned cnt = (unsigned)__popcll(m);
+                if (fill + cnt > (unsigned)SURV_BUF) {
+                    surv_flush(G, sb, fill);
+                    fill = 0;
+                }
+                if (ps)
+                    sb[fill + (unsigned)__popcll(m & ltmask)] =
+                        make_int2(pa + 32 * rb + 8 * (q >> 2) + (q & 3) + 4 * hi, colp);
+                fill += cnt;
+            }
+        }
+        if (lane == 0)
+            *fillS = fill;
+        return;
+    }
 #pragma unroll
     for (int cb = 0; cb < 2; ++cb) {
         if (!G.validate && hm[cb] == 0)
