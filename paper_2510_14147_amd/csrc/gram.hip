@@ -1230,11 +1230,14 @@ __device__ __forceinline__ void surv_flush(const GramArgs &G, const int2 *sb, un
 // Position q of acc[cb] in a lane holds row 32 rb + 8 (q / 4) + q % 4 + 4 hi
 // of column 32 cb + l32; acc[cb] starts at -ax of its row, ay[cb] is the
 // lane's column term (FLT_MAX past nb) and hm[cb] the lanes whose largest
-// sum of that block reaches it.  The pairs that pass (every valid pair with
-// its pass flag when validating) are written column first, each lane's
-// next to each other, into the wave's LDS buffer sb (*fill entries held),
-// which goes to the list when it would overflow; more pairs than the
-// buffer holds (only when validating) go to the list directly.
+// sum of that block reaches it.  The pairs that pass go to the wave's LDS
+// buffer sb (*fill entries held), which goes to the list when it would
+// overflow.  Blocks of two different packs (not validating) take one ballot
+// per row position and write each position's pairs row first; self blocks
+// and validation (every valid pair with its pass flag) build per-lane pass
+// and validity masks and write each lane's pairs column first, next to
+// each other; more pairs than the buffer holds (only when validating) go to
+// the list directly.
 __device__ __forceinline__ void half_finish(const GramArgs &G, const f32x16 (&acc)[2],
                                             const float (&ay)[2], const uint64_t (&hm)[2],
                                             int rb, int na, int nb, bool self, int pa,
