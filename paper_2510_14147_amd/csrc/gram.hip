@@ -1613,6 +1613,44 @@ __device__ __forceinline__ float key32_staged(const Pts &P, int pi, int pj, floa
     return s;
 }
 
+// Counter value of `key` per lane (key < 0: none): one atomic add per run of
+// equal keys among the wave's active lanes (lanes with key < 0 in between do
+// not end a run), and the lanes of a run take consecutive values from its
+// start.  The filters write a row's survivors within a column block next to
+// each other, so runs are the common case.  Called by every lane of the wave
+// that is still in its loop; returns the lane's value where key >= 0 (a
+// CSR slot for row cursors, a rank in the row for degree counters).
+template <class T>
+__device__ __forceinline__ T claim_run(T *ctr, int key)
+{
+    const int lane = threadIdx.x & (WAVE - 1);
+    const bool act = key >= 0;
+    const uint64_t A = __ballot(act);
+    const uint64_t below = A & ((1ull << lane) - 1);  // lane < 64: no overflow
+    const int p = below ? 63 - __builtin_clzll(below) : lane;
+    const int pk = __shfl(key, p, WAVE);  // key of the previous active lane
+    const bool cont = act && below != 0 && pk == key;
+    const uint64_t Hd = A & ~__ballot(cont);  // run heads
+    const uint64_t upto = lane == WAVE - 1 ? ~0ull : ((2ull << lane) - 1);
+    const uint64_t hb = Hd & upto;
+    const int h = hb ? 63 - __builtin_clzll(hb) : 0;
+    const uint64_t from_h = ~((1ull << h) - 1);
+    T base = 0;
+    if (act && h == lane) {
+        const uint64_t nxt = Hd & ~upto;  // next head above
+        const uint64_t run = nxt ? (nxt & (0 - nxt)) - 1 : ~0ull;
+        base = atomicAdd(&ctr[key], (T)__popcll(A & from_h & run));
+    }
+    const T off = (T)(__popcll(A & from_h & upto) - 1);
+    if constexpr (sizeof(T) == 8) {
+        const unsigned blo = __shfl((unsigned)base, h, WAVE);
+        const unsigned bhi = __shfl((unsigned)((unsigned long long)base >> 32), h, WAVE);
+        return (T)(((unsigned long long)bhi << 32) | blo) + off;
+    } else {
+        return __shfl(base, h, WAVE) + off;
+    }
+}
+
 // Exact decision of every survivor: direct-difference FP32 key, FP64 inside
 // the rounding band; survivor i's edge (input ids, distance) goes to slot i
 // of an unordered list, (-1, -1) when it is none, and to the row degrees.
@@ -1691,7 +1729,6 @@ k_survive(Pts P, GramArgs G, long long ns, int2 *__restrict__ edges,
                 oi = G.perm[pi];
                 oj = G.perm[pj];
                 if (G.erank) {
-                    rk.x = atomicAdd(&out.deg[oi], 1);
                     rk.y = atomicAdd(&out.deg[oj], 1);
                 } else {
                     atomicAdd(&out.deg[oi], 1);
@@ -1699,6 +1736,10 @@ k_survive(Pts P, GramArgs G, long long ns, int2 *__restrict__ edges,
                 }
             }
         }
+        // the first endpoint's rank: the list holds a row's survivors of a
+        // block in runs, so one returning atomic serves a run
+        if (G.erank)
+            rk.x = claim_run(out.deg, edge ? oi : -1);
         // the survivor's own slot: an edge, or a hole (-1, -1) that the
         // scatter skips (no shared counter to contend on)
         if (i < ns) {
@@ -1724,38 +1765,6 @@ k_survive(Pts P, GramArgs G, long long ns, int2 *__restrict__ edges,
     }
 }
 
-// One CSR slot of row `key` per lane (key < 0: none), claimed with one
-// cursor atomic per run of equal keys among the wave's active lanes (lanes
-// with key < 0 in between do not end a run): the filters write a row's
-// survivors within a column block next to each other, so runs are the
-// common case.  Called by every lane of the wave that is still in its loop;
-// returns the lane's slot where key >= 0.
-__device__ __forceinline__ unsigned long long claim_run_slot(unsigned long long *cursor,
-                                                             int key)
-{
-    const int lane = threadIdx.x & (WAVE - 1);
-    const bool act = key >= 0;
-    const uint64_t A = __ballot(act);
-    const uint64_t below = A & ((1ull << lane) - 1);  // lane < 64: no overflow
-    const int p = below ? 63 - __builtin_clzll(below) : lane;
-    const int pk = __shfl(key, p, WAVE);  // key of the previous active lane
-    const bool cont = act && below != 0 && pk == key;
-    const uint64_t Hd = A & ~__ballot(cont);  // run heads
-    const uint64_t upto = lane == WAVE - 1 ? ~0ull : ((2ull << lane) - 1);
-    const uint64_t hb = Hd & upto;
-    const int h = hb ? 63 - __builtin_clzll(hb) : 0;
-    const uint64_t from_h = ~((1ull << h) - 1);
-    unsigned long long base = 0;
-    if (act && h == lane) {
-        const uint64_t nxt = Hd & ~upto;  // next head above
-        const uint64_t run = nxt ? (nxt & (0 - nxt)) - 1 : ~0ull;
-        base = atomicAdd(&cursor[key], (unsigned long long)__popcll(A & from_h & run));
-    }
-    const unsigned blo = __shfl((unsigned)base, h, WAVE);
-    const unsigned bhi = __shfl((unsigned)(base >> 32), h, WAVE);
-    return (((unsigned long long)bhi << 32) | blo) + (unsigned)(__popcll(A & from_h & upto) - 1);
-}
-
 // Writes an edge list (input ids, distance; entries (-1, -1) are skipped)
 // into the CSR: each entry into the slots of both endpoints when the list
 // holds every edge once, else (every edge listed in both directions) into
@@ -1767,7 +1776,7 @@ __global__ void k_edges_scatter(const int2 *__restrict__ edges,
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < ne;
          i += (long long)gridDim.x * blockDim.x) {
         const int2 e = edges[i];
-        const unsigned long long s1 = claim_run_slot(out.cursor, e.x);
+        const unsigned long long s1 = claim_run(out.cursor, e.x);
         if (e.x < 0)
             continue;  // a survivor that is no edge
         const float d = edist[i];
@@ -1877,7 +1886,7 @@ __global__ void k_edges_scatter_ham(const int2 *__restrict__ surv, long long ne,
          i += (long long)gridDim.x * blockDim.x) {
         const int2 e = surv[i];
         const int oi = e.x < 0 ? -1 : perm[e.x];
-        const unsigned long long s1 = claim_run_slot(out.cursor, oi);
+        const unsigned long long s1 = claim_run(out.cursor, oi);
         if (e.x < 0)
             continue;  // an unused slot
         const int pi = e.x, pj = e.y & 0x7FFFFFFF;

@@ -1979,12 +1979,14 @@ static void eps_graph_impl(const fnn_tree *Tc, const double *epsv,
                         gedist = S.get<float>(got + 1);
                         // with no plain tiles in the query every CSR entry
                         // comes from a survivor: keep the ranks its degree
-                        // counters return and place it without cursors.
-                        // Measured at C2: 2.2 ms faster at ~53 survivors per
-                        // point, 2.6 ms slower at ~350 (the returning atomics
-                        // then contend on rows of ~500 entries), so only up
-                        // to 128 per point
-                        if (nplain == 0 && got <= 128ll * n)
+                        // counters return and place it without cursors
+                        // (measured at C2: 2.2 ms faster at ~53 survivors per
+                        // point, 15 ms at ~350), while the ranks take under a
+                        // quarter of the free device memory
+                        size_t free_now = 0, tot_now = 0;
+                        FNN_HIP(hipMemGetInfo(&free_now, &tot_now));
+                        if (nplain == 0 &&
+                            (double)(got + 1) * sizeof(int2) < 0.25 * (double)free_now)
                             G.erank = S.get<int2>(got + 1);
                         // slot per survivor: holes where it is no edge
                         survivors_launch(M, P, G, got, gedges, gedist, o, s);
