@@ -584,6 +584,20 @@ __global__ void k_max_pack(const int32_t *__restrict__ pb, const int32_t *__rest
             *big = 1;
 }
 
+// Packs of GP consecutive tree positions (the last one shorter) for the
+// closed-form work list over a single cloud: the tree's packs hold up to GP
+// points (60 on average at C2), so screening them leaves a tenth of the
+// matrix slots empty, while any partition of one cloud covers every pair.
+__global__ void k_uniform_packs(int n, int np, int32_t *__restrict__ pb,
+                                int32_t *__restrict__ pe)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < np;
+         i += gridDim.x * blockDim.x) {
+        pb[i] = i * GP;
+        pe[i] = min(i * GP + GP, n);
+    }
+}
+
 // Unit table of the closed-form work list from per-run tables.  Run k
 // covers B packs [k R, h_k), h_k = min((k + 1) R, npk); its units are
 // U[k] .. U[k+1] - 1, unit U[k] + g pairing group g with packs
@@ -2422,6 +2436,8 @@ void gram_prepare(const fnn_tree *T, int prec, int proj, double eps, const Thr &
     }
     G.e2f = gram_eps2(T->metric, eps, E, G.t2mul, G.e2add);
     G.E = E;
+    G.q_pb = T->q_pt_begin;
+    G.q_pe = T->q_pt_end;
 
     const int nn = (int)T->nnodes;
     const int npk = (int)T->npacks;
@@ -2443,16 +2459,34 @@ void gram_prepare(const fnn_tree *T, int prec, int proj, double eps, const Thr &
             FNN_LAUNCH(k_max_pack, dim3(grid_for(npk, 256)), dim3(256), 0, s,
                        T->q_pt_begin + nn, T->q_pt_end + nn, npk, GP, big);
             if (read_scalar(big, s) == 0) {
+                // one cloud: full packs of consecutive tree positions in
+                // place of the tree's (indexed from 0, not past the nodes)
+                const bool one = T->ncloud <= 1 && T->cross_a < 0;
+                int base = nn, np = npk;
+                if (one) {
+                    np = (int)((T->n + GP - 1) / GP);
+                    int32_t *vpb = S.get<int32_t>(np), *vpe = S.get<int32_t>(np);
+                    FNN_LAUNCH(k_uniform_packs, dim3(grid_for(np, 256)), dim3(256), 0, s,
+                               (int)T->n, np, vpb, vpe);
+                    base = 0;
+                    G.q_pb = vpb;
+                    G.q_pe = vpe;
+                    const int ng1 = (np + GW - 1) / GW;
+                    mu = 0;
+                    for (int g = 0; g < ng1; ++g)
+                        mu += np - GW * g;
+                }
+                const int ngp = (np + GW - 1) / GW;
                 // units ordered by B run (runs aligned to RUN packs), then by
                 // group: the units of one run read the same B tiles.  The
                 // host sums the per-run counts; the unit table itself is
                 // filled on the device (k_dense_plan).
-                const int nrun = (npk + RUN - 1) / RUN;
+                const int nrun = (np + RUN - 1) / RUN;
                 std::vector<long long> U(nrun + 1, 0), E(nrun + 1, 0);
                 for (int k = 0; k < nrun; ++k) {
                     const long long kR = (long long)k * RUN;
-                    const long long h = std::min<long long>(kR + RUN, npk);
-                    const long long c = std::min<long long>(ngr, (h + GW - 1) / GW);
+                    const long long h = std::min<long long>(kR + RUN, np);
+                    const long long c = std::min<long long>(ngp, (h + GW - 1) / GW);
                     const long long a = std::min<long long>(c, kR / GW + 1);
                     U[k + 1] = U[k] + c;
                     E[k + 1] = E[k] + a * (h - kR) + (c - a) * h -
@@ -2469,21 +2503,21 @@ void gram_prepare(const fnn_tree *T, int prec, int proj, double eps, const Thr &
                 FNN_HIP(hipMemcpyAsync(UE + nrun + 1, E.data(), sizeof(long long) * (nrun + 1),
                                        hipMemcpyHostToDevice, s));
                 FNN_LAUNCH(k_dense_plan, dim3(grid_for(nu, 256)), dim3(256), 0, s, UE,
-                           UE + nrun + 1, nrun, RUN, npk, nu, ubeg, ug_d, ulo_d);
+                           UE + nrun + 1, nrun, RUN, np, nu, ubeg, ug_d, ulo_d);
                 FNN_LAUNCH(k_dense_units, dim3(grid_cap(nu, 4, 16384)), dim3(256), 0, s,
                            ubeg, ug_d, ulo_d, nu, lg, lb);
                 FNN_HIP(hipStreamSynchronize(s));  // host vectors go out of scope
                 *rest = nullptr;
                 *nrest = 0;
-                G.nn = nn;
-                G.npacks = npk;
+                G.nn = base;
+                G.npacks = np;
                 G.lg = lg;
                 G.lb = lb;
                 G.ubeg = ubeg;
                 G.nunits = nu;
                 G.nlist = (int)e;
                 // every pair of one cloud: the narrow kernel screens each once
-                if (T->ncloud <= 1 && T->cross_a < 0)
+                if (one)
                     G.dense_pairs = T->n * (T->n - 1) / 2;
                 return;
             }

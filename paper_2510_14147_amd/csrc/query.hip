@@ -1860,8 +1860,6 @@ static void eps_graph_impl(const fnn_tree *Tc, const double *epsv,
                          &plain, &nplain, &gpre);
             G.fp64_dist = fp64_dist;
             G.validate = opt.validate;
-            G.q_pb = T->q_pt_begin;
-            G.q_pe = T->q_pt_end;
             G.perm = T->perm;
             gram_pad_packs(M, prec, G, S);
             G.ct = ncl > 1 ? ct_d : nullptr;
