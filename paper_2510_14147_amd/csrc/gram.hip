@@ -1371,7 +1371,7 @@ __device__ __forceinline__ void half_finish(const GramArgs &G, const f32x16 (&ac
 // waves of its work-group; the four waves of a group read the same B rows
 // at about the same time, so most of those reads hit L1.
 template <int M, int PREC, int NKS>
-__global__ void __launch_bounds__(GT, NKS == 1 ? 5 : 4)  // waves / SIMD that fit unspilled
+__global__ void __launch_bounds__(GT, 4)  // waves / SIMD that fit unspilled
 k_gram_direct(Pts P, GramArgs G, TileOut out)
 {
     static_assert(NKS >= 1 && NKS <= 2, "narrow rows only");
@@ -1415,8 +1415,8 @@ k_gram_direct(Pts P, GramArgs G, TileOut out)
                     v = *(const int4 *)(Q + (size_t)(pa + r) * rowb + ks * 32 + hi * 16);
                 Af[rb][ks] = v;
             }
-        // accumulator start values -ax of the wave's rows, in LDS: each row
-        // half reads its 16 per lane as the addend of both of its products
+        // accumulator start values -ax of the wave's rows, through LDS: each
+        // row half's 16 per lane are the addend of both of its products
         const int ca = (G.pcl && has_a) ? G.pcl[pa] : -1;
         const float e2 = ca >= 0 ? G.ct[ca].e2f : G.e2f;
         for (int r = lane; r < GP; r += WAVE)
@@ -1430,6 +1430,28 @@ k_gram_direct(Pts P, GramArgs G, TileOut out)
             eC[i] = G.pcl ? G.pcl[pbb] : -1;
         }
         __syncthreads();
+        // lane (l32, hi) of row half rb takes rows 32 rb + 8 (q / 4) + 4 hi +
+        // q % 4, the layout of the accumulators it starts.  With one k-step
+        // they stay in registers for the whole unit; with two, the second
+        // step's fragments take those registers and each half re-reads them
+        auto load_sv = [&](int rb) {
+            f32x16 v;
+#pragma unroll
+            for (int q4 = 0; q4 < 4; ++q4) {
+                const float4 a4 = *reinterpret_cast<const float4 *>(
+                    &axS[w][rb * 32 + 8 * q4 + 4 * hi]);
+                v[4 * q4 + 0] = a4.x;
+                v[4 * q4 + 1] = a4.y;
+                v[4 * q4 + 2] = a4.z;
+                v[4 * q4 + 3] = a4.w;
+            }
+            return v;
+        };
+        f32x16 svr[2];
+        if constexpr (NKS == 1) {
+            svr[0] = load_sv(0);
+            svr[1] = load_sv(1);
+        }
         // B fragments and column norms of one entry (columns 32 cb + l32), in
         // two register sets: entry e uses set e % 2, whose load was issued
         // two entries earlier (no copy of a register with a load in flight)
@@ -1475,16 +1497,12 @@ k_gram_direct(Pts P, GramArgs G, TileOut out)
                 // pairs never pass
 #pragma unroll
                 for (int rb = 0; rb < 2; ++rb) {
-                    f32x16 sv, acc[2];
-                    asm volatile("" ::: "memory");  // re-read (no registers held)
-#pragma unroll
-                    for (int q4 = 0; q4 < 4; ++q4) {
-                        const float4 a4 = *reinterpret_cast<const float4 *>(
-                            &axS[w][rb * 32 + 8 * q4 + 4 * hi]);
-                        sv[4 * q4 + 0] = a4.x;
-                        sv[4 * q4 + 1] = a4.y;
-                        sv[4 * q4 + 2] = a4.z;
-                        sv[4 * q4 + 3] = a4.w;
+                    f32x16 acc[2], sv;
+                    if constexpr (NKS == 1) {
+                        sv = svr[rb];
+                    } else {
+                        asm volatile("" ::: "memory");  // re-read (no registers held)
+                        sv = load_sv(rb);
                     }
 #pragma unroll
                     for (int cb = 0; cb < 2; ++cb)
