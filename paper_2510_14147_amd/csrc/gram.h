@@ -86,6 +86,10 @@ struct GramArgs {
     // staged kernel runs
     const void *qp;
     const float *ayp;
+    // uniform packs over one cloud: pack k holds tree positions GP k ..
+    // min(GP k + GP, upk) - 1 and a work unit's B packs are consecutive;
+    // 0: packs from q_pb / q_pe and the list
+    int upk;
 };
 
 // Per-pack copies of the quantised rows and column terms for the narrow

@@ -1219,6 +1219,9 @@ __device__ __forceinline__ unsigned long long uniform_u64(unsigned long long v)
 }
 
 constexpr int SURV_BUF = 256;  // survivors buffered per wave in LDS
+// Fourth word of a raw buffer resource on gfx9-family GPUs (32-bit data,
+// no swizzle; loads past the record count return zero)
+constexpr int BUF_RSRC_W3 = 0x00020000;
 
 // Appends a wave's n buffered survivors to the list: one atomic for their
 // slots, then coalesced stores.  Called with every lane of the wave active.
@@ -1403,6 +1406,8 @@ k_gram_direct(Pts P, GramArgs G, TileOut out)
         const bool has_a = (GW * g + w) < G.npacks && G.q_pe[a] - G.q_pb[a] <= GP;
         const int pa = has_a ? G.q_pb[a] : 0;
         const int na = has_a ? G.q_pe[a] - pa : 0;
+        // uniform packs: entry e of the unit is B pack ub0 + e - e0
+        const int ub0 = G.upk ? __builtin_amdgcn_readfirstlane(G.lb[e0]) : 0;
         // A fragments: rows 32 rb + l32, bytes 32 ks + 16 hi
         int4 Af[2][NKS];
 #pragma unroll
@@ -1421,7 +1426,8 @@ k_gram_direct(Pts P, GramArgs G, TileOut out)
         const float e2 = ca >= 0 ? G.ct[ca].e2f : G.e2f;
         for (int r = lane; r < GP; r += WAVE)
             axS[w][r] = r < na ? -0.5f * (G.hx[pa + r] - e2) : -FLT_MAX;
-        for (int i = t; i < e1 - e0; i += GT) {
+        // (uniform packs: the entries' fields follow from their index)
+        for (int i = G.upk ? e1 - e0 : t; i < e1 - e0; i += GT) {
             const int bb = G.nn + G.lb[e0 + i];
             const int pbb = G.q_pb[bb];
             eB[i] = bb;
@@ -1462,30 +1468,45 @@ k_gram_direct(Pts P, GramArgs G, TileOut out)
         // so every lane loads at a fixed offset and an entry costs no vector
         // arithmetic; the loads of one entry are a fixed count, so the next
         // entry's stay in flight while this one computes.
-        const unsigned char *QP = (const unsigned char *)G.qp;
-        const char *AYP = (const char *)G.ayp;
+        const __amdgpu_buffer_rsrc_t rq = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<void *>(G.qp), (short)0, G.npacks * GP * rowb, BUF_RSRC_W3);
+        const __amdgpu_buffer_rsrc_t ra = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<float *>(G.ayp), (short)0, G.npacks * GP * 4, BUF_RSRC_W3);
         auto load_b = [&](int e, int4 (&B)[2][NKS], float (&ay)[2]) {
-            // 32-bit byte offsets from the fixed bases (gram_pad_packs checks
-            // that the copies fit)
-            const unsigned pk = (unsigned)(__builtin_amdgcn_readfirstlane(eB[e - e0]) - G.nn);
+            // buffer loads: the pack's offset in a scalar register, the
+            // lane's offset fixed (32 bits: gram_pad_packs checks that the
+            // copies fit), so an entry costs no vector arithmetic
+            const unsigned pk =
+                G.upk ? (unsigned)(ub0 + (e - e0))
+                      : (unsigned)(__builtin_amdgcn_readfirstlane(eB[e - e0]) - G.nn);
+            const int sq = (int)(pk * (unsigned)(GP * rowb)), sa = (int)(pk * (unsigned)(GP * 4));
 #pragma unroll
             for (int cb = 0; cb < 2; ++cb) {
-                const unsigned c = (unsigned)(cb * 32 + l32);
+                const int c = cb * 32 + l32;
 #pragma unroll
                 for (int ks = 0; ks < NKS; ++ks)
-                    B[cb][ks] = *(const int4 *)(QP + (pk * (unsigned)(GP * rowb) +
-                                                      c * (unsigned)rowb +
-                                                      (unsigned)(ks * 32 + hi * 16)));
+                    B[cb][ks] = __builtin_bit_cast(
+                        int4, __builtin_amdgcn_raw_buffer_load_b128(rq, c * rowb + ks * 32 + hi * 16,
+                                                                    sq, 0));
                 // used (and waited for) only when processed
-                ay[cb] = *(const float *)(AYP + (pk * (unsigned)(GP * 4) + c * 4u));
+                ay[cb] = __builtin_bit_cast(float,
+                                            __builtin_amdgcn_raw_buffer_load_b32(ra, c * 4, sa, 0));
             }
         };
         auto step = [&](int e, int4 (&B)[2][NKS], float (&ay)[2]) {
             // the entry's fields are the same in every lane
-            const int b = __builtin_amdgcn_readfirstlane(eB[e - e0]);
-            const int pb = __builtin_amdgcn_readfirstlane(eP[e - e0]);
-            const int nb = __builtin_amdgcn_readfirstlane(eN[e - e0]);
-            const int cb_cl = __builtin_amdgcn_readfirstlane(eC[e - e0]);
+            int b, pb, nb, cb_cl;
+            if (G.upk) {
+                b = ub0 + (e - e0);
+                pb = b * GP;
+                nb = min(GP, G.upk - pb);
+                cb_cl = -1;
+            } else {
+                b = __builtin_amdgcn_readfirstlane(eB[e - e0]);
+                pb = __builtin_amdgcn_readfirstlane(eP[e - e0]);
+                nb = __builtin_amdgcn_readfirstlane(eN[e - e0]);
+                cb_cl = __builtin_amdgcn_readfirstlane(eC[e - e0]);
+            }
             const bool skip = !has_a || b < a || (ca >= 0 && (cb_cl == ca) == (bool)G.cross);
             if (!skip) {
                 const bool self = (b == a);
@@ -1511,24 +1532,21 @@ k_gram_direct(Pts P, GramArgs G, TileOut out)
                             acc[cb] = mfma16<PREC>(Af[rb][ks], B[cb][ks],
                                                    ks == 0 ? sv : acc[cb]);
                         }
-                    // fast test: the lane's largest sum per column block
-                    // minus its column term (exact in sign: x - y >= 0 iff
-                    // x >= y), one vote for the whole half
-                    float mg[2];
+                    // fast test: the lanes whose largest sum of a column
+                    // block reaches their column term, one vote for the
+                    // whole half
+                    uint64_t hm[2];
 #pragma unroll
                     for (int cb = 0; cb < 2; ++cb) {
                         float mx = -FLT_MAX;
 #pragma unroll
                         for (int q = 0; q < 16; ++q)
                             mx = fmaxf(mx, acc[cb][q]);
-                        mg[cb] = __fsub_rn(mx, ayc[cb]);
+                        hm[cb] = __ballot(mx >= ayc[cb]);
                     }
-                    if (__any(fmaxf(mg[0], mg[1]) >= 0.f) || G.validate) {
-                        const uint64_t hm[2] = {__ballot(mg[0] >= 0.f),
-                                                __ballot(mg[1] >= 0.f)};
+                    if ((hm[0] | hm[1]) != 0 || G.validate)
                         half_finish(G, acc, ayc, hm, rb, na, nb, self, pa, pb, &fillS[w], survS[w],
                                     rmS);
-                    }
                 }
             }
             // issued on every path (past the end: the last entry again),
@@ -2444,6 +2462,7 @@ void gram_prepare(const fnn_tree *T, int prec, int proj, double eps, const Thr &
     hipStream_t s = S.stream();
     G.e2add = 0.0;
     G.dense_pairs = -1;
+    G.upk = 0;
     if (T->metric == M_HAM) {
         quantise_ham(T, prec, S, G);
         G.t2mul = 1.0;
@@ -2489,6 +2508,7 @@ void gram_prepare(const fnn_tree *T, int prec, int proj, double eps, const Thr &
                     base = 0;
                     G.q_pb = vpb;
                     G.q_pe = vpe;
+                    G.upk = (int)T->n;
                     const int ng1 = (np + GW - 1) / GW;
                     mu = 0;
                     for (int g = 0; g < ng1; ++g)
