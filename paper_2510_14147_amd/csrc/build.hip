@@ -380,35 +380,64 @@ static_assert(CH == 64 && UPD_K % 8 == 0, "lane layout of the distance loop");
 
 // One point per lane against a staged batch of nj (<= UPD_K) centres
 // (rows ldc apart in LDS; every lane reads the same centre row, a
-// broadcast): UPD_K FMA chains over the coordinates in order, the lane's
-// row read four coordinates at a time with UPD_PF reads in flight, then the
+// broadcast): UPD_K FMA chains over the coordinates in order, then the
 // running nearest over the batch in centre order (strict '<': the first
-// minimum stays).  Groups of eight centres past nj are skipped (a
-// wave-uniform test); rows between nj and the group's end are staged data
-// that is never compared.
-constexpr int UPD_PF = 4;
-__device__ __forceinline__ void upd_lane(const float *__restrict__ row,
+// minimum stays).  The wave's 64 point rows (point o of each lane) come
+// through the wave's LDS rows stg, US_CH coordinates at a time: each load
+// instruction reads whole row segments of several rows instead of 64
+// scattered lines, and the next segment is in flight while this one is
+// used.  Groups of eight centres past nj are skipped (a wave-uniform test);
+// rows between nj and the group's end are staged data that is never
+// compared.  Called with every lane of the wave active.
+constexpr int US_CH = 8;              // coordinates per staged segment
+constexpr int US_LDR = US_CH + 4;       // floats per staged row (bank spread)
+constexpr int US_F = US_CH / 4;         // float4 per row segment
+__device__ __forceinline__ void upd_lane(const float *__restrict__ X, int o, float *stg,
                                          const float *__restrict__ cen, int ldc, int dp,
                                          int jb, int nj, float &dcur, int &lcur)
 {
     constexpr int NJ = UPD_K;
+    const int lane = threadIdx.x & (CH - 1);
     float acc[NJ];
 #pragma unroll
     for (int j = 0; j < NJ; ++j)
         acc[j] = 0.f;
-    const int q4 = dp >> 2;
-    const float4 *r4 = reinterpret_cast<const float4 *>(row);
-    float4 pf[UPD_PF];
+    const int q4 = dp >> 2, p4 = 4 * (lane % US_F);
+    // this lane stages float4 p4 / 4 of the rows of lanes lane / F + (64 / F) i
+    const float *rs[US_F];
+    int so[US_F];
 #pragma unroll
-    for (int u = 0; u < UPD_PF; ++u)
-        pf[u] = r4[u < q4 ? u : q4 - 1];
-    for (int c4 = 0; c4 < q4; c4 += UPD_PF) {
+    for (int i = 0; i < US_F; ++i) {
+        const int r = lane / US_F + (CH / US_F) * i;
+        rs[i] = X + (size_t)__shfl(o, r, CH) * dp + p4;
+        so[i] = r * US_LDR + p4;
+    }
+    float4 va[US_F];
+    auto fetch = [&](int c0) {
+        const bool in = c0 + p4 < dp;
 #pragma unroll
-        for (int u = 0; u < UPD_PF; ++u) {
-            const int cc4 = c4 + u;
-            const float4 v = pf[u];
-            const int nx = cc4 + UPD_PF;
-            pf[u] = r4[nx < q4 ? nx : q4 - 1];
+        for (int i = 0; i < US_F; ++i)
+            va[i] = in ? *(const float4 *)(rs[i] + c0) : make_float4(0.f, 0.f, 0.f, 0.f);
+    };
+    fetch(0);
+    for (int c0 = 0; c0 < dp; c0 += US_CH) {
+#pragma unroll
+        for (int i = 0; i < US_F; ++i)
+            *(float4 *)(stg + so[i]) = va[i];
+        if (c0 + US_CH < dp)
+            fetch(c0 + US_CH);
+        // one wave's LDS accesses complete in order: only the compiler must
+        // keep the reads after the writes (and the next writes after them)
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        float4 vr[US_F];
+#pragma unroll
+        for (int u = 0; u < US_F; ++u)
+            vr[u] = *(const float4 *)(stg + lane * US_LDR + 4 * u);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+#pragma unroll
+        for (int u = 0; u < US_F; ++u) {
+            const int cc4 = c0 / 4 + u;
+            const float4 v = vr[u];
             if (cc4 < q4) {
 #pragma unroll
                 for (int g = 0; g < NJ / 8; ++g) {
@@ -453,6 +482,7 @@ k_update(Pts P, const int32_t *__restrict__ ch_hub, const int32_t *__restrict__ 
     // work-group's waves whose chunks belong to the same hub (a hub's chunks
     // are consecutive in the queue)
     extern __shared__ __align__(16) float cen[];
+    __shared__ __align__(16) float ustg[UPD_W][CH * US_LDR];  // each wave's staged rows
     __shared__ int hub_s[UPD_W];
     const int w = threadIdx.x / CH, lane = threadIdx.x % CH;
     // the queue lists the chunks of the hubs still active (device-resident
@@ -484,7 +514,6 @@ k_update(Pts P, const int32_t *__restrict__ ch_hub, const int32_t *__restrict__ 
             const int dp = P.dp, ldc = dp + 4;  // rows 16-byte aligned
             // one point per lane (its row read once per batch), the batch's
             // centres broadcast from LDS
-            const float *row = X + (size_t)o * dp;
             __syncthreads();  // hub_s of the previous entries is consumed
             if (lane == 0)
                 hub_s[w] = act && j1 > j0 ? h : -1;
@@ -530,7 +559,7 @@ k_update(Pts P, const int32_t *__restrict__ ch_hub, const int32_t *__restrict__ 
                     }
                     __syncthreads();
                     if (mine)
-                        upd_lane(row, cen, ldc, dp, jb, nj, dcur, lcur);
+                        upd_lane(X, o, ustg[w], cen, ldc, dp, jb, nj, dcur, lcur);
                 }
             }
         }
