@@ -1472,13 +1472,20 @@ k_gram_direct(Pts P, GramArgs G, TileOut out)
             const_cast<void *>(G.qp), (short)0, G.npacks * GP * rowb, BUF_RSRC_W3);
         const __amdgpu_buffer_rsrc_t ra = __builtin_amdgcn_make_buffer_rsrc(
             const_cast<float *>(G.ayp), (short)0, G.npacks * GP * 4, BUF_RSRC_W3);
-        auto load_b = [&](int e, int4 (&B)[2][NKS], float (&ay)[2]) {
+        // Entry loops: with uniform packs (U) entry e is B pack ub0 + e - e0
+        // and the loop starts at the wave's own pack (no B pack before it,
+        // no other cloud), so an entry needs no field reads and no tests;
+        // otherwise the fields come from LDS and each entry is tested.
+        auto load_b = [&](auto uc, int e, int4 (&B)[2][NKS], float (&ay)[2]) __attribute__((always_inline)) {
+            constexpr bool U = decltype(uc)::value;
             // buffer loads: the pack's offset in a scalar register, the
             // lane's offset fixed (32 bits: gram_pad_packs checks that the
             // copies fit), so an entry costs no vector arithmetic
-            const unsigned pk =
-                G.upk ? (unsigned)(ub0 + (e - e0))
-                      : (unsigned)(__builtin_amdgcn_readfirstlane(eB[e - e0]) - G.nn);
+            unsigned pk;
+            if constexpr (U)
+                pk = (unsigned)(ub0 + (e - e0));
+            else
+                pk = (unsigned)(__builtin_amdgcn_readfirstlane(eB[e - e0]) - G.nn);
             const int sq = (int)(pk * (unsigned)(GP * rowb)), sa = (int)(pk * (unsigned)(GP * 4));
 #pragma unroll
             for (int cb = 0; cb < 2; ++cb) {
@@ -1493,21 +1500,23 @@ k_gram_direct(Pts P, GramArgs G, TileOut out)
                                             __builtin_amdgcn_raw_buffer_load_b32(ra, c * 4, sa, 0));
             }
         };
-        auto step = [&](int e, int4 (&B)[2][NKS], float (&ay)[2]) {
+        auto step = [&](auto uc, int e, int4 (&B)[2][NKS], float (&ay)[2]) __attribute__((always_inline)) {
+            constexpr bool U = decltype(uc)::value;
             // the entry's fields are the same in every lane
-            int b, pb, nb, cb_cl;
-            if (G.upk) {
+            int b, pb, nb;
+            bool skip;
+            if constexpr (U) {
                 b = ub0 + (e - e0);
                 pb = b * GP;
                 nb = min(GP, G.upk - pb);
-                cb_cl = -1;
+                skip = false;
             } else {
                 b = __builtin_amdgcn_readfirstlane(eB[e - e0]);
                 pb = __builtin_amdgcn_readfirstlane(eP[e - e0]);
                 nb = __builtin_amdgcn_readfirstlane(eN[e - e0]);
-                cb_cl = __builtin_amdgcn_readfirstlane(eC[e - e0]);
+                const int cb_cl = __builtin_amdgcn_readfirstlane(eC[e - e0]);
+                skip = !has_a || b < a || (ca >= 0 && (cb_cl == ca) == (bool)G.cross);
             }
-            const bool skip = !has_a || b < a || (ca >= 0 && (cb_cl == ca) == (bool)G.cross);
             if (!skip) {
                 const bool self = (b == a);
                 const float ayc[2] = {ay[0], ay[1]};
@@ -1551,16 +1560,29 @@ k_gram_direct(Pts P, GramArgs G, TileOut out)
             }
             // issued on every path (past the end: the last entry again),
             // so the count of loads in flight never depends on the branch
-            load_b(min(e + 2, e1 - 1), B, ay);
+            load_b(uc, min(e + 2, e1 - 1), B, ay);
         };
-        load_b(e0, BA, ayA);
-        load_b(min(e0 + 1, e1 - 1), BB, ayB);
-        for (int e = e0; e < e1; e += 2) {
-            step(e, BA, ayA);
-            if (e + 1 < e1)
-                step(e + 1, BB, ayB);
-            else
-                load_b(e1 - 1, BB, ayB);  // same loads in flight on both paths
+        auto run = [&](auto uc, int es) __attribute__((always_inline)) {
+            load_b(uc, es, BA, ayA);
+            // one entry's loads after the other's: the loop's waits count
+            // them in this order
+            asm volatile("" ::: "memory");
+            load_b(uc, min(es + 1, e1 - 1), BB, ayB);
+            for (int e = es; e < e1; e += 2) {
+                step(uc, e, BA, ayA);
+                if (e + 1 < e1)
+                    step(uc, e + 1, BB, ayB);
+                else
+                    load_b(uc, e1 - 1, BB, ayB);  // same loads in flight on both paths
+            }
+        };
+        if (G.upk) {
+            // entries before the wave's own pack pair it with earlier packs
+            const int es = has_a ? e0 + max(0, a - ub0) : e1;
+            if (es < e1)
+                run(std::true_type{}, es);
+        } else {
+            run(std::false_type{}, e0);
         }
         __syncthreads();  // eB.. are rewritten by the next unit
     }
