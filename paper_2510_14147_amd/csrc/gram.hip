@@ -225,15 +225,22 @@ k_cov_partial(const float *__restrict__ x, int n, int dp, int stride, Centre C,
             }
 }
 
+// C = inv_m * (sum of the nparts partial matrices): eight partial sums per
+// element keep eight loads in flight.
 __global__ void k_cov_reduce(const double *__restrict__ part, int nparts, int dd,
                              double inv_m, double *__restrict__ C)
 {
     for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < dd;
          e += gridDim.x * blockDim.x) {
-        double v = 0.0;
-        for (int b = 0; b < nparts; ++b)
-            v += part[(size_t)b * dd + e];
-        C[e] = v * inv_m;
+        double v[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        int b = 0;
+        for (; b + 8 <= nparts; b += 8)
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                v[u] += part[(size_t)(b + u) * dd + e];
+        for (; b < nparts; ++b)
+            v[0] += part[(size_t)b * dd + e];
+        C[e] = (((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]))) * inv_m;
     }
 }
 
@@ -246,6 +253,18 @@ __device__ __forceinline__ double block_sum256(double v, double *red)
         red[t / WAVE] = v;
     __syncthreads();
     return red[0] + red[1] + red[2] + red[3];
+}
+
+// Largest v over a work-group of 256 threads (v >= 0), in every thread.
+__device__ __forceinline__ float block_max256(float v, float *red)
+{
+    v = wave_max(v);
+    const int t = threadIdx.x;
+    __syncthreads();
+    if ((t & (WAVE - 1)) == 0)
+        red[t / WAVE] = v;
+    __syncthreads();
+    return fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
 }
 
 __device__ __forceinline__ double pm_one(int j, int c, int salt)
@@ -482,29 +501,40 @@ __global__ void k_absmax(const float *__restrict__ x, int n, int dp, Centre C,
         atomicMax(mx, __float_as_uint(m));
 }
 
-// Sum over points of |x - mu|^2 (mu per cloud), one atomic per wave.
+// Sum over points of |x - mu|^2 (mu per cloud) and the largest |x - mu|.
+// Thread t takes float4 t, t + T, ... of the rows' flattened coordinates
+// (dp is a multiple of 4), so a wave reads 1 KB of consecutive rows per
+// load; FP32 sums per thread, FP64 across the work-group (256 threads),
+// one atomic per work-group (atomics on one address serialise).
 __global__ void k_sqdev(const float *__restrict__ x, int n, int dp, Centre C,
                         double *__restrict__ out, unsigned *__restrict__ amax)
 {
-    const int lane = threadIdx.x & (WAVE - 1);
-    const int wpb = blockDim.x / WAVE;
-    double acc = 0.0;
-    float m = 0.f;  // and the largest |x - mu|
-    for (int i = blockIdx.x * wpb + threadIdx.x / WAVE; i < n; i += gridDim.x * wpb) {
-        const int cl = C.cloud(i);
-        float ss = 0.f;
-        for (int k = lane; k < dp; k += WAVE) {
-            const float v = x[(size_t)i * dp + k] - C.mu(cl, k);
-            ss = fmaf(v, v, ss);
-            m = fmaxf(m, fabsf(v));
-        }
-        acc += (double)ss;
+    const unsigned long long q4 = (unsigned long long)(dp >> 2);
+    const unsigned long long tot = (unsigned long long)n * q4;
+    const float4 *x4 = reinterpret_cast<const float4 *>(x);
+    float ss = 0.f, m = 0.f;
+    for (unsigned long long f = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x;
+         f < tot; f += (unsigned long long)gridDim.x * blockDim.x) {
+        // 32-bit division while the flattened index fits
+        const unsigned long long i = tot <= 0xFFFFFFFFull ? (unsigned)f / (unsigned)q4 : f / q4;
+        const int k = 4 * (int)(f - i * q4);
+        const int cl = C.cloud((long long)i);
+        const float4 v = x4[f];
+        const float d0 = v.x - C.mu(cl, k), d1 = v.y - C.mu(cl, k + 1),
+                    d2 = v.z - C.mu(cl, k + 2), d3 = v.w - C.mu(cl, k + 3);
+        ss = fmaf(d0, d0, ss);
+        ss = fmaf(d1, d1, ss);
+        ss = fmaf(d2, d2, ss);
+        ss = fmaf(d3, d3, ss);
+        m = fmaxf(m, fmaxf(fmaxf(fabsf(d0), fabsf(d1)), fmaxf(fabsf(d2), fabsf(d3))));
     }
-    acc = wave_sum(acc);
-    m = wave_max(m);
-    if (lane == 0 && acc != 0.0)
+    __shared__ double red[4];
+    __shared__ float redf[4];
+    const double acc = block_sum256((double)ss, red);
+    m = block_max256(m, redf);
+    if (threadIdx.x == 0 && acc != 0.0)
         atomicAdd(out, acc);
-    if (lane == 0 && amax)
+    if (threadIdx.x == 0 && amax)
         atomicMax(amax, __float_as_uint(m));
 }
 
@@ -1247,7 +1277,8 @@ __device__ __forceinline__ void surv_flush(const GramArgs &G, const int2 *sb, un
 // Position q of acc[cb] in a lane holds row 32 rb + 8 (q / 4) + q % 4 + 4 hi
 // of column 32 cb + l32; acc[cb] starts at -ax of its row, ay[cb] is the
 // lane's column term (FLT_MAX past nb) and hm[cb] the lanes whose largest
-// sum of that block reaches it.  The pairs that pass go to the wave's LDS
+// sum of that block reaches it; ba is the B pack's index minus the A
+// pack's (0: a self block).  The pairs that pass go to the wave's LDS
 // buffer sb (*fill entries held), which goes to the list when it would
 // overflow.  Blocks of two different packs (not validating) take one ballot
 // per row position and write each position's pairs row first; self blocks
@@ -1257,7 +1288,7 @@ __device__ __forceinline__ void surv_flush(const GramArgs &G, const int2 *sb, un
 // the list directly.
 __device__ __forceinline__ void half_finish(const GramArgs &G, const f32x16 (&acc)[2],
                                             const float (&ay)[2], const uint64_t (&hm)[2],
-                                            int rb, int na, int nb, bool self, int pa,
+                                            int rb, int na, int nb, int ba, int pa,
                                             int pb, unsigned *fillS, int2 *sb,
                                             const unsigned *rmS)
 {
@@ -1265,6 +1296,7 @@ __device__ __forceinline__ void half_finish(const GramArgs &G, const f32x16 (&ac
     // keep the entry-dependent row and column arithmetic here: without this
     // the compiler computes it ahead of the vote, on every half
     asm volatile("" : "+v"(na), "+v"(nb), "+v"(pa), "+v"(pb));
+    const bool self = ba == 0;
     unsigned fill = (unsigned)__builtin_amdgcn_readfirstlane((int)*fillS);
     const uint64_t ltmask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     if (!G.validate && !self) {
@@ -1386,6 +1418,7 @@ k_gram_direct(Pts P, GramArgs G, TileOut out)
         rmS[i] = c_rowmask.m[i];
     const int t = threadIdx.x, lane = t & (WAVE - 1);
     const int w = __builtin_amdgcn_readfirstlane(t / WAVE);  // wave-uniform
+    const bool uloop = G.upk && !G.validate;  // the uniform-pack entry loop
     const int l32 = lane & 31, hi = lane >> 5;
     const unsigned char *Q = (const unsigned char *)G.q;
     __shared__ unsigned fillS[GW];                     // each wave's buffered survivors
@@ -1407,7 +1440,7 @@ k_gram_direct(Pts P, GramArgs G, TileOut out)
         const int pa = has_a ? G.q_pb[a] : 0;
         const int na = has_a ? G.q_pe[a] - pa : 0;
         // uniform packs: entry e of the unit is B pack ub0 + e - e0
-        const int ub0 = G.upk ? __builtin_amdgcn_readfirstlane(G.lb[e0]) : 0;
+        const int ub0 = uloop ? __builtin_amdgcn_readfirstlane(G.lb[e0]) : 0;
         // A fragments: rows 32 rb + l32, bytes 32 ks + 16 hi
         int4 Af[2][NKS];
 #pragma unroll
@@ -1426,8 +1459,8 @@ k_gram_direct(Pts P, GramArgs G, TileOut out)
         const float e2 = ca >= 0 ? G.ct[ca].e2f : G.e2f;
         for (int r = lane; r < GP; r += WAVE)
             axS[w][r] = r < na ? -0.5f * (G.hx[pa + r] - e2) : -FLT_MAX;
-        // (uniform packs: the entries' fields follow from their index)
-        for (int i = G.upk ? e1 - e0 : t; i < e1 - e0; i += GT) {
+        // (the uniform-pack loop derives the entries' fields from their index)
+        for (int i = uloop ? e1 - e0 : t; i < e1 - e0; i += GT) {
             const int bb = G.nn + G.lb[e0 + i];
             const int pbb = G.q_pb[bb];
             eB[i] = bb;
@@ -1472,10 +1505,11 @@ k_gram_direct(Pts P, GramArgs G, TileOut out)
             const_cast<void *>(G.qp), (short)0, G.npacks * GP * rowb, BUF_RSRC_W3);
         const __amdgpu_buffer_rsrc_t ra = __builtin_amdgcn_make_buffer_rsrc(
             const_cast<float *>(G.ayp), (short)0, G.npacks * GP * 4, BUF_RSRC_W3);
-        // Entry loops: with uniform packs (U) entry e is B pack ub0 + e - e0
-        // and the loop starts at the wave's own pack (no B pack before it,
-        // no other cloud), so an entry needs no field reads and no tests;
-        // otherwise the fields come from LDS and each entry is tested.
+        // Entry loops: with uniform packs and no validation (U) entry e is B
+        // pack ub0 + e - e0 and the loop starts at the wave's own pack (no B
+        // pack before it, no other cloud), so an entry needs no field reads
+        // and no tests; otherwise the fields come from LDS and each entry is
+        // tested.
         auto load_b = [&](auto uc, int e, int4 (&B)[2][NKS], float (&ay)[2]) __attribute__((always_inline)) {
             constexpr bool U = decltype(uc)::value;
             // buffer loads: the pack's offset in a scalar register, the
@@ -1518,7 +1552,6 @@ k_gram_direct(Pts P, GramArgs G, TileOut out)
                 skip = !has_a || b < a || (ca >= 0 && (cb_cl == ca) == (bool)G.cross);
             }
             if (!skip) {
-                const bool self = (b == a);
                 const float ayc[2] = {ay[0], ay[1]};
                 // one 32-row half at a time against both column blocks: the
                 // half's 16 start values feed both products.  Rows past na
@@ -1553,8 +1586,8 @@ k_gram_direct(Pts P, GramArgs G, TileOut out)
                             mx = fmaxf(mx, acc[cb][q]);
                         hm[cb] = __ballot(mx >= ayc[cb]);
                     }
-                    if ((hm[0] | hm[1]) != 0 || G.validate)
-                        half_finish(G, acc, ayc, hm, rb, na, nb, self, pa, pb, &fillS[w], survS[w],
+                    if ((hm[0] | hm[1]) != 0 || (!U && G.validate))
+                        half_finish(G, acc, ayc, hm, rb, na, nb, b - a, pa, pb, &fillS[w], survS[w],
                                     rmS);
                 }
             }
@@ -1576,7 +1609,7 @@ k_gram_direct(Pts P, GramArgs G, TileOut out)
                     load_b(uc, e1 - 1, BB, ayB);  // same loads in flight on both paths
             }
         };
-        if (G.upk) {
+        if (uloop) {
             // entries before the wave's own pack pair it with earlier packs
             const int es = has_a ? e0 + max(0, a - ub0) : e1;
             if (es < e1)
@@ -2208,7 +2241,7 @@ static int project_pca(const float *X, int n, int dp, int kq_full, int proj,
         return 0;
     const int stride = (int)cdiv(n, PCA_ROWS);
     const long long m = cdiv(n, stride);
-    const int nparts = (int)std::min<long long>(64, cdiv(m, 32));
+    const int nparts = (int)std::min<long long>(256, cdiv(m, 32));
     const int dd = dp * dp;
     double *part = S.get<double>((size_t)nparts * dd);
     double *Cv = S.get<double>(dd);
@@ -2308,7 +2341,8 @@ double gram_margin_ratio(const fnn_tree *T, double t2min, int prec, Scratch &S,
     const Centre CX = make_centre(T, X, dp, inv, S);
     double *acc = S.get<double>(2);  // [0] sum of |x - mu|^2, [1] largest |x - mu|
     fill(acc, 0.0, 2, s);
-    FNN_LAUNCH(k_sqdev, dim3(grid_cap(n, 4, 4096)), dim3(256), 0, s, X, n, dp, CX, acc,
+    FNN_LAUNCH(k_sqdev, dim3(grid_cap((int64_t)n * (dp / 4), 256 * 8, 1024)), dim3(256), 0, s, X, n,
+               dp, CX, acc,
                reinterpret_cast<unsigned *>(acc + 1));
     double h[2];
     FNN_HIP(hipMemcpyAsync(h, acc, sizeof h, hipMemcpyDeviceToHost, s));
