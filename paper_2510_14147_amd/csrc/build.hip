@@ -1194,10 +1194,29 @@ __global__ void k_center_pos(const int32_t *__restrict__ center,
         cpos[v] = inv[center[v]];
 }
 
+// out row p = in row perm[p].  Rows of a multiple of 16 bytes (16-byte
+// aligned arrays) move as int4
+// chunks of the flattened output (a wave writes 1 KB of consecutive rows
+// per store); other rows one element per lane, a wave per row.
 template <class T>
 __global__ void k_gather_rows(const T *__restrict__ in, const int32_t *__restrict__ perm,
                               int n, int stride, T *__restrict__ out)
 {
+    const size_t rowb = (size_t)stride * sizeof(T);
+    if (rowb % 16 == 0 && (((uintptr_t)in | (uintptr_t)out) & 15) == 0) {
+        const unsigned long long q = rowb / 16;
+        const unsigned long long tot = (unsigned long long)n * q;
+        const int4 *in4 = reinterpret_cast<const int4 *>(in);
+        int4 *out4 = reinterpret_cast<int4 *>(out);
+        for (unsigned long long f = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x;
+             f < tot; f += (unsigned long long)gridDim.x * blockDim.x) {
+            // 32-bit division while the flattened index fits
+            const unsigned long long p =
+                tot <= 0xFFFFFFFFull ? (unsigned)f / (unsigned)q : f / q;
+            out4[f] = in4[(size_t)perm[p] * q + (f - p * q)];
+        }
+        return;
+    }
     const int lane = threadIdx.x & (WAVE - 1);
     const int wpb = blockDim.x / WAVE;
     for (int p = blockIdx.x * wpb + threadIdx.x / WAVE; p < n;
@@ -1211,7 +1230,36 @@ __global__ void k_gather_rows(const T *__restrict__ in, const int32_t *__restric
 
 // ---- query tree: packs of consecutive sibling leaf blocks ----------------
 
-constexpr int QT_PF = 8;  // children whose fields are loaded at once
+// One wave per vertex: its children are read 64 at a time (one per lane,
+// coalesced), and the next-fit walk over them (a run of consecutive leaf
+// blocks grows while its points fit in P; a non-leaf child ends the run)
+// runs on scalar registers, one child per step, marking the children that
+// open a pack.  Every query-tree kid (a non-leaf child or a new pack) then
+// takes its slot from a prefix count over the lanes.
+struct QtChunk {
+    uint64_t open;  // lanes whose child opens a new pack
+    uint64_t kid;   // lanes whose child is a query-tree kid (non-leaf or open)
+};
+__device__ __forceinline__ QtChunk qt_walk(int cnt, bool leaf, int sz, int P, int &run)
+{
+    const uint64_t leafm = __ballot(leaf);
+    uint64_t open = 0;
+    for (int j = 0; j < cnt; ++j) {
+        if (!((leafm >> j) & 1ull)) {
+            run = -1;
+            continue;
+        }
+        const int s = __builtin_amdgcn_readlane(sz, j);
+        if (run >= 0 && run + s <= P) {
+            run += s;
+        } else {
+            open |= 1ull << j;
+            run = s;
+        }
+    }
+    const uint64_t valid = cnt >= WAVE ? ~0ull : ((1ull << cnt) - 1);
+    return QtChunk{open, (~leafm & valid) | open};
+}
 
 __global__ void k_qt_count(int nn, const int32_t *__restrict__ ccnt,
                            const int32_t *__restrict__ cbeg,
@@ -1219,7 +1267,9 @@ __global__ void k_qt_count(int nn, const int32_t *__restrict__ ccnt,
                            const int32_t *__restrict__ pe, int P, int solo,
                            int32_t *__restrict__ npk, int32_t *__restrict__ nqk)
 {
-    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int v = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (blockDim.x / WAVE) +
+                                                      threadIdx.x / WAVE));
     if (v >= nn)
         return;
     const int cc = ccnt[v];
@@ -1229,37 +1279,20 @@ __global__ void k_qt_count(int nn, const int32_t *__restrict__ ccnt,
         P = 0;
     int packs = 0, kids = 0, run = -1;
     const int c0 = cc > 0 ? cbeg[v] : 0;
-    // children read QT_PF at a time (the walk itself is sequential)
-    for (int a0 = 0; a0 < cc; a0 += QT_PF) {
-        int ck[QT_PF], szk[QT_PF];
-#pragma unroll
-        for (int j = 0; j < QT_PF; ++j) {
-            const int u = c0 + a0 + j;
-            const bool in = a0 + j < cc;
-            ck[j] = in ? ccnt[u] : 0;
-            szk[j] = in ? pe[u] - pb[u] : 0;
-        }
-#pragma unroll
-        for (int j = 0; j < QT_PF; ++j) {
-            if (a0 + j >= cc)
-                break;
-            if (ck[j] > 0) {
-                ++kids;
-                run = -1;
-                continue;
-            }
-            const int sz = szk[j];
-            if (run >= 0 && run + sz <= P) {
-                run += sz;
-            } else {
-                ++packs;
-                ++kids;
-                run = sz;
-            }
-        }
+    for (int a0 = 0; a0 < cc; a0 += WAVE) {
+        const int cnt = min(WAVE, cc - a0);
+        const int u = c0 + a0 + lane;
+        const bool in = lane < cnt;
+        const bool leaf = in && ccnt[u] == 0;
+        const int sz = in ? pe[u] - pb[u] : 0;
+        const QtChunk q = qt_walk(cnt, leaf, sz, P, run);
+        packs += __popcll(q.open);
+        kids += __popcll(q.kid);
     }
-    npk[v] = packs;
-    nqk[v] = kids;
+    if (lane == 0) {
+        npk[v] = packs;
+        nqk[v] = kids;
+    }
 }
 
 __global__ void k_qt_fill(int nn, const int32_t *__restrict__ ccnt,
@@ -1276,63 +1309,62 @@ __global__ void k_qt_fill(int nn, const int32_t *__restrict__ ccnt,
                           int32_t *__restrict__ q_kcnt,
                           int32_t *__restrict__ q_kids)
 {
-    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int v = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (blockDim.x / WAVE) +
+                                                      threadIdx.x / WAVE));
     if (v >= nn)
         return;
     const int cc = ccnt[v];
     // internal vertices keep their own attributes; leaf blocks are not
     // query-tree vertices (they live inside packs)
-    q_cpos[v] = cpos[v];
-    q_rad[v] = radius[v];
-    q_pb[v] = pb[v];
-    q_pe[v] = pe[v];
-    q_kbeg[v] = kidoff[v];
-    q_kcnt[v] = kidoff[v + 1] - kidoff[v];
+    if (lane == 0) {
+        q_cpos[v] = cpos[v];
+        q_rad[v] = radius[v];
+        q_pb[v] = pb[v];
+        q_pe[v] = pe[v];
+        q_kbeg[v] = kidoff[v];
+        q_kcnt[v] = kidoff[v + 1] - kidoff[v];
+    }
     if (cc == 0)
         return;
     if (v == solo)
         P = 0;
-    int pk = nn + pkoff[v] - 1;  // id of the current pack
-    int kd = kidoff[v];
+    const uint64_t below = lane == 0 ? 0ull : (~0ull >> (WAVE - lane));  // lanes < lane
+    int pk0 = nn + pkoff[v] - 1;  // id of the current pack
+    int kd0 = kidoff[v];
     int run = -1;
     const int c0 = cbeg[v];
-    for (int a0 = 0; a0 < cc; a0 += QT_PF) {
-        int ck[QT_PF], pbk[QT_PF], pek[QT_PF], cpk[QT_PF];
-#pragma unroll
-        for (int j = 0; j < QT_PF; ++j) {
-            const int u = c0 + a0 + j;
-            const bool in = a0 + j < cc;
-            ck[j] = in ? ccnt[u] : 0;
-            pbk[j] = in ? pb[u] : 0;
-            pek[j] = in ? pe[u] : 0;
-            cpk[j] = in ? cpos[u] : 0;
+    for (int a0 = 0; a0 < cc; a0 += WAVE) {
+        const int cnt = min(WAVE, cc - a0);
+        const int u = c0 + a0 + lane;
+        const bool in = lane < cnt;
+        const bool leaf = in && ccnt[u] == 0;
+        const int pbk = in ? pb[u] : 0, pek = in ? pe[u] : 0;
+        const QtChunk q = qt_walk(cnt, leaf, pek - pbk, P, run);
+        // this lane's pack (the last one opened at or before it) and slot
+        const int pk = pk0 + __popcll(q.open & (below | (1ull << lane)));
+        const int kd = kd0 + __popcll(q.kid & below);
+        if (in && !leaf)
+            q_kids[kd] = u;
+        if ((q.open >> lane) & 1ull) {
+            q_kids[kd] = pk;
+            q_cpos[pk] = cpos[u];
+            q_pb[pk] = pbk;
+            q_kbeg[pk] = 0;
+            q_kcnt[pk] = 0;
+            q_rad[pk] = 0.f;
         }
-#pragma unroll
-        for (int j = 0; j < QT_PF; ++j) {
-            if (a0 + j >= cc)
-                break;
-            const int u = c0 + a0 + j;
-            if (ck[j] > 0) {
-                q_kids[kd++] = u;
-                run = -1;
-                continue;
-            }
-            const int sz = pek[j] - pbk[j];
-            if (run >= 0 && run + sz <= P) {
-                run += sz;
-                q_pe[pk] = pek[j];
-            } else {
-                ++pk;
-                q_kids[kd++] = pk;
-                run = sz;
-                q_cpos[pk] = cpk[j];
-                q_pb[pk] = pbk[j];
-                q_pe[pk] = pek[j];
-                q_kbeg[pk] = 0;
-                q_kcnt[pk] = 0;
-                q_rad[pk] = 0.f;
-            }
-        }
+        // the pack's end: written by its last leaf in this chunk (a run
+        // that goes on in the next chunk is written again there, after this
+        // store has completed)
+        const bool last =
+            lane == cnt - 1 || (lane < WAVE - 1 && ((q.kid >> (lane + 1)) & 1ull));
+        if (leaf && last)
+            q_pe[pk] = pek;
+        pk0 += __popcll(q.open);
+        kd0 += __popcll(q.kid);
+        if (a0 + WAVE < cc)
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     }
 }
 
@@ -1764,7 +1796,7 @@ static void build_impl(fnn_tree *T, const void *points, Scratch &S)
     const int solo = NCL > 1 ? 0 : -1;
     int32_t *npk = S.get<int32_t>(nn + 1), *nqk = S.get<int32_t>(nn + 1);
     int32_t *pkoff = S.get<int32_t>(nn + 2), *kidoff = S.get<int32_t>(nn + 2);
-    FNN_LAUNCH(k_qt_count, dim3(cdiv(nn, 256)), dim3(256), 0, st, nn,
+    FNN_LAUNCH(k_qt_count, dim3(cdiv(nn, 256 / WAVE)), dim3(256), 0, st, nn,
                        nd.ccnt, nd.cbeg, nd.pb, nd.pe, PK, solo, npk, nqk);
     scan_i32(npk, pkoff, nn, S);
     scan_i32(nqk, kidoff, nn, S);
@@ -1786,7 +1818,7 @@ static void build_impl(fnn_tree *T, const void *points, Scratch &S)
     T->q_kbeg = (int32_t *)T->own(sizeof(int32_t) * nq);
     T->q_kcnt = (int32_t *)T->own(sizeof(int32_t) * nq);
     T->q_kids = (int32_t *)T->own(sizeof(int32_t) * (nkids + 1));
-    FNN_LAUNCH(k_qt_fill, dim3(cdiv(nn, 256)), dim3(256), 0, st, nn,
+    FNN_LAUNCH(k_qt_fill, dim3(cdiv(nn, 256 / WAVE)), dim3(256), 0, st, nn,
                        nd.ccnt, nd.cbeg, nd.pb, nd.pe, T->center_pos, nd.radius, PK,
                        solo, pkoff, kidoff, T->q_center_pos, T->q_radius, T->q_pt_begin,
                        T->q_pt_end, T->q_kbeg, T->q_kcnt, T->q_kids);
