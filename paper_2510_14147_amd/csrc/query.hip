@@ -1999,7 +1999,7 @@ static void eps_graph_impl(const fnn_tree *Tc, const double *epsv,
         }
         // Plain tiles: count degrees and append each edge, in both
         // directions, to an edge list, so the fill needs no second tile
-        // pass.  The list holds up to 256 entries per point (bounded by
+        // pass.  The list holds up to 512 entries per point (bounded by
         // twice the pairs the tiles can evaluate and by an eighth of the
         // free device memory); if it overflows, the fill pass runs instead.
         bool listed = false;
@@ -2014,7 +2014,7 @@ static void eps_graph_impl(const fnn_tree *Tc, const double *epsv,
             FNN_HIP(hipMemGetInfo(&freeb, &totb));
             const unsigned long long room = (unsigned long long)(freeb / 8 / 12);
             o.ecap = std::max<unsigned long long>(
-                1024, std::min({2 * bound, room, 256ull * (unsigned long long)n}));
+                1024, std::min({2 * bound, room, 512ull * (unsigned long long)n}));
             if (opt.list_cap > 0)
                 o.ecap = (unsigned long long)opt.list_cap;
             o.elist = S.get<int2>(o.ecap);
