@@ -334,3 +334,20 @@ def test_auto_precision(fnn, orc, case, want):
     tree, g, cmp = check(fnn, orc, x, metric, eps, tree_check=False, precision="auto")
     names = {v: k for k, v in fnn.PRECISIONS.items()}
     assert names[int(g.stats["precision_used"])] == want
+
+
+@pytest.mark.parametrize("n", [2, 63, 64, 65, 129, 1000])
+@pytest.mark.parametrize("validate", [False, True])
+def test_dense_list_full_packs(fnn, orc, n, validate):
+    """One cloud whose pack pairs are all kept takes the closed-form work
+    list over full packs of 64 consecutive tree positions (the last one
+    ragged); every pair is screened once and the graph is exact, with the
+    uniform-pack entry loop (no validation) and the general one (validation)."""
+    x = G.random_points(n, 16, seed=300 + n)
+    eps = 1.6  # about half the pairs: no pack pair can be pruned
+    tree, g, cmp = check(fnn, orc, x, "l2", eps, tree_check=False, precision="fp16",
+                         validate=validate)
+    st = g.stats
+    assert st["filter_pairs"] == n * (n - 1) // 2, st["filter_pairs"]
+    if validate:
+        assert st["validate_mismatch"] == 0
