@@ -836,6 +836,45 @@ __device__ int topk_stream(long long nv, int K, KeyF key, unsigned long long *bu
     return nk;
 }
 
+// The K largest of nv <= SEL_RANK keys (0: no candidate; the others are
+// distinct), in descending order in buf[0 .. nk), by rank: every key counts
+// the keys above it (a broadcast read per key of the buffer).  Returns nk.
+constexpr int SEL_RANK = 512;
+template <class KeyF>
+__device__ int topk_rank(int nv, int K, KeyF key, unsigned long long *buf,
+                         unsigned long long *out, int *cnt_s)
+{
+    if (threadIdx.x == 0)
+        *cnt_s = 0;
+    for (int v = threadIdx.x; v < nv; v += SEL_T)
+        buf[v] = key(v);
+    __syncthreads();
+    for (int v = threadIdx.x; v < nv; v += SEL_T) {
+        const unsigned long long k = buf[v];
+        if (!k)
+            continue;
+        atomicAdd(cnt_s, 1);
+        int r = 0;
+        // eight reads in flight (the buffer's tail past nv is never read)
+        int u = 0;
+        for (; u + 8 <= nv; u += 8) {
+#pragma unroll
+            for (int o = 0; o < 8; ++o)
+                r += buf[u + o] > k;
+        }
+        for (; u < nv; ++u)
+            r += buf[u] > k;
+        if (r < K)
+            out[r] = k;
+    }
+    __syncthreads();
+    const int nk = min(K, *cnt_s);
+    for (int r = threadIdx.x; r < nk; r += SEL_T)
+        buf[r] = out[r];
+    __syncthreads();
+    return nk;
+}
+
 // Candidate slices of a hub with many candidates (more than SEL_PRE): nsl
 // slices of len candidates each (the last may be shorter); 0 when the hub
 // streams its candidates whole.
@@ -922,16 +961,15 @@ k_select(Pts P, Hubs hb, int H, int32_t *__restrict__ cent,
     long long len;
     sel_slices(c1 - c0, nsl, len);
     const long long nv = nsl ? (long long)nsl * K : c1 - c0;
-    int nk = topk_stream(
-        nv, K,
-        [&](long long v) -> unsigned long long {
-            const long long q = nsl ? c0 + (v / K) * len + (v % K) : c0 + v;
-            if (q >= c1 || (nsl && (v % K) >= len))
-                return 0ull;
-            const size_t a = (size_t)(q / R) * CAND_R + (size_t)(q % R);
-            return cand_key(cb_D[a], cb_id[a]);
-        },
-        buf, &fill_s, out);
+    auto ckey = [&](long long v) -> unsigned long long {
+        const long long q = nsl ? c0 + (v / K) * len + (v % K) : c0 + v;
+        if (q >= c1 || (nsl && (v % K) >= len))
+            return 0ull;
+        const size_t a = (size_t)(q / R) * CAND_R + (size_t)(q % R);
+        return cand_key(cb_D[a], cb_id[a]);
+    };
+    int nk = nv <= SEL_RANK ? topk_rank((int)nv, K, ckey, buf, out, &fill_s)
+                            : topk_stream(nv, K, ckey, buf, &fill_s, out);
     if (threadIdx.x == 0)
         nk_s = nk;
     for (int i = threadIdx.x; i < MAX_K * SEL_W; i += SEL_T)
@@ -948,18 +986,38 @@ k_select(Pts P, Hubs hb, int H, int32_t *__restrict__ cent,
     const int ldr = P.dp + 4;
     if (lds_rows) {
         const float *X = M == M_ANG ? P.xn : P.x;
-        const int dp = P.dp;
-        for (int e = threadIdx.x; e < nk * dp; e += SEL_T) {
-            const int r = e / dp, c = e % dp;
-            const int id = 0x7FFFFFFF - (int)(uint32_t)buf[r];
-            crow[r * ldr + c] = X[(size_t)id * dp + c];
+        const int dp = P.dp, q4 = dp / 4;
+        // float4 pieces, every load issued before the first store (at most
+        // SEL_CR rows of UPD_D floats: eight pieces per thread)
+        constexpr int SU = SEL_CR * UPD_D / 4 / SEL_T;
+        float4 v[SU];
+#pragma unroll
+        for (int u = 0; u < SU; ++u) {
+            const int e = threadIdx.x + u * SEL_T;
+            if (e < nk * q4) {
+                const int r = e / q4, c4 = e - r * q4;
+                const int id = 0x7FFFFFFF - (int)(uint32_t)buf[r];
+                v[u] = *reinterpret_cast<const float4 *>(X + (size_t)id * dp + 4 * c4);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < SU; ++u) {
+            const int e = threadIdx.x + u * SEL_T;
+            if (e < nk * q4) {
+                const int r = e / q4, c4 = e - r * q4;
+                *reinterpret_cast<float4 *>(crow + r * ldr + 4 * c4) = v[u];
+            }
         }
         __syncthreads();
     }
-    for (int q = threadIdx.x; q < nk * nk; q += SEL_T) {
-        const int i = q / nk, j = q % nk;
-        if (j >= i)
-            continue;
+    // pairs j < i enumerated over the triangle: q = i (i - 1) / 2 + j
+    for (int q = threadIdx.x; q < nk * (nk - 1) / 2; q += SEL_T) {
+        int i = (int)((1.0f + sqrtf(1.0f + 8.0f * (float)q)) * 0.5f);
+        while (i * (i - 1) / 2 > q)
+            --i;
+        while ((i + 1) * i / 2 <= q)
+            ++i;
+        const int j = q - i * (i - 1) / 2;
         const int a = 0x7FFFFFFF - (int)(uint32_t)buf[i];
         const int c = 0x7FFFFFFF - (int)(uint32_t)buf[j];
         ++tests;
@@ -971,7 +1029,30 @@ k_select(Pts P, Hubs hb, int H, int32_t *__restrict__ cent,
     __syncthreads();
 
     // ---- greedy acceptance in candidate order ------------------------------
-    if (threadIdx.x == 0) {
+    if (nk <= WAVE) {
+        // one wave: lane i holds candidate i's conflicts with the ones
+        // before it, the scan runs on scalar registers, and the accepted
+        // candidates take their places by a prefix count
+        if (threadIdx.x < WAVE) {
+            const int l = threadIdx.x;
+            const unsigned long long ci = l < nk ? conf[l][0] : 0ull;
+            const unsigned clo = (unsigned)ci, chi = (unsigned)(ci >> 32);
+            unsigned long long am = 0ull;
+            for (int i = 0; i < nk; ++i) {
+                const unsigned long long c =
+                    ((unsigned long long)(unsigned)__builtin_amdgcn_readlane((int)chi, i) << 32) |
+                    (unsigned)__builtin_amdgcn_readlane((int)clo, i);
+                if ((c & am) == 0ull)
+                    am |= 1ull << i;
+            }
+            if (l < nk && ((am >> l) & 1ull)) {
+                const unsigned long long below = l == 0 ? 0ull : (~0ull >> (WAVE - l));
+                acc[__popcll(am & below)] = 0x7FFFFFFF - (int)(uint32_t)buf[l];
+            }
+            if (l == 0)
+                nacc_s = __popcll(am);
+        }
+    } else if (threadIdx.x == 0) {
         unsigned long long am[SEL_W];
 #pragma unroll
         for (int w = 0; w < SEL_W; ++w)
