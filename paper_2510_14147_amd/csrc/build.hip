@@ -1817,14 +1817,20 @@ static void build_impl(fnn_tree *T, const void *points, Scratch &S)
     int32_t *inv = S.get<int32_t>(n);
     FNN_LAUNCH(k_inverse, dim3(cdiv(n, 256)), dim3(256), 0, st, perm, n,
                        inv);
-    T->center = (int32_t *)T->own(sizeof(int32_t) * nn);
-    T->center_pos = (int32_t *)T->own(sizeof(int32_t) * nn);
-    T->radius = (float *)T->own(sizeof(float) * nn);
-    T->level = (int32_t *)T->own(sizeof(int32_t) * nn);
-    T->child_begin = (int32_t *)T->own(sizeof(int32_t) * nn);
-    T->child_count = (int32_t *)T->own(sizeof(int32_t) * nn);
-    T->pt_begin = (int32_t *)T->own(sizeof(int32_t) * nn);
-    T->pt_end = (int32_t *)T->own(sizeof(int32_t) * nn);
+    {
+        const size_t vb = sizeof(int32_t) * (size_t)nn;
+        const size_t sizes[8] = {vb, vb, vb, vb, vb, vb, vb, vb};
+        void *v[8];
+        T->own_many(sizes, v);
+        T->center = (int32_t *)v[0];
+        T->center_pos = (int32_t *)v[1];
+        T->radius = (float *)v[2];
+        T->level = (int32_t *)v[3];
+        T->child_begin = (int32_t *)v[4];
+        T->child_count = (int32_t *)v[5];
+        T->pt_begin = (int32_t *)v[6];
+        T->pt_end = (int32_t *)v[7];
+    }
     auto cp = [&](void *dst, const void *src, size_t b) {
         FNN_HIP(hipMemcpyAsync(dst, src, b, hipMemcpyDeviceToDevice, st));
     };
@@ -1892,13 +1898,19 @@ static void build_impl(fnn_tree *T, const void *points, Scratch &S)
     const int nq = nn + npacks;
     T->npacks = npacks;
     T->nq = nq;
-    T->q_center_pos = (int32_t *)T->own(sizeof(int32_t) * nq);
-    T->q_radius = (float *)T->own(sizeof(float) * nq);
-    T->q_pt_begin = (int32_t *)T->own(sizeof(int32_t) * nq);
-    T->q_pt_end = (int32_t *)T->own(sizeof(int32_t) * nq);
-    T->q_kbeg = (int32_t *)T->own(sizeof(int32_t) * nq);
-    T->q_kcnt = (int32_t *)T->own(sizeof(int32_t) * nq);
-    T->q_kids = (int32_t *)T->own(sizeof(int32_t) * (nkids + 1));
+    {
+        const size_t qb = sizeof(int32_t) * (size_t)nq;
+        const size_t sizes[7] = {qb, qb, qb, qb, qb, qb, sizeof(int32_t) * ((size_t)nkids + 1)};
+        void *v[7];
+        T->own_many(sizes, v);
+        T->q_center_pos = (int32_t *)v[0];
+        T->q_radius = (float *)v[1];
+        T->q_pt_begin = (int32_t *)v[2];
+        T->q_pt_end = (int32_t *)v[3];
+        T->q_kbeg = (int32_t *)v[4];
+        T->q_kcnt = (int32_t *)v[5];
+        T->q_kids = (int32_t *)v[6];
+    }
     FNN_LAUNCH(k_qt_fill, dim3(cdiv(nn, 256 / WAVE)), dim3(256), 0, st, nn,
                        nd.ccnt, nd.cbeg, nd.pb, nd.pe, T->center_pos, nd.radius, PK,
                        solo, pkoff, kidoff, T->q_center_pos, T->q_radius, T->q_pt_begin,

@@ -1657,11 +1657,11 @@ __global__ void k_gram_pairs(GramArgs G, TileOut out)
 // FP32 key of every lane's pair (pi, pj), summed exactly as sqdiff_seq sums
 // it (one FMA per coordinate, coordinates in index order, zero padding
 // adding nothing), so the distances equal the FP32 tiles' bit for bit.  The
-// wave stages its 64 pairs' rows through LDS 16 coordinates at a time:
-// each load instruction then reads 64-byte row segments of 16 rows instead
+// wave stages its 64 pairs' rows through LDS 32 coordinates at a time:
+// each load instruction then reads 128-byte row segments of 8 rows instead
 // of 64 scattered lines, and the next segment is in flight while this one
 // is summed.  sA, sB: the wave's LDS rows (64 x SV_LDR floats each).
-constexpr int SV_CH = 16;            // coordinates per staged segment
+constexpr int SV_CH = 32;            // coordinates per staged segment
 constexpr int SV_LDR = SV_CH + 4;    // floats per staged row (bank spread)
 constexpr int SV_F = SV_CH / 4;      // float4 per row segment
 template <int M>

@@ -1973,8 +1973,6 @@ static void eps_graph_impl(const fnn_tree *Tc, const double *epsv,
                         gedges = G.surv;
                         ngedges = got;
                     } else {
-                        gedges = S.get<int2>(got + 1);
-                        gedist = S.get<float>(got + 1);
                         // with no plain tiles in the query every CSR entry
                         // comes from a survivor: keep the ranks its degree
                         // counters return and place it without cursors
@@ -1983,8 +1981,12 @@ static void eps_graph_impl(const fnn_tree *Tc, const double *epsv,
                         // quarter of the free device memory
                         size_t free_now = 0, tot_now = 0;
                         FNN_HIP(hipMemGetInfo(&free_now, &tot_now));
-                        if (nplain == 0 &&
-                            (double)(got + 1) * sizeof(int2) < 0.25 * (double)free_now)
+                        const bool ranks =
+                            nplain == 0 &&
+                            (double)(got + 1) * sizeof(int2) < 0.25 * (double)free_now;
+                        gedges = S.get<int2>(got + 1);
+                        gedist = S.get<float>(got + 1);
+                        if (ranks)
                             G.erank = S.get<int2>(got + 1);
                         // slot per survivor: holes where it is no edge
                         survivors_launch(M, P, G, got, gedges, gedist, o, s);

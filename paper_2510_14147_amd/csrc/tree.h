@@ -107,6 +107,20 @@ struct fnn_tree {
         owned.push_back(p);
         return p;
     }
+    // One allocation carved into N arrays of the given sizes (each starting
+    // 256-byte aligned): one call of the caller's allocator instead of N.
+    template <size_t N>
+    void own_many(const size_t (&bytes)[N], void *(&out)[N])
+    {
+        size_t off[N], tot = 0;
+        for (size_t i = 0; i < N; ++i) {
+            off[i] = tot;
+            tot += (bytes[i] + 255) / 256 * 256;
+        }
+        char *p = static_cast<char *>(own(tot > 0 ? tot : 256));
+        for (size_t i = 0; i < N; ++i)
+            out[i] = p + off[i];
+    }
     ~fnn_tree()
     {
         for (void *p : owned)
