@@ -1501,10 +1501,14 @@ k_gram_direct(Pts P, GramArgs G, TileOut out)
         // so every lane loads at a fixed offset and an entry costs no vector
         // arithmetic; the loads of one entry are a fixed count, so the next
         // entry's stay in flight while this one computes.
+        // record counts in bytes, below 2^32 (gram_pad_packs checks), as
+        // the resource's unsigned 32-bit word
         const __amdgpu_buffer_rsrc_t rq = __builtin_amdgcn_make_buffer_rsrc(
-            const_cast<void *>(G.qp), (short)0, G.npacks * GP * rowb, BUF_RSRC_W3);
+            const_cast<void *>(G.qp), (short)0,
+            (int)(unsigned)((unsigned long long)G.npacks * GP * rowb), BUF_RSRC_W3);
         const __amdgpu_buffer_rsrc_t ra = __builtin_amdgcn_make_buffer_rsrc(
-            const_cast<float *>(G.ayp), (short)0, G.npacks * GP * 4, BUF_RSRC_W3);
+            const_cast<float *>(G.ayp), (short)0,
+            (int)(unsigned)((unsigned long long)G.npacks * GP * 4), BUF_RSRC_W3);
         // Entry loops: with uniform packs and no validation (U) entry e is B
         // pack ub0 + e - e0 and the loop starts at the wave's own pack (no B
         // pack before it, no other cloud), so an entry needs no field reads
