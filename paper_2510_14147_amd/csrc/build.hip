@@ -250,9 +250,14 @@ __global__ void k_root_keys(Pts P, int32_t *__restrict__ perm,
         }
         D[i] = k;
     }
+    // one atomic per work-group of 256 (atomics on one address serialise)
+    __shared__ float wm[4];
     k = wave_max(k);
     if ((threadIdx.x & (WAVE - 1)) == 0)
-        atomicMax(kmax, __float_as_uint(k));
+        wm[threadIdx.x / WAVE] = k;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        atomicMax(kmax, __float_as_uint(fmaxf(fmaxf(wm[0], wm[1]), fmaxf(wm[2], wm[3]))));
 }
 
 // Forest of independent clouds: cloud id of every position, and each point's
@@ -1155,15 +1160,35 @@ __global__ void k_part_store(const uint32_t *__restrict__ skey, int NH,
         if (k == NH - 1 || skey[k + 1] != key)
             clast[key] = p;
     }
-    // wave-aggregated maximum when the whole wave belongs to one child
+    // maximum aggregated over a wave whose points all belong to one child,
+    // then over the work-group's waves of one child (the first rounds have
+    // few large children: their atomics on one address would serialise)
+    __shared__ uint32_t wkey[4];
+    __shared__ float wmax[4];
+    const int w = threadIdx.x / WAVE;
     const uint32_t k0 = __shfl(key, 0, WAVE);
     const bool same = __all(key == k0);
-    if (same) {
-        float m = wave_max(d);
-        if ((threadIdx.x & (WAVE - 1)) == 0 && k0 != 0xFFFFFFFFu)
-            atomicMax(&ckmax[k0], __float_as_uint(m));
-    } else if (valid) {
+    const float m = same ? wave_max(d) : 0.f;
+    if ((threadIdx.x & (WAVE - 1)) == 0) {
+        wkey[w] = same ? k0 : 0xFFFFFFFFu;
+        wmax[w] = m;
+    }
+    if (!same && valid)
         atomicMax(&ckmax[key], __float_as_uint(d));
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        // runs of equal keys among the waves: one atomic per run
+        for (int a = 0; a < 4;) {
+            int b = a + 1;
+            float mm = wmax[a];
+            while (b < 4 && wkey[b] == wkey[a]) {
+                mm = fmaxf(mm, wmax[b]);
+                ++b;
+            }
+            if (wkey[a] != 0xFFFFFFFFu)
+                atomicMax(&ckmax[wkey[a]], __float_as_uint(mm));
+            a = b;
+        }
     }
 }
 
