@@ -81,7 +81,7 @@ struct GramArgs {
     double captured;
     // bichromatic query: only pairs across the two clouds are evaluated
     int cross;
-    // narrow BF16 rows copied per pack (64 rows each, zero past the pack)
+    // narrow 16-bit rows copied per pack (64 rows each, zero past the pack)
     // and their column terms 0.5 hx (FLT_MAX past the pack); null when the
     // staged kernel runs
     const void *qp;
@@ -93,7 +93,7 @@ struct GramArgs {
 };
 
 // Per-pack copies of the quantised rows and column terms for the narrow
-// BF16 kernel (G.qp, G.ayp), when that kernel applies; needs G.q, G.hx,
+// 16-bit kernel (G.qp, G.ayp), when that kernel applies; needs G.q, G.hx,
 // G.kq, G.q_pb, G.q_pe, G.nn, G.npacks.
 void gram_pad_packs(int metric, int prec, GramArgs &G, Scratch &S);
 // Exact decision of the survivor list: edges[i] and edist[i] (input ids,

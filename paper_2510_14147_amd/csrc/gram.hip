@@ -1,7 +1,8 @@
 // MFMA Gram filter for the Euclidean and angular leaf tiles.
 //
 // d(x,y)^2 = |x|^2 + |y|^2 - 2 x.y.  The inner products of a tile are taken
-// on the matrix cores from BF16 (or FP8 E4M3) copies of the centred points
+// on the matrix cores from BF16, FP16 (scaled by a power of two) or FP8
+// E4M3 copies of the centred points
 // (each cloud of a batch about its own mean), accumulated in FP32.  With u
 // the unit roundoff of the input format, |q(x).q(y) - x.y| <= (2u + u^2)
 // |x||y| (Cauchy-Schwarz), plus the
@@ -21,9 +22,12 @@
 // pack ids).  A work-group (GW waves) takes one group and a run of the union
 // of its members' interaction lists; wave w holds pack GW*g+w (<= 64 rows) in
 // registers, the B pack of each step is staged once in LDS and read by all
-// GW waves.  Every unordered point pair is evaluated once: a wave skips B
-// packs with a smaller id, and inside its own pack keeps only pairs whose
-// first point precedes the second in tree order.
+// GW waves (the narrow kernel reads its B rows itself, see k_gram_direct).
+// Every unordered point pair is evaluated once: a wave skips B packs with a
+// smaller id, and inside its own pack keeps only pairs whose first point
+// precedes the second in tree order.  Over a single cloud whose pack pairs
+// are all kept, the list is every group against every later pack, and the
+// packs are full runs of 64 consecutive tree positions.
 #include <float.h>
 #include <limits.h>
 #include <math.h>
@@ -1397,14 +1401,14 @@ __device__ __forceinline__ void half_finish(const GramArgs &G, const f32x16 (&ac
         *fillS = fill;
 }
 
-// Filter for narrow BF16 rows (kq <= 32: the leading principal
+// Filter for narrow 16-bit rows (kq <= 32: the leading principal
 // coordinates).  Same work units as k_gram, but no LDS staging and no
 // barrier in the entry loop: each wave reads its B fragments (16 bytes per
-// lane, k-step and column block) from L2 into registers two entries ahead,
-// and takes an entry as two 32-row halves (a half past na is skipped) by
-// both 32-column blocks.  A wave that emits survivors then never holds up the other
-// waves of its work-group; the four waves of a group read the same B rows
-// at about the same time, so most of those reads hit L1.
+// lane, k-step and column block) from the per-pack copies into registers
+// two entries ahead, and takes an entry as two 32-row halves, each against
+// both 32-column blocks.  A wave that emits survivors then never holds up
+// the other waves of its work-group; the four waves of a group read the
+// same B rows at about the same time, so most of those reads hit L1.
 template <int M, int PREC, int NKS>
 __global__ void __launch_bounds__(GT, 4)  // waves / SIMD that fit unspilled
 k_gram_direct(Pts P, GramArgs G, TileOut out)
@@ -2367,7 +2371,7 @@ double gram_margin_ratio(const fnn_tree *T, double t2min, int prec, Scratch &S,
     return t2min > 0 ? 2.0 * c1 * mean / t2min : HUGE_VAL;
 }
 
-// Centred, shrunk BF16 or FP8 copy of the coordinates (or of their leading
+// Centred, shrunk BF16, FP16 or FP8 copy of the coordinates (or of their leading
 // principal coordinates) and the per-point norms of the filter.
 //
 // With principal coordinates z~ (FP32 roundings of z = Q^T (x - mu)
