@@ -123,6 +123,31 @@ float coord_bound(int dim)
 // sets bound = min(1e16, sqrt(1e37 / dim))); angular rows must be non-zero.
 // The unit rows of the angular metric are computed from an FP64 norm, so
 // tiny rows whose FP32 squared norm would underflow are still accepted.
+// Euclidean rows already a multiple of four floats wide (no padding) and
+// 16-byte aligned: a flat float4 copy with the same checks, one error flag
+// per wave.
+__global__ void k_ingest_flat(const float4 *__restrict__ in, long long n4, float bound,
+                              float4 *__restrict__ x, int *err)
+{
+    bool bad = false, big = false;
+    for (long long f = (long long)blockIdx.x * blockDim.x + threadIdx.x; f < n4;
+         f += (long long)gridDim.x * blockDim.x) {
+        const float4 v = in[f];
+        bad |= !isfinite(v.x) || !isfinite(v.y) || !isfinite(v.z) || !isfinite(v.w);
+        big |= fabsf(v.x) > bound || fabsf(v.y) > bound || fabsf(v.z) > bound ||
+               fabsf(v.w) > bound;
+        x[f] = v;
+    }
+    // a non-finite coordinate reports ERR_INPUT (and no range error for it)
+    const bool b = __any(bad), g = __any(big && !bad);
+    if ((threadIdx.x & (WAVE - 1)) == 0) {
+        if (b)
+            atomicOr(err, ERR_INPUT);
+        if (g)
+            atomicOr(err, ERR_RANGE);
+    }
+}
+
 __global__ void k_ingest_vec(const float *__restrict__ in, int n, int dim,
                              int dp, int angular, float bound,
                              float *__restrict__ x, float *__restrict__ xn,
@@ -1531,9 +1556,15 @@ static Pts ingest_impl(fnn_tree *T, const void *points, Scratch &S)
         x_in = S.get<float>((size_t)n * T->dp);
         if (M == M_ANG)
             xn_in = S.get<float>((size_t)n * T->dp);
-        FNN_LAUNCH(k_ingest_vec, dim3(grid_cap(n, 4, 16384)), dim3(256), 0, st,
-                           (const float *)points, n, T->dim, T->dp,
-                           M == M_ANG ? 1 : 0, coord_bound(T->dim), x_in, xn_in, err);
+        if (M == M_L2 && T->dim == T->dp && ((uintptr_t)points & 15) == 0) {
+            const long long n4 = (long long)n * T->dp / 4;
+            FNN_LAUNCH(k_ingest_flat, dim3(grid_cap(n4, 256 * 8, 8192)), dim3(256), 0, st,
+                       (const float4 *)points, n4, coord_bound(T->dim), (float4 *)x_in, err);
+        } else {
+            FNN_LAUNCH(k_ingest_vec, dim3(grid_cap(n, 4, 16384)), dim3(256), 0, st,
+                       (const float *)points, n, T->dim, T->dp,
+                       M == M_ANG ? 1 : 0, coord_bound(T->dim), x_in, xn_in, err);
+        }
         P.x = x_in;
         P.xn = xn_in;
     } else if (M == M_HAM) {

@@ -49,9 +49,10 @@ def _build_rc(fnn, x, metric="l2"):
 
 @pytest.mark.parametrize("bad", [np.nan, np.inf, -np.inf])
 @pytest.mark.parametrize("metric", ["l2", "angular"])
-def test_non_finite_coordinate_is_einval(fnn, bad, metric):
-    print(f"[case] non-finite {bad} {metric}", flush=True)
-    x = G.random_points(500, 6, seed=3)
+@pytest.mark.parametrize("dim", [6, 8])  # padded rows; unpadded (flat copy on L2)
+def test_non_finite_coordinate_is_einval(fnn, bad, metric, dim):
+    print(f"[case] non-finite {bad} {metric} dim={dim}", flush=True)
+    x = G.random_points(500, dim, seed=3)
     x[417, 2] = bad
     rc, msg = _build_rc(fnn, x, metric)
     assert rc == EINVAL and "NaN/Inf" in msg
@@ -75,6 +76,11 @@ def test_coordinate_beyond_bound_is_unsupported(fnn):
     assert rc == EUNSUPPORTED and "magnitude" in msg
     x[7, 3] = 9.9e15
     assert _build_rc(fnn, x)[0] == 0
+    # a non-finite coordinate beside an out-of-range one reports the former
+    x[7, 3] = 3e17
+    x[100, 0] = np.nan
+    rc, msg = _build_rc(fnn, x)
+    assert rc == EINVAL and "NaN/Inf" in msg
 
 
 @pytest.mark.parametrize("eps", [0.0, -1.0, math.nan, math.inf, -math.inf])
