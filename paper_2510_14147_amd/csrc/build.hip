@@ -124,8 +124,9 @@ float coord_bound(int dim)
 // The unit rows of the angular metric are computed from an FP64 norm, so
 // tiny rows whose FP32 squared norm would underflow are still accepted.
 // Euclidean rows already a multiple of four floats wide (no padding) and
-// 16-byte aligned: a flat float4 copy with the same checks, one error flag
-// per wave.
+// 16-byte aligned: the same checks over flat float4 pieces, one error flag
+// per wave; the build then reads the caller's rows in place (x null: no
+// copy).
 __global__ void k_ingest_flat(const float4 *__restrict__ in, long long n4, float bound,
                               float4 *__restrict__ x, int *err)
 {
@@ -136,7 +137,8 @@ __global__ void k_ingest_flat(const float4 *__restrict__ in, long long n4, float
         bad |= !isfinite(v.x) || !isfinite(v.y) || !isfinite(v.z) || !isfinite(v.w);
         big |= fabsf(v.x) > bound || fabsf(v.y) > bound || fabsf(v.z) > bound ||
                fabsf(v.w) > bound;
-        x[f] = v;
+        if (x)
+            x[f] = v;
     }
     // a non-finite coordinate reports ERR_INPUT (and no range error for it)
     const bool b = __any(bad), g = __any(big && !bad);
@@ -1553,20 +1555,24 @@ static Pts ingest_impl(fnn_tree *T, const void *points, Scratch &S)
     P.dp = T->dp;
     float *x_in = nullptr, *xn_in = nullptr;
     if (M == M_L2 || M == M_ANG) {
-        x_in = S.get<float>((size_t)n * T->dp);
-        if (M == M_ANG)
-            xn_in = S.get<float>((size_t)n * T->dp);
         if (M == M_L2 && T->dim == T->dp && ((uintptr_t)points & 15) == 0) {
+            // unpadded, aligned rows: checked, then read in place (the
+            // caller's rows stay unchanged during the call)
             const long long n4 = (long long)n * T->dp / 4;
             FNN_LAUNCH(k_ingest_flat, dim3(grid_cap(n4, 256 * 8, 8192)), dim3(256), 0, st,
-                       (const float4 *)points, n4, coord_bound(T->dim), (float4 *)x_in, err);
+                       (const float4 *)points, n4, coord_bound(T->dim), (float4 *)nullptr,
+                       err);
+            P.x = (const float *)points;
         } else {
+            x_in = S.get<float>((size_t)n * T->dp);
+            if (M == M_ANG)
+                xn_in = S.get<float>((size_t)n * T->dp);
             FNN_LAUNCH(k_ingest_vec, dim3(grid_cap(n, 4, 16384)), dim3(256), 0, st,
                        (const float *)points, n, T->dim, T->dp,
                        M == M_ANG ? 1 : 0, coord_bound(T->dim), x_in, xn_in, err);
+            P.x = x_in;
+            P.xn = xn_in;
         }
-        P.x = x_in;
-        P.xn = xn_in;
     } else if (M == M_HAM) {
         P.h = (const uint64_t *)points;
     } else {
