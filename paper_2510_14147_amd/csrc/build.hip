@@ -1011,8 +1011,8 @@ k_select(Pts P, Hubs hb, int H, int32_t *__restrict__ cent,
 
     // ---- pairwise conflicts (j < i): within 2^{l-1} ----------------------
     // Vector rows of up to SEL_CR candidates are staged in LDS first (rows
-    // padded by 4 floats: neighbouring rows start in different banks); the
-    // FP32 key is the same sqdiff_key either way.
+    // padded by 4 floats: neighbouring rows start in different banks) and
+    // tested in 2 x 2 blocks; the FP32 key is that of sqdiff_key either way.
     unsigned long long tests = 0;
     const bool lds_rows = (M == M_L2 || M == M_ANG) && P.dp <= UPD_D && nk <= SEL_CR;
     const int ldr = P.dp + 4;
@@ -1041,22 +1041,68 @@ k_select(Pts P, Hubs hb, int H, int32_t *__restrict__ cent,
             }
         }
         __syncthreads();
-    }
-    // pairs j < i enumerated over the triangle: q = i (i - 1) / 2 + j
-    for (int q = threadIdx.x; q < nk * (nk - 1) / 2; q += SEL_T) {
-        int i = (int)((1.0f + sqrtf(1.0f + 8.0f * (float)q)) * 0.5f);
-        while (i * (i - 1) / 2 > q)
-            --i;
-        while ((i + 1) * i / 2 <= q)
-            ++i;
-        const int j = q - i * (i - 1) / 2;
-        const int a = 0x7FFFFFFF - (int)(uint32_t)buf[i];
-        const int c = 0x7FFFFFFF - (int)(uint32_t)buf[j];
-        ++tests;
-        const float k = lds_rows ? sqdiff_key(crow + i * ldr, crow + j * ldr, P.dp)
-                                 : key32<M>(P, a, c);
-        if (within<M>(P, a, c, k, T, cnt + 1))
-            atomicOr(&conf[i][j >> 6], 1ull << (j & 63));
+        // 2 x 2 blocks of the triangle (rows 2 bi, 2 bi + 1 against columns
+        // 2 bj, 2 bj + 1, bj <= bi): four keys from four row reads, each
+        // summed exactly as sqdiff_key sums it
+        const int nb = (nk + 1) / 2;
+        for (int q = threadIdx.x; q < nb * (nb + 1) / 2; q += SEL_T) {
+            int bi = (int)((sqrtf(1.0f + 8.0f * (float)q) - 1.0f) * 0.5f);
+            while (bi * (bi + 1) / 2 > q)
+                --bi;
+            while ((bi + 1) * (bi + 2) / 2 <= q)
+                ++bi;
+            const int bj = q - bi * (bi + 1) / 2;
+            const int i0 = 2 * bi, j0 = 2 * bj;
+            const float *r0 = crow + i0 * ldr, *r1 = crow + min(i0 + 1, nk - 1) * ldr;
+            const float *c0 = crow + j0 * ldr, *c1 = crow + min(j0 + 1, nk - 1) * ldr;
+            float4 s00 = {0.f, 0.f, 0.f, 0.f}, s01 = s00, s10 = s00, s11 = s00;
+            auto acc = [](float4 &t, const float4 &x, const float4 &y) {
+                const float d0 = x.x - y.x, d1 = x.y - y.y, d2 = x.z - y.z, d3 = x.w - y.w;
+                t.x = fmaf(d0, d0, t.x);
+                t.y = fmaf(d1, d1, t.y);
+                t.z = fmaf(d2, d2, t.z);
+                t.w = fmaf(d3, d3, t.w);
+            };
+            for (int k = 0; k < P.dp; k += 4) {
+                const float4 a0 = *reinterpret_cast<const float4 *>(r0 + k);
+                const float4 a1 = *reinterpret_cast<const float4 *>(r1 + k);
+                const float4 b0 = *reinterpret_cast<const float4 *>(c0 + k);
+                const float4 b1 = *reinterpret_cast<const float4 *>(c1 + k);
+                acc(s00, a0, b0);
+                acc(s01, a0, b1);
+                acc(s10, a1, b0);
+                acc(s11, a1, b1);
+            }
+            auto test = [&](int i, int j, const float4 &t) {
+                if (i >= nk || j >= i)
+                    return;
+                const int a = 0x7FFFFFFF - (int)(uint32_t)buf[i];
+                const int c = 0x7FFFFFFF - (int)(uint32_t)buf[j];
+                ++tests;
+                const float k = (t.x + t.y) + (t.z + t.w);
+                if (within<M>(P, a, c, k, T, cnt + 1))
+                    atomicOr(&conf[i][j >> 6], 1ull << (j & 63));
+            };
+            test(i0, j0, s00);
+            test(i0, j0 + 1, s01);
+            test(i0 + 1, j0, s10);
+            test(i0 + 1, j0 + 1, s11);
+        }
+    } else {
+        // pairs j < i enumerated over the triangle: q = i (i - 1) / 2 + j
+        for (int q = threadIdx.x; q < nk * (nk - 1) / 2; q += SEL_T) {
+            int i = (int)((1.0f + sqrtf(1.0f + 8.0f * (float)q)) * 0.5f);
+            while (i * (i - 1) / 2 > q)
+                --i;
+            while ((i + 1) * i / 2 <= q)
+                ++i;
+            const int j = q - i * (i - 1) / 2;
+            const int a = 0x7FFFFFFF - (int)(uint32_t)buf[i];
+            const int c = 0x7FFFFFFF - (int)(uint32_t)buf[j];
+            ++tests;
+            if (within<M>(P, a, c, key32<M>(P, a, c), T, cnt + 1))
+                atomicOr(&conf[i][j >> 6], 1ull << (j & 63));
+        }
     }
     __syncthreads();
 
