@@ -38,7 +38,7 @@ namespace fnn {
 
 Pts ingest_input(fnn_tree *T, const void *points, Scratch &S);
 void sort_csr_rows(const int64_t *row_ptr, int n, int32_t *col, float *dist,
-                   int64_t nnz, Scratch &S);
+                   int64_t nnz, Scratch &S, const unsigned long long *pk);
 
 namespace {
 
@@ -520,7 +520,7 @@ void landmark_graph(fnn_tree *hdr, const void *points, double eps, int m,
     int *bad = a.err;
     FNN_LAUNCH(k_rows_check, dim3(grid_for(n, 256)), dim3(256), 0, s, C->row_ptr, (int)n,
                cur, bad);
-    sort_csr_rows(C->row_ptr, (int)n, C->col, C->dist, nnz, S);
+    sort_csr_rows(C->row_ptr, (int)n, C->col, C->dist, nnz, S, nullptr);
     FNN_HIP(hipEventRecord(ev[3], s));
     if (read_scalar(bad, s))
         fail(FNN_EINTERNAL, "landmark: kept-pair count and fill disagree");

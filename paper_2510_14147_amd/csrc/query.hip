@@ -869,6 +869,36 @@ k_tile(Pts P, const int2 *__restrict__ inter, long long ninter,
         atomicAdd(&out.cnt[0], pairs);
 }
 
+// Decided survivors into their CSR slots as packed entries (column << 32 |
+// distance bits, the row sort's key): edge i (input ids a, b) goes to slot
+// row_ptr[a] + rank.x and row_ptr[b] + rank.y, one 8-byte store each, so the
+// scattered stores are half as many as with separate column and distance
+// stores; the row sort writes col and dist.  A rank past its row sets
+// ERR_INDEX.
+__global__ void k_place_packed(const int2 *__restrict__ edges, const float *__restrict__ edist,
+                               const int2 *__restrict__ erank, long long ne,
+                               const int64_t *__restrict__ row_ptr,
+                               unsigned long long *__restrict__ pk, int *__restrict__ err)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < ne;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int2 e = edges[i];
+        if (e.x < 0)
+            continue;  // a survivor that is no edge
+        const int2 r = erank[i];
+        const uint32_t d = __float_as_uint(edist[i]);
+        const int64_t a0 = row_ptr[e.x], a1 = row_ptr[e.x + 1];
+        const int64_t b0 = row_ptr[e.y], b1 = row_ptr[e.y + 1];
+        const int64_t s1 = a0 + r.x, s2 = b0 + r.y;
+        if (r.x >= 0 && r.y >= 0 && s1 < a1 && s2 < b1) {
+            pk[s1] = ((unsigned long long)(uint32_t)e.y << 32) | d;
+            pk[s2] = ((unsigned long long)(uint32_t)e.x << 32) | d;
+        } else {
+            atomicOr(err, ERR_INDEX);
+        }
+    }
+}
+
 // ------------------------------------------------------------ row sort ---
 
 __device__ __forceinline__ unsigned long long pack_entry(int32_t c, float d)
@@ -878,17 +908,20 @@ __device__ __forceinline__ unsigned long long pack_entry(int32_t c, float d)
 
 // One row of up to 64*V entries sorted by one wave: element v*64 + lane
 // lives in register v of that lane; bitonic stages with stride >= 64 swap
-// registers within a lane, shorter strides exchange across lanes.
+// registers within a lane, shorter strides exchange across lanes.  The
+// entries come from pk (packed, same slots) when it is non-null, else from
+// col and dist; the sorted row goes to col and dist.
 template <int V>
 __device__ __forceinline__ void wave_sort_row(int32_t *__restrict__ col,
                                               float *__restrict__ dist, int64_t b,
-                                              int len, int lane)
+                                              int len, int lane,
+                                              const unsigned long long *__restrict__ pk = nullptr)
 {
     unsigned long long x[V];
 #pragma unroll
     for (int v = 0; v < V; ++v) {
         const int i = v * WAVE + lane;
-        x[v] = i < len ? pack_entry(col[b + i], dist[b + i]) : ~0ull;
+        x[v] = i >= len ? ~0ull : pk ? pk[b + i] : pack_entry(col[b + i], dist[b + i]);
     }
 #pragma unroll
     for (int k = 2; k <= WAVE * V; k <<= 1) {
@@ -930,11 +963,15 @@ __device__ __forceinline__ void wave_sort_row(int32_t *__restrict__ col,
 }
 
 // Rows of at most 512 entries: one wave per row (register bitonic sort);
-// longer rows are listed for the work-group and global sorts.
+// longer rows are listed for the work-group and global sorts.  With pk
+// non-null the entries are read packed from pk (same slots) and every row
+// is written to col and dist: sorted here, or unpacked in place for the
+// listed sorts.
 __global__ void __launch_bounds__(256)
 k_sort_small(const int64_t *__restrict__ row_ptr, int n, int32_t *__restrict__ col,
              float *__restrict__ dist, int32_t *__restrict__ mid_list,
-             int32_t *__restrict__ long_list, int32_t *__restrict__ counts)
+             int32_t *__restrict__ long_list, int32_t *__restrict__ counts,
+             const unsigned long long *__restrict__ pk)
 {
     const int lane = threadIdx.x & (WAVE - 1);
     const int wpb = blockDim.x / WAVE;
@@ -942,6 +979,12 @@ k_sort_small(const int64_t *__restrict__ row_ptr, int n, int32_t *__restrict__ c
          r += gridDim.x * wpb) {
     const int64_t b = row_ptr[r];
     const int64_t len = row_ptr[r + 1] - b;
+    if (pk && (len == 1 || len > 8 * WAVE))
+        for (int64_t i = lane; i < len; i += WAVE) {
+            const unsigned long long x = pk[b + i];
+            col[b + i] = (int32_t)(x >> 32);
+            dist[b + i] = __uint_as_float((uint32_t)x);
+        }
     if (len <= 1)
         continue;
     if (len > 8 * WAVE) {
@@ -954,19 +997,20 @@ k_sort_small(const int64_t *__restrict__ row_ptr, int n, int32_t *__restrict__ c
         continue;
     }
     if (len > 4 * WAVE) {
-        wave_sort_row<8>(col, dist, b, (int)len, lane);
+        wave_sort_row<8>(col, dist, b, (int)len, lane, pk);
         continue;
     }
     if (len > 2 * WAVE) {
-        wave_sort_row<4>(col, dist, b, (int)len, lane);
+        wave_sort_row<4>(col, dist, b, (int)len, lane, pk);
         continue;
     }
     if (len > WAVE) {
-        wave_sort_row<2>(col, dist, b, (int)len, lane);
+        wave_sort_row<2>(col, dist, b, (int)len, lane, pk);
         continue;
     }
-    unsigned long long v = lane < len ? pack_entry(col[b + lane], dist[b + lane])
-                                      : ~0ull;
+    unsigned long long v = lane >= len ? ~0ull
+                           : pk        ? pk[b + lane]
+                                       : pack_entry(col[b + lane], dist[b + lane]);
     for (int k = 2; k <= WAVE; k <<= 1) {
         for (int j = k >> 1; j > 0; j >>= 1) {
             unsigned long long o = __shfl_xor(v, j, WAVE);
@@ -1626,9 +1670,12 @@ __global__ void k_pair_bound(const int2 *__restrict__ inter, long long ni,
 
 // Sorts every CSR row by column (entries are (column, distance) pairs):
 // rows of up to 512 entries by one wave, up to 4096 by one wave or four,
-// up to 16384 by sixteen waves, longer rows in a global buffer.
+// up to 16384 by sixteen waves, longer rows in a global buffer.  pk: the
+// entries packed as (column << 32 | distance bits) in their slots, when the
+// fill wrote them so (col and dist are then written here); null: they are
+// in col and dist.
 void sort_csr_rows(const int64_t *row_ptr, int n, int32_t *col, float *dist,
-                   int64_t nnz, Scratch &S)
+                   int64_t nnz, Scratch &S, const unsigned long long *pk)
 {
     hipStream_t s = S.stream();
     int32_t *mid = S.get<int32_t>(n), *lng = S.get<int32_t>(n);
@@ -1636,7 +1683,7 @@ void sort_csr_rows(const int64_t *row_ptr, int n, int32_t *col, float *dist,
     fill(cc, 0, 2, s);
     if (nnz > 0) {
         FNN_LAUNCH(k_sort_small, dim3(grid_cap(n, 4, 16384)), dim3(256), 0, s,
-                   row_ptr, n, col, dist, mid, lng, cc);
+                   row_ptr, n, col, dist, mid, lng, cc, pk);
         int32_t hcc[2];
         FNN_HIP(hipMemcpyAsync(hcc, cc, sizeof hcc, hipMemcpyDeviceToHost, s));
         FNN_HIP(hipStreamSynchronize(s));
@@ -1895,6 +1942,7 @@ static void eps_graph_impl(const fnn_tree *Tc, const double *epsv,
     C->row_ptr = (int64_t *)out_alloc(sizeof(int64_t) * ((size_t)n + 1));
     int64_t nnz = 0;
     int64_t novf = 0;
+    unsigned long long *packed = nullptr;  // packed CSR entries (see k_place_packed)
     unsigned long long hc0[9] = {0};
 
     if (use_gram || !learned) {
@@ -2045,8 +2093,19 @@ static void eps_graph_impl(const fnn_tree *Tc, const double *epsv,
             // every entry at its row start plus its rank: the ranks of a row
             // are distinct and below its degree, so the rows fill exactly
             // (a rank past its row raises ERR_INDEX)
-            if (nnz > 0)
-                edges_place(gedges, gedist, G.erank, ngedges, C->row_ptr, o, s);
+            if (nnz > 0) {
+                // packed entries while a copy of the CSR's nnz fits easily
+                size_t free_now = 0, tot_now = 0;
+                FNN_HIP(hipMemGetInfo(&free_now, &tot_now));
+                if ((double)nnz * sizeof(unsigned long long) < 0.25 * (double)free_now) {
+                    packed = S.get<unsigned long long>(nnz);
+                    FNN_LAUNCH(k_place_packed, dim3(grid_cap(ngedges, 256, 65536)), dim3(256),
+                               0, s, gedges, gedist, G.erank, ngedges, C->row_ptr, packed,
+                               o.err);
+                } else {
+                    edges_place(gedges, gedist, G.erank, ngedges, C->row_ptr, o, s);
+                }
+            }
         } else {
             o.cursor = S.get<unsigned long long>(n);
             FNN_LAUNCH(k_cursor_init, dim3(grid_for(n, 256)), dim3(256), 0, s,
@@ -2185,7 +2244,7 @@ static void eps_graph_impl(const fnn_tree *Tc, const double *epsv,
     }
 
     // ---- per-row sort ---------------------------------------------------
-    sort_csr_rows(C->row_ptr, n, C->col, C->dist, nnz, S);
+    sort_csr_rows(C->row_ptr, n, C->col, C->dist, nnz, S, packed);
     tm.mark();  // 6
 
     // ---- trace targets, prediction error ---------------------------------
