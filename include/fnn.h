@@ -191,7 +191,10 @@ typedef struct fnn_stats {
     int64_t launches;         /* kernels launched eagerly by the call         */
     int64_t graph_launches;   /* recorded launch sequences replayed           */
     int64_t graph_kernels;    /* kernels those replays ran                    */
-    double reserved[1];
+    int64_t fill_path;        /* how the CSR was filled: 0 row cursors (or    */
+                              /* the learned slots), 1 the survivor ranks     */
+                              /* with column and distance stores, 2 the ranks */
+                              /* with packed words that the row sort unpacks  */
 } fnn_stats;
 
 /* Build the cover tree of n points (Algorithms 1-2).  points: device

@@ -80,7 +80,7 @@ class fnn_stats(ctypes.Structure):
                  ("landmark_merge_ms", ctypes.c_double),
                  ("launches", ctypes.c_int64), ("graph_launches", ctypes.c_int64),
                  ("graph_kernels", ctypes.c_int64),
-                 ("reserved", ctypes.c_double * 1)])
+                 ("fill_path", ctypes.c_int64)])
 
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -211,7 +211,8 @@ def _stats(handle) -> dict:
     return {k: getattr(s, k) for k in _STAT_I64 + _STAT_F64 +
             ["proj_dim", "proj_captured", "precision_used", "landmark_cells",
              "landmark_rows", "landmark_partition_ms", "landmark_forest_ms",
-             "landmark_merge_ms", "launches", "graph_launches", "graph_kernels"]}
+             "landmark_merge_ms", "launches", "graph_launches", "graph_kernels",
+             "fill_path"]}
 
 
 class Tree:

@@ -2099,11 +2099,13 @@ static void eps_graph_impl(const fnn_tree *Tc, const double *epsv,
                 FNN_HIP(hipMemGetInfo(&free_now, &tot_now));
                 if ((double)nnz * sizeof(unsigned long long) < 0.25 * (double)free_now) {
                     packed = S.get<unsigned long long>(nnz);
+                    st.fill_path = 2;
                     FNN_LAUNCH(k_place_packed, dim3(grid_cap(ngedges, 256, 65536)), dim3(256),
                                0, s, gedges, gedist, G.erank, ngedges, C->row_ptr, packed,
                                o.err);
                 } else {
                     edges_place(gedges, gedist, G.erank, ngedges, C->row_ptr, o, s);
+                    st.fill_path = 1;
                 }
             }
         } else {

@@ -113,20 +113,29 @@ def test_complete_graph_scatter(fnn, orc, prec):
     check(fnn, orc, x, "l2", 100.0, tree_check=False, precision=prec)
 
 
-def test_row_sort_lengths(fnn, orc):
+@pytest.mark.parametrize("prec", [None, "fp16"])
+def test_row_sort_lengths(fnn, orc, prec):
     # separated tight clusters, complete inside, so a row of a cluster of m
     # points holds m - 1 entries and takes one path of the per-row sort:
+    #   0 and 1 entries: no sort (a single point, a pair);
     #   49 / 99 / 199 / 299 entries: one wave, 1 / 2 / 4 / 8 keys per lane
     #   (k_sort_small); 599 and 1099: one wave, 16 and 32 keys per lane
     #   (k_sort_wave); 2099: four waves in registers, the longest strides
     #   through LDS (k_sort_blk<4>); 4199: sixteen waves (k_sort_blk<16>).
     # Rows beyond 16384 entries (k_sort_long) are test_long_rows_sorted's.
-    sizes = [50, 100, 200, 300, 600, 1100, 2100, 4200]
-    parts = [np.float32(100.0 * k) + G.random_points(m, 3, seed=20 + k, scale=0.01)
+    # Default precision: FP32 tiles, row cursors.  FP16: the filter's
+    # survivors placed by rank as packed words, which the row sort unpacks
+    # (rows of 0 and 1 entries and those handed to the longer sorts too).
+    sizes = [1, 2, 50, 100, 200, 300, 600, 1100, 2100, 4200]
+    d = 3 if prec is None else 16
+    parts = [np.float32(100.0 * k) + G.random_points(m, d, seed=20 + k, scale=0.01)
              for k, m in enumerate(sizes)]
     x = np.concatenate(parts).astype(np.float32)
     x = x[np.random.default_rng(12).permutation(len(x))]
-    check(fnn, orc, x, "l2", 1.0, tree_check=False)
+    kw = {} if prec is None else {"precision": prec}
+    _, g, _ = check(fnn, orc, x, "l2", 1.0, tree_check=False, **kw)
+    if prec is not None:
+        assert g.stats["fill_path"] == 2, g.stats["fill_path"]
 
 
 def test_long_rows_sorted(fnn):
