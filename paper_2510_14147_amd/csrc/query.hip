@@ -906,35 +906,41 @@ __device__ __forceinline__ unsigned long long pack_entry(int32_t c, float d)
     return ((unsigned long long)(uint32_t)c << 32) | __float_as_uint(d);
 }
 
-// One row of up to 64*V entries sorted by one wave: element v*64 + lane
-// lives in register v of that lane; bitonic stages with stride >= 64 swap
-// registers within a lane, shorter strides exchange across lanes.  The
-// entries come from pk (packed, same slots) when it is non-null, else from
-// col and dist; the sorted row goes to col and dist.
+// One row of up to 64*V entries sorted by one wave with a bitonic network
+// in registers.  Up to 8 keys per lane, element lane*V + v lives in
+// register v of that lane: strides below V swap registers within a lane and
+// only the longer ones exchange across lanes (fewer exchanges; the lane's
+// entries are V consecutive slots).  From 16 keys per lane, element
+// v*64 + lane: each load and store instruction covers 64 consecutive slots,
+// strides of 64 and more swap registers, shorter ones exchange across
+// lanes.  The entries come from pk (packed, same slots) when it is
+// non-null, else from col and dist; the sorted row goes to col and dist.
 template <int V>
 __device__ __forceinline__ void wave_sort_row(int32_t *__restrict__ col,
                                               float *__restrict__ dist, int64_t b,
                                               int len, int lane,
                                               const unsigned long long *__restrict__ pk = nullptr)
 {
+    constexpr bool LM = V <= 8;  // lane-major layout
+    auto idx = [&](int v) { return LM ? lane * V + v : v * WAVE + lane; };
     unsigned long long x[V];
 #pragma unroll
     for (int v = 0; v < V; ++v) {
-        const int i = v * WAVE + lane;
+        const int i = idx(v);
         x[v] = i >= len ? ~0ull : pk ? pk[b + i] : pack_entry(col[b + i], dist[b + i]);
     }
 #pragma unroll
     for (int k = 2; k <= WAVE * V; k <<= 1) {
 #pragma unroll
         for (int j = k >> 1; j > 0; j >>= 1) {
-            if (j >= WAVE) {
-                const int jv = j / WAVE;
+            if (LM ? j < V : j >= WAVE) {
+                const int jr = LM ? j : j / WAVE;  // register stride
 #pragma unroll
                 for (int v = 0; v < V; ++v) {
-                    if (v & jv)
+                    if (v & jr)
                         continue;
-                    const int w = v | jv;
-                    const bool up = ((v * WAVE + lane) & k) == 0;
+                    const int w = v | jr;
+                    const bool up = (idx(v) & k) == 0;
                     const unsigned long long a = x[v], c = x[w];
                     if ((a > c) == up) {
                         x[v] = c;
@@ -942,11 +948,12 @@ __device__ __forceinline__ void wave_sort_row(int32_t *__restrict__ col,
                     }
                 }
             } else {
+                const int lj = LM ? j / V : j;  // lane stride
+                const bool lower = (lane & lj) == 0;
 #pragma unroll
                 for (int v = 0; v < V; ++v) {
-                    const unsigned long long o = __shfl_xor(x[v], j, WAVE);
-                    const bool up = ((v * WAVE + lane) & k) == 0;
-                    const bool lower = (lane & j) == 0;
+                    const unsigned long long o = __shfl_xor(x[v], lj, WAVE);
+                    const bool up = (idx(v) & k) == 0;
                     x[v] = (lower == up) ? (o < x[v] ? o : x[v]) : (o > x[v] ? o : x[v]);
                 }
             }
@@ -954,7 +961,7 @@ __device__ __forceinline__ void wave_sort_row(int32_t *__restrict__ col,
     }
 #pragma unroll
     for (int v = 0; v < V; ++v) {
-        const int i = v * WAVE + lane;
+        const int i = idx(v);
         if (i < len) {
             col[b + i] = (int32_t)(x[v] >> 32);
             dist[b + i] = __uint_as_float((uint32_t)x[v]);
