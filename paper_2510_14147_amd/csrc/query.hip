@@ -907,11 +907,14 @@ __device__ __forceinline__ unsigned long long pack_entry(int32_t c, float d)
 }
 
 // One row of up to 64*V entries sorted by one wave with a bitonic network
-// in registers.  Up to 8 keys per lane, element lane*V + v lives in
+// in registers.  Up to 16 keys per lane, element lane*V + v lives in
 // register v of that lane: strides below V swap registers within a lane and
-// only the longer ones exchange across lanes (fewer exchanges; the lane's
-// entries are V consecutive slots).  From 16 keys per lane, element
-// v*64 + lane: each load and store instruction covers 64 consecutive slots,
+// only the longer ones exchange across lanes.  With 8 or 16 keys per lane
+// the row moves between memory and registers through the wave's LDS tile tr
+// (WAVE * (V + 1) words; element g at word g + g / V, so both the coalesced
+// side, 64 consecutive slots per instruction, and the lane-major side stay
+// within two-way bank sharing); with fewer keys the lane reads its
+// consecutive slots directly.  32 keys per lane: element v*64 + lane,
 // strides of 64 and more swap registers, shorter ones exchange across
 // lanes.  The entries come from pk (packed, same slots) when it is
 // non-null, else from col and dist; the sorted row goes to col and dist.
@@ -919,15 +922,33 @@ template <int V>
 __device__ __forceinline__ void wave_sort_row(int32_t *__restrict__ col,
                                               float *__restrict__ dist, int64_t b,
                                               int len, int lane,
-                                              const unsigned long long *__restrict__ pk = nullptr)
+                                              const unsigned long long *__restrict__ pk,
+                                              unsigned long long *tr)
 {
-    constexpr bool LM = V <= 8;  // lane-major layout
+    constexpr bool LM = V <= 16;          // lane-major layout
+    constexpr bool LT = LM && V >= 8;     // memory side through the LDS tile
     auto idx = [&](int v) { return LM ? lane * V + v : v * WAVE + lane; };
+    auto ld = [&](int i) {
+        return i >= len ? ~0ull : pk ? pk[b + i] : pack_entry(col[b + i], dist[b + i]);
+    };
     unsigned long long x[V];
+    if constexpr (LT) {
+        // one wave's LDS accesses complete in order: only the compiler must
+        // keep the reads after the writes (and later writes after them)
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 #pragma unroll
-    for (int v = 0; v < V; ++v) {
-        const int i = idx(v);
-        x[v] = i >= len ? ~0ull : pk ? pk[b + i] : pack_entry(col[b + i], dist[b + i]);
+        for (int v = 0; v < V; ++v) {
+            const int g = v * WAVE + lane;
+            tr[g + g / V] = ld(g);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+#pragma unroll
+        for (int v = 0; v < V; ++v)
+            x[v] = tr[lane * (V + 1) + v];
+    } else {
+#pragma unroll
+        for (int v = 0; v < V; ++v)
+            x[v] = ld(idx(v));
     }
 #pragma unroll
     for (int k = 2; k <= WAVE * V; k <<= 1) {
@@ -959,13 +980,27 @@ __device__ __forceinline__ void wave_sort_row(int32_t *__restrict__ col,
             }
         }
     }
-#pragma unroll
-    for (int v = 0; v < V; ++v) {
-        const int i = idx(v);
+    auto st = [&](int i, unsigned long long e) {
         if (i < len) {
-            col[b + i] = (int32_t)(x[v] >> 32);
-            dist[b + i] = __uint_as_float((uint32_t)x[v]);
+            col[b + i] = (int32_t)(e >> 32);
+            dist[b + i] = __uint_as_float((uint32_t)e);
         }
+    };
+    if constexpr (LT) {
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+#pragma unroll
+        for (int v = 0; v < V; ++v)
+            tr[lane * (V + 1) + v] = x[v];
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const int g = v * WAVE + lane;
+            st(g, tr[g + g / V]);
+        }
+    } else {
+#pragma unroll
+        for (int v = 0; v < V; ++v)
+            st(idx(v), x[v]);
     }
 }
 
@@ -980,8 +1015,10 @@ k_sort_small(const int64_t *__restrict__ row_ptr, int n, int32_t *__restrict__ c
              int32_t *__restrict__ long_list, int32_t *__restrict__ counts,
              const unsigned long long *__restrict__ pk)
 {
+    __shared__ unsigned long long tr_s[256 / WAVE][WAVE * 9];  // 8 keys per lane
     const int lane = threadIdx.x & (WAVE - 1);
     const int wpb = blockDim.x / WAVE;
+    unsigned long long *tr = tr_s[threadIdx.x / WAVE];
     for (int r = blockIdx.x * wpb + threadIdx.x / WAVE; r < n;
          r += gridDim.x * wpb) {
     const int64_t b = row_ptr[r];
@@ -1004,15 +1041,15 @@ k_sort_small(const int64_t *__restrict__ row_ptr, int n, int32_t *__restrict__ c
         continue;
     }
     if (len > 4 * WAVE) {
-        wave_sort_row<8>(col, dist, b, (int)len, lane, pk);
+        wave_sort_row<8>(col, dist, b, (int)len, lane, pk, tr);
         continue;
     }
     if (len > 2 * WAVE) {
-        wave_sort_row<4>(col, dist, b, (int)len, lane, pk);
+        wave_sort_row<4>(col, dist, b, (int)len, lane, pk, tr);
         continue;
     }
     if (len > WAVE) {
-        wave_sort_row<2>(col, dist, b, (int)len, lane, pk);
+        wave_sort_row<2>(col, dist, b, (int)len, lane, pk, tr);
         continue;
     }
     unsigned long long v = lane >= len ? ~0ull
@@ -1040,8 +1077,10 @@ __global__ void __launch_bounds__(256)
 k_sort_wave(const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ list,
             int nl, int32_t *__restrict__ col, float *__restrict__ dist)
 {
+    __shared__ unsigned long long tr_s[256 / WAVE][WAVE * 17];  // 16 keys per lane
     const int lane = threadIdx.x & (WAVE - 1);
     const int wpb = blockDim.x / WAVE;
+    unsigned long long *tr = tr_s[threadIdx.x / WAVE];
     for (int li = blockIdx.x * wpb + threadIdx.x / WAVE; li < nl; li += gridDim.x * wpb) {
         const int r = list[li];
         const int64_t b = row_ptr[r];
@@ -1049,9 +1088,9 @@ k_sort_wave(const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ lis
         if (len > 32 * WAVE)
             continue;  // the work-group sort's
         if (len > 16 * WAVE)
-            wave_sort_row<32>(col, dist, b, len, lane);
+            wave_sort_row<32>(col, dist, b, len, lane, nullptr, tr);
         else
-            wave_sort_row<16>(col, dist, b, len, lane);
+            wave_sort_row<16>(col, dist, b, len, lane, nullptr, tr);
     }
 }
 
