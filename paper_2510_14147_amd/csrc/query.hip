@@ -907,17 +907,16 @@ __device__ __forceinline__ unsigned long long pack_entry(int32_t c, float d)
 }
 
 // One row of up to 64*V entries sorted by one wave with a bitonic network
-// in registers.  Up to 16 keys per lane, element lane*V + v lives in
-// register v of that lane: strides below V swap registers within a lane and
-// only the longer ones exchange across lanes.  With 8 or 16 keys per lane
-// the row moves between memory and registers through the wave's LDS tile tr
+// in registers: element lane*V + v lives in register v of that lane, so
+// strides below V swap registers within a lane and only the longer ones
+// exchange across lanes.  With 8 or more keys per lane the row moves
+// between memory and registers through the wave's LDS tile tr
 // (WAVE * (V + 1) words; element g at word g + g / V, so both the coalesced
 // side, 64 consecutive slots per instruction, and the lane-major side stay
 // within two-way bank sharing); with fewer keys the lane reads its
-// consecutive slots directly.  32 keys per lane: element v*64 + lane,
-// strides of 64 and more swap registers, shorter ones exchange across
-// lanes.  The entries come from pk (packed, same slots) when it is
-// non-null, else from col and dist; the sorted row goes to col and dist.
+// consecutive slots directly.  The entries come from pk (packed, same
+// slots) when it is non-null, else from col and dist; the sorted row goes
+// to col and dist.
 template <int V>
 __device__ __forceinline__ void wave_sort_row(int32_t *__restrict__ col,
                                               float *__restrict__ dist, int64_t b,
@@ -925,9 +924,9 @@ __device__ __forceinline__ void wave_sort_row(int32_t *__restrict__ col,
                                               const unsigned long long *__restrict__ pk,
                                               unsigned long long *tr)
 {
-    constexpr bool LM = V <= 16;          // lane-major layout
-    constexpr bool LT = LM && V >= 8;     // memory side through the LDS tile
-    auto idx = [&](int v) { return LM ? lane * V + v : v * WAVE + lane; };
+    static_assert(V >= 1 && V <= 32, "keys per lane");
+    constexpr bool LT = V >= 8;  // memory side through the LDS tile
+    auto idx = [&](int v) { return lane * V + v; };
     auto ld = [&](int i) {
         return i >= len ? ~0ull : pk ? pk[b + i] : pack_entry(col[b + i], dist[b + i]);
     };
@@ -954,13 +953,12 @@ __device__ __forceinline__ void wave_sort_row(int32_t *__restrict__ col,
     for (int k = 2; k <= WAVE * V; k <<= 1) {
 #pragma unroll
         for (int j = k >> 1; j > 0; j >>= 1) {
-            if (LM ? j < V : j >= WAVE) {
-                const int jr = LM ? j : j / WAVE;  // register stride
+            if (j < V) {
 #pragma unroll
                 for (int v = 0; v < V; ++v) {
-                    if (v & jr)
+                    if (v & j)
                         continue;
-                    const int w = v | jr;
+                    const int w = v | j;
                     const bool up = (idx(v) & k) == 0;
                     const unsigned long long a = x[v], c = x[w];
                     if ((a > c) == up) {
@@ -969,7 +967,7 @@ __device__ __forceinline__ void wave_sort_row(int32_t *__restrict__ col,
                     }
                 }
             } else {
-                const int lj = LM ? j / V : j;  // lane stride
+                const int lj = j / V;  // lane stride
                 const bool lower = (lane & lj) == 0;
 #pragma unroll
                 for (int v = 0; v < V; ++v) {
@@ -1077,7 +1075,7 @@ __global__ void __launch_bounds__(256)
 k_sort_wave(const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ list,
             int nl, int32_t *__restrict__ col, float *__restrict__ dist)
 {
-    __shared__ unsigned long long tr_s[256 / WAVE][WAVE * 17];  // 16 keys per lane
+    __shared__ unsigned long long tr_s[256 / WAVE][WAVE * 33];  // up to 32 keys per lane
     const int lane = threadIdx.x & (WAVE - 1);
     const int wpb = blockDim.x / WAVE;
     unsigned long long *tr = tr_s[threadIdx.x / WAVE];
